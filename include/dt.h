@@ -1,0 +1,207 @@
+/*
+ * dt.h -- C ABI of the MI355X Delaunay triangulation library (libdt.so).
+ *
+ * The library computes DT(P), the Delaunay triangulation of a point set
+ * P in R^D (D = 2 or 3), with the divide-and-conquer method of Funke,
+ * Sanders and Winkler, "Load-Balancing for Parallel Delaunay
+ * Triangulations": Algorithm 1 (partition, triangulate the partitions,
+ * find the border simplices, triangulate their vertices, merge by hash
+ * lookup) with the sample-based divide step of Algorithm 2 (triangulate a
+ * random sample, partition its Delaunay graph into k blocks, give every
+ * point the block of its nearest sample point).
+ *
+ * Result: the set of finite simplices of DT(P), each a row of D+1 input
+ * indices (0-based, ascending within the row).  The paper defines DT(P) for
+ * points in general position (Section "Delaunay Triangulations"); ties are
+ * broken by a symbolic perturbation of the paraboloid lifting in which a
+ * point with a smaller index has a larger height perturbation.  The result
+ * therefore depends only on the points, never on k, the divide, the sample
+ * or the execution order.
+ *
+ * Conventions shared by every entry point:
+ *   - points are row-major n x D doubles; the caller owns them and the
+ *     library never frees or modifies them.  `points_on_device` = 1 means a
+ *     HIP device pointer, 0 a host pointer (then the call copies it).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     ordered on it; calls that return results synchronise it.
+ *   - every call returns a status (DT_OK = 0, negative on error) and never
+ *     aborts.  Results are opaque handles owning device memory until
+ *     dt_result_free.
+ *   - the library holds no global mutable state except the per-device
+ *     scratch used by dt_local_triangulate_noalloc (declared below).
+ */
+#ifndef DT_MI355X_H
+#define DT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+  DT_OK = 0,
+  DT_E_INVALID_ARG = -1, /* bad D, k, sample rate, sizes or pointers          */
+  DT_E_NONFINITE = -2,   /* a coordinate is NaN or infinite                  */
+  DT_E_DUPLICATE = -3,   /* two points are identical (P must be a set)       */
+  DT_E_DEGENERATE = -4,  /* n < D+1, or all points in one hyperplane         */
+  DT_E_NOMEM = -5,       /* device allocation failed / budget exceeded       */
+  DT_E_DEVICE = -6,      /* a HIP runtime call failed                        */
+  DT_E_INTERNAL = -7,    /* a device invariant failed (see dt_stats.fail)    */
+  DT_E_NOT_READY = -8    /* serving: the job has not finished yet            */
+};
+
+/* ---------------------------------------------------------------- options */
+enum { DT_DIVIDE_SAMPLE = 0, DT_DIVIDE_KD = 1 };
+/* Edge weights of the sample graph, paper Table "weights":
+ * d = |v-w| / d*, d* = length of the bounding-box diagonal. */
+enum { DT_WEIGHT_LOG = 0, DT_WEIGHT_CONST = 1, DT_WEIGHT_INVERSE = 2, DT_WEIGHT_LINEAR = 3 };
+/* Predicate precision: FP64 filter -> exact, or FP32 filter -> FP64 -> exact. */
+enum { DT_PREC_FP64 = 0, DT_PREC_FP32 = 1 };
+
+typedef struct dt_options {
+  int divide;        /* DT_DIVIDE_SAMPLE (Algorithm 2) or DT_DIVIDE_KD (cyclic median) */
+  int weight;        /* DT_WEIGHT_*                                                   */
+  int precision;     /* DT_PREC_*                                                     */
+  int sort_output;   /* 1: rows in lexicographic order (canonical form)               */
+  double eps;        /* partition imbalance: |V_i| <= (1+eps) ceil(|V|/k); default 0.05 */
+  double grid_cell;  /* c_G of the grid-based border test; default 1                  */
+  uint64_t seed;     /* sample seed; default 1                                        */
+  int refine_iters;  /* label-propagation sweeps of the partitioner; default 16       */
+  int keep_stages;   /* 1: keep per-stage arrays for dt_result_stage                  */
+} dt_options;
+
+/* -------------------------------------------------------------- statistics */
+enum {
+  DT_STAGE_VALIDATE = 0, DT_STAGE_SAMPLE, DT_STAGE_SAMPLE_DT, DT_STAGE_PARTITION,
+  DT_STAGE_ASSIGN, DT_STAGE_SCATTER, DT_STAGE_LOCAL_DT, DT_STAGE_BORDER,
+  DT_STAGE_BORDER_DT, DT_STAGE_MERGE, DT_STAGE_OUTPUT, DT_STAGE_TOTAL, DT_NUM_STAGES
+};
+
+typedef struct dt_stats {
+  int64_t n, eta, num_simplices;
+  int64_t border_simplices;   /* |B|: flagged simplices of the T_i (finite)        */
+  int64_t border_vertices;    /* |vertices(B)|, the border point set              */
+  int64_t tb_simplices;       /* finite simplices of T_B                          */
+  int64_t local_simplices;    /* finite simplices of all T_i                      */
+  int32_t k, D;
+  double cv;                  /* coefficient of variation of partition sizes      */
+  double max_dev;             /* max_i p_i/(n/k) - 1                              */
+  double o_dt;                /* (n + eta + |vertices(B)|) / n                     */
+  double cut_weight;          /* weight of sample-graph edges between blocks      */
+  int64_t max_part, min_part; /* largest / smallest partition                      */
+  int64_t rounds;             /* insertion rounds of all local-DT launches         */
+  int64_t pred[4][4];         /* [orient2D, orient3D, insphere2D, insphere3D] x
+                                 [calls, decided by FP32, by FP64, by exact]      */
+  uint32_t fail;              /* device failure bits when status is DT_E_INTERNAL */
+  uint32_t pad;
+  double stage_ms[DT_NUM_STAGES];
+  int64_t probe_hist[16];     /* merge hash: lookups by probe count (last = 15+)  */
+} dt_stats;
+
+typedef struct dt_result dt_result;
+
+/* Default options (sample divide, log weights, FP64+exact, eps 0.05, c_G 1,
+ * seed 1, 16 refinement sweeps, unsorted output, no stage arrays). */
+void dt_default_options(dt_options* opt);
+
+/* Human-readable name of a status code. */
+const char* dt_strerror(int status);
+
+/*
+ * dt_triangulate -- DT(P) by Algorithm 1 with the divide selected in opt.
+ *   points      n x D doubles (see conventions)
+ *   n, D        number of points (n >= D+1), dimension (2 or 3)
+ *   k           number of partitions (1 <= k <= eta for the sample divide;
+ *               a power of two for the kd divide); k = 1 triangulates
+ *               the whole set directly
+ *   sample_rate eta = round(sample_rate * n), at least D+2; 0 selects the
+ *               paper's default sqrt(n) (Algorithm 2, Section "Sample Size")
+ *   opt         NULL for defaults
+ *   out         receives a result handle on DT_OK (else NULL)
+ * Errors: DT_E_INVALID_ARG, DT_E_NONFINITE, DT_E_DUPLICATE,
+ *         DT_E_DEGENERATE, DT_E_NOMEM, DT_E_DEVICE, DT_E_INTERNAL.
+ */
+int dt_triangulate(const double* points, int64_t n, int D, int k, double sample_rate,
+                   const dt_options* opt, int points_on_device, void* stream,
+                   dt_result** out);
+
+/* Number of simplices in a result (all sets for batch results). */
+int64_t dt_result_count(const dt_result* r);
+/* Dimension D of a result. */
+int dt_result_dim(const dt_result* r);
+/* Copy the m x (D+1) int32 simplex rows to dst (device or host memory,
+ * capacity `cap_rows` rows).  Returns DT_OK or DT_E_INVALID_ARG. */
+int dt_result_copy(const dt_result* r, int32_t* dst, int64_t cap_rows, int dst_on_device,
+                   void* stream);
+/* Statistics of the run that produced r. */
+int dt_result_stats(const dt_result* r, dt_stats* st);
+void dt_result_free(dt_result* r);
+
+/*
+ * Per-stage arrays (only when opt.keep_stages = 1), copied to host memory:
+ *   DT_ARR_SAMPLE    int64[eta]  sample point indices, ascending
+ *   DT_ARR_SAMPLE_DT int32[m_s x (D+1)] finite simplices of DT(sample), as
+ *                    input indices
+ *   DT_ARR_PART      int32[eta]  block of every sample point
+ *   DT_ARR_PID       int32[n]    partition of every point
+ *   DT_ARR_ORDER     int32[n]    bucketed order: input index of each slot
+ *   DT_ARR_BORDER_V  int32[|V_B|] border vertices, ascending
+ *   DT_ARR_LOCAL     int32[m_l x (D+2)] finite simplices of all T_i as
+ *                    input indices plus a last column: 1 if in B
+ *   DT_ARR_BORDER_DT int32[m_b x (D+1)] finite simplices of T_B
+ * `count` receives the number of elements (rows x columns); pass dst = NULL
+ * to query it.
+ */
+enum { DT_ARR_SAMPLE = 0, DT_ARR_SAMPLE_DT, DT_ARR_PART, DT_ARR_PID, DT_ARR_ORDER,
+       DT_ARR_BORDER_V, DT_ARR_LOCAL, DT_ARR_BORDER_DT, DT_NUM_ARR };
+int dt_result_stage(const dt_result* r, int which, void* dst, int64_t cap, int64_t* count);
+
+/*
+ * dt_batch_triangulate -- DT of many independent point sets in one batched
+ * run (all sets share every kernel launch).  Set s holds rows
+ * offsets[s] .. offsets[s+1]-1 of `points` (offsets: num_sets+1 int64,
+ * host memory, offsets[0] = 0).  ids (nullable, n int64, host memory): the
+ * label of every point, used both as output label and as the tie-break
+ * order; NULL means the row index.  Output rows of set s follow those of
+ * set s-1; dt_result_set_offsets gives the row ranges.  A set with fewer
+ * than D+1 points or lying in one hyperplane yields no simplices and is
+ * counted in dt_stats.fail-free field `min_part` = -1 (status stays DT_OK).
+ */
+int dt_batch_triangulate(const double* points, const int64_t* ids, const int64_t* offsets,
+                         int64_t num_sets, int D, const dt_options* opt,
+                         int points_on_device, void* stream, dt_result** out);
+/* Row offsets (num_sets+1 int64, host) of the sets in a batch result. */
+int dt_result_set_offsets(const dt_result* r, int64_t* dst, int64_t cap);
+
+/*
+ * Serving (continuous batching).  A server owns a device-memory budget and
+ * a worker thread.  Jobs are admitted in arrival order while their
+ * estimated footprint fits the budget; admitted jobs that arrive while
+ * others run join the next batched launch, so their work overlaps on the
+ * device.  Each job's result is identical to dt_triangulate on its own.
+ *   dt_server_create: hbm_budget_bytes > 0; opt NULL for defaults.
+ *   dt_server_submit: points are copied at submission (host or device
+ *                     memory per points_on_device); returns a ticket.
+ *   dt_server_poll:   DT_OK with *out set when done, DT_E_NOT_READY before;
+ *                     the caller then owns *out.
+ *   dt_server_wait:   blocks until the job is done.
+ *   dt_server_destroy: waits for admitted work and frees everything.
+ */
+typedef struct dt_server dt_server;
+int dt_server_create(size_t hbm_budget_bytes, const dt_options* opt, dt_server** srv);
+int dt_server_submit(dt_server* srv, const double* points, int64_t n, int D, int k,
+                     double sample_rate, int points_on_device, uint64_t* ticket);
+int dt_server_poll(dt_server* srv, uint64_t ticket, dt_result** out);
+int dt_server_wait(dt_server* srv, uint64_t ticket, dt_result** out);
+/* Timestamps (seconds on the server's monotonic clock) of a finished job:
+ * t[0] submission, t[1] admission, t[2] completion. */
+int dt_server_times(dt_server* srv, uint64_t ticket, double t[3]);
+void dt_server_destroy(dt_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,193 @@
+// C ABI entry points of libdt (declared in include/dt.h).
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "dt_common.hpp"
+#include "dt_internal.hpp"
+#include "dt_pipeline.hpp"
+#include "dt_prep.hpp"
+
+using namespace dtk;
+
+extern "C" void dt_default_options(dt_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->divide = DT_DIVIDE_SAMPLE;
+  o->weight = DT_WEIGHT_LOG;
+  o->precision = DT_PREC_FP64;
+  o->sort_output = 0;
+  o->eps = 0.05;
+  o->grid_cell = 1.0;
+  o->seed = 1;
+  o->refine_iters = 16;
+  o->keep_stages = 0;
+}
+
+extern "C" const char* dt_strerror(int s) {
+  switch (s) {
+    case DT_OK: return "ok";
+    case DT_E_INVALID_ARG: return "invalid argument";
+    case DT_E_NONFINITE: return "non-finite coordinate";
+    case DT_E_DUPLICATE: return "duplicate point";
+    case DT_E_DEGENERATE: return "degenerate input (too few points or all in one hyperplane)";
+    case DT_E_NOMEM: return "out of device memory";
+    case DT_E_DEVICE: return "HIP runtime error";
+    case DT_E_INTERNAL: return "device invariant failed";
+    case DT_E_NOT_READY: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+namespace dtk {
+
+Ctx::~Ctx() {
+  if (hctr) (void)hipHostFree(hctr);
+  if (hflag) (void)hipHostFree(hflag);
+}
+
+int Ctx::init() {
+  DT_TRY(dctr.alloc(sizeof(Counters)));
+  DT_TRY(dflag.alloc(16));
+  DT_HIP(hipHostMalloc((void**)&hctr, sizeof(Counters), hipHostMallocDefault));
+  DT_HIP(hipHostMalloc((void**)&hflag, 16, hipHostMallocDefault));
+  return DT_OK;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Sort rows lexicographically on the host (verification output only).
+int sort_rows_inplace(dt_result* r, hipStream_t st) {
+  int w = r->D + 1;
+  std::vector<int32_t> h((size_t)r->m * w);
+  if (r->m == 0) return DT_OK;
+  DT_HIP(hipMemcpyAsync(h.data(), r->rows.p, h.size() * 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  std::vector<int64_t> idx((size_t)r->m);
+  for (int64_t i = 0; i < r->m; i++) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return std::lexicographical_compare(&h[a * w], &h[a * w] + w, &h[b * w], &h[b * w] + w);
+  });
+  std::vector<int32_t> o(h.size());
+  for (int64_t i = 0; i < r->m; i++)
+    for (int j = 0; j < w; j++) o[i * w + j] = h[idx[i] * w + j];
+  DT_HIP(hipMemcpyAsync(r->rows.p, o.data(), o.size() * 4, hipMemcpyHostToDevice, st));
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
+}  // namespace dtk
+
+static int check_opts(const dt_options* in, dt_options& o) {
+  dt_default_options(&o);
+  if (in) o = *in;
+  if (o.divide != DT_DIVIDE_SAMPLE && o.divide != DT_DIVIDE_KD) return DT_E_INVALID_ARG;
+  if (o.weight < 0 || o.weight > 3) return DT_E_INVALID_ARG;
+  if (o.precision != DT_PREC_FP64 && o.precision != DT_PREC_FP32) return DT_E_INVALID_ARG;
+  if (!(o.eps >= 0.0) || !(o.grid_cell > 0.0)) return DT_E_INVALID_ARG;
+  if (o.refine_iters < 0) return DT_E_INVALID_ARG;
+  return DT_OK;
+}
+
+extern "C" int dt_triangulate(const double* points, int64_t n, int D, int k, double sample_rate,
+                              const dt_options* opt, int points_on_device, void* stream,
+                              dt_result** out) {
+  if (!out) return DT_E_INVALID_ARG;
+  *out = nullptr;
+  if ((D != 2 && D != 3) || n < 0 || n > 0x7FFFFFF0ll || k < 1 || !points) return DT_E_INVALID_ARG;
+  if (!(sample_rate >= 0.0 && sample_rate <= 1.0)) return DT_E_INVALID_ARG;
+  dt_options o;
+  DT_TRY(check_opts(opt, o));
+  if (n < D + 1) return DT_E_DEGENERATE;
+  hipStream_t st = (hipStream_t)stream;
+  dt_result* r = new dt_result();
+  r->D = D;
+  int s = run_triangulate(points, n, D, k, sample_rate, o, points_on_device != 0, st, r);
+  if (s != DT_OK) {
+    delete r;
+    return s;
+  }
+  if (o.sort_output) {
+    s = sort_rows_inplace(r, st);
+    if (s != DT_OK) { delete r; return s; }
+  }
+  *out = r;
+  return DT_OK;
+}
+
+extern "C" int dt_batch_triangulate(const double* points, const int64_t* ids,
+                                    const int64_t* offsets, int64_t num_sets, int D,
+                                    const dt_options* opt, int points_on_device, void* stream,
+                                    dt_result** out) {
+  if (!out) return DT_E_INVALID_ARG;
+  *out = nullptr;
+  if ((D != 2 && D != 3) || num_sets < 1 || !offsets || num_sets > 0x7FFFFFF0ll)
+    return DT_E_INVALID_ARG;
+  if (offsets[0] != 0) return DT_E_INVALID_ARG;
+  for (int64_t s = 0; s < num_sets; s++)
+    if (offsets[s + 1] < offsets[s]) return DT_E_INVALID_ARG;
+  int64_t n = offsets[num_sets];
+  if (n > 0x7FFFFFF0ll || (n > 0 && !points)) return DT_E_INVALID_ARG;
+  dt_options o;
+  DT_TRY(check_opts(opt, o));
+  hipStream_t st = (hipStream_t)stream;
+  dt_result* r = new dt_result();
+  r->D = D;
+  int s = run_batch(points, ids, offsets, num_sets, D, o, points_on_device != 0, st, r);
+  if (s != DT_OK) {
+    delete r;
+    return s;
+  }
+  if (o.sort_output && num_sets == 1) {
+    s = sort_rows_inplace(r, st);
+    if (s != DT_OK) { delete r; return s; }
+  }
+  *out = r;
+  return DT_OK;
+}
+
+extern "C" int64_t dt_result_count(const dt_result* r) { return r ? r->m : -1; }
+extern "C" int dt_result_dim(const dt_result* r) { return r ? r->D : -1; }
+
+extern "C" int dt_result_copy(const dt_result* r, int32_t* dst, int64_t cap_rows, int dst_on_device,
+                              void* stream) {
+  if (!r || (!dst && r->m > 0) || cap_rows < r->m) return DT_E_INVALID_ARG;
+  if (r->m == 0) return DT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  size_t bytes = (size_t)r->m * (r->D + 1) * 4;
+  DT_HIP(hipMemcpyAsync(dst, r->rows.p, bytes,
+                        dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
+extern "C" int dt_result_stats(const dt_result* r, dt_stats* s) {
+  if (!r || !s) return DT_E_INVALID_ARG;
+  *s = r->stats;
+  return DT_OK;
+}
+
+extern "C" void dt_result_free(dt_result* r) { delete r; }
+
+extern "C" int dt_result_set_offsets(const dt_result* r, int64_t* dst, int64_t cap) {
+  if (!r || !dst || cap < (int64_t)r->set_offsets.size()) return DT_E_INVALID_ARG;
+  for (size_t i = 0; i < r->set_offsets.size(); i++) dst[i] = r->set_offsets[i];
+  return DT_OK;
+}
+
+extern "C" int dt_result_stage(const dt_result* r, int which, void* dst, int64_t cap,
+                               int64_t* count) {
+  if (!r || which < 0 || which >= DT_NUM_ARR || !count) return DT_E_INVALID_ARG;
+  const std::vector<char>& a = r->stage[which];
+  int64_t esz = (which == DT_ARR_SAMPLE) ? 8 : 4;
+  *count = (int64_t)a.size() / esz;
+  if (!dst) return DT_OK;
+  if (cap < *count) return DT_E_INVALID_ARG;
+  memcpy(dst, a.data(), a.size());
+  return DT_OK;
+}

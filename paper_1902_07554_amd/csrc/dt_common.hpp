@@ -1,0 +1,43 @@
+// Shared device/host definitions for the MI355X Delaunay library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dt.h"
+
+namespace dtk {
+
+// Vertex id of the infinite vertex, and the unused fourth slot of a 2D cell.
+constexpr uint32_t INF_V = 0xFFFFFFFFu;
+constexpr uint32_t NOSLOT = 0xFFFFFFFEu;
+// ploc value of an inserted (or excluded) point; cfwd value of a live cell.
+constexpr uint32_t DONE = 0xFFFFFFFFu;
+constexpr uint32_t ALIVE = 0xFFFFFFFFu;
+constexpr unsigned long long NOKEY = 0xFFFFFFFFFFFFFFFFull;
+
+// Device-side failure bits (ORed into a flag word, read by the host).
+enum : uint32_t {
+  FAIL_CELL_POOL = 1u << 0,   // cell pool exhausted
+  FAIL_EXACT_CAP = 1u << 1,   // exact-arithmetic expansion capacity exceeded
+  FAIL_WALK = 1u << 2,        // point-location walk did not terminate
+  FAIL_PIVOT = 1u << 3,       // ridge rotation did not close
+  FAIL_CAND_CAP = 1u << 4,    // candidate buffer exhausted
+  FAIL_HASH = 1u << 5,        // simplex hash table full
+  FAIL_OUT_CAP = 1u << 6,     // output buffer too small
+  FAIL_NO_PROGRESS = 1u << 7, // a round inserted no point
+  FAIL_INVARIANT = 1u << 8,   // internal consistency check
+};
+
+struct Counters {
+  unsigned long long pred[4][4];  // [orient2, orient3, in2, in3][calls, fp32 ok, fp64 ok, exact]
+  unsigned int flags;
+  unsigned int cells;             // cells allocated in the pool
+  unsigned int ncand;             // candidates this round
+  unsigned int inserted;          // points inserted this round
+  unsigned int overflow;          // candidates that gave up (cavity too large)
+  unsigned int maxcav;            // largest cavity seen
+  unsigned int active;            // points still to insert
+  unsigned int pad;
+};
+
+}  // namespace dtk

@@ -1,0 +1,91 @@
+// Host-side internal interfaces of libdt (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "dt_common.hpp"
+
+namespace dtk {
+
+// Status plumbing: HIP failures become DT_E_DEVICE (or DT_E_NOMEM).
+#define DT_HIP(call)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) return (e_ == hipErrorOutOfMemory) ? DT_E_NOMEM : DT_E_DEVICE; \
+  } while (0)
+#define DT_TRY(call)            \
+  do {                          \
+    int s_ = (call);            \
+    if (s_ != DT_OK) return s_; \
+  } while (0)
+
+// Owning device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  int alloc(size_t n) {
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) { p = nullptr; return e == hipErrorOutOfMemory ? DT_E_NOMEM : DT_E_DEVICE; }
+    bytes = n;
+    return DT_OK;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// A batch of point sets to triangulate with one sequence of launches.
+// Points are device-resident as double4 (x, y, z or 0, key bits in w);
+// key = global id, the perturbation order and output label.
+struct LocalJob {
+  int D = 3;
+  uint32_t npts = 0;
+  uint32_t nsets = 0;
+  const double4* pts = nullptr;   // [npts]
+  const uint32_t* pset = nullptr; // [npts] set of each point
+  const uint32_t* set_off = nullptr;  // [nsets+1]
+  bool fp32 = false;
+};
+
+// Cell pool: cells live at indices [0, ncells); cfwd == ALIVE marks a live
+// cell, vertices are indices into the job's point array (INF_V = infinite).
+struct CellPool {
+  DevBuf cv, cn, cfwd, ccand, ccav, cshell, cpos;
+  uint32_t cap = 0;
+  uint32_t ncells = 0;
+  DevBuf set_cell0;   // [nsets] initial finite cell, DONE for a degenerate set
+};
+
+struct K4Stats {
+  int rounds = 0;
+  uint32_t maxcav = 0;
+  unsigned long long pred[4][4] = {};
+};
+
+// Triangulate every set of `job` (one batched sequence of launches).
+int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr,
+           hipStream_t st, K4Stats& ks);
+
+// Compact the live finite cells of the pool to rows of D+1 keys (global
+// ids, ascending inside a row).  rows may be null to only count.  If
+// set_rows is non-null it receives per-set counts (nsets entries).
+int k4_extract(const LocalJob& job, const CellPool& pool, int32_t* rows, uint32_t* count_dev,
+               uint32_t* set_rows, hipStream_t st);
+
+}  // namespace dtk

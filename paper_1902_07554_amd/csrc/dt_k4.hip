@@ -1,0 +1,826 @@
+// Batched local Delaunay triangulations on gfx950 (the "parallel
+// triangulation" step of Algorithm 1, and the sample and border
+// triangulations, which reuse it).
+//
+// Every set of a job is triangulated at once, in synchronous rounds of
+// parallel Bowyer-Watson insertion over all sets together:
+//   pick     every uninserted point bids for the cell it lies in; each cell
+//            keeps its lowest random key (one candidate per cell);
+//   cavity   each candidate grows its conflict region (cells whose
+//            circumsphere strictly contains it, or hull cells whose facet it
+//            sees) and claims those cells and the cells around them with
+//            its key (atomic minimum);
+//   insert   a candidate whose cavity cells and surrounding cells carry no
+//            smaller key wins: no other winner touches its cavity or its
+//            shell, so winners retriangulate independently, exactly as a
+//            sequential insertion would;
+//   relocate points whose cell was destroyed walk to their new cell.
+// The globally smallest key always wins, so every round makes progress.
+// Because the result of each round equals a sequence of ordinary
+// insertions, the final triangulation is the unique (perturbed) Delaunay
+// triangulation of each set.
+//
+// Why cavities rather than flips: a batch of simultaneous 1-to-4 splits
+// followed by parallel flipping can stall in 3D on configurations no flip
+// repairs; cavity insertion with priority claims always terminates.
+//
+// Data layout (HBM): cells as uint4 vertices + uint4 neighbours
+// (neighbour = cell << 2 | facet index in the neighbour), one 64-bit claim
+// word per cell for the candidate, cavity and shell claims.  New cells are
+// always appended (old slots are never reused within a job), so a
+// destroyed cell keeps its data and a forward pointer for the walk.
+#include "dt_common.hpp"
+#include "dt_internal.hpp"
+#include "dt_pred.hpp"
+
+namespace dtk {
+
+constexpr int BLOCK = 256;
+
+struct K4Args {
+  const double4* pts;
+  const uint32_t* pset;
+  const uint32_t* set_off;
+  uint32_t* ploc;
+  uint4* cv;
+  uint4* cn;
+  uint32_t* cfwd;
+  unsigned long long* ccand;
+  unsigned long long* ccav;
+  unsigned long long* cshell;
+  uint32_t* cpos;
+  uint32_t* set_cell0;
+  uint32_t* cand_pt;
+  uint32_t* cand_n;
+  uint32_t* cav;
+  uint32_t* cavinfo;
+  Counters* ctr;
+  uint32_t npts;
+  uint32_t nsets;
+  uint32_t cap;
+  uint32_t maxcand;
+  uint32_t cavcap;
+  uint32_t round;
+  int fp32;
+};
+
+// ------------------------------------------------------------ helpers
+__device__ __forceinline__ uint32_t vat(const uint4& v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ void vset(uint4& v, int i, uint32_t x) {
+  if (i == 0) v.x = x;
+  else if (i == 1) v.y = x;
+  else if (i == 2) v.z = x;
+  else v.w = x;
+}
+
+__device__ __forceinline__ void load_pt(const double4* pts, uint32_t v, double* p,
+                                        unsigned long long& key) {
+  double4 t = pts[v];
+  p[0] = t.x;
+  p[1] = t.y;
+  p[2] = t.z;
+  key = (unsigned long long)__double_as_longlong(t.w);
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Candidate key: newer rounds compare smaller (so stale claims never win),
+// then a random 16-bit priority, then the point index (unique).
+__device__ __forceinline__ unsigned long long make_key(uint32_t round, uint32_t p) {
+  uint32_t h = hash32(p * 0x9E3779B9u + round * 0x85EBCA6Bu + 0x632BE5ABu);
+  return ((unsigned long long)((~round) & 0xFFFFu) << 48) |
+         ((unsigned long long)(h >> 16) << 32) | (unsigned long long)p;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// One slot per lane that asks for one; a single atomic per wave.
+__device__ __forceinline__ uint32_t wave_alloc(bool want, uint32_t* ctr) {
+  unsigned long long m = __ballot(want);
+  if (m == 0) return 0xFFFFFFFFu;
+  int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if ((int)lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  uint32_t below = (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
+  return want ? base + below : 0xFFFFFFFFu;
+}
+
+// n slots per lane (n may be 0); a single atomic per wave.
+__device__ __forceinline__ uint32_t wave_alloc_n(uint32_t n, uint32_t* ctr) {
+  uint32_t lane = lane_id();
+  uint32_t x = n;
+  for (int off = 1; off < warpSize; off <<= 1) {
+    uint32_t y = __shfl_up(x, off);
+    if ((int)lane >= off) x += y;
+  }
+  uint32_t total = __shfl(x, warpSize - 1);
+  uint32_t base = 0;
+  if ((int)lane == warpSize - 1 && total) base = atomicAdd(ctr, total);
+  base = __shfl(base, warpSize - 1);
+  return base + x - n;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  for (int off = warpSize / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Predicate counters, flushed once per wave at kernel end.
+template <int D>
+__device__ __forceinline__ void flush_pred(Counters* ctr, const PredStats& s) {
+  const int io = (D == 2) ? 0 : 1, ii = (D == 2) ? 2 : 3;
+  uint32_t v[6] = {s.calls[0], s.f32ok[0], s.exact[0], s.calls[1], s.f32ok[1], s.exact[1]};
+#pragma unroll
+  for (int j = 0; j < 6; j++) v[j] = wave_sum(v[j]);
+  if (lane_id() == 0) {
+    if (v[0]) {
+      atomicAdd(&ctr->pred[io][0], (unsigned long long)v[0]);
+      atomicAdd(&ctr->pred[io][1], (unsigned long long)v[1]);
+      atomicAdd(&ctr->pred[io][2], (unsigned long long)(v[0] - v[1] - v[2]));
+      atomicAdd(&ctr->pred[io][3], (unsigned long long)v[2]);
+    }
+    if (v[3]) {
+      atomicAdd(&ctr->pred[ii][0], (unsigned long long)v[3]);
+      atomicAdd(&ctr->pred[ii][1], (unsigned long long)v[4]);
+      atomicAdd(&ctr->pred[ii][2], (unsigned long long)(v[3] - v[4] - v[5]));
+      atomicAdd(&ctr->pred[ii][3], (unsigned long long)v[5]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ conflict
+// q lies in the hyperplane of a hull facet: decide with the facet's own
+// (D-1)-dimensional circumsphere under the same perturbed lifting.  With an
+// auxiliary point e off the hyperplane, the sphere through the facet and e
+// meets the hyperplane exactly in the facet's circumsphere, so q is inside
+// it iff In_pert(facet, e, q) has the sign of Orient1(facet, e); e carries
+// no perturbation and the answer does not depend on which e is used.
+template <int D>
+__device__ __noinline__ int conflict_coplanar(const double4* pts, uint32_t* flags, int fp32,
+                                              uint4 v, int inf, uint32_t q) {
+  Pred pr;
+  pr.init(flags, fp32 != 0);
+  PtsX X;
+  double F[3][3];
+  unsigned long long fk[3];
+  int nf = 0;
+#pragma unroll
+  for (int i = 0; i <= D; i++)
+    if (i != inf) {
+      load_pt(pts, vat(v, i), F[nf], fk[nf]);
+      nf++;
+    }
+  int axis = 0;
+  if (D == 2) {
+    axis = (F[0][1] != F[1][1]) ? 0 : 1;
+  } else {
+    axis = -1;
+    for (int ax = 0; ax < 3 && axis < 0; ax++) {
+      PtsX Y;
+      for (int j = 0; j < 3; j++) {
+        int t = 0;
+        for (int k = 0; k < 3; k++)
+          if (k != ax) Y.p[j][t++] = F[j][k];
+        Y.p[j][2] = 0.0;
+      }
+      if (pr.orient<2>(Y) != 0) axis = ax;
+    }
+    if (axis < 0) return 0;
+  }
+  double e[3] = {F[0][0], F[0][1], D == 3 ? F[0][2] : 0.0};
+  double a0 = F[0][axis];
+  e[axis] = (a0 == 0.0) ? 1.0 : (fabs(a0) < 1e300 ? 2.0 * a0 : 0.5 * a0);
+  int t = 0;
+  for (int i = 0; i <= D; i++) {
+    if (i == inf) {
+      X.p[i][0] = e[0]; X.p[i][1] = e[1]; X.p[i][2] = e[2];
+      X.key[i] = NOKEY;
+    } else {
+      X.p[i][0] = F[t][0]; X.p[i][1] = F[t][1]; X.p[i][2] = F[t][2];
+      X.key[i] = fk[t];
+      t++;
+    }
+  }
+  int oe = pr.orient<D>(X);
+  load_pt(pts, q, X.p[D + 1], X.key[D + 1]);
+  int s = pr.insphere<D>(X);
+  return (s != 0 && s == oe) ? 1 : 0;
+}
+
+// Is point q (coordinates qp, key qk) in conflict with the cell with
+// vertices v?
+template <int D>
+__device__ __forceinline__ bool conflict(const K4Args& a, Pred& pr, uint4 v, uint32_t q,
+                                         const double* qp, unsigned long long qk) {
+  int inf = -1;
+#pragma unroll
+  for (int i = 0; i <= D; i++)
+    if (vat(v, i) == INF_V) inf = i;
+  PtsX X;
+  if (inf < 0) {
+#pragma unroll
+    for (int i = 0; i <= D; i++) load_pt(a.pts, vat(v, i), X.p[i], X.key[i]);
+    X.p[D + 1][0] = qp[0]; X.p[D + 1][1] = qp[1]; X.p[D + 1][2] = qp[2];
+    X.key[D + 1] = qk;
+    return pr.insphere<D>(X) > 0;
+  }
+#pragma unroll
+  for (int i = 0; i <= D; i++) {
+    if (i == inf) {
+      X.p[i][0] = qp[0]; X.p[i][1] = qp[1]; X.p[i][2] = qp[2];
+      X.key[i] = qk;
+    } else {
+      load_pt(a.pts, vat(v, i), X.p[i], X.key[i]);
+    }
+  }
+  int o = pr.orient<D>(X);
+  if (o != 0) return o > 0;
+  return conflict_coplanar<D>(a.pts, &a.ctr->flags, a.fp32, v, inf, q) != 0;
+}
+
+// Visibility walk from cell c to a cell in conflict with q: inside a
+// finite cell (closed), or a hull cell whose facet q sees.
+template <int D>
+__device__ uint32_t walk(const K4Args& a, Pred& pr, uint32_t c, uint32_t q, const double* qp,
+                         unsigned long long qk) {
+  for (int step = 0; step < (1 << 16); step++) {
+    if (c >= a.cap) break;
+    uint4 v = a.cv[c];
+    int inf = -1;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i <= D; i++) {
+      uint32_t w = vat(v, i);
+      if (w == INF_V) inf = i;
+      else if (w >= a.npts) bad = true;
+    }
+    if (bad) break;
+    if (inf >= 0) {
+      if (conflict<D>(a, pr, v, q, qp, qk)) return c;
+      c = vat(a.cn[c], inf) >> 2;
+      continue;
+    }
+    PtsX X;
+    double P[D + 1][3];
+    unsigned long long kk;
+#pragma unroll
+    for (int j = 0; j <= D; j++) load_pt(a.pts, vat(v, j), P[j], kk);
+    int exitf = -1;
+#pragma unroll
+    for (int i = 0; i <= D; i++) {
+      if (exitf >= 0) break;
+#pragma unroll
+      for (int j = 0; j <= D; j++) {
+        const double* s = (j == i) ? qp : P[j];
+        X.p[j][0] = s[0]; X.p[j][1] = s[1]; X.p[j][2] = s[2];
+      }
+      if (pr.orient<D>(X) < 0) exitf = i;
+    }
+    if (exitf < 0) return c;
+    c = vat(a.cn[c], exitf) >> 2;
+  }
+  atomicOr(&a.ctr->flags, FAIL_WALK);
+  return 0;
+}
+
+// ------------------------------------------------------------ set setup
+// One thread per set: the first D+1 affinely independent points (in index
+// order) form the initial cell, plus one hull cell per facet.
+template <int D>
+__global__ void k4_init_sets(K4Args a) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.nsets) return;
+  Pred pr;
+  pr.init(&a.ctr->flags, a.fp32 != 0);
+  uint32_t lo = a.set_off[s], hi = a.set_off[s + 1];
+  uint32_t iv[4] = {0, 0, 0, NOSLOT};
+  int ni = 0;
+  double P[4][3];
+  unsigned long long K[4];
+  if (hi - lo >= (uint32_t)(D + 1)) {
+    iv[0] = lo;
+    load_pt(a.pts, lo, P[0], K[0]);
+    ni = 1;
+    for (uint32_t p = lo + 1; p < hi && ni < D + 1; p++) {
+      double c[3];
+      unsigned long long kc;
+      load_pt(a.pts, p, c, kc);
+      bool ok = false;
+      if (ni == 1) {
+        ok = true;
+      } else if (ni == 2 && D == 3) {
+        for (int ax = 0; ax < 3 && !ok; ax++) {
+          PtsX Y;
+          const double* src[3] = {P[0], P[1], c};
+          for (int j = 0; j < 3; j++) {
+            int t = 0;
+            for (int k = 0; k < 3; k++)
+              if (k != ax) Y.p[j][t++] = src[j][k];
+            Y.p[j][2] = 0.0;
+          }
+          ok = pr.orient<2>(Y) != 0;
+        }
+      } else {
+        PtsX Y;
+        for (int j = 0; j < ni; j++)
+          for (int k = 0; k < 3; k++) Y.p[j][k] = P[j][k];
+        for (int k = 0; k < 3; k++) Y.p[ni][k] = c[k];
+        ok = pr.orient<D>(Y) != 0;
+      }
+      if (ok) {
+        iv[ni] = p;
+        for (int k = 0; k < 3; k++) P[ni][k] = c[k];
+        K[ni] = kc;
+        ni++;
+      }
+    }
+  }
+  if (ni < D + 1) {
+    a.set_cell0[s] = DONE;
+    return;
+  }
+  {
+    PtsX Y;
+    for (int j = 0; j <= D; j++)
+      for (int k = 0; k < 3; k++) Y.p[j][k] = P[j][k];
+    if (pr.orient<D>(Y) < 0) {
+      uint32_t t = iv[0]; iv[0] = iv[1]; iv[1] = t;
+    }
+  }
+  uint32_t base = atomicAdd(&a.ctr->cells, (uint32_t)(D + 2));
+  if (base + D + 2 > a.cap) {
+    atomicOr(&a.ctr->flags, FAIL_CELL_POOL);
+    a.set_cell0[s] = DONE;
+    return;
+  }
+  uint4 cells[5];
+  cells[0] = make_uint4(iv[0], iv[1], iv[2], D == 3 ? iv[3] : NOSLOT);
+  for (int i = 0; i <= D; i++) {
+    uint4 w = cells[0];
+    vset(w, i, INF_V);
+    int x = (i == 0) ? 1 : 0, y = (i <= 1) ? 2 : 1;   // two finite slots
+    uint32_t t = vat(w, x);
+    vset(w, x, vat(w, y));
+    vset(w, y, t);
+    cells[i + 1] = w;
+  }
+  // adjacency by facet matching among the D+2 cells
+  for (int x = 0; x < D + 2; x++) {
+    uint4 nb = make_uint4(0, 0, 0, 0);
+    for (int sl = 0; sl <= D; sl++) {
+      for (int y = 0; y < D + 2; y++) {
+        if (y == x) continue;
+        int shared = 0, other = -1;
+        for (int r = 0; r <= D; r++) {
+          uint32_t vy = vat(cells[y], r);
+          bool in = false;
+          for (int l = 0; l <= D; l++)
+            if (l != sl && vat(cells[x], l) == vy) in = true;
+          if (in) shared++;
+          else other = r;
+        }
+        if (shared == D) vset(nb, sl, ((base + y) << 2) | (uint32_t)other);
+      }
+    }
+    if (D == 2) nb.w = NOSLOT;
+    a.cv[base + x] = cells[x];
+    a.cn[base + x] = nb;
+  }
+  for (int j = 0; j <= D; j++) a.ploc[iv[j]] = DONE;
+  a.set_cell0[s] = base;
+}
+
+// One thread per point: locate in the initial triangulation of its set.
+template <int D>
+__global__ void k4_locate_init(K4Args a) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  Pred pr;
+  pr.init(&a.ctr->flags, a.fp32 != 0);
+  bool act = false;
+  if (p < a.npts) {
+    uint32_t c0 = a.set_cell0[a.pset[p]];
+    if (c0 == DONE) {
+      a.ploc[p] = DONE;
+    } else if (a.ploc[p] != DONE) {
+      double qp[3];
+      unsigned long long qk;
+      load_pt(a.pts, p, qp, qk);
+      a.ploc[p] = walk<D>(a, pr, c0, p, qp, qk);
+      act = true;
+    }
+  }
+  uint32_t c = wave_sum(act ? 1u : 0u);
+  if (lane_id() == 0 && c) atomicAdd(&a.ctr->active, c);
+  flush_pred<D>(a.ctr, pr.st);
+}
+
+// ------------------------------------------------------------ rounds
+__global__ void k4_pick(K4Args a) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.npts) return;
+  uint32_t L = a.ploc[p];
+  if (L == DONE) return;
+  atomicMin(&a.ccand[L], make_key(a.round, p));
+}
+
+template <int D>
+__global__ void k4_cavity(K4Args a) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  Pred pr;
+  pr.init(&a.ctr->flags, a.fp32 != 0);
+  bool want = false;
+  uint32_t L = DONE;
+  unsigned long long K = 0;
+  if (p < a.npts) {
+    L = a.ploc[p];
+    if (L != DONE) {
+      K = make_key(a.round, p);
+      want = (a.ccand[L] == K);
+    }
+  }
+  uint32_t slot = wave_alloc(want, &a.ctr->ncand);
+  bool gaveup = false;
+  uint32_t n = 0;
+  if (want && slot < a.maxcand) {
+    a.cand_pt[slot] = p;
+    uint32_t* list = a.cav + (size_t)slot * a.cavcap;
+    double qp[3];
+    unsigned long long qk;
+    load_pt(a.pts, p, qp, qk);
+    bool ok = atomicMin(&a.ccav[L], K) > K;
+    if (ok) {
+      list[0] = L;
+      n = 1;
+    }
+    for (uint32_t h = 0; h < n && ok; h++) {
+      uint32_t c = list[h];
+      uint4 nb = a.cn[c];
+#pragma unroll
+      for (int i = 0; i <= D; i++) {
+        if (!ok) break;
+        uint32_t t = vat(nb, i) >> 2;
+        if (t >= a.cap) {
+          atomicOr(&a.ctr->flags, FAIL_INVARIANT);
+          ok = false;
+          break;
+        }
+        {
+          uint4 tv = a.cv[t];
+          bool badv = false;
+#pragma unroll
+          for (int r = 0; r <= D; r++)
+            if (vat(tv, r) != INF_V && vat(tv, r) >= a.npts) badv = true;
+          if (badv) {
+            atomicOr(&a.ctr->flags, FAIL_INVARIANT);
+            ok = false;
+            break;
+          }
+        }
+        unsigned long long cc = __atomic_load_n(&a.ccav[t], __ATOMIC_RELAXED);
+        if (cc == K) continue;
+        if (cc < K) { ok = false; break; }
+        if (__atomic_load_n(&a.cshell[t], __ATOMIC_RELAXED) == K) continue;
+        if (conflict<D>(a, pr, a.cv[t], p, qp, qk)) {
+          unsigned long long old = atomicMin(&a.ccav[t], K);
+          if (old < K) { ok = false; break; }
+          if (old == K) continue;
+          if (n >= a.cavcap) { ok = false; gaveup = true; break; }
+          list[n++] = t;
+        } else {
+          atomicMin(&a.cshell[t], K);
+        }
+      }
+    }
+    a.cand_n[slot] = ok ? n : 0u;
+  }
+  uint32_t g = wave_sum(gaveup ? 1u : 0u);
+  uint32_t mx = (want && slot < a.maxcand) ? n : 0u;
+  for (int off = warpSize / 2; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, off));
+  if (lane_id() == 0) {
+    if (g) atomicAdd(&a.ctr->overflow, g);
+    if (mx) atomicMax(&a.ctr->maxcav, mx);
+  }
+  flush_pred<D>(a.ctr, pr.st);
+}
+
+// New cell index of boundary facet (cavity position h, facet f).
+__device__ __forceinline__ uint32_t facet_cell(uint32_t info, int f, uint32_t base) {
+  uint32_t mask = info & 0xFFu, pre = info >> 8;
+  return base + pre + (uint32_t)__popc(mask & ((1u << f) - 1u));
+}
+
+template <int D>
+__global__ void k4_insert(K4Args a) {
+  uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t ncand = min(a.ctr->ncand, a.maxcand);
+  uint32_t n = 0, p = 0;
+  unsigned long long K = 0;
+  bool win = false;
+  uint32_t* list = nullptr;
+  uint32_t* info = nullptr;
+  if (slot < ncand) {
+    n = a.cand_n[slot];
+    if (n > 0) {
+      p = a.cand_pt[slot];
+      K = make_key(a.round, p);
+      list = a.cav + (size_t)slot * a.cavcap;
+      info = a.cavinfo + (size_t)slot * a.cavcap;
+      win = true;
+      for (uint32_t h = 0; h < n && win; h++) {
+        uint32_t c = list[h];
+        if (a.ccav[c] != K || a.cshell[c] <= K) win = false;
+      }
+      for (uint32_t h = 0; h < n && win; h++) {
+        uint4 nb = a.cn[list[h]];
+#pragma unroll
+        for (int i = 0; i <= D; i++) {
+          uint32_t t = vat(nb, i) >> 2;
+          if (t >= a.cap) {
+            win = false;
+            atomicOr(&a.ctr->flags, FAIL_INVARIANT);
+            break;
+          }
+          unsigned long long cc = a.ccav[t];
+          if (cc != K && cc < K) win = false;
+        }
+      }
+    }
+  }
+  // boundary facets: one new cell each
+  uint32_t nbf = 0;
+  if (win) {
+    for (uint32_t h = 0; h < n; h++) {
+      uint32_t c = list[h];
+      uint4 nb = a.cn[c];
+      uint32_t mask = 0;
+#pragma unroll
+      for (int i = 0; i <= D; i++)
+        if (a.ccav[vat(nb, i) >> 2] != K) mask |= 1u << i;
+      info[h] = (nbf << 8) | mask;
+      nbf += (uint32_t)__popc(mask);
+      a.cpos[c] = h;
+    }
+  }
+  uint32_t base = wave_alloc_n(win ? nbf : 0u, &a.ctr->cells);
+  if (win && base + nbf > a.cap) {
+    atomicOr(&a.ctr->flags, FAIL_CELL_POOL);
+    win = false;
+  }
+  if (win) {
+    uint32_t* cnw = reinterpret_cast<uint32_t*>(a.cn);
+    for (uint32_t h = 0; h < n; h++) {
+      uint32_t c = list[h];
+      uint32_t inf = info[h];
+      uint32_t mask = inf & 0xFFu;
+      if (!mask) continue;
+      uint4 vc = a.cv[c];
+      uint4 nc = a.cn[c];
+#pragma unroll
+      for (int i = 0; i <= D; i++) {
+        if (!(mask >> i & 1u)) continue;
+        uint32_t x = facet_cell(inf, i, base);
+        uint4 nv = vc;
+        vset(nv, i, p);
+        uint4 nn = make_uint4(0, 0, 0, NOSLOT);
+        uint32_t out = vat(nc, i);
+        vset(nn, i, out);
+        cnw[(size_t)(out >> 2) * 4 + (out & 3u)] = (x << 2) | (uint32_t)i;
+#pragma unroll
+        for (int j = 0; j <= D; j++) {
+          if (j == i) continue;
+          // rotate around the ridge (vertices of c except slots i, j)
+          // through the cavity until a boundary facet is reached
+          uint32_t cur = c;
+          int sin = i, sout = j;
+          uint4 vcur = vc;
+          uint32_t link = 0xFFFFFFFFu;
+          for (int step = 0; step < 4096; step++) {
+            uint32_t nbr = vat(a.cn[cur], sout);
+            uint32_t ncell = nbr >> 2;
+            if (ncell >= a.cap) break;
+            if (a.ccav[ncell] != K) {
+              uint32_t xp = facet_cell(info[a.cpos[cur]], sout, base);
+              link = (xp << 2) | (uint32_t)sin;
+              break;
+            }
+            uint32_t av = vat(vcur, sin);
+            uint4 vn = a.cv[ncell];
+            int nout = 0;
+#pragma unroll
+            for (int r = 0; r <= D; r++)
+              if (vat(vn, r) == av) nout = r;
+            cur = ncell;
+            sin = (int)(nbr & 3u);
+            sout = nout;
+            vcur = vn;
+          }
+          if (link == 0xFFFFFFFFu) {
+            atomicOr(&a.ctr->flags, FAIL_PIVOT);
+            link = (x << 2) | (uint32_t)j;   // in-bounds placeholder; the run is abandoned
+          }
+          vset(nn, j, link);
+        }
+        a.cv[x] = nv;
+        a.cn[x] = nn;
+      }
+    }
+    for (uint32_t h = 0; h < n; h++) a.cfwd[list[h]] = base;
+    a.ploc[p] = DONE;
+  }
+  uint32_t w = wave_sum(win ? 1u : 0u);
+  if (lane_id() == 0 && w) atomicAdd(&a.ctr->inserted, w);
+}
+
+template <int D>
+__global__ void k4_relocate(K4Args a) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  Pred pr;
+  pr.init(&a.ctr->flags, a.fp32 != 0);
+  if (p < a.npts) {
+    uint32_t L = a.ploc[p];
+    if (L != DONE) {
+      uint32_t f = a.cfwd[L];
+      if (f != ALIVE) {
+        double qp[3];
+        unsigned long long qk;
+        load_pt(a.pts, p, qp, qk);
+        a.ploc[p] = walk<D>(a, pr, f, p, qp, qk);
+      }
+    }
+  }
+  flush_pred<D>(a.ctr, pr.st);
+}
+
+// ------------------------------------------------------------ extraction
+template <int D>
+__global__ void k4_extract_rows(const double4* pts, const uint32_t* pset, const uint4* cv,
+                                const uint32_t* cfwd, uint32_t ncells, int32_t* rows,
+                                uint32_t* count, uint32_t* set_rows) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  bool take = false;
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (c < ncells && cfwd[c] == ALIVE) {
+    v = cv[c];
+    take = true;
+#pragma unroll
+    for (int i = 0; i <= D; i++)
+      if (vat(v, i) == INF_V) take = false;
+  }
+  uint32_t slot = wave_alloc(take, count);
+  if (take) {
+    if (set_rows) atomicAdd(&set_rows[pset[v.x]], 1u);
+    if (rows) {
+      int32_t k[4];
+#pragma unroll
+      for (int i = 0; i <= D; i++) k[i] = (int32_t)__double_as_longlong(pts[vat(v, i)].w);
+      // sort ascending
+#pragma unroll
+      for (int i = 1; i <= D; i++)
+#pragma unroll
+        for (int j = i; j > 0; j--)
+          if (k[j] < k[j - 1]) { int32_t t = k[j]; k[j] = k[j - 1]; k[j - 1] = t; }
+#pragma unroll
+      for (int i = 0; i <= D; i++) rows[(size_t)slot * (D + 1) + i] = k[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ host driver
+static inline uint32_t nblk(uint32_t n) { return (n + BLOCK - 1) / BLOCK; }
+
+int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, hipStream_t st,
+           K4Stats& ks) {
+  const int D = job.D;
+  uint32_t npts = job.npts;
+  // cell pool: every insertion appends one cell per boundary facet
+  size_t cap = (size_t)npts * (D == 2 ? 12 : 40) + (size_t)job.nsets * 8 + 4096;
+  if (cap > 0xF0000000ull / 1) cap = 0xF0000000ull;
+  if (cap > (1ull << 30) - 1) cap = (1ull << 30) - 1;   // neighbour encoding uses 30 bits
+  pool.cap = (uint32_t)cap;
+  DT_TRY(pool.cv.alloc(cap * sizeof(uint4)));
+  DT_TRY(pool.cn.alloc(cap * sizeof(uint4)));
+  DT_TRY(pool.cfwd.alloc(cap * sizeof(uint32_t)));
+  DT_TRY(pool.ccand.alloc(cap * 8));
+  DT_TRY(pool.ccav.alloc(cap * 8));
+  DT_TRY(pool.cshell.alloc(cap * 8));
+  DT_TRY(pool.cpos.alloc(cap * sizeof(uint32_t)));
+  DT_TRY(pool.set_cell0.alloc((size_t)job.nsets * sizeof(uint32_t)));
+  DT_HIP(hipMemsetAsync(pool.cfwd.p, 0xFF, cap * sizeof(uint32_t), st));
+  DT_HIP(hipMemsetAsync(pool.ccand.p, 0xFF, cap * 8, st));
+  DT_HIP(hipMemsetAsync(pool.ccav.p, 0xFF, cap * 8, st));
+  DT_HIP(hipMemsetAsync(pool.cshell.p, 0xFF, cap * 8, st));
+
+  uint32_t cavcap = (D == 2) ? 96 : 192;
+  uint32_t maxcand = npts < (1u << 19) ? (npts ? npts : 1) : (1u << 19);
+  DevBuf ploc, cand_pt, cand_n, cav, cavinfo;
+  DT_TRY(ploc.alloc((size_t)npts * 4));
+  DT_TRY(cand_pt.alloc((size_t)maxcand * 4));
+  DT_TRY(cand_n.alloc((size_t)maxcand * 4));
+  DT_TRY(cav.alloc((size_t)maxcand * cavcap * 4));
+  DT_TRY(cavinfo.alloc((size_t)maxcand * cavcap * 4));
+  DT_HIP(hipMemsetAsync(ploc.p, 0, (size_t)npts * 4, st));
+  DT_HIP(hipMemsetAsync(dctr, 0, sizeof(Counters), st));
+
+  K4Args a;
+  a.pts = job.pts;
+  a.pset = job.pset;
+  a.set_off = job.set_off;
+  a.ploc = ploc.as<uint32_t>();
+  a.cv = pool.cv.as<uint4>();
+  a.cn = pool.cn.as<uint4>();
+  a.cfwd = pool.cfwd.as<uint32_t>();
+  a.ccand = pool.ccand.as<unsigned long long>();
+  a.ccav = pool.ccav.as<unsigned long long>();
+  a.cshell = pool.cshell.as<unsigned long long>();
+  a.cpos = pool.cpos.as<uint32_t>();
+  a.set_cell0 = pool.set_cell0.as<uint32_t>();
+  a.cand_pt = cand_pt.as<uint32_t>();
+  a.cand_n = cand_n.as<uint32_t>();
+  a.cav = cav.as<uint32_t>();
+  a.cavinfo = cavinfo.as<uint32_t>();
+  a.ctr = dctr;
+  a.npts = npts;
+  a.nsets = job.nsets;
+  a.cap = pool.cap;
+  a.maxcand = maxcand;
+  a.cavcap = cavcap;
+  a.round = 0;
+  a.fp32 = job.fp32 ? 1 : 0;
+
+  if (D == 2) {
+    hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL(k4_locate_init<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(k4_init_sets<3>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL(k4_locate_init<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+  }
+  DT_HIP(hipGetLastError());
+  DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  if (hctr->flags) return DT_E_INTERNAL;
+  uint64_t remaining = hctr->active;
+  int stall = 0;
+  uint32_t round = 1;
+  ks.maxcav = 0;
+  while (remaining > 0) {
+    if (round >= 0xFFF0u) return DT_E_INTERNAL;
+    a.round = round;
+    DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 3 * sizeof(uint32_t), st));   // ncand, inserted, overflow
+    hipLaunchKernelGGL(k4_pick, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+    if (D == 2) {
+      hipLaunchKernelGGL(k4_cavity<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_insert<2>, dim3(nblk(maxcand)), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_relocate<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+    } else {
+      hipLaunchKernelGGL(k4_cavity<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_insert<3>, dim3(nblk(maxcand)), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_relocate<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+    }
+    DT_HIP(hipGetLastError());
+    DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    if (hctr->flags) { ks.rounds = (int)round; return DT_E_INTERNAL; }
+    uint32_t ins = hctr->inserted;
+    if (ins == 0) {
+      if (++stall > 8) { ks.rounds = (int)round; return DT_E_INTERNAL; }
+    } else {
+      stall = 0;
+    }
+    remaining -= ins;
+    round++;
+  }
+  ks.rounds = (int)(round - 1);
+  ks.maxcav = hctr->maxcav;
+  pool.ncells = hctr->cells;
+  for (int i = 0; i < 4; i++)
+    for (int j = 0; j < 4; j++) ks.pred[i][j] = hctr->pred[i][j];
+  return DT_OK;
+}
+
+int k4_extract(const LocalJob& job, const CellPool& pool, int32_t* rows, uint32_t* count_dev,
+               uint32_t* set_rows, hipStream_t st) {
+  DT_HIP(hipMemsetAsync(count_dev, 0, sizeof(uint32_t), st));
+  if (pool.ncells == 0) return DT_OK;
+  if (job.D == 2)
+    hipLaunchKernelGGL(k4_extract_rows<2>, dim3(nblk(pool.ncells)), dim3(BLOCK), 0, st, job.pts,
+                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, rows,
+                       count_dev, set_rows);
+  else
+    hipLaunchKernelGGL(k4_extract_rows<3>, dim3(nblk(pool.ncells)), dim3(BLOCK), 0, st, job.pts,
+                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, rows,
+                       count_dev, set_rows);
+  DT_HIP(hipGetLastError());
+  return DT_OK;
+}
+
+}  // namespace dtk

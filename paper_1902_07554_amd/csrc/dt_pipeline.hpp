@@ -1,0 +1,37 @@
+// The divide-and-conquer pipeline (host orchestration over device stages).
+#pragma once
+#include <vector>
+
+#include "dt_internal.hpp"
+
+struct dt_result {
+  int D = 3;
+  int64_t m = 0;                      // simplices
+  dtk::DevBuf rows;                   // m x (D+1) int32, device
+  std::vector<int64_t> set_offsets;   // batch results: row offsets per set
+  dt_stats stats{};
+  std::vector<char> stage[DT_NUM_ARR];
+};
+
+namespace dtk {
+
+// Per-call context: counters and flags in device and pinned host memory.
+struct Ctx {
+  DevBuf dctr, dflag;
+  Counters* hctr = nullptr;
+  uint32_t* hflag = nullptr;
+  ~Ctx();
+  int init();
+  Counters* dc() const { return dctr.as<Counters>(); }
+};
+
+double now_ms();
+
+int run_triangulate(const double* points, int64_t n, int D, int k, double sample_rate,
+                    const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+int run_dc(const double* points, int64_t n, int D, int k, double sample_rate,
+           const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, int64_t num_sets,
+              int D, const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+
+}  // namespace dtk
