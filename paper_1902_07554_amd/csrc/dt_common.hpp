@@ -35,9 +35,9 @@ struct Counters {
   unsigned int ncand;             // candidates this round
   unsigned int inserted;          // points inserted this round
   unsigned int overflow;          // candidates that gave up (cavity too large)
+  unsigned int extused;           // cavity extension chunks taken this round
   unsigned int maxcav;            // largest cavity seen
   unsigned int active;            // points still to insert
-  unsigned int pad;
 };
 
 }  // namespace dtk

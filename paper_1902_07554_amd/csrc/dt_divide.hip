@@ -1,0 +1,688 @@
+// Divide step on the GPU.
+//
+// Sample-based divide (paper, Algorithm 2):
+//   1. choose eta(n) points uniformly at random without replacement -- the
+//      eta points with the smallest keys splitmix64(seed ^ id*golden), ties
+//      by id (a histogram of the top 16 key bits finds the threshold bucket;
+//      its few members are ordered exactly);
+//   2. triangulate the sample (the batched local-DT kernels, one set);
+//   3. graph G = (sample, Delaunay edges, w) with the weights of the paper's
+//      Table "weights", d = |v-w| / d*, d* = bounding-box diagonal;
+//   4. balanced k-way partition of G, |V_i| <= (1+eps) ceil(|V|/k): chunks
+//      of the sample in Morton order, then label-propagation sweeps that
+//      move vertices to the block they are most strongly connected to when
+//      the gain is positive and the target block has room (proposals into a
+//      block are ranked by gain, then vertex id, so the result does not
+//      depend on thread timing);
+//   5. every point gets the block of its nearest sample point, key
+//      (fl(d^2), sample id) with d^2 = ((dx dx + dy dy) + dz dz) rounded
+//      after each operation; the search visits grid shells around the point
+//      and stops once no unvisited cell can hold a closer sample, with a
+//      margin far above the rounding error of d^2, so the result is the
+//      exact argmin of the key.
+// kd divide (Section "Recursive Bisection", the cyclic scheme): log2 k
+// levels; at level l every block is split at the median of coordinate
+// l mod D, the lower half being the floor(m/2) smallest (coordinate, id).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "dt_common.hpp"
+#include "dt_internal.hpp"
+#include "dt_prims.hpp"
+#include "dt_stages.hpp"
+
+namespace dtk {
+
+constexpr int DB = 256;
+static inline uint32_t dblocks(uint64_t n) { return (uint32_t)((n + DB - 1) / DB); }
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ unsigned long long sample_key(unsigned long long seed, uint32_t id) {
+  return splitmix64(seed ^ ((unsigned long long)id * 0x9E3779B97F4A7C15ull));
+}
+
+// ------------------------------------------------------------ 1. sample
+__global__ void k_sample_hist(uint32_t n, unsigned long long seed, uint32_t* hist) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&hist[sample_key(seed, i) >> 48], 1u);
+}
+
+__global__ void k_sample_mark(uint32_t n, unsigned long long seed, uint32_t thr, uint32_t* flag,
+                              unsigned long long* cand, uint32_t* ncand, uint32_t cap) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long k = sample_key(seed, i);
+  uint32_t top = (uint32_t)(k >> 48);
+  flag[i] = top < thr ? 1u : 0u;
+  if (top == thr) {
+    uint32_t s = atomicAdd(ncand, 1u);
+    if (s < cap) {
+      cand[2 * s] = k;
+      cand[2 * s + 1] = i;
+    }
+  }
+}
+
+__global__ void k_set_flags(const uint32_t* idx, uint32_t m, uint32_t* flag) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) flag[idx[i]] = 1u;
+}
+
+int select_sample(uint32_t n, uint32_t eta, uint64_t seed, DevBuf& sid, hipStream_t st) {
+  DevBuf hist, flag, cand, ncand;
+  DT_TRY(hist.alloc(65536 * 4));
+  DT_TRY(flag.alloc((size_t)n * 4));
+  DT_HIP(hipMemsetAsync(hist.p, 0, 65536 * 4, st));
+  hipLaunchKernelGGL(k_sample_hist, dim3(dblocks(n)), dim3(DB), 0, st, n,
+                     (unsigned long long)seed, hist.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  std::vector<uint32_t> h(65536);
+  DT_HIP(hipMemcpyAsync(h.data(), hist.p, 65536 * 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  uint32_t thr = 0, below = 0;
+  while (thr < 65536 && below + h[thr] < eta) below += h[thr++];
+  if (thr >= 65536) thr = 65535;
+  uint32_t cap = h[thr] + 16;
+  DT_TRY(cand.alloc((size_t)cap * 16));
+  DT_TRY(ncand.alloc(4));
+  DT_HIP(hipMemsetAsync(ncand.p, 0, 4, st));
+  hipLaunchKernelGGL(k_sample_mark, dim3(dblocks(n)), dim3(DB), 0, st, n,
+                     (unsigned long long)seed, thr, flag.as<uint32_t>(),
+                     cand.as<unsigned long long>(), ncand.as<uint32_t>(), cap);
+  DT_HIP(hipGetLastError());
+  uint32_t nc = 0;
+  DT_HIP(hipMemcpyAsync(&nc, ncand.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  if (nc > cap) return DT_E_INTERNAL;
+  std::vector<unsigned long long> c(2 * (size_t)nc);
+  if (nc) DT_HIP(hipMemcpyAsync(c.data(), cand.p, (size_t)nc * 16, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  std::vector<std::pair<unsigned long long, uint32_t>> v(nc);
+  for (uint32_t i = 0; i < nc; i++) v[i] = {c[2 * i], (uint32_t)c[2 * i + 1]};
+  std::sort(v.begin(), v.end());
+  uint32_t need = eta - below;
+  if (need > nc) return DT_E_INTERNAL;
+  std::vector<uint32_t> pick(need);
+  for (uint32_t i = 0; i < need; i++) pick[i] = v[i].second;
+  if (need) {
+    DevBuf dp;
+    DT_TRY(dp.alloc((size_t)need * 4));
+    DT_HIP(hipMemcpyAsync(dp.p, pick.data(), (size_t)need * 4, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_set_flags, dim3(dblocks(need)), dim3(DB), 0, st, dp.as<uint32_t>(), need,
+                       flag.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    DT_HIP(hipStreamSynchronize(st));
+  }
+  uint32_t cnt = 0;
+  DT_TRY(compact_indices(flag.as<uint32_t>(), n, sid, &cnt, st));
+  if (cnt != eta) return DT_E_INTERNAL;
+  return DT_OK;
+}
+
+__global__ void k_gather_pts(const double4* P, const uint32_t* idx, uint32_t m, double4* out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = P[idx[i]];
+}
+
+int gather_points(const double4* P, const uint32_t* idx, uint32_t m, double4* out,
+                  hipStream_t st) {
+  if (m == 0) return DT_OK;
+  hipLaunchKernelGGL(k_gather_pts, dim3(dblocks(m)), dim3(DB), 0, st, P, idx, m, out);
+  DT_HIP(hipGetLastError());
+  return DT_OK;
+}
+
+// ------------------------------------------------------------ 3. graph
+// Unique Delaunay edges of the sample triangulation through an
+// open-addressing set keyed by (u << 32 | v), u < v (sample-local ids).
+__global__ void k_edges(const uint4* cv, const uint32_t* cfwd, uint32_t ncells, int D,
+                        unsigned long long* table, uint32_t tmask, uint32_t* elist,
+                        uint32_t* ecount, uint32_t ecap) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells || cfwd[c] != ALIVE) return;
+  uint4 v4 = cv[c];
+  uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+  for (int i = 0; i <= D; i++)
+    for (int j = i + 1; j <= D; j++) {
+      uint32_t a = v[i], b = v[j];
+      if (a == INF_V || b == INF_V) continue;
+      if (a > b) { uint32_t t = a; a = b; b = t; }
+      unsigned long long key = ((unsigned long long)a << 32) | b;
+      uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 32);
+      for (uint32_t pr = 0; pr <= tmask; pr++) {
+        uint32_t s = (h + pr) & tmask;
+        unsigned long long old = atomicCAS(&table[s], ~0ull, key);
+        if (old == ~0ull) {
+          uint32_t e = atomicAdd(ecount, 1u);
+          if (e < ecap) {
+            elist[2 * e] = a;
+            elist[2 * e + 1] = b;
+          }
+          break;
+        }
+        if (old == key) break;
+      }
+    }
+}
+
+__global__ void k_degree(const uint32_t* elist, uint32_t m, uint32_t* deg) {
+  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  atomicAdd(&deg[elist[2 * e]], 1u);
+  atomicAdd(&deg[elist[2 * e + 1]], 1u);
+}
+
+__global__ void k_fill_adj(const uint32_t* elist, uint32_t m, const uint32_t* off, uint32_t* cur,
+                           uint32_t* adj) {
+  uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  uint32_t a = elist[2 * e], b = elist[2 * e + 1];
+  adj[off[a] + atomicAdd(&cur[a], 1u)] = b;
+  adj[off[b] + atomicAdd(&cur[b], 1u)] = a;
+}
+
+// Sort each adjacency list (deterministic summation order) and compute the
+// edge weights.  d* = bounding-box diagonal of the whole input.
+__global__ void k_adj_weights(const double4* S, uint32_t eta, const uint32_t* off, uint32_t* adj,
+                              double* w, int kind, double dstar) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= eta) return;
+  uint32_t a = off[v], b = off[v + 1];
+  for (uint32_t i = a + 1; i < b; i++)
+    for (uint32_t j = i; j > a && adj[j] < adj[j - 1]; j--) {
+      uint32_t t = adj[j]; adj[j] = adj[j - 1]; adj[j - 1] = t;
+    }
+  double4 p = S[v];
+  for (uint32_t i = a; i < b; i++) {
+    double4 q = S[adj[i]];
+    double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+    double d = sqrt(dx * dx + dy * dy + dz * dz) / dstar;
+    if (d < 1e-300) d = 1e-300;
+    double x;
+    switch (kind) {
+      case DT_WEIGHT_CONST: x = 1.0; break;
+      case DT_WEIGHT_INVERSE: x = 1.0 / d; break;
+      case DT_WEIGHT_LINEAR: x = 1.0 - d; break;
+      default: x = -log(d); break;
+    }
+    w[i] = x;
+  }
+}
+
+// ------------------------------------------------------------ 4. partition
+__device__ __forceinline__ unsigned long long spread3(unsigned long long x) {
+  x &= 0x1FFFFFull;
+  x = (x | (x << 32)) & 0x1F00000000FFFFull;
+  x = (x | (x << 16)) & 0x1F0000FF0000FFull;
+  x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+  x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+__device__ __forceinline__ unsigned long long spread2(unsigned long long x) {
+  x &= 0xFFFFFFFFull;
+  x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+
+__global__ void k_morton(const double4* S, uint32_t m, int D, double3 lo, double3 inv,
+                         unsigned long long* keys, uint32_t* vals) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double4 p = S[i];
+  double scale = (D == 3) ? 2097151.0 : 4294967295.0;
+  unsigned long long x = (unsigned long long)(fmin(fmax((p.x - lo.x) * inv.x, 0.0), 1.0) * scale);
+  unsigned long long y = (unsigned long long)(fmin(fmax((p.y - lo.y) * inv.y, 0.0), 1.0) * scale);
+  unsigned long long z = (unsigned long long)(fmin(fmax((p.z - lo.z) * inv.z, 0.0), 1.0) * scale);
+  keys[i] = (D == 3) ? (spread3(x) | (spread3(y) << 1) | (spread3(z) << 2))
+                     : (spread2(x) | (spread2(y) << 1));
+  vals[i] = i;
+}
+
+__global__ void k_init_blocks(const uint32_t* order, uint32_t m, uint32_t k, uint32_t* part) {
+  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  part[order[r]] = (uint32_t)(((unsigned long long)r * k) / m);
+}
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Proposal: move v to the neighbouring block with the largest connection
+// weight if that beats the current block.  Half the vertices (by a hash
+// alternating with the sweep) may move per sweep to damp oscillation.
+__global__ void k_lp_propose(uint32_t eta, const uint32_t* off, const uint32_t* adj,
+                             const double* w, const uint32_t* part, uint32_t sweep,
+                             uint32_t* pblock, double* pgain, uint32_t* pcount) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= eta) return;
+  pblock[v] = DONE;
+  if (((mix32(v) + sweep) & 1u) != 0) return;
+  uint32_t a = off[v], b = off[v + 1];
+  uint32_t cur = part[v];
+  double own = 0.0;
+  for (uint32_t i = a; i < b; i++)
+    if (part[adj[i]] == cur) own += w[i];
+  uint32_t best = DONE;
+  double bestw = 0.0;
+  for (uint32_t i = a; i < b; i++) {
+    uint32_t pb = part[adj[i]];
+    if (pb == cur) continue;
+    bool seen = false;
+    for (uint32_t j = a; j < i; j++)
+      if (part[adj[j]] == pb) { seen = true; break; }
+    if (seen) continue;
+    double c = 0.0;
+    for (uint32_t j = i; j < b; j++)
+      if (part[adj[j]] == pb) c += w[j];
+    if (c > bestw || (c == bestw && best != DONE && pb < best)) {
+      bestw = c;
+      best = pb;
+    }
+  }
+  if (best != DONE && bestw - own > 1e-12 * (bestw + own + 1.0)) {
+    pblock[v] = best;
+    pgain[v] = bestw - own;
+    atomicAdd(&pcount[best], 1u);
+  }
+}
+
+__global__ void k_lp_list(uint32_t eta, const uint32_t* pblock, const uint32_t* poff,
+                          uint32_t* pcur, uint32_t* plist) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= eta) return;
+  uint32_t b = pblock[v];
+  if (b == DONE) return;
+  plist[poff[b] + atomicAdd(&pcur[b], 1u)] = v;
+}
+
+// Accept the best proposals into each block up to its free capacity
+// (capacity measured at the start of the sweep, so the bound always holds).
+__global__ void k_lp_accept(uint32_t eta, const uint32_t* pblock, const double* pgain,
+                            const uint32_t* poff, const uint32_t* pcount, const uint32_t* plist,
+                            const int* size, int lmax, uint32_t* part, int* delta) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= eta) return;
+  uint32_t b = pblock[v];
+  if (b == DONE) return;
+  int room = lmax - size[b];
+  if (room <= 0) return;
+  double g = pgain[v];
+  uint32_t rank = 0;
+  for (uint32_t i = poff[b]; i < poff[b] + pcount[b]; i++) {
+    uint32_t u = plist[i];
+    double gu = pgain[u];
+    if (gu > g || (gu == g && u < v)) rank++;
+  }
+  if ((int)rank < room) {
+    atomicAdd(&delta[part[v]], -1);
+    atomicAdd(&delta[b], 1);
+    part[v] = b;
+  }
+}
+
+__global__ void k_apply_delta(uint32_t k, int* size, int* delta) {
+  uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= k) return;
+  size[b] += delta[b];
+  delta[b] = 0;
+}
+
+__global__ void k_cut(uint32_t eta, const uint32_t* off, const uint32_t* adj, const double* w,
+                      const uint32_t* part, double* cut) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= eta) return;
+  double c = 0.0;
+  for (uint32_t i = off[v]; i < off[v + 1]; i++)
+    if (adj[i] > v && part[adj[i]] != part[v]) c += w[i];
+  if (c != 0.0) atomicAdd(cut, c);
+}
+
+__global__ void k_count_u32(const uint32_t* x, uint32_t m, uint32_t* cnt) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) atomicAdd(&cnt[x[i]], 1u);
+}
+
+int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
+                     const dt_options& o, const double lo[3], const double hi[3],
+                     DevBuf& part, double* cut, hipStream_t st) {
+  // edges
+  uint32_t ncells = pool.ncells;
+  uint32_t tsize = 1024;
+  while (tsize < (uint64_t)ncells * (D == 3 ? 4 : 3)) tsize <<= 1;
+  DevBuf table, elist, ecount;
+  DT_TRY(table.alloc((size_t)tsize * 8));
+  uint32_t ecap = tsize;
+  DT_TRY(elist.alloc((size_t)ecap * 8));
+  DT_TRY(ecount.alloc(4));
+  DT_HIP(hipMemsetAsync(table.p, 0xFF, (size_t)tsize * 8, st));
+  DT_HIP(hipMemsetAsync(ecount.p, 0, 4, st));
+  hipLaunchKernelGGL(k_edges, dim3(dblocks(ncells)), dim3(DB), 0, st, pool.cv.as<uint4>(),
+                     pool.cfwd.as<uint32_t>(), ncells, D, table.as<unsigned long long>(),
+                     tsize - 1, elist.as<uint32_t>(), ecount.as<uint32_t>(), ecap);
+  DT_HIP(hipGetLastError());
+  uint32_t m = 0;
+  DT_HIP(hipMemcpyAsync(&m, ecount.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  if (m > ecap) return DT_E_INTERNAL;
+  DevBuf deg, off, cur, adj, w;
+  DT_TRY(deg.alloc((size_t)(eta + 1) * 4));
+  DT_TRY(off.alloc((size_t)(eta + 1) * 4));
+  DT_TRY(cur.alloc((size_t)(eta + 1) * 4));
+  DT_TRY(adj.alloc((size_t)2 * m * 4 + 4));
+  DT_TRY(w.alloc((size_t)2 * m * 8 + 8));
+  DT_HIP(hipMemsetAsync(deg.p, 0, (size_t)(eta + 1) * 4, st));
+  DT_HIP(hipMemsetAsync(cur.p, 0, (size_t)(eta + 1) * 4, st));
+  hipLaunchKernelGGL(k_degree, dim3(dblocks(m)), dim3(DB), 0, st, elist.as<uint32_t>(), m,
+                     deg.as<uint32_t>());
+  DT_TRY(exclusive_scan(deg.as<uint32_t>(), off.as<uint32_t>(), eta + 1, st));
+  hipLaunchKernelGGL(k_fill_adj, dim3(dblocks(m)), dim3(DB), 0, st, elist.as<uint32_t>(), m,
+                     off.as<uint32_t>(), cur.as<uint32_t>(), adj.as<uint32_t>());
+  double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+  double dstar = sqrt(dx * dx + dy * dy + dz * dz);
+  if (!(dstar > 0)) dstar = 1.0;
+  hipLaunchKernelGGL(k_adj_weights, dim3(dblocks(eta)), dim3(DB), 0, st, S, eta,
+                     off.as<uint32_t>(), adj.as<uint32_t>(), w.as<double>(), o.weight, dstar);
+  DT_HIP(hipGetLastError());
+  // initial blocks: Morton order of the sample, k equal chunks
+  DevBuf mk, mv;
+  DT_TRY(mk.alloc((size_t)eta * 8));
+  DT_TRY(mv.alloc((size_t)eta * 4));
+  double3 dlo = make_double3(lo[0], lo[1], lo[2]);
+  double3 inv = make_double3(dx > 0 ? 1.0 / dx : 0.0, dy > 0 ? 1.0 / dy : 0.0,
+                             dz > 0 ? 1.0 / dz : 0.0);
+  hipLaunchKernelGGL(k_morton, dim3(dblocks(eta)), dim3(DB), 0, st, S, eta, D, dlo, inv,
+                     mk.as<unsigned long long>(), mv.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  DT_TRY(radix_sort_pairs(mk.as<unsigned long long>(), mv.as<uint32_t>(), eta, 64, st));
+  DT_TRY(part.alloc((size_t)eta * 4));
+  hipLaunchKernelGGL(k_init_blocks, dim3(dblocks(eta)), dim3(DB), 0, st, mv.as<uint32_t>(), eta,
+                     k, part.as<uint32_t>());
+  // label propagation under the balance bound
+  DevBuf size, delta, pblock, pgain, pcount, poff, pcur, plist;
+  DT_TRY(size.alloc((size_t)k * 4));
+  DT_TRY(delta.alloc((size_t)k * 4));
+  DT_TRY(pblock.alloc((size_t)eta * 4));
+  DT_TRY(pgain.alloc((size_t)eta * 8));
+  DT_TRY(pcount.alloc((size_t)(k + 1) * 4));
+  DT_TRY(poff.alloc((size_t)(k + 1) * 4));
+  DT_TRY(pcur.alloc((size_t)(k + 1) * 4));
+  DT_TRY(plist.alloc((size_t)eta * 4));
+  DT_HIP(hipMemsetAsync(size.p, 0, (size_t)k * 4, st));
+  DT_HIP(hipMemsetAsync(delta.p, 0, (size_t)k * 4, st));
+  hipLaunchKernelGGL(k_count_u32, dim3(dblocks(eta)), dim3(DB), 0, st, part.as<uint32_t>(), eta,
+                     (uint32_t*)size.p);
+  uint32_t avg = (eta + k - 1) / k;
+  int lmax = (int)floor((1.0 + o.eps) * (double)avg + 1e-9);
+  for (int it = 0; it < o.refine_iters; it++) {
+    DT_HIP(hipMemsetAsync(pcount.p, 0, (size_t)(k + 1) * 4, st));
+    DT_HIP(hipMemsetAsync(pcur.p, 0, (size_t)(k + 1) * 4, st));
+    hipLaunchKernelGGL(k_lp_propose, dim3(dblocks(eta)), dim3(DB), 0, st, eta, off.as<uint32_t>(),
+                       adj.as<uint32_t>(), w.as<double>(), part.as<uint32_t>(), (uint32_t)it,
+                       pblock.as<uint32_t>(), pgain.as<double>(), pcount.as<uint32_t>());
+    DT_TRY(exclusive_scan(pcount.as<uint32_t>(), poff.as<uint32_t>(), k + 1, st));
+    hipLaunchKernelGGL(k_lp_list, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
+                       pblock.as<uint32_t>(), poff.as<uint32_t>(), pcur.as<uint32_t>(),
+                       plist.as<uint32_t>());
+    hipLaunchKernelGGL(k_lp_accept, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
+                       pblock.as<uint32_t>(), pgain.as<double>(), poff.as<uint32_t>(),
+                       pcount.as<uint32_t>(), plist.as<uint32_t>(), (const int*)size.p, lmax,
+                       part.as<uint32_t>(), (int*)delta.p);
+    hipLaunchKernelGGL(k_apply_delta, dim3(dblocks(k)), dim3(DB), 0, st, k, (int*)size.p,
+                       (int*)delta.p);
+    DT_HIP(hipGetLastError());
+  }
+  DevBuf dcut;
+  DT_TRY(dcut.alloc(8));
+  DT_HIP(hipMemsetAsync(dcut.p, 0, 8, st));
+  hipLaunchKernelGGL(k_cut, dim3(dblocks(eta)), dim3(DB), 0, st, eta, off.as<uint32_t>(),
+                     adj.as<uint32_t>(), w.as<double>(), part.as<uint32_t>(), dcut.as<double>());
+  DT_HIP(hipGetLastError());
+  DT_HIP(hipMemcpyAsync(cut, dcut.p, 8, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
+// ------------------------------------------------------------ 5. assign
+struct Grid {
+  double lo[3];
+  double h;
+  int g[3];
+};
+
+static Grid make_grid(const double lo[3], const double hi[3], int D, double cells_target) {
+  Grid G;
+  double vol = 1.0;
+  int nd = 0;
+  for (int k = 0; k < D; k++) {
+    double e = hi[k] - lo[k];
+    if (e > 0) { vol *= e; nd++; }
+  }
+  double h = (nd > 0) ? pow(vol / (cells_target > 1 ? cells_target : 1), 1.0 / nd) : 1.0;
+  if (!(h > 0)) h = 1.0;
+  for (int k = 0; k < 3; k++) {
+    G.lo[k] = lo[k];
+    double e = (k < D) ? hi[k] - lo[k] : 0.0;
+    long g = (long)floor(e / h) + 1;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    G.g[k] = (k < D) ? (int)g : 1;
+  }
+  G.h = h;
+  return G;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double lo, double h, int g) {
+  double t = (x - lo) / h;
+  int c = (int)floor(t);
+  return c < 0 ? 0 : (c >= g ? g - 1 : c);
+}
+
+__global__ void k_grid_count(const double4* S, uint32_t m, Grid G, uint32_t* cnt, uint32_t* cellof) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double4 p = S[i];
+  int cx = cell_coord(p.x, G.lo[0], G.h, G.g[0]);
+  int cy = cell_coord(p.y, G.lo[1], G.h, G.g[1]);
+  int cz = cell_coord(p.z, G.lo[2], G.h, G.g[2]);
+  uint32_t c = ((uint32_t)cz * G.g[1] + cy) * G.g[0] + cx;
+  cellof[i] = c;
+  atomicAdd(&cnt[c], 1u);
+}
+
+__global__ void k_grid_fill(uint32_t m, const uint32_t* cellof, const uint32_t* start, uint32_t* cur,
+                            uint32_t* items) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint32_t c = cellof[i];
+  items[start[c] + atomicAdd(&cur[c], 1u)] = i;
+}
+
+// Exact nearest sample under the key (fl(d^2), sample id).
+__global__ void k_assign(const double4* P, uint32_t n, const double4* S, const uint32_t* start,
+                         const uint32_t* items, Grid G, const uint32_t* part, uint32_t* pid,
+                         uint32_t* nearest) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double4 p = P[i];
+  int c[3] = {cell_coord(p.x, G.lo[0], G.h, G.g[0]), cell_coord(p.y, G.lo[1], G.h, G.g[1]),
+              cell_coord(p.z, G.lo[2], G.h, G.g[2])};
+  double pc[3] = {p.x, p.y, p.z};
+  double best = INFINITY;
+  long long bestid = 0x7FFFFFFFFFFFFFFFll;
+  uint32_t bests = 0;
+  int gmax = max(G.g[0], max(G.g[1], G.g[2]));
+  for (int r = 0; r <= gmax; r++) {
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; k++) {
+      lo[k] = max(c[k] - r, 0);
+      hi[k] = min(c[k] + r, G.g[k] - 1);
+    }
+    for (int z = lo[2]; z <= hi[2]; z++)
+      for (int y = lo[1]; y <= hi[1]; y++) {
+        bool edge_zy = (z == c[2] - r) || (z == c[2] + r) || (y == c[1] - r) || (y == c[1] + r);
+        for (int x = lo[0]; x <= hi[0]; x++) {
+          if (!edge_zy && x != c[0] - r && x != c[0] + r) {
+            // interior of the shell: skip to the far face
+            if (x < c[0] + r) x = c[0] + r - 1;
+            continue;
+          }
+          uint32_t cell = ((uint32_t)z * G.g[1] + y) * G.g[0] + x;
+          for (uint32_t j = start[cell]; j < start[cell + 1]; j++) {
+            uint32_t s = items[j];
+            double4 q = S[s];
+            double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            long long sid = __double_as_longlong(q.w);
+            if (d2 < best || (d2 == best && sid < bestid)) {
+              best = d2;
+              bestid = sid;
+              bests = s;
+            }
+          }
+        }
+      }
+    // lower bound of the distance to any cell outside this block
+    bool all = true;
+    double dmin = INFINITY;
+    for (int k = 0; k < 3; k++) {
+      if (c[k] - r > 0) {
+        all = false;
+        dmin = fmin(dmin, pc[k] - (G.lo[k] + (c[k] - r) * G.h));
+      }
+      if (c[k] + r < G.g[k] - 1) {
+        all = false;
+        dmin = fmin(dmin, (G.lo[k] + (c[k] + r + 1) * G.h) - pc[k]);
+      }
+    }
+    if (all) break;
+    if (best < INFINITY) {
+      double dm = fmax(dmin, 0.0) * (1.0 - 1e-9);
+      if (dm * dm > best * (1.0 + 1e-9)) break;
+    }
+  }
+  nearest[i] = bests;
+  pid[i] = part[bests];
+}
+
+int assign_points(const double4* P, uint32_t n, const double4* S, uint32_t eta, int D,
+                  const uint32_t* part, const double lo[3], const double hi[3], DevBuf& pid,
+                  DevBuf& nearest, hipStream_t st) {
+  Grid G = make_grid(lo, hi, D, eta / 2.0);
+  uint32_t ncell = (uint32_t)G.g[0] * G.g[1] * G.g[2];
+  DevBuf cnt, start, cur, items, cellof;
+  DT_TRY(cnt.alloc((size_t)(ncell + 1) * 4));
+  DT_TRY(start.alloc((size_t)(ncell + 1) * 4));
+  DT_TRY(cur.alloc((size_t)(ncell + 1) * 4));
+  DT_TRY(items.alloc((size_t)eta * 4));
+  DT_TRY(cellof.alloc((size_t)eta * 4));
+  DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)(ncell + 1) * 4, st));
+  DT_HIP(hipMemsetAsync(cur.p, 0, (size_t)(ncell + 1) * 4, st));
+  hipLaunchKernelGGL(k_grid_count, dim3(dblocks(eta)), dim3(DB), 0, st, S, eta, G,
+                     cnt.as<uint32_t>(), cellof.as<uint32_t>());
+  DT_TRY(exclusive_scan(cnt.as<uint32_t>(), start.as<uint32_t>(), ncell + 1, st));
+  hipLaunchKernelGGL(k_grid_fill, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
+                     cellof.as<uint32_t>(), start.as<uint32_t>(), cur.as<uint32_t>(),
+                     items.as<uint32_t>());
+  DT_TRY(pid.alloc((size_t)n * 4));
+  DT_TRY(nearest.alloc((size_t)n * 4));
+  hipLaunchKernelGGL(k_assign, dim3(dblocks(n)), dim3(DB), 0, st, P, n, S, start.as<uint32_t>(),
+                     items.as<uint32_t>(), G, part, pid.as<uint32_t>(), nearest.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
+// ------------------------------------------------------------ kd divide
+__device__ __forceinline__ unsigned long long ord_bits(double x) {
+  unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__global__ void k_kd_keys(const double4* P, uint32_t n, int dim, unsigned long long* keys,
+                          uint32_t* vals) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double4 p = P[i];
+  double x = dim == 0 ? p.x : (dim == 1 ? p.y : p.z);
+  keys[i] = ord_bits(x);
+  vals[i] = i;
+}
+
+__global__ void k_kd_segkeys(const uint32_t* vals, uint32_t n, const uint32_t* seg,
+                             unsigned long long* keys) {
+  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) keys[j] = seg[vals[j]];
+}
+
+__global__ void k_kd_split(const unsigned long long* segk, const uint32_t* vals, uint32_t n,
+                           const uint32_t* segoff, uint32_t* seg) {
+  uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  uint32_t s = (uint32_t)segk[j];
+  uint32_t a = segoff[s], b = segoff[s + 1];
+  uint32_t half = (b - a) / 2;
+  seg[vals[j]] = 2 * s + ((j - a) >= half ? 1u : 0u);
+}
+
+int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, hipStream_t st) {
+  int levels = 0;
+  while ((1u << levels) < k) levels++;
+  DT_TRY(pid.alloc((size_t)n * 4));
+  DT_HIP(hipMemsetAsync(pid.p, 0, (size_t)n * 4, st));
+  DevBuf keys, vals, cnt, off;
+  DT_TRY(keys.alloc((size_t)n * 8));
+  DT_TRY(vals.alloc((size_t)n * 4));
+  DT_TRY(cnt.alloc((size_t)(k + 1) * 4));
+  DT_TRY(off.alloc((size_t)(k + 1) * 4));
+  for (int l = 0; l < levels; l++) {
+    uint32_t nseg = 1u << l;
+    hipLaunchKernelGGL(k_kd_keys, dim3(dblocks(n)), dim3(DB), 0, st, P, n, l % D,
+                       keys.as<unsigned long long>(), vals.as<uint32_t>());
+    DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), vals.as<uint32_t>(), n, 64, st));
+    hipLaunchKernelGGL(k_kd_segkeys, dim3(dblocks(n)), dim3(DB), 0, st, vals.as<uint32_t>(), n,
+                       pid.as<uint32_t>(), keys.as<unsigned long long>());
+    int sbits = l == 0 ? 1 : l;
+    DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), vals.as<uint32_t>(), n, sbits, st));
+    DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)(k + 1) * 4, st));
+    hipLaunchKernelGGL(k_count_u32, dim3(dblocks(n)), dim3(DB), 0, st, pid.as<uint32_t>(), n,
+                       cnt.as<uint32_t>());
+    DT_TRY(exclusive_scan(cnt.as<uint32_t>(), off.as<uint32_t>(), nseg + 1, st));
+    hipLaunchKernelGGL(k_kd_split, dim3(dblocks(n)), dim3(DB), 0, st,
+                       keys.as<unsigned long long>(), vals.as<uint32_t>(), n, off.as<uint32_t>(),
+                       pid.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+  }
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
+int count_by(const uint32_t* x, uint32_t m, uint32_t k, uint32_t* cnt, hipStream_t st) {
+  DT_HIP(hipMemsetAsync(cnt, 0, (size_t)k * 4, st));
+  if (m == 0) return DT_OK;
+  hipLaunchKernelGGL(k_count_u32, dim3(dblocks(m)), dim3(DB), 0, st, x, m, cnt);
+  DT_HIP(hipGetLastError());
+  return DT_OK;
+}
+
+}  // namespace dtk

@@ -33,6 +33,9 @@
 #include "dt_internal.hpp"
 #include "dt_pred.hpp"
 
+#include <stdio.h>
+#include <stdlib.h>
+
 namespace dtk {
 
 constexpr int BLOCK = 256;
@@ -54,6 +57,9 @@ struct K4Args {
   uint32_t* cand_n;
   uint32_t* cav;
   uint32_t* cavinfo;
+  uint32_t* cand_ext;   // extension chunk of a candidate's cavity list, or DONE
+  uint32_t* extcell;    // [MAXEXT * EXTCAP]
+  uint32_t* extinfo;
   Counters* ctr;
   uint32_t npts;
   uint32_t nsets;
@@ -62,6 +68,21 @@ struct K4Args {
   uint32_t cavcap;
   uint32_t round;
   int fp32;
+};
+
+// Large cavities spill from the fixed per-candidate list into extension
+// chunks taken from a small pool (reset every round).
+constexpr uint32_t MAXEXT = 256;
+constexpr uint32_t EXTCAP = 8192;
+
+struct CavList {
+  uint32_t* a;
+  uint32_t* ia;
+  uint32_t* b;
+  uint32_t* ib;
+  uint32_t cap;
+  __device__ __forceinline__ uint32_t& cell(uint32_t h) { return h < cap ? a[h] : b[h - cap]; }
+  __device__ __forceinline__ uint32_t& info(uint32_t h) { return h < cap ? ia[h] : ib[h - cap]; }
 };
 
 // ------------------------------------------------------------ helpers
@@ -94,9 +115,11 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 }
 
 // Candidate key: newer rounds compare smaller (so stale claims never win),
-// then a random 16-bit priority, then the point index (unique).
+// then a random 16-bit priority fixed per point (a random insertion order,
+// so that rounds follow the dependence structure of randomised incremental
+// construction), then the point index (unique).
 __device__ __forceinline__ unsigned long long make_key(uint32_t round, uint32_t p) {
-  uint32_t h = hash32(p * 0x9E3779B9u + round * 0x85EBCA6Bu + 0x632BE5ABu);
+  uint32_t h = hash32(p * 0x9E3779B9u + 0x632BE5ABu);
   return ((unsigned long long)((~round) & 0xFFFFu) << 48) |
          ((unsigned long long)(h >> 16) << 32) | (unsigned long long)p;
 }
@@ -453,17 +476,18 @@ __global__ void k4_cavity(K4Args a) {
   uint32_t n = 0;
   if (want && slot < a.maxcand) {
     a.cand_pt[slot] = p;
-    uint32_t* list = a.cav + (size_t)slot * a.cavcap;
+    a.cand_ext[slot] = DONE;
+    CavList L2{a.cav + (size_t)slot * a.cavcap, nullptr, nullptr, nullptr, a.cavcap};
     double qp[3];
     unsigned long long qk;
     load_pt(a.pts, p, qp, qk);
     bool ok = atomicMin(&a.ccav[L], K) > K;
     if (ok) {
-      list[0] = L;
+      L2.cell(0) = L;
       n = 1;
     }
     for (uint32_t h = 0; h < n && ok; h++) {
-      uint32_t c = list[h];
+      uint32_t c = L2.cell(h);
       uint4 nb = a.cn[c];
 #pragma unroll
       for (int i = 0; i <= D; i++) {
@@ -494,8 +518,14 @@ __global__ void k4_cavity(K4Args a) {
           unsigned long long old = atomicMin(&a.ccav[t], K);
           if (old < K) { ok = false; break; }
           if (old == K) continue;
-          if (n >= a.cavcap) { ok = false; gaveup = true; break; }
-          list[n++] = t;
+          if (n == a.cavcap) {
+            uint32_t e = atomicAdd(&a.ctr->extused, 1u);
+            if (e >= MAXEXT) { ok = false; gaveup = true; break; }
+            a.cand_ext[slot] = e;
+            L2.b = a.extcell + (size_t)e * EXTCAP;
+          }
+          if (n >= a.cavcap + EXTCAP) { ok = false; gaveup = true; break; }
+          L2.cell(n++) = t;
         } else {
           atomicMin(&a.cshell[t], K);
         }
@@ -526,22 +556,26 @@ __global__ void k4_insert(K4Args a) {
   uint32_t n = 0, p = 0;
   unsigned long long K = 0;
   bool win = false;
-  uint32_t* list = nullptr;
-  uint32_t* info = nullptr;
+  CavList cl{nullptr, nullptr, nullptr, nullptr, a.cavcap};
   if (slot < ncand) {
     n = a.cand_n[slot];
     if (n > 0) {
       p = a.cand_pt[slot];
       K = make_key(a.round, p);
-      list = a.cav + (size_t)slot * a.cavcap;
-      info = a.cavinfo + (size_t)slot * a.cavcap;
+      cl.a = a.cav + (size_t)slot * a.cavcap;
+      cl.ia = a.cavinfo + (size_t)slot * a.cavcap;
+      uint32_t e = a.cand_ext[slot];
+      if (e != DONE) {
+        cl.b = a.extcell + (size_t)e * EXTCAP;
+        cl.ib = a.extinfo + (size_t)e * EXTCAP;
+      }
       win = true;
       for (uint32_t h = 0; h < n && win; h++) {
-        uint32_t c = list[h];
+        uint32_t c = cl.cell(h);
         if (a.ccav[c] != K || a.cshell[c] <= K) win = false;
       }
       for (uint32_t h = 0; h < n && win; h++) {
-        uint4 nb = a.cn[list[h]];
+        uint4 nb = a.cn[cl.cell(h)];
 #pragma unroll
         for (int i = 0; i <= D; i++) {
           uint32_t t = vat(nb, i) >> 2;
@@ -560,13 +594,13 @@ __global__ void k4_insert(K4Args a) {
   uint32_t nbf = 0;
   if (win) {
     for (uint32_t h = 0; h < n; h++) {
-      uint32_t c = list[h];
+      uint32_t c = cl.cell(h);
       uint4 nb = a.cn[c];
       uint32_t mask = 0;
 #pragma unroll
       for (int i = 0; i <= D; i++)
         if (a.ccav[vat(nb, i) >> 2] != K) mask |= 1u << i;
-      info[h] = (nbf << 8) | mask;
+      cl.info(h) = (nbf << 8) | mask;
       nbf += (uint32_t)__popc(mask);
       a.cpos[c] = h;
     }
@@ -579,8 +613,8 @@ __global__ void k4_insert(K4Args a) {
   if (win) {
     uint32_t* cnw = reinterpret_cast<uint32_t*>(a.cn);
     for (uint32_t h = 0; h < n; h++) {
-      uint32_t c = list[h];
-      uint32_t inf = info[h];
+      uint32_t c = cl.cell(h);
+      uint32_t inf = cl.info(h);
       uint32_t mask = inf & 0xFFu;
       if (!mask) continue;
       uint4 vc = a.cv[c];
@@ -609,7 +643,7 @@ __global__ void k4_insert(K4Args a) {
             uint32_t ncell = nbr >> 2;
             if (ncell >= a.cap) break;
             if (a.ccav[ncell] != K) {
-              uint32_t xp = facet_cell(info[a.cpos[cur]], sout, base);
+              uint32_t xp = facet_cell(cl.info(a.cpos[cur]), sout, base);
               link = (xp << 2) | (uint32_t)sin;
               break;
             }
@@ -634,7 +668,7 @@ __global__ void k4_insert(K4Args a) {
         a.cn[x] = nn;
       }
     }
-    for (uint32_t h = 0; h < n; h++) a.cfwd[list[h]] = base;
+    for (uint32_t h = 0; h < n; h++) a.cfwd[cl.cell(h)] = base;
     a.ploc[p] = DONE;
   }
   uint32_t w = wave_sum(win ? 1u : 0u);
@@ -722,7 +756,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
 
   uint32_t cavcap = (D == 2) ? 96 : 192;
   uint32_t maxcand = npts < (1u << 19) ? (npts ? npts : 1) : (1u << 19);
-  DevBuf ploc, cand_pt, cand_n, cav, cavinfo;
+  DevBuf ploc, cand_pt, cand_n, cav, cavinfo, cand_ext, extcell, extinfo;
+  DT_TRY(cand_ext.alloc((size_t)maxcand * 4));
+  DT_TRY(extcell.alloc((size_t)MAXEXT * EXTCAP * 4));
+  DT_TRY(extinfo.alloc((size_t)MAXEXT * EXTCAP * 4));
   DT_TRY(ploc.alloc((size_t)npts * 4));
   DT_TRY(cand_pt.alloc((size_t)maxcand * 4));
   DT_TRY(cand_n.alloc((size_t)maxcand * 4));
@@ -748,6 +785,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.cand_n = cand_n.as<uint32_t>();
   a.cav = cav.as<uint32_t>();
   a.cavinfo = cavinfo.as<uint32_t>();
+  a.cand_ext = cand_ext.as<uint32_t>();
+  a.extcell = extcell.as<uint32_t>();
+  a.extinfo = extinfo.as<uint32_t>();
   a.ctr = dctr;
   a.npts = npts;
   a.nsets = job.nsets;
@@ -767,6 +807,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   DT_HIP(hipGetLastError());
   DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
+  if (getenv("DT_DEBUG"))
+    fprintf(stderr, "[k4] init npts %u sets %u active %u cells %u flags %x\n", npts, job.nsets,
+            hctr->active, hctr->cells, hctr->flags);
   if (hctr->flags) return DT_E_INTERNAL;
   uint64_t remaining = hctr->active;
   int stall = 0;
@@ -775,7 +818,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   while (remaining > 0) {
     if (round >= 0xFFF0u) return DT_E_INTERNAL;
     a.round = round;
-    DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 3 * sizeof(uint32_t), st));   // ncand, inserted, overflow
+    // ncand, inserted, overflow, extused
+    DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 4 * sizeof(uint32_t), st));
     hipLaunchKernelGGL(k4_pick, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
     if (D == 2) {
       hipLaunchKernelGGL(k4_cavity<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
@@ -789,6 +833,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     DT_HIP(hipGetLastError());
     DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
+    if (getenv("DT_DEBUG"))
+      fprintf(stderr, "[k4] round %u cand %u inserted %u overflow %u cells %u maxcav %u flags %x\n",
+              round, hctr->ncand, hctr->inserted, hctr->overflow, hctr->cells, hctr->maxcav,
+              hctr->flags);
     if (hctr->flags) { ks.rounds = (int)round; return DT_E_INTERNAL; }
     uint32_t ins = hctr->inserted;
     if (ins == 0) {

@@ -1,0 +1,434 @@
+// Border detection and merge (paper, Algorithm 1, "Border triangulation"
+// and "Merging"; the grid-based intersection test of Section "Geometric
+// Primitives").
+//
+// Border: a uniform grid of cell edge c_G (V/eta)^(1/D) records, per grid
+// cell, the partition owning all of its points (or "mixed", or empty).  A
+// finite simplex of T_i is a border simplex if its circumball meets a grid
+// cell occupied by another partition (box-sphere test on the cells under
+// the ball's bounding box).  The circumball is computed in FP64 and
+// enlarged by a bound far above its rounding error, and nearly flat
+// simplices are always flagged, so the test can only over-flag.  Every
+// simplex is tested, not only those reachable from the hull: partitions of
+// the sample divide are unions of Voronoi cells and need not be convex.
+// Hull cells of T_i (the infinite vertex) are always flagged, which is the
+// conservative form of the test for the outer half-space of a hull facet.
+//
+// Merge: T = (union T_i minus B) plus every simplex of T_B that spans
+// several partitions or whose vertex set is that of a simplex of B, found
+// in an open-addressing hash table keyed by the sorted vertex ids.
+#include <math.h>
+
+#include "dt_common.hpp"
+#include "dt_internal.hpp"
+#include "dt_prims.hpp"
+#include "dt_stages.hpp"
+
+namespace dtk {
+
+constexpr int MB = 256;
+static inline uint32_t mblocks(uint64_t n) { return (uint32_t)((n + MB - 1) / MB); }
+constexpr uint32_t OWN_EMPTY = 0xFFFFFFFFu;
+constexpr uint32_t OWN_MIXED = 0xFFFFFFFEu;
+
+struct BGrid {
+  double lo[3];
+  double h;
+  int g[3];
+};
+
+__device__ __forceinline__ int bcoord(double x, const BGrid& G, int k) {
+  double t = (x - G.lo[k]) / G.h;
+  int c = (int)floor(t);
+  return c < 0 ? 0 : (c >= G.g[k] ? G.g[k] - 1 : c);
+}
+
+__global__ void k_occupancy(const double4* P, const uint32_t* pset, uint32_t n, BGrid G,
+                            uint32_t* owner) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double4 p = P[i];
+  uint32_t c = ((uint32_t)bcoord(p.z, G, 2) * G.g[1] + bcoord(p.y, G, 1)) * G.g[0] + bcoord(p.x, G, 0);
+  uint32_t me = pset[i];
+  uint32_t cur = owner[c];
+  if (cur == me || cur == OWN_MIXED) return;
+  uint32_t old = atomicCAS(&owner[c], OWN_EMPTY, me);
+  if (old != OWN_EMPTY && old != me) atomicExch(&owner[c], OWN_MIXED);
+}
+
+__device__ __forceinline__ uint32_t key_of(const double4* P, uint32_t v) {
+  return (uint32_t)__double_as_longlong(P[v].w);
+}
+
+template <int D>
+__global__ void k_border(const double4* P, const uint32_t* pset, const uint4* cv,
+                         const uint32_t* cfwd, uint32_t ncells, BGrid G, const uint32_t* owner,
+                         uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  bool flag = false, finite = false;
+  if (c < ncells && cfwd[c] == ALIVE) {
+    uint4 v4 = cv[c];
+    uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+    bool inf = false;
+#pragma unroll
+    for (int i = 0; i <= D; i++)
+      if (v[i] == INF_V) inf = true;
+    if (inf) {
+      flag = true;
+    } else {
+      finite = true;
+      double4 a = P[v[0]];
+      double ctr[3], r;
+      bool sliver = false;
+      if (D == 3) {
+        double4 pb = P[v[1]], pc = P[v[2]], pd = P[v[3]];
+        double b0 = pb.x - a.x, b1 = pb.y - a.y, b2 = pb.z - a.z;
+        double c0 = pc.x - a.x, c1 = pc.y - a.y, c2 = pc.z - a.z;
+        double d0 = pd.x - a.x, d1 = pd.y - a.y, d2 = pd.z - a.z;
+        double cd0 = c1 * d2 - c2 * d1, cd1 = c2 * d0 - c0 * d2, cd2 = c0 * d1 - c1 * d0;
+        double db0 = d1 * b2 - d2 * b1, db1 = d2 * b0 - d0 * b2, db2 = d0 * b1 - d1 * b0;
+        double bc0 = b1 * c2 - b2 * c1, bc1 = b2 * c0 - b0 * c2, bc2 = b0 * c1 - b1 * c0;
+        double det = b0 * cd0 + b1 * cd1 + b2 * cd2;
+        double lb = b0 * b0 + b1 * b1 + b2 * b2, lc = c0 * c0 + c1 * c1 + c2 * c2,
+               ld = d0 * d0 + d1 * d1 + d2 * d2;
+        double scale = sqrt(lb * lc * ld);
+        if (!(fabs(det) > 1e-7 * scale)) {
+          sliver = true;
+        } else {
+          double inv = 0.5 / det;
+          double x = (lb * cd0 + lc * db0 + ld * bc0) * inv;
+          double y = (lb * cd1 + lc * db1 + ld * bc1) * inv;
+          double z = (lb * cd2 + lc * db2 + ld * bc2) * inv;
+          r = sqrt(x * x + y * y + z * z);
+          double L = sqrt(fmax(lb, fmax(lc, ld)));
+          r += 1e-6 * (r + L) + 1e-12 * (fabs(a.x) + fabs(a.y) + fabs(a.z));
+          ctr[0] = a.x + x;
+          ctr[1] = a.y + y;
+          ctr[2] = a.z + z;
+        }
+      } else {
+        double4 pb = P[v[1]], pc = P[v[2]];
+        double b0 = pb.x - a.x, b1 = pb.y - a.y, c0 = pc.x - a.x, c1 = pc.y - a.y;
+        double det = b0 * c1 - b1 * c0;
+        double lb = b0 * b0 + b1 * b1, lc = c0 * c0 + c1 * c1;
+        if (!(fabs(det) > 1e-7 * sqrt(lb * lc))) {
+          sliver = true;
+        } else {
+          double inv = 0.5 / det;
+          double x = (c1 * lb - b1 * lc) * inv;
+          double y = (b0 * lc - c0 * lb) * inv;
+          r = sqrt(x * x + y * y);
+          double L = sqrt(fmax(lb, lc));
+          r += 1e-6 * (r + L) + 1e-12 * (fabs(a.x) + fabs(a.y));
+          ctr[0] = a.x + x;
+          ctr[1] = a.y + y;
+          ctr[2] = 0.0;
+        }
+      }
+      if (sliver) {
+        flag = true;
+      } else {
+        uint32_t me = pset[v[0]];
+        int lo[3], hi[3];
+        long ncover = 1;
+        for (int k = 0; k < 3; k++) {
+          if (k < D) {
+            lo[k] = bcoord(ctr[k] - r, G, k);
+            hi[k] = bcoord(ctr[k] + r, G, k);
+          } else {
+            lo[k] = hi[k] = 0;
+          }
+          ncover *= (hi[k] - lo[k] + 1);
+        }
+        if (ncover > 4096) {
+          flag = true;
+        } else {
+          double r2 = r * r;
+          for (int z = lo[2]; z <= hi[2] && !flag; z++)
+            for (int y = lo[1]; y <= hi[1] && !flag; y++)
+              for (int x = lo[0]; x <= hi[0] && !flag; x++) {
+                uint32_t own = owner[((uint32_t)z * G.g[1] + y) * G.g[0] + x];
+                if (own == OWN_EMPTY || own == me) continue;
+                // squared distance from the centre to the grid cell (box)
+                int cc[3] = {x, y, z};
+                double d2 = 0.0;
+                for (int k = 0; k < D; k++) {
+                  double bl = G.lo[k] + cc[k] * G.h, bh = bl + G.h;
+                  // the first and last cells extend to infinity (points are clamped)
+                  if (cc[k] == 0) bl = -INFINITY;
+                  if (cc[k] == G.g[k] - 1) bh = INFINITY;
+                  double t = ctr[k] < bl ? bl - ctr[k] : (ctr[k] > bh ? ctr[k] - bh : 0.0);
+                  d2 += t * t;
+                }
+                if (d2 <= r2) flag = true;
+              }
+        }
+      }
+    }
+    if (flag) {
+      cflag[c] = 1;
+#pragma unroll
+      for (int i = 0; i <= D; i++)
+        if (v[i] != INF_V) vbflag[key_of(P, v[i])] = 1u;
+    } else {
+      cflag[c] = 0;
+    }
+  } else if (c < ncells) {
+    cflag[c] = 0;
+  }
+  unsigned long long m = __ballot(flag && finite);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(nb, (unsigned long long)__popcll(m));
+}
+
+// Points of partitions that have no full-dimensional triangulation (fewer
+// than D+1 points or all in one hyperplane) all join the border set.
+__global__ void k_degenerate_parts(const double4* P, const uint32_t* pset, uint32_t n,
+                                   const uint32_t* set_cell0, uint32_t* vbflag) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (set_cell0[pset[i]] == DONE) vbflag[key_of(P, i)] = 1u;
+}
+
+int border_detect(const LocalJob& job, const CellPool& pool, const uint32_t* pid_by_id,
+                  uint32_t n, uint32_t k, int D, double cells_target, const double lo[3],
+                  const double hi[3], BorderOut& out, hipStream_t st) {
+  (void)pid_by_id;
+  (void)k;
+  BGrid G;
+  double vol = 1.0;
+  int nd = 0;
+  for (int a = 0; a < D; a++) {
+    double e = hi[a] - lo[a];
+    if (e > 0) { vol *= e; nd++; }
+  }
+  double h = nd ? pow(vol / (cells_target > 1 ? cells_target : 1.0), 1.0 / nd) : 1.0;
+  if (!(h > 0)) h = 1.0;
+  uint64_t total = 1;
+  for (int a = 0; a < 3; a++) {
+    G.lo[a] = lo[a];
+    long g = (a < D) ? (long)floor((hi[a] - lo[a]) / h) + 1 : 1;
+    if (g < 1) g = 1;
+    if (g > 2048) g = 2048;
+    G.g[a] = (int)g;
+    total *= (uint64_t)g;
+  }
+  G.h = h;
+  DevBuf owner, vbflag, nb;
+  DT_TRY(owner.alloc(total * 4));
+  DT_TRY(vbflag.alloc((size_t)n * 4));
+  DT_TRY(out.cflag.alloc((size_t)pool.ncells + 1));
+  DT_TRY(nb.alloc(8));
+  DT_HIP(hipMemsetAsync(owner.p, 0xFF, total * 4, st));
+  DT_HIP(hipMemsetAsync(vbflag.p, 0, (size_t)n * 4, st));
+  DT_HIP(hipMemsetAsync(nb.p, 0, 8, st));
+  hipLaunchKernelGGL(k_occupancy, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts, job.pset,
+                     job.npts, G, owner.as<uint32_t>());
+  if (D == 2)
+    hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
+                       owner.as<uint32_t>(), out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       nb.as<unsigned long long>());
+  else
+    hipLaunchKernelGGL(k_border<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
+                       owner.as<uint32_t>(), out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       nb.as<unsigned long long>());
+  hipLaunchKernelGGL(k_degenerate_parts, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
+                     job.pset, job.npts, pool.set_cell0.as<uint32_t>(), vbflag.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  unsigned long long hnb = 0;
+  DT_HIP(hipMemcpyAsync(&hnb, nb.p, 8, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  out.nb_finite = hnb;
+  DT_TRY(compact_indices(vbflag.as<uint32_t>(), n, out.vb, &out.nvb, st));
+  return DT_OK;
+}
+
+// ------------------------------------------------------------ merge
+__device__ __forceinline__ void sorted_keys(const double4* P, uint4 v, int D, uint32_t k[4]) {
+  uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+  for (int i = 0; i <= D; i++) k[i] = key_of(P, vv[i]);
+  for (int i = 1; i <= D; i++)
+    for (int j = i; j > 0 && k[j] < k[j - 1]; j--) {
+      uint32_t t = k[j]; k[j] = k[j - 1]; k[j - 1] = t;
+    }
+  if (D == 2) k[3] = 0;
+}
+
+__device__ __forceinline__ uint32_t hkey(const uint32_t k[4]) {
+  unsigned long long h = ((unsigned long long)k[0] << 32 | k[1]) * 0x9E3779B97F4A7C15ull;
+  h ^= ((unsigned long long)k[2] << 32 | k[3]) * 0xC2B2AE3D27D4EB4Full;
+  h ^= h >> 29;
+  return (uint32_t)(h * 0xBF58476D1CE4E5B9ull >> 32);
+}
+
+template <int D>
+__device__ __forceinline__ bool finite_live(const uint4* cv, const uint32_t* cfwd, uint32_t c,
+                                            uint4& v) {
+  if (cfwd[c] != ALIVE) return false;
+  v = cv[c];
+  uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i <= D; i++)
+    if (vv[i] == INF_V) return false;
+  return true;
+}
+
+__device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* ctr) {
+  unsigned long long m = __ballot(want);
+  if (m == 0) return 0;
+  int leader = __ffsll((long long)m) - 1;
+  uint32_t lane = threadIdx.x & 63;
+  uint32_t base = 0;
+  if ((int)lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+template <int D>
+__device__ __forceinline__ void write_row(int32_t* rows, uint32_t slot, const uint32_t k[4]) {
+#pragma unroll
+  for (int i = 0; i <= D; i++) rows[(size_t)slot * (D + 1) + i] = (int32_t)k[i];
+}
+
+// Local cells: unflagged finite cells are output; flagged ones go to the table.
+template <int D>
+__global__ void k_merge_local(const double4* P, const uint4* cv, const uint32_t* cfwd,
+                              uint32_t ncells, const uint8_t* cflag, uint32_t* occ,
+                              uint4* tkeys, uint32_t tmask, int32_t* rows, uint32_t* count,
+                              uint32_t cap, uint32_t* flags) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint4 v;
+  bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
+  bool emit = live && cflag[c] == 0;
+  uint32_t k[4] = {0, 0, 0, 0};
+  if (live) sorted_keys(P, v, D, k);
+  uint32_t slot = wave_slot(emit, count);
+  if (emit) {
+    if (slot < cap) write_row<D>(rows, slot, k);
+    else atomicOr(flags, FAIL_OUT_CAP);
+  }
+  if (live && !emit) {
+    uint32_t h = hkey(k);
+    for (uint32_t pr = 0; pr <= tmask; pr++) {
+      uint32_t s = (h + pr) & tmask;
+      if (atomicCAS(&occ[s], 0u, 1u) == 0u) {
+        tkeys[s] = make_uint4(k[0], k[1], k[2], k[3]);
+        break;
+      }
+      if (pr == tmask) atomicOr(flags, FAIL_HASH);
+    }
+  }
+}
+
+// Border cells: spanning, or present in B.
+template <int D>
+__global__ void k_merge_border(const double4* P, const uint4* cv, const uint32_t* cfwd,
+                               uint32_t ncells, const uint32_t* pid_by_id, const uint32_t* occ,
+                               const uint4* tkeys, uint32_t tmask, int32_t* rows, uint32_t* count,
+                               uint32_t cap, unsigned long long* probe_hist, uint32_t* flags) {
+  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint4 v;
+  bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
+  bool emit = false;
+  uint32_t k[4] = {0, 0, 0, 0};
+  if (live) {
+    sorted_keys(P, v, D, k);
+    uint32_t p0 = pid_by_id[k[0]];
+    bool span = false;
+#pragma unroll
+    for (int i = 1; i <= D; i++)
+      if (pid_by_id[k[i]] != p0) span = true;
+    if (span) {
+      emit = true;
+    } else {
+      uint32_t h = hkey(k);
+      uint32_t pr = 0;
+      for (; pr <= tmask; pr++) {
+        uint32_t s = (h + pr) & tmask;
+        if (occ[s] == 0u) break;
+        uint4 t = tkeys[s];
+        if (t.x == k[0] && t.y == k[1] && t.z == k[2] && t.w == k[3]) {
+          emit = true;
+          break;
+        }
+      }
+      atomicAdd(&probe_hist[pr < 15 ? pr : 15], 1ull);
+    }
+  }
+  uint32_t slot = wave_slot(emit, count);
+  if (emit) {
+    if (slot < cap) write_row<D>(rows, slot, k);
+    else atomicOr(flags, FAIL_OUT_CAP);
+  }
+}
+
+int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
+                 const LocalJob& bjob, const CellPool& bpool, const uint32_t* pid_by_id, int D,
+                 DevBuf& rows, int64_t* m, int64_t probe_hist[16], hipStream_t st) {
+  // upper bound of the output: live finite cells of both pools
+  DevBuf cnt;
+  DT_TRY(cnt.alloc(16));
+  uint32_t nl = 0, nbd = 0;
+  DT_TRY(k4_extract(job, pool, nullptr, cnt.as<uint32_t>(), nullptr, st));
+  DT_HIP(hipMemcpyAsync(&nl, cnt.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  if (bpool.ncells) {
+    DT_TRY(k4_extract(bjob, bpool, nullptr, cnt.as<uint32_t>(), nullptr, st));
+    DT_HIP(hipMemcpyAsync(&nbd, cnt.p, 4, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+  }
+  uint32_t cap = nl + nbd;
+  DT_TRY(rows.alloc((size_t)(cap ? cap : 1) * (D + 1) * 4));
+  uint32_t tsize = 64;
+  while (tsize < 2 * b.nb_finite + 16) tsize <<= 1;
+  DevBuf occ, tkeys, ctr, hist, flags;
+  DT_TRY(occ.alloc((size_t)tsize * 4));
+  DT_TRY(tkeys.alloc((size_t)tsize * 16));
+  DT_TRY(ctr.alloc(4));
+  DT_TRY(hist.alloc(16 * 8));
+  DT_TRY(flags.alloc(4));
+  DT_HIP(hipMemsetAsync(occ.p, 0, (size_t)tsize * 4, st));
+  DT_HIP(hipMemsetAsync(ctr.p, 0, 4, st));
+  DT_HIP(hipMemsetAsync(hist.p, 0, 16 * 8, st));
+  DT_HIP(hipMemsetAsync(flags.p, 0, 4, st));
+  if (pool.ncells) {
+    if (D == 2)
+      hipLaunchKernelGGL(k_merge_local<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
+                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap, flags.as<uint32_t>());
+    else
+      hipLaunchKernelGGL(k_merge_local<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
+                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap, flags.as<uint32_t>());
+  }
+  if (bpool.ncells) {
+    if (D == 2)
+      hipLaunchKernelGGL(k_merge_border<2>, dim3(mblocks(bpool.ncells)), dim3(MB), 0, st,
+                         bjob.pts, bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
+                         pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
+                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap,
+                         hist.as<unsigned long long>(), flags.as<uint32_t>());
+    else
+      hipLaunchKernelGGL(k_merge_border<3>, dim3(mblocks(bpool.ncells)), dim3(MB), 0, st,
+                         bjob.pts, bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
+                         pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
+                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap,
+                         hist.as<unsigned long long>(), flags.as<uint32_t>());
+  }
+  DT_HIP(hipGetLastError());
+  uint32_t hm = 0, hf = 0;
+  unsigned long long hh[16];
+  DT_HIP(hipMemcpyAsync(&hm, ctr.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipMemcpyAsync(&hf, flags.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipMemcpyAsync(hh, hist.p, 16 * 8, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  if (hf) return DT_E_INTERNAL;
+  *m = hm;
+  for (int i = 0; i < 16; i++) probe_hist[i] = (int64_t)hh[i];
+  return DT_OK;
+}
+
+}  // namespace dtk

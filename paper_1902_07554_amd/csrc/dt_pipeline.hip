@@ -119,40 +119,53 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
     return s;
   }
   double t2 = now_ms();
-  // per-set counts, then grouped rows
-  DevBuf cnt, base, cursor;
-  DT_TRY(cnt.alloc((size_t)ns * 4));
-  DT_TRY(base.alloc((size_t)ns * 4));
-  DT_TRY(cursor.alloc((size_t)ns * 4));
-  DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)ns * 4, st));
-  DT_TRY(k4_extract(job, pool, nullptr, cx.dflag.as<uint32_t>(), cnt.as<uint32_t>(), st));
-  std::vector<uint32_t> hc(ns);
-  DT_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
-  DT_HIP(hipStreamSynchronize(st));
-  std::vector<uint32_t> hb(ns);
-  uint64_t tot = 0;
-  for (uint32_t i = 0; i < ns; i++) {
-    hb[i] = (uint32_t)tot;
-    r->set_offsets[i] = (int64_t)tot;
-    tot += hc[i];
-  }
-  r->set_offsets[ns] = (int64_t)tot;
-  r->m = (int64_t)tot;
-  DT_TRY(r->rows.alloc((size_t)tot * (D + 1) * 4));
-  DT_HIP(hipMemcpyAsync(base.p, hb.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
-  DT_HIP(hipMemsetAsync(cursor.p, 0, (size_t)ns * 4, st));
-  if (pool.ncells) {
-    if (D == 2)
-      hipLaunchKernelGGL(k_extract_grouped<2>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
-                         job.pts, job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(),
-                         pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
-                         r->rows.as<int32_t>());
-    else
-      hipLaunchKernelGGL(k_extract_grouped<3>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
-                         job.pts, job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(),
-                         pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
-                         r->rows.as<int32_t>());
-    DT_HIP(hipGetLastError());
+  if (ns == 1) {
+    // single set: count, then compact with one atomic per wave
+    DT_TRY(k4_extract(job, pool, nullptr, cx.dflag.as<uint32_t>(), nullptr, st));
+    uint32_t hcount = 0;
+    DT_HIP(hipMemcpyAsync(cx.hflag, cx.dflag.p, 4, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    hcount = *cx.hflag;
+    r->m = hcount;
+    r->set_offsets[1] = hcount;
+    DT_TRY(r->rows.alloc((size_t)hcount * (D + 1) * 4));
+    DT_TRY(k4_extract(job, pool, r->rows.as<int32_t>(), cx.dflag.as<uint32_t>(), nullptr, st));
+  } else {
+    // per-set counts, then rows grouped by set
+    DevBuf cnt, base, cursor;
+    DT_TRY(cnt.alloc((size_t)ns * 4));
+    DT_TRY(base.alloc((size_t)ns * 4));
+    DT_TRY(cursor.alloc((size_t)ns * 4));
+    DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)ns * 4, st));
+    DT_TRY(k4_extract(job, pool, nullptr, cx.dflag.as<uint32_t>(), cnt.as<uint32_t>(), st));
+    std::vector<uint32_t> hc(ns);
+    DT_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    std::vector<uint32_t> hb(ns);
+    uint64_t tot = 0;
+    for (uint32_t i = 0; i < ns; i++) {
+      hb[i] = (uint32_t)tot;
+      r->set_offsets[i] = (int64_t)tot;
+      tot += hc[i];
+    }
+    r->set_offsets[ns] = (int64_t)tot;
+    r->m = (int64_t)tot;
+    DT_TRY(r->rows.alloc((size_t)tot * (D + 1) * 4));
+    DT_HIP(hipMemcpyAsync(base.p, hb.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+    DT_HIP(hipMemsetAsync(cursor.p, 0, (size_t)ns * 4, st));
+    if (pool.ncells) {
+      if (D == 2)
+        hipLaunchKernelGGL(k_extract_grouped<2>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
+                           job.pts, job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(),
+                           pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
+                           r->rows.as<int32_t>());
+      else
+        hipLaunchKernelGGL(k_extract_grouped<3>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
+                           job.pts, job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(),
+                           pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
+                           r->rows.as<int32_t>());
+      DT_HIP(hipGetLastError());
+    }
   }
   DT_HIP(hipStreamSynchronize(st));
   double t3 = now_ms();
