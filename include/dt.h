@@ -27,8 +27,7 @@
  *   - every call returns a status (DT_OK = 0, negative on error) and never
  *     aborts.  Results are opaque handles owning device memory until
  *     dt_result_free.
- *   - the library holds no global mutable state except the per-device
- *     scratch used by dt_local_triangulate_noalloc (declared below).
+ *   - the library holds no global mutable state.
  */
 #ifndef DT_MI355X_H
 #define DT_MI355X_H
@@ -60,6 +59,9 @@ enum { DT_DIVIDE_SAMPLE = 0, DT_DIVIDE_KD = 1 };
 enum { DT_WEIGHT_LOG = 0, DT_WEIGHT_CONST = 1, DT_WEIGHT_INVERSE = 2, DT_WEIGHT_LINEAR = 3 };
 /* Predicate precision: FP64 filter -> exact, or FP32 filter -> FP64 -> exact. */
 enum { DT_PREC_FP64 = 0, DT_PREC_FP32 = 1 };
+/* Border primitive (Algorithm 1, intersection test): the exact regions of
+ * the divide (sample Voronoi cells / kd boxes), or the paper's grid test. */
+enum { DT_BORDER_REGION = 0, DT_BORDER_GRID = 1 };
 
 typedef struct dt_options {
   int divide;        /* DT_DIVIDE_SAMPLE (Algorithm 2) or DT_DIVIDE_KD (cyclic median) */
@@ -71,6 +73,7 @@ typedef struct dt_options {
   uint64_t seed;     /* sample seed; default 1                                        */
   int refine_iters;  /* label-propagation sweeps of the partitioner; default 16       */
   int keep_stages;   /* 1: keep per-stage arrays for dt_result_stage                  */
+  int border;        /* DT_BORDER_*; default DT_BORDER_REGION                         */
 } dt_options;
 
 /* -------------------------------------------------------------- statistics */

@@ -22,6 +22,7 @@ DT_E_NOMEM, DT_E_DEVICE, DT_E_INTERNAL, DT_E_NOT_READY = -5, -6, -7, -8
 DIVIDE = {"sample": 0, "kd": 1}
 WEIGHT = {"log": 0, "const": 1, "inverse": 2, "linear": 3}
 PRECISION = {"fp64": 0, "fp32": 1}
+BORDER = {"region": 0, "grid": 1}
 STAGES = ["validate", "sample", "sample_dt", "partition", "assign", "scatter", "local_dt",
           "border", "border_dt", "merge", "output", "total"]
 ARR = {"sample": 0, "sample_dt": 1, "part": 2, "pid": 3, "order": 4, "border_v": 5,
@@ -37,7 +38,8 @@ class Options(ctypes.Structure):
     _fields_ = [("divide", ctypes.c_int), ("weight", ctypes.c_int), ("precision", ctypes.c_int),
                 ("sort_output", ctypes.c_int), ("eps", ctypes.c_double),
                 ("grid_cell", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("refine_iters", ctypes.c_int), ("keep_stages", ctypes.c_int)]
+                ("refine_iters", ctypes.c_int), ("keep_stages", ctypes.c_int),
+                ("border", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -137,6 +139,8 @@ def options(**kw) -> Options:
             v = WEIGHT[v] if isinstance(v, str) else v
         elif k == "precision":
             v = PRECISION[v] if isinstance(v, str) else v
+        elif k == "border":
+            v = BORDER[v] if isinstance(v, str) else v
         setattr(o, k, v)
     return o
 

@@ -24,6 +24,7 @@ extern "C" void dt_default_options(dt_options* o) {
   o->seed = 1;
   o->refine_iters = 16;
   o->keep_stages = 0;
+  o->border = DT_BORDER_REGION;
 }
 
 extern "C" const char* dt_strerror(int s) {
@@ -91,6 +92,7 @@ static int check_opts(const dt_options* in, dt_options& o) {
   if (o.precision != DT_PREC_FP64 && o.precision != DT_PREC_FP32) return DT_E_INVALID_ARG;
   if (!(o.eps >= 0.0) || !(o.grid_cell > 0.0)) return DT_E_INVALID_ARG;
   if (o.refine_iters < 0) return DT_E_INVALID_ARG;
+  if (o.border != DT_BORDER_REGION && o.border != DT_BORDER_GRID) return DT_E_INVALID_ARG;
   return DT_OK;
 }
 

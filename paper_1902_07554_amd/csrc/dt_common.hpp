@@ -36,8 +36,10 @@ struct Counters {
   unsigned int inserted;          // points inserted this round
   unsigned int overflow;          // candidates that gave up (cavity too large)
   unsigned int extused;           // cavity extension chunks taken this round
+  unsigned int pending;           // active points not yet inserted (this round)
   unsigned int maxcav;            // largest cavity seen
-  unsigned int active;            // points still to insert
+  unsigned int active;            // points to insert
+  unsigned int pad;
 };
 
 }  // namespace dtk

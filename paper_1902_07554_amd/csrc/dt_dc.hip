@@ -138,7 +138,8 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   S.stage_ms[DT_STAGE_VALIDATE] = t1 - t0;
 
   // ---- divide
-  DevBuf pid, sid, Sp, part, nearest;
+  DevBuf pid, sid, Sp, part, nearest, boxes;
+  SampleGrid sgrid;
   CellPool spool;
   LocalJob sjob;
   DevBuf sset, soff;
@@ -173,12 +174,12 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     double tc = now_ms();
     S.stage_ms[DT_STAGE_PARTITION] = tc - tb;
     DT_TRY(assign_points(P.as<double4>(), n, Sp.as<double4>(), eta, D, part.as<uint32_t>(), lo, hi,
-                         pid, nearest, st));
+                         pid, nearest, sgrid, st));
     S.stage_ms[DT_STAGE_ASSIGN] = now_ms() - tc;
     S.eta = eta;
     S.cut_weight = cut;
   } else {
-    DT_TRY(kd_divide(P.as<double4>(), n, D, (uint32_t)k, pid, st));
+    DT_TRY(kd_divide(P.as<double4>(), n, D, (uint32_t)k, pid, boxes, st));
     S.stage_ms[DT_STAGE_ASSIGN] = now_ms() - t1;
     S.eta = 0;
   }
@@ -245,9 +246,24 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
 
   // ---- border
   BorderOut bo;
-  double cells = (double)sample_size(n, rate, D);
+  // grid of about one input point per cell at c_G = 1
+  double cells = (double)n;
   for (int a = 0; a < D; a++) cells /= o.grid_cell;
-  DT_TRY(border_detect(job, pool, pid.as<uint32_t>(), n, (uint32_t)k, D, cells, lo, hi, bo, st));
+  Region reg;
+  if (o.border == DT_BORDER_REGION) {
+    if (o.divide == DT_DIVIDE_SAMPLE) {
+      reg.kind = BORDER_VORONOI;
+      reg.S = Sp.as<double4>();
+      reg.part = part.as<uint32_t>();
+      reg.start = sgrid.start.as<uint32_t>();
+      reg.items = sgrid.items.as<uint32_t>();
+      reg.G = sgrid.G;
+    } else {
+      reg.kind = BORDER_BOXES;
+      reg.boxes = boxes.as<double>();
+    }
+  }
+  DT_TRY(border_detect(job, pool, reg, n, D, cells, lo, hi, bo, st));
   double tg = now_ms();
   S.stage_ms[DT_STAGE_BORDER] = tg - tf;
   S.border_simplices = (int64_t)bo.nb_finite;

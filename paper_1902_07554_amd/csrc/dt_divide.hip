@@ -32,6 +32,7 @@
 #include "dt_common.hpp"
 #include "dt_internal.hpp"
 #include "dt_prims.hpp"
+#include "dt_grid.hpp"
 #include "dt_stages.hpp"
 
 namespace dtk {
@@ -464,12 +465,6 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
 }
 
 // ------------------------------------------------------------ 5. assign
-struct Grid {
-  double lo[3];
-  double h;
-  int g[3];
-};
-
 static Grid make_grid(const double lo[3], const double hi[3], int D, double cells_target) {
   Grid G;
   double vol = 1.0;
@@ -490,12 +485,6 @@ static Grid make_grid(const double lo[3], const double hi[3], int D, double cell
   }
   G.h = h;
   return G;
-}
-
-__device__ __forceinline__ int cell_coord(double x, double lo, double h, int g) {
-  double t = (x - lo) / h;
-  int c = (int)floor(t);
-  return c < 0 ? 0 : (c >= g ? g - 1 : c);
 }
 
 __global__ void k_grid_count(const double4* S, uint32_t m, Grid G, uint32_t* cnt, uint32_t* cellof) {
@@ -525,72 +514,21 @@ __global__ void k_assign(const double4* P, uint32_t n, const double4* S, const u
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double4 p = P[i];
-  int c[3] = {cell_coord(p.x, G.lo[0], G.h, G.g[0]), cell_coord(p.y, G.lo[1], G.h, G.g[1]),
-              cell_coord(p.z, G.lo[2], G.h, G.g[2])};
-  double pc[3] = {p.x, p.y, p.z};
-  double best = INFINITY;
-  long long bestid = 0x7FFFFFFFFFFFFFFFll;
-  uint32_t bests = 0;
-  int gmax = max(G.g[0], max(G.g[1], G.g[2]));
-  for (int r = 0; r <= gmax; r++) {
-    int lo[3], hi[3];
-    for (int k = 0; k < 3; k++) {
-      lo[k] = max(c[k] - r, 0);
-      hi[k] = min(c[k] + r, G.g[k] - 1);
-    }
-    for (int z = lo[2]; z <= hi[2]; z++)
-      for (int y = lo[1]; y <= hi[1]; y++) {
-        bool edge_zy = (z == c[2] - r) || (z == c[2] + r) || (y == c[1] - r) || (y == c[1] + r);
-        for (int x = lo[0]; x <= hi[0]; x++) {
-          if (!edge_zy && x != c[0] - r && x != c[0] + r) {
-            // interior of the shell: skip to the far face
-            if (x < c[0] + r) x = c[0] + r - 1;
-            continue;
-          }
-          uint32_t cell = ((uint32_t)z * G.g[1] + y) * G.g[0] + x;
-          for (uint32_t j = start[cell]; j < start[cell + 1]; j++) {
-            uint32_t s = items[j];
-            double4 q = S[s];
-            double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-            double d2 = (dx * dx + dy * dy) + dz * dz;
-            long long sid = __double_as_longlong(q.w);
-            if (d2 < best || (d2 == best && sid < bestid)) {
-              best = d2;
-              bestid = sid;
-              bests = s;
-            }
-          }
-        }
-      }
-    // lower bound of the distance to any cell outside this block
-    bool all = true;
-    double dmin = INFINITY;
-    for (int k = 0; k < 3; k++) {
-      if (c[k] - r > 0) {
-        all = false;
-        dmin = fmin(dmin, pc[k] - (G.lo[k] + (c[k] - r) * G.h));
-      }
-      if (c[k] + r < G.g[k] - 1) {
-        all = false;
-        dmin = fmin(dmin, (G.lo[k] + (c[k] + r + 1) * G.h) - pc[k]);
-      }
-    }
-    if (all) break;
-    if (best < INFINITY) {
-      double dm = fmax(dmin, 0.0) * (1.0 - 1e-9);
-      if (dm * dm > best * (1.0 + 1e-9)) break;
-    }
-  }
-  nearest[i] = bests;
-  pid[i] = part[bests];
+  double d2;
+  uint32_t s = grid_nearest(S, start, items, G, p.x, p.y, p.z, &d2);
+  nearest[i] = s;
+  pid[i] = part[s];
 }
 
 int assign_points(const double4* P, uint32_t n, const double4* S, uint32_t eta, int D,
                   const uint32_t* part, const double lo[3], const double hi[3], DevBuf& pid,
-                  DevBuf& nearest, hipStream_t st) {
+                  DevBuf& nearest, SampleGrid& sg, hipStream_t st) {
   Grid G = make_grid(lo, hi, D, eta / 2.0);
+  sg.G = G;
   uint32_t ncell = (uint32_t)G.g[0] * G.g[1] * G.g[2];
-  DevBuf cnt, start, cur, items, cellof;
+  DevBuf cnt, cur, cellof;
+  DevBuf& start = sg.start;
+  DevBuf& items = sg.items;
   DT_TRY(cnt.alloc((size_t)(ncell + 1) * 4));
   DT_TRY(start.alloc((size_t)(ncell + 1) * 4));
   DT_TRY(cur.alloc((size_t)(ncell + 1) * 4));
@@ -636,18 +574,34 @@ __global__ void k_kd_segkeys(const uint32_t* vals, uint32_t n, const uint32_t* s
 }
 
 __global__ void k_kd_split(const unsigned long long* segk, const uint32_t* vals, uint32_t n,
-                           const uint32_t* segoff, uint32_t* seg) {
+                           const uint32_t* segoff, uint32_t* seg, const double4* P, int dim,
+                           double* split) {
   uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   uint32_t s = (uint32_t)segk[j];
   uint32_t a = segoff[s], b = segoff[s + 1];
   uint32_t half = (b - a) / 2;
   seg[vals[j]] = 2 * s + ((j - a) >= half ? 1u : 0u);
+  if (j - a == half) {
+    // first element of the upper half: lower child x <= v, upper child x >= v
+    double4 p = P[vals[j]];
+    split[s] = dim == 0 ? p.x : (dim == 1 ? p.y : p.z);
+  }
 }
 
-int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, hipStream_t st) {
+int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, DevBuf& boxes,
+              hipStream_t st) {
   int levels = 0;
   while ((1u << levels) < k) levels++;
+  // region of every block: [lo, hi] per dimension, refined by each split
+  std::vector<double> box((size_t)k * 6);
+  for (uint32_t b = 0; b < k; b++)
+    for (int a = 0; a < 3; a++) {
+      box[b * 6 + a] = -INFINITY;
+      box[b * 6 + 3 + a] = INFINITY;
+    }
+  DevBuf dsplit;
+  DT_TRY(dsplit.alloc((size_t)k * 8));
   DT_TRY(pid.alloc((size_t)n * 4));
   DT_HIP(hipMemsetAsync(pid.p, 0, (size_t)n * 4, st));
   DevBuf keys, vals, cnt, off;
@@ -668,11 +622,27 @@ int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, hipS
     hipLaunchKernelGGL(k_count_u32, dim3(dblocks(n)), dim3(DB), 0, st, pid.as<uint32_t>(), n,
                        cnt.as<uint32_t>());
     DT_TRY(exclusive_scan(cnt.as<uint32_t>(), off.as<uint32_t>(), nseg + 1, st));
+    std::vector<double> nanv(nseg, NAN);
+    DT_HIP(hipMemcpyAsync(dsplit.p, nanv.data(), (size_t)nseg * 8, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_kd_split, dim3(dblocks(n)), dim3(DB), 0, st,
                        keys.as<unsigned long long>(), vals.as<uint32_t>(), n, off.as<uint32_t>(),
-                       pid.as<uint32_t>());
+                       pid.as<uint32_t>(), P, l % D, dsplit.as<double>());
     DT_HIP(hipGetLastError());
+    std::vector<double> hs(nseg);
+    DT_HIP(hipMemcpyAsync(hs.data(), dsplit.p, (size_t)nseg * 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    // leaves below segment s at this level: [s << (levels-l), (s+1) << (levels-l))
+    int sh = levels - l;
+    for (uint32_t sgm = 0; sgm < nseg; sgm++) {
+      double v = hs[sgm];
+      if (v != v) continue;   // empty block
+      uint32_t mid = (2 * sgm + 1) << (sh - 1);
+      for (uint32_t b = sgm << sh; b < mid; b++) box[b * 6 + 3 + l % D] = v;
+      for (uint32_t b = mid; b < ((sgm + 1) << sh); b++) box[b * 6 + l % D] = v;
+    }
   }
+  DT_TRY(boxes.alloc((size_t)k * 48));
+  DT_HIP(hipMemcpyAsync(boxes.p, box.data(), (size_t)k * 48, hipMemcpyHostToDevice, st));
   DT_HIP(hipStreamSynchronize(st));
   return DT_OK;
 }

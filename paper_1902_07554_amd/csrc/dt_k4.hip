@@ -14,7 +14,10 @@
 //            smaller key wins: no other winner touches its cavity or its
 //            shell, so winners retriangulate independently, exactly as a
 //            sequential insertion would;
-//   relocate points whose cell was destroyed walk to their new cell.
+//   relocate (lazily, at the next pick) active points whose cell was
+//            destroyed follow forward pointers and walk to their new cell.
+// Points become active in levels of growing priority threshold, so a point
+// is located when its turn approaches rather than after every round.
 // The globally smallest key always wins, so every round makes progress.
 // Because the result of each round equals a sequence of ordinary
 // insertions, the final triangulation is the unique (perturbed) Delaunay
@@ -39,6 +42,8 @@
 namespace dtk {
 
 constexpr int BLOCK = 256;
+// ploc flag: the stored cell is only a start for the walk (dormant point)
+constexpr uint32_t NEEDWALK = 0x80000000u;
 
 struct K4Args {
   const double4* pts;
@@ -67,6 +72,7 @@ struct K4Args {
   uint32_t maxcand;
   uint32_t cavcap;
   uint32_t round;
+  uint32_t thresh;      // points with prio_of(p) < thresh are active
   int fp32;
 };
 
@@ -114,14 +120,19 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   return x;
 }
 
-// Candidate key: newer rounds compare smaller (so stale claims never win),
-// then a random 16-bit priority fixed per point (a random insertion order,
-// so that rounds follow the dependence structure of randomised incremental
-// construction), then the point index (unique).
+// Fixed random priority of a point (20 bits): the insertion order follows
+// it, as in randomised incremental construction, and points become active
+// in levels of growing priority threshold.
+__device__ __forceinline__ uint32_t prio_of(uint32_t p) {
+  return hash32(p * 0x9E3779B9u + 0x632BE5ABu) >> 12;
+}
+
+// Candidate key: newer rounds compare smaller (12-bit round stamp, so stale
+// claims never win; the claim words are reset every 4095 rounds), then the
+// priority, then the point index (unique).
 __device__ __forceinline__ unsigned long long make_key(uint32_t round, uint32_t p) {
-  uint32_t h = hash32(p * 0x9E3779B9u + 0x632BE5ABu);
-  return ((unsigned long long)((~round) & 0xFFFFu) << 48) |
-         ((unsigned long long)(h >> 16) << 32) | (unsigned long long)p;
+  return ((unsigned long long)((~round) & 0xFFFu) << 52) |
+         ((unsigned long long)prio_of(p) << 32) | (unsigned long long)p;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -423,37 +434,59 @@ __global__ void k4_init_sets(K4Args a) {
   a.set_cell0[s] = base;
 }
 
-// One thread per point: locate in the initial triangulation of its set.
-template <int D>
-__global__ void k4_locate_init(K4Args a) {
+// One thread per point: every point starts in the initial cell of its set;
+// it is located (walked) only when it becomes active.
+__global__ void k4_place_init(K4Args a) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  Pred pr;
-  pr.init(&a.ctr->flags, a.fp32 != 0);
   bool act = false;
   if (p < a.npts) {
     uint32_t c0 = a.set_cell0[a.pset[p]];
     if (c0 == DONE) {
       a.ploc[p] = DONE;
     } else if (a.ploc[p] != DONE) {
-      double qp[3];
-      unsigned long long qk;
-      load_pt(a.pts, p, qp, qk);
-      a.ploc[p] = walk<D>(a, pr, c0, p, qp, qk);
+      a.ploc[p] = c0 | NEEDWALK;   // a start cell, not yet a location
       act = true;
     }
   }
   uint32_t c = wave_sum(act ? 1u : 0u);
   if (lane_id() == 0 && c) atomicAdd(&a.ctr->active, c);
-  flush_pred<D>(a.ctr, pr.st);
 }
 
 // ------------------------------------------------------------ rounds
+// Active points whose cell was destroyed follow the forward pointers of
+// destroyed cells (each points into the star that replaced it) to a live
+// cell near them and walk from there; then every active point bids for its
+// cell.  Dormant points are not touched.
+template <int D>
 __global__ void k4_pick(K4Args a) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.npts) return;
-  uint32_t L = a.ploc[p];
-  if (L == DONE) return;
-  atomicMin(&a.ccand[L], make_key(a.round, p));
+  Pred pr;
+  pr.init(&a.ctr->flags, a.fp32 != 0);
+  bool pending = false;
+  if (p < a.npts) {
+    uint32_t L = a.ploc[p];
+    if (L != DONE && prio_of(p) < a.thresh) {
+      pending = true;
+      bool need = (L & NEEDWALK) != 0;
+      L &= ~NEEDWALK;
+      if (need || a.cfwd[L] != ALIVE) {
+        for (int h = 0; h < (1 << 16); h++) {
+          uint32_t f = a.cfwd[L];
+          if (f == ALIVE) break;
+          L = f;
+        }
+        double qp[3];
+        unsigned long long qk;
+        load_pt(a.pts, p, qp, qk);
+        L = walk<D>(a, pr, L, p, qp, qk);
+        a.ploc[p] = L;
+      }
+      atomicMin(&a.ccand[L], make_key(a.round, p));
+    }
+  }
+  uint32_t c = wave_sum(pending ? 1u : 0u);
+  if (lane_id() == 0 && c) atomicAdd(&a.ctr->pending, c);
+  flush_pred<D>(a.ctr, pr.st);
 }
 
 template <int D>
@@ -466,9 +499,17 @@ __global__ void k4_cavity(K4Args a) {
   unsigned long long K = 0;
   if (p < a.npts) {
     L = a.ploc[p];
-    if (L != DONE) {
+    if (L != DONE && (L & NEEDWALK) == 0 && prio_of(p) < a.thresh) {
       K = make_key(a.round, p);
       want = (a.ccand[L] == K);
+      if (want) {
+        // A smaller bid in a neighbouring cell always wins against this one:
+        // its cavity holds that cell, which touches this point's cell.
+        uint4 nb = a.cn[L];
+#pragma unroll
+        for (int i = 0; i <= D; i++)
+          if (a.ccand[vat(nb, i) >> 2] < K) want = false;
+      }
     }
   }
   uint32_t slot = wave_alloc(want, &a.ctr->ncand);
@@ -675,26 +716,6 @@ __global__ void k4_insert(K4Args a) {
   if (lane_id() == 0 && w) atomicAdd(&a.ctr->inserted, w);
 }
 
-template <int D>
-__global__ void k4_relocate(K4Args a) {
-  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  Pred pr;
-  pr.init(&a.ctr->flags, a.fp32 != 0);
-  if (p < a.npts) {
-    uint32_t L = a.ploc[p];
-    if (L != DONE) {
-      uint32_t f = a.cfwd[L];
-      if (f != ALIVE) {
-        double qp[3];
-        unsigned long long qk;
-        load_pt(a.pts, p, qp, qk);
-        a.ploc[p] = walk<D>(a, pr, f, p, qp, qk);
-      }
-    }
-  }
-  flush_pred<D>(a.ctr, pr.st);
-}
-
 // ------------------------------------------------------------ extraction
 template <int D>
 __global__ void k4_extract_rows(const double4* pts, const uint32_t* pset, const uint4* cv,
@@ -797,54 +818,70 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.round = 0;
   a.fp32 = job.fp32 ? 1 : 0;
 
-  if (D == 2) {
+  if (D == 2)
     hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
-    hipLaunchKernelGGL(k4_locate_init<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
-  } else {
+  else
     hipLaunchKernelGGL(k4_init_sets<3>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
-    hipLaunchKernelGGL(k4_locate_init<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
-  }
+  hipLaunchKernelGGL(k4_place_init, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
   DT_HIP(hipGetLastError());
   DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
-  if (getenv("DT_DEBUG"))
+  const bool dbg = getenv("DT_DEBUG") != nullptr;
+  if (dbg)
     fprintf(stderr, "[k4] init npts %u sets %u active %u cells %u flags %x\n", npts, job.nsets,
             hctr->active, hctr->cells, hctr->flags);
   if (hctr->flags) return DT_E_INTERNAL;
-  uint64_t remaining = hctr->active;
+  uint64_t remaining = hctr->active, done = 0;
+  // activation levels: about 1024 active points per set at first, doubled
+  // whenever fewer than half as many are pending as are already inserted
+  const uint32_t PMAX = 1u << 20;
+  uint64_t t0 = ((uint64_t)PMAX * 1024ull * job.nsets) / (npts ? npts : 1);
+  uint32_t thresh = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
   int stall = 0;
   uint32_t round = 1;
   ks.maxcav = 0;
   while (remaining > 0) {
-    if (round >= 0xFFF0u) return DT_E_INTERNAL;
+    if (round >= (1u << 30)) return DT_E_INTERNAL;
+    if ((round & 0xFFFu) == 0) {
+      // the 12-bit round stamp wraps: clear every claim word
+      size_t used = hctr->cells;
+      DT_HIP(hipMemsetAsync(pool.ccand.p, 0xFF, used * 8, st));
+      DT_HIP(hipMemsetAsync(pool.ccav.p, 0xFF, used * 8, st));
+      DT_HIP(hipMemsetAsync(pool.cshell.p, 0xFF, used * 8, st));
+    }
     a.round = round;
-    // ncand, inserted, overflow, extused
-    DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 4 * sizeof(uint32_t), st));
-    hipLaunchKernelGGL(k4_pick, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
+    a.thresh = thresh;
+    // ncand, inserted, overflow, extused, pending
+    DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 5 * sizeof(uint32_t), st));
     if (D == 2) {
+      hipLaunchKernelGGL(k4_pick<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
       hipLaunchKernelGGL(k4_cavity<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
       hipLaunchKernelGGL(k4_insert<2>, dim3(nblk(maxcand)), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_relocate<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
     } else {
+      hipLaunchKernelGGL(k4_pick<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
       hipLaunchKernelGGL(k4_cavity<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
       hipLaunchKernelGGL(k4_insert<3>, dim3(nblk(maxcand)), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_relocate<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
     }
     DT_HIP(hipGetLastError());
     DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    if (getenv("DT_DEBUG"))
-      fprintf(stderr, "[k4] round %u cand %u inserted %u overflow %u cells %u maxcav %u flags %x\n",
-              round, hctr->ncand, hctr->inserted, hctr->overflow, hctr->cells, hctr->maxcav,
-              hctr->flags);
+    if (dbg)
+      fprintf(stderr,
+              "[k4] round %u thresh %u pending %u cand %u inserted %u overflow %u cells %u "
+              "maxcav %u flags %x\n",
+              round, thresh, hctr->pending, hctr->ncand, hctr->inserted, hctr->overflow,
+              hctr->cells, hctr->maxcav, hctr->flags);
     if (hctr->flags) { ks.rounds = (int)round; return DT_E_INTERNAL; }
     uint32_t ins = hctr->inserted;
-    if (ins == 0) {
-      if (++stall > 8) { ks.rounds = (int)round; return DT_E_INTERNAL; }
-    } else {
-      stall = 0;
-    }
     remaining -= ins;
+    done += ins;
+    uint64_t left = hctr->pending >= ins ? hctr->pending - ins : 0;
+    if (thresh < PMAX && left < (done / 2 > 256 ? done / 2 : 256)) {
+      thresh = thresh * 2 > PMAX ? PMAX : thresh * 2;
+    } else if (ins == 0) {
+      if (++stall > 8) { ks.rounds = (int)round; return DT_E_INTERNAL; }
+    }
+    if (ins) stall = 0;
     round++;
   }
   ks.rounds = (int)(round - 1);

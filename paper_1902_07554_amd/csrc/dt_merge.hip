@@ -2,11 +2,14 @@
 // and "Merging"; the grid-based intersection test of Section "Geometric
 // Primitives").
 //
-// Border: a uniform grid of cell edge c_G (V/eta)^(1/D) records, per grid
-// cell, the partition owning all of its points (or "mixed", or empty).  A
-// finite simplex of T_i is a border simplex if its circumball meets a grid
-// cell occupied by another partition (box-sphere test on the cells under
-// the ball's bounding box).  The circumball is computed in FP64 and
+// Border: a finite simplex of T_i is a border simplex if its circumball
+// may contain a point of another partition.  Two tests:
+//   grid (the paper's grid-based primitive): a uniform grid of cell edge
+//     c_G (V/n)^(1/D) (about one input point per cell at c_G = 1) records
+//     the partition owning each cell's points (or "mixed", or empty); the
+//     ball is tested against the cells of other partitions (box-sphere);
+//   region (default): the exact regions of the divide -- Voronoi cells of
+//     the sample for the sample divide, boxes for the kd divide.  The circumball is computed in FP64 and
 // enlarged by a bound far above its rounding error, and nearly flat
 // simplices are always flagged, so the test can only over-flag.  Every
 // simplex is tested, not only those reachable from the hull: partitions of
@@ -60,10 +63,57 @@ __device__ __forceinline__ uint32_t key_of(const double4* P, uint32_t v) {
   return (uint32_t)__double_as_longlong(P[v].w);
 }
 
+// Does the ball (ctr, r) of a simplex of partition `me` reach the region
+// of another partition?  kd boxes: the ball leaves the block's box.
+// Sample Voronoi cells: let t be the sample nearest to the centre; a point
+// of the ball belongs to another block only if it is (up to rounding) at
+// least as close to a foreign sample s as to t, which needs the ball to
+// reach the bisector of s and t; such s lie within |t - ctr| + 2r of the
+// centre.  Margins cover the rounding of the assignment's distance keys.
+template <int D>
+__device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, double r) {
+  if (R.kind == BORDER_BOXES) {
+    const double* b = R.boxes + (size_t)me * 6;
+    for (int k = 0; k < D; k++)
+      if (ctr[k] - r <= b[k] || ctr[k] + r >= b[3 + k]) return true;
+    return false;
+  }
+  double d2t;
+  uint32_t t = grid_nearest(R.S, R.start, R.items, R.G, ctr[0], ctr[1], D == 3 ? ctr[2] : 0.0, &d2t);
+  if (R.part[t] != me) return true;
+  double4 tp = R.S[t];
+  double rad = sqrt(d2t) * (1.0 + 1e-9) + 2.0 * r;
+  int lo[3], hi[3];
+  for (int k = 0; k < 3; k++) {
+    double x = k < D ? ctr[k] : 0.0;
+    lo[k] = cell_coord(x - rad, R.G.lo[k], R.G.h, R.G.g[k]);
+    hi[k] = cell_coord(x + rad, R.G.lo[k], R.G.h, R.G.g[k]);
+  }
+  double cz = D == 3 ? ctr[2] : 0.0;
+  for (int z = lo[2]; z <= hi[2]; z++)
+    for (int y = lo[1]; y <= hi[1]; y++)
+      for (int x = lo[0]; x <= hi[0]; x++) {
+        uint32_t cell = ((uint32_t)z * R.G.g[1] + y) * R.G.g[0] + x;
+        for (uint32_t j = R.start[cell]; j < R.start[cell + 1]; j++) {
+          uint32_t s = R.items[j];
+          if (R.part[s] == me) continue;
+          double4 sp = R.S[s];
+          double ax = ctr[0] - sp.x, ay = ctr[1] - sp.y, az = cz - sp.z;
+          double bx = ctr[0] - tp.x, by = ctr[1] - tp.y, bz = cz - tp.z;
+          double ds = ax * ax + ay * ay + az * az, dt = bx * bx + by * by + bz * bz;
+          double ex = sp.x - tp.x, ey = sp.y - tp.y, ez = sp.z - tp.z;
+          double gap = sqrt(ex * ex + ey * ey + ez * ez);
+          // distance of the centre from the bisector, on t's side: (ds - dt) / (2 gap)
+          if (ds - dt <= 2.0 * gap * r + 1e-12 * (ds + dt)) return true;
+        }
+      }
+  return false;
+}
+
 template <int D>
 __global__ void k_border(const double4* P, const uint32_t* pset, const uint4* cv,
                          const uint32_t* cfwd, uint32_t ncells, BGrid G, const uint32_t* owner,
-                         uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb) {
+                         Region R, uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   bool flag = false, finite = false;
   if (c < ncells && cfwd[c] == ALIVE) {
@@ -127,6 +177,8 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const uint4* cv
       }
       if (sliver) {
         flag = true;
+      } else if (R.kind != BORDER_GRID) {
+        flag = region_hit<D>(R, pset[v[0]], ctr, r);
       } else {
         uint32_t me = pset[v[0]];
         int lo[3], hi[3];
@@ -189,11 +241,9 @@ __global__ void k_degenerate_parts(const double4* P, const uint32_t* pset, uint3
   if (set_cell0[pset[i]] == DONE) vbflag[key_of(P, i)] = 1u;
 }
 
-int border_detect(const LocalJob& job, const CellPool& pool, const uint32_t* pid_by_id,
-                  uint32_t n, uint32_t k, int D, double cells_target, const double lo[3],
-                  const double hi[3], BorderOut& out, hipStream_t st) {
-  (void)pid_by_id;
-  (void)k;
+int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, uint32_t n,
+                  int D, double cells_target, const double lo[3], const double hi[3],
+                  BorderOut& out, hipStream_t st) {
   BGrid G;
   double vol = 1.0;
   int nd = 0;
@@ -208,7 +258,7 @@ int border_detect(const LocalJob& job, const CellPool& pool, const uint32_t* pid
     G.lo[a] = lo[a];
     long g = (a < D) ? (long)floor((hi[a] - lo[a]) / h) + 1 : 1;
     if (g < 1) g = 1;
-    if (g > 2048) g = 2048;
+    if (g > 4096) g = 4096;
     G.g[a] = (int)g;
     total *= (uint64_t)g;
   }
@@ -226,12 +276,12 @@ int border_detect(const LocalJob& job, const CellPool& pool, const uint32_t* pid
   if (D == 2)
     hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
-                       owner.as<uint32_t>(), out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       owner.as<uint32_t>(), reg, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>());
   else
     hipLaunchKernelGGL(k_border<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
-                       owner.as<uint32_t>(), out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       owner.as<uint32_t>(), reg, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>());
   hipLaunchKernelGGL(k_degenerate_parts, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
                      job.pset, job.npts, pool.set_cell0.as<uint32_t>(), vbflag.as<uint32_t>());

@@ -1,6 +1,7 @@
 // Stage functions of the divide-and-conquer pipeline (device work, host
 // orchestration).  All pointers are device pointers.
 #pragma once
+#include "dt_grid.hpp"
 #include "dt_internal.hpp"
 
 namespace dtk {
@@ -12,10 +13,17 @@ int gather_points(const double4* P, const uint32_t* idx, uint32_t m, double4* ou
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
                      const dt_options& o, const double lo[3], const double hi[3],
                      DevBuf& part, double* cut, hipStream_t st);
+// Samples bucketed by grid cell (cells in start[0..ncell], items).
+struct SampleGrid {
+  Grid G;
+  DevBuf start, items;
+};
 int assign_points(const double4* P, uint32_t n, const double4* S, uint32_t eta, int D,
                   const uint32_t* part, const double lo[3], const double hi[3], DevBuf& pid,
-                  DevBuf& nearest, hipStream_t st);
-int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, hipStream_t st);
+                  DevBuf& nearest, SampleGrid& sg, hipStream_t st);
+// boxes: k x 6 doubles (lo xyz, hi xyz) of every block's region.
+int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, DevBuf& boxes,
+              hipStream_t st);
 int count_by(const uint32_t* x, uint32_t m, uint32_t k, uint32_t* cnt, hipStream_t st);
 
 // Border and merge (dt_merge.hip)
@@ -25,9 +33,22 @@ struct BorderOut {
   uint32_t nvb = 0;
   uint64_t nb_finite = 0;   // |B| (finite flagged cells)
 };
-int border_detect(const LocalJob& job, const CellPool& pool, const uint32_t* pid_by_id,
-                  uint32_t n, uint32_t k, int D, double cellsize, const double lo[3],
-                  const double hi[3], BorderOut& out, hipStream_t st);
+// How a simplex's circumball is tested against the other partitions:
+// the grid of occupied cells (the paper's grid test), or the exact regions
+// of the divide (sample Voronoi cells, kd boxes).
+enum { BORDER_GRID = 0, BORDER_VORONOI = 1, BORDER_BOXES = 2 };
+struct Region {
+  int kind = BORDER_GRID;
+  const double4* S = nullptr;      // samples (Voronoi)
+  const uint32_t* part = nullptr;  // block of every sample
+  const uint32_t* start = nullptr; // sample grid
+  const uint32_t* items = nullptr;
+  Grid G{};
+  const double* boxes = nullptr;   // k x 6 (boxes)
+};
+int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, uint32_t n,
+                  int D, double cells_target, const double lo[3], const double hi[3],
+                  BorderOut& out, hipStream_t st);
 int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
                  const LocalJob& bjob, const CellPool& bpool, const uint32_t* pid_by_id, int D,
                  DevBuf& rows, int64_t* m, int64_t probe_hist[16], hipStream_t st);

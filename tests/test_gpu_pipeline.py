@@ -12,9 +12,10 @@ from paper_1902_07554_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _stage_checks(dtlib, p, k, rate, seed, divide):
+def _stage_checks(dtlib, p, k, rate, seed, divide, border="region"):
     n, dim = p.shape
-    res = dtlib.triangulate(p, k=k, sample_rate=rate, divide=divide, seed=seed, keep_stages=1)
+    res = dtlib.triangulate(p, k=k, sample_rate=rate, divide=divide, seed=seed, keep_stages=1,
+                            border=border)
     ids = np.arange(n)
     full = oracle.delaunay(p)
     got = oracle.canonical(res.rows())
@@ -60,21 +61,24 @@ def _stage_checks(dtlib, p, k, rate, seed, divide):
     return res
 
 
-@pytest.mark.parametrize("divide", ["sample", "kd"])
-def test_config_2d_10k(dtlib, divide):
+@pytest.mark.parametrize("divide,border", [("sample", "region"), ("kd", "region"),
+                                           ("sample", "grid")])
+def test_config_2d_10k(dtlib, divide, border):
     """2D, n = 10,000 uniform, sample 1 % (100 points), k = 4."""
     p = inputs.uniform(10_000, 2, seed=1)
-    print(f"[pipeline] 2d 10k {divide}", flush=True)
-    _stage_checks(dtlib, p, 4, 0.01, 1, divide)
+    print(f"[pipeline] 2d 10k {divide} {border}", flush=True)
+    _stage_checks(dtlib, p, 4, 0.01, 1, divide, border)
 
 
-@pytest.mark.parametrize("divide,dist,k", [("sample", "uniform", 16), ("kd", "uniform", 16),
-                                           ("sample", "bubbles", 32), ("kd", "bubbles", 32),
-                                           ("sample", "normal", 8)])
-def test_3d_stages(dtlib, divide, dist, k):
+@pytest.mark.parametrize("divide,dist,k,border", [
+    ("sample", "uniform", 16, "region"), ("kd", "uniform", 16, "region"),
+    ("sample", "bubbles", 32, "region"), ("kd", "bubbles", 32, "region"),
+    ("sample", "normal", 8, "region"), ("sample", "bubbles", 32, "grid"),
+    ("kd", "uniform", 16, "grid")])
+def test_3d_stages(dtlib, divide, dist, k, border):
     p = inputs.make(dist, 20_000, 3, seed=4)
-    print(f"[pipeline] 3d 20k {dist} {divide} k={k}", flush=True)
-    _stage_checks(dtlib, p, k, 0.01, 3, divide)
+    print(f"[pipeline] 3d 20k {dist} {divide} k={k} border={border}", flush=True)
+    _stage_checks(dtlib, p, k, 0.01, 3, divide, border)
 
 
 @pytest.mark.parametrize("dim,side,k", [(2, 60, 4), (3, 12, 8)])
@@ -82,9 +86,11 @@ def test_lattice_through_pipeline(dtlib, dim, side, k):
     """Degenerate input: ties everywhere, also across partition borders."""
     p = inputs.lattice(side, dim, seed=2)
     print(f"[pipeline] lattice dim={dim} side={side}", flush=True)
+    want = oracle.delaunay(p)
     for divide in ("sample", "kd"):
-        res = dtlib.triangulate(p, k=k, sample_rate=0.02, divide=divide)
-        assert np.array_equal(oracle.canonical(res.rows()), oracle.delaunay(p)), divide
+        for border in ("region", "grid"):
+            res = dtlib.triangulate(p, k=k, sample_rate=0.02, divide=divide, border=border)
+            assert np.array_equal(oracle.canonical(res.rows()), want), (divide, border)
 
 
 def test_independent_of_division(dtlib):
