@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the sample-based divide-and-conquer Delaunay triangulation.
+
+One step = one full triangulation (every stage of the path: sample, sample
+DT, partition, nearest-sample assignment, bucket scatter, local DTs, border
+test, border DT, merge) of one synthetic point set already resident in HBM.
+
+Default workload: 3D, n = 4,194,304 "bubbles" points (64 Gaussian clusters,
+sigma log-uniform in [0.01, 0.05], Dirichlet(1) weights, 5 % uniform
+background, seed 1), k = 256 partitions, sample rate 0.5 % (eta = 20,972),
+FP32-filtered predicates with FP64 and exact fallbacks.  The metric is
+Mpoints/s with the sample divide; the kd median-split divide runs on the
+same input for comparison, with balance and border sizes for both.
+
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 is not supported: the
+build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (distribution, n, dim, k, sample rate, precision)
+    "bubbles-3d-4M-k256": ("bubbles", 4_194_304, 3, 256, 0.005, "fp32"),
+    "uniform-3d-1M-k64": ("uniform", 1_048_576, 3, 64, 0.005, "fp64"),
+    "uniform-2d-10k-k4": ("uniform", 10_000, 2, 4, 0.01, "fp64"),
+}
+
+# Algorithmic bytes per unit of work of each timed kernel:
+# the records the kernel must gather or stream for that unit.
+PT = 32          # point record: x, y, z, id (double4)
+CELL = 16        # cell vertex record (uint4); neighbours another 16
+
+
+def kernel_bytes(name: str, st: dict, dim: int) -> float:
+    pred = st["pred"]
+    o = pred["orient3d" if dim == 3 else "orient2d"]["calls"]
+    ins = pred["insphere3d" if dim == 3 else "insphere2d"]["calls"]
+    v = dim + 1
+    n = st["n"]
+    if name == "k4_cavity":     # per in-sphere test: cell vertices + neighbours + claim + D+1 points
+        return ins * (2 * CELL + 8 + v * PT)
+    if name == "k4_pick":       # per walk step (about D+1 orientation tests): cell + D+1 points
+        return (o / v) * (2 * CELL + v * PT)
+    if name == "k4_insert":     # per cavity cell: vertices, neighbours, two claim words
+        return st["cavity_cells"] * (2 * CELL + 16)
+    if name == "assign":        # per point: read the point, write block and nearest sample
+        return n * (PT + 8)
+    if name == "bucket":        # per point: read pid, write order, read + write the point
+        return n * (4 + 4 + 2 * PT)
+    if name == "border":        # per local simplex: vertices, D+1 points, flag
+        return st["local_simplices"] * (CELL + v * PT + 1)
+    if name == "merge":         # per simplex of T_i and T_B: vertices, keys, flag, row
+        return (st["local_simplices"] + st["tb_simplices"]) * (CELL + v * PT + 1 + 4 * v)
+    return 0.0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(points, sample_n: int) -> dict:
+    """The CPU oracle (single-threaded Bowyer-Watson, exact predicates) on
+    the first `sample_n` points of the same input."""
+    import oracle
+    sub = points[:sample_n]
+    t0 = time.perf_counter()
+    simp = oracle.delaunay(sub)
+    dt = time.perf_counter() - t0
+    return {"value": round(sample_n / dt / 1e6, 4), "unit": "Mpoints/s", "cores": 1,
+            "kind": "oracle", "seconds": round(dt, 2), "simplices": int(len(simp)),
+            "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"first {sample_n} points of the same input (same generator and seed)"}
+
+
+def run(binding, pts, steps: int, warmup: int, k: int, rate: float, **opts):
+    import torch
+    res = None
+    for _ in range(warmup):
+        res = binding.triangulate(pts, k=k, sample_rate=rate, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern = {}
+    for _ in range(steps):
+        res = binding.triangulate(pts, k=k, sample_rate=rate, profile=1, **opts)
+        st = res.stats()
+        for name, v in st["kern"].items():
+            a = kern.setdefault(name, {"ms": 0.0, "launches": 0})
+            a["ms"] += v["ms"]
+            a["launches"] += v["launches"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return res, (t1 - t0) * 1000.0 / steps, kern
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bubbles-3d-4M-k256", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-kd", action="store_true", help="skip the kd-divide comparison")
+    ap.add_argument("--cpu-sample", type=int, default=250_000,
+                    help="points of the CPU-oracle baseline sample (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+              "(the multi-GPU sharding is a design in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1902_07554_amd import binding, inputs
+
+    dist, n, dim, k, rate, prec = WORKLOADS[args.workload]
+    host = inputs.make(dist, n, dim, seed=1)
+    pts = torch.from_numpy(host).to("cuda")
+    torch.cuda.synchronize()
+
+    res, ms, kern = run(binding, pts, args.steps, args.warmup, k, rate, precision=prec,
+                        divide="sample")
+    st = res.stats()
+    value = n / (ms / 1000.0) / 1e6
+
+    # dominant kernel of the timed region: achieved algorithmic bytes / time
+    per_step = {name: {"ms": v["ms"] / args.steps, "launches": v["launches"] / args.steps}
+                for name, v in kern.items() if v["launches"]}
+    dom = max(per_step, key=lambda x: per_step[x]["ms"])
+    dom_bytes = kernel_bytes(dom, st, dim)
+    dom_s = per_step[dom]["ms"] / 1000.0
+    achieved = dom_bytes / dom_s / 1e9 if dom_s > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": 8000.0,
+                "unit": "GB/s", "frac": round(achieved / 8000.0, 5), "traffic": None,
+                "launches_per_step": per_step[dom]["launches"],
+                "ms_per_step": round(per_step[dom]["ms"], 3)}
+    kernels = {}
+    for name, v in per_step.items():
+        b = kernel_bytes(name, st, dim)
+        kernels[name] = {"ms": round(v["ms"], 3), "launches": v["launches"],
+                         "GB/s": round(b / (v["ms"] / 1000.0) / 1e9, 2) if v["ms"] > 0 else None}
+
+    def summary(s):
+        return {"border_vertices": s["border_vertices"], "border_simplices": s["border_simplices"],
+                "tb_simplices": s["tb_simplices"], "o_dt": round(s["o_dt"], 4),
+                "cv": round(s["cv"], 4), "max_dev": round(s["max_dev"], 4),
+                "cut_weight": round(s["cut_weight"], 2), "rounds": s["rounds"],
+                "stage_ms": {a: round(b, 2) for a, b in s["stage_ms"].items() if b}}
+
+    line = {
+        "metric": "Mpoints/s DT (3D, 4M pts) sample- vs kd-divide; border size; p50/p99 latency",
+        "value": round(value, 4),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "distribution": dist, "n": n, "dim": dim, "k": k,
+                   "sample_rate": rate, "eta": st["eta"], "divide": "sample",
+                   "precision": prec, "border": "region"},
+        "simplices": res.count,
+        "sample_divide": summary(st),
+        "predicates": st["pred"],
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_kd:
+        kres, kms, _ = run(binding, pts, args.steps, args.warmup, k, rate, precision=prec,
+                           divide="kd")
+        kst = kres.stats()
+        line["kd_divide"] = dict(value=round(n / (kms / 1000.0) / 1e6, 4), ms_per_step=round(kms, 3),
+                                 **summary(kst))
+        line["sample_vs_kd_speedup"] = round(kms / ms, 4)
+        line["kd_simplices_equal"] = bool(kres.count == res.count)
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(host, min(args.cpu_sample, n))
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -74,7 +74,12 @@ typedef struct dt_options {
   int refine_iters;  /* label-propagation sweeps of the partitioner; default 16       */
   int keep_stages;   /* 1: keep per-stage arrays for dt_result_stage                  */
   int border;        /* DT_BORDER_*; default DT_BORDER_REGION                         */
+  int profile;       /* 1: time the kernels below with HIP events (dt_stats.kern_*)   */
 } dt_options;
+
+/* Kernels timed when dt_options.profile = 1. */
+enum { DT_KERN_K4_PICK = 0, DT_KERN_K4_CAVITY, DT_KERN_K4_INSERT, DT_KERN_ASSIGN,
+       DT_KERN_BUCKET, DT_KERN_BORDER, DT_KERN_MERGE, DT_NUM_KERN = 8 };
 
 /* -------------------------------------------------------------- statistics */
 enum {
@@ -102,6 +107,9 @@ typedef struct dt_stats {
   uint32_t pad;
   double stage_ms[DT_NUM_STAGES];
   int64_t probe_hist[16];     /* merge hash: lookups by probe count (last = 15+)  */
+  double kern_ms[DT_NUM_KERN];        /* summed HIP-event time per kernel (profile)  */
+  int64_t kern_launches[DT_NUM_KERN]; /* launches per kernel (profile)               */
+  int64_t cavity_cells;       /* cells visited by winning and losing cavity searches */
 } dt_stats;
 
 typedef struct dt_result dt_result;

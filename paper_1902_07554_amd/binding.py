@@ -25,6 +25,7 @@ PRECISION = {"fp64": 0, "fp32": 1}
 BORDER = {"region": 0, "grid": 1}
 STAGES = ["validate", "sample", "sample_dt", "partition", "assign", "scatter", "local_dt",
           "border", "border_dt", "merge", "output", "total"]
+KERNELS = ["k4_pick", "k4_cavity", "k4_insert", "assign", "bucket", "border", "merge"]
 ARR = {"sample": 0, "sample_dt": 1, "part": 2, "pid": 3, "order": 4, "border_v": 5,
        "local": 6, "border_dt": 7}
 EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_count",
@@ -39,7 +40,7 @@ class Options(ctypes.Structure):
                 ("sort_output", ctypes.c_int), ("eps", ctypes.c_double),
                 ("grid_cell", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("refine_iters", ctypes.c_int), ("keep_stages", ctypes.c_int),
-                ("border", ctypes.c_int)]
+                ("border", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -52,17 +53,20 @@ class Stats(ctypes.Structure):
                 ("min_part", ctypes.c_int64), ("rounds", ctypes.c_int64),
                 ("pred", (ctypes.c_int64 * 4) * 4), ("fail", ctypes.c_uint32),
                 ("pad", ctypes.c_uint32), ("stage_ms", ctypes.c_double * 12),
-                ("probe_hist", ctypes.c_int64 * 16)]
+                ("probe_hist", ctypes.c_int64 * 16), ("kern_ms", ctypes.c_double * 8),
+                ("kern_launches", ctypes.c_int64 * 8), ("cavity_cells", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("pred", "stage_ms",
-                                                                       "probe_hist", "pad")}
+        d = {f: getattr(self, f) for f, _ in self._fields_
+             if f not in ("pred", "stage_ms", "probe_hist", "pad", "kern_ms", "kern_launches")}
         names = ["orient2d", "orient3d", "insphere2d", "insphere3d"]
         d["pred"] = {names[i]: {"calls": self.pred[i][0], "fp32": self.pred[i][1],
                                 "fp64": self.pred[i][2], "exact": self.pred[i][3]}
                      for i in range(4)}
         d["stage_ms"] = {STAGES[i]: self.stage_ms[i] for i in range(12)}
         d["probe_hist"] = list(self.probe_hist)
+        d["kern"] = {KERNELS[i]: {"ms": self.kern_ms[i], "launches": self.kern_launches[i]}
+                     for i in range(7)}
         return d
 
 

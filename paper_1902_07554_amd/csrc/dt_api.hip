@@ -57,6 +57,10 @@ int Ctx::init() {
   return DT_OK;
 }
 
+static thread_local Profiler* g_prof = nullptr;
+Profiler* active_profiler() { return g_prof; }
+void set_active_profiler(Profiler* p) { g_prof = p; }
+
 double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -109,7 +113,15 @@ extern "C" int dt_triangulate(const double* points, int64_t n, int D, int k, dou
   hipStream_t st = (hipStream_t)stream;
   dt_result* r = new dt_result();
   r->D = D;
+  Profiler prof;
+  if (o.profile) set_active_profiler(&prof);
   int s = run_triangulate(points, n, D, k, sample_rate, o, points_on_device != 0, st, r);
+  set_active_profiler(nullptr);
+  prof.resolve();
+  for (int i = 0; i < DT_NUM_KERN; i++) {
+    r->stats.kern_ms[i] = prof.ms[i];
+    r->stats.kern_launches[i] = prof.launches[i];
+  }
   if (s != DT_OK) {
     delete r;
     return s;
@@ -140,7 +152,15 @@ extern "C" int dt_batch_triangulate(const double* points, const int64_t* ids,
   hipStream_t st = (hipStream_t)stream;
   dt_result* r = new dt_result();
   r->D = D;
+  Profiler prof;
+  if (o.profile) set_active_profiler(&prof);
   int s = run_batch(points, ids, offsets, num_sets, D, o, points_on_device != 0, st, r);
+  set_active_profiler(nullptr);
+  prof.resolve();
+  for (int i = 0; i < DT_NUM_KERN; i++) {
+    r->stats.kern_ms[i] = prof.ms[i];
+    r->stats.kern_launches[i] = prof.launches[i];
+  }
   if (s != DT_OK) {
     delete r;
     return s;

@@ -29,7 +29,8 @@ enum : uint32_t {
 };
 
 struct Counters {
-  unsigned long long pred[4][4];  // [orient2, orient3, in2, in3][calls, fp32 ok, fp64 ok, exact]
+  unsigned long long pred[4][4];
+  unsigned long long cavcells;    // cells placed in cavities (all candidates)  // [orient2, orient3, in2, in3][calls, fp32 ok, fp64 ok, exact]
   unsigned int flags;
   unsigned int cells;             // cells allocated in the pool
   unsigned int ncand;             // candidates this round

@@ -104,6 +104,7 @@ static void add_pred(dt_stats& s, const K4Stats& ks) {
   for (int i = 0; i < 4; i++)
     for (int j = 0; j < 4; j++) s.pred[i][j] += (int64_t)ks.pred[i][j];
   s.rounds += ks.rounds;
+  s.cavity_cells += (int64_t)ks.cavity_cells;
 }
 
 int run_dc(const double* points, int64_t n64, int D, int k, double rate, const dt_options& o,
@@ -193,10 +194,12 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
                      keys.as<unsigned long long>(), order.as<uint32_t>());
   int kbits = 1;
   while ((1u << kbits) < (uint32_t)k) kbits++;
-  DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), order.as<uint32_t>(), n, kbits, st));
-  keys.release();
   DT_TRY(Pp.alloc((size_t)n * sizeof(double4)));
+  DT_PROF_BEGIN(DT_KERN_BUCKET, st);
+  DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), order.as<uint32_t>(), n, kbits, st));
   DT_TRY(gather_points(P.as<double4>(), order.as<uint32_t>(), n, Pp.as<double4>(), st));
+  DT_PROF_END(st);
+  keys.release();
   DT_TRY(cnt.alloc((size_t)(k + 1) * 4));
   DT_TRY(off.alloc((size_t)(k + 1) * 4));
   DT_TRY(count_by(pid.as<uint32_t>(), n, (uint32_t)k + 1, cnt.as<uint32_t>(), st));

@@ -544,8 +544,10 @@ int assign_points(const double4* P, uint32_t n, const double4* S, uint32_t eta, 
                      items.as<uint32_t>());
   DT_TRY(pid.alloc((size_t)n * 4));
   DT_TRY(nearest.alloc((size_t)n * 4));
+  DT_PROF_BEGIN(DT_KERN_ASSIGN, st);
   hipLaunchKernelGGL(k_assign, dim3(dblocks(n)), dim3(DB), 0, st, P, n, S, start.as<uint32_t>(),
                      items.as<uint32_t>(), G, part, pid.as<uint32_t>(), nearest.as<uint32_t>());
+  DT_PROF_END(st);
   DT_HIP(hipGetLastError());
   DT_HIP(hipStreamSynchronize(st));
   return DT_OK;

@@ -73,10 +73,48 @@ struct CellPool {
 };
 
 struct K4Stats {
+  unsigned long long cavity_cells = 0;
   int rounds = 0;
   uint32_t maxcav = 0;
   unsigned long long pred[4][4] = {};
 };
+
+// Optional kernel timing: HIP events recorded around launches on the
+// launch stream, resolved when the call finishes.  The active profiler is
+// per host thread (one call at a time per thread).
+struct Profiler {
+  struct Rec { int id; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  double ms[DT_NUM_KERN] = {};
+  long long launches[DT_NUM_KERN] = {};
+  void begin(int id, hipStream_t st) {
+    Rec r{id, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, st);
+    recs.push_back(r);
+  }
+  void end(hipStream_t st) {
+    if (!recs.empty()) (void)hipEventRecord(recs.back().b, st);
+  }
+  void resolve() {
+    for (auto& r : recs) {
+      float t = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.id] += t;
+        launches[r.id]++;
+      }
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    recs.clear();
+  }
+};
+Profiler* active_profiler();
+void set_active_profiler(Profiler* p);
+#define DT_PROF_BEGIN(id, st) \
+  do { if (::dtk::active_profiler()) ::dtk::active_profiler()->begin((id), (st)); } while (0)
+#define DT_PROF_END(st) \
+  do { if (::dtk::active_profiler()) ::dtk::active_profiler()->end((st)); } while (0)
 
 // Triangulate every set of `job` (one batched sequence of launches).
 int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr,

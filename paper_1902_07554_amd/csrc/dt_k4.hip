@@ -73,6 +73,8 @@ struct K4Args {
   uint32_t cavcap;
   uint32_t round;
   uint32_t thresh;      // points with prio_of(p) < thresh are active
+  const uint32_t* act;  // active point list (a superset of the pending points)
+  uint32_t nact;
   int fp32;
 };
 
@@ -452,6 +454,15 @@ __global__ void k4_place_init(K4Args a) {
   if (lane_id() == 0 && c) atomicAdd(&a.ctr->active, c);
 }
 
+// Active list: the points not yet inserted whose priority is below the
+// threshold (rebuilt when the threshold grows or the list thins out).
+__global__ void k4_build_active(K4Args a, uint32_t* list, uint32_t* count) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  bool take = p < a.npts && a.ploc[p] != DONE && prio_of(p) < a.thresh;
+  uint32_t slot = wave_alloc(take, count);
+  if (take) list[slot] = p;
+}
+
 // ------------------------------------------------------------ rounds
 // Active points whose cell was destroyed follow the forward pointers of
 // destroyed cells (each points into the star that replaced it) to a live
@@ -459,11 +470,12 @@ __global__ void k4_place_init(K4Args a) {
 // cell.  Dormant points are not touched.
 template <int D>
 __global__ void k4_pick(K4Args a) {
-  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x;
   Pred pr;
   pr.init(&a.ctr->flags, a.fp32 != 0);
   bool pending = false;
-  if (p < a.npts) {
+  uint32_t p = ia < a.nact ? a.act[ia] : 0xFFFFFFFFu;
+  if (ia < a.nact) {
     uint32_t L = a.ploc[p];
     if (L != DONE && prio_of(p) < a.thresh) {
       pending = true;
@@ -491,13 +503,14 @@ __global__ void k4_pick(K4Args a) {
 
 template <int D>
 __global__ void k4_cavity(K4Args a) {
-  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t p = ia < a.nact ? a.act[ia] : 0xFFFFFFFFu;
   Pred pr;
   pr.init(&a.ctr->flags, a.fp32 != 0);
   bool want = false;
   uint32_t L = DONE;
   unsigned long long K = 0;
-  if (p < a.npts) {
+  if (ia < a.nact) {
     L = a.ploc[p];
     if (L != DONE && (L & NEEDWALK) == 0 && prio_of(p) < a.thresh) {
       K = make_key(a.round, p);
@@ -575,6 +588,8 @@ __global__ void k4_cavity(K4Args a) {
     a.cand_n[slot] = ok ? n : 0u;
   }
   uint32_t g = wave_sum(gaveup ? 1u : 0u);
+  uint32_t tot = wave_sum((want && slot < a.maxcand) ? n : 0u);
+  if (lane_id() == 0 && tot) atomicAdd(&a.ctr->cavcells, (unsigned long long)tot);
   uint32_t mx = (want && slot < a.maxcand) ? n : 0u;
   for (int off = warpSize / 2; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, off));
   if (lane_id() == 0) {
@@ -777,7 +792,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
 
   uint32_t cavcap = (D == 2) ? 96 : 192;
   uint32_t maxcand = npts < (1u << 19) ? (npts ? npts : 1) : (1u << 19);
-  DevBuf ploc, cand_pt, cand_n, cav, cavinfo, cand_ext, extcell, extinfo;
+  DevBuf ploc, cand_pt, cand_n, cav, cavinfo, cand_ext, extcell, extinfo, actbuf;
+  DT_TRY(actbuf.alloc((size_t)(npts ? npts : 1) * 4));
   DT_TRY(cand_ext.alloc((size_t)maxcand * 4));
   DT_TRY(extcell.alloc((size_t)MAXEXT * EXTCAP * 4));
   DT_TRY(extinfo.alloc((size_t)MAXEXT * EXTCAP * 4));
@@ -840,7 +856,24 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   int stall = 0;
   uint32_t round = 1;
   ks.maxcav = 0;
+  uint32_t built_thresh = 0xFFFFFFFFu;   // threshold the active list was built for
+  uint64_t nact = 0, ins_since = 0;
+  a.act = actbuf.as<uint32_t>();
   while (remaining > 0) {
+    if (thresh != built_thresh || ins_since * 2 > nact) {
+      a.thresh = thresh;
+      DT_HIP(hipMemsetAsync(&dctr->pad, 0, sizeof(uint32_t), st));
+      hipLaunchKernelGGL(k4_build_active, dim3(nblk(npts)), dim3(BLOCK), 0, st, a,
+                         actbuf.as<uint32_t>(), &dctr->pad);
+      DT_HIP(hipGetLastError());
+      uint32_t hn = 0;
+      DT_HIP(hipMemcpyAsync(&hn, &dctr->pad, 4, hipMemcpyDeviceToHost, st));
+      DT_HIP(hipStreamSynchronize(st));
+      nact = hn;
+      built_thresh = thresh;
+      ins_since = 0;
+    }
+    a.nact = (uint32_t)nact;
     if (round >= (1u << 30)) return DT_E_INTERNAL;
     if ((round & 0xFFFu) == 0) {
       // the 12-bit round stamp wraps: clear every claim word
@@ -853,15 +886,20 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     a.thresh = thresh;
     // ncand, inserted, overflow, extused, pending
     DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 5 * sizeof(uint32_t), st));
-    if (D == 2) {
-      hipLaunchKernelGGL(k4_pick<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_cavity<2>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_insert<2>, dim3(nblk(maxcand)), dim3(BLOCK), 0, st, a);
-    } else {
-      hipLaunchKernelGGL(k4_pick<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_cavity<3>, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_insert<3>, dim3(nblk(maxcand)), dim3(BLOCK), 0, st, a);
-    }
+    uint32_t ga = nblk(nact ? (uint32_t)nact : 1u);
+    uint32_t gi = nblk((uint32_t)(nact < maxcand ? (nact ? nact : 1) : maxcand));
+    DT_PROF_BEGIN(DT_KERN_K4_PICK, st);
+    if (D == 2) hipLaunchKernelGGL(k4_pick<2>, dim3(ga), dim3(BLOCK), 0, st, a);
+    else hipLaunchKernelGGL(k4_pick<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+    DT_PROF_END(st);
+    DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
+    if (D == 2) hipLaunchKernelGGL(k4_cavity<2>, dim3(ga), dim3(BLOCK), 0, st, a);
+    else hipLaunchKernelGGL(k4_cavity<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+    DT_PROF_END(st);
+    DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
+    if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(BLOCK), 0, st, a);
+    else hipLaunchKernelGGL(k4_insert<3>, dim3(gi), dim3(BLOCK), 0, st, a);
+    DT_PROF_END(st);
     DT_HIP(hipGetLastError());
     DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
@@ -875,6 +913,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     uint32_t ins = hctr->inserted;
     remaining -= ins;
     done += ins;
+    ins_since += ins;
     uint64_t left = hctr->pending >= ins ? hctr->pending - ins : 0;
     if (thresh < PMAX && left < (done / 2 > 256 ? done / 2 : 256)) {
       thresh = thresh * 2 > PMAX ? PMAX : thresh * 2;
@@ -886,6 +925,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   }
   ks.rounds = (int)(round - 1);
   ks.maxcav = hctr->maxcav;
+  ks.cavity_cells = hctr->cavcells;
   pool.ncells = hctr->cells;
   for (int i = 0; i < 4; i++)
     for (int j = 0; j < 4; j++) ks.pred[i][j] = hctr->pred[i][j];

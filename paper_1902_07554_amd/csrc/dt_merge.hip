@@ -273,6 +273,7 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
   DT_HIP(hipMemsetAsync(nb.p, 0, 8, st));
   hipLaunchKernelGGL(k_occupancy, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts, job.pset,
                      job.npts, G, owner.as<uint32_t>());
+  DT_PROF_BEGIN(DT_KERN_BORDER, st);
   if (D == 2)
     hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
@@ -283,6 +284,7 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
                        job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
                        owner.as<uint32_t>(), reg, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>());
+  DT_PROF_END(st);
   hipLaunchKernelGGL(k_degenerate_parts, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
                      job.pset, job.npts, pool.set_cell0.as<uint32_t>(), vbflag.as<uint32_t>());
   DT_HIP(hipGetLastError());
@@ -442,6 +444,7 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
   DT_HIP(hipMemsetAsync(ctr.p, 0, 4, st));
   DT_HIP(hipMemsetAsync(hist.p, 0, 16 * 8, st));
   DT_HIP(hipMemsetAsync(flags.p, 0, 4, st));
+  DT_PROF_BEGIN(DT_KERN_MERGE, st);
   if (pool.ncells) {
     if (D == 2)
       hipLaunchKernelGGL(k_merge_local<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
@@ -468,6 +471,7 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
                          rows.as<int32_t>(), ctr.as<uint32_t>(), cap,
                          hist.as<unsigned long long>(), flags.as<uint32_t>());
   }
+  DT_PROF_END(st);
   DT_HIP(hipGetLastError());
   uint32_t hm = 0, hf = 0;
   unsigned long long hh[16];
