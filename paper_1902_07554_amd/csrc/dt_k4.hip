@@ -501,23 +501,22 @@ __global__ void k4_pick(K4Args a) {
   flush_pred<D>(a.ctr, pr.st);
 }
 
+// Candidate selection (one thread per active point): a located point
+// whose bid won its cell becomes a candidate unless a neighbouring cell
+// holds a smaller bid -- that bidder's cavity holds its own cell, which
+// touches this point's cell, so it would always win against this one.
 template <int D>
-__global__ void k4_cavity(K4Args a) {
+__global__ void k4_select(K4Args a) {
   uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t p = ia < a.nact ? a.act[ia] : 0xFFFFFFFFu;
-  Pred pr;
-  pr.init(&a.ctr->flags, a.fp32 != 0);
   bool want = false;
-  uint32_t L = DONE;
-  unsigned long long K = 0;
+  uint32_t p = 0;
   if (ia < a.nact) {
-    L = a.ploc[p];
+    p = a.act[ia];
+    uint32_t L = a.ploc[p];
     if (L != DONE && (L & NEEDWALK) == 0 && prio_of(p) < a.thresh) {
-      K = make_key(a.round, p);
+      unsigned long long K = make_key(a.round, p);
       want = (a.ccand[L] == K);
       if (want) {
-        // A smaller bid in a neighbouring cell always wins against this one:
-        // its cavity holds that cell, which touches this point's cell.
         uint4 nb = a.cn[L];
 #pragma unroll
         for (int i = 0; i <= D; i++)
@@ -526,75 +525,124 @@ __global__ void k4_cavity(K4Args a) {
     }
   }
   uint32_t slot = wave_alloc(want, &a.ctr->ncand);
-  bool gaveup = false;
-  uint32_t n = 0;
-  if (want && slot < a.maxcand) {
-    a.cand_pt[slot] = p;
-    a.cand_ext[slot] = DONE;
-    CavList L2{a.cav + (size_t)slot * a.cavcap, nullptr, nullptr, nullptr, a.cavcap};
+  if (want && slot < a.maxcand) a.cand_pt[slot] = p;
+}
+
+// Cavity search, one wavefront (block of 64) per candidate: a
+// level-synchronous breadth-first search over the conflict region, the
+// lanes testing the neighbours of the current frontier in parallel.  Each
+// cell found in conflict is claimed with the candidate's key (atomic
+// minimum; the previous value also detects a cell found twice); each
+// neighbour found not in conflict gets a shell claim.  A smaller claim
+// anywhere means this candidate cannot win: the search stops.
+template <int D>
+__global__ __launch_bounds__(64) void k4_cavity(K4Args a) {
+  __shared__ uint32_t s_n, s_flo, s_fhi, s_abort, s_gave, s_ext;
+  Pred pr;
+  pr.init(&a.ctr->flags, a.fp32 != 0);
+  const uint32_t lane = threadIdx.x;
+  const uint32_t ncand = min(a.ctr->ncand, a.maxcand);
+  uint32_t mx = 0, gave = 0;
+  unsigned long long cells = 0;
+  for (uint32_t slot = blockIdx.x; slot < ncand; slot += gridDim.x) {
+    const uint32_t p = a.cand_pt[slot];
+    const unsigned long long K = make_key(a.round, p);
+    const uint32_t L = a.ploc[p];
     double qp[3];
     unsigned long long qk;
     load_pt(a.pts, p, qp, qk);
-    bool ok = atomicMin(&a.ccav[L], K) > K;
-    if (ok) {
-      L2.cell(0) = L;
-      n = 1;
+    uint32_t* la = a.cav + (size_t)slot * a.cavcap;
+    if (lane == 0) {
+      a.cand_ext[slot] = DONE;
+      s_ext = DONE;
+      bool ok = atomicMin(&a.ccav[L], K) > K;
+      if (ok) la[0] = L;
+      s_abort = ok ? 0u : 1u;
+      s_gave = 0;
+      s_n = ok ? 1u : 0u;
+      s_flo = 0;
+      s_fhi = s_n;
     }
-    for (uint32_t h = 0; h < n && ok; h++) {
-      uint32_t c = L2.cell(h);
-      uint4 nb = a.cn[c];
-#pragma unroll
-      for (int i = 0; i <= D; i++) {
-        if (!ok) break;
-        uint32_t t = vat(nb, i) >> 2;
+    __syncthreads();
+    for (;;) {
+      const uint32_t flo = s_flo, fhi = s_fhi;
+      if (s_abort || flo >= fhi) break;
+      const uint32_t items = (fhi - flo) * (D + 1);
+      if (lane == 0 && s_n + items > a.cavcap) {
+        // this level may append up to `items` cells: make room first
+        if (s_n + items > a.cavcap + EXTCAP) {
+          s_abort = 1;
+          s_gave = 1;
+        } else if (s_ext == DONE) {
+          uint32_t e = atomicAdd(&a.ctr->extused, 1u);
+          if (e >= MAXEXT) {
+            s_abort = 1;
+            s_gave = 1;
+          } else {
+            s_ext = e;
+            a.cand_ext[slot] = e;
+          }
+        }
+      }
+      __syncthreads();
+      if (s_abort) break;
+      uint32_t* lb = (s_ext == DONE) ? nullptr : a.extcell + (size_t)s_ext * EXTCAP;
+      for (uint32_t it = lane; it < items; it += 64) {
+        if (s_abort) break;
+        const uint32_t h = flo + it / (D + 1);
+        const int i = (int)(it % (D + 1));
+        const uint32_t c = h < a.cavcap ? la[h] : lb[h - a.cavcap];
+        const uint32_t t = vat(a.cn[c], i) >> 2;
         if (t >= a.cap) {
           atomicOr(&a.ctr->flags, FAIL_INVARIANT);
-          ok = false;
+          s_abort = 1;
           break;
         }
-        {
-          uint4 tv = a.cv[t];
-          bool badv = false;
+        const uint4 tv = a.cv[t];
+        bool badv = false;
 #pragma unroll
-          for (int r = 0; r <= D; r++)
-            if (vat(tv, r) != INF_V && vat(tv, r) >= a.npts) badv = true;
-          if (badv) {
-            atomicOr(&a.ctr->flags, FAIL_INVARIANT);
-            ok = false;
-            break;
-          }
+        for (int r = 0; r <= D; r++)
+          if (vat(tv, r) != INF_V && vat(tv, r) >= a.npts) badv = true;
+        if (badv) {
+          atomicOr(&a.ctr->flags, FAIL_INVARIANT);
+          s_abort = 1;
+          break;
         }
-        unsigned long long cc = __atomic_load_n(&a.ccav[t], __ATOMIC_RELAXED);
+        const unsigned long long cc = __atomic_load_n(&a.ccav[t], __ATOMIC_RELAXED);
         if (cc == K) continue;
-        if (cc < K) { ok = false; break; }
+        if (cc < K) { s_abort = 1; break; }
         if (__atomic_load_n(&a.cshell[t], __ATOMIC_RELAXED) == K) continue;
-        if (conflict<D>(a, pr, a.cv[t], p, qp, qk)) {
-          unsigned long long old = atomicMin(&a.ccav[t], K);
-          if (old < K) { ok = false; break; }
+        if (conflict<D>(a, pr, tv, p, qp, qk)) {
+          const unsigned long long old = atomicMin(&a.ccav[t], K);
+          if (old < K) { s_abort = 1; break; }
           if (old == K) continue;
-          if (n == a.cavcap) {
-            uint32_t e = atomicAdd(&a.ctr->extused, 1u);
-            if (e >= MAXEXT) { ok = false; gaveup = true; break; }
-            a.cand_ext[slot] = e;
-            L2.b = a.extcell + (size_t)e * EXTCAP;
-          }
-          if (n >= a.cavcap + EXTCAP) { ok = false; gaveup = true; break; }
-          L2.cell(n++) = t;
+          const uint32_t pos = atomicAdd(&s_n, 1u);
+          if (pos < a.cavcap) la[pos] = t;
+          else lb[pos - a.cavcap] = t;
         } else {
           atomicMin(&a.cshell[t], K);
         }
       }
+      __syncthreads();
+      if (lane == 0) {
+        s_flo = fhi;
+        s_fhi = s_n;
+      }
+      __syncthreads();
     }
-    a.cand_n[slot] = ok ? n : 0u;
+    if (lane == 0) {
+      const uint32_t nn = s_abort ? 0u : s_n;
+      a.cand_n[slot] = nn;
+      mx = max(mx, s_n);
+      cells += s_n;
+      gave += s_gave;
+    }
+    __syncthreads();
   }
-  uint32_t g = wave_sum(gaveup ? 1u : 0u);
-  uint32_t tot = wave_sum((want && slot < a.maxcand) ? n : 0u);
-  if (lane_id() == 0 && tot) atomicAdd(&a.ctr->cavcells, (unsigned long long)tot);
-  uint32_t mx = (want && slot < a.maxcand) ? n : 0u;
-  for (int off = warpSize / 2; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, off));
-  if (lane_id() == 0) {
-    if (g) atomicAdd(&a.ctr->overflow, g);
+  if (lane == 0) {
+    if (gave) atomicAdd(&a.ctr->overflow, gave);
     if (mx) atomicMax(&a.ctr->maxcav, mx);
+    if (cells) atomicAdd(&a.ctr->cavcells, cells);
   }
   flush_pred<D>(a.ctr, pr.st);
 }
@@ -605,106 +653,130 @@ __device__ __forceinline__ uint32_t facet_cell(uint32_t info, int f, uint32_t ba
   return base + pre + (uint32_t)__popc(mask & ((1u << f) - 1u));
 }
 
+// Verification and retriangulation, one wavefront per candidate.  A
+// candidate wins if its cavity cells carry its cavity claim and no smaller
+// shell claim, and no cell around the cavity carries a smaller cavity
+// claim: then no other winner's cavity overlaps or touches its own, and
+// it can replace its cavity by the cone of new cells from the point to the
+// cavity boundary exactly as a sequential insertion would.  The lanes take
+// the cavity cells; the new cell on a boundary facet links to its
+// neighbours across the facets through the point by rotating around the
+// shared ridge inside the cavity.
 template <int D>
-__global__ void k4_insert(K4Args a) {
-  uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t ncand = min(a.ctr->ncand, a.maxcand);
-  uint32_t n = 0, p = 0;
-  unsigned long long K = 0;
-  bool win = false;
-  CavList cl{nullptr, nullptr, nullptr, nullptr, a.cavcap};
-  if (slot < ncand) {
-    n = a.cand_n[slot];
-    if (n > 0) {
-      p = a.cand_pt[slot];
-      K = make_key(a.round, p);
-      cl.a = a.cav + (size_t)slot * a.cavcap;
-      cl.ia = a.cavinfo + (size_t)slot * a.cavcap;
-      uint32_t e = a.cand_ext[slot];
-      if (e != DONE) {
-        cl.b = a.extcell + (size_t)e * EXTCAP;
-        cl.ib = a.extinfo + (size_t)e * EXTCAP;
-      }
-      win = true;
-      for (uint32_t h = 0; h < n && win; h++) {
-        uint32_t c = cl.cell(h);
-        if (a.ccav[c] != K || a.cshell[c] <= K) win = false;
-      }
-      for (uint32_t h = 0; h < n && win; h++) {
-        uint4 nb = a.cn[cl.cell(h)];
+__global__ __launch_bounds__(64) void k4_insert(K4Args a) {
+  __shared__ uint32_t s_fail, s_run, s_base;
+  const uint32_t lane = threadIdx.x;
+  const uint32_t ncand = min(a.ctr->ncand, a.maxcand);
+  uint32_t won = 0;
+  uint32_t* cnw = reinterpret_cast<uint32_t*>(a.cn);
+  for (uint32_t slot = blockIdx.x; slot < ncand; slot += gridDim.x) {
+    const uint32_t n = a.cand_n[slot];
+    if (n == 0) continue;
+    const uint32_t p = a.cand_pt[slot];
+    const unsigned long long K = make_key(a.round, p);
+    CavList cl{a.cav + (size_t)slot * a.cavcap, a.cavinfo + (size_t)slot * a.cavcap, nullptr,
+               nullptr, a.cavcap};
+    const uint32_t e = a.cand_ext[slot];
+    if (e != DONE) {
+      cl.b = a.extcell + (size_t)e * EXTCAP;
+      cl.ib = a.extinfo + (size_t)e * EXTCAP;
+    }
+    if (lane == 0) s_fail = 0;
+    __syncthreads();
+    for (uint32_t h = lane; h < n; h += 64) {
+      const uint32_t c = cl.cell(h);
+      if (a.ccav[c] != K || a.cshell[c] <= K) { s_fail = 1; continue; }
+      const uint4 nb = a.cn[c];
 #pragma unroll
-        for (int i = 0; i <= D; i++) {
-          uint32_t t = vat(nb, i) >> 2;
-          if (t >= a.cap) {
-            win = false;
-            atomicOr(&a.ctr->flags, FAIL_INVARIANT);
-            break;
-          }
-          unsigned long long cc = a.ccav[t];
-          if (cc != K && cc < K) win = false;
+      for (int i = 0; i <= D; i++) {
+        const uint32_t t = vat(nb, i) >> 2;
+        if (t >= a.cap) {
+          atomicOr(&a.ctr->flags, FAIL_INVARIANT);
+          s_fail = 1;
+          break;
         }
+        if (a.ccav[t] < K) s_fail = 1;
       }
     }
-  }
-  // boundary facets: one new cell each
-  uint32_t nbf = 0;
-  if (win) {
-    for (uint32_t h = 0; h < n; h++) {
-      uint32_t c = cl.cell(h);
-      uint4 nb = a.cn[c];
+    __syncthreads();
+    if (s_fail) continue;
+    // boundary facets of every cavity cell and their new cell numbers
+    if (lane == 0) s_run = 0;
+    __syncthreads();
+    for (uint32_t start = 0; start < n; start += 64) {
+      const uint32_t h = start + lane;
       uint32_t mask = 0;
+      uint32_t c = 0;
+      if (h < n) {
+        c = cl.cell(h);
+        const uint4 nb = a.cn[c];
 #pragma unroll
-      for (int i = 0; i <= D; i++)
-        if (a.ccav[vat(nb, i) >> 2] != K) mask |= 1u << i;
-      cl.info(h) = (nbf << 8) | mask;
-      nbf += (uint32_t)__popc(mask);
-      a.cpos[c] = h;
+        for (int i = 0; i <= D; i++)
+          if (a.ccav[vat(nb, i) >> 2] != K) mask |= 1u << i;
+      }
+      const uint32_t cnt = (uint32_t)__popc(mask);
+      uint32_t incl = cnt;
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if ((int)lane >= off) incl += y;
+      }
+      const uint32_t run = s_run;
+      if (h < n) {
+        cl.info(h) = ((run + incl - cnt) << 8) | mask;
+        a.cpos[c] = h;
+      }
+      const uint32_t total = __shfl(incl, 63, 64);
+      __syncthreads();
+      if (lane == 0) s_run = run + total;
+      __syncthreads();
     }
-  }
-  uint32_t base = wave_alloc_n(win ? nbf : 0u, &a.ctr->cells);
-  if (win && base + nbf > a.cap) {
-    atomicOr(&a.ctr->flags, FAIL_CELL_POOL);
-    win = false;
-  }
-  if (win) {
-    uint32_t* cnw = reinterpret_cast<uint32_t*>(a.cn);
-    for (uint32_t h = 0; h < n; h++) {
-      uint32_t c = cl.cell(h);
-      uint32_t inf = cl.info(h);
-      uint32_t mask = inf & 0xFFu;
+    const uint32_t nbf = s_run;
+    if (lane == 0) {
+      uint32_t b = atomicAdd(&a.ctr->cells, nbf);
+      if (b + nbf > a.cap) {
+        atomicOr(&a.ctr->flags, FAIL_CELL_POOL);
+        s_fail = 1;
+      }
+      s_base = b;
+    }
+    __syncthreads();
+    if (s_fail) continue;
+    const uint32_t base = s_base;
+    for (uint32_t h = lane; h < n; h += 64) {
+      const uint32_t c = cl.cell(h);
+      const uint32_t inf = cl.info(h);
+      const uint32_t mask = inf & 0xFFu;
       if (!mask) continue;
-      uint4 vc = a.cv[c];
-      uint4 nc = a.cn[c];
+      const uint4 vc = a.cv[c];
+      const uint4 nc = a.cn[c];
 #pragma unroll
       for (int i = 0; i <= D; i++) {
         if (!(mask >> i & 1u)) continue;
-        uint32_t x = facet_cell(inf, i, base);
+        const uint32_t x = facet_cell(inf, i, base);
         uint4 nv = vc;
         vset(nv, i, p);
         uint4 nn = make_uint4(0, 0, 0, NOSLOT);
-        uint32_t out = vat(nc, i);
+        const uint32_t out = vat(nc, i);
         vset(nn, i, out);
         cnw[(size_t)(out >> 2) * 4 + (out & 3u)] = (x << 2) | (uint32_t)i;
 #pragma unroll
         for (int j = 0; j <= D; j++) {
           if (j == i) continue;
-          // rotate around the ridge (vertices of c except slots i, j)
-          // through the cavity until a boundary facet is reached
           uint32_t cur = c;
           int sin = i, sout = j;
           uint4 vcur = vc;
           uint32_t link = 0xFFFFFFFFu;
           for (int step = 0; step < 4096; step++) {
-            uint32_t nbr = vat(a.cn[cur], sout);
-            uint32_t ncell = nbr >> 2;
+            const uint32_t nbr = vat(a.cn[cur], sout);
+            const uint32_t ncell = nbr >> 2;
             if (ncell >= a.cap) break;
             if (a.ccav[ncell] != K) {
-              uint32_t xp = facet_cell(cl.info(a.cpos[cur]), sout, base);
+              const uint32_t xp = facet_cell(cl.info(a.cpos[cur]), sout, base);
               link = (xp << 2) | (uint32_t)sin;
               break;
             }
-            uint32_t av = vat(vcur, sin);
-            uint4 vn = a.cv[ncell];
+            const uint32_t av = vat(vcur, sin);
+            const uint4 vn = a.cv[ncell];
             int nout = 0;
 #pragma unroll
             for (int r = 0; r <= D; r++)
@@ -724,11 +796,14 @@ __global__ void k4_insert(K4Args a) {
         a.cn[x] = nn;
       }
     }
-    for (uint32_t h = 0; h < n; h++) a.cfwd[cl.cell(h)] = base;
-    a.ploc[p] = DONE;
+    for (uint32_t h = lane; h < n; h += 64) a.cfwd[cl.cell(h)] = base;
+    if (lane == 0) {
+      a.ploc[p] = DONE;
+      won++;
+    }
+    __syncthreads();
   }
-  uint32_t w = wave_sum(win ? 1u : 0u);
-  if (lane_id() == 0 && w) atomicAdd(&a.ctr->inserted, w);
+  if (lane == 0 && won) atomicAdd(&a.ctr->inserted, won);
 }
 
 // ------------------------------------------------------------ extraction
@@ -887,18 +962,25 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     // ncand, inserted, overflow, extused, pending
     DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 5 * sizeof(uint32_t), st));
     uint32_t ga = nblk(nact ? (uint32_t)nact : 1u);
-    uint32_t gi = nblk((uint32_t)(nact < maxcand ? (nact ? nact : 1) : maxcand));
+    // one wavefront-sized block per candidate, grid-stride over the candidates
+    uint64_t cbound = nact < maxcand ? (nact ? nact : 1) : maxcand;
+    uint32_t gi = (uint32_t)(cbound < 16384 ? cbound : 16384);
     DT_PROF_BEGIN(DT_KERN_K4_PICK, st);
     if (D == 2) hipLaunchKernelGGL(k4_pick<2>, dim3(ga), dim3(BLOCK), 0, st, a);
     else hipLaunchKernelGGL(k4_pick<3>, dim3(ga), dim3(BLOCK), 0, st, a);
     DT_PROF_END(st);
     DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
-    if (D == 2) hipLaunchKernelGGL(k4_cavity<2>, dim3(ga), dim3(BLOCK), 0, st, a);
-    else hipLaunchKernelGGL(k4_cavity<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+    if (D == 2) {
+      hipLaunchKernelGGL(k4_select<2>, dim3(ga), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_cavity<2>, dim3(gi), dim3(64), 0, st, a);
+    } else {
+      hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_cavity<3>, dim3(gi), dim3(64), 0, st, a);
+    }
     DT_PROF_END(st);
     DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
-    if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(BLOCK), 0, st, a);
-    else hipLaunchKernelGGL(k4_insert<3>, dim3(gi), dim3(BLOCK), 0, st, a);
+    if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL(k4_insert<3>, dim3(gi), dim3(64), 0, st, a);
     DT_PROF_END(st);
     DT_HIP(hipGetLastError());
     DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
