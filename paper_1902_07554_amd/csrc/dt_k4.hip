@@ -521,6 +521,19 @@ __global__ void k4_select(K4Args a) {
 #pragma unroll
         for (int i = 0; i <= D; i++)
           if (a.ccand[vat(nb, i) >> 2] < K) want = false;
+        // Second ring: a smaller bid two cells away almost always claims a
+        // cell next to this cavity.  Skipping such candidates now (they
+        // would lose) saves their searches; the smallest bid of all is
+        // never skipped, so every round still inserts a point.
+        if (want) {
+#pragma unroll
+          for (int i = 0; i <= D && want; i++) {
+            uint4 nb2 = a.cn[vat(nb, i) >> 2];
+#pragma unroll
+            for (int j = 0; j <= D; j++)
+              if (a.ccand[vat(nb2, j) >> 2] < K) want = false;
+          }
+        }
       }
     }
   }
