@@ -7,7 +7,8 @@ test, border DT, merge) of one synthetic point set already resident in HBM.
 
 Default workload: 3D, n = 4,194,304 "bubbles" points (64 Gaussian clusters,
 sigma log-uniform in [0.01, 0.05], Dirichlet(1) weights, 5 % uniform
-background, seed 1), k = 256 partitions, sample rate 0.5 % (eta = 20,972),
+background, seed 1), k = 256 partitions, sample size sqrt(n) = 2048 (the
+paper's default),
 FP32-filtered predicates with FP64 and exact fallbacks.  The metric is
 Mpoints/s with the sample divide; the kd median-split divide runs on the
 same input for comparison, with balance and border sizes for both.
@@ -28,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 WORKLOADS = {
     # name: (distribution, n, dim, k, sample rate, precision)
-    "bubbles-3d-4M-k256": ("bubbles", 4_194_304, 3, 256, 0.005, "fp32"),
+    # sample size: the paper's default sqrt(n) (rate 0); the workload fixes only k
+    "bubbles-3d-4M-k256": ("bubbles", 4_194_304, 3, 256, 0.0, "fp32"),
     "uniform-3d-1M-k64": ("uniform", 1_048_576, 3, 64, 0.005, "fp64"),
     "uniform-2d-10k-k4": ("uniform", 10_000, 2, 4, 0.01, "fp64"),
 }
@@ -114,7 +116,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bubbles-3d-4M-k256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-kd", action="store_true", help="skip the kd-divide comparison")
-    ap.add_argument("--cpu-sample", type=int, default=250_000,
+    ap.add_argument("--cpu-sample", type=int, default=1_500_000,
                     help="points of the CPU-oracle baseline sample (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:

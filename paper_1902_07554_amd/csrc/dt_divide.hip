@@ -8,8 +8,9 @@
 //   2. triangulate the sample (the batched local-DT kernels, one set);
 //   3. graph G = (sample, Delaunay edges, w) with the weights of the paper's
 //      Table "weights", d = |v-w| / d*, d* = bounding-box diagonal;
-//   4. balanced k-way partition of G, |V_i| <= (1+eps) ceil(|V|/k): chunks
-//      of the sample in Morton order, then label-propagation sweeps that
+//   4. balanced k-way partition of G, |V_i| <= (1+eps) ceil(|V|/k): a
+//      recursive coordinate bisection of the sample (Morton-order chunks
+//      when k is not a power of two), then label-propagation sweeps that
 //      move vertices to the block they are most strongly connected to when
 //      the gain is positive and the target block has room (proposals into a
 //      block are ranked by gain, then vertex id, so the result does not
@@ -405,20 +406,27 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   hipLaunchKernelGGL(k_adj_weights, dim3(dblocks(eta)), dim3(DB), 0, st, S, eta,
                      off.as<uint32_t>(), adj.as<uint32_t>(), w.as<double>(), o.weight, dstar);
   DT_HIP(hipGetLastError());
-  // initial blocks: Morton order of the sample, k equal chunks
-  DevBuf mk, mv;
-  DT_TRY(mk.alloc((size_t)eta * 8));
-  DT_TRY(mv.alloc((size_t)eta * 4));
-  double3 dlo = make_double3(lo[0], lo[1], lo[2]);
-  double3 inv = make_double3(dx > 0 ? 1.0 / dx : 0.0, dy > 0 ? 1.0 / dy : 0.0,
-                             dz > 0 ? 1.0 / dz : 0.0);
-  hipLaunchKernelGGL(k_morton, dim3(dblocks(eta)), dim3(DB), 0, st, S, eta, D, dlo, inv,
-                     mk.as<unsigned long long>(), mv.as<uint32_t>());
-  DT_HIP(hipGetLastError());
-  DT_TRY(radix_sort_pairs(mk.as<unsigned long long>(), mv.as<uint32_t>(), eta, 64, st));
-  DT_TRY(part.alloc((size_t)eta * 4));
-  hipLaunchKernelGGL(k_init_blocks, dim3(dblocks(eta)), dim3(DB), 0, st, mv.as<uint32_t>(), eta,
-                     k, part.as<uint32_t>());
+  // initial blocks: recursive coordinate bisection of the sample (compact,
+  // balanced to +-1 vertex when k is a power of two); otherwise k equal
+  // chunks of the sample in Morton order
+  if ((k & (k - 1)) == 0) {
+    DevBuf boxes_unused;
+    DT_TRY(kd_divide(S, eta, D, k, part, boxes_unused, st));
+  } else {
+    DevBuf mk, mv;
+    DT_TRY(mk.alloc((size_t)eta * 8));
+    DT_TRY(mv.alloc((size_t)eta * 4));
+    double3 dlo = make_double3(lo[0], lo[1], lo[2]);
+    double3 inv = make_double3(dx > 0 ? 1.0 / dx : 0.0, dy > 0 ? 1.0 / dy : 0.0,
+                               dz > 0 ? 1.0 / dz : 0.0);
+    hipLaunchKernelGGL(k_morton, dim3(dblocks(eta)), dim3(DB), 0, st, S, eta, D, dlo, inv,
+                       mk.as<unsigned long long>(), mv.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    DT_TRY(radix_sort_pairs(mk.as<unsigned long long>(), mv.as<uint32_t>(), eta, 64, st));
+    DT_TRY(part.alloc((size_t)eta * 4));
+    hipLaunchKernelGGL(k_init_blocks, dim3(dblocks(eta)), dim3(DB), 0, st, mv.as<uint32_t>(), eta,
+                       k, part.as<uint32_t>());
+  }
   // label propagation under the balance bound
   DevBuf size, delta, pblock, pgain, pcount, poff, pcur, plist;
   DT_TRY(size.alloc((size_t)k * 4));

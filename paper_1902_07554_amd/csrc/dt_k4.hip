@@ -201,11 +201,11 @@ __device__ __forceinline__ void flush_pred(Counters* ctr, const PredStats& s) {
 // meets the hyperplane exactly in the facet's circumsphere, so q is inside
 // it iff In_pert(facet, e, q) has the sign of Orient1(facet, e); e carries
 // no perturbation and the answer does not depend on which e is used.
-template <int D>
-__device__ __noinline__ int conflict_coplanar(const double4* pts, uint32_t* flags, int fp32,
-                                              uint4 v, int inf, uint32_t q) {
-  Pred pr;
-  pr.init(flags, fp32 != 0);
+template <int D, bool F32>
+__device__ __noinline__ int conflict_coplanar(const double4* pts, uint32_t* flags, uint4 v,
+                                              int inf, uint32_t q) {
+  PredT<F32> pr;
+  pr.init(flags);
   PtsX X;
   double F[3][3];
   unsigned long long fk[3];
@@ -229,7 +229,7 @@ __device__ __noinline__ int conflict_coplanar(const double4* pts, uint32_t* flag
           if (k != ax) Y.p[j][t++] = F[j][k];
         Y.p[j][2] = 0.0;
       }
-      if (pr.orient<2>(Y) != 0) axis = ax;
+      if (pr.template orient<2>(Y) != 0) axis = ax;
     }
     if (axis < 0) return 0;
   }
@@ -247,16 +247,16 @@ __device__ __noinline__ int conflict_coplanar(const double4* pts, uint32_t* flag
       t++;
     }
   }
-  int oe = pr.orient<D>(X);
+  int oe = pr.template orient<D>(X);
   load_pt(pts, q, X.p[D + 1], X.key[D + 1]);
-  int s = pr.insphere<D>(X);
+  int s = pr.template insphere<D>(X);
   return (s != 0 && s == oe) ? 1 : 0;
 }
 
 // Is point q (coordinates qp, key qk) in conflict with the cell with
 // vertices v?
-template <int D>
-__device__ __forceinline__ bool conflict(const K4Args& a, Pred& pr, uint4 v, uint32_t q,
+template <int D, bool F32>
+__device__ __forceinline__ bool conflict(const K4Args& a, PredT<F32>& pr, uint4 v, uint32_t q,
                                          const double* qp, unsigned long long qk) {
   int inf = -1;
 #pragma unroll
@@ -268,7 +268,7 @@ __device__ __forceinline__ bool conflict(const K4Args& a, Pred& pr, uint4 v, uin
     for (int i = 0; i <= D; i++) load_pt(a.pts, vat(v, i), X.p[i], X.key[i]);
     X.p[D + 1][0] = qp[0]; X.p[D + 1][1] = qp[1]; X.p[D + 1][2] = qp[2];
     X.key[D + 1] = qk;
-    return pr.insphere<D>(X) > 0;
+    return pr.template insphere<D>(X) > 0;
   }
 #pragma unroll
   for (int i = 0; i <= D; i++) {
@@ -279,15 +279,15 @@ __device__ __forceinline__ bool conflict(const K4Args& a, Pred& pr, uint4 v, uin
       load_pt(a.pts, vat(v, i), X.p[i], X.key[i]);
     }
   }
-  int o = pr.orient<D>(X);
+  int o = pr.template orient<D>(X);
   if (o != 0) return o > 0;
-  return conflict_coplanar<D>(a.pts, &a.ctr->flags, a.fp32, v, inf, q) != 0;
+  return conflict_coplanar<D, F32>(a.pts, &a.ctr->flags, v, inf, q) != 0;
 }
 
 // Visibility walk from cell c to a cell in conflict with q: inside a
 // finite cell (closed), or a hull cell whose facet q sees.
-template <int D>
-__device__ uint32_t walk(const K4Args& a, Pred& pr, uint32_t c, uint32_t q, const double* qp,
+template <int D, bool F32>
+__device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q, const double* qp,
                          unsigned long long qk) {
   for (int step = 0; step < (1 << 16); step++) {
     if (c >= a.cap) break;
@@ -302,7 +302,7 @@ __device__ uint32_t walk(const K4Args& a, Pred& pr, uint32_t c, uint32_t q, cons
     }
     if (bad) break;
     if (inf >= 0) {
-      if (conflict<D>(a, pr, v, q, qp, qk)) return c;
+      if (conflict<D, F32>(a, pr, v, q, qp, qk)) return c;
       c = vat(a.cn[c], inf) >> 2;
       continue;
     }
@@ -320,7 +320,7 @@ __device__ uint32_t walk(const K4Args& a, Pred& pr, uint32_t c, uint32_t q, cons
         const double* s = (j == i) ? qp : P[j];
         X.p[j][0] = s[0]; X.p[j][1] = s[1]; X.p[j][2] = s[2];
       }
-      if (pr.orient<D>(X) < 0) exitf = i;
+      if (pr.template orient<D>(X) < 0) exitf = i;
     }
     if (exitf < 0) return c;
     c = vat(a.cn[c], exitf) >> 2;
@@ -336,8 +336,8 @@ template <int D>
 __global__ void k4_init_sets(K4Args a) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.nsets) return;
-  Pred pr;
-  pr.init(&a.ctr->flags, a.fp32 != 0);
+  PredT<false> pr;
+  pr.init(&a.ctr->flags);
   uint32_t lo = a.set_off[s], hi = a.set_off[s + 1];
   uint32_t iv[4] = {0, 0, 0, NOSLOT};
   int ni = 0;
@@ -364,14 +364,14 @@ __global__ void k4_init_sets(K4Args a) {
               if (k != ax) Y.p[j][t++] = src[j][k];
             Y.p[j][2] = 0.0;
           }
-          ok = pr.orient<2>(Y) != 0;
+          ok = pr.template orient<2>(Y) != 0;
         }
       } else {
         PtsX Y;
         for (int j = 0; j < ni; j++)
           for (int k = 0; k < 3; k++) Y.p[j][k] = P[j][k];
         for (int k = 0; k < 3; k++) Y.p[ni][k] = c[k];
-        ok = pr.orient<D>(Y) != 0;
+        ok = pr.template orient<D>(Y) != 0;
       }
       if (ok) {
         iv[ni] = p;
@@ -389,7 +389,7 @@ __global__ void k4_init_sets(K4Args a) {
     PtsX Y;
     for (int j = 0; j <= D; j++)
       for (int k = 0; k < 3; k++) Y.p[j][k] = P[j][k];
-    if (pr.orient<D>(Y) < 0) {
+    if (pr.template orient<D>(Y) < 0) {
       uint32_t t = iv[0]; iv[0] = iv[1]; iv[1] = t;
     }
   }
@@ -468,11 +468,11 @@ __global__ void k4_build_active(K4Args a, uint32_t* list, uint32_t* count) {
 // destroyed cells (each points into the star that replaced it) to a live
 // cell near them and walk from there; then every active point bids for its
 // cell.  Dormant points are not touched.
-template <int D>
+template <int D, bool F32>
 __global__ void k4_pick(K4Args a) {
   uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x;
-  Pred pr;
-  pr.init(&a.ctr->flags, a.fp32 != 0);
+  PredT<F32> pr;
+  pr.init(&a.ctr->flags);
   bool pending = false;
   uint32_t p = ia < a.nact ? a.act[ia] : 0xFFFFFFFFu;
   if (ia < a.nact) {
@@ -490,7 +490,7 @@ __global__ void k4_pick(K4Args a) {
         double qp[3];
         unsigned long long qk;
         load_pt(a.pts, p, qp, qk);
-        L = walk<D>(a, pr, L, p, qp, qk);
+        L = walk<D, F32>(a, pr, L, p, qp, qk);
         a.ploc[p] = L;
       }
       atomicMin(&a.ccand[L], make_key(a.round, p));
@@ -548,11 +548,11 @@ __global__ void k4_select(K4Args a) {
 // minimum; the previous value also detects a cell found twice); each
 // neighbour found not in conflict gets a shell claim.  A smaller claim
 // anywhere means this candidate cannot win: the search stops.
-template <int D>
-__global__ __launch_bounds__(64) void k4_cavity(K4Args a) {
+template <int D, bool F32>
+__global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
   __shared__ uint32_t s_n, s_flo, s_fhi, s_abort, s_gave, s_ext;
-  Pred pr;
-  pr.init(&a.ctr->flags, a.fp32 != 0);
+  PredT<F32> pr;
+  pr.init(&a.ctr->flags);
   const uint32_t lane = threadIdx.x;
   const uint32_t ncand = min(a.ctr->ncand, a.maxcand);
   uint32_t mx = 0, gave = 0;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(64) void k4_cavity(K4Args a) {
         if (cc == K) continue;
         if (cc < K) { s_abort = 1; break; }
         if (__atomic_load_n(&a.cshell[t], __ATOMIC_RELAXED) == K) continue;
-        if (conflict<D>(a, pr, tv, p, qp, qk)) {
+        if (conflict<D, F32>(a, pr, tv, p, qp, qk)) {
           const unsigned long long old = atomicMin(&a.ccav[t], K);
           if (old < K) { s_abort = 1; break; }
           if (old == K) continue;
@@ -979,17 +979,18 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     uint64_t cbound = nact < maxcand ? (nact ? nact : 1) : maxcand;
     uint32_t gi = (uint32_t)(cbound < 16384 ? cbound : 16384);
     DT_PROF_BEGIN(DT_KERN_K4_PICK, st);
-    if (D == 2) hipLaunchKernelGGL(k4_pick<2>, dim3(ga), dim3(BLOCK), 0, st, a);
-    else hipLaunchKernelGGL(k4_pick<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+    if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_pick<2, true>), dim3(ga), dim3(BLOCK), 0, st, a);
+    else if (D == 2) hipLaunchKernelGGL((k4_pick<2, false>), dim3(ga), dim3(BLOCK), 0, st, a);
+    else if (a.fp32) hipLaunchKernelGGL((k4_pick<3, true>), dim3(ga), dim3(BLOCK), 0, st, a);
+    else hipLaunchKernelGGL((k4_pick<3, false>), dim3(ga), dim3(BLOCK), 0, st, a);
     DT_PROF_END(st);
     DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
-    if (D == 2) {
-      hipLaunchKernelGGL(k4_select<2>, dim3(ga), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_cavity<2>, dim3(gi), dim3(64), 0, st, a);
-    } else {
-      hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
-      hipLaunchKernelGGL(k4_cavity<3>, dim3(gi), dim3(64), 0, st, a);
-    }
+    if (D == 2) hipLaunchKernelGGL(k4_select<2>, dim3(ga), dim3(BLOCK), 0, st, a);
+    else hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+    if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gi), dim3(64), 0, st, a);
+    else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gi), dim3(64), 0, st, a);
+    else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gi), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gi), dim3(64), 0, st, a);
     DT_PROF_END(st);
     DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
     if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);

@@ -502,14 +502,32 @@ __device__ __forceinline__ int in_f32(const PtsX& X) {
 }
 
 // ------------------------------------------------------------ front ends
-struct Pred {
+// Out-of-line FP64 filter followed by the exact stage, for the FP32 mode:
+// keeping it out of the callers' inline code keeps their register use (and
+// so the number of resident wavefronts) at the level of the FP32 path.
+// Result: 2*sign + (1 if the exact stage ran).
+template <int D>
+__device__ __noinline__ int orient_slow64(uint32_t* flags, PtsX X) {
+  int s = orient_f64<D>(X);
+  if (s) return 2 * ((D & 1) ? -s : s);
+  return 2 * orient1_exact(flags, D, X) + 1;
+}
+template <int D>
+__device__ __noinline__ int insphere_slow64(uint32_t* flags, PtsX X) {
+  int s = in_f64<D>(X);
+  if (s) return 2 * s;
+  return 2 * in_exact_pert(flags, D, X) + 1;
+}
+__device__ __forceinline__ int slow_sign(int r) { return (r - (r & 1)) / 2; }
+
+// F32: FP32 filter first (then FP64, then exact); otherwise FP64 first.
+template <bool F32>
+struct PredT {
   uint32_t* flags;
-  bool fp32;
   PredStats st;
 
-  __device__ void init(uint32_t* f, bool use32) {
+  __device__ void init(uint32_t* f) {
     flags = f;
-    fp32 = use32;
     st.calls[0] = st.calls[1] = st.f32ok[0] = st.f32ok[1] = st.exact[0] = st.exact[1] = 0;
   }
 
@@ -517,30 +535,36 @@ struct Pred {
   template <int D>
   __device__ int orient(const PtsX& X) {
     st.calls[0]++;
-    int s;
-    if (fp32) {
-      s = orient_f32<D>(X);
+    if (F32) {
+      int s = orient_f32<D>(X);
       if (s) { st.f32ok[0]++; return (D & 1) ? -s : s; }
+      int r = orient_slow64<D>(flags, X);
+      st.exact[0] += (uint32_t)(r & 1);
+      return slow_sign(r);
+    } else {
+      int s = orient_f64<D>(X);
+      if (s) return (D & 1) ? -s : s;
+      st.exact[0]++;
+      return orient1_exact(flags, D, X);
     }
-    s = orient_f64<D>(X);
-    if (s) return (D & 1) ? -s : s;
-    st.exact[0]++;
-    return orient1_exact(flags, D, X);
   }
 
   // sign of In_pert(X.p[0..D], X.p[D+1])
   template <int D>
   __device__ int insphere(const PtsX& X) {
     st.calls[1]++;
-    int s;
-    if (fp32) {
-      s = in_f32<D>(X);
+    if (F32) {
+      int s = in_f32<D>(X);
       if (s) { st.f32ok[1]++; return s; }
+      int r = insphere_slow64<D>(flags, X);
+      st.exact[1] += (uint32_t)(r & 1);
+      return slow_sign(r);
+    } else {
+      int s = in_f64<D>(X);
+      if (s) return s;
+      st.exact[1]++;
+      return in_exact_pert(flags, D, X);
     }
-    s = in_f64<D>(X);
-    if (s) return s;
-    st.exact[1]++;
-    return in_exact_pert(flags, D, X);
   }
 };
 
