@@ -35,8 +35,8 @@ WORKLOADS = {
     "uniform-2d-10k-k4": ("uniform", 10_000, 2, 4, 0.01, "fp64"),
 }
 
-# Algorithmic bytes per unit of work of each timed kernel:
-# the records the kernel must gather or stream for that unit.
+# Algorithmic bytes per unit of work of each timed kernel: the records the
+# kernel must gather or stream for that unit.
 PT = 32          # point record: x, y, z, id (double4)
 CELL = 16        # cell vertex record (uint4); neighbours another 16
 
@@ -109,6 +109,119 @@ def run(binding, pts, steps: int, warmup: int, k: int, rate: float, **opts):
     return res, (t1 - t0) * 1000.0 / steps, kern
 
 
+def bench_batch(args) -> dict:
+    """Batching pattern: 4096 independent 2D sets, sizes log-uniform in
+    [64, 65536], each uniform or N(0, I) (seed 1); one batched run with
+    autotuned launch tunables vs one launch per set."""
+    import torch
+    from paper_1902_07554_amd import binding, inputs
+    host, offsets = inputs.batch_sets(4096, 64, 65536, dim=2, seed=1)
+    n = int(offsets[-1])
+    pts = torch.from_numpy(host).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tuned = binding.batch_autotune(pts, offsets)
+    tune_s = time.perf_counter() - t0
+
+    def timed(**o):
+        res = None
+        for _ in range(args.warmup):
+            res = binding.batch_triangulate(pts, offsets, **o)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            res = binding.batch_triangulate(pts, offsets, **o)
+        torch.cuda.synchronize()
+        return res, (time.perf_counter() - a) * 1000.0 / args.steps
+
+    res, ms = timed(**tuned)
+    _, ms_def = timed()
+    # one launch per set on every 8th set (512 sets, same size mix)
+    sub = list(range(0, 4096, 8))
+    so = res.set_offsets(4096)
+    sub_n = int(sum(offsets[s + 1] - offsets[s] for s in sub))
+    for s in sub[:8]:
+        binding.triangulate(pts[offsets[s]:offsets[s + 1]], k=1)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    counts_equal = True
+    for s in sub:
+        r = binding.triangulate(pts[offsets[s]:offsets[s + 1]], k=1)
+        counts_equal &= (r.count == so[s + 1] - so[s])
+    torch.cuda.synchronize()
+    per_set_s = time.perf_counter() - a
+    per_set = sub_n / per_set_s / 1e6
+    value = n / (ms / 1000.0) / 1e6
+    return {
+        "metric": "Mpoints/s batched 2D DT, one batched run vs one launch per set",
+        "value": round(value, 4), "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch-2d-4096-sets", "sets": 4096, "n": n,
+                   "sizes": "log-uniform [64, 65536]", "dim": 2, "precision": "fp64"},
+        "simplices": res.count, "autotuned": tuned, "autotune_s": round(tune_s, 3),
+        "default_tunables_ms": round(ms_def, 3),
+        "per_set_launches": {"sets": len(sub), "points": sub_n, "seconds": round(per_set_s, 3),
+                             "Mpoints_per_s": round(per_set, 4),
+                             "simplex_counts_equal": bool(counts_equal)},
+        "batched_vs_per_set": round(value / per_set, 3),
+    }
+
+
+def bench_serve(args) -> dict:
+    """Serving pattern: Poisson stream of 3D jobs (mean rate --serve-rate per
+    second over --serve-seconds), n log-uniform in [1e3, 1e6], half uniform
+    half bubbles; k = max(1, n / 16384) rounded to a power of two; HBM
+    budget 64 GiB.  Latency = arrival to result ready."""
+    import math
+    import threading
+    import numpy as np
+    import torch
+    from paper_1902_07554_amd import binding, inputs
+    jobs = inputs.serve_stream(args.serve_rate, args.serve_seconds, 1000, 1_000_000, 3, seed=1)
+    data = [inputs.make(kind, n, 3, seed=js) for _, n, kind, js in jobs]
+    ks = [1 << max(0, round(math.log2(max(1.0, n / 16384)))) for _, n, _, _ in jobs]
+    torch.cuda.synchronize()
+    srv = binding.Server(64 << 30)
+    tickets = [None] * len(jobs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, (at, n, kind, js) in enumerate(jobs):
+            d = at - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit(data[i], k=ks[i])
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat, total = [], 0
+    for i, t in enumerate(tickets):
+        r = srv.wait(t)
+        total += jobs[i][1]
+        tt = srv.times(t)
+        lat.append(tt[2] - tt[0])
+        del r
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array(lat) * 1000.0
+    return {
+        "metric": "Mpoints/s and p50/p99 latency of a served Poisson stream of 3D DT jobs",
+        "value": round(total / wall / 1e6, 4), "unit": "Mpoints/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": round(wall * 1000.0, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serve-3d-poisson", "rate_per_s": args.serve_rate,
+                   "seconds": args.serve_seconds, "jobs": len(jobs), "points": total,
+                   "n": "log-uniform [1e3, 1e6]", "kinds": "uniform / bubbles",
+                   "hbm_budget_GiB": 64, "offered_Mpoints_per_s":
+                       round(total / args.serve_seconds / 1e6, 3)},
+        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "max_ms": round(float(lat.max()), 2),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,11 +231,21 @@ def main() -> int:
     ap.add_argument("--no-kd", action="store_true", help="skip the kd-divide comparison")
     ap.add_argument("--cpu-sample", type=int, default=1_500_000,
                     help="points of the CPU-oracle baseline sample (0 = skip)")
+    ap.add_argument("--mode", default="dt", choices=["dt", "batch", "serve"],
+                    help="dt: the headline triangulation; batch / serve: the patterns")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
-              "(the multi-GPU sharding is a design in DESIGN.md)", file=sys.stderr)
+              "(sharding over several GPUs is a design, not built)", file=sys.stderr)
         return 2
+    if args.mode == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return 0
+    if args.mode == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
+        return 0
 
     import torch
     from paper_1902_07554_amd import binding, inputs

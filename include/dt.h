@@ -75,6 +75,11 @@ typedef struct dt_options {
   int keep_stages;   /* 1: keep per-stage arrays for dt_result_stage                  */
   int border;        /* DT_BORDER_*; default DT_BORDER_REGION                         */
   int profile;       /* 1: time the kernels below with HIP events (dt_stats.kern_*)   */
+  /* Launch tunables of the parallel insertion (0 = default; dt_batch_autotune
+   * picks them for a batch).  They change timing only, never the result. */
+  int start_active;  /* points per set active in the first level; default 1024      */
+  int grow_div;      /* next level starts when pending < inserted/grow_div; default 2 */
+  int cand_blocks;   /* cap on wavefronts of the cavity/insert launches; default 16384 */
 } dt_options;
 
 /* Kernels timed when dt_options.profile = 1. */
@@ -188,18 +193,48 @@ int dt_batch_triangulate(const double* points, const int64_t* ids, const int64_t
 int dt_result_set_offsets(const dt_result* r, int64_t* dst, int64_t cap);
 
 /*
- * Serving (continuous batching).  A server owns a device-memory budget and
- * a worker thread.  Jobs are admitted in arrival order while their
- * estimated footprint fits the budget; admitted jobs that arrive while
- * others run join the next batched launch, so their work overlaps on the
- * device.  Each job's result is identical to dt_triangulate on its own.
- *   dt_server_create: hbm_budget_bytes > 0; opt NULL for defaults.
- *   dt_server_submit: points are copied at submission (host or device
- *                     memory per points_on_device); returns a ticket.
- *   dt_server_poll:   DT_OK with *out set when done, DT_E_NOT_READY before;
- *                     the caller then owns *out.
- *   dt_server_wait:   blocks until the job is done.
- *   dt_server_destroy: waits for admitted work and frees everything.
+ * dt_batch_autotune -- pick the launch tunables (dt_options.start_active,
+ * grow_div, cand_blocks) for batches like this one.  Times batched runs on
+ * every s-th set (about sample_points points in all; <= 0 means 2 Mi),
+ * changing one tunable at a time from the defaults, and writes opt (NULL =
+ * defaults) with the fastest tunables into *tuned.  The choice is cached
+ * per (D, precision, log2 mean set size, log2 set count) for the life of
+ * the process; a cached class returns at once.  points / offsets /
+ * points_on_device / stream as for dt_batch_triangulate.  The tunables
+ * never change a triangulation, only its time.
+ */
+int dt_batch_autotune(const double* points, const int64_t* offsets, int64_t num_sets, int D,
+                      const dt_options* opt, int points_on_device, void* stream,
+                      int64_t sample_points, dt_options* tuned);
+
+/*
+ * Serving (continuous batching; the paper's method applied to a stream of
+ * independent requests).  A server owns a device-memory budget and two
+ * worker threads, each with its own stream.  Jobs are admitted in arrival
+ * order while their estimated footprint fits the budget (a job alone may
+ * use the whole budget).  A worker takes the admitted jobs that have not
+ * started: consecutive direct jobs (k = 1) of one dimension run together
+ * as one batched run (as dt_batch_triangulate, up to 8 Mi points), a
+ * divide-and-conquer job (k > 1) runs alone; the two workers' runs overlap
+ * on the device.  Each job's result (rows labelled by row index, sorted
+ * when opt.sort_output) is identical to dt_triangulate on its own; if a
+ * batched run fails its jobs run again one by one, so each gets its own
+ * status.  Statistics of a batched job are those of its batch (n, k,
+ * num_simplices and part sizes are the job's own).
+ *   dt_server_create:  hbm_budget_bytes > 0; opt NULL for defaults
+ *                      (profile and keep_stages are ignored).
+ *   dt_server_submit:  points (n x D row-major doubles, host or device
+ *                      memory per points_on_device) are copied before it
+ *                      returns; returns a ticket.  DT_E_INVALID_ARG for bad
+ *                      arguments, DT_E_DEGENERATE when n < D+1, DT_E_NOMEM
+ *                      when the job's estimate exceeds the whole budget.
+ *   dt_server_poll:    DT_E_NOT_READY before the job is done; then its
+ *                      status, with *out set (owned by the caller) on DT_OK.
+ *                      A result is handed out once; later calls give DT_OK
+ *                      with *out = NULL.  DT_E_INVALID_ARG: unknown ticket.
+ *   dt_server_wait:    as poll, but blocks until the job is done.
+ *   dt_server_destroy: finishes all submitted jobs, joins the workers and
+ *                      frees every result not handed out.
  */
 typedef struct dt_server dt_server;
 int dt_server_create(size_t hbm_budget_bytes, const dt_options* opt, dt_server** srv);

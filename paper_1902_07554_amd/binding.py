@@ -32,7 +32,7 @@ EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_cou
            "dt_result_dim", "dt_result_copy", "dt_result_stats", "dt_result_free",
            "dt_result_stage", "dt_batch_triangulate", "dt_result_set_offsets",
            "dt_server_create", "dt_server_submit", "dt_server_poll", "dt_server_wait",
-           "dt_server_times", "dt_server_destroy"]
+           "dt_server_times", "dt_server_destroy", "dt_batch_autotune"]
 
 
 class Options(ctypes.Structure):
@@ -40,7 +40,9 @@ class Options(ctypes.Structure):
                 ("sort_output", ctypes.c_int), ("eps", ctypes.c_double),
                 ("grid_cell", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("refine_iters", ctypes.c_int), ("keep_stages", ctypes.c_int),
-                ("border", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("border", ctypes.c_int), ("profile", ctypes.c_int),
+                ("start_active", ctypes.c_int), ("grow_div", ctypes.c_int),
+                ("cand_blocks", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -107,9 +109,8 @@ def load():
     lib.dt_batch_triangulate.restype = I
     lib.dt_result_set_offsets.argtypes = [VP, VP, I64]
     lib.dt_result_set_offsets.restype = I
-    if not hasattr(lib, "dt_server_create"):
-        _lib = lib
-        return lib
+    lib.dt_batch_autotune.argtypes = [VP, VP, I64, I, P(Options), I, VP, I64, P(Options)]
+    lib.dt_batch_autotune.restype = I
     lib.dt_server_create.argtypes = [ctypes.c_size_t, P(Options), P(VP)]
     lib.dt_server_create.restype = I
     lib.dt_server_submit.argtypes = [VP, VP, I64, I, I, D, I, P(ctypes.c_uint64)]
@@ -278,6 +279,24 @@ def batch_triangulate(points, offsets, ids=None, **opts) -> Result:
     return Result(h)
 
 
+def batch_autotune(points, offsets, sample_points: int = 0, **opts) -> dict:
+    """dt_batch_autotune: the fastest launch tunables for batches like this
+    one, as a dict of option values to pass to batch_triangulate."""
+    lib = load()
+    ptr, n, d, on_dev, keep, stream = _pointer(points)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    o = options(**opts)
+    out = Options()
+    st = lib.dt_batch_autotune(ctypes.c_void_p(ptr), off.ctypes.data, len(off) - 1, d,
+                               ctypes.byref(o), on_dev, ctypes.c_void_p(stream) if stream else None,
+                               int(sample_points), ctypes.byref(out))
+    del keep
+    if st != DT_OK:
+        raise DTError(st)
+    return {"start_active": out.start_active, "grow_div": out.grow_div,
+            "cand_blocks": out.cand_blocks}
+
+
 class Server:
     """dt_server_*: continuous-batching triangulation server."""
 
@@ -306,6 +325,8 @@ class Server:
             return None
         if st != DT_OK:
             raise DTError(st)
+        if not h:
+            raise DTError(DT_E_INVALID_ARG, "result already taken")
         return Result(h)
 
     def wait(self, ticket: int) -> Result:
@@ -313,6 +334,8 @@ class Server:
         st = self.lib.dt_server_wait(self.h, ticket, ctypes.byref(h))
         if st != DT_OK:
             raise DTError(st)
+        if not h:
+            raise DTError(DT_E_INVALID_ARG, "result already taken")
         return Result(h)
 
     def times(self, ticket: int):

@@ -44,18 +44,43 @@ extern "C" const char* dt_strerror(int s) {
 
 namespace dtk {
 
+// Pinned host words of the call contexts, kept per thread and reused
+// (freeing pinned memory synchronises the device).
+namespace {
+struct PinnedCache {
+  std::vector<void*> free_blocks;
+  ~PinnedCache() {
+    for (void* b : free_blocks) (void)hipHostFree(b);
+  }
+};
+thread_local PinnedCache g_pinned;
+constexpr size_t PINNED_BLOCK = 256;
+static_assert(sizeof(Counters) + 16 <= PINNED_BLOCK, "pinned block too small");
+}  // namespace
+
 Ctx::~Ctx() {
-  if (hctr) (void)hipHostFree(hctr);
-  if (hflag) (void)hipHostFree(hflag);
+  if (hctr) g_pinned.free_blocks.push_back(hctr);
 }
 
 int Ctx::init() {
   DT_TRY(dctr.alloc(sizeof(Counters)));
   DT_TRY(dflag.alloc(16));
-  DT_HIP(hipHostMalloc((void**)&hctr, sizeof(Counters), hipHostMallocDefault));
-  DT_HIP(hipHostMalloc((void**)&hflag, 16, hipHostMallocDefault));
+  void* b = nullptr;
+  if (!g_pinned.free_blocks.empty()) {
+    b = g_pinned.free_blocks.back();
+    g_pinned.free_blocks.pop_back();
+  } else {
+    DT_HIP(hipHostMalloc(&b, PINNED_BLOCK, hipHostMallocDefault));
+  }
+  hctr = static_cast<Counters*>(b);
+  hflag = reinterpret_cast<uint32_t*>(static_cast<char*>(b) + sizeof(Counters));
   return DT_OK;
 }
+
+static thread_local hipStream_t g_alloc_stream = nullptr;
+hipStream_t alloc_stream() { return g_alloc_stream; }
+AllocStreamScope::AllocStreamScope(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
+AllocStreamScope::~AllocStreamScope() { g_alloc_stream = prev; }
 
 static thread_local Profiler* g_prof = nullptr;
 Profiler* active_profiler() { return g_prof; }
@@ -86,9 +111,7 @@ int sort_rows_inplace(dt_result* r, hipStream_t st) {
   return DT_OK;
 }
 
-}  // namespace dtk
-
-static int check_opts(const dt_options* in, dt_options& o) {
+int check_options(const dt_options* in, dt_options& o) {
   dt_default_options(&o);
   if (in) o = *in;
   if (o.divide != DT_DIVIDE_SAMPLE && o.divide != DT_DIVIDE_KD) return DT_E_INVALID_ARG;
@@ -97,8 +120,13 @@ static int check_opts(const dt_options* in, dt_options& o) {
   if (!(o.eps >= 0.0) || !(o.grid_cell > 0.0)) return DT_E_INVALID_ARG;
   if (o.refine_iters < 0) return DT_E_INVALID_ARG;
   if (o.border != DT_BORDER_REGION && o.border != DT_BORDER_GRID) return DT_E_INVALID_ARG;
+  if (o.start_active < 0 || o.start_active > (1 << 24)) return DT_E_INVALID_ARG;
+  if (o.grow_div < 0 || o.grow_div > 64) return DT_E_INVALID_ARG;
+  if (o.cand_blocks < 0 || o.cand_blocks > (1 << 20)) return DT_E_INVALID_ARG;
   return DT_OK;
 }
+
+}  // namespace dtk
 
 extern "C" int dt_triangulate(const double* points, int64_t n, int D, int k, double sample_rate,
                               const dt_options* opt, int points_on_device, void* stream,
@@ -108,7 +136,7 @@ extern "C" int dt_triangulate(const double* points, int64_t n, int D, int k, dou
   if ((D != 2 && D != 3) || n < 0 || n > 0x7FFFFFF0ll || k < 1 || !points) return DT_E_INVALID_ARG;
   if (!(sample_rate >= 0.0 && sample_rate <= 1.0)) return DT_E_INVALID_ARG;
   dt_options o;
-  DT_TRY(check_opts(opt, o));
+  DT_TRY(check_options(opt, o));
   if (n < D + 1) return DT_E_DEGENERATE;
   hipStream_t st = (hipStream_t)stream;
   dt_result* r = new dt_result();
@@ -148,7 +176,7 @@ extern "C" int dt_batch_triangulate(const double* points, const int64_t* ids,
   int64_t n = offsets[num_sets];
   if (n > 0x7FFFFFF0ll || (n > 0 && !points)) return DT_E_INVALID_ARG;
   dt_options o;
-  DT_TRY(check_opts(opt, o));
+  DT_TRY(check_options(opt, o));
   hipStream_t st = (hipStream_t)stream;
   dt_result* r = new dt_result();
   r->D = D;

@@ -130,7 +130,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     dp = din.as<double>();
   }
   DT_TRY(P.alloc((size_t)n * sizeof(double4)));
-  DT_TRY(prep_points(dp, nullptr, n, D, P.as<double4>(), scratch, cx.dflag.as<uint32_t>(),
+  DT_TRY(prep_points(dp, nullptr, nullptr, n, D, P.as<double4>(), scratch, cx.dflag.as<uint32_t>(),
                      cx.hflag, st));
   scratch.release();
   double lo[3], hi[3];
@@ -237,6 +237,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   job.pset = pset.as<uint32_t>();
   job.set_off = off.as<uint32_t>();
   job.fp32 = o.precision == DT_PREC_FP32;
+  job.tune(o);
   CellPool pool;
   {
     K4Stats ks;

@@ -21,29 +21,67 @@ namespace dtk {
     if (s_ != DT_OK) return s_; \
   } while (0)
 
+// Stream-ordered allocation: while a thread has an allocation stream set,
+// DevBuf::alloc takes memory from the device's stream-ordered pool on that
+// stream (no device-wide synchronisation at free, so concurrent calls on
+// other streams keep running); otherwise plain hipMalloc/hipFree.  Every
+// use of such a buffer must be on that stream.
+hipStream_t alloc_stream();
+struct AllocStreamScope {
+  hipStream_t prev;
+  explicit AllocStreamScope(hipStream_t s);
+  ~AllocStreamScope();
+};
+
 // Owning device buffer.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t ast = nullptr;   // stream of a stream-ordered allocation
+  bool ordered = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), ast(o.ast), ordered(o.ordered) {
+    o.p = nullptr;
+    o.bytes = 0;
+    o.ordered = false;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; ast = o.ast; ordered = o.ordered;
+      o.p = nullptr; o.bytes = 0; o.ordered = false;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)(ordered ? hipFreeAsync(p, ast) : hipFree(p));
     p = nullptr;
     bytes = 0;
+    ordered = false;
   }
+  static int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? DT_E_NOMEM : DT_E_DEVICE; }
+  // Scratch memory (stream-ordered when the thread has an allocation stream).
   int alloc(size_t n) {
+    hipStream_t s = alloc_stream();
+    if (!s) return alloc_plain(n);
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMallocAsync(&p, n, s);
+    if (e != hipSuccess) { p = nullptr; return status_of(e); }
+    bytes = n;
+    ast = s;
+    ordered = true;
+    return DT_OK;
+  }
+  // Memory that outlives the call (result rows): always hipMalloc.
+  int alloc_plain(size_t n) {
     release();
     if (n == 0) n = 16;
     hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) { p = nullptr; return e == hipErrorOutOfMemory ? DT_E_NOMEM : DT_E_DEVICE; }
+    if (e != hipSuccess) { p = nullptr; return status_of(e); }
     bytes = n;
     return DT_OK;
   }
@@ -61,6 +99,15 @@ struct LocalJob {
   const uint32_t* pset = nullptr; // [npts] set of each point
   const uint32_t* set_off = nullptr;  // [nsets+1]
   bool fp32 = false;
+  // launch tunables (timing only)
+  uint32_t start_active = 1024;   // active points per set in the first level
+  uint32_t grow_div = 2;          // next level when pending < inserted / grow_div
+  uint32_t cand_blocks = 16384;   // cap on cavity/insert wavefronts
+  void tune(const dt_options& o) {
+    if (o.start_active > 0) start_active = (uint32_t)o.start_active;
+    if (o.grow_div > 0) grow_div = (uint32_t)o.grow_div;
+    if (o.cand_blocks > 0) cand_blocks = (uint32_t)o.cand_blocks;
+  }
 };
 
 // Cell pool: cells live at indices [0, ncells); cfwd == ALIVE marks a live

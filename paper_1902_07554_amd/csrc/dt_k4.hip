@@ -936,10 +936,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
             hctr->active, hctr->cells, hctr->flags);
   if (hctr->flags) return DT_E_INTERNAL;
   uint64_t remaining = hctr->active, done = 0;
-  // activation levels: about 1024 active points per set at first, doubled
-  // whenever fewer than half as many are pending as are already inserted
+  // activation levels: about start_active points per set at first, doubled
+  // whenever fewer are pending than 1/grow_div of those already inserted
   const uint32_t PMAX = 1u << 20;
-  uint64_t t0 = ((uint64_t)PMAX * 1024ull * job.nsets) / (npts ? npts : 1);
+  uint64_t t0 = ((uint64_t)PMAX * job.start_active * job.nsets) / (npts ? npts : 1);
   uint32_t thresh = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
   int stall = 0;
   uint32_t round = 1;
@@ -977,7 +977,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     uint32_t ga = nblk(nact ? (uint32_t)nact : 1u);
     // one wavefront-sized block per candidate, grid-stride over the candidates
     uint64_t cbound = nact < maxcand ? (nact ? nact : 1) : maxcand;
-    uint32_t gi = (uint32_t)(cbound < 16384 ? cbound : 16384);
+    uint32_t gi = (uint32_t)(cbound < job.cand_blocks ? cbound : job.cand_blocks);
     DT_PROF_BEGIN(DT_KERN_K4_PICK, st);
     if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_pick<2, true>), dim3(ga), dim3(BLOCK), 0, st, a);
     else if (D == 2) hipLaunchKernelGGL((k4_pick<2, false>), dim3(ga), dim3(BLOCK), 0, st, a);
@@ -1011,7 +1011,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     done += ins;
     ins_since += ins;
     uint64_t left = hctr->pending >= ins ? hctr->pending - ins : 0;
-    if (thresh < PMAX && left < (done / 2 > 256 ? done / 2 : 256)) {
+    uint64_t lim = done / job.grow_div;
+    if (thresh < PMAX && left < (lim > 256 ? lim : 256)) {
       thresh = thresh * 2 > PMAX ? PMAX : thresh * 2;
     } else if (ins == 0) {
       if (++stall > 8) { ks.rounds = (int)round; return DT_E_INTERNAL; }

@@ -431,7 +431,7 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
     DT_HIP(hipStreamSynchronize(st));
   }
   uint32_t cap = nl + nbd;
-  DT_TRY(rows.alloc((size_t)(cap ? cap : 1) * (D + 1) * 4));
+  DT_TRY(rows.alloc_plain((size_t)(cap ? cap : 1) * (D + 1) * 4));
   uint32_t tsize = 64;
   while (tsize < 2 * b.nb_finite + 16) tsize <<= 1;
   DevBuf occ, tkeys, ctr, hist, flags;

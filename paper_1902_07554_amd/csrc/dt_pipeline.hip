@@ -92,9 +92,6 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
     DT_TRY(dkeys.alloc((size_t)n * 8));
     DT_HIP(hipMemcpyAsync(dkeys.p, ids, (size_t)n * 8, hipMemcpyHostToDevice, st));
   }
-  DT_TRY(pts.alloc((size_t)n * sizeof(double4)));
-  DT_TRY(prep_points(dp, ids ? dkeys.as<long long>() : nullptr, n, D, pts.as<double4>(), scratch,
-                     cx.dflag.as<uint32_t>(), cx.hflag, st));
   std::vector<uint32_t> off32(num_sets + 1);
   for (int64_t s = 0; s <= num_sets; s++) off32[s] = (uint32_t)offsets[s];
   DT_TRY(setoff.alloc((size_t)(ns + 1) * 4));
@@ -102,6 +99,9 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   DT_TRY(pset.alloc((size_t)n * 4));
   hipLaunchKernelGGL(k_set_of_point, dim3(blocks(n)), dim3(TB), 0, st, setoff.as<uint32_t>(), ns,
                      n, pset.as<uint32_t>());
+  DT_TRY(pts.alloc((size_t)n * sizeof(double4)));
+  DT_TRY(prep_points(dp, ids ? dkeys.as<long long>() : nullptr, ns > 1 ? pset.as<uint32_t>() : nullptr,
+                     n, D, pts.as<double4>(), scratch, cx.dflag.as<uint32_t>(), cx.hflag, st));
   double t1 = now_ms();
   LocalJob job;
   job.D = D;
@@ -111,6 +111,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   job.pset = pset.as<uint32_t>();
   job.set_off = setoff.as<uint32_t>();
   job.fp32 = o.precision == DT_PREC_FP32;
+  job.tune(o);
   CellPool pool;
   K4Stats ks;
   int s = k4_run(job, pool, cx.dc(), cx.hctr, st, ks);
@@ -128,7 +129,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
     hcount = *cx.hflag;
     r->m = hcount;
     r->set_offsets[1] = hcount;
-    DT_TRY(r->rows.alloc((size_t)hcount * (D + 1) * 4));
+    DT_TRY(r->rows.alloc_plain((size_t)hcount * (D + 1) * 4));
     DT_TRY(k4_extract(job, pool, r->rows.as<int32_t>(), cx.dflag.as<uint32_t>(), nullptr, st));
   } else {
     // per-set counts, then rows grouped by set
@@ -150,7 +151,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
     }
     r->set_offsets[ns] = (int64_t)tot;
     r->m = (int64_t)tot;
-    DT_TRY(r->rows.alloc((size_t)tot * (D + 1) * 4));
+    DT_TRY(r->rows.alloc_plain((size_t)tot * (D + 1) * 4));
     DT_HIP(hipMemcpyAsync(base.p, hb.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
     DT_HIP(hipMemsetAsync(cursor.p, 0, (size_t)ns * 4, st));
     if (pool.ncells) {

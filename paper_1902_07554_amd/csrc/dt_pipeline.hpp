@@ -26,6 +26,10 @@ struct Ctx {
 };
 
 double now_ms();
+// Validate options (NULL = defaults) into o.
+int check_options(const dt_options* in, dt_options& o);
+// Sort the rows of r lexicographically (host round trip).
+int sort_rows_inplace(dt_result* r, hipStream_t st);
 
 int run_triangulate(const double* points, int64_t n, int D, int k, double sample_rate,
                     const dt_options& o, bool on_device, hipStream_t st, dt_result* r);

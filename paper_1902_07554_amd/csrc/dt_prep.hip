@@ -33,22 +33,24 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z;
 }
 
-// Duplicate detection by open addressing on the coordinate bits: the table
-// stores point index + 1; a collision compares coordinates.
-__global__ void k_dupcheck(const double4* __restrict__ p, uint32_t n, uint32_t* table,
-                           uint32_t tmask, uint32_t* flags) {
+// Duplicate detection by open addressing on the coordinate bits (and the
+// set, when points belong to independent sets): the table stores point
+// index + 1; a collision compares coordinates and set.
+__global__ void k_dupcheck(const double4* __restrict__ p, const uint32_t* __restrict__ pset,
+                           uint32_t n, uint32_t* table, uint32_t tmask, uint32_t* flags) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double4 a = p[i];
+  uint32_t sa = pset ? pset[i] : 0u;
   uint64_t bx = (uint64_t)__double_as_longlong(a.x), by = (uint64_t)__double_as_longlong(a.y),
            bz = (uint64_t)__double_as_longlong(a.z);
-  uint32_t h = (uint32_t)mix64(bx ^ mix64(by ^ mix64(bz)));
+  uint32_t h = (uint32_t)mix64(bx ^ mix64(by ^ mix64(bz ^ mix64(sa))));
   for (uint32_t probe = 0; probe <= tmask; probe++) {
     uint32_t s = (h + probe) & tmask;
     uint32_t old = atomicCAS(&table[s], 0u, i + 1);
     if (old == 0) return;
     double4 b = p[old - 1];
-    if (b.x == a.x && b.y == a.y && b.z == a.z) {
+    if (b.x == a.x && b.y == a.y && b.z == a.z && (!pset || pset[old - 1] == sa)) {
       atomicOr(flags, 2u);
       return;
     }
@@ -56,8 +58,9 @@ __global__ void k_dupcheck(const double4* __restrict__ p, uint32_t n, uint32_t* 
   atomicOr(flags, 4u);
 }
 
-int prep_points(const double* dev_in, const long long* dev_keys, uint32_t n, int D, double4* out,
-                DevBuf& scratch, uint32_t* dflag, uint32_t* hflag, hipStream_t st) {
+int prep_points(const double* dev_in, const long long* dev_keys, const uint32_t* pset, uint32_t n,
+                int D, double4* out, DevBuf& scratch, uint32_t* dflag, uint32_t* hflag,
+                hipStream_t st) {
   if (n == 0) return DT_OK;
   uint32_t tsize = 1;
   while (tsize < 2 * n) tsize <<= 1;
@@ -66,7 +69,7 @@ int prep_points(const double* dev_in, const long long* dev_keys, uint32_t n, int
   DT_HIP(hipMemsetAsync(dflag, 0, 4, st));
   hipLaunchKernelGGL(k_pack, dim3((n + PB - 1) / PB), dim3(PB), 0, st, dev_in, dev_keys, n, D, out,
                      dflag);
-  hipLaunchKernelGGL(k_dupcheck, dim3((n + PB - 1) / PB), dim3(PB), 0, st, out, n,
+  hipLaunchKernelGGL(k_dupcheck, dim3((n + PB - 1) / PB), dim3(PB), 0, st, out, pset, n,
                      scratch.as<uint32_t>(), tsize - 1, dflag);
   DT_HIP(hipGetLastError());
   DT_HIP(hipMemcpyAsync(hflag, dflag, 4, hipMemcpyDeviceToHost, st));

@@ -71,3 +71,61 @@ def test_error_paths(dtlib):
     with pytest.raises(dtlib.DTError) as e:
         dtlib.triangulate(np.zeros((5, 4)))
     assert e.value.status == dtlib.DT_E_INVALID_ARG
+
+
+def test_autotuned_batch_is_identical(dtlib):
+    """Launch tunables change timing only: the autotuned batch, the default
+    batch and extreme tunables give the same simplices, equal to the
+    oracle's on sampled sets."""
+    pts, offsets = inputs.batch_sets(96, 64, 8192, dim=2, seed=4)
+    print(f"[autotune] sets=96 n={offsets[-1]}", flush=True)
+    tuned = dtlib.batch_autotune(pts, offsets, sample_points=60000)
+    assert set(tuned) == {"start_active", "grow_div", "cand_blocks"}
+    # a second call of the same size class comes from the cache
+    assert dtlib.batch_autotune(pts, offsets, sample_points=60000) == tuned
+    a = dtlib.batch_triangulate(pts, offsets, **tuned)
+    b = dtlib.batch_triangulate(pts, offsets)
+    c = dtlib.batch_triangulate(pts, offsets, start_active=16, grow_div=64, cand_blocks=1)
+    ra, rb, rc = a.rows(), b.rows(), c.rows()
+    soa, sob, soc = a.set_offsets(96), b.set_offsets(96), c.set_offsets(96)
+    for s in range(96):
+        x = oracle.canonical(ra[soa[s]:soa[s + 1]])
+        assert np.array_equal(x, oracle.canonical(rb[sob[s]:sob[s + 1]])), s
+        assert np.array_equal(x, oracle.canonical(rc[soc[s]:soc[s + 1]])), s
+        if s % 16 == 0:
+            a, b = offsets[s], offsets[s + 1]   # rows carry global point indices
+            assert np.array_equal(x, oracle.delaunay(pts[a:b], np.arange(a, b))), s
+
+
+def test_batch_allows_same_point_in_different_sets(dtlib):
+    """Sets are independent: a point repeated in another set is no duplicate."""
+    p = inputs.make("uniform", 300, 3, seed=8)
+    pts = np.concatenate([p, p[::-1]])
+    res = dtlib.batch_triangulate(pts, [0, 300, 600])
+    rows, so = res.rows(), res.set_offsets(2)
+    want = oracle.delaunay(p)
+    assert np.array_equal(oracle.canonical(rows[so[0]:so[1]]), want)
+    assert len(rows[so[1]:so[2]]) == len(want)
+    dup = pts.copy()
+    dup[400] = dup[420]
+    with pytest.raises(dtlib.DTError) as e:
+        dtlib.batch_triangulate(dup, [0, 300, 600])
+    assert e.value.status == dtlib.DT_E_DUPLICATE
+
+
+@pytest.mark.parametrize("dim,n,dist", [(2, 20000, "normal"), (3, 30000, "bubbles"),
+                                        (3, 8 ** 3, "lattice")])
+def test_fp32_filter_matches_oracle(dtlib, dim, n, dist):
+    """FP32 filtered predicates (with FP64 and exact fallbacks) decide every
+    sign exactly: the simplex set is the oracle's, and on a lattice the
+    exact stage is reached."""
+    p = inputs.lattice(8, 3, seed=6) if dist == "lattice" else inputs.make(dist, n, dim, seed=12)
+    print(f"[fp32] dim={dim} n={len(p)} dist={dist}", flush=True)
+    res = dtlib.triangulate(p, k=1, precision="fp32")
+    assert np.array_equal(_rows(res), oracle.delaunay(p))
+    pred = res.stats()["pred"]
+    ins = pred["insphere3d" if dim == 3 else "insphere2d"]
+    assert ins["calls"] > 0
+    assert ins["calls"] == ins["fp32"] + ins["fp64"] + ins["exact"]
+    if dist == "lattice":
+        assert ins["exact"] > 0
