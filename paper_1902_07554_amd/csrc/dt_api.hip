@@ -54,7 +54,7 @@ struct PinnedCache {
   }
 };
 thread_local PinnedCache g_pinned;
-constexpr size_t PINNED_BLOCK = 256;
+constexpr size_t PINNED_BLOCK = 512;
 static_assert(sizeof(Counters) + 16 <= PINNED_BLOCK, "pinned block too small");
 }  // namespace
 

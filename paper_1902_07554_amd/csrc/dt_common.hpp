@@ -41,6 +41,19 @@ struct Counters {
   unsigned int maxcav;            // largest cavity seen
   unsigned int active;            // points to insert
   unsigned int pad;
+  // round control, kept on the device so that rounds run back to back
+  // without the host in the loop
+  unsigned long long remaining;   // points not yet inserted
+  unsigned long long done;        // points inserted
+  unsigned long long ins_since;   // inserted since the active list was built
+  unsigned int thresh;            // priority threshold of the current level
+  unsigned int built_thresh;      // threshold the active list was built for
+  unsigned int nact;              // length of the active list
+  unsigned int rebuild;           // 1: rebuild the active list this round
+  unsigned int stall;             // consecutive rounds without an insertion
+  unsigned int skip;              // 1: finished or failed; later rounds do nothing
+  unsigned int rounds;            // rounds that did work
+  unsigned int pad2;
 };
 
 }  // namespace dtk

@@ -72,9 +72,9 @@ struct K4Args {
   uint32_t maxcand;
   uint32_t cavcap;
   uint32_t round;
-  uint32_t thresh;      // points with prio_of(p) < thresh are active
-  const uint32_t* act;  // active point list (a superset of the pending points)
-  uint32_t nact;
+  uint32_t* act;        // active point list (a superset of the pending points);
+                        // its length and the level's threshold live in ctr
+  uint32_t grow_div;
   int fp32;
 };
 
@@ -455,12 +455,67 @@ __global__ void k4_place_init(K4Args a) {
 }
 
 // Active list: the points not yet inserted whose priority is below the
-// threshold (rebuilt when the threshold grows or the list thins out).
-__global__ void k4_build_active(K4Args a, uint32_t* list, uint32_t* count) {
-  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  bool take = p < a.npts && a.ploc[p] != DONE && prio_of(p) < a.thresh;
-  uint32_t slot = wave_alloc(take, count);
-  if (take) list[slot] = p;
+// threshold (rebuilt when the threshold grows or the list thins out; the
+// round's control step decides).  Grid-stride, whole waves per step.
+__global__ void k4_build_active(K4Args a) {
+  if (!a.ctr->rebuild || a.ctr->skip) return;
+  const uint32_t thresh = a.ctr->thresh;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < a.npts; base += stride) {
+    uint32_t p = base + threadIdx.x;
+    bool take = p < a.npts && a.ploc[p] != DONE && prio_of(p) < thresh;
+    uint32_t slot = wave_alloc(take, &a.ctr->nact);
+    if (take) a.act[slot] = p;
+  }
+}
+
+// Round control (one thread).  Initial state: every located point is
+// pending, the first level's threshold is thresh0.
+__global__ void k4_ctl_init(K4Args a, uint32_t thresh0) {
+  Counters* c = a.ctr;
+  c->remaining = c->active;
+  c->done = 0;
+  c->ins_since = 0;
+  c->thresh = thresh0;
+  c->stall = 0;
+  c->rounds = 0;
+  c->skip = (c->active == 0 || c->flags) ? 1u : 0u;
+  c->ncand = c->inserted = c->overflow = c->extused = c->pending = 0;
+  c->rebuild = 1;
+  c->nact = 0;
+  c->built_thresh = thresh0;
+}
+
+// End of a round: account the insertions, move to the next level when
+// fewer points are pending than 1/grow_div of those inserted, detect a
+// stall, then prepare the next round (counters, active-list rebuild).
+__global__ void k4_ctl_end(K4Args a) {
+  Counters* c = a.ctr;
+  if (c->skip) return;
+  const uint32_t PMAX = 1u << 20;
+  const uint32_t ins = c->inserted;
+  c->rounds++;
+  c->remaining -= ins;
+  c->done += ins;
+  c->ins_since += ins;
+  const unsigned long long left = c->pending >= ins ? c->pending - ins : 0;
+  const unsigned long long lim = c->done / a.grow_div;
+  if (c->thresh < PMAX && left < (lim > 256 ? lim : 256)) {
+    c->thresh = c->thresh * 2 > PMAX ? PMAX : c->thresh * 2;
+  } else if (ins == 0) {
+    if (++c->stall > 8) c->flags |= FAIL_NO_PROGRESS;
+  }
+  if (ins) c->stall = 0;
+  if (c->remaining == 0 || c->flags) c->skip = 1;
+  c->ncand = c->inserted = c->overflow = c->extused = c->pending = 0;
+  if (c->thresh != c->built_thresh || c->ins_since * 2 > c->nact) {
+    c->rebuild = 1;
+    c->nact = 0;
+    c->built_thresh = c->thresh;
+    c->ins_since = 0;
+  } else {
+    c->rebuild = 0;
+  }
 }
 
 // ------------------------------------------------------------ rounds
@@ -470,15 +525,17 @@ __global__ void k4_build_active(K4Args a, uint32_t* list, uint32_t* count) {
 // cell.  Dormant points are not touched.
 template <int D, bool F32>
 __global__ void k4_pick(K4Args a) {
-  uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.ctr->skip) return;
+  const uint32_t nact = a.ctr->nact, thresh = a.ctr->thresh;
   PredT<F32> pr;
   pr.init(&a.ctr->flags);
-  bool pending = false;
-  uint32_t p = ia < a.nact ? a.act[ia] : 0xFFFFFFFFu;
-  if (ia < a.nact) {
+  uint32_t npend = 0;
+  for (uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x; ia < nact;
+       ia += gridDim.x * blockDim.x) {
+    const uint32_t p = a.act[ia];
     uint32_t L = a.ploc[p];
-    if (L != DONE && prio_of(p) < a.thresh) {
-      pending = true;
+    if (L != DONE && prio_of(p) < thresh) {
+      npend++;
       bool need = (L & NEEDWALK) != 0;
       L &= ~NEEDWALK;
       if (need || a.cfwd[L] != ALIVE) {
@@ -496,7 +553,7 @@ __global__ void k4_pick(K4Args a) {
       atomicMin(&a.ccand[L], make_key(a.round, p));
     }
   }
-  uint32_t c = wave_sum(pending ? 1u : 0u);
+  uint32_t c = wave_sum(npend);
   if (lane_id() == 0 && c) atomicAdd(&a.ctr->pending, c);
   flush_pred<D>(a.ctr, pr.st);
 }
@@ -507,13 +564,17 @@ __global__ void k4_pick(K4Args a) {
 // touches this point's cell, so it would always win against this one.
 template <int D>
 __global__ void k4_select(K4Args a) {
-  uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a.ctr->skip) return;
+  const uint32_t nact = a.ctr->nact, thresh = a.ctr->thresh;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nact; base += stride) {
+  const uint32_t ia = base + threadIdx.x;
   bool want = false;
   uint32_t p = 0;
-  if (ia < a.nact) {
+  if (ia < nact) {
     p = a.act[ia];
     uint32_t L = a.ploc[p];
-    if (L != DONE && (L & NEEDWALK) == 0 && prio_of(p) < a.thresh) {
+    if (L != DONE && (L & NEEDWALK) == 0 && prio_of(p) < thresh) {
       unsigned long long K = make_key(a.round, p);
       want = (a.ccand[L] == K);
       if (want) {
@@ -539,6 +600,7 @@ __global__ void k4_select(K4Args a) {
   }
   uint32_t slot = wave_alloc(want, &a.ctr->ncand);
   if (want && slot < a.maxcand) a.cand_pt[slot] = p;
+  }
 }
 
 // Cavity search, one wavefront (block of 64) per candidate: a
@@ -935,92 +997,70 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     fprintf(stderr, "[k4] init npts %u sets %u active %u cells %u flags %x\n", npts, job.nsets,
             hctr->active, hctr->cells, hctr->flags);
   if (hctr->flags) return DT_E_INTERNAL;
-  uint64_t remaining = hctr->active, done = 0;
   // activation levels: about start_active points per set at first, doubled
   // whenever fewer are pending than 1/grow_div of those already inserted
+  // (decided on the device, see k4_ctl_end)
   const uint32_t PMAX = 1u << 20;
   uint64_t t0 = ((uint64_t)PMAX * job.start_active * job.nsets) / (npts ? npts : 1);
-  uint32_t thresh = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
-  int stall = 0;
-  uint32_t round = 1;
-  ks.maxcav = 0;
-  uint32_t built_thresh = 0xFFFFFFFFu;   // threshold the active list was built for
-  uint64_t nact = 0, ins_since = 0;
+  uint32_t thresh0 = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
   a.act = actbuf.as<uint32_t>();
-  while (remaining > 0) {
-    if (thresh != built_thresh || ins_since * 2 > nact) {
-      a.thresh = thresh;
-      DT_HIP(hipMemsetAsync(&dctr->pad, 0, sizeof(uint32_t), st));
-      hipLaunchKernelGGL(k4_build_active, dim3(nblk(npts)), dim3(BLOCK), 0, st, a,
-                         actbuf.as<uint32_t>(), &dctr->pad);
+  a.grow_div = job.grow_div ? job.grow_div : 2;
+  hipLaunchKernelGGL(k4_ctl_init, dim3(1), dim3(1), 0, st, a, thresh0);
+  // Rounds run back to back in groups; the host reads the control state
+  // once per group.  Rounds past the end do nothing (the skip word).
+  const uint32_t gb = npts ? (nblk(npts) < 2048 ? nblk(npts) : 2048) : 1;
+  const uint32_t ga = npts ? (nblk(npts) < 8192 ? nblk(npts) : 8192) : 1;
+  uint64_t cbound = npts < maxcand ? (npts ? npts : 1) : maxcand;
+  const uint32_t gi = (uint32_t)(cbound < job.cand_blocks ? cbound : job.cand_blocks);
+  uint32_t round = 1, group = 4;
+  for (;;) {
+    for (uint32_t r = 0; r < group; r++, round++) {
+      if (round >= (1u << 30)) return DT_E_INTERNAL;
+      if ((round & 0xFFFu) == 0) {
+        // the 12-bit round stamp wraps: clear every claim word in use
+        DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+        DT_HIP(hipStreamSynchronize(st));
+        size_t used = hctr->cells < pool.cap ? hctr->cells : pool.cap;
+        DT_HIP(hipMemsetAsync(pool.ccand.p, 0xFF, used * 8, st));
+        DT_HIP(hipMemsetAsync(pool.ccav.p, 0xFF, used * 8, st));
+        DT_HIP(hipMemsetAsync(pool.cshell.p, 0xFF, used * 8, st));
+      }
+      a.round = round;
+      hipLaunchKernelGGL(k4_build_active, dim3(gb), dim3(BLOCK), 0, st, a);
+      DT_PROF_BEGIN(DT_KERN_K4_PICK, st);
+      if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_pick<2, true>), dim3(ga), dim3(BLOCK), 0, st, a);
+      else if (D == 2) hipLaunchKernelGGL((k4_pick<2, false>), dim3(ga), dim3(BLOCK), 0, st, a);
+      else if (a.fp32) hipLaunchKernelGGL((k4_pick<3, true>), dim3(ga), dim3(BLOCK), 0, st, a);
+      else hipLaunchKernelGGL((k4_pick<3, false>), dim3(ga), dim3(BLOCK), 0, st, a);
+      DT_PROF_END(st);
+      DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
+      if (D == 2) hipLaunchKernelGGL(k4_select<2>, dim3(ga), dim3(BLOCK), 0, st, a);
+      else hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+      if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gi), dim3(64), 0, st, a);
+      else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gi), dim3(64), 0, st, a);
+      else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gi), dim3(64), 0, st, a);
+      else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gi), dim3(64), 0, st, a);
+      DT_PROF_END(st);
+      DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
+      if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);
+      else hipLaunchKernelGGL(k4_insert<3>, dim3(gi), dim3(64), 0, st, a);
+      DT_PROF_END(st);
+      hipLaunchKernelGGL(k4_ctl_end, dim3(1), dim3(1), 0, st, a);
       DT_HIP(hipGetLastError());
-      uint32_t hn = 0;
-      DT_HIP(hipMemcpyAsync(&hn, &dctr->pad, 4, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipStreamSynchronize(st));
-      nact = hn;
-      built_thresh = thresh;
-      ins_since = 0;
     }
-    a.nact = (uint32_t)nact;
-    if (round >= (1u << 30)) return DT_E_INTERNAL;
-    if ((round & 0xFFFu) == 0) {
-      // the 12-bit round stamp wraps: clear every claim word
-      size_t used = hctr->cells;
-      DT_HIP(hipMemsetAsync(pool.ccand.p, 0xFF, used * 8, st));
-      DT_HIP(hipMemsetAsync(pool.ccav.p, 0xFF, used * 8, st));
-      DT_HIP(hipMemsetAsync(pool.cshell.p, 0xFF, used * 8, st));
-    }
-    a.round = round;
-    a.thresh = thresh;
-    // ncand, inserted, overflow, extused, pending
-    DT_HIP(hipMemsetAsync(&dctr->ncand, 0, 5 * sizeof(uint32_t), st));
-    uint32_t ga = nblk(nact ? (uint32_t)nact : 1u);
-    // one wavefront-sized block per candidate, grid-stride over the candidates
-    uint64_t cbound = nact < maxcand ? (nact ? nact : 1) : maxcand;
-    uint32_t gi = (uint32_t)(cbound < job.cand_blocks ? cbound : job.cand_blocks);
-    DT_PROF_BEGIN(DT_KERN_K4_PICK, st);
-    if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_pick<2, true>), dim3(ga), dim3(BLOCK), 0, st, a);
-    else if (D == 2) hipLaunchKernelGGL((k4_pick<2, false>), dim3(ga), dim3(BLOCK), 0, st, a);
-    else if (a.fp32) hipLaunchKernelGGL((k4_pick<3, true>), dim3(ga), dim3(BLOCK), 0, st, a);
-    else hipLaunchKernelGGL((k4_pick<3, false>), dim3(ga), dim3(BLOCK), 0, st, a);
-    DT_PROF_END(st);
-    DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
-    if (D == 2) hipLaunchKernelGGL(k4_select<2>, dim3(ga), dim3(BLOCK), 0, st, a);
-    else hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
-    if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gi), dim3(64), 0, st, a);
-    else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gi), dim3(64), 0, st, a);
-    else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gi), dim3(64), 0, st, a);
-    else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gi), dim3(64), 0, st, a);
-    DT_PROF_END(st);
-    DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
-    if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);
-    else hipLaunchKernelGGL(k4_insert<3>, dim3(gi), dim3(64), 0, st, a);
-    DT_PROF_END(st);
-    DT_HIP(hipGetLastError());
     DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
     if (dbg)
       fprintf(stderr,
-              "[k4] round %u thresh %u pending %u cand %u inserted %u overflow %u cells %u "
-              "maxcav %u flags %x\n",
-              round, thresh, hctr->pending, hctr->ncand, hctr->inserted, hctr->overflow,
-              hctr->cells, hctr->maxcav, hctr->flags);
-    if (hctr->flags) { ks.rounds = (int)round; return DT_E_INTERNAL; }
-    uint32_t ins = hctr->inserted;
-    remaining -= ins;
-    done += ins;
-    ins_since += ins;
-    uint64_t left = hctr->pending >= ins ? hctr->pending - ins : 0;
-    uint64_t lim = done / job.grow_div;
-    if (thresh < PMAX && left < (lim > 256 ? lim : 256)) {
-      thresh = thresh * 2 > PMAX ? PMAX : thresh * 2;
-    } else if (ins == 0) {
-      if (++stall > 8) { ks.rounds = (int)round; return DT_E_INTERNAL; }
-    }
-    if (ins) stall = 0;
-    round++;
+              "[k4] round %u (device %u) thresh %u nact %u remaining %llu cells %u maxcav %u "
+              "flags %x\n",
+              round - 1, hctr->rounds, hctr->thresh, hctr->nact, hctr->remaining, hctr->cells,
+              hctr->maxcav, hctr->flags);
+    if (hctr->flags) { ks.rounds = (int)hctr->rounds; return DT_E_INTERNAL; }
+    if (hctr->skip) break;
+    if (group < 32) group *= 2;
   }
-  ks.rounds = (int)(round - 1);
+  ks.rounds = (int)hctr->rounds;
   ks.maxcav = hctr->maxcav;
   ks.cavity_cells = hctr->cavcells;
   pool.ncells = hctr->cells;
