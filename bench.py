@@ -90,23 +90,74 @@ def cpu_baseline(points, sample_n: int) -> dict:
 
 
 def run(binding, pts, steps: int, warmup: int, k: int, rate: float, **opts):
+    """Warm-up steps, then `steps` timed steps; then one more step with
+    kernel timing on (HIP events around every timed launch, on the launch
+    stream), outside the timed region, for the per-kernel table."""
     import torch
     res = None
     for _ in range(warmup):
         res = binding.triangulate(pts, k=k, sample_rate=rate, **opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    kern = {}
     for _ in range(steps):
-        res = binding.triangulate(pts, k=k, sample_rate=rate, profile=1, **opts)
-        st = res.stats()
-        for name, v in st["kern"].items():
-            a = kern.setdefault(name, {"ms": 0.0, "launches": 0})
-            a["ms"] += v["ms"]
-            a["launches"] += v["launches"]
+        res = binding.triangulate(pts, k=k, sample_rate=rate, **opts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return res, (t1 - t0) * 1000.0 / steps, kern
+    prof = binding.triangulate(pts, k=k, sample_rate=rate, profile=1, **opts)
+    pst = prof.stats()
+    kern = {name: dict(v) for name, v in pst["kern"].items()}
+    return res, (t1 - t0) * 1000.0 / steps, kern, pst
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources the insertion kernels are built from (a traffic
+    measurement is valid only for the kernels it was taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dt_k4.hip", "dt_pred.hpp", "dt_common.hpp", "dt_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1902_07554_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the same
+    counters on a copy kernel of known size), or None when there is no
+    summary or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                a, b = line.split(":", 1)
+                kv[a.strip()] = b.strip()
+    try:
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["copy_fetch_factor"])
+        write = float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["copy_write_factor"])
+        return fetch + write
+    except (KeyError, ValueError):
+        return None
+
+
+def bench_copy(args) -> dict:
+    """Calibration for the HBM counters: a plain device copy of 1 GiB."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 3
+    return {"metric": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+            "GB/s": round(2 * nbytes / dt / 1e9, 1)}
 
 
 def bench_batch(args) -> dict:
@@ -231,7 +282,7 @@ def main() -> int:
     ap.add_argument("--no-kd", action="store_true", help="skip the kd-divide comparison")
     ap.add_argument("--cpu-sample", type=int, default=1_500_000,
                     help="points of the CPU-oracle baseline sample (0 = skip)")
-    ap.add_argument("--mode", default="dt", choices=["dt", "batch", "serve"],
+    ap.add_argument("--mode", default="dt", choices=["dt", "batch", "serve", "copy"],
                     help="dt: the headline triangulation; batch / serve: the patterns")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -246,6 +297,9 @@ def main() -> int:
     if args.mode == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
         return 0
+    if args.mode == "copy":
+        print(json.dumps(bench_copy(args)), flush=True)
+        return 0
 
     import torch
     from paper_1902_07554_amd import binding, inputs
@@ -255,25 +309,30 @@ def main() -> int:
     pts = torch.from_numpy(host).to("cuda")
     torch.cuda.synchronize()
 
-    res, ms, kern = run(binding, pts, args.steps, args.warmup, k, rate, precision=prec,
-                        divide="sample")
+    res, ms, kern, pst = run(binding, pts, args.steps, args.warmup, k, rate, precision=prec,
+                             divide="sample")
     st = res.stats()
     value = n / (ms / 1000.0) / 1e6
 
     # dominant kernel of the timed region: achieved algorithmic bytes / time
-    per_step = {name: {"ms": v["ms"] / args.steps, "launches": v["launches"] / args.steps}
+    per_step = {name: {"ms": v["ms"], "launches": v["launches"]}
                 for name, v in kern.items() if v["launches"]}
     dom = max(per_step, key=lambda x: per_step[x]["ms"])
-    dom_bytes = kernel_bytes(dom, st, dim)
-    dom_s = per_step[dom]["ms"] / 1000.0
-    achieved = dom_bytes / dom_s / 1e9 if dom_s > 0 else 0.0
+    launches = per_step[dom]["launches"]
+    dom_bytes = kernel_bytes(dom, pst, dim) / launches          # algorithmic bytes per launch
+    dom_avg_s = per_step[dom]["ms"] / 1000.0 / launches        # average launch duration
+    achieved = dom_bytes / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
+    traffic = measured_traffic(dom, args.workload)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": 8000.0,
-                "unit": "GB/s", "frac": round(achieved / 8000.0, 5), "traffic": None,
-                "launches_per_step": per_step[dom]["launches"],
-                "ms_per_step": round(per_step[dom]["ms"], 3)}
+                "unit": "GB/s", "frac": round(achieved / 8000.0, 5),
+                "traffic": round(traffic) if traffic is not None else None,
+                "algorithmic_bytes_per_launch": round(dom_bytes),
+                "avg_launch_us": round(dom_avg_s * 1e6, 2), "launches_per_step": launches,
+                "ms_per_step": round(per_step[dom]["ms"], 3),
+                "kernel_source": kernel_source_hash()}
     kernels = {}
     for name, v in per_step.items():
-        b = kernel_bytes(name, st, dim)
+        b = kernel_bytes(name, pst, dim)
         kernels[name] = {"ms": round(v["ms"], 3), "launches": v["launches"],
                          "GB/s": round(b / (v["ms"] / 1000.0) / 1e9, 2) if v["ms"] > 0 else None}
 
@@ -307,7 +366,7 @@ def main() -> int:
         "kernels": kernels,
     }
     if not args.no_kd:
-        kres, kms, _ = run(binding, pts, args.steps, args.warmup, k, rate, precision=prec,
+        kres, kms, _, _ = run(binding, pts, args.steps, args.warmup, k, rate, precision=prec,
                            divide="kd")
         kst = kres.stats()
         line["kd_divide"] = dict(value=round(n / (kms / 1000.0) / 1e6, 4), ms_per_step=round(kms, 3),

@@ -84,7 +84,7 @@ typedef struct dt_options {
 
 /* Kernels timed when dt_options.profile = 1. */
 enum { DT_KERN_K4_PICK = 0, DT_KERN_K4_CAVITY, DT_KERN_K4_INSERT, DT_KERN_ASSIGN,
-       DT_KERN_BUCKET, DT_KERN_BORDER, DT_KERN_MERGE, DT_NUM_KERN = 8 };
+       DT_KERN_BUCKET, DT_KERN_BORDER, DT_KERN_MERGE, DT_KERN_K4_SELECT, DT_NUM_KERN = 8 };
 
 /* -------------------------------------------------------------- statistics */
 enum {
@@ -209,13 +209,13 @@ int dt_batch_autotune(const double* points, const int64_t* offsets, int64_t num_
 
 /*
  * Serving (continuous batching; the paper's method applied to a stream of
- * independent requests).  A server owns a device-memory budget and two
+ * independent requests).  A server owns a device-memory budget and four
  * worker threads, each with its own stream.  Jobs are admitted in arrival
  * order while their estimated footprint fits the budget (a job alone may
  * use the whole budget).  A worker takes the admitted jobs that have not
  * started: consecutive direct jobs (k = 1) of one dimension run together
  * as one batched run (as dt_batch_triangulate, up to 8 Mi points), a
- * divide-and-conquer job (k > 1) runs alone; the two workers' runs overlap
+ * divide-and-conquer job (k > 1) runs alone; the workers' runs overlap
  * on the device.  Each job's result (rows labelled by row index, sorted
  * when opt.sort_output) is identical to dt_triangulate on its own; if a
  * batched run fails its jobs run again one by one, so each gets its own

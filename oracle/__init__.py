@@ -217,10 +217,37 @@ def nearest_sample(points: np.ndarray, sample_pts: np.ndarray,
     return out
 
 
-def bucket_order(pid: np.ndarray) -> np.ndarray:
-    """The partitions P_1..P_k as contiguous buckets: a stable sort by
-    partition id (within a partition, ascending original index)."""
-    return np.argsort(np.asarray(pid), kind="stable")
+def morton_codes(points: np.ndarray) -> np.ndarray:
+    """Position along the Z-order (Morton) curve over the bounding box of
+    the points: every coordinate is scaled to [0, 1] in the box, clamped,
+    quantised to 10 bits in 3D (15 in 2D) by truncation, and the bits are
+    interleaved with x lowest (bit b of axis a goes to bit D*b + a)."""
+    p = np.asarray(points, dtype=np.float64)
+    n, d = p.shape
+    bits = 10 if d == 3 else 15
+    cells = float((1 << bits) - 1)
+    lo, hi = p.min(axis=0), p.max(axis=0)
+    w = hi - lo
+    inv = np.where(w > 0, 1.0 / np.where(w > 0, w, 1.0), 0.0)
+    codes = np.zeros(n, dtype=np.uint64)
+    for a in range(d):
+        t = np.minimum(np.maximum((p[:, a] - lo[a]) * inv[a], 0.0), 1.0) * cells
+        q = t.astype(np.uint64)
+        for b in range(bits):
+            codes |= ((q >> np.uint64(b)) & np.uint64(1)) << np.uint64(d * b + a)
+    return codes
+
+
+def bucket_order(pid: np.ndarray, points: np.ndarray | None = None) -> np.ndarray:
+    """The partitions P_1..P_k as contiguous buckets in partition order.
+    Inside a bucket the method allows any order; the library orders it
+    along the Morton curve of the whole input's bounding box (ties by
+    original index).  Without points: ascending original index."""
+    pid = np.asarray(pid, dtype=np.int64)
+    if points is None:
+        return np.argsort(pid, kind="stable")
+    code = morton_codes(points)
+    return np.lexsort((np.arange(len(pid)), code, pid))
 
 
 def kd_divide(points: np.ndarray, k: int) -> np.ndarray:

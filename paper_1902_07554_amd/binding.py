@@ -25,7 +25,8 @@ PRECISION = {"fp64": 0, "fp32": 1}
 BORDER = {"region": 0, "grid": 1}
 STAGES = ["validate", "sample", "sample_dt", "partition", "assign", "scatter", "local_dt",
           "border", "border_dt", "merge", "output", "total"]
-KERNELS = ["k4_pick", "k4_cavity", "k4_insert", "assign", "bucket", "border", "merge"]
+KERNELS = ["k4_pick", "k4_cavity", "k4_insert", "assign", "bucket", "border", "merge",
+           "k4_select"]
 ARR = {"sample": 0, "sample_dt": 1, "part": 2, "pid": 3, "order": 4, "border_v": 5,
        "local": 6, "border_dt": 7}
 EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_count",

@@ -54,6 +54,7 @@ struct Counters {
   unsigned int skip;              // 1: finished or failed; later rounds do nothing
   unsigned int rounds;            // rounds that did work
   unsigned int pad2;
+  unsigned long long cand_total;  // candidates over all rounds
 };
 
 }  // namespace dtk

@@ -31,14 +31,6 @@ static uint32_t sample_size(uint32_t n, double rate, int D) {
   return (uint32_t)e;
 }
 
-__global__ void k_iota_keys(const uint32_t* pid, uint32_t n, unsigned long long* keys,
-                            uint32_t* vals) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  keys[i] = pid[i];
-  vals[i] = i;
-}
-
 __global__ void k_fill_u32(uint32_t* x, uint32_t n, uint32_t v) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -190,13 +182,17 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   DevBuf keys, order, Pp, cnt, off, pset;
   DT_TRY(keys.alloc((size_t)n * 8));
   DT_TRY(order.alloc((size_t)n * 4));
-  hipLaunchKernelGGL(k_iota_keys, dim3(cblocks(n)), dim3(CB), 0, st, pid.as<uint32_t>(), n,
-                     keys.as<unsigned long long>(), order.as<uint32_t>());
+  // key: partition, then position along a space-filling curve (the order
+  // inside a bucket does not change any triangulation; a spatial order
+  // makes the gathers of neighbouring points and cells share cache lines)
+  DT_TRY(spatial_keys(P.as<double4>(), n, D, lo, hi, pid.as<uint32_t>(),
+                      keys.as<unsigned long long>(), order.as<uint32_t>(), st));
   int kbits = 1;
   while ((1u << kbits) < (uint32_t)k) kbits++;
   DT_TRY(Pp.alloc((size_t)n * sizeof(double4)));
   DT_PROF_BEGIN(DT_KERN_BUCKET, st);
-  DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), order.as<uint32_t>(), n, kbits, st));
+  DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), order.as<uint32_t>(), n,
+                          kbits + MORTON_BITS, st));
   DT_TRY(gather_points(P.as<double4>(), order.as<uint32_t>(), n, Pp.as<double4>(), st));
   DT_PROF_END(st);
   keys.release();
@@ -280,6 +276,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   if (bo.nvb > 0) {
     DT_TRY(Pb.alloc((size_t)bo.nvb * sizeof(double4)));
     DT_TRY(gather_points(P.as<double4>(), bo.vb.as<uint32_t>(), bo.nvb, Pb.as<double4>(), st));
+    DT_TRY(spatial_sort(Pb, bo.nvb, D, lo, hi, nullptr, 0, st));
     DT_TRY(bset.alloc((size_t)bo.nvb * 4));
     DT_TRY(boff.alloc(8));
     DT_HIP(hipMemsetAsync(bset.p, 0, (size_t)bo.nvb * 4, st));

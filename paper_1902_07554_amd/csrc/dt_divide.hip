@@ -144,6 +144,22 @@ int gather_points(const double4* P, const uint32_t* idx, uint32_t m, double4* ou
   return DT_OK;
 }
 
+int spatial_sort(DevBuf& pts, uint32_t n, int D, const double lo[3], const double hi[3],
+                 const uint32_t* prefix, int prefix_bits, hipStream_t st) {
+  if (n < 2) return DT_OK;
+  DevBuf keys, order, sorted;
+  DT_TRY(keys.alloc((size_t)n * 8));
+  DT_TRY(order.alloc((size_t)n * 4));
+  DT_TRY(sorted.alloc((size_t)n * sizeof(double4)));
+  DT_TRY(spatial_keys(pts.as<double4>(), n, D, lo, hi, prefix, keys.as<unsigned long long>(),
+                      order.as<uint32_t>(), st));
+  DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), order.as<uint32_t>(), n,
+                          (prefix ? prefix_bits : 0) + MORTON_BITS, st));
+  DT_TRY(gather_points(pts.as<double4>(), order.as<uint32_t>(), n, sorted.as<double4>(), st));
+  pts = std::move(sorted);
+  return DT_OK;
+}
+
 // ------------------------------------------------------------ 3. graph
 // Unique Delaunay edges of the sample triangulation through an
 // open-addressing set keyed by (u << 32 | v), u < v (sample-local ids).

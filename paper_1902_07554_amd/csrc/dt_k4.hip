@@ -495,6 +495,7 @@ __global__ void k4_ctl_end(K4Args a) {
   const uint32_t PMAX = 1u << 20;
   const uint32_t ins = c->inserted;
   c->rounds++;
+  c->cand_total += c->ncand;
   c->remaining -= ins;
   c->done += ins;
   c->ins_since += ins;
@@ -599,78 +600,124 @@ __global__ void k4_select(K4Args a) {
     }
   }
   uint32_t slot = wave_alloc(want, &a.ctr->ncand);
-  if (want && slot < a.maxcand) a.cand_pt[slot] = p;
+  if (want && slot < a.maxcand) {
+    a.cand_pt[slot] = p;
+    // Claim the candidate's own cell now: it lies in the candidate's
+    // cavity whatever else does, so any larger candidate whose search
+    // reaches it loses (it would fail verification anyway) and can stop
+    // at once instead of finishing its search.
+    atomicMin(&a.ccav[a.ploc[p]], make_key(a.round, p));
+  }
   }
 }
 
-// Cavity search, one wavefront (block of 64) per candidate: a
-// level-synchronous breadth-first search over the conflict region, the
-// lanes testing the neighbours of the current frontier in parallel.  Each
-// cell found in conflict is claimed with the candidate's key (atomic
-// minimum; the previous value also detects a cell found twice); each
-// neighbour found not in conflict gets a shell claim.  A smaller claim
-// anywhere means this candidate cannot win: the search stops.
+// Cavity search: four candidates per wavefront, sixteen lanes each, in
+// lockstep levels.  Each candidate runs a level-synchronous breadth-first
+// search over its conflict region, the lanes of its group testing the
+// neighbours of the current frontier in parallel; the four groups' memory
+// accesses overlap, which is what bounds this search (a few dependent
+// gathers per level).  Each cell found in conflict is claimed with the
+// candidate's key (atomic minimum; the previous value also detects a cell
+// found twice); each neighbour found not in conflict gets a shell claim.
+// A smaller claim anywhere means this candidate cannot win: its search
+// stops.  All control state is per group in LDS; the barriers are outside
+// every group-dependent branch.
+constexpr uint32_t CAV_GROUPS = 4;
+constexpr uint32_t CAV_LANES = 64 / CAV_GROUPS;
+
 template <int D, bool F32>
 __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
-  __shared__ uint32_t s_n, s_flo, s_fhi, s_abort, s_gave, s_ext;
+  constexpr uint32_t G = CAV_GROUPS, GL = CAV_LANES;
+  constexpr uint32_t IDLE = 0, BUSY = 1, EXHAUSTED = 2;
+  __shared__ uint32_t s_n[G], s_flo[G], s_fhi[G], s_abort[G], s_gave[G], s_ext[G], s_slot[G],
+      s_state[G];
   PredT<F32> pr;
   pr.init(&a.ctr->flags);
-  const uint32_t lane = threadIdx.x;
+  const uint32_t lane = threadIdx.x, g = lane / GL, gl = lane % GL;
   const uint32_t ncand = min(a.ctr->ncand, a.maxcand);
+  const uint32_t stride = gridDim.x * G;
   uint32_t mx = 0, gave = 0;
   unsigned long long cells = 0;
-  for (uint32_t slot = blockIdx.x; slot < ncand; slot += gridDim.x) {
-    const uint32_t p = a.cand_pt[slot];
-    const unsigned long long K = make_key(a.round, p);
-    const uint32_t L = a.ploc[p];
-    double qp[3];
-    unsigned long long qk;
-    load_pt(a.pts, p, qp, qk);
-    uint32_t* la = a.cav + (size_t)slot * a.cavcap;
-    if (lane == 0) {
-      a.cand_ext[slot] = DONE;
-      s_ext = DONE;
-      bool ok = atomicMin(&a.ccav[L], K) > K;
-      if (ok) la[0] = L;
-      s_abort = ok ? 0u : 1u;
-      s_gave = 0;
-      s_n = ok ? 1u : 0u;
-      s_flo = 0;
-      s_fhi = s_n;
+  if (gl == 0) {
+    s_slot[g] = blockIdx.x * G + g;
+    s_state[g] = IDLE;
+  }
+  // candidate of this lane's group, as loaded by this lane
+  uint32_t cur = 0xFFFFFFFFu, p = 0;
+  unsigned long long K = 0, qk = 0;
+  double qp[3] = {0.0, 0.0, 0.0};
+  __syncthreads();
+  for (;;) {
+    // leaders start a candidate in every idle group
+    if (gl == 0 && s_state[g] == IDLE) {
+      const uint32_t slot = s_slot[g];
+      if (slot >= ncand) {
+        s_state[g] = EXHAUSTED;
+      } else {
+        const uint32_t q = a.cand_pt[slot];
+        const unsigned long long Kq = make_key(a.round, q);
+        const uint32_t L = a.ploc[q];
+        a.cand_ext[slot] = DONE;
+        // the own cell was claimed at selection; a smaller claim means a
+        // smaller candidate's cavity holds it already
+        const bool ok = atomicMin(&a.ccav[L], Kq) >= Kq;
+        if (ok) a.cav[(size_t)slot * a.cavcap] = L;
+        s_ext[g] = DONE;
+        s_abort[g] = ok ? 0u : 1u;
+        s_gave[g] = 0;
+        s_n[g] = ok ? 1u : 0u;
+        s_flo[g] = 0;
+        s_fhi[g] = ok ? 1u : 0u;
+        s_state[g] = BUSY;
+      }
     }
     __syncthreads();
-    for (;;) {
-      const uint32_t flo = s_flo, fhi = s_fhi;
-      if (s_abort || flo >= fhi) break;
-      const uint32_t items = (fhi - flo) * (D + 1);
-      if (lane == 0 && s_n + items > a.cavcap) {
-        // this level may append up to `items` cells: make room first
-        if (s_n + items > a.cavcap + EXTCAP) {
-          s_abort = 1;
-          s_gave = 1;
-        } else if (s_ext == DONE) {
-          uint32_t e = atomicAdd(&a.ctr->extused, 1u);
+    bool any = false;
+#pragma unroll
+    for (uint32_t h = 0; h < G; h++) any |= (s_state[h] == BUSY);
+    if (!any) break;
+    const bool busy = s_state[g] == BUSY;
+    const uint32_t slot = s_slot[g];
+    if (busy && slot != cur) {
+      cur = slot;
+      p = a.cand_pt[slot];
+      K = make_key(a.round, p);
+      load_pt(a.pts, p, qp, qk);
+    }
+    // leaders make room for the level's appends
+    if (gl == 0 && busy && !s_abort[g] && s_flo[g] < s_fhi[g]) {
+      const uint32_t items = (s_fhi[g] - s_flo[g]) * (D + 1);
+      if (s_n[g] + items > a.cavcap) {
+        if (s_n[g] + items > a.cavcap + EXTCAP) {
+          s_abort[g] = 1;
+          s_gave[g] = 1;
+        } else if (s_ext[g] == DONE) {
+          const uint32_t e = atomicAdd(&a.ctr->extused, 1u);
           if (e >= MAXEXT) {
-            s_abort = 1;
-            s_gave = 1;
+            s_abort[g] = 1;
+            s_gave[g] = 1;
           } else {
-            s_ext = e;
+            s_ext[g] = e;
             a.cand_ext[slot] = e;
           }
         }
       }
-      __syncthreads();
-      if (s_abort) break;
-      uint32_t* lb = (s_ext == DONE) ? nullptr : a.extcell + (size_t)s_ext * EXTCAP;
-      for (uint32_t it = lane; it < items; it += 64) {
-        if (s_abort) break;
+    }
+    __syncthreads();
+    const uint32_t flo = s_flo[g], fhi = s_fhi[g];
+    if (busy && !s_abort[g] && flo < fhi) {
+      uint32_t* la = a.cav + (size_t)slot * a.cavcap;
+      uint32_t* lb = (s_ext[g] == DONE) ? nullptr : a.extcell + (size_t)s_ext[g] * EXTCAP;
+      const uint32_t items = (fhi - flo) * (D + 1);
+      for (uint32_t it = gl; it < items; it += GL) {
+        if (s_abort[g]) break;
         const uint32_t h = flo + it / (D + 1);
         const int i = (int)(it % (D + 1));
         const uint32_t c = h < a.cavcap ? la[h] : lb[h - a.cavcap];
         const uint32_t t = vat(a.cn[c], i) >> 2;
         if (t >= a.cap) {
           atomicOr(&a.ctr->flags, FAIL_INVARIANT);
-          s_abort = 1;
+          s_abort[g] = 1;
           break;
         }
         const uint4 tv = a.cv[t];
@@ -680,41 +727,42 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
           if (vat(tv, r) != INF_V && vat(tv, r) >= a.npts) badv = true;
         if (badv) {
           atomicOr(&a.ctr->flags, FAIL_INVARIANT);
-          s_abort = 1;
+          s_abort[g] = 1;
           break;
         }
         const unsigned long long cc = __atomic_load_n(&a.ccav[t], __ATOMIC_RELAXED);
         if (cc == K) continue;
-        if (cc < K) { s_abort = 1; break; }
+        if (cc < K) { s_abort[g] = 1; break; }
         if (__atomic_load_n(&a.cshell[t], __ATOMIC_RELAXED) == K) continue;
         if (conflict<D, F32>(a, pr, tv, p, qp, qk)) {
           const unsigned long long old = atomicMin(&a.ccav[t], K);
-          if (old < K) { s_abort = 1; break; }
+          if (old < K) { s_abort[g] = 1; break; }
           if (old == K) continue;
-          const uint32_t pos = atomicAdd(&s_n, 1u);
+          const uint32_t pos = atomicAdd(&s_n[g], 1u);
           if (pos < a.cavcap) la[pos] = t;
           else lb[pos - a.cavcap] = t;
         } else {
           atomicMin(&a.cshell[t], K);
         }
       }
-      __syncthreads();
-      if (lane == 0) {
-        s_flo = fhi;
-        s_fhi = s_n;
-      }
-      __syncthreads();
     }
-    if (lane == 0) {
-      const uint32_t nn = s_abort ? 0u : s_n;
-      a.cand_n[slot] = nn;
-      mx = max(mx, s_n);
-      cells += s_n;
-      gave += s_gave;
+    __syncthreads();
+    // leaders advance to the next level, or finish the candidate
+    if (gl == 0 && busy) {
+      s_flo[g] = fhi;
+      s_fhi[g] = s_n[g];
+      if (s_abort[g] || s_flo[g] >= s_fhi[g]) {
+        a.cand_n[slot] = s_abort[g] ? 0u : s_n[g];
+        mx = max(mx, s_n[g]);
+        cells += s_n[g];
+        gave += s_gave[g];
+        s_slot[g] = slot + stride;
+        s_state[g] = IDLE;
+      }
     }
     __syncthreads();
   }
-  if (lane == 0) {
+  if (gl == 0) {
     if (gave) atomicAdd(&a.ctr->overflow, gave);
     if (mx) atomicMax(&a.ctr->maxcav, mx);
     if (cells) atomicAdd(&a.ctr->cavcells, cells);
@@ -1033,9 +1081,11 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
       else if (a.fp32) hipLaunchKernelGGL((k4_pick<3, true>), dim3(ga), dim3(BLOCK), 0, st, a);
       else hipLaunchKernelGGL((k4_pick<3, false>), dim3(ga), dim3(BLOCK), 0, st, a);
       DT_PROF_END(st);
-      DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
+      DT_PROF_BEGIN(DT_KERN_K4_SELECT, st);
       if (D == 2) hipLaunchKernelGGL(k4_select<2>, dim3(ga), dim3(BLOCK), 0, st, a);
       else hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
+      DT_PROF_END(st);
+      DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
       if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gi), dim3(64), 0, st, a);
       else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gi), dim3(64), 0, st, a);
       else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gi), dim3(64), 0, st, a);
@@ -1061,6 +1111,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     if (group < 32) group *= 2;
   }
   ks.rounds = (int)hctr->rounds;
+  if (dbg)
+    fprintf(stderr, "[k4] done npts %u sets %u rounds %u candidates %llu cavity cells %llu\n", npts,
+            job.nsets, hctr->rounds, hctr->cand_total, hctr->cavcells);
   ks.maxcav = hctr->maxcav;
   ks.cavity_cells = hctr->cavcells;
   pool.ncells = hctr->cells;

@@ -8,7 +8,9 @@
 #include "dt_common.hpp"
 #include "dt_internal.hpp"
 #include "dt_pipeline.hpp"
+#include "dt_prims.hpp"
 #include "dt_prep.hpp"
+#include "dt_stages.hpp"
 
 namespace dtk {
 
@@ -102,6 +104,16 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   DT_TRY(pts.alloc((size_t)n * sizeof(double4)));
   DT_TRY(prep_points(dp, ids ? dkeys.as<long long>() : nullptr, ns > 1 ? pset.as<uint32_t>() : nullptr,
                      n, D, pts.as<double4>(), scratch, cx.dflag.as<uint32_t>(), cx.hflag, st));
+  {
+    // order every set along a space-filling curve (the set is the major
+    // key, so sets keep their ranges); labels travel with the points, so no
+    // triangulation changes, but neighbouring points share cache lines
+    double lo[3], hi[3];
+    DT_TRY(bbox(pts.as<double4>(), n, lo, hi, st));
+    int sbits = 0;
+    while ((1u << sbits) < ns) sbits++;
+    DT_TRY(spatial_sort(pts, n, D, lo, hi, ns > 1 ? pset.as<uint32_t>() : nullptr, sbits, st));
+  }
   double t1 = now_ms();
   LocalJob job;
   job.D = D;

@@ -261,4 +261,47 @@ int bbox(const double4* p, uint32_t n, double lo[3], double hi[3], hipStream_t s
   return DT_OK;
 }
 
+// Bits of v (at most 10 or 15 used) spread to every third / second bit.
+__device__ __forceinline__ unsigned long long spread_bits(uint32_t v, int D) {
+  unsigned long long r = 0;
+  if (D == 3) {
+    for (int b = 0; b < 10; b++) r |= (unsigned long long)((v >> b) & 1u) << (3 * b);
+  } else {
+    for (int b = 0; b < 15; b++) r |= (unsigned long long)((v >> b) & 1u) << (2 * b);
+  }
+  return r;
+}
+
+__global__ void k_spatial_keys(const double4* __restrict__ p, uint32_t n, int D, double3 lo,
+                               double3 inv, const uint32_t* __restrict__ prefix,
+                               unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 q = p[i];
+  const double cells = (D == 3) ? 1023.0 : 32767.0;
+  uint32_t x = (uint32_t)(fmin(fmax((q.x - lo.x) * inv.x, 0.0), 1.0) * cells);
+  uint32_t y = (uint32_t)(fmin(fmax((q.y - lo.y) * inv.y, 0.0), 1.0) * cells);
+  uint32_t z = (uint32_t)(fmin(fmax((q.z - lo.z) * inv.z, 0.0), 1.0) * cells);
+  unsigned long long m = spread_bits(x, D) | (spread_bits(y, D) << 1);
+  if (D == 3) m |= spread_bits(z, D) << 2;
+  keys[i] = (prefix ? ((unsigned long long)prefix[i] << MORTON_BITS) : 0ull) | m;
+  vals[i] = i;
+}
+
+int spatial_keys(const double4* p, uint32_t n, int D, const double lo[3], const double hi[3],
+                 const uint32_t* prefix, unsigned long long* keys, uint32_t* vals,
+                 hipStream_t st) {
+  if (n == 0) return DT_OK;
+  double inv[3];
+  for (int k = 0; k < 3; k++) {
+    double w = hi[k] - lo[k];
+    inv[k] = w > 0 ? 1.0 / w : 0.0;
+  }
+  hipLaunchKernelGGL(k_spatial_keys, dim3((n + 255) / 256), dim3(256), 0, st, p, n, D,
+                     make_double3(lo[0], lo[1], lo[2]), make_double3(inv[0], inv[1], inv[2]),
+                     prefix, keys, vals);
+  DT_HIP(hipGetLastError());
+  return DT_OK;
+}
+
 }  // namespace dtk

@@ -2,13 +2,13 @@
 // budget.
 //
 // A job is admitted (FIFO) when its estimated footprint fits the remaining
-// budget.  Two worker threads, each with its own HIP stream, repeatedly take
+// budget.  Four worker threads, each with its own HIP stream, repeatedly take
 // the admitted jobs that have not started: a run of consecutive direct jobs
 // (k = 1) is triangulated together as one batched run (all of them share
 // every kernel launch); a divide-and-conquer job (k > 1) runs on its own.
 // Jobs that arrive while a batch runs are admitted as memory frees up and
 // start with the next batch, which may run concurrently with the other
-// worker's batch.  A job's result is DT of its own points labelled by row
+// workers' batches.  A job's result is DT of its own points labelled by row
 // index, with the row index as tie-break order: what dt_triangulate returns
 // for it alone, since the triangulation depends only on the point set.  If a
 // batched run fails, its jobs run again one by one so that each gets its own
@@ -68,6 +68,8 @@ size_t footprint_of(int64_t n, int D, int k) {
 }
 
 constexpr int64_t MAX_BATCH_POINTS = 8 << 20;
+// One worker per hardware queue the runtime gives a process by default.
+constexpr int NUM_WORKERS = 4;
 
 }  // namespace
 
@@ -230,7 +232,7 @@ extern "C" int dt_server_create(size_t hbm_budget_bytes, const dt_options* opt, 
     uint64_t keep = UINT64_MAX;
     (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
   }
-  for (int i = 0; i < 2; i++) s->workers.emplace_back([s] { s->worker(); });
+  for (int i = 0; i < NUM_WORKERS; i++) s->workers.emplace_back([s] { s->worker(); });
   *srv = s;
   return DT_OK;
 }

@@ -10,6 +10,11 @@ namespace dtk {
 int select_sample(uint32_t n, uint32_t eta, uint64_t seed, DevBuf& sid, hipStream_t st);
 int gather_points(const double4* P, const uint32_t* idx, uint32_t m, double4* out,
                   hipStream_t st);
+// Reorder pts[0..n) along a space-filling curve over [lo, hi], grouped by
+// prefix (prefix[i] < 2^prefix_bits; null = one group, groups contiguous
+// and in order, so each keeps its range).  Labels travel with the points.
+int spatial_sort(DevBuf& pts, uint32_t n, int D, const double lo[3], const double hi[3],
+                 const uint32_t* prefix, int prefix_bits, hipStream_t st);
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
                      const dt_options& o, const double lo[3], const double hi[3],
                      DevBuf& part, double* cut, hipStream_t st);

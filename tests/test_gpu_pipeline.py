@@ -32,7 +32,7 @@ def _stage_checks(dtlib, p, k, rate, seed, divide, border="region"):
         assert np.array_equal(pid, part[near])
     else:
         assert np.array_equal(pid, oracle.kd_divide(p, k))
-    assert np.array_equal(res.stage("order"), oracle.bucket_order(pid))
+    assert np.array_equal(res.stage("order"), oracle.bucket_order(pid, p))
     loc = res.stage("local")
     rows, flag = oracle.canonical(loc[:, :-1]), None
     # per-partition triangulations and border soundness
