@@ -115,6 +115,7 @@ typedef struct dt_stats {
   double kern_ms[DT_NUM_KERN];        /* summed HIP-event time per kernel (profile)  */
   int64_t kern_launches[DT_NUM_KERN]; /* launches per kernel (profile)               */
   int64_t cavity_cells;       /* cells visited by winning and losing cavity searches */
+  int64_t candidates;         /* cavity searches (winning and losing) over all rounds   */
 } dt_stats;
 
 typedef struct dt_result dt_result;

@@ -57,7 +57,8 @@ class Stats(ctypes.Structure):
                 ("pred", (ctypes.c_int64 * 4) * 4), ("fail", ctypes.c_uint32),
                 ("pad", ctypes.c_uint32), ("stage_ms", ctypes.c_double * 12),
                 ("probe_hist", ctypes.c_int64 * 16), ("kern_ms", ctypes.c_double * 8),
-                ("kern_launches", ctypes.c_int64 * 8), ("cavity_cells", ctypes.c_int64)]
+                ("kern_launches", ctypes.c_int64 * 8), ("cavity_cells", ctypes.c_int64),
+                ("candidates", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_
@@ -69,7 +70,7 @@ class Stats(ctypes.Structure):
         d["stage_ms"] = {STAGES[i]: self.stage_ms[i] for i in range(12)}
         d["probe_hist"] = list(self.probe_hist)
         d["kern"] = {KERNELS[i]: {"ms": self.kern_ms[i], "launches": self.kern_launches[i]}
-                     for i in range(7)}
+                     for i in range(len(KERNELS))}
         return d
 
 

@@ -97,6 +97,7 @@ static void add_pred(dt_stats& s, const K4Stats& ks) {
     for (int j = 0; j < 4; j++) s.pred[i][j] += (int64_t)ks.pred[i][j];
   s.rounds += ks.rounds;
   s.cavity_cells += (int64_t)ks.cavity_cells;
+  s.candidates += (int64_t)ks.candidates;
 }
 
 int run_dc(const double* points, int64_t n64, int D, int k, double rate, const dt_options& o,

@@ -39,11 +39,16 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <vector>
+
 namespace dtk {
 
 constexpr int BLOCK = 256;
 // ploc flag: the stored cell is only a start for the walk (dormant point)
 constexpr uint32_t NEEDWALK = 0x80000000u;
+// ploc flag: the point's bid is in place on its (live) cell
+constexpr uint32_t BIDDED = 0x40000000u;
+constexpr uint32_t LOCMASK = 0x3FFFFFFFu;   // cell indices stay below 2^30
 
 struct K4Args {
   const double4* pts;
@@ -66,6 +71,11 @@ struct K4Args {
   uint32_t* extcell;    // [MAXEXT * EXTCAP]
   uint32_t* extinfo;
   Counters* ctr;
+  // striped statistics (many blocks add to them at once; 64 copies keep the
+  // atomics from serialising on one address): predicate counts
+  // [NSTRIPE][4][4] and pending points [NSTRIPE]
+  unsigned long long* pstripe;
+  uint32_t* pend;
   uint32_t npts;
   uint32_t nsets;
   uint32_t cap;
@@ -81,6 +91,7 @@ struct K4Args {
 // Large cavities spill from the fixed per-candidate list into extension
 // chunks taken from a small pool (reset every round).
 constexpr uint32_t MAXEXT = 256;
+constexpr uint32_t NSTRIPE = 64;
 constexpr uint32_t EXTCAP = 8192;
 
 struct CavList {
@@ -129,12 +140,20 @@ __device__ __forceinline__ uint32_t prio_of(uint32_t p) {
   return hash32(p * 0x9E3779B9u + 0x632BE5ABu) >> 12;
 }
 
-// Candidate key: newer rounds compare smaller (12-bit round stamp, so stale
-// claims never win; the claim words are reset every 4095 rounds), then the
-// priority, then the point index (unique).
+// Candidate key of the cavity and shell claims: newer rounds compare
+// smaller (12-bit round stamp, so stale claims never win; those claim words
+// are reset every 4096 rounds), then the priority, then the point index
+// (unique).
 __device__ __forceinline__ unsigned long long make_key(uint32_t round, uint32_t p) {
   return ((unsigned long long)((~round) & 0xFFFu) << 52) |
          ((unsigned long long)prio_of(p) << 32) | (unsigned long long)p;
+}
+
+// Bid of a point for the cell it lies in (no round stamp: a bid on a live
+// cell stays valid, since the cell dies as soon as its bidder is inserted
+// or moves on); ordered like the candidate keys of one round.
+__device__ __forceinline__ unsigned long long bid_key(uint32_t p) {
+  return ((unsigned long long)prio_of(p) << 32) | (unsigned long long)p;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -173,23 +192,24 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 
 // Predicate counters, flushed once per wave at kernel end.
 template <int D>
-__device__ __forceinline__ void flush_pred(Counters* ctr, const PredStats& s) {
+__device__ __forceinline__ void flush_pred(unsigned long long* pstripe, const PredStats& s) {
   const int io = (D == 2) ? 0 : 1, ii = (D == 2) ? 2 : 3;
   uint32_t v[6] = {s.calls[0], s.f32ok[0], s.exact[0], s.calls[1], s.f32ok[1], s.exact[1]};
 #pragma unroll
   for (int j = 0; j < 6; j++) v[j] = wave_sum(v[j]);
   if (lane_id() == 0) {
+    unsigned long long* st = pstripe + (size_t)(blockIdx.x % NSTRIPE) * 16;
     if (v[0]) {
-      atomicAdd(&ctr->pred[io][0], (unsigned long long)v[0]);
-      atomicAdd(&ctr->pred[io][1], (unsigned long long)v[1]);
-      atomicAdd(&ctr->pred[io][2], (unsigned long long)(v[0] - v[1] - v[2]));
-      atomicAdd(&ctr->pred[io][3], (unsigned long long)v[2]);
+      atomicAdd(&st[io * 4 + 0], (unsigned long long)v[0]);
+      atomicAdd(&st[io * 4 + 1], (unsigned long long)v[1]);
+      atomicAdd(&st[io * 4 + 2], (unsigned long long)(v[0] - v[1] - v[2]));
+      atomicAdd(&st[io * 4 + 3], (unsigned long long)v[2]);
     }
     if (v[3]) {
-      atomicAdd(&ctr->pred[ii][0], (unsigned long long)v[3]);
-      atomicAdd(&ctr->pred[ii][1], (unsigned long long)v[4]);
-      atomicAdd(&ctr->pred[ii][2], (unsigned long long)(v[3] - v[4] - v[5]));
-      atomicAdd(&ctr->pred[ii][3], (unsigned long long)v[5]);
+      atomicAdd(&st[ii * 4 + 0], (unsigned long long)v[3]);
+      atomicAdd(&st[ii * 4 + 1], (unsigned long long)v[4]);
+      atomicAdd(&st[ii * 4 + 2], (unsigned long long)(v[3] - v[4] - v[5]));
+      atomicAdd(&st[ii * 4 + 3], (unsigned long long)v[5]);
     }
   }
 }
@@ -481,6 +501,7 @@ __global__ void k4_ctl_init(K4Args a, uint32_t thresh0) {
   c->rounds = 0;
   c->skip = (c->active == 0 || c->flags) ? 1u : 0u;
   c->ncand = c->inserted = c->overflow = c->extused = c->pending = 0;
+  for (uint32_t i = 0; i < NSTRIPE; i++) a.pend[i] = 0;
   c->rebuild = 1;
   c->nact = 0;
   c->built_thresh = thresh0;
@@ -494,6 +515,12 @@ __global__ void k4_ctl_end(K4Args a) {
   if (c->skip) return;
   const uint32_t PMAX = 1u << 20;
   const uint32_t ins = c->inserted;
+  uint32_t pending = 0;
+  for (uint32_t i = 0; i < NSTRIPE; i++) {
+    pending += a.pend[i];
+    a.pend[i] = 0;
+  }
+  c->pending = pending;
   c->rounds++;
   c->cand_total += c->ncand;
   c->remaining -= ins;
@@ -534,11 +561,12 @@ __global__ void k4_pick(K4Args a) {
   for (uint32_t ia = blockIdx.x * blockDim.x + threadIdx.x; ia < nact;
        ia += gridDim.x * blockDim.x) {
     const uint32_t p = a.act[ia];
-    uint32_t L = a.ploc[p];
-    if (L != DONE && prio_of(p) < thresh) {
+    const uint32_t raw = a.ploc[p];
+    if (raw != DONE && prio_of(p) < thresh) {
       npend++;
-      bool need = (L & NEEDWALK) != 0;
-      L &= ~NEEDWALK;
+      const bool need = (raw & NEEDWALK) != 0;
+      bool bid = (raw & BIDDED) != 0;
+      uint32_t L = raw & LOCMASK;
       if (need || a.cfwd[L] != ALIVE) {
         for (int h = 0; h < (1 << 16); h++) {
           uint32_t f = a.cfwd[L];
@@ -549,14 +577,17 @@ __global__ void k4_pick(K4Args a) {
         unsigned long long qk;
         load_pt(a.pts, p, qp, qk);
         L = walk<D, F32>(a, pr, L, p, qp, qk);
-        a.ploc[p] = L;
+        bid = false;
       }
-      atomicMin(&a.ccand[L], make_key(a.round, p));
+      if (!bid) {
+        atomicMin(&a.ccand[L], bid_key(p));
+        a.ploc[p] = L | BIDDED;
+      }
     }
   }
   uint32_t c = wave_sum(npend);
-  if (lane_id() == 0 && c) atomicAdd(&a.ctr->pending, c);
-  flush_pred<D>(a.ctr, pr.st);
+  if (lane_id() == 0 && c) atomicAdd(&a.pend[blockIdx.x % NSTRIPE], c);
+  flush_pred<D>(a.pstripe, pr.st);
 }
 
 // Candidate selection (one thread per active point): a located point
@@ -574,9 +605,10 @@ __global__ void k4_select(K4Args a) {
   uint32_t p = 0;
   if (ia < nact) {
     p = a.act[ia];
-    uint32_t L = a.ploc[p];
-    if (L != DONE && (L & NEEDWALK) == 0 && prio_of(p) < thresh) {
-      unsigned long long K = make_key(a.round, p);
+    const uint32_t raw = a.ploc[p];
+    if (raw != DONE && (raw & NEEDWALK) == 0 && prio_of(p) < thresh) {
+      const uint32_t L = raw & LOCMASK;
+      const unsigned long long K = bid_key(p);
       want = (a.ccand[L] == K);
       if (want) {
         uint4 nb = a.cn[L];
@@ -606,7 +638,7 @@ __global__ void k4_select(K4Args a) {
     // cavity whatever else does, so any larger candidate whose search
     // reaches it loses (it would fail verification anyway) and can stop
     // at once instead of finishing its search.
-    atomicMin(&a.ccav[a.ploc[p]], make_key(a.round, p));
+    atomicMin(&a.ccav[a.ploc[p] & LOCMASK], make_key(a.round, p));
   }
   }
 }
@@ -656,7 +688,7 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
       } else {
         const uint32_t q = a.cand_pt[slot];
         const unsigned long long Kq = make_key(a.round, q);
-        const uint32_t L = a.ploc[q];
+        const uint32_t L = a.ploc[q] & LOCMASK;
         a.cand_ext[slot] = DONE;
         // the own cell was claimed at selection; a smaller claim means a
         // smaller candidate's cavity holds it already
@@ -767,7 +799,7 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
     if (mx) atomicMax(&a.ctr->maxcav, mx);
     if (cells) atomicAdd(&a.ctr->cavcells, cells);
   }
-  flush_pred<D>(a.ctr, pr.st);
+  flush_pred<D>(a.pstripe, pr.st);
 }
 
 // New cell index of boundary facet (cavity position h, facet f).
@@ -990,7 +1022,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
 
   uint32_t cavcap = (D == 2) ? 96 : 192;
   uint32_t maxcand = npts < (1u << 19) ? (npts ? npts : 1) : (1u << 19);
-  DevBuf ploc, cand_pt, cand_n, cav, cavinfo, cand_ext, extcell, extinfo, actbuf;
+  DevBuf ploc, cand_pt, cand_n, cav, cavinfo, cand_ext, extcell, extinfo, actbuf, stripes;
+  DT_TRY(stripes.alloc((size_t)NSTRIPE * 16 * 8 + NSTRIPE * 4));
+  DT_HIP(hipMemsetAsync(stripes.p, 0, (size_t)NSTRIPE * 16 * 8 + NSTRIPE * 4, st));
   DT_TRY(actbuf.alloc((size_t)(npts ? npts : 1) * 4));
   DT_TRY(cand_ext.alloc((size_t)maxcand * 4));
   DT_TRY(extcell.alloc((size_t)MAXEXT * EXTCAP * 4));
@@ -1024,6 +1058,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.extcell = extcell.as<uint32_t>();
   a.extinfo = extinfo.as<uint32_t>();
   a.ctr = dctr;
+  a.pstripe = stripes.as<unsigned long long>();
+  a.pend = reinterpret_cast<uint32_t*>(stripes.as<unsigned long long>() + NSTRIPE * 16);
   a.npts = npts;
   a.nsets = job.nsets;
   a.cap = pool.cap;
@@ -1060,16 +1096,18 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   const uint32_t ga = npts ? (nblk(npts) < 8192 ? nblk(npts) : 8192) : 1;
   uint64_t cbound = npts < maxcand ? (npts ? npts : 1) : maxcand;
   const uint32_t gi = (uint32_t)(cbound < job.cand_blocks ? cbound : job.cand_blocks);
+  // the cavity search runs CAV_GROUPS candidates per block
+  const uint32_t gc = (gi + CAV_GROUPS - 1) / CAV_GROUPS;
   uint32_t round = 1, group = 4;
   for (;;) {
     for (uint32_t r = 0; r < group; r++, round++) {
       if (round >= (1u << 30)) return DT_E_INTERNAL;
       if ((round & 0xFFFu) == 0) {
-        // the 12-bit round stamp wraps: clear every claim word in use
+        // the 12-bit round stamp wraps: clear every cavity and shell claim
+        // in use (bids carry no stamp)
         DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
         DT_HIP(hipStreamSynchronize(st));
         size_t used = hctr->cells < pool.cap ? hctr->cells : pool.cap;
-        DT_HIP(hipMemsetAsync(pool.ccand.p, 0xFF, used * 8, st));
         DT_HIP(hipMemsetAsync(pool.ccav.p, 0xFF, used * 8, st));
         DT_HIP(hipMemsetAsync(pool.cshell.p, 0xFF, used * 8, st));
       }
@@ -1086,10 +1124,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
       else hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
       DT_PROF_END(st);
       DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
-      if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gi), dim3(64), 0, st, a);
-      else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gi), dim3(64), 0, st, a);
-      else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gi), dim3(64), 0, st, a);
-      else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gi), dim3(64), 0, st, a);
+      if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gc), dim3(64), 0, st, a);
+      else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gc), dim3(64), 0, st, a);
+      else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gc), dim3(64), 0, st, a);
+      else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gc), dim3(64), 0, st, a);
       DT_PROF_END(st);
       DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
       if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);
@@ -1116,9 +1154,18 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
             job.nsets, hctr->rounds, hctr->cand_total, hctr->cavcells);
   ks.maxcav = hctr->maxcav;
   ks.cavity_cells = hctr->cavcells;
+  ks.candidates = hctr->cand_total;
   pool.ncells = hctr->cells;
   for (int i = 0; i < 4; i++)
-    for (int j = 0; j < 4; j++) ks.pred[i][j] = hctr->pred[i][j];
+    for (int j = 0; j < 4; j++) ks.pred[i][j] = 0;
+  {
+    std::vector<unsigned long long> hs((size_t)NSTRIPE * 16);
+    DT_HIP(hipMemcpyAsync(hs.data(), stripes.p, hs.size() * 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    for (uint32_t b = 0; b < NSTRIPE; b++)
+      for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) ks.pred[i][j] += hs[(size_t)b * 16 + i * 4 + j];
+  }
   return DT_OK;
 }
 

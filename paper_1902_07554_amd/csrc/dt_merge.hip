@@ -379,6 +379,10 @@ __global__ void k_merge_border(const double4* P, const uint4* cv, const uint32_t
                                uint32_t ncells, const uint32_t* pid_by_id, const uint32_t* occ,
                                const uint4* tkeys, uint32_t tmask, int32_t* rows, uint32_t* count,
                                uint32_t cap, unsigned long long* probe_hist, uint32_t* flags) {
+  // probe-length histogram: per block in LDS, one global add per bin
+  __shared__ uint32_t s_hist[16];
+  if (threadIdx.x < 16) s_hist[threadIdx.x] = 0;
+  __syncthreads();
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint4 v;
   bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
@@ -405,7 +409,7 @@ __global__ void k_merge_border(const double4* P, const uint4* cv, const uint32_t
           break;
         }
       }
-      atomicAdd(&probe_hist[pr < 15 ? pr : 15], 1ull);
+      atomicAdd(&s_hist[pr < 15 ? pr : 15], 1u);
     }
   }
   uint32_t slot = wave_slot(emit, count);
@@ -413,6 +417,9 @@ __global__ void k_merge_border(const double4* P, const uint4* cv, const uint32_t
     if (slot < cap) write_row<D>(rows, slot, k);
     else atomicOr(flags, FAIL_OUT_CAP);
   }
+  __syncthreads();
+  if (threadIdx.x < 16 && s_hist[threadIdx.x])
+    atomicAdd(&probe_hist[threadIdx.x], (unsigned long long)s_hist[threadIdx.x]);
 }
 
 int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,

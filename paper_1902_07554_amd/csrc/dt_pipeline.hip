@@ -185,6 +185,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   r->stats.num_simplices = r->m;
   r->stats.rounds = ks.rounds;
   r->stats.cavity_cells = (int64_t)ks.cavity_cells;
+  r->stats.candidates = (int64_t)ks.candidates;
   fill_pred_stats(r->stats, ks);
   r->stats.stage_ms[DT_STAGE_VALIDATE] = t1 - t0;
   r->stats.stage_ms[DT_STAGE_LOCAL_DT] = t2 - t1;

@@ -48,3 +48,21 @@ def test_library_loads_and_binds(libpath):
     assert b.dt_strerror(binding.DT_E_DUPLICATE)
     o = binding.options()
     assert o.divide == 0
+
+
+def test_binding_structs_match_header(tmp_path):
+    """ctypes mirrors of dt_options and dt_stats have the C layout."""
+    from paper_1902_07554_amd import binding
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dt.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(dt_options), '
+                   'sizeof(dt_stats), offsetof(dt_options, cand_blocks), '
+                   'offsetof(dt_stats, candidates));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(binding.Options), ctypes.sizeof(binding.Stats),
+            binding.Options.cand_blocks.offset, binding.Stats.candidates.offset]
+    assert got == want
