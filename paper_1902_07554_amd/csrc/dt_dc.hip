@@ -299,30 +299,17 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   S.stage_ms[DT_STAGE_BORDER_DT] = th - tg;
 
   // ---- merge
+  int64_t local_finite = 0, border_finite = 0;
   DT_TRY(merge_output(job, pool, bo, bjob, bpool, pid.as<uint32_t>(), D, r->rows, &r->m,
-                      S.probe_hist, st));
+                      &local_finite, &border_finite, S.probe_hist, st));
   double ti = now_ms();
   S.stage_ms[DT_STAGE_MERGE] = ti - th;
   S.num_simplices = r->m;
   r->set_offsets = {0, r->m};
   S.o_dt = ((double)n + (o.divide == DT_DIVIDE_SAMPLE ? eta : 0) + bo.nvb) / (double)n;
+  S.local_simplices = local_finite;
+  S.tb_simplices = border_finite;
 
-  // ---- statistics needing counts, and optional stage arrays
-  {
-    DevBuf c1;
-    DT_TRY(c1.alloc(16));
-    uint32_t a = 0, b = 0;
-    DT_TRY(k4_extract(job, pool, nullptr, c1.as<uint32_t>(), nullptr, st));
-    DT_HIP(hipMemcpyAsync(&a, c1.p, 4, hipMemcpyDeviceToHost, st));
-    DT_HIP(hipStreamSynchronize(st));
-    if (bpool.ncells) {
-      DT_TRY(k4_extract(bjob, bpool, nullptr, c1.as<uint32_t>(), nullptr, st));
-      DT_HIP(hipMemcpyAsync(&b, c1.p, 4, hipMemcpyDeviceToHost, st));
-      DT_HIP(hipStreamSynchronize(st));
-    }
-    S.local_simplices = a;
-    S.tb_simplices = b;
-  }
   if (o.keep_stages) {
     if (o.divide == DT_DIVIDE_SAMPLE) {
       std::vector<uint32_t> h(eta);

@@ -35,6 +35,8 @@
 #include "dt_common.hpp"
 #include "dt_internal.hpp"
 #include "dt_pred.hpp"
+#include "dt_block.hpp"
+#include "dt_prims.hpp"
 
 #include <stdio.h>
 #include <stdlib.h>
@@ -962,37 +964,51 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
 }
 
 // ------------------------------------------------------------ extraction
+// Live finite cells, in cell order: a counting pass (per block of BLOCK
+// cells, optionally also per set), a scan of the block counts, and a
+// writing pass that puts each block's rows at its offset.
 template <int D>
-__global__ void k4_extract_rows(const double4* pts, const uint32_t* pset, const uint4* cv,
-                                const uint32_t* cfwd, uint32_t ncells, int32_t* rows,
-                                uint32_t* count, uint32_t* set_rows) {
-  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  bool take = false;
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if (c < ncells && cfwd[c] == ALIVE) {
-    v = cv[c];
-    take = true;
+__device__ __forceinline__ bool finite_live_cell(const uint4* cv, const uint32_t* cfwd,
+                                                 uint32_t ncells, uint32_t c, uint4& v) {
+  v = make_uint4(0, 0, 0, 0);
+  if (c >= ncells || cfwd[c] != ALIVE) return false;
+  v = cv[c];
 #pragma unroll
-    for (int i = 0; i <= D; i++)
-      if (vat(v, i) == INF_V) take = false;
-  }
-  uint32_t slot = wave_alloc(take, count);
-  if (take) {
-    if (set_rows) atomicAdd(&set_rows[pset[v.x]], 1u);
-    if (rows) {
-      int32_t k[4];
+  for (int i = 0; i <= D; i++)
+    if (vat(v, i) == INF_V) return false;
+  return true;
+}
+
+template <int D>
+__global__ void k4_count_rows(const uint32_t* pset, const uint4* cv, const uint32_t* cfwd,
+                              uint32_t ncells, uint32_t* bcnt, uint32_t* set_rows) {
+  uint4 v;
+  const bool take = finite_live_cell<D>(cv, cfwd, ncells, blockIdx.x * BLOCK + threadIdx.x, v);
+  if (take && set_rows) atomicAdd(&set_rows[pset[v.x]], 1u);
+  uint32_t tot;
+  block_exclusive<BLOCK>(take ? 1u : 0u, &tot);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+}
+
+template <int D>
+__global__ void k4_write_rows(const double4* pts, const uint4* cv, const uint32_t* cfwd,
+                              uint32_t ncells, const uint32_t* boff, int32_t* rows) {
+  uint4 v;
+  const bool take = finite_live_cell<D>(cv, cfwd, ncells, blockIdx.x * BLOCK + threadIdx.x, v);
+  uint32_t tot;
+  const uint32_t pre = block_exclusive<BLOCK>(take ? 1u : 0u, &tot);
+  if (!take) return;
+  const size_t slot = (size_t)boff[blockIdx.x] + pre;
+  int32_t k[4];
 #pragma unroll
-      for (int i = 0; i <= D; i++) k[i] = (int32_t)__double_as_longlong(pts[vat(v, i)].w);
-      // sort ascending
+  for (int i = 0; i <= D; i++) k[i] = (int32_t)__double_as_longlong(pts[vat(v, i)].w);
 #pragma unroll
-      for (int i = 1; i <= D; i++)
+  for (int i = 1; i <= D; i++)
 #pragma unroll
-        for (int j = i; j > 0; j--)
-          if (k[j] < k[j - 1]) { int32_t t = k[j]; k[j] = k[j - 1]; k[j - 1] = t; }
+    for (int j = i; j > 0; j--)
+      if (k[j] < k[j - 1]) { int32_t t = k[j]; k[j] = k[j - 1]; k[j - 1] = t; }
 #pragma unroll
-      for (int i = 0; i <= D; i++) rows[(size_t)slot * (D + 1) + i] = k[i];
-    }
-  }
+  for (int i = 0; i <= D; i++) rows[slot * (D + 1) + i] = k[i];
 }
 
 // ------------------------------------------------------------ host driver
@@ -1173,15 +1189,35 @@ int k4_extract(const LocalJob& job, const CellPool& pool, int32_t* rows, uint32_
                uint32_t* set_rows, hipStream_t st) {
   DT_HIP(hipMemsetAsync(count_dev, 0, sizeof(uint32_t), st));
   if (pool.ncells == 0) return DT_OK;
+  const uint32_t nb = nblk(pool.ncells);
+  DevBuf bcnt, boff;
+  DT_TRY(bcnt.alloc((size_t)(nb + 1) * 4));
+  DT_TRY(boff.alloc((size_t)(nb + 1) * 4));
+  DT_HIP(hipMemsetAsync(bcnt.as<uint32_t>() + nb, 0, 4, st));
   if (job.D == 2)
-    hipLaunchKernelGGL(k4_extract_rows<2>, dim3(nblk(pool.ncells)), dim3(BLOCK), 0, st, job.pts,
-                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, rows,
-                       count_dev, set_rows);
+    hipLaunchKernelGGL(k4_count_rows<2>, dim3(nb), dim3(BLOCK), 0, st, job.pset,
+                       pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                       bcnt.as<uint32_t>(), set_rows);
   else
-    hipLaunchKernelGGL(k4_extract_rows<3>, dim3(nblk(pool.ncells)), dim3(BLOCK), 0, st, job.pts,
-                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, rows,
-                       count_dev, set_rows);
+    hipLaunchKernelGGL(k4_count_rows<3>, dim3(nb), dim3(BLOCK), 0, st, job.pset,
+                       pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                       bcnt.as<uint32_t>(), set_rows);
   DT_HIP(hipGetLastError());
+  DT_TRY(exclusive_scan(bcnt.as<uint32_t>(), boff.as<uint32_t>(), nb + 1, st));
+  DT_HIP(hipMemcpyAsync(count_dev, boff.as<uint32_t>() + nb, 4, hipMemcpyDeviceToDevice, st));
+  if (rows) {
+    if (job.D == 2)
+      hipLaunchKernelGGL(k4_write_rows<2>, dim3(nb), dim3(BLOCK), 0, st, job.pts,
+                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         boff.as<uint32_t>(), rows);
+    else
+      hipLaunchKernelGGL(k4_write_rows<3>, dim3(nb), dim3(BLOCK), 0, st, job.pts,
+                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         boff.as<uint32_t>(), rows);
+    DT_HIP(hipGetLastError());
+  }
+  // the block offsets are freed on return: finish the launches first
+  DT_HIP(hipStreamSynchronize(st));
   return DT_OK;
 }
 

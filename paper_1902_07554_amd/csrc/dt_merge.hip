@@ -22,6 +22,7 @@
 // in an open-addressing hash table keyed by the sorted vertex ids.
 #include <math.h>
 
+#include "dt_block.hpp"
 #include "dt_common.hpp"
 #include "dt_internal.hpp"
 #include "dt_prims.hpp"
@@ -326,16 +327,6 @@ __device__ __forceinline__ bool finite_live(const uint4* cv, const uint32_t* cfw
   return true;
 }
 
-__device__ __forceinline__ uint32_t wave_slot(bool want, uint32_t* ctr) {
-  unsigned long long m = __ballot(want);
-  if (m == 0) return 0;
-  int leader = __ffsll((long long)m) - 1;
-  uint32_t lane = threadIdx.x & 63;
-  uint32_t base = 0;
-  if ((int)lane == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
-  base = __shfl(base, leader);
-  return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-}
 
 template <int D>
 __device__ __forceinline__ void write_row(int32_t* rows, uint32_t slot, const uint32_t k[4]) {
@@ -343,27 +334,28 @@ __device__ __forceinline__ void write_row(int32_t* rows, uint32_t slot, const ui
   for (int i = 0; i <= D; i++) rows[(size_t)slot * (D + 1) + i] = (int32_t)k[i];
 }
 
-// Local cells: unflagged finite cells are output; flagged ones go to the table.
+// The merge runs in two passes over each pool, so that the output needs no
+// atomic cursor and comes out in cell order: a marking pass (per block:
+// the number of cells to output, and the number of finite cells for the
+// statistics; local flagged cells go into the table, border cells are
+// looked up in it), a scan of the block counts, and a writing pass.
+
+// Local pass 1: count unflagged finite cells; insert flagged ones into B.
 template <int D>
-__global__ void k_merge_local(const double4* P, const uint4* cv, const uint32_t* cfwd,
-                              uint32_t ncells, const uint8_t* cflag, uint32_t* occ,
-                              uint4* tkeys, uint32_t tmask, int32_t* rows, uint32_t* count,
-                              uint32_t cap, uint32_t* flags) {
-  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_merge_mark_local(const double4* P, const uint4* cv, const uint32_t* cfwd,
+                                   uint32_t ncells, const uint8_t* cflag, uint32_t* occ,
+                                   uint4* tkeys, uint32_t tmask, uint32_t* bemit,
+                                   uint32_t* bfinite, uint32_t* flags) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint4 v;
-  bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
-  bool emit = live && cflag[c] == 0;
-  uint32_t k[4] = {0, 0, 0, 0};
-  if (live) sorted_keys(P, v, D, k);
-  uint32_t slot = wave_slot(emit, count);
-  if (emit) {
-    if (slot < cap) write_row<D>(rows, slot, k);
-    else atomicOr(flags, FAIL_OUT_CAP);
-  }
-  if (live && !emit) {
-    uint32_t h = hkey(k);
+  const bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
+  const bool flagged = live && cflag[c] != 0;
+  if (flagged) {
+    uint32_t k[4];
+    sorted_keys(P, v, D, k);
+    const uint32_t h = hkey(k);
     for (uint32_t pr = 0; pr <= tmask; pr++) {
-      uint32_t s = (h + pr) & tmask;
+      const uint32_t s = (h + pr) & tmask;
       if (atomicCAS(&occ[s], 0u, 1u) == 0u) {
         tkeys[s] = make_uint4(k[0], k[1], k[2], k[3]);
         break;
@@ -371,26 +363,51 @@ __global__ void k_merge_local(const double4* P, const uint4* cv, const uint32_t*
       if (pr == tmask) atomicOr(flags, FAIL_HASH);
     }
   }
+  uint32_t ne, nf;
+  block_exclusive<MB>((live && !flagged) ? 1u : 0u, &ne);
+  block_exclusive<MB>(live ? 1u : 0u, &nf);
+  if (threadIdx.x == 0) {
+    bemit[blockIdx.x] = ne;
+    bfinite[blockIdx.x] = nf;
+  }
 }
 
-// Border cells: spanning, or present in B.
+// Local pass 2: write the unflagged finite cells.
 template <int D>
-__global__ void k_merge_border(const double4* P, const uint4* cv, const uint32_t* cfwd,
-                               uint32_t ncells, const uint32_t* pid_by_id, const uint32_t* occ,
-                               const uint4* tkeys, uint32_t tmask, int32_t* rows, uint32_t* count,
-                               uint32_t cap, unsigned long long* probe_hist, uint32_t* flags) {
+__global__ void k_merge_write_local(const double4* P, const uint4* cv, const uint32_t* cfwd,
+                                    uint32_t ncells, const uint8_t* cflag, const uint32_t* boff,
+                                    int32_t* rows) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  uint4 v;
+  const bool emit = c < ncells && finite_live<D>(cv, cfwd, c, v) && cflag[c] == 0;
+  uint32_t tot;
+  const uint32_t pre = block_exclusive<MB>(emit ? 1u : 0u, &tot);
+  if (!emit) return;
+  uint32_t k[4];
+  sorted_keys(P, v, D, k);
+  write_row<D>(rows, boff[blockIdx.x] + pre, k);
+}
+
+// Border pass 1: a finite cell of T_B is output if it spans several
+// partitions or its vertex set is in B; the decision is kept per cell.
+template <int D>
+__global__ void k_merge_mark_border(const double4* P, const uint4* cv, const uint32_t* cfwd,
+                                    uint32_t ncells, const uint32_t* pid_by_id,
+                                    const uint32_t* occ, const uint4* tkeys, uint32_t tmask,
+                                    uint8_t* emitf, uint32_t* bemit, uint32_t* bfinite,
+                                    unsigned long long* probe_hist) {
   // probe-length histogram: per block in LDS, one global add per bin
   __shared__ uint32_t s_hist[16];
   if (threadIdx.x < 16) s_hist[threadIdx.x] = 0;
   __syncthreads();
-  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint4 v;
-  bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
+  const bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
   bool emit = false;
-  uint32_t k[4] = {0, 0, 0, 0};
   if (live) {
+    uint32_t k[4];
     sorted_keys(P, v, D, k);
-    uint32_t p0 = pid_by_id[k[0]];
+    const uint32_t p0 = pid_by_id[k[0]];
     bool span = false;
 #pragma unroll
     for (int i = 1; i <= D; i++)
@@ -398,12 +415,12 @@ __global__ void k_merge_border(const double4* P, const uint4* cv, const uint32_t
     if (span) {
       emit = true;
     } else {
-      uint32_t h = hkey(k);
+      const uint32_t h = hkey(k);
       uint32_t pr = 0;
       for (; pr <= tmask; pr++) {
-        uint32_t s = (h + pr) & tmask;
+        const uint32_t s = (h + pr) & tmask;
         if (occ[s] == 0u) break;
-        uint4 t = tkeys[s];
+        const uint4 t = tkeys[s];
         if (t.x == k[0] && t.y == k[1] && t.z == k[2] && t.w == k[3]) {
           emit = true;
           break;
@@ -412,82 +429,137 @@ __global__ void k_merge_border(const double4* P, const uint4* cv, const uint32_t
       atomicAdd(&s_hist[pr < 15 ? pr : 15], 1u);
     }
   }
-  uint32_t slot = wave_slot(emit, count);
-  if (emit) {
-    if (slot < cap) write_row<D>(rows, slot, k);
-    else atomicOr(flags, FAIL_OUT_CAP);
+  if (c < ncells) emitf[c] = emit ? 1 : 0;
+  uint32_t ne, nf;
+  block_exclusive<MB>(emit ? 1u : 0u, &ne);
+  block_exclusive<MB>(live ? 1u : 0u, &nf);
+  if (threadIdx.x == 0) {
+    bemit[blockIdx.x] = ne;
+    bfinite[blockIdx.x] = nf;
   }
-  __syncthreads();
   if (threadIdx.x < 16 && s_hist[threadIdx.x])
     atomicAdd(&probe_hist[threadIdx.x], (unsigned long long)s_hist[threadIdx.x]);
 }
 
+// Border pass 2: write the kept cells after the local ones.
+template <int D>
+__global__ void k_merge_write_border(const double4* P, const uint4* cv, uint32_t ncells,
+                                     const uint8_t* emitf, const uint32_t* boff, uint32_t base,
+                                     int32_t* rows) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool emit = c < ncells && emitf[c] != 0;
+  uint32_t tot;
+  const uint32_t pre = block_exclusive<MB>(emit ? 1u : 0u, &tot);
+  if (!emit) return;
+  uint32_t k[4];
+  sorted_keys(P, cv[c], D, k);
+  write_row<D>(rows, base + boff[blockIdx.x] + pre, k);
+}
+
+// Sum of n block counts: exclusive offsets into off[0..n], total returned.
+static int scan_counts(DevBuf& cnt, DevBuf& off, uint32_t n, uint32_t* total, hipStream_t st) {
+  DT_HIP(hipMemsetAsync(cnt.as<uint32_t>() + n, 0, 4, st));
+  DT_TRY(exclusive_scan(cnt.as<uint32_t>(), off.as<uint32_t>(), n + 1, st));
+  DT_HIP(hipMemcpyAsync(total, off.as<uint32_t>() + n, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
 int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
                  const LocalJob& bjob, const CellPool& bpool, const uint32_t* pid_by_id, int D,
-                 DevBuf& rows, int64_t* m, int64_t probe_hist[16], hipStream_t st) {
-  // upper bound of the output: live finite cells of both pools
-  DevBuf cnt;
-  DT_TRY(cnt.alloc(16));
-  uint32_t nl = 0, nbd = 0;
-  DT_TRY(k4_extract(job, pool, nullptr, cnt.as<uint32_t>(), nullptr, st));
-  DT_HIP(hipMemcpyAsync(&nl, cnt.p, 4, hipMemcpyDeviceToHost, st));
-  DT_HIP(hipStreamSynchronize(st));
-  if (bpool.ncells) {
-    DT_TRY(k4_extract(bjob, bpool, nullptr, cnt.as<uint32_t>(), nullptr, st));
-    DT_HIP(hipMemcpyAsync(&nbd, cnt.p, 4, hipMemcpyDeviceToHost, st));
-    DT_HIP(hipStreamSynchronize(st));
-  }
-  uint32_t cap = nl + nbd;
-  DT_TRY(rows.alloc_plain((size_t)(cap ? cap : 1) * (D + 1) * 4));
+                 DevBuf& rows, int64_t* m, int64_t* local_finite, int64_t* border_finite,
+                 int64_t probe_hist[16], hipStream_t st) {
   uint32_t tsize = 64;
   while (tsize < 2 * b.nb_finite + 16) tsize <<= 1;
-  DevBuf occ, tkeys, ctr, hist, flags;
+  const uint32_t nbl = mblocks(pool.ncells), nbb = mblocks(bpool.ncells);
+  DevBuf occ, tkeys, hist, flags, lemit, lfin, loff, bemit, bfin, boff, emitf, junk;
   DT_TRY(occ.alloc((size_t)tsize * 4));
   DT_TRY(tkeys.alloc((size_t)tsize * 16));
-  DT_TRY(ctr.alloc(4));
   DT_TRY(hist.alloc(16 * 8));
   DT_TRY(flags.alloc(4));
+  DT_TRY(lemit.alloc((size_t)(nbl + 1) * 4));
+  DT_TRY(lfin.alloc((size_t)(nbl + 1) * 4));
+  DT_TRY(loff.alloc((size_t)(nbl + 1) * 4));
+  DT_TRY(bemit.alloc((size_t)(nbb + 1) * 4));
+  DT_TRY(bfin.alloc((size_t)(nbb + 1) * 4));
+  DT_TRY(boff.alloc((size_t)(nbb + 1) * 4));
+  DT_TRY(emitf.alloc((size_t)(bpool.ncells ? bpool.ncells : 1)));
+  DT_TRY(junk.alloc((size_t)(((nbl > nbb) ? nbl : nbb) + 1) * 4));
   DT_HIP(hipMemsetAsync(occ.p, 0, (size_t)tsize * 4, st));
-  DT_HIP(hipMemsetAsync(ctr.p, 0, 4, st));
   DT_HIP(hipMemsetAsync(hist.p, 0, 16 * 8, st));
   DT_HIP(hipMemsetAsync(flags.p, 0, 4, st));
   DT_PROF_BEGIN(DT_KERN_MERGE, st);
   if (pool.ncells) {
     if (D == 2)
-      hipLaunchKernelGGL(k_merge_local<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+      hipLaunchKernelGGL(k_merge_mark_local<2>, dim3(nbl), dim3(MB), 0, st, job.pts,
                          pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
                          b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap, flags.as<uint32_t>());
+                         lemit.as<uint32_t>(), lfin.as<uint32_t>(), flags.as<uint32_t>());
     else
-      hipLaunchKernelGGL(k_merge_local<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+      hipLaunchKernelGGL(k_merge_mark_local<3>, dim3(nbl), dim3(MB), 0, st, job.pts,
                          pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
                          b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap, flags.as<uint32_t>());
+                         lemit.as<uint32_t>(), lfin.as<uint32_t>(), flags.as<uint32_t>());
   }
   if (bpool.ncells) {
     if (D == 2)
-      hipLaunchKernelGGL(k_merge_border<2>, dim3(mblocks(bpool.ncells)), dim3(MB), 0, st,
-                         bjob.pts, bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
+      hipLaunchKernelGGL(k_merge_mark_border<2>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
+                         bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
                          pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap,
-                         hist.as<unsigned long long>(), flags.as<uint32_t>());
+                         emitf.as<uint8_t>(), bemit.as<uint32_t>(), bfin.as<uint32_t>(),
+                         hist.as<unsigned long long>());
     else
-      hipLaunchKernelGGL(k_merge_border<3>, dim3(mblocks(bpool.ncells)), dim3(MB), 0, st,
-                         bjob.pts, bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
+      hipLaunchKernelGGL(k_merge_mark_border<3>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
+                         bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
                          pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         rows.as<int32_t>(), ctr.as<uint32_t>(), cap,
-                         hist.as<unsigned long long>(), flags.as<uint32_t>());
+                         emitf.as<uint8_t>(), bemit.as<uint32_t>(), bfin.as<uint32_t>(),
+                         hist.as<unsigned long long>());
   }
   DT_PROF_END(st);
   DT_HIP(hipGetLastError());
-  uint32_t hm = 0, hf = 0;
+  uint32_t nl = 0, nb = 0, fl = 0, fb = 0;
+  if (pool.ncells) {
+    DT_TRY(scan_counts(lemit, loff, nbl, &nl, st));
+    DT_TRY(scan_counts(lfin, junk, nbl, &fl, st));
+  }
+  if (bpool.ncells) {
+    DT_TRY(scan_counts(bemit, boff, nbb, &nb, st));
+    DT_TRY(scan_counts(bfin, junk, nbb, &fb, st));
+  }
+  const uint64_t total = (uint64_t)nl + nb;
+  DT_TRY(rows.alloc_plain((size_t)(total ? total : 1) * (D + 1) * 4));
+  DT_PROF_BEGIN(DT_KERN_MERGE, st);
+  if (nl) {
+    if (D == 2)
+      hipLaunchKernelGGL(k_merge_write_local<2>, dim3(nbl), dim3(MB), 0, st, job.pts,
+                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         b.cflag.as<uint8_t>(), loff.as<uint32_t>(), rows.as<int32_t>());
+    else
+      hipLaunchKernelGGL(k_merge_write_local<3>, dim3(nbl), dim3(MB), 0, st, job.pts,
+                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         b.cflag.as<uint8_t>(), loff.as<uint32_t>(), rows.as<int32_t>());
+  }
+  if (nb) {
+    if (D == 2)
+      hipLaunchKernelGGL(k_merge_write_border<2>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
+                         bpool.cv.as<uint4>(), bpool.ncells, emitf.as<uint8_t>(),
+                         boff.as<uint32_t>(), nl, rows.as<int32_t>());
+    else
+      hipLaunchKernelGGL(k_merge_write_border<3>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
+                         bpool.cv.as<uint4>(), bpool.ncells, emitf.as<uint8_t>(),
+                         boff.as<uint32_t>(), nl, rows.as<int32_t>());
+  }
+  DT_PROF_END(st);
+  DT_HIP(hipGetLastError());
+  uint32_t hf = 0;
   unsigned long long hh[16];
-  DT_HIP(hipMemcpyAsync(&hm, ctr.p, 4, hipMemcpyDeviceToHost, st));
   DT_HIP(hipMemcpyAsync(&hf, flags.p, 4, hipMemcpyDeviceToHost, st));
   DT_HIP(hipMemcpyAsync(hh, hist.p, 16 * 8, hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
   if (hf) return DT_E_INTERNAL;
-  *m = hm;
+  *m = (int64_t)total;
+  *local_finite = fl;
+  *border_finite = fb;
   for (int i = 0; i < 16; i++) probe_hist[i] = (int64_t)hh[i];
   return DT_OK;
 }

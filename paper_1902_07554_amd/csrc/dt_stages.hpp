@@ -54,8 +54,11 @@ struct Region {
 int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, uint32_t n,
                   int D, double cells_target, const double lo[3], const double hi[3],
                   BorderOut& out, hipStream_t st);
+// rows: the output (cell order: local cells, then border cells); *m their
+// number; *local_finite / *border_finite: finite cells of the T_i / T_B.
 int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
                  const LocalJob& bjob, const CellPool& bpool, const uint32_t* pid_by_id, int D,
-                 DevBuf& rows, int64_t* m, int64_t probe_hist[16], hipStream_t st);
+                 DevBuf& rows, int64_t* m, int64_t* local_finite, int64_t* border_finite,
+                 int64_t probe_hist[16], hipStream_t st);
 
 }  // namespace dtk
