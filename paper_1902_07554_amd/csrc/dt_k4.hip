@@ -819,9 +819,63 @@ __device__ __forceinline__ uint32_t facet_cell(uint32_t info, int f, uint32_t ba
 // the cavity cells; the new cell on a boundary facet links to its
 // neighbours across the facets through the point by rotating around the
 // shared ridge inside the cavity.
+// Boundary facets listed in LDS for the facet-parallel build (a cavity
+// with more falls back to one lane per cavity cell).
+constexpr uint32_t FTAB = 1024;
+
+// The new cell on boundary facet i of cavity cell c (cavity position of c
+// encoded in inf): its vertices, and its neighbour across facet i, which
+// gets the back link.
+template <int D>
+__device__ __forceinline__ void new_cell_outer(K4Args& a, uint32_t* cnw, uint32_t c, uint32_t inf,
+                                               int i, uint32_t base, uint32_t p) {
+  const uint32_t x = facet_cell(inf, i, base);
+  uint4 nv = a.cv[c];
+  vset(nv, i, p);
+  a.cv[x] = nv;
+  const uint32_t out = vat(a.cn[c], i);
+  cnw[(size_t)x * 4 + i] = out;
+  if (D == 2) cnw[(size_t)x * 4 + 3] = NOSLOT;
+  cnw[(size_t)(out >> 2) * 4 + (out & 3u)] = (x << 2) | (uint32_t)i;
+}
+
+// Neighbour of the new cell on facet i of cavity cell c across its facet
+// j (a facet through the new point): rotate around the ridge shared by
+// facets i and j inside the cavity until leaving it; the boundary facet
+// reached carries that neighbour.
+template <int D>
+__device__ __forceinline__ uint32_t new_cell_link(K4Args& a, CavList& cl, uint32_t c, int i, int j,
+                                                  uint32_t base, unsigned long long K) {
+  uint32_t cur = c;
+  int sin = i, sout = j;
+  uint4 vcur = a.cv[c];
+  for (int step = 0; step < 4096; step++) {
+    const uint32_t nbr = vat(a.cn[cur], sout);
+    const uint32_t ncell = nbr >> 2;
+    if (ncell >= a.cap) break;
+    if (a.ccav[ncell] != K) {
+      const uint32_t xp = facet_cell(cl.info(a.cpos[cur]), sout, base);
+      return (xp << 2) | (uint32_t)sin;
+    }
+    const uint32_t av = vat(vcur, sin);
+    const uint4 vn = a.cv[ncell];
+    int nout = 0;
+#pragma unroll
+    for (int r = 0; r <= D; r++)
+      if (vat(vn, r) == av) nout = r;
+    cur = ncell;
+    sin = (int)(nbr & 3u);
+    sout = nout;
+    vcur = vn;
+  }
+  atomicOr(&a.ctr->flags, FAIL_PIVOT);
+  return 0xFFFFFFFFu;
+}
+
 template <int D>
 __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
   __shared__ uint32_t s_fail, s_run, s_base;
+  __shared__ uint32_t s_ftab[FTAB];   // boundary facet f: cavity position << 2 | facet
   const uint32_t lane = threadIdx.x;
   const uint32_t ncand = min(a.ctr->ncand, a.maxcand);
   uint32_t won = 0;
@@ -879,8 +933,13 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
       }
       const uint32_t run = s_run;
       if (h < n) {
-        cl.info(h) = ((run + incl - cnt) << 8) | mask;
+        const uint32_t pre = run + incl - cnt;
+        cl.info(h) = (pre << 8) | mask;
         a.cpos[c] = h;
+        uint32_t f = pre;
+#pragma unroll
+        for (int i = 0; i <= D; i++)
+          if ((mask >> i & 1u) && f < FTAB) s_ftab[f++] = (h << 2) | (uint32_t)i;
       }
       const uint32_t total = __shfl(incl, 63, 64);
       __syncthreads();
@@ -899,6 +958,27 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
     __syncthreads();
     if (s_fail) continue;
     const uint32_t base = s_base;
+    if (nbf <= FTAB) {
+      // facet-parallel build: one task per (boundary facet, other facet of
+      // the new cell); the numbering written by the other lanes is read here
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      const uint32_t ntask = nbf * D;
+      for (uint32_t t = lane; t < ntask; t += 64) {
+        const uint32_t f = t / D, jj = t % D;
+        const uint32_t hf = s_ftab[f];
+        const uint32_t h = hf >> 2;
+        const int i = (int)(hf & 3u);
+        const int j = (int)jj < i ? (int)jj : (int)jj + 1;
+        const uint32_t c = cl.cell(h);
+        const uint32_t inf = cl.info(h);
+        const uint32_t x = facet_cell(inf, i, base);
+        if (jj == 0) new_cell_outer<D>(a, cnw, c, inf, i, base, p);
+        uint32_t link = new_cell_link<D>(a, cl, c, i, j, base, K);
+        if (link == 0xFFFFFFFFu) link = (x << 2) | (uint32_t)j;   // in-bounds; the run is abandoned
+        cnw[(size_t)x * 4 + j] = link;
+      }
+    } else {
+    // large cavity: one lane per cavity cell builds all its new cells
     for (uint32_t h = lane; h < n; h += 64) {
       const uint32_t c = cl.cell(h);
       const uint32_t inf = cl.info(h);
@@ -952,6 +1032,7 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
         a.cv[x] = nv;
         a.cn[x] = nn;
       }
+    }
     }
     for (uint32_t h = lane; h < n; h += 64) a.cfwd[cl.cell(h)] = base;
     if (lane == 0) {
