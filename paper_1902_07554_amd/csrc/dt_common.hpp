@@ -28,6 +28,19 @@ enum : uint32_t {
   FAIL_INVARIANT = 1u << 8,   // internal consistency check
 };
 
+// One triangulation cell, all its fields in one 64-byte record so that a
+// cell costs one cache line wherever it is touched.
+struct alignas(64) Cell {
+  uint4 v;                    // vertices (point indices, INF_V = infinite)
+  uint4 n;                    // neighbours: cell << 2 | facet index in the neighbour
+  unsigned long long cand;    // smallest bid of a pending point inside
+  unsigned long long cav;     // cavity claim (round-stamped key)
+  unsigned long long shell;   // shell claim (round-stamped key)
+  unsigned int fwd;           // ALIVE, or the first cell of the star that replaced it
+  unsigned int pos;           // position in the cavity list of its inserting candidate
+};
+static_assert(sizeof(Cell) == 64, "one cache line per cell");
+
 struct Counters {
   unsigned long long pred[4][4];
   unsigned long long cavcells;    // cells placed in cavities (all candidates)  // [orient2, orient3, in2, in3][calls, fp32 ok, fp64 ok, exact]

@@ -50,12 +50,12 @@ __global__ void k_set_of_point2(const uint32_t* off, uint32_t nsets, uint32_t n,
 
 // Finite live cells of a pool with their border flag (stage output).
 template <int D>
-__global__ void k_rows_with_flag(const double4* P, const uint4* cv, const uint32_t* cfwd,
+__global__ void k_rows_with_flag(const double4* P, const Cell* cells,
                                  uint32_t ncells, const uint8_t* cflag, int32_t* rows,
                                  uint32_t* count) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells || cfwd[c] != ALIVE) return;
-  uint4 v = cv[c];
+  if (c >= ncells || cells[c].fwd != ALIVE) return;
+  uint4 v = cells[c].v;
   uint32_t vv[4] = {v.x, v.y, v.z, v.w};
   int32_t k[4];
   for (int i = 0; i <= D; i++) {
@@ -332,11 +332,11 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
       if (pool.ncells) {
         if (D == 2)
           hipLaunchKernelGGL(k_rows_with_flag<2>, dim3(cblocks(pool.ncells)), dim3(CB), 0, st,
-                             job.pts, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                             job.pts, pool.cells.as<Cell>(), pool.ncells,
                              bo.cflag.as<uint8_t>(), rows.as<int32_t>(), c2.as<uint32_t>());
         else
           hipLaunchKernelGGL(k_rows_with_flag<3>, dim3(cblocks(pool.ncells)), dim3(CB), 0, st,
-                             job.pts, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                             job.pts, pool.cells.as<Cell>(), pool.ncells,
                              bo.cflag.as<uint8_t>(), rows.as<int32_t>(), c2.as<uint32_t>());
         DT_HIP(hipGetLastError());
       }

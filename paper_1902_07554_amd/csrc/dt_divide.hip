@@ -163,12 +163,12 @@ int spatial_sort(DevBuf& pts, uint32_t n, int D, const double lo[3], const doubl
 // ------------------------------------------------------------ 3. graph
 // Unique Delaunay edges of the sample triangulation through an
 // open-addressing set keyed by (u << 32 | v), u < v (sample-local ids).
-__global__ void k_edges(const uint4* cv, const uint32_t* cfwd, uint32_t ncells, int D,
+__global__ void k_edges(const Cell* cells, uint32_t ncells, int D,
                         unsigned long long* table, uint32_t tmask, uint32_t* elist,
                         uint32_t* ecount, uint32_t ecap) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells || cfwd[c] != ALIVE) return;
-  uint4 v4 = cv[c];
+  if (c >= ncells || cells[c].fwd != ALIVE) return;
+  uint4 v4 = cells[c].v;
   uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
   for (int i = 0; i <= D; i++)
     for (int j = i + 1; j <= D; j++) {
@@ -395,8 +395,7 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   DT_TRY(ecount.alloc(4));
   DT_HIP(hipMemsetAsync(table.p, 0xFF, (size_t)tsize * 8, st));
   DT_HIP(hipMemsetAsync(ecount.p, 0, 4, st));
-  hipLaunchKernelGGL(k_edges, dim3(dblocks(ncells)), dim3(DB), 0, st, pool.cv.as<uint4>(),
-                     pool.cfwd.as<uint32_t>(), ncells, D, table.as<unsigned long long>(),
+  hipLaunchKernelGGL(k_edges, dim3(dblocks(ncells)), dim3(DB), 0, st, pool.cells.as<Cell>(), ncells, D, table.as<unsigned long long>(),
                      tsize - 1, elist.as<uint32_t>(), ecount.as<uint32_t>(), ecap);
   DT_HIP(hipGetLastError());
   uint32_t m = 0;

@@ -113,7 +113,7 @@ struct LocalJob {
 // Cell pool: cells live at indices [0, ncells); cfwd == ALIVE marks a live
 // cell, vertices are indices into the job's point array (INF_V = infinite).
 struct CellPool {
-  DevBuf cv, cn, cfwd, ccand, ccav, cshell, cpos;
+  DevBuf cells;   // Cell[cap]
   uint32_t cap = 0;
   uint32_t ncells = 0;
   DevBuf set_cell0;   // [nsets] initial finite cell, DONE for a degenerate set

@@ -57,13 +57,7 @@ struct K4Args {
   const uint32_t* pset;
   const uint32_t* set_off;
   uint32_t* ploc;
-  uint4* cv;
-  uint4* cn;
-  uint32_t* cfwd;
-  unsigned long long* ccand;
-  unsigned long long* ccav;
-  unsigned long long* cshell;
-  uint32_t* cpos;
+  Cell* cells;
   uint32_t* set_cell0;
   uint32_t* cand_pt;
   uint32_t* cand_n;
@@ -109,6 +103,19 @@ struct CavList {
 // ------------------------------------------------------------ helpers
 __device__ __forceinline__ uint32_t vat(const uint4& v, int i) {
   return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+// A new cell: vertices, no claims, alive (neighbours are written apart).
+__device__ __forceinline__ void init_cell(Cell& c, const uint4& v) {
+  c.v = v;
+  c.cand = NOKEY;
+  c.cav = NOKEY;
+  c.shell = NOKEY;
+  c.fwd = ALIVE;
+  c.pos = 0;
+}
+// Neighbour slot s of cell x, for single-slot updates.
+__device__ __forceinline__ uint32_t* nslot(Cell* cells, uint32_t x, uint32_t s) {
+  return reinterpret_cast<uint32_t*>(&cells[x].n) + s;
 }
 __device__ __forceinline__ void vset(uint4& v, int i, uint32_t x) {
   if (i == 0) v.x = x;
@@ -313,7 +320,7 @@ __device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q
                          unsigned long long qk) {
   for (int step = 0; step < (1 << 16); step++) {
     if (c >= a.cap) break;
-    uint4 v = a.cv[c];
+    uint4 v = a.cells[c].v;
     int inf = -1;
     bool bad = false;
 #pragma unroll
@@ -325,7 +332,7 @@ __device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q
     if (bad) break;
     if (inf >= 0) {
       if (conflict<D, F32>(a, pr, v, q, qp, qk)) return c;
-      c = vat(a.cn[c], inf) >> 2;
+      c = vat(a.cells[c].n, inf) >> 2;
       continue;
     }
     PtsX X;
@@ -345,7 +352,7 @@ __device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q
       if (pr.template orient<D>(X) < 0) exitf = i;
     }
     if (exitf < 0) return c;
-    c = vat(a.cn[c], exitf) >> 2;
+    c = vat(a.cells[c].n, exitf) >> 2;
   }
   atomicOr(&a.ctr->flags, FAIL_WALK);
   return 0;
@@ -451,8 +458,8 @@ __global__ void k4_init_sets(K4Args a) {
       }
     }
     if (D == 2) nb.w = NOSLOT;
-    a.cv[base + x] = cells[x];
-    a.cn[base + x] = nb;
+    init_cell(a.cells[base + x], cells[x]);
+    a.cells[base + x].n = nb;
   }
   for (int j = 0; j <= D; j++) a.ploc[iv[j]] = DONE;
   a.set_cell0[s] = base;
@@ -569,9 +576,9 @@ __global__ void k4_pick(K4Args a) {
       const bool need = (raw & NEEDWALK) != 0;
       bool bid = (raw & BIDDED) != 0;
       uint32_t L = raw & LOCMASK;
-      if (need || a.cfwd[L] != ALIVE) {
+      if (need || a.cells[L].fwd != ALIVE) {
         for (int h = 0; h < (1 << 16); h++) {
-          uint32_t f = a.cfwd[L];
+          uint32_t f = a.cells[L].fwd;
           if (f == ALIVE) break;
           L = f;
         }
@@ -582,7 +589,7 @@ __global__ void k4_pick(K4Args a) {
         bid = false;
       }
       if (!bid) {
-        atomicMin(&a.ccand[L], bid_key(p));
+        atomicMin(&a.cells[L].cand, bid_key(p));
         a.ploc[p] = L | BIDDED;
       }
     }
@@ -611,12 +618,12 @@ __global__ void k4_select(K4Args a) {
     if (raw != DONE && (raw & NEEDWALK) == 0 && prio_of(p) < thresh) {
       const uint32_t L = raw & LOCMASK;
       const unsigned long long K = bid_key(p);
-      want = (a.ccand[L] == K);
+      want = (a.cells[L].cand == K);
       if (want) {
-        uint4 nb = a.cn[L];
+        uint4 nb = a.cells[L].n;
 #pragma unroll
         for (int i = 0; i <= D; i++)
-          if (a.ccand[vat(nb, i) >> 2] < K) want = false;
+          if (a.cells[vat(nb, i) >> 2].cand < K) want = false;
         // Second ring: a smaller bid two cells away almost always claims a
         // cell next to this cavity.  Skipping such candidates now (they
         // would lose) saves their searches; the smallest bid of all is
@@ -624,10 +631,10 @@ __global__ void k4_select(K4Args a) {
         if (want) {
 #pragma unroll
           for (int i = 0; i <= D && want; i++) {
-            uint4 nb2 = a.cn[vat(nb, i) >> 2];
+            uint4 nb2 = a.cells[vat(nb, i) >> 2].n;
 #pragma unroll
             for (int j = 0; j <= D; j++)
-              if (a.ccand[vat(nb2, j) >> 2] < K) want = false;
+              if (a.cells[vat(nb2, j) >> 2].cand < K) want = false;
           }
         }
       }
@@ -640,7 +647,7 @@ __global__ void k4_select(K4Args a) {
     // cavity whatever else does, so any larger candidate whose search
     // reaches it loses (it would fail verification anyway) and can stop
     // at once instead of finishing its search.
-    atomicMin(&a.ccav[a.ploc[p] & LOCMASK], make_key(a.round, p));
+    atomicMin(&a.cells[a.ploc[p] & LOCMASK].cav, make_key(a.round, p));
   }
   }
 }
@@ -694,7 +701,7 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
         a.cand_ext[slot] = DONE;
         // the own cell was claimed at selection; a smaller claim means a
         // smaller candidate's cavity holds it already
-        const bool ok = atomicMin(&a.ccav[L], Kq) >= Kq;
+        const bool ok = atomicMin(&a.cells[L].cav, Kq) >= Kq;
         if (ok) a.cav[(size_t)slot * a.cavcap] = L;
         s_ext[g] = DONE;
         s_abort[g] = ok ? 0u : 1u;
@@ -748,13 +755,13 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
         const uint32_t h = flo + it / (D + 1);
         const int i = (int)(it % (D + 1));
         const uint32_t c = h < a.cavcap ? la[h] : lb[h - a.cavcap];
-        const uint32_t t = vat(a.cn[c], i) >> 2;
+        const uint32_t t = vat(a.cells[c].n, i) >> 2;
         if (t >= a.cap) {
           atomicOr(&a.ctr->flags, FAIL_INVARIANT);
           s_abort[g] = 1;
           break;
         }
-        const uint4 tv = a.cv[t];
+        const uint4 tv = a.cells[t].v;
         bool badv = false;
 #pragma unroll
         for (int r = 0; r <= D; r++)
@@ -764,19 +771,19 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
           s_abort[g] = 1;
           break;
         }
-        const unsigned long long cc = __atomic_load_n(&a.ccav[t], __ATOMIC_RELAXED);
+        const unsigned long long cc = __atomic_load_n(&a.cells[t].cav, __ATOMIC_RELAXED);
         if (cc == K) continue;
         if (cc < K) { s_abort[g] = 1; break; }
-        if (__atomic_load_n(&a.cshell[t], __ATOMIC_RELAXED) == K) continue;
+        if (__atomic_load_n(&a.cells[t].shell, __ATOMIC_RELAXED) == K) continue;
         if (conflict<D, F32>(a, pr, tv, p, qp, qk)) {
-          const unsigned long long old = atomicMin(&a.ccav[t], K);
+          const unsigned long long old = atomicMin(&a.cells[t].cav, K);
           if (old < K) { s_abort[g] = 1; break; }
           if (old == K) continue;
           const uint32_t pos = atomicAdd(&s_n[g], 1u);
           if (pos < a.cavcap) la[pos] = t;
           else lb[pos - a.cavcap] = t;
         } else {
-          atomicMin(&a.cshell[t], K);
+          atomicMin(&a.cells[t].shell, K);
         }
       }
     }
@@ -827,16 +834,16 @@ constexpr uint32_t FTAB = 1024;
 // encoded in inf): its vertices, and its neighbour across facet i, which
 // gets the back link.
 template <int D>
-__device__ __forceinline__ void new_cell_outer(K4Args& a, uint32_t* cnw, uint32_t c, uint32_t inf,
+__device__ __forceinline__ void new_cell_outer(K4Args& a, uint32_t c, uint32_t inf,
                                                int i, uint32_t base, uint32_t p) {
   const uint32_t x = facet_cell(inf, i, base);
-  uint4 nv = a.cv[c];
+  uint4 nv = a.cells[c].v;
   vset(nv, i, p);
-  a.cv[x] = nv;
-  const uint32_t out = vat(a.cn[c], i);
-  cnw[(size_t)x * 4 + i] = out;
-  if (D == 2) cnw[(size_t)x * 4 + 3] = NOSLOT;
-  cnw[(size_t)(out >> 2) * 4 + (out & 3u)] = (x << 2) | (uint32_t)i;
+  init_cell(a.cells[x], nv);
+  const uint32_t out = vat(a.cells[c].n, i);
+  *nslot(a.cells, x, i) = out;
+  if (D == 2) *nslot(a.cells, x, 3) = NOSLOT;
+  *nslot(a.cells, out >> 2, out & 3u) = (x << 2) | (uint32_t)i;
 }
 
 // Neighbour of the new cell on facet i of cavity cell c across its facet
@@ -848,17 +855,17 @@ __device__ __forceinline__ uint32_t new_cell_link(K4Args& a, CavList& cl, uint32
                                                   uint32_t base, unsigned long long K) {
   uint32_t cur = c;
   int sin = i, sout = j;
-  uint4 vcur = a.cv[c];
+  uint4 vcur = a.cells[c].v;
   for (int step = 0; step < 4096; step++) {
-    const uint32_t nbr = vat(a.cn[cur], sout);
+    const uint32_t nbr = vat(a.cells[cur].n, sout);
     const uint32_t ncell = nbr >> 2;
     if (ncell >= a.cap) break;
-    if (a.ccav[ncell] != K) {
-      const uint32_t xp = facet_cell(cl.info(a.cpos[cur]), sout, base);
+    if (a.cells[ncell].cav != K) {
+      const uint32_t xp = facet_cell(cl.info(a.cells[cur].pos), sout, base);
       return (xp << 2) | (uint32_t)sin;
     }
     const uint32_t av = vat(vcur, sin);
-    const uint4 vn = a.cv[ncell];
+    const uint4 vn = a.cells[ncell].v;
     int nout = 0;
 #pragma unroll
     for (int r = 0; r <= D; r++)
@@ -879,7 +886,6 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
   const uint32_t lane = threadIdx.x;
   const uint32_t ncand = min(a.ctr->ncand, a.maxcand);
   uint32_t won = 0;
-  uint32_t* cnw = reinterpret_cast<uint32_t*>(a.cn);
   for (uint32_t slot = blockIdx.x; slot < ncand; slot += gridDim.x) {
     const uint32_t n = a.cand_n[slot];
     if (n == 0) continue;
@@ -896,8 +902,8 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
     __syncthreads();
     for (uint32_t h = lane; h < n; h += 64) {
       const uint32_t c = cl.cell(h);
-      if (a.ccav[c] != K || a.cshell[c] <= K) { s_fail = 1; continue; }
-      const uint4 nb = a.cn[c];
+      if (a.cells[c].cav != K || a.cells[c].shell <= K) { s_fail = 1; continue; }
+      const uint4 nb = a.cells[c].n;
 #pragma unroll
       for (int i = 0; i <= D; i++) {
         const uint32_t t = vat(nb, i) >> 2;
@@ -906,7 +912,7 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
           s_fail = 1;
           break;
         }
-        if (a.ccav[t] < K) s_fail = 1;
+        if (a.cells[t].cav < K) s_fail = 1;
       }
     }
     __syncthreads();
@@ -920,10 +926,10 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
       uint32_t c = 0;
       if (h < n) {
         c = cl.cell(h);
-        const uint4 nb = a.cn[c];
+        const uint4 nb = a.cells[c].n;
 #pragma unroll
         for (int i = 0; i <= D; i++)
-          if (a.ccav[vat(nb, i) >> 2] != K) mask |= 1u << i;
+          if (a.cells[vat(nb, i) >> 2].cav != K) mask |= 1u << i;
       }
       const uint32_t cnt = (uint32_t)__popc(mask);
       uint32_t incl = cnt;
@@ -935,7 +941,7 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
       if (h < n) {
         const uint32_t pre = run + incl - cnt;
         cl.info(h) = (pre << 8) | mask;
-        a.cpos[c] = h;
+        a.cells[c].pos = h;
         uint32_t f = pre;
 #pragma unroll
         for (int i = 0; i <= D; i++)
@@ -972,10 +978,10 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
         const uint32_t c = cl.cell(h);
         const uint32_t inf = cl.info(h);
         const uint32_t x = facet_cell(inf, i, base);
-        if (jj == 0) new_cell_outer<D>(a, cnw, c, inf, i, base, p);
+        if (jj == 0) new_cell_outer<D>(a, c, inf, i, base, p);
         uint32_t link = new_cell_link<D>(a, cl, c, i, j, base, K);
         if (link == 0xFFFFFFFFu) link = (x << 2) | (uint32_t)j;   // in-bounds; the run is abandoned
-        cnw[(size_t)x * 4 + j] = link;
+        *nslot(a.cells, x, j) = link;
       }
     } else {
     // large cavity: one lane per cavity cell builds all its new cells
@@ -984,8 +990,8 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
       const uint32_t inf = cl.info(h);
       const uint32_t mask = inf & 0xFFu;
       if (!mask) continue;
-      const uint4 vc = a.cv[c];
-      const uint4 nc = a.cn[c];
+      const uint4 vc = a.cells[c].v;
+      const uint4 nc = a.cells[c].n;
 #pragma unroll
       for (int i = 0; i <= D; i++) {
         if (!(mask >> i & 1u)) continue;
@@ -995,7 +1001,7 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
         uint4 nn = make_uint4(0, 0, 0, NOSLOT);
         const uint32_t out = vat(nc, i);
         vset(nn, i, out);
-        cnw[(size_t)(out >> 2) * 4 + (out & 3u)] = (x << 2) | (uint32_t)i;
+        *nslot(a.cells, out >> 2, out & 3u) = (x << 2) | (uint32_t)i;
 #pragma unroll
         for (int j = 0; j <= D; j++) {
           if (j == i) continue;
@@ -1004,16 +1010,16 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
           uint4 vcur = vc;
           uint32_t link = 0xFFFFFFFFu;
           for (int step = 0; step < 4096; step++) {
-            const uint32_t nbr = vat(a.cn[cur], sout);
+            const uint32_t nbr = vat(a.cells[cur].n, sout);
             const uint32_t ncell = nbr >> 2;
             if (ncell >= a.cap) break;
-            if (a.ccav[ncell] != K) {
-              const uint32_t xp = facet_cell(cl.info(a.cpos[cur]), sout, base);
+            if (a.cells[ncell].cav != K) {
+              const uint32_t xp = facet_cell(cl.info(a.cells[cur].pos), sout, base);
               link = (xp << 2) | (uint32_t)sin;
               break;
             }
             const uint32_t av = vat(vcur, sin);
-            const uint4 vn = a.cv[ncell];
+            const uint4 vn = a.cells[ncell].v;
             int nout = 0;
 #pragma unroll
             for (int r = 0; r <= D; r++)
@@ -1029,12 +1035,12 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
           }
           vset(nn, j, link);
         }
-        a.cv[x] = nv;
-        a.cn[x] = nn;
+        init_cell(a.cells[x], nv);
+        a.cells[x].n = nn;
       }
     }
     }
-    for (uint32_t h = lane; h < n; h += 64) a.cfwd[cl.cell(h)] = base;
+    for (uint32_t h = lane; h < n; h += 64) a.cells[cl.cell(h)].fwd = base;
     if (lane == 0) {
       a.ploc[p] = DONE;
       won++;
@@ -1049,11 +1055,11 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
 // cells, optionally also per set), a scan of the block counts, and a
 // writing pass that puts each block's rows at its offset.
 template <int D>
-__device__ __forceinline__ bool finite_live_cell(const uint4* cv, const uint32_t* cfwd,
+__device__ __forceinline__ bool finite_live_cell(const Cell* cells,
                                                  uint32_t ncells, uint32_t c, uint4& v) {
   v = make_uint4(0, 0, 0, 0);
-  if (c >= ncells || cfwd[c] != ALIVE) return false;
-  v = cv[c];
+  if (c >= ncells || cells[c].fwd != ALIVE) return false;
+  v = cells[c].v;
 #pragma unroll
   for (int i = 0; i <= D; i++)
     if (vat(v, i) == INF_V) return false;
@@ -1061,10 +1067,10 @@ __device__ __forceinline__ bool finite_live_cell(const uint4* cv, const uint32_t
 }
 
 template <int D>
-__global__ void k4_count_rows(const uint32_t* pset, const uint4* cv, const uint32_t* cfwd,
+__global__ void k4_count_rows(const uint32_t* pset, const Cell* cells,
                               uint32_t ncells, uint32_t* bcnt, uint32_t* set_rows) {
   uint4 v;
-  const bool take = finite_live_cell<D>(cv, cfwd, ncells, blockIdx.x * BLOCK + threadIdx.x, v);
+  const bool take = finite_live_cell<D>(cells, ncells, blockIdx.x * BLOCK + threadIdx.x, v);
   if (take && set_rows) atomicAdd(&set_rows[pset[v.x]], 1u);
   uint32_t tot;
   block_exclusive<BLOCK>(take ? 1u : 0u, &tot);
@@ -1072,10 +1078,10 @@ __global__ void k4_count_rows(const uint32_t* pset, const uint4* cv, const uint3
 }
 
 template <int D>
-__global__ void k4_write_rows(const double4* pts, const uint4* cv, const uint32_t* cfwd,
+__global__ void k4_write_rows(const double4* pts, const Cell* cells,
                               uint32_t ncells, const uint32_t* boff, int32_t* rows) {
   uint4 v;
-  const bool take = finite_live_cell<D>(cv, cfwd, ncells, blockIdx.x * BLOCK + threadIdx.x, v);
+  const bool take = finite_live_cell<D>(cells, ncells, blockIdx.x * BLOCK + threadIdx.x, v);
   uint32_t tot;
   const uint32_t pre = block_exclusive<BLOCK>(take ? 1u : 0u, &tot);
   if (!take) return;
@@ -1092,6 +1098,15 @@ __global__ void k4_write_rows(const double4* pts, const uint4* cv, const uint32_
   for (int i = 0; i <= D; i++) rows[slot * (D + 1) + i] = k[i];
 }
 
+// Clear the cavity and shell claims of the cells in use (the round stamp
+// of the claim keys wraps every 4096 rounds).
+__global__ void k4_reset_claims(Cell* cells, uint32_t used) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= used) return;
+  cells[c].cav = NOKEY;
+  cells[c].shell = NOKEY;
+}
+
 // ------------------------------------------------------------ host driver
 static inline uint32_t nblk(uint32_t n) { return (n + BLOCK - 1) / BLOCK; }
 
@@ -1104,18 +1119,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   if (cap > 0xF0000000ull / 1) cap = 0xF0000000ull;
   if (cap > (1ull << 30) - 1) cap = (1ull << 30) - 1;   // neighbour encoding uses 30 bits
   pool.cap = (uint32_t)cap;
-  DT_TRY(pool.cv.alloc(cap * sizeof(uint4)));
-  DT_TRY(pool.cn.alloc(cap * sizeof(uint4)));
-  DT_TRY(pool.cfwd.alloc(cap * sizeof(uint32_t)));
-  DT_TRY(pool.ccand.alloc(cap * 8));
-  DT_TRY(pool.ccav.alloc(cap * 8));
-  DT_TRY(pool.cshell.alloc(cap * 8));
-  DT_TRY(pool.cpos.alloc(cap * sizeof(uint32_t)));
+  // every cell is written whole when it is created: no clearing needed
+  DT_TRY(pool.cells.alloc(cap * sizeof(Cell)));
   DT_TRY(pool.set_cell0.alloc((size_t)job.nsets * sizeof(uint32_t)));
-  DT_HIP(hipMemsetAsync(pool.cfwd.p, 0xFF, cap * sizeof(uint32_t), st));
-  DT_HIP(hipMemsetAsync(pool.ccand.p, 0xFF, cap * 8, st));
-  DT_HIP(hipMemsetAsync(pool.ccav.p, 0xFF, cap * 8, st));
-  DT_HIP(hipMemsetAsync(pool.cshell.p, 0xFF, cap * 8, st));
 
   uint32_t cavcap = (D == 2) ? 96 : 192;
   uint32_t maxcand = npts < (1u << 19) ? (npts ? npts : 1) : (1u << 19);
@@ -1139,13 +1145,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.pset = job.pset;
   a.set_off = job.set_off;
   a.ploc = ploc.as<uint32_t>();
-  a.cv = pool.cv.as<uint4>();
-  a.cn = pool.cn.as<uint4>();
-  a.cfwd = pool.cfwd.as<uint32_t>();
-  a.ccand = pool.ccand.as<unsigned long long>();
-  a.ccav = pool.ccav.as<unsigned long long>();
-  a.cshell = pool.cshell.as<unsigned long long>();
-  a.cpos = pool.cpos.as<uint32_t>();
+  a.cells = pool.cells.as<Cell>();
   a.set_cell0 = pool.set_cell0.as<uint32_t>();
   a.cand_pt = cand_pt.as<uint32_t>();
   a.cand_n = cand_n.as<uint32_t>();
@@ -1205,8 +1205,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
         DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
         DT_HIP(hipStreamSynchronize(st));
         size_t used = hctr->cells < pool.cap ? hctr->cells : pool.cap;
-        DT_HIP(hipMemsetAsync(pool.ccav.p, 0xFF, used * 8, st));
-        DT_HIP(hipMemsetAsync(pool.cshell.p, 0xFF, used * 8, st));
+        if (used)
+          hipLaunchKernelGGL(k4_reset_claims, dim3(nblk((uint32_t)used)), dim3(BLOCK), 0, st,
+                             pool.cells.as<Cell>(), (uint32_t)used);
       }
       a.round = round;
       hipLaunchKernelGGL(k4_build_active, dim3(gb), dim3(BLOCK), 0, st, a);
@@ -1277,11 +1278,11 @@ int k4_extract(const LocalJob& job, const CellPool& pool, int32_t* rows, uint32_
   DT_HIP(hipMemsetAsync(bcnt.as<uint32_t>() + nb, 0, 4, st));
   if (job.D == 2)
     hipLaunchKernelGGL(k4_count_rows<2>, dim3(nb), dim3(BLOCK), 0, st, job.pset,
-                       pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                       pool.cells.as<Cell>(), pool.ncells,
                        bcnt.as<uint32_t>(), set_rows);
   else
     hipLaunchKernelGGL(k4_count_rows<3>, dim3(nb), dim3(BLOCK), 0, st, job.pset,
-                       pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                       pool.cells.as<Cell>(), pool.ncells,
                        bcnt.as<uint32_t>(), set_rows);
   DT_HIP(hipGetLastError());
   DT_TRY(exclusive_scan(bcnt.as<uint32_t>(), boff.as<uint32_t>(), nb + 1, st));
@@ -1289,11 +1290,11 @@ int k4_extract(const LocalJob& job, const CellPool& pool, int32_t* rows, uint32_
   if (rows) {
     if (job.D == 2)
       hipLaunchKernelGGL(k4_write_rows<2>, dim3(nb), dim3(BLOCK), 0, st, job.pts,
-                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         pool.cells.as<Cell>(), pool.ncells,
                          boff.as<uint32_t>(), rows);
     else
       hipLaunchKernelGGL(k4_write_rows<3>, dim3(nb), dim3(BLOCK), 0, st, job.pts,
-                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         pool.cells.as<Cell>(), pool.ncells,
                          boff.as<uint32_t>(), rows);
     DT_HIP(hipGetLastError());
   }

@@ -112,13 +112,12 @@ __device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, doub
 }
 
 template <int D>
-__global__ void k_border(const double4* P, const uint32_t* pset, const uint4* cv,
-                         const uint32_t* cfwd, uint32_t ncells, BGrid G, const uint32_t* owner,
+__global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cells, uint32_t ncells, BGrid G, const uint32_t* owner,
                          Region R, uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   bool flag = false, finite = false;
-  if (c < ncells && cfwd[c] == ALIVE) {
-    uint4 v4 = cv[c];
+  if (c < ncells && cells[c].fwd == ALIVE) {
+    uint4 v4 = cells[c].v;
     uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
     bool inf = false;
 #pragma unroll
@@ -277,12 +276,12 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
   DT_PROF_BEGIN(DT_KERN_BORDER, st);
   if (D == 2)
     hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
-                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
+                       job.pset, pool.cells.as<Cell>(), pool.ncells, G,
                        owner.as<uint32_t>(), reg, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>());
   else
     hipLaunchKernelGGL(k_border<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
-                       job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells, G,
+                       job.pset, pool.cells.as<Cell>(), pool.ncells, G,
                        owner.as<uint32_t>(), reg, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>());
   DT_PROF_END(st);
@@ -316,10 +315,10 @@ __device__ __forceinline__ uint32_t hkey(const uint32_t k[4]) {
 }
 
 template <int D>
-__device__ __forceinline__ bool finite_live(const uint4* cv, const uint32_t* cfwd, uint32_t c,
+__device__ __forceinline__ bool finite_live(const Cell* cells, uint32_t c,
                                             uint4& v) {
-  if (cfwd[c] != ALIVE) return false;
-  v = cv[c];
+  if (cells[c].fwd != ALIVE) return false;
+  v = cells[c].v;
   uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int i = 0; i <= D; i++)
@@ -342,13 +341,13 @@ __device__ __forceinline__ void write_row(int32_t* rows, uint32_t slot, const ui
 
 // Local pass 1: count unflagged finite cells; insert flagged ones into B.
 template <int D>
-__global__ void k_merge_mark_local(const double4* P, const uint4* cv, const uint32_t* cfwd,
+__global__ void k_merge_mark_local(const double4* P, const Cell* cells,
                                    uint32_t ncells, const uint8_t* cflag, uint32_t* occ,
                                    uint4* tkeys, uint32_t tmask, uint32_t* bemit,
                                    uint32_t* bfinite, uint32_t* flags) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint4 v;
-  const bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
+  const bool live = c < ncells && finite_live<D>(cells, c, v);
   const bool flagged = live && cflag[c] != 0;
   if (flagged) {
     uint32_t k[4];
@@ -374,12 +373,12 @@ __global__ void k_merge_mark_local(const double4* P, const uint4* cv, const uint
 
 // Local pass 2: write the unflagged finite cells.
 template <int D>
-__global__ void k_merge_write_local(const double4* P, const uint4* cv, const uint32_t* cfwd,
+__global__ void k_merge_write_local(const double4* P, const Cell* cells,
                                     uint32_t ncells, const uint8_t* cflag, const uint32_t* boff,
                                     int32_t* rows) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint4 v;
-  const bool emit = c < ncells && finite_live<D>(cv, cfwd, c, v) && cflag[c] == 0;
+  const bool emit = c < ncells && finite_live<D>(cells, c, v) && cflag[c] == 0;
   uint32_t tot;
   const uint32_t pre = block_exclusive<MB>(emit ? 1u : 0u, &tot);
   if (!emit) return;
@@ -391,7 +390,7 @@ __global__ void k_merge_write_local(const double4* P, const uint4* cv, const uin
 // Border pass 1: a finite cell of T_B is output if it spans several
 // partitions or its vertex set is in B; the decision is kept per cell.
 template <int D>
-__global__ void k_merge_mark_border(const double4* P, const uint4* cv, const uint32_t* cfwd,
+__global__ void k_merge_mark_border(const double4* P, const Cell* cells,
                                     uint32_t ncells, const uint32_t* pid_by_id,
                                     const uint32_t* occ, const uint4* tkeys, uint32_t tmask,
                                     uint8_t* emitf, uint32_t* bemit, uint32_t* bfinite,
@@ -402,7 +401,7 @@ __global__ void k_merge_mark_border(const double4* P, const uint4* cv, const uin
   __syncthreads();
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   uint4 v;
-  const bool live = c < ncells && finite_live<D>(cv, cfwd, c, v);
+  const bool live = c < ncells && finite_live<D>(cells, c, v);
   bool emit = false;
   if (live) {
     uint32_t k[4];
@@ -443,7 +442,7 @@ __global__ void k_merge_mark_border(const double4* P, const uint4* cv, const uin
 
 // Border pass 2: write the kept cells after the local ones.
 template <int D>
-__global__ void k_merge_write_border(const double4* P, const uint4* cv, uint32_t ncells,
+__global__ void k_merge_write_border(const double4* P, const Cell* cells, uint32_t ncells,
                                      const uint8_t* emitf, const uint32_t* boff, uint32_t base,
                                      int32_t* rows) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,7 +451,7 @@ __global__ void k_merge_write_border(const double4* P, const uint4* cv, uint32_t
   const uint32_t pre = block_exclusive<MB>(emit ? 1u : 0u, &tot);
   if (!emit) return;
   uint32_t k[4];
-  sorted_keys(P, cv[c], D, k);
+  sorted_keys(P, cells[c].v, D, k);
   write_row<D>(rows, base + boff[blockIdx.x] + pre, k);
 }
 
@@ -492,25 +491,25 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
   if (pool.ncells) {
     if (D == 2)
       hipLaunchKernelGGL(k_merge_mark_local<2>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         pool.cells.as<Cell>(), pool.ncells,
                          b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
                          lemit.as<uint32_t>(), lfin.as<uint32_t>(), flags.as<uint32_t>());
     else
       hipLaunchKernelGGL(k_merge_mark_local<3>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         pool.cells.as<Cell>(), pool.ncells,
                          b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
                          lemit.as<uint32_t>(), lfin.as<uint32_t>(), flags.as<uint32_t>());
   }
   if (bpool.ncells) {
     if (D == 2)
       hipLaunchKernelGGL(k_merge_mark_border<2>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
-                         bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
+                         bpool.cells.as<Cell>(), bpool.ncells,
                          pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
                          emitf.as<uint8_t>(), bemit.as<uint32_t>(), bfin.as<uint32_t>(),
                          hist.as<unsigned long long>());
     else
       hipLaunchKernelGGL(k_merge_mark_border<3>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
-                         bpool.cv.as<uint4>(), bpool.cfwd.as<uint32_t>(), bpool.ncells,
+                         bpool.cells.as<Cell>(), bpool.ncells,
                          pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
                          emitf.as<uint8_t>(), bemit.as<uint32_t>(), bfin.as<uint32_t>(),
                          hist.as<unsigned long long>());
@@ -532,21 +531,21 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
   if (nl) {
     if (D == 2)
       hipLaunchKernelGGL(k_merge_write_local<2>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         pool.cells.as<Cell>(), pool.ncells,
                          b.cflag.as<uint8_t>(), loff.as<uint32_t>(), rows.as<int32_t>());
     else
       hipLaunchKernelGGL(k_merge_write_local<3>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(), pool.ncells,
+                         pool.cells.as<Cell>(), pool.ncells,
                          b.cflag.as<uint8_t>(), loff.as<uint32_t>(), rows.as<int32_t>());
   }
   if (nb) {
     if (D == 2)
       hipLaunchKernelGGL(k_merge_write_border<2>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
-                         bpool.cv.as<uint4>(), bpool.ncells, emitf.as<uint8_t>(),
+                         bpool.cells.as<Cell>(), bpool.ncells, emitf.as<uint8_t>(),
                          boff.as<uint32_t>(), nl, rows.as<int32_t>());
     else
       hipLaunchKernelGGL(k_merge_write_border<3>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
-                         bpool.cv.as<uint4>(), bpool.ncells, emitf.as<uint8_t>(),
+                         bpool.cells.as<Cell>(), bpool.ncells, emitf.as<uint8_t>(),
                          boff.as<uint32_t>(), nl, rows.as<int32_t>());
   }
   DT_PROF_END(st);

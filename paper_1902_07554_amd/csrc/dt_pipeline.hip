@@ -33,12 +33,11 @@ __global__ void k_set_of_point(const uint32_t* off, uint32_t nsets, uint32_t n, 
 // Write the live finite cells grouped by set: row slot = set_base[s] +
 // cursor[s]++ (order inside a set is unspecified).
 template <int D>
-__global__ void k_extract_grouped(const double4* pts, const uint32_t* pset, const uint4* cv,
-                                  const uint32_t* cfwd, uint32_t ncells, const uint32_t* set_base,
+__global__ void k_extract_grouped(const double4* pts, const uint32_t* pset, const Cell* cells, uint32_t ncells, const uint32_t* set_base,
                                   uint32_t* cursor, int32_t* rows) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells || cfwd[c] != ALIVE) return;
-  uint4 v = cv[c];
+  if (c >= ncells || cells[c].fwd != ALIVE) return;
+  uint4 v = cells[c].v;
   uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int i = 0; i <= D; i++)
@@ -169,12 +168,12 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
     if (pool.ncells) {
       if (D == 2)
         hipLaunchKernelGGL(k_extract_grouped<2>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
-                           job.pts, job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(),
+                           job.pts, job.pset, pool.cells.as<Cell>(),
                            pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
                            r->rows.as<int32_t>());
       else
         hipLaunchKernelGGL(k_extract_grouped<3>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
-                           job.pts, job.pset, pool.cv.as<uint4>(), pool.cfwd.as<uint32_t>(),
+                           job.pts, job.pset, pool.cells.as<Cell>(),
                            pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
                            r->rows.as<int32_t>());
       DT_HIP(hipGetLastError());
