@@ -77,8 +77,8 @@ typedef struct dt_options {
   int profile;       /* 1: time the kernels below with HIP events (dt_stats.kern_*)   */
   /* Launch tunables of the parallel insertion (0 = default; dt_batch_autotune
    * picks them for a batch).  They change timing only, never the result. */
-  int start_active;  /* points per set active in the first level; default 1024      */
-  int grow_div;      /* next level starts when pending < inserted/grow_div; default 2 */
+  int start_active;  /* points per set active in the first level; default 256       */
+  int grow_div;      /* next level starts when pending < inserted/grow_div; default 64 */
   int cand_blocks;   /* cap on wavefronts of the cavity/insert launches; default 16384 */
 } dt_options;
 
@@ -196,8 +196,9 @@ int dt_result_set_offsets(const dt_result* r, int64_t* dst, int64_t cap);
 /*
  * dt_batch_autotune -- pick the launch tunables (dt_options.start_active,
  * grow_div, cand_blocks) for batches like this one.  Times batched runs on
- * every s-th set (about sample_points points in all; <= 0 means 2 Mi),
- * changing one tunable at a time from the defaults, and writes opt (NULL =
+ * every s-th set (about sample_points points in all; <= 0 means 4 Mi),
+ * changing one tunable at a time from the defaults (a trial is the faster
+ * of two runs; a change must gain 3 %), and writes opt (NULL =
  * defaults) with the fastest tunables into *tuned.  The choice is cached
  * per (D, precision, log2 mean set size, log2 set count) for the life of
  * the process; a cached class returns at once.  points / offsets /

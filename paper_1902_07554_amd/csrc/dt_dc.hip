@@ -290,6 +290,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     bjob.pset = bset.as<uint32_t>();
     bjob.set_off = boff.as<uint32_t>();
     bjob.fp32 = o.precision == DT_PREC_FP32;
+    bjob.tune(o);
     K4Stats ks;
     int s = k4_run(bjob, bpool, cx.dc(), cx.hctr, st, ks);
     add_pred(S, ks);

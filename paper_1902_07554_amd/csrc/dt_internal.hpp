@@ -100,8 +100,8 @@ struct LocalJob {
   const uint32_t* set_off = nullptr;  // [nsets+1]
   bool fp32 = false;
   // launch tunables (timing only)
-  uint32_t start_active = 1024;   // active points per set in the first level
-  uint32_t grow_div = 2;          // next level when pending < inserted / grow_div
+  uint32_t start_active = 256;    // active points per set in the first level
+  uint32_t grow_div = 64;         // next level when pending < inserted / grow_div
   uint32_t cand_blocks = 16384;   // cap on cavity/insert wavefronts
   void tune(const dt_options& o) {
     if (o.start_active > 0) start_active = (uint32_t)o.start_active;

@@ -1185,7 +1185,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   uint64_t t0 = ((uint64_t)PMAX * job.start_active * job.nsets) / (npts ? npts : 1);
   uint32_t thresh0 = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
   a.act = actbuf.as<uint32_t>();
-  a.grow_div = job.grow_div ? job.grow_div : 2;
+  a.grow_div = job.grow_div ? job.grow_div : 64;
   hipLaunchKernelGGL(k4_ctl_init, dim3(1), dim3(1), 0, st, a, thresh0);
   // Rounds run back to back in groups; the host reads the control state
   // once per group.  Rounds past the end do nothing (the skip word).
