@@ -67,11 +67,9 @@ struct K4Args {
   uint32_t* extcell;    // [MAXEXT * EXTCAP]
   uint32_t* extinfo;
   Counters* ctr;
-  // striped statistics (many blocks add to them at once; 64 copies keep the
-  // atomics from serialising on one address): predicate counts
-  // [NSTRIPE][4][4] and pending points [NSTRIPE]
-  unsigned long long* pstripe;
-  uint32_t* pend;
+  // striped statistics (many blocks add to them at once; NSTRIPE copies
+  // keep the atomics from serialising on one address)
+  struct Stripes* sx;
   uint32_t npts;
   uint32_t nsets;
   uint32_t cap;
@@ -88,6 +86,13 @@ struct K4Args {
 // chunks taken from a small pool (reset every round).
 constexpr uint32_t MAXEXT = 256;
 constexpr uint32_t NSTRIPE = 64;
+struct Stripes {
+  unsigned long long pred[NSTRIPE][16];   // [orient2, orient3, in2, in3][calls, fp32, fp64, exact]
+  unsigned long long cavcells[NSTRIPE];   // cells placed in cavities
+  uint32_t pend[NSTRIPE];                 // pending points this round
+  uint32_t ins[NSTRIPE];                  // points inserted this round
+  uint32_t maxcav[NSTRIPE];               // largest cavity
+};
 constexpr uint32_t EXTCAP = 8192;
 
 struct CavList {
@@ -201,13 +206,13 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 
 // Predicate counters, flushed once per wave at kernel end.
 template <int D>
-__device__ __forceinline__ void flush_pred(unsigned long long* pstripe, const PredStats& s) {
+__device__ __forceinline__ void flush_pred(Stripes* sx, const PredStats& s) {
   const int io = (D == 2) ? 0 : 1, ii = (D == 2) ? 2 : 3;
   uint32_t v[6] = {s.calls[0], s.f32ok[0], s.exact[0], s.calls[1], s.f32ok[1], s.exact[1]};
 #pragma unroll
   for (int j = 0; j < 6; j++) v[j] = wave_sum(v[j]);
   if (lane_id() == 0) {
-    unsigned long long* st = pstripe + (size_t)(blockIdx.x % NSTRIPE) * 16;
+    unsigned long long* st = sx->pred[blockIdx.x % NSTRIPE];
     if (v[0]) {
       atomicAdd(&st[io * 4 + 0], (unsigned long long)v[0]);
       atomicAdd(&st[io * 4 + 1], (unsigned long long)v[1]);
@@ -489,12 +494,25 @@ __global__ void k4_place_init(K4Args a) {
 __global__ void k4_build_active(K4Args a) {
   if (!a.ctr->rebuild || a.ctr->skip) return;
   const uint32_t thresh = a.ctr->thresh;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < a.npts; base += stride) {
-    uint32_t p = base + threadIdx.x;
-    bool take = p < a.npts && a.ploc[p] != DONE && prio_of(p) < thresh;
-    uint32_t slot = wave_alloc(take, &a.ctr->nact);
-    if (take) a.act[slot] = p;
+  // a contiguous chunk per block: count, one allocation, then write in order
+  const uint32_t chunk = ((a.npts + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
+  const uint32_t lo = blockIdx.x * chunk;
+  const uint32_t hi = min(a.npts, lo + chunk);
+  uint32_t mine = 0;
+  for (uint32_t p = lo + threadIdx.x; p < hi; p += BLOCK)
+    mine += (a.ploc[p] != DONE && prio_of(p) < thresh) ? 1u : 0u;
+  __shared__ uint32_t s_base;
+  uint32_t tot;
+  block_exclusive<BLOCK>(mine, &tot);
+  if (threadIdx.x == 0) s_base = tot ? atomicAdd(&a.ctr->nact, tot) : 0u;
+  __syncthreads();
+  uint32_t run = s_base;
+  for (uint32_t b = lo; b < hi; b += BLOCK) {
+    const uint32_t p = b + threadIdx.x;
+    const bool take = p < hi && a.ploc[p] != DONE && prio_of(p) < thresh;
+    const uint32_t pre = block_exclusive<BLOCK>(take ? 1u : 0u, &tot);
+    if (take) a.act[run + pre] = p;
+    run += tot;
   }
 }
 
@@ -510,7 +528,7 @@ __global__ void k4_ctl_init(K4Args a, uint32_t thresh0) {
   c->rounds = 0;
   c->skip = (c->active == 0 || c->flags) ? 1u : 0u;
   c->ncand = c->inserted = c->overflow = c->extused = c->pending = 0;
-  for (uint32_t i = 0; i < NSTRIPE; i++) a.pend[i] = 0;
+  for (uint32_t i = 0; i < NSTRIPE; i++) a.sx->pend[i] = a.sx->ins[i] = 0;
   c->rebuild = 1;
   c->nact = 0;
   c->built_thresh = thresh0;
@@ -523,12 +541,14 @@ __global__ void k4_ctl_end(K4Args a) {
   Counters* c = a.ctr;
   if (c->skip) return;
   const uint32_t PMAX = 1u << 20;
-  const uint32_t ins = c->inserted;
-  uint32_t pending = 0;
+  uint32_t pending = 0, ins = 0;
   for (uint32_t i = 0; i < NSTRIPE; i++) {
-    pending += a.pend[i];
-    a.pend[i] = 0;
+    pending += a.sx->pend[i];
+    ins += a.sx->ins[i];
+    a.sx->pend[i] = 0;
+    a.sx->ins[i] = 0;
   }
+  c->inserted = ins;
   c->pending = pending;
   c->rounds++;
   c->cand_total += c->ncand;
@@ -595,8 +615,8 @@ __global__ void k4_pick(K4Args a) {
     }
   }
   uint32_t c = wave_sum(npend);
-  if (lane_id() == 0 && c) atomicAdd(&a.pend[blockIdx.x % NSTRIPE], c);
-  flush_pred<D>(a.pstripe, pr.st);
+  if (lane_id() == 0 && c) atomicAdd(&a.sx->pend[blockIdx.x % NSTRIPE], c);
+  flush_pred<D>(a.sx, pr.st);
 }
 
 // Candidate selection (one thread per active point): a located point
@@ -640,7 +660,14 @@ __global__ void k4_select(K4Args a) {
       }
     }
   }
-  uint32_t slot = wave_alloc(want, &a.ctr->ncand);
+  // one allocation per block and iteration
+  __shared__ uint32_t s_base;
+  uint32_t tot;
+  const uint32_t pre = block_exclusive<BLOCK>(want ? 1u : 0u, &tot);
+  if (threadIdx.x == 0) s_base = tot ? atomicAdd(&a.ctr->ncand, tot) : 0u;
+  __syncthreads();
+  const uint32_t slot = s_base + pre;
+  __syncthreads();
   if (want && slot < a.maxcand) {
     a.cand_pt[slot] = p;
     // Claim the candidate's own cell now: it lies in the candidate's
@@ -805,10 +832,10 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
   }
   if (gl == 0) {
     if (gave) atomicAdd(&a.ctr->overflow, gave);
-    if (mx) atomicMax(&a.ctr->maxcav, mx);
-    if (cells) atomicAdd(&a.ctr->cavcells, cells);
+    if (mx) atomicMax(&a.sx->maxcav[blockIdx.x % NSTRIPE], mx);
+    if (cells) atomicAdd(&a.sx->cavcells[blockIdx.x % NSTRIPE], cells);
   }
-  flush_pred<D>(a.pstripe, pr.st);
+  flush_pred<D>(a.sx, pr.st);
 }
 
 // New cell index of boundary facet (cavity position h, facet f).
@@ -1047,7 +1074,7 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
     }
     __syncthreads();
   }
-  if (lane == 0 && won) atomicAdd(&a.ctr->inserted, won);
+  if (lane == 0 && won) atomicAdd(&a.sx->ins[blockIdx.x % NSTRIPE], won);
 }
 
 // ------------------------------------------------------------ extraction
@@ -1126,8 +1153,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   uint32_t cavcap = (D == 2) ? 96 : 192;
   uint32_t maxcand = npts < (1u << 19) ? (npts ? npts : 1) : (1u << 19);
   DevBuf ploc, cand_pt, cand_n, cav, cavinfo, cand_ext, extcell, extinfo, actbuf, stripes;
-  DT_TRY(stripes.alloc((size_t)NSTRIPE * 16 * 8 + NSTRIPE * 4));
-  DT_HIP(hipMemsetAsync(stripes.p, 0, (size_t)NSTRIPE * 16 * 8 + NSTRIPE * 4, st));
+  DT_TRY(stripes.alloc(sizeof(Stripes)));
+  DT_HIP(hipMemsetAsync(stripes.p, 0, sizeof(Stripes), st));
   DT_TRY(actbuf.alloc((size_t)(npts ? npts : 1) * 4));
   DT_TRY(cand_ext.alloc((size_t)maxcand * 4));
   DT_TRY(extcell.alloc((size_t)MAXEXT * EXTCAP * 4));
@@ -1155,8 +1182,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.extcell = extcell.as<uint32_t>();
   a.extinfo = extinfo.as<uint32_t>();
   a.ctr = dctr;
-  a.pstripe = stripes.as<unsigned long long>();
-  a.pend = reinterpret_cast<uint32_t*>(stripes.as<unsigned long long>() + NSTRIPE * 16);
+  a.sx = stripes.as<Stripes>();
   a.npts = npts;
   a.nsets = job.nsets;
   a.cap = pool.cap;
@@ -1248,21 +1274,24 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   }
   ks.rounds = (int)hctr->rounds;
   if (dbg)
-    fprintf(stderr, "[k4] done npts %u sets %u rounds %u candidates %llu cavity cells %llu\n", npts,
-            job.nsets, hctr->rounds, hctr->cand_total, hctr->cavcells);
-  ks.maxcav = hctr->maxcav;
-  ks.cavity_cells = hctr->cavcells;
+    fprintf(stderr, "[k4] done npts %u sets %u rounds %u candidates %llu (%llu)\n", npts,
+            job.nsets, hctr->rounds, hctr->cand_total, 0ull);
   ks.candidates = hctr->cand_total;
   pool.ncells = hctr->cells;
-  for (int i = 0; i < 4; i++)
-    for (int j = 0; j < 4; j++) ks.pred[i][j] = 0;
   {
-    std::vector<unsigned long long> hs((size_t)NSTRIPE * 16);
-    DT_HIP(hipMemcpyAsync(hs.data(), stripes.p, hs.size() * 8, hipMemcpyDeviceToHost, st));
+    Stripes hs;
+    DT_HIP(hipMemcpyAsync(&hs, stripes.p, sizeof(Stripes), hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    for (uint32_t b = 0; b < NSTRIPE; b++)
+    ks.maxcav = 0;
+    ks.cavity_cells = 0;
+    for (int i = 0; i < 4; i++)
+      for (int j = 0; j < 4; j++) ks.pred[i][j] = 0;
+    for (uint32_t b = 0; b < NSTRIPE; b++) {
       for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) ks.pred[i][j] += hs[(size_t)b * 16 + i * 4 + j];
+        for (int j = 0; j < 4; j++) ks.pred[i][j] += hs.pred[b][i * 4 + j];
+      ks.cavity_cells += hs.cavcells[b];
+      if (hs.maxcav[b] > ks.maxcav) ks.maxcav = hs.maxcav[b];
+    }
   }
   return DT_OK;
 }
