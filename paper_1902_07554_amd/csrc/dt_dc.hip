@@ -259,6 +259,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
       reg.start = sgrid.start.as<uint32_t>();
       reg.items = sgrid.items.as<uint32_t>();
       reg.G = sgrid.G;
+      reg.nearest = nearest.as<uint32_t>();
     } else {
       reg.kind = BORDER_BOXES;
       reg.boxes = boxes.as<double>();

@@ -111,6 +111,56 @@ __device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, doub
   return false;
 }
 
+// Lower bound of a point's clearance from the foreign Voronoi cells: with t
+// its own (assigned) sample, the least signed distance of the point from
+// the bisector of t and any foreign sample s, on t's side.  Foreign samples
+// within rho = |x - t| + h / 2 of the point are scanned; any other s is at
+// least (rho - |x - t|) / 2 away from its bisector.  Each bisector distance
+// is 1-Lipschitz in x, so a ball through the point of radius r with
+// clearance above 2 r holds no point of another block.
+template <int D>
+__global__ void k_point_margin(const double4* pts, uint32_t n, const uint32_t* nearest,
+                               Region R, double* margin) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 q = pts[i];
+  const uint32_t id = (uint32_t)__double_as_longlong(q.w);
+  const uint32_t t = nearest[id];
+  const uint32_t me = R.part[t];
+  const double4 tp = R.S[t];
+  const double qz = D == 3 ? q.z : 0.0;
+  const double tx = q.x - tp.x, ty = q.y - tp.y, tz = qz - tp.z;
+  const double dt = tx * tx + ty * ty + tz * tz;
+  const double rt = sqrt(dt);
+  const double rho = rt * (1.0 + 1e-9) + 0.5 * R.G.h;
+  double f = 0.5 * (rho - rt * (1.0 + 1e-9));
+  const double c[3] = {q.x, q.y, qz};
+  int lo[3], hi[3];
+  for (int k = 0; k < 3; k++) {
+    lo[k] = cell_coord(c[k] - rho, R.G.lo[k], R.G.h, R.G.g[k]);
+    hi[k] = cell_coord(c[k] + rho, R.G.lo[k], R.G.h, R.G.g[k]);
+  }
+  for (int z = lo[2]; z <= hi[2]; z++)
+    for (int y = lo[1]; y <= hi[1]; y++)
+      for (int x = lo[0]; x <= hi[0]; x++) {
+        const uint32_t cell = ((uint32_t)z * R.G.g[1] + y) * R.G.g[0] + x;
+        for (uint32_t j = R.start[cell]; j < R.start[cell + 1]; j++) {
+          const uint32_t s = R.items[j];
+          if (R.part[s] == me) continue;
+          const double4 sp = R.S[s];
+          const double ax = q.x - sp.x, ay = q.y - sp.y, az = qz - sp.z;
+          const double ds = ax * ax + ay * ay + az * az;
+          const double ex = sp.x - tp.x, ey = sp.y - tp.y, ez = sp.z - tp.z;
+          const double gap = sqrt(ex * ex + ey * ey + ez * ez);
+          // signed distance from the bisector, less the rounding slack of
+          // the assignment keys (as in region_hit)
+          const double d = (ds - dt - 1e-12 * (ds + dt)) / (2.0 * gap);
+          f = fmin(f, d);
+        }
+      }
+  margin[id] = f;
+}
+
 template <int D>
 __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cells, uint32_t ncells, BGrid G, const uint32_t* owner,
                          Region R, uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb) {
@@ -177,6 +227,12 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
       }
       if (sliver) {
         flag = true;
+      } else if (R.kind == BORDER_VORONOI && R.margin) {
+        // clearance of the vertices first (every vertex lies on the sphere)
+        double m = R.margin[key_of(P, v[0])];
+#pragma unroll
+        for (int i = 1; i <= D; i++) m = fmax(m, R.margin[key_of(P, v[i])]);
+        flag = !(m > 2.0 * r) && region_hit<D>(R, pset[v[0]], ctr, r);
       } else if (R.kind != BORDER_GRID) {
         flag = region_hit<D>(R, pset[v[0]], ctr, r);
       } else {
@@ -263,26 +319,41 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
     total *= (uint64_t)g;
   }
   G.h = h;
-  DevBuf owner, vbflag, nb;
-  DT_TRY(owner.alloc(total * 4));
+  const bool grid = reg.kind == BORDER_GRID;
+  DevBuf owner, vbflag, nb, margin;
+  DT_TRY(owner.alloc(grid ? total * 4 : 16));
   DT_TRY(vbflag.alloc((size_t)n * 4));
   DT_TRY(out.cflag.alloc((size_t)pool.ncells + 1));
   DT_TRY(nb.alloc(8));
-  DT_HIP(hipMemsetAsync(owner.p, 0xFF, total * 4, st));
   DT_HIP(hipMemsetAsync(vbflag.p, 0, (size_t)n * 4, st));
   DT_HIP(hipMemsetAsync(nb.p, 0, 8, st));
-  hipLaunchKernelGGL(k_occupancy, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts, job.pset,
-                     job.npts, G, owner.as<uint32_t>());
+  if (grid) {
+    // occupancy of the grid cells (only the grid primitive uses it)
+    DT_HIP(hipMemsetAsync(owner.p, 0xFF, total * 4, st));
+    hipLaunchKernelGGL(k_occupancy, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts, job.pset,
+                       job.npts, G, owner.as<uint32_t>());
+  }
+  Region R = reg;
   DT_PROF_BEGIN(DT_KERN_BORDER, st);
+  if (reg.kind == BORDER_VORONOI && reg.nearest && job.npts) {
+    DT_TRY(margin.alloc((size_t)n * sizeof(double)));
+    if (D == 2)
+      hipLaunchKernelGGL(k_point_margin<2>, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
+                         job.npts, reg.nearest, reg, margin.as<double>());
+    else
+      hipLaunchKernelGGL(k_point_margin<3>, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
+                         job.npts, reg.nearest, reg, margin.as<double>());
+    R.margin = margin.as<double>();
+  }
   if (D == 2)
     hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cells.as<Cell>(), pool.ncells, G,
-                       owner.as<uint32_t>(), reg, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       owner.as<uint32_t>(), R, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>());
   else
     hipLaunchKernelGGL(k_border<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cells.as<Cell>(), pool.ncells, G,
-                       owner.as<uint32_t>(), reg, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       owner.as<uint32_t>(), R, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>());
   DT_PROF_END(st);
   hipLaunchKernelGGL(k_degenerate_parts, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,

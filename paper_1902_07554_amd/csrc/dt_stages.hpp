@@ -50,6 +50,8 @@ struct Region {
   const uint32_t* items = nullptr;
   Grid G{};
   const double* boxes = nullptr;   // k x 6 (boxes)
+  const uint32_t* nearest = nullptr;  // nearest sample of every point, by id (Voronoi)
+  const double* margin = nullptr;     // filled by border_detect (Voronoi)
 };
 int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, uint32_t n,
                   int D, double cells_target, const double lo[3], const double hi[3],
