@@ -68,6 +68,8 @@ struct Counters {
   unsigned int rounds;            // rounds that did work
   unsigned int pad2;
   unsigned long long cand_total;  // candidates over all rounds
+  unsigned int last_ins;          // inserted in the last round (diagnostics)
+  unsigned int last_cand;         // candidates in the last round (diagnostics)
 };
 
 }  // namespace dtk

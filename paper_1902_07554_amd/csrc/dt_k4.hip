@@ -79,6 +79,7 @@ struct K4Args {
   uint32_t* act;        // active point list (a superset of the pending points);
                         // its length and the level's threshold live in ctr
   uint32_t grow_div;
+  uint32_t rings;       // bid rings checked by the selection (0, 1 or 2)
   int fp32;
 };
 
@@ -552,6 +553,8 @@ __global__ void k4_ctl_end(K4Args a) {
   c->pending = pending;
   c->rounds++;
   c->cand_total += c->ncand;
+  c->last_ins = ins;
+  c->last_cand = c->ncand;
   c->remaining -= ins;
   c->done += ins;
   c->ins_since += ins;
@@ -639,7 +642,7 @@ __global__ void k4_select(K4Args a) {
       const uint32_t L = raw & LOCMASK;
       const unsigned long long K = bid_key(p);
       want = (a.cells[L].cand == K);
-      if (want) {
+      if (want && a.rings > 0) {
         uint4 nb = a.cells[L].n;
 #pragma unroll
         for (int i = 0; i <= D; i++)
@@ -648,7 +651,7 @@ __global__ void k4_select(K4Args a) {
         // cell next to this cavity.  Skipping such candidates now (they
         // would lose) saves their searches; the smallest bid of all is
         // never skipped, so every round still inserts a point.
-        if (want) {
+        if (want && a.rings > 1) {
 #pragma unroll
           for (int i = 0; i <= D && want; i++) {
             uint4 nb2 = a.cells[vat(nb, i) >> 2].n;
@@ -1212,6 +1215,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   uint32_t thresh0 = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
   a.act = actbuf.as<uint32_t>();
   a.grow_div = job.grow_div ? job.grow_div : 64;
+  a.rings = 2;   // two rings filter best on clustered and uniform 3D input
   hipLaunchKernelGGL(k4_ctl_init, dim3(1), dim3(1), 0, st, a, thresh0);
   // Rounds run back to back in groups; the host reads the control state
   // once per group.  Rounds past the end do nothing (the skip word).
@@ -1221,7 +1225,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   const uint32_t gi = (uint32_t)(cbound < job.cand_blocks ? cbound : job.cand_blocks);
   // the cavity search runs CAV_GROUPS candidates per block
   const uint32_t gc = (gi + CAV_GROUPS - 1) / CAV_GROUPS;
-  uint32_t round = 1, group = 4;
+  // DT_DEBUG=2: one round per group, traced
+  const bool trace = dbg && getenv("DT_DEBUG")[0] == '2';
+  uint32_t round = 1, group = trace ? 1 : 4;
   for (;;) {
     for (uint32_t r = 0; r < group; r++, round++) {
       if (round >= (1u << 30)) return DT_E_INTERNAL;
@@ -1269,8 +1275,11 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
               round - 1, hctr->rounds, hctr->thresh, hctr->nact, hctr->remaining, hctr->cells,
               hctr->maxcav, hctr->flags);
     if (hctr->flags) { ks.rounds = (int)hctr->rounds; return DT_E_INTERNAL; }
+    if (trace)
+      fprintf(stderr, "[k4r] %u %u %u %u %u\n", hctr->rounds, hctr->thresh, hctr->nact,
+              hctr->last_cand, hctr->last_ins);
     if (hctr->skip) break;
-    if (group < 32) group *= 2;
+    if (group < 32 && !trace) group *= 2;
   }
   ks.rounds = (int)hctr->rounds;
   if (dbg)
