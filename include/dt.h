@@ -59,9 +59,14 @@ enum { DT_DIVIDE_SAMPLE = 0, DT_DIVIDE_KD = 1 };
 enum { DT_WEIGHT_LOG = 0, DT_WEIGHT_CONST = 1, DT_WEIGHT_INVERSE = 2, DT_WEIGHT_LINEAR = 3 };
 /* Predicate precision: FP64 filter -> exact, or FP32 filter -> FP64 -> exact. */
 enum { DT_PREC_FP64 = 0, DT_PREC_FP32 = 1 };
-/* Border primitive (Algorithm 1, intersection test): the exact regions of
- * the divide (sample Voronoi cells / kd boxes), or the paper's grid test. */
-enum { DT_BORDER_REGION = 0, DT_BORDER_GRID = 1 };
+/* Border primitive (Algorithm 1, intersection test; Section "Geometric
+ * Primitives"): the exact regions of the divide (sample Voronoi cells / kd
+ * boxes); the paper's grid test (cells of edge grid_cell * (V/n)^(1/D)
+ * occupied by another partition); the bounding-box test (the ball meets
+ * another partition's bounding box); the exact test (a point of another
+ * partition lies inside the circumsphere, decided with the exact perturbed
+ * in-sphere predicate on the points of the grid cells the ball covers). */
+enum { DT_BORDER_REGION = 0, DT_BORDER_GRID = 1, DT_BORDER_BBOX = 2, DT_BORDER_EXACT = 3 };
 
 typedef struct dt_options {
   int divide;        /* DT_DIVIDE_SAMPLE (Algorithm 2) or DT_DIVIDE_KD (cyclic median) */

@@ -264,6 +264,10 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
       reg.kind = BORDER_BOXES;
       reg.boxes = boxes.as<double>();
     }
+  } else if (o.border == DT_BORDER_BBOX) {
+    reg.kind = BORDER_BBOX;
+  } else if (o.border == DT_BORDER_EXACT) {
+    reg.kind = BORDER_EXACT;
   }
   DT_TRY(border_detect(job, pool, reg, n, D, cells, lo, hi, bo, st));
   double tg = now_ms();

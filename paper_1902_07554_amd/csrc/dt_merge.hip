@@ -25,6 +25,7 @@
 #include "dt_block.hpp"
 #include "dt_common.hpp"
 #include "dt_internal.hpp"
+#include "dt_pred.hpp"
 #include "dt_prims.hpp"
 #include "dt_stages.hpp"
 
@@ -111,6 +112,108 @@ __device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, doub
   return false;
 }
 
+// Bounding box of every partition (one block per partition; the job's
+// points are grouped by partition).
+__global__ void k_part_boxes(const double4* pts, const uint32_t* set_off, double* boxes) {
+  __shared__ double s_v[6][MB];
+  const uint32_t s = blockIdx.x, lo = set_off[s], hi = set_off[s + 1];
+  double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const double4 q = pts[i];
+    v[0] = fmin(v[0], q.x); v[1] = fmin(v[1], q.y); v[2] = fmin(v[2], q.z);
+    v[3] = fmax(v[3], q.x); v[4] = fmax(v[4], q.y); v[5] = fmax(v[5], q.z);
+  }
+  for (int k = 0; k < 6; k++) s_v[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (uint32_t w = MB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 6; k++)
+        s_v[k][threadIdx.x] = k < 3 ? fmin(s_v[k][threadIdx.x], s_v[k][threadIdx.x + w])
+                                    : fmax(s_v[k][threadIdx.x], s_v[k][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) boxes[(size_t)s * 6 + threadIdx.x] = s_v[threadIdx.x][0];
+}
+
+__device__ __forceinline__ uint32_t grid_cell_of(const double4& p, const BGrid& G) {
+  return ((uint32_t)bcoord(p.z, G, 2) * G.g[1] + bcoord(p.y, G, 1)) * G.g[0] + bcoord(p.x, G, 0);
+}
+
+// Points listed by grid cell (counting sort: count, scan, fill).
+__global__ void k_cell_count(const double4* pts, uint32_t n, BGrid G, uint32_t* cnt) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[grid_cell_of(pts[i], G)], 1u);
+}
+__global__ void k_cell_fill(const double4* pts, uint32_t n, BGrid G, const uint32_t* start,
+                            uint32_t* cur, uint32_t* items) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t c = grid_cell_of(pts[i], G);
+  items[start[c] + atomicAdd(&cur[c], 1u)] = i;
+}
+
+// Exact test: is a point of another partition strictly inside the
+// circumsphere of the (positively oriented) finite cell v, under the same
+// perturbed in-sphere predicate as the triangulations?  The grid cells
+// covering the inflated ball hold every such point.
+template <int D>
+__device__ bool exact_hit(const double4* P, const uint32_t* pset, const uint32_t* v, uint32_t me,
+                          const double* ctr, double r, const BGrid& G, const Region& R,
+                          uint32_t* flags) {
+  int lo[3], hi[3];
+  long ncover = 1;
+  for (int k = 0; k < 3; k++) {
+    if (k < D) {
+      lo[k] = bcoord(ctr[k] - r, G, k);
+      hi[k] = bcoord(ctr[k] + r, G, k);
+    } else {
+      lo[k] = hi[k] = 0;
+    }
+    ncover *= (hi[k] - lo[k] + 1);
+  }
+  if (ncover > 4096) return true;
+  PredT<false> pr;
+  pr.init(flags);
+  PtsX X;
+  for (int i = 0; i <= D; i++) {
+    const double4 a = P[v[i]];
+    X.p[i][0] = a.x; X.p[i][1] = a.y; X.p[i][2] = a.z;
+    X.key[i] = (unsigned long long)__double_as_longlong(a.w);
+  }
+  for (int z = lo[2]; z <= hi[2]; z++)
+    for (int y = lo[1]; y <= hi[1]; y++)
+      for (int x = lo[0]; x <= hi[0]; x++) {
+        const uint32_t cell = ((uint32_t)z * G.g[1] + y) * G.g[0] + x;
+        for (uint32_t j = R.cstart[cell]; j < R.cstart[cell + 1]; j++) {
+          const uint32_t q = R.citems[j];
+          if (pset[q] == me) continue;
+          const double4 b = P[q];
+          X.p[D + 1][0] = b.x; X.p[D + 1][1] = b.y; X.p[D + 1][2] = b.z;
+          X.key[D + 1] = (unsigned long long)__double_as_longlong(b.w);
+          if (pr.template insphere<D>(X) > 0) return true;
+        }
+      }
+  return false;
+}
+
+// Bounding-box test: does the ball meet the box of another partition?
+template <int D>
+__device__ bool bbox_hit(const Region& R, uint32_t me, const double* ctr, double r) {
+  const double r2 = r * r;
+  for (uint32_t j = 0; j < R.nparts; j++) {
+    if (j == me) continue;
+    const double* b = R.pboxes + (size_t)j * 6;
+    if (!(b[0] <= b[3])) continue;   // empty partition
+    double d2 = 0.0;
+    for (int k = 0; k < D; k++) {
+      const double t = ctr[k] < b[k] ? b[k] - ctr[k] : (ctr[k] > b[3 + k] ? ctr[k] - b[3 + k] : 0.0);
+      d2 += t * t;
+    }
+    if (d2 <= r2) return true;
+  }
+  return false;
+}
+
 // Lower bound of a point's clearance from the foreign Voronoi cells: with t
 // its own (assigned) sample, the least signed distance of the point from
 // the bisector of t and any foreign sample s, on t's side.  Foreign samples
@@ -162,8 +265,10 @@ __global__ void k_point_margin(const double4* pts, uint32_t n, const uint32_t* n
 }
 
 template <int D>
-__global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cells, uint32_t ncells, BGrid G, const uint32_t* owner,
-                         Region R, uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb) {
+__global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cells,
+                         uint32_t ncells, BGrid G, const uint32_t* owner, Region R,
+                         uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb,
+                         uint32_t* flags) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   bool flag = false, finite = false;
   if (c < ncells && cells[c].fwd == ALIVE) {
@@ -233,6 +338,10 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
 #pragma unroll
         for (int i = 1; i <= D; i++) m = fmax(m, R.margin[key_of(P, v[i])]);
         flag = !(m > 2.0 * r) && region_hit<D>(R, pset[v[0]], ctr, r);
+      } else if (R.kind == BORDER_BBOX) {
+        flag = bbox_hit<D>(R, pset[v[0]], ctr, r);
+      } else if (R.kind == BORDER_EXACT) {
+        flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
       } else if (R.kind != BORDER_GRID) {
         flag = region_hit<D>(R, pset[v[0]], ctr, r);
       } else {
@@ -334,6 +443,32 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
                        job.npts, G, owner.as<uint32_t>());
   }
   Region R = reg;
+  DevBuf pflags, pboxes, cstart, ccount, ccur, citems;
+  DT_TRY(pflags.alloc(4));
+  DT_HIP(hipMemsetAsync(pflags.p, 0, 4, st));
+  if (reg.kind == BORDER_BBOX && job.nsets) {
+    DT_TRY(pboxes.alloc((size_t)job.nsets * 6 * sizeof(double)));
+    hipLaunchKernelGGL(k_part_boxes, dim3(job.nsets), dim3(MB), 0, st, job.pts, job.set_off,
+                       pboxes.as<double>());
+    R.pboxes = pboxes.as<double>();
+    R.nparts = job.nsets;
+  }
+  if (reg.kind == BORDER_EXACT) {
+    // the job's points listed by grid cell
+    DT_TRY(ccount.alloc((total + 1) * 4));
+    DT_TRY(cstart.alloc((total + 1) * 4));
+    DT_TRY(ccur.alloc(total * 4));
+    DT_TRY(citems.alloc((size_t)(job.npts ? job.npts : 1) * 4));
+    DT_HIP(hipMemsetAsync(ccount.p, 0, (total + 1) * 4, st));
+    DT_HIP(hipMemsetAsync(ccur.p, 0, total * 4, st));
+    hipLaunchKernelGGL(k_cell_count, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts, job.npts,
+                       G, ccount.as<uint32_t>());
+    DT_TRY(exclusive_scan(ccount.as<uint32_t>(), cstart.as<uint32_t>(), (uint32_t)total + 1, st));
+    hipLaunchKernelGGL(k_cell_fill, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts, job.npts,
+                       G, cstart.as<uint32_t>(), ccur.as<uint32_t>(), citems.as<uint32_t>());
+    R.cstart = cstart.as<uint32_t>();
+    R.citems = citems.as<uint32_t>();
+  }
   DT_PROF_BEGIN(DT_KERN_BORDER, st);
   if (reg.kind == BORDER_VORONOI && reg.nearest && job.npts) {
     DT_TRY(margin.alloc((size_t)n * sizeof(double)));
@@ -349,19 +484,22 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
     hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cells.as<Cell>(), pool.ncells, G,
                        owner.as<uint32_t>(), R, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
-                       nb.as<unsigned long long>());
+                       nb.as<unsigned long long>(), pflags.as<uint32_t>());
   else
     hipLaunchKernelGGL(k_border<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cells.as<Cell>(), pool.ncells, G,
                        owner.as<uint32_t>(), R, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
-                       nb.as<unsigned long long>());
+                       nb.as<unsigned long long>(), pflags.as<uint32_t>());
   DT_PROF_END(st);
   hipLaunchKernelGGL(k_degenerate_parts, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
                      job.pset, job.npts, pool.set_cell0.as<uint32_t>(), vbflag.as<uint32_t>());
   DT_HIP(hipGetLastError());
   unsigned long long hnb = 0;
+  uint32_t hpf = 0;
   DT_HIP(hipMemcpyAsync(&hnb, nb.p, 8, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipMemcpyAsync(&hpf, pflags.p, 4, hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
+  if (hpf) return DT_E_INTERNAL;   // the exact predicate ran out of expansion capacity
   out.nb_finite = hnb;
   DT_TRY(compact_indices(vbflag.as<uint32_t>(), n, out.vb, &out.nvb, st));
   return DT_OK;

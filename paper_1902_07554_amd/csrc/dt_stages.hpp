@@ -41,7 +41,7 @@ struct BorderOut {
 // How a simplex's circumball is tested against the other partitions:
 // the grid of occupied cells (the paper's grid test), or the exact regions
 // of the divide (sample Voronoi cells, kd boxes).
-enum { BORDER_GRID = 0, BORDER_VORONOI = 1, BORDER_BOXES = 2 };
+enum { BORDER_GRID = 0, BORDER_VORONOI = 1, BORDER_BOXES = 2, BORDER_BBOX = 3, BORDER_EXACT = 4 };
 struct Region {
   int kind = BORDER_GRID;
   const double4* S = nullptr;      // samples (Voronoi)
@@ -52,6 +52,12 @@ struct Region {
   const double* boxes = nullptr;   // k x 6 (boxes)
   const uint32_t* nearest = nullptr;  // nearest sample of every point, by id (Voronoi)
   const double* margin = nullptr;     // filled by border_detect (Voronoi)
+  // filled by border_detect: bounding boxes of the partitions (bbox), and
+  // the points of every grid cell (exact)
+  const double* pboxes = nullptr;     // nparts x 6
+  uint32_t nparts = 0;
+  const uint32_t* cstart = nullptr;   // grid cell c: items[cstart[c] .. cstart[c+1])
+  const uint32_t* citems = nullptr;   // point indices of the job
 };
 int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, uint32_t n,
                   int D, double cells_target, const double lo[3], const double hi[3],

@@ -62,7 +62,8 @@ def _stage_checks(dtlib, p, k, rate, seed, divide, border="region"):
 
 
 @pytest.mark.parametrize("divide,border", [("sample", "region"), ("kd", "region"),
-                                           ("sample", "grid")])
+                                           ("sample", "grid"), ("sample", "bbox"),
+                                           ("sample", "exact"), ("kd", "exact")])
 def test_config_2d_10k(dtlib, divide, border):
     """2D, n = 10,000 uniform, sample 1 % (100 points), k = 4."""
     p = inputs.uniform(10_000, 2, seed=1)
@@ -74,7 +75,8 @@ def test_config_2d_10k(dtlib, divide, border):
     ("sample", "uniform", 16, "region"), ("kd", "uniform", 16, "region"),
     ("sample", "bubbles", 32, "region"), ("kd", "bubbles", 32, "region"),
     ("sample", "normal", 8, "region"), ("sample", "bubbles", 32, "grid"),
-    ("kd", "uniform", 16, "grid")])
+    ("kd", "uniform", 16, "grid"), ("sample", "bubbles", 32, "bbox"),
+    ("sample", "bubbles", 32, "exact"), ("kd", "uniform", 16, "exact")])
 def test_3d_stages(dtlib, divide, dist, k, border):
     p = inputs.make(dist, 20_000, 3, seed=4)
     print(f"[pipeline] 3d 20k {dist} {divide} k={k} border={border}", flush=True)
@@ -123,3 +125,20 @@ def test_small_and_edge_inputs(dtlib):
     with pytest.raises(dtlib.DTError) as e:
         dtlib.triangulate(p, k=40, sample_rate=0.1)   # k > eta
     assert e.value.status == dtlib.DT_E_INVALID_ARG
+
+
+def test_border_primitives_order(dtlib):
+    """Section "Geometric Primitives": the exact test flags the fewest
+    simplices, the bounding-box test the most; every primitive gives the
+    same triangulation."""
+    p = inputs.make("bubbles", 20_000, 3, seed=9)
+    print("[pipeline] border primitives", flush=True)
+    nb, rows = {}, {}
+    for border in ("exact", "region", "grid", "bbox"):
+        res = dtlib.triangulate(p, k=16, sample_rate=0.01, border=border, sort_output=1)
+        nb[border] = res.stats()["border_simplices"]
+        rows[border] = res.rows()
+    for border in ("region", "grid", "bbox"):
+        assert np.array_equal(rows[border], rows["exact"])
+        assert nb["exact"] <= nb[border]
+    assert nb["region"] <= nb["bbox"] and nb["grid"] <= nb["bbox"]
