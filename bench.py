@@ -275,6 +275,45 @@ def bench_serve(args) -> dict:
     }
 
 
+def bench_sweep(args) -> dict:
+    """Primitive, sample-size and weight sweeps (border size vs runtime) on
+    3D bubbles, n = 1,048,576, k = 64, FP32 filter, and the same for the kd
+    divide's primitives."""
+    import torch
+    from paper_1902_07554_amd import binding, inputs
+    n, k = 1_048_576, 64
+    pts = torch.from_numpy(inputs.make("bubbles", n, 3, seed=1)).to("cuda")
+    binding.triangulate(pts, k=k, precision="fp32")
+    rows = []
+
+    def one(**o):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = binding.triangulate(pts, k=k, precision="fp32", **o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) * 1000.0
+        st = r.stats()
+        row = dict(o)
+        row.update(ms=round(dt, 2), eta=st["eta"], border_vertices=st["border_vertices"],
+                   border_simplices=st["border_simplices"], tb_simplices=st["tb_simplices"],
+                   o_dt=round(st["o_dt"], 4), cv=round(st["cv"], 4),
+                   border_ms=round(st["stage_ms"]["border"], 2),
+                   border_dt_ms=round(st["stage_ms"]["border_dt"], 2))
+        rows.append(row)
+
+    for rate in (0.0, 0.005, 0.01, 0.02):
+        for border, cell in (("region", 1.0), ("grid", 0.5), ("grid", 1.0), ("grid", 2.0),
+                             ("bbox", 1.0), ("exact", 1.0)):
+            one(divide="sample", sample_rate=rate, border=border, grid_cell=cell)
+    for w in ("const", "inverse", "linear"):
+        one(divide="sample", sample_rate=0.005, weight=w)
+    for border, cell in (("region", 1.0), ("grid", 1.0), ("bbox", 1.0), ("exact", 1.0)):
+        one(divide="kd", border=border, grid_cell=cell)
+    return {"metric": "border size and runtime by primitive, sample size and weight",
+            "config": {"workload": "bubbles-3d-1M-k64", "n": n, "k": k, "precision": "fp32"},
+            "runs": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,7 +323,7 @@ def main() -> int:
     ap.add_argument("--no-kd", action="store_true", help="skip the kd-divide comparison")
     ap.add_argument("--cpu-sample", type=int, default=1_500_000,
                     help="points of the CPU-oracle baseline sample (0 = skip)")
-    ap.add_argument("--mode", default="dt", choices=["dt", "batch", "serve", "copy"],
+    ap.add_argument("--mode", default="dt", choices=["dt", "batch", "serve", "copy", "sweep"],
                     help="dt: the headline triangulation; batch / serve: the patterns")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
@@ -301,6 +340,9 @@ def main() -> int:
         return 0
     if args.mode == "copy":
         print(json.dumps(bench_copy(args)), flush=True)
+        return 0
+    if args.mode == "sweep":
+        print(json.dumps(bench_sweep(args)), flush=True)
         return 0
 
     import torch

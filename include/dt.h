@@ -53,7 +53,12 @@ enum {
 };
 
 /* ---------------------------------------------------------------- options */
-enum { DT_DIVIDE_SAMPLE = 0, DT_DIVIDE_KD = 1 };
+/* DT_DIVIDE_AUTO draws the sample, then takes the kd divide when the
+ * sample looks evenly spread (coefficient of variation of its counts over a
+ * grid of about eta/4 cells at most DT_AUTO_CV) and k is a power of two,
+ * else the sample divide; dt_stats.divide_used tells which. */
+enum { DT_DIVIDE_SAMPLE = 0, DT_DIVIDE_KD = 1, DT_DIVIDE_AUTO = 2 };
+#define DT_AUTO_CV 1.0
 /* Edge weights of the sample graph, paper Table "weights":
  * d = |v-w| / d*, d* = length of the bounding-box diagonal. */
 enum { DT_WEIGHT_LOG = 0, DT_WEIGHT_CONST = 1, DT_WEIGHT_INVERSE = 2, DT_WEIGHT_LINEAR = 3 };
@@ -121,6 +126,8 @@ typedef struct dt_stats {
   int64_t kern_launches[DT_NUM_KERN]; /* launches per kernel (profile)               */
   int64_t cavity_cells;       /* cells visited by winning and losing cavity searches */
   int64_t candidates;         /* cavity searches (winning and losing) over all rounds   */
+  int64_t divide_used;        /* DT_DIVIDE_SAMPLE or DT_DIVIDE_KD                        */
+  double divide_stat;         /* DT_DIVIDE_AUTO: the sample's grid-count variation       */
 } dt_stats;
 
 typedef struct dt_result dt_result;

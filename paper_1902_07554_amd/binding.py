@@ -19,7 +19,7 @@ _lib = None
 
 DT_OK, DT_E_INVALID_ARG, DT_E_NONFINITE, DT_E_DUPLICATE, DT_E_DEGENERATE = 0, -1, -2, -3, -4
 DT_E_NOMEM, DT_E_DEVICE, DT_E_INTERNAL, DT_E_NOT_READY = -5, -6, -7, -8
-DIVIDE = {"sample": 0, "kd": 1}
+DIVIDE = {"sample": 0, "kd": 1, "auto": 2}
 WEIGHT = {"log": 0, "const": 1, "inverse": 2, "linear": 3}
 PRECISION = {"fp64": 0, "fp32": 1}
 BORDER = {"region": 0, "grid": 1, "bbox": 2, "exact": 3}
@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("pad", ctypes.c_uint32), ("stage_ms", ctypes.c_double * 12),
                 ("probe_hist", ctypes.c_int64 * 16), ("kern_ms", ctypes.c_double * 8),
                 ("kern_launches", ctypes.c_int64 * 8), ("cavity_cells", ctypes.c_int64),
-                ("candidates", ctypes.c_int64)]
+                ("candidates", ctypes.c_int64),
+                ("divide_used", ctypes.c_int64), ("divide_stat", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_

@@ -114,7 +114,7 @@ int sort_rows_inplace(dt_result* r, hipStream_t st) {
 int check_options(const dt_options* in, dt_options& o) {
   dt_default_options(&o);
   if (in) o = *in;
-  if (o.divide != DT_DIVIDE_SAMPLE && o.divide != DT_DIVIDE_KD) return DT_E_INVALID_ARG;
+  if (o.divide < DT_DIVIDE_SAMPLE || o.divide > DT_DIVIDE_AUTO) return DT_E_INVALID_ARG;
   if (o.weight < 0 || o.weight > 3) return DT_E_INVALID_ARG;
   if (o.precision != DT_PREC_FP64 && o.precision != DT_PREC_FP32) return DT_E_INVALID_ARG;
   if (!(o.eps >= 0.0) || !(o.grid_cell > 0.0)) return DT_E_INVALID_ARG;

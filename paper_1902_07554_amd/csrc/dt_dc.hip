@@ -100,6 +100,32 @@ static void add_pred(dt_stats& s, const K4Stats& ks) {
   s.candidates += (int64_t)ks.candidates;
 }
 
+// Coefficient of variation of the sample's counts over a uniform grid of
+// about eta/4 cells spanning the input's box (empty cells included): near
+// 1/2 for an evenly spread sample, far above 1 for a clustered one.
+static double sample_spread(const std::vector<double4>& s, int D, const double lo[3],
+                            const double hi[3]) {
+  const size_t m = s.size();
+  const double target = m / 4.0 > 1.0 ? m / 4.0 : 1.0;
+  int g = (int)floor(pow(target, 1.0 / D));
+  if (g < 1) g = 1;
+  std::vector<uint32_t> cnt((size_t)(D == 3 ? g * g * g : g * g), 0);
+  auto cell = [&](double x, int a) {
+    const double w = hi[a] - lo[a];
+    int c = w > 0 ? (int)((x - lo[a]) / w * g) : 0;
+    return c < 0 ? 0 : (c >= g ? g - 1 : c);
+  };
+  for (const double4& p : s) {
+    size_t c = (size_t)cell(p.x, 0) + (size_t)g * cell(p.y, 1);
+    if (D == 3) c += (size_t)g * g * cell(p.z, 2);
+    cnt[c]++;
+  }
+  const double mean = (double)m / cnt.size();
+  double ss = 0.0;
+  for (uint32_t c : cnt) ss += (c - mean) * (c - mean);
+  return mean > 0 ? sqrt(ss / cnt.size()) / mean : 0.0;
+}
+
 int run_dc(const double* points, int64_t n64, int D, int k, double rate, const dt_options& o,
            bool on_device, hipStream_t st, dt_result* r) {
   double t0 = now_ms();
@@ -109,7 +135,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   S.k = k;
   uint32_t n = (uint32_t)n64;
   uint32_t eta = sample_size(n, rate, D);
-  if (o.divide == DT_DIVIDE_SAMPLE && (uint32_t)k > eta) return DT_E_INVALID_ARG;
+  if (o.divide != DT_DIVIDE_KD && (uint32_t)k > eta) return DT_E_INVALID_ARG;
   if (o.divide == DT_DIVIDE_KD && (k & (k - 1)) != 0) return DT_E_INVALID_ARG;
   if ((uint32_t)k > n) return DT_E_INVALID_ARG;
   Ctx cx;
@@ -138,12 +164,25 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   LocalJob sjob;
   DevBuf sset, soff;
   double cut = 0.0;
-  if (o.divide == DT_DIVIDE_SAMPLE) {
+  int divide = o.divide;
+  if (divide != DT_DIVIDE_KD) {
     DT_TRY(select_sample(n, eta, o.seed, sid, st));
-    double ta = now_ms();
-    S.stage_ms[DT_STAGE_SAMPLE] = ta - t1;
     DT_TRY(Sp.alloc((size_t)eta * sizeof(double4)));
     DT_TRY(gather_points(P.as<double4>(), sid.as<uint32_t>(), eta, Sp.as<double4>(), st));
+  }
+  if (divide == DT_DIVIDE_AUTO) {
+    // how evenly the sample fills its box: counts over a grid of ~eta/4 cells
+    std::vector<double4> hs(eta);
+    DT_HIP(hipMemcpyAsync(hs.data(), Sp.p, (size_t)eta * sizeof(double4), hipMemcpyDeviceToHost,
+                          st));
+    DT_HIP(hipStreamSynchronize(st));
+    S.divide_stat = sample_spread(hs, D, lo, hi);
+    divide = (S.divide_stat <= DT_AUTO_CV && (k & (k - 1)) == 0) ? DT_DIVIDE_KD : DT_DIVIDE_SAMPLE;
+  }
+  S.divide_used = divide;
+  if (divide == DT_DIVIDE_SAMPLE) {
+    double ta = now_ms();
+    S.stage_ms[DT_STAGE_SAMPLE] = ta - t1;
     DT_TRY(sset.alloc((size_t)eta * 4));
     DT_TRY(soff.alloc(8));
     DT_HIP(hipMemsetAsync(sset.p, 0, (size_t)eta * 4, st));
@@ -252,7 +291,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   for (int a = 0; a < D; a++) cells /= o.grid_cell;
   Region reg;
   if (o.border == DT_BORDER_REGION) {
-    if (o.divide == DT_DIVIDE_SAMPLE) {
+    if (divide == DT_DIVIDE_SAMPLE) {
       reg.kind = BORDER_VORONOI;
       reg.S = Sp.as<double4>();
       reg.part = part.as<uint32_t>();
@@ -312,12 +351,12 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   S.stage_ms[DT_STAGE_MERGE] = ti - th;
   S.num_simplices = r->m;
   r->set_offsets = {0, r->m};
-  S.o_dt = ((double)n + (o.divide == DT_DIVIDE_SAMPLE ? eta : 0) + bo.nvb) / (double)n;
+  S.o_dt = ((double)n + (divide == DT_DIVIDE_SAMPLE ? eta : 0) + bo.nvb) / (double)n;
   S.local_simplices = local_finite;
   S.tb_simplices = border_finite;
 
   if (o.keep_stages) {
-    if (o.divide == DT_DIVIDE_SAMPLE) {
+    if (divide == DT_DIVIDE_SAMPLE) {
       std::vector<uint32_t> h(eta);
       DT_HIP(hipMemcpyAsync(h.data(), sid.p, (size_t)eta * 4, hipMemcpyDeviceToHost, st));
       DT_HIP(hipStreamSynchronize(st));

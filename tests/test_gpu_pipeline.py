@@ -142,3 +142,15 @@ def test_border_primitives_order(dtlib):
         assert np.array_equal(rows[border], rows["exact"])
         assert nb["exact"] <= nb[border]
     assert nb["region"] <= nb["bbox"] and nb["grid"] <= nb["bbox"]
+
+
+@pytest.mark.parametrize("dist,want", [("uniform", 1), ("bubbles", 0)])
+def test_auto_divide(dtlib, dist, want):
+    """The adaptive divide picks kd for evenly spread input and the sample
+    divide for clustered input; either way the result is the DT."""
+    p = inputs.make(dist, 30_000, 3, seed=2)
+    print(f"[pipeline] auto divide {dist}", flush=True)
+    res = dtlib.triangulate(p, k=16, sample_rate=0.02, divide="auto", sort_output=1)
+    st = res.stats()
+    assert st["divide_used"] == want, st["divide_stat"]
+    assert np.array_equal(res.rows(), oracle.delaunay(p))
