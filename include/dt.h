@@ -165,6 +165,16 @@ int dt_result_dim(const dt_result* r);
  * capacity `cap_rows` rows).  Returns DT_OK or DT_E_INVALID_ARG. */
 int dt_result_copy(const dt_result* r, int32_t* dst, int64_t cap_rows, int dst_on_device,
                    void* stream);
+/* Neighbours (Algorithm 1, neighbourhood update): m x (D+1) int32 to dst
+ * (device or host memory, capacity cap_rows rows); entry (i, j) is the row
+ * of the simplex that shares the facet of row i opposite its j-th vertex
+ * (rows as dt_result_copy returns them), or -1 on the convex hull.  For a
+ * batch result, rows of different sets are never neighbours.  Computed on
+ * the device at the first call and kept with the result (not safe to call
+ * concurrently on one result).  DT_OK, DT_E_INVALID_ARG, DT_E_NOMEM,
+ * DT_E_DEVICE. */
+int dt_result_neighbors(const dt_result* r, int32_t* dst, int64_t cap_rows, int dst_on_device,
+                        void* stream);
 /* Statistics of the run that produced r. */
 int dt_result_stats(const dt_result* r, dt_stats* st);
 void dt_result_free(dt_result* r);

@@ -73,6 +73,27 @@ class OracleError(RuntimeError):
         self.status = status
 
 
+def neighbors(rows: np.ndarray) -> np.ndarray:
+    """Algorithm 1, neighbourhood update, by its definition: two simplices
+    are neighbours when they share a facet (D of their D+1 vertices).
+    Entry (i, j) is the row sharing the facet of row i opposite its j-th
+    vertex, -1 when no other row has that facet (a convex-hull facet)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    m, w = rows.shape
+    out = np.full((m, w), -1, dtype=np.int64)
+    seen = {}
+    for i in range(m):
+        for j in range(w):
+            f = tuple(sorted(int(rows[i, r]) for r in range(w) if r != j))
+            if f in seen:
+                i2, j2 = seen.pop(f)
+                out[i, j] = i2
+                out[i2, j2] = i
+            else:
+                seen[f] = (i, j)
+    return out
+
+
 def canonical(simplices: np.ndarray) -> np.ndarray:
     """Sort ids inside each row, then rows lexicographically."""
     s = np.sort(np.asarray(simplices, dtype=np.int64), axis=1)

@@ -33,7 +33,7 @@ EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_cou
            "dt_result_dim", "dt_result_copy", "dt_result_stats", "dt_result_free",
            "dt_result_stage", "dt_batch_triangulate", "dt_result_set_offsets",
            "dt_server_create", "dt_server_submit", "dt_server_poll", "dt_server_wait",
-           "dt_server_times", "dt_server_destroy", "dt_batch_autotune"]
+           "dt_server_times", "dt_server_destroy", "dt_batch_autotune", "dt_result_neighbors"]
 
 
 class Options(ctypes.Structure):
@@ -102,6 +102,8 @@ def load():
     lib.dt_result_dim.restype = I
     lib.dt_result_copy.argtypes = [VP, VP, I64, I, VP]
     lib.dt_result_copy.restype = I
+    lib.dt_result_neighbors.argtypes = [VP, VP, I64, I, VP]
+    lib.dt_result_neighbors.restype = I
     lib.dt_result_stats.argtypes = [VP, P(Stats)]
     lib.dt_result_stats.restype = I
     lib.dt_result_free.argtypes = [VP]
@@ -199,6 +201,16 @@ class Result:
         m, d = self.count, self.dim
         out = np.empty((m, d + 1), dtype=np.int32)
         st = load().dt_result_copy(self.h, out.ctypes.data, m, 0, None)
+        if st != DT_OK:
+            raise DTError(st)
+        return out
+
+    def neighbors(self) -> np.ndarray:
+        """dt_result_neighbors: row of the simplex across the facet opposite
+        each vertex, -1 on the hull."""
+        m, d = self.count, self.dim
+        out = np.empty((m, d + 1), dtype=np.int32)
+        st = load().dt_result_neighbors(self.h, out.ctypes.data, m, 0, None)
         if st != DT_OK:
             raise DTError(st)
         return out

@@ -216,6 +216,22 @@ extern "C" int dt_result_copy(const dt_result* r, int32_t* dst, int64_t cap_rows
   return DT_OK;
 }
 
+extern "C" int dt_result_neighbors(const dt_result* r, int32_t* dst, int64_t cap_rows,
+                                   int dst_on_device, void* stream) {
+  if (!r || (!dst && r->m > 0) || cap_rows < r->m) return DT_E_INVALID_ARG;
+  if (r->m == 0) return DT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (!r->nbr_ready) {
+    DT_TRY(compute_neighbors(*r, r->nbr, st));
+    r->nbr_ready = true;
+  }
+  size_t bytes = (size_t)r->m * (r->D + 1) * 4;
+  DT_HIP(hipMemcpyAsync(dst, r->nbr.p, bytes,
+                        dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
 extern "C" int dt_result_stats(const dt_result* r, dt_stats* s) {
   if (!r || !s) return DT_E_INVALID_ARG;
   *s = r->stats;

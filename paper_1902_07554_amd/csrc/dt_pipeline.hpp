@@ -11,6 +11,9 @@ struct dt_result {
   std::vector<int64_t> set_offsets;   // batch results: row offsets per set
   dt_stats stats{};
   std::vector<char> stage[DT_NUM_ARR];
+  // neighbours of every row, computed on the first request
+  mutable dtk::DevBuf nbr;
+  mutable bool nbr_ready = false;
 };
 
 namespace dtk {
@@ -37,5 +40,8 @@ int run_dc(const double* points, int64_t n, int D, int k, double sample_rate,
            const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
 int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, int64_t num_sets,
               int D, const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+// Neighbours of every row of r (m x (D+1) int32: row sharing the facet
+// opposite each vertex, -1 on the hull), within each set.
+int compute_neighbors(const dt_result& r, DevBuf& nbr, hipStream_t st);
 
 }  // namespace dtk

@@ -129,3 +129,31 @@ def test_fp32_filter_matches_oracle(dtlib, dim, n, dist):
     assert ins["calls"] == ins["fp32"] + ins["fp64"] + ins["exact"]
     if dist == "lattice":
         assert ins["exact"] > 0
+
+
+@pytest.mark.parametrize("dim,k", [(2, 1), (3, 1), (3, 8)])
+def test_neighbors_match_oracle(dtlib, dim, k):
+    """dt_result_neighbors equals the facet-sharing definition on the rows
+    the library returns."""
+    p = inputs.make("bubbles" if dim == 3 else "normal", 6000, dim, seed=5)
+    print(f"[neighbors] dim={dim} k={k}", flush=True)
+    res = dtlib.triangulate(p, k=k, sample_rate=0.05, sort_output=1)
+    rows = res.rows()
+    assert np.array_equal(rows, oracle.delaunay(p))
+    assert np.array_equal(res.neighbors(), oracle.neighbors(rows))
+
+
+def test_neighbors_stay_inside_each_set(dtlib):
+    """Batch rows of different sets never pair, even with equal labels."""
+    a = inputs.make("uniform", 400, 2, seed=1)
+    b = inputs.make("normal", 300, 2, seed=2)
+    pts = np.concatenate([a, b])
+    ids = np.concatenate([np.arange(400), np.arange(300)]).astype(np.int64)
+    res = dtlib.batch_triangulate(pts, [0, 400, 700], ids=ids)
+    rows, so, nb = res.rows(), res.set_offsets(2), res.neighbors()
+    for s in range(2):
+        lo, hi = so[s], so[s + 1]
+        want = oracle.neighbors(rows[lo:hi])
+        got = nb[lo:hi].astype(np.int64)
+        got[got >= 0] -= lo
+        assert np.array_equal(got, want)

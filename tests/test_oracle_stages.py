@@ -223,3 +223,28 @@ def test_merge_reproduces_dt_3d():
     parts, flags, vb = _border_sets(p, pid, k, all_hull=True)
     tb = oracle.delaunay(p[vb], vb)
     assert np.array_equal(oracle.merge(parts, flags, tb, pid), oracle.delaunay(p))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_neighbors_pins(dim):
+    """Neighbours of DT(P): symmetric, sharing exactly D vertices; the
+    facets without a neighbour are the convex hull's facets (Qhull)."""
+    from scipy.spatial import ConvexHull
+    p = inputs.uniform(300, dim, seed=6)
+    rows = oracle.delaunay(p)
+    nb = oracle.neighbors(rows)
+    m, w = rows.shape
+    for i in range(m):
+        for j in range(w):
+            k = nb[i, j]
+            if k < 0:
+                continue
+            assert i in nb[k]
+            shared = set(rows[i]) & set(rows[k])
+            assert len(shared) == dim and rows[i, j] not in shared
+    hull = ConvexHull(p)
+    assert (nb < 0).sum() == len(hull.simplices)
+    hull_facets = {tuple(sorted(f)) for f in hull.simplices}
+    got = {tuple(sorted(int(rows[i, r]) for r in range(w) if r != j))
+           for i, j in zip(*np.nonzero(nb < 0))}
+    assert got == hull_facets
