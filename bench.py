@@ -298,7 +298,8 @@ def bench_sweep(args) -> dict:
                    border_simplices=st["border_simplices"], tb_simplices=st["tb_simplices"],
                    o_dt=round(st["o_dt"], 4), cv=round(st["cv"], 4),
                    border_ms=round(st["stage_ms"]["border"], 2),
-                   border_dt_ms=round(st["stage_ms"]["border_dt"], 2))
+                   border_dt_ms=round(st["stage_ms"]["border_dt"], 2),
+                   divide_used=st["divide_used"])
         rows.append(row)
 
     for rate in (0.0, 0.005, 0.01, 0.02):
@@ -309,6 +310,10 @@ def bench_sweep(args) -> dict:
         one(divide="sample", sample_rate=0.005, weight=w)
     for border, cell in (("region", 1.0), ("grid", 1.0), ("bbox", 1.0), ("exact", 1.0)):
         one(divide="kd", border=border, grid_cell=cell)
+    # recursive bisection (log2 k levels, k-1 merges with the grid test)
+    one(divide="kd", recursive=1)
+    one(divide="sample", sample_rate=0.0, recursive=1)
+    one(divide="auto", sample_rate=0.0)
     return {"metric": "border size and runtime by primitive, sample size and weight",
             "config": {"workload": "bubbles-3d-1M-k64", "n": n, "k": k, "precision": "fp32"},
             "runs": rows}

@@ -90,6 +90,12 @@ typedef struct dt_options {
   int start_active;  /* points per set active in the first level; default 256       */
   int grow_div;      /* next level starts when pending < inserted/grow_div; default 64 */
   int cand_blocks;   /* cap on wavefronts of the cavity/insert launches; default 16384 */
+  /* 1: recursive bisection (Section "Recursive Bisection"): log2 k levels of
+   * 2-way division with the chosen divide (kd: cyclic median split; sample:
+   * a new sample per block and level, split at its median), then k-1
+   * merges bottom-up with the grid test; k must be a power of two.
+   * 0 (default): one k-way division and one merge (Algorithm 1). */
+  int recursive;
 } dt_options;
 
 /* Kernels timed when dt_options.profile = 1. */

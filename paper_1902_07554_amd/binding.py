@@ -43,7 +43,7 @@ class Options(ctypes.Structure):
                 ("refine_iters", ctypes.c_int), ("keep_stages", ctypes.c_int),
                 ("border", ctypes.c_int), ("profile", ctypes.c_int),
                 ("start_active", ctypes.c_int), ("grow_div", ctypes.c_int),
-                ("cand_blocks", ctypes.c_int)]
+                ("cand_blocks", ctypes.c_int), ("recursive", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -24,6 +24,7 @@
 
 #include "dt_block.hpp"
 #include "dt_common.hpp"
+#include "dt_geom.hpp"
 #include "dt_internal.hpp"
 #include "dt_pred.hpp"
 #include "dt_prims.hpp"
@@ -36,17 +37,6 @@ static inline uint32_t mblocks(uint64_t n) { return (uint32_t)((n + MB - 1) / MB
 constexpr uint32_t OWN_EMPTY = 0xFFFFFFFFu;
 constexpr uint32_t OWN_MIXED = 0xFFFFFFFEu;
 
-struct BGrid {
-  double lo[3];
-  double h;
-  int g[3];
-};
-
-__device__ __forceinline__ int bcoord(double x, const BGrid& G, int k) {
-  double t = (x - G.lo[k]) / G.h;
-  int c = (int)floor(t);
-  return c < 0 ? 0 : (c >= G.g[k] ? G.g[k] - 1 : c);
-}
 
 __global__ void k_occupancy(const double4* P, const uint32_t* pset, uint32_t n, BGrid G,
                             uint32_t* owner) {
@@ -282,54 +272,8 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
       flag = true;
     } else {
       finite = true;
-      double4 a = P[v[0]];
-      double ctr[3], r;
-      bool sliver = false;
-      if (D == 3) {
-        double4 pb = P[v[1]], pc = P[v[2]], pd = P[v[3]];
-        double b0 = pb.x - a.x, b1 = pb.y - a.y, b2 = pb.z - a.z;
-        double c0 = pc.x - a.x, c1 = pc.y - a.y, c2 = pc.z - a.z;
-        double d0 = pd.x - a.x, d1 = pd.y - a.y, d2 = pd.z - a.z;
-        double cd0 = c1 * d2 - c2 * d1, cd1 = c2 * d0 - c0 * d2, cd2 = c0 * d1 - c1 * d0;
-        double db0 = d1 * b2 - d2 * b1, db1 = d2 * b0 - d0 * b2, db2 = d0 * b1 - d1 * b0;
-        double bc0 = b1 * c2 - b2 * c1, bc1 = b2 * c0 - b0 * c2, bc2 = b0 * c1 - b1 * c0;
-        double det = b0 * cd0 + b1 * cd1 + b2 * cd2;
-        double lb = b0 * b0 + b1 * b1 + b2 * b2, lc = c0 * c0 + c1 * c1 + c2 * c2,
-               ld = d0 * d0 + d1 * d1 + d2 * d2;
-        double scale = sqrt(lb * lc * ld);
-        if (!(fabs(det) > 1e-7 * scale)) {
-          sliver = true;
-        } else {
-          double inv = 0.5 / det;
-          double x = (lb * cd0 + lc * db0 + ld * bc0) * inv;
-          double y = (lb * cd1 + lc * db1 + ld * bc1) * inv;
-          double z = (lb * cd2 + lc * db2 + ld * bc2) * inv;
-          r = sqrt(x * x + y * y + z * z);
-          double L = sqrt(fmax(lb, fmax(lc, ld)));
-          r += 1e-6 * (r + L) + 1e-12 * (fabs(a.x) + fabs(a.y) + fabs(a.z));
-          ctr[0] = a.x + x;
-          ctr[1] = a.y + y;
-          ctr[2] = a.z + z;
-        }
-      } else {
-        double4 pb = P[v[1]], pc = P[v[2]];
-        double b0 = pb.x - a.x, b1 = pb.y - a.y, c0 = pc.x - a.x, c1 = pc.y - a.y;
-        double det = b0 * c1 - b1 * c0;
-        double lb = b0 * b0 + b1 * b1, lc = c0 * c0 + c1 * c1;
-        if (!(fabs(det) > 1e-7 * sqrt(lb * lc))) {
-          sliver = true;
-        } else {
-          double inv = 0.5 / det;
-          double x = (c1 * lb - b1 * lc) * inv;
-          double y = (b0 * lc - c0 * lb) * inv;
-          r = sqrt(x * x + y * y);
-          double L = sqrt(fmax(lb, lc));
-          r += 1e-6 * (r + L) + 1e-12 * (fabs(a.x) + fabs(a.y));
-          ctr[0] = a.x + x;
-          ctr[1] = a.y + y;
-          ctr[2] = 0.0;
-        }
-      }
+      double ctr[3], r = 0.0;
+      const bool sliver = !circumball<D>(P[v[0]], P[v[1]], P[v[2]], P[v[D == 3 ? 3 : 2]], ctr, &r);
       if (sliver) {
         flag = true;
       } else if (R.kind == BORDER_VORONOI && R.margin) {
@@ -409,25 +353,8 @@ __global__ void k_degenerate_parts(const double4* P, const uint32_t* pset, uint3
 int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, uint32_t n,
                   int D, double cells_target, const double lo[3], const double hi[3],
                   BorderOut& out, hipStream_t st) {
-  BGrid G;
-  double vol = 1.0;
-  int nd = 0;
-  for (int a = 0; a < D; a++) {
-    double e = hi[a] - lo[a];
-    if (e > 0) { vol *= e; nd++; }
-  }
-  double h = nd ? pow(vol / (cells_target > 1 ? cells_target : 1.0), 1.0 / nd) : 1.0;
-  if (!(h > 0)) h = 1.0;
   uint64_t total = 1;
-  for (int a = 0; a < 3; a++) {
-    G.lo[a] = lo[a];
-    long g = (a < D) ? (long)floor((hi[a] - lo[a]) / h) + 1 : 1;
-    if (g < 1) g = 1;
-    if (g > 4096) g = 4096;
-    G.g[a] = (int)g;
-    total *= (uint64_t)g;
-  }
-  G.h = h;
+  const BGrid G = make_bgrid(lo, hi, D, cells_target, &total);
   const bool grid = reg.kind == BORDER_GRID;
   DevBuf owner, vbflag, nb, margin;
   DT_TRY(owner.alloc(grid ? total * 4 : 16));

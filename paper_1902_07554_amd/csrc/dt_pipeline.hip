@@ -56,6 +56,30 @@ __global__ void k_extract_grouped(const double4* pts, const uint32_t* pset, cons
   for (int i = 0; i <= D; i++) rows[(size_t)slot * (D + 1) + i] = k[i];
 }
 
+int extract_grouped(const LocalJob& job, const CellPool& pool,
+                    const std::vector<int64_t>& set_offsets, int32_t* rows, hipStream_t st) {
+  const uint32_t ns = job.nsets;
+  if (pool.ncells == 0 || ns == 0) return DT_OK;
+  DevBuf base, cursor;
+  DT_TRY(base.alloc((size_t)ns * 4));
+  DT_TRY(cursor.alloc((size_t)ns * 4));
+  std::vector<uint32_t> hb(ns);
+  for (uint32_t i = 0; i < ns; i++) hb[i] = (uint32_t)set_offsets[i];
+  DT_HIP(hipMemcpyAsync(base.p, hb.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+  DT_HIP(hipMemsetAsync(cursor.p, 0, (size_t)ns * 4, st));
+  if (job.D == 2)
+    hipLaunchKernelGGL(k_extract_grouped<2>, dim3(blocks(pool.ncells)), dim3(TB), 0, st, job.pts,
+                       job.pset, pool.cells.as<Cell>(), pool.ncells, base.as<uint32_t>(),
+                       cursor.as<uint32_t>(), rows);
+  else
+    hipLaunchKernelGGL(k_extract_grouped<3>, dim3(blocks(pool.ncells)), dim3(TB), 0, st, job.pts,
+                       job.pset, pool.cells.as<Cell>(), pool.ncells, base.as<uint32_t>(),
+                       cursor.as<uint32_t>(), rows);
+  DT_HIP(hipGetLastError());
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
 static void fill_pred_stats(dt_stats& s, const K4Stats& ks) {
   for (int i = 0; i < 4; i++)
     for (int j = 0; j < 4; j++) s.pred[i][j] += (int64_t)ks.pred[i][j];
@@ -144,42 +168,18 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
     DT_TRY(k4_extract(job, pool, r->rows.as<int32_t>(), cx.dflag.as<uint32_t>(), nullptr, st));
   } else {
     // per-set counts, then rows grouped by set
-    DevBuf cnt, base, cursor;
+    DevBuf cnt;
     DT_TRY(cnt.alloc((size_t)ns * 4));
-    DT_TRY(base.alloc((size_t)ns * 4));
-    DT_TRY(cursor.alloc((size_t)ns * 4));
     DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)ns * 4, st));
     DT_TRY(k4_extract(job, pool, nullptr, cx.dflag.as<uint32_t>(), cnt.as<uint32_t>(), st));
     std::vector<uint32_t> hc(ns);
     DT_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    std::vector<uint32_t> hb(ns);
-    uint64_t tot = 0;
-    for (uint32_t i = 0; i < ns; i++) {
-      hb[i] = (uint32_t)tot;
-      r->set_offsets[i] = (int64_t)tot;
-      tot += hc[i];
-    }
-    r->set_offsets[ns] = (int64_t)tot;
-    r->m = (int64_t)tot;
-    DT_TRY(r->rows.alloc_plain((size_t)tot * (D + 1) * 4));
-    DT_HIP(hipMemcpyAsync(base.p, hb.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
-    DT_HIP(hipMemsetAsync(cursor.p, 0, (size_t)ns * 4, st));
-    if (pool.ncells) {
-      if (D == 2)
-        hipLaunchKernelGGL(k_extract_grouped<2>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
-                           job.pts, job.pset, pool.cells.as<Cell>(),
-                           pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
-                           r->rows.as<int32_t>());
-      else
-        hipLaunchKernelGGL(k_extract_grouped<3>, dim3(blocks(pool.ncells)), dim3(TB), 0, st,
-                           job.pts, job.pset, pool.cells.as<Cell>(),
-                           pool.ncells, base.as<uint32_t>(), cursor.as<uint32_t>(),
-                           r->rows.as<int32_t>());
-      DT_HIP(hipGetLastError());
-    }
-  }
-  DT_HIP(hipStreamSynchronize(st));
+    for (uint32_t i = 0; i < ns; i++) r->set_offsets[i + 1] = r->set_offsets[i] + hc[i];
+    r->m = r->set_offsets[ns];
+    DT_TRY(r->rows.alloc_plain((size_t)r->m * (D + 1) * 4));
+    DT_TRY(extract_grouped(job, pool, r->set_offsets, r->rows.as<int32_t>(), st));
+  }  DT_HIP(hipStreamSynchronize(st));
   double t3 = now_ms();
   r->stats.num_simplices = r->m;
   r->stats.rounds = ks.rounds;
@@ -204,6 +204,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
 
 int run_triangulate(const double* points, int64_t n, int D, int k, double sample_rate,
                     const dt_options& o, bool on_device, hipStream_t st, dt_result* r) {
+  if (k > 1 && o.recursive) return run_recursive(points, n, D, k, sample_rate, o, on_device, st, r);
   if (k == 1) {
     int64_t off[2] = {0, n};
     int s = run_batch(points, nullptr, off, 1, D, o, on_device, st, r);

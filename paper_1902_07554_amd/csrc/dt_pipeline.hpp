@@ -40,6 +40,13 @@ int run_dc(const double* points, int64_t n, int D, int k, double sample_rate,
            const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
 int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, int64_t num_sets,
               int D, const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+// Recursive bisection: log2 k levels of 2-way division, k-1 merges.
+int run_recursive(const double* points, int64_t n, int D, int k, double sample_rate,
+                  const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+// Rows of the live finite cells of a batched job, grouped by set at the
+// given row offsets (order inside a set unspecified).
+int extract_grouped(const LocalJob& job, const CellPool& pool,
+                    const std::vector<int64_t>& set_offsets, int32_t* rows, hipStream_t st);
 // Neighbours of every row of r (m x (D+1) int32: row sharing the facet
 // opposite each vertex, -1 on the hull), within each set.
 int compute_neighbors(const dt_result& r, DevBuf& nbr, hipStream_t st);

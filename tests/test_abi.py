@@ -56,7 +56,7 @@ def test_binding_structs_match_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dt.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(dt_options), '
-                   'sizeof(dt_stats), offsetof(dt_options, cand_blocks), '
+                   'sizeof(dt_stats), offsetof(dt_options, recursive), '
                    'offsetof(dt_stats, candidates));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
@@ -64,5 +64,5 @@ def test_binding_structs_match_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(binding.Options), ctypes.sizeof(binding.Stats),
-            binding.Options.cand_blocks.offset, binding.Stats.candidates.offset]
+            binding.Options.recursive.offset, binding.Stats.candidates.offset]
     assert got == want

@@ -154,3 +154,19 @@ def test_auto_divide(dtlib, dist, want):
     st = res.stats()
     assert st["divide_used"] == want, st["divide_stat"]
     assert np.array_equal(res.rows(), oracle.delaunay(p))
+
+
+@pytest.mark.parametrize("dim,dist,n,k,divide", [
+    (2, "uniform", 10_000, 4, "kd"), (2, "normal", 10_000, 8, "sample"),
+    (3, "bubbles", 20_000, 8, "kd"), (3, "bubbles", 20_000, 16, "sample"),
+    (3, "uniform", 20_000, 2, "sample")])
+def test_recursive_bisection(dtlib, dim, dist, n, k, divide):
+    """Section "Recursive Bisection": log2 k levels of 2-way division and
+    k-1 merges give DT(P) as well."""
+    p = inputs.make(dist, n, dim, seed=11)
+    print(f"[pipeline] recursive {dim}d {dist} k={k} {divide}", flush=True)
+    res = dtlib.triangulate(p, k=k, sample_rate=0.02, divide=divide, recursive=1, sort_output=1)
+    assert np.array_equal(res.rows(), oracle.delaunay(p))
+    st = res.stats()
+    assert st["num_simplices"] == len(res.rows())
+    assert st["border_vertices"] > 0
