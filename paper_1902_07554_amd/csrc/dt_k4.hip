@@ -804,8 +804,11 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
         const unsigned long long cc = __atomic_load_n(&a.cells[t].cav, __ATOMIC_RELAXED);
         if (cc == K) continue;
         if (cc < K) { s_abort[g] = 1; break; }
-        if (__atomic_load_n(&a.cells[t].shell, __ATOMIC_RELAXED) == K) continue;
+        const unsigned long long sh = __atomic_load_n(&a.cells[t].shell, __ATOMIC_RELAXED);
+        if (sh == K) continue;
         if (conflict<D, F32>(a, pr, tv, p, qp, qk)) {
+          // a cavity cell in a smaller candidate's shell fails verification
+          if (sh < K) { s_abort[g] = 1; break; }
           const unsigned long long old = atomicMin(&a.cells[t].cav, K);
           if (old < K) { s_abort[g] = 1; break; }
           if (old == K) continue;
