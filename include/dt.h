@@ -71,7 +71,8 @@ enum { DT_PREC_FP64 = 0, DT_PREC_FP32 = 1 };
  * another partition's bounding box); the exact test (a point of another
  * partition lies inside the circumsphere, decided with the exact perturbed
  * in-sphere predicate on the points of the grid cells the ball covers). */
-enum { DT_BORDER_REGION = 0, DT_BORDER_GRID = 1, DT_BORDER_BBOX = 2, DT_BORDER_EXACT = 3 };
+enum { DT_BORDER_REGION = 0, DT_BORDER_GRID = 1, DT_BORDER_BBOX = 2, DT_BORDER_EXACT = 3,
+       DT_BORDER_REFINED = 4 /* the region test, then the exact test on its hits */ };
 
 typedef struct dt_options {
   int divide;        /* DT_DIVIDE_SAMPLE (Algorithm 2) or DT_DIVIDE_KD (cyclic median) */

@@ -22,7 +22,7 @@ DT_E_NOMEM, DT_E_DEVICE, DT_E_INTERNAL, DT_E_NOT_READY = -5, -6, -7, -8
 DIVIDE = {"sample": 0, "kd": 1, "auto": 2}
 WEIGHT = {"log": 0, "const": 1, "inverse": 2, "linear": 3}
 PRECISION = {"fp64": 0, "fp32": 1}
-BORDER = {"region": 0, "grid": 1, "bbox": 2, "exact": 3}
+BORDER = {"region": 0, "grid": 1, "bbox": 2, "exact": 3, "refined": 4}
 STAGES = ["validate", "sample", "sample_dt", "partition", "assign", "scatter", "local_dt",
           "border", "border_dt", "merge", "output", "total"]
 KERNELS = ["k4_pick", "k4_cavity", "k4_insert", "assign", "bucket", "border", "merge",

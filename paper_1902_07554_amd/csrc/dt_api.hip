@@ -119,7 +119,7 @@ int check_options(const dt_options* in, dt_options& o) {
   if (o.precision != DT_PREC_FP64 && o.precision != DT_PREC_FP32) return DT_E_INVALID_ARG;
   if (!(o.eps >= 0.0) || !(o.grid_cell > 0.0)) return DT_E_INVALID_ARG;
   if (o.refine_iters < 0) return DT_E_INVALID_ARG;
-  if (o.border < DT_BORDER_REGION || o.border > DT_BORDER_EXACT) return DT_E_INVALID_ARG;
+  if (o.border < DT_BORDER_REGION || o.border > DT_BORDER_REFINED) return DT_E_INVALID_ARG;
   if (o.start_active < 0 || o.start_active > (1 << 24)) return DT_E_INVALID_ARG;
   if (o.grow_div < 0 || o.grow_div > (1 << 20)) return DT_E_INVALID_ARG;
   if (o.cand_blocks < 0 || o.cand_blocks > (1 << 20)) return DT_E_INVALID_ARG;

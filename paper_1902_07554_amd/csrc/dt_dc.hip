@@ -290,7 +290,8 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   double cells = (double)n;
   for (int a = 0; a < D; a++) cells /= o.grid_cell;
   Region reg;
-  if (o.border == DT_BORDER_REGION) {
+  if (o.border == DT_BORDER_REGION || o.border == DT_BORDER_REFINED) {
+    reg.refine = o.border == DT_BORDER_REFINED;
     if (divide == DT_DIVIDE_SAMPLE) {
       reg.kind = BORDER_VORONOI;
       reg.S = Sp.as<double4>();

@@ -282,12 +282,16 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
 #pragma unroll
         for (int i = 1; i <= D; i++) m = fmax(m, R.margin[key_of(P, v[i])]);
         flag = !(m > 2.0 * r) && region_hit<D>(R, pset[v[0]], ctr, r);
+        // refined: of the region test's simplices keep those whose sphere
+        // really holds a point of another partition
+        if (flag && R.refine) flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
       } else if (R.kind == BORDER_BBOX) {
         flag = bbox_hit<D>(R, pset[v[0]], ctr, r);
       } else if (R.kind == BORDER_EXACT) {
         flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
       } else if (R.kind != BORDER_GRID) {
         flag = region_hit<D>(R, pset[v[0]], ctr, r);
+        if (flag && R.refine) flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
       } else {
         uint32_t me = pset[v[0]];
         int lo[3], hi[3];
@@ -380,7 +384,7 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
     R.pboxes = pboxes.as<double>();
     R.nparts = job.nsets;
   }
-  if (reg.kind == BORDER_EXACT) {
+  if (reg.kind == BORDER_EXACT || reg.refine) {
     // the job's points listed by grid cell
     DT_TRY(ccount.alloc((total + 1) * 4));
     DT_TRY(cstart.alloc((total + 1) * 4));

@@ -58,6 +58,7 @@ struct Region {
   uint32_t nparts = 0;
   const uint32_t* cstart = nullptr;   // grid cell c: items[cstart[c] .. cstart[c+1])
   const uint32_t* citems = nullptr;   // point indices of the job
+  bool refine = false;                // region test, then the exact test on its hits
 };
 int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, uint32_t n,
                   int D, double cells_target, const double lo[3], const double hi[3],

@@ -63,7 +63,8 @@ def _stage_checks(dtlib, p, k, rate, seed, divide, border="region"):
 
 @pytest.mark.parametrize("divide,border", [("sample", "region"), ("kd", "region"),
                                            ("sample", "grid"), ("sample", "bbox"),
-                                           ("sample", "exact"), ("kd", "exact")])
+                                           ("sample", "exact"), ("kd", "exact"),
+                                           ("sample", "refined"), ("kd", "refined")])
 def test_config_2d_10k(dtlib, divide, border):
     """2D, n = 10,000 uniform, sample 1 % (100 points), k = 4."""
     p = inputs.uniform(10_000, 2, seed=1)
@@ -76,7 +77,8 @@ def test_config_2d_10k(dtlib, divide, border):
     ("sample", "bubbles", 32, "region"), ("kd", "bubbles", 32, "region"),
     ("sample", "normal", 8, "region"), ("sample", "bubbles", 32, "grid"),
     ("kd", "uniform", 16, "grid"), ("sample", "bubbles", 32, "bbox"),
-    ("sample", "bubbles", 32, "exact"), ("kd", "uniform", 16, "exact")])
+    ("sample", "bubbles", 32, "exact"), ("kd", "uniform", 16, "exact"),
+    ("sample", "bubbles", 32, "refined")])
 def test_3d_stages(dtlib, divide, dist, k, border):
     p = inputs.make(dist, 20_000, 3, seed=4)
     print(f"[pipeline] 3d 20k {dist} {divide} k={k} border={border}", flush=True)
@@ -134,13 +136,14 @@ def test_border_primitives_order(dtlib):
     p = inputs.make("bubbles", 20_000, 3, seed=9)
     print("[pipeline] border primitives", flush=True)
     nb, rows = {}, {}
-    for border in ("exact", "region", "grid", "bbox"):
+    for border in ("exact", "refined", "region", "grid", "bbox"):
         res = dtlib.triangulate(p, k=16, sample_rate=0.01, border=border, sort_output=1)
         nb[border] = res.stats()["border_simplices"]
         rows[border] = res.rows()
-    for border in ("region", "grid", "bbox"):
+    for border in ("refined", "region", "grid", "bbox"):
         assert np.array_equal(rows[border], rows["exact"])
         assert nb["exact"] <= nb[border]
+    assert nb["refined"] == nb["exact"] and nb["refined"] <= nb["region"]
     assert nb["region"] <= nb["bbox"] and nb["grid"] <= nb["bbox"]
 
 
