@@ -79,7 +79,7 @@ struct K4Args {
   uint32_t* act;        // active point list (a superset of the pending points);
                         // its length and the level's threshold live in ctr
   uint32_t grow_div;
-  uint32_t rings;       // bid rings checked by the selection (0, 1 or 2)
+  uint32_t rings;       // bid rings checked by the selection (0 to 3)
   int fp32;
 };
 
@@ -647,10 +647,11 @@ __global__ void k4_select(K4Args a) {
 #pragma unroll
         for (int i = 0; i <= D; i++)
           if (a.cells[vat(nb, i) >> 2].cand < K) want = false;
-        // Second ring: a smaller bid two cells away almost always claims a
-        // cell next to this cavity.  Skipping such candidates now (they
-        // would lose) saves their searches; the smallest bid of all is
-        // never skipped, so every round still inserts a point.
+        // Second and third rings: a smaller bid two or three cells away
+        // almost always claims a cell next to this cavity.  Skipping such
+        // candidates now (they would lose) saves their searches; the
+        // smallest bid of all is never skipped, so every round still
+        // inserts a point.
         if (want && a.rings > 1) {
 #pragma unroll
           for (int i = 0; i <= D && want; i++) {
@@ -658,6 +659,16 @@ __global__ void k4_select(K4Args a) {
 #pragma unroll
             for (int j = 0; j <= D; j++)
               if (a.cells[vat(nb2, j) >> 2].cand < K) want = false;
+          }
+        }
+        if (want && a.rings > 2) {
+          for (int i = 0; i <= D && want; i++) {
+            uint4 nb2 = a.cells[vat(nb, i) >> 2].n;
+            for (int j = 0; j <= D && want; j++) {
+              uint4 nb3 = a.cells[vat(nb2, j) >> 2].n;
+              for (int l = 0; l <= D; l++)
+                if (a.cells[vat(nb3, l) >> 2].cand < K) want = false;
+            }
           }
         }
       }
@@ -1218,7 +1229,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   uint32_t thresh0 = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
   a.act = actbuf.as<uint32_t>();
   a.grow_div = job.grow_div ? job.grow_div : 64;
-  a.rings = 2;   // two rings filter best on clustered and uniform 3D input
+  a.rings = 3;   // three rings of bids: fewest rounds on clustered 3D input
   hipLaunchKernelGGL(k4_ctl_init, dim3(1), dim3(1), 0, st, a, thresh0);
   // Rounds run back to back in groups; the host reads the control state
   // once per group.  Rounds past the end do nothing (the skip word).
