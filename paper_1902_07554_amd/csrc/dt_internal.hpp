@@ -122,6 +122,7 @@ struct CellPool {
 struct K4Stats {
   unsigned long long cavity_cells = 0;
   unsigned long long candidates = 0;
+  unsigned long long verified = 0;    // cavity searches that completed
   int rounds = 0;
   uint32_t maxcav = 0;
   unsigned long long pred[4][4] = {};

@@ -93,6 +93,7 @@ struct Stripes {
   uint32_t pend[NSTRIPE];                 // pending points this round
   uint32_t ins[NSTRIPE];                  // points inserted this round
   uint32_t maxcav[NSTRIPE];               // largest cavity
+  unsigned long long verified[NSTRIPE];   // candidates whose search completed
 };
 constexpr uint32_t EXTCAP = 8192;
 
@@ -933,6 +934,7 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
   for (uint32_t slot = blockIdx.x; slot < ncand; slot += gridDim.x) {
     const uint32_t n = a.cand_n[slot];
     if (n == 0) continue;
+    if (lane == 0) atomicAdd(&a.sx->verified[blockIdx.x % NSTRIPE], 1ull);
     const uint32_t p = a.cand_pt[slot];
     const unsigned long long K = make_key(a.round, p);
     CavList cl{a.cav + (size_t)slot * a.cavcap, a.cavinfo + (size_t)slot * a.cavcap, nullptr,
@@ -1296,9 +1298,6 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     if (group < 32 && !trace) group *= 2;
   }
   ks.rounds = (int)hctr->rounds;
-  if (dbg)
-    fprintf(stderr, "[k4] done npts %u sets %u rounds %u candidates %llu (%llu)\n", npts,
-            job.nsets, hctr->rounds, hctr->cand_total, 0ull);
   ks.candidates = hctr->cand_total;
   pool.ncells = hctr->cells;
   {
@@ -1313,9 +1312,13 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
       for (int i = 0; i < 4; i++)
         for (int j = 0; j < 4; j++) ks.pred[i][j] += hs.pred[b][i * 4 + j];
       ks.cavity_cells += hs.cavcells[b];
+      ks.verified += hs.verified[b];
       if (hs.maxcav[b] > ks.maxcav) ks.maxcav = hs.maxcav[b];
     }
   }
+  if (dbg)
+    fprintf(stderr, "[k4] done npts %u sets %u rounds %u candidates %llu searches completed %llu\n",
+            npts, job.nsets, hctr->rounds, hctr->cand_total, ks.verified);
   return DT_OK;
 }
 
