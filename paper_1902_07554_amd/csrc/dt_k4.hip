@@ -1086,7 +1086,14 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
       }
     }
     }
-    for (uint32_t h = lane; h < n; h += 64) a.cells[cl.cell(h)].fwd = base;
+    // destroyed cavity cells point into the star: to the new cell over one
+    // of their own boundary facets when they have one (near the points
+    // they held), else to the star's first cell
+    for (uint32_t h = lane; h < n; h += 64) {
+      const uint32_t inf = cl.info(h);
+      const uint32_t mask = inf & 0xFFu;
+      a.cells[cl.cell(h)].fwd = mask ? facet_cell(inf, __ffs(mask) - 1, base) : base;
+    }
     if (lane == 0) {
       a.ploc[p] = DONE;
       won++;
