@@ -653,22 +653,28 @@ __global__ void k4_select(K4Args a) {
         // candidates now (they would lose) saves their searches; the
         // smallest bid of all is never skipped, so every round still
         // inserts a point.
+        // (each step skips the facet leading back: its index in the
+        // neighbour is the low two bits of the link)
         if (want && a.rings > 1) {
 #pragma unroll
           for (int i = 0; i <= D && want; i++) {
-            uint4 nb2 = a.cells[vat(nb, i) >> 2].n;
+            const uint32_t w = vat(nb, i);
+            const uint4 nb2 = a.cells[w >> 2].n;
 #pragma unroll
             for (int j = 0; j <= D; j++)
-              if (a.cells[vat(nb2, j) >> 2].cand < K) want = false;
+              if (j != (int)(w & 3u) && a.cells[vat(nb2, j) >> 2].cand < K) want = false;
           }
         }
         if (want && a.rings > 2) {
           for (int i = 0; i <= D && want; i++) {
-            uint4 nb2 = a.cells[vat(nb, i) >> 2].n;
+            const uint32_t w = vat(nb, i);
+            const uint4 nb2 = a.cells[w >> 2].n;
             for (int j = 0; j <= D && want; j++) {
-              uint4 nb3 = a.cells[vat(nb2, j) >> 2].n;
+              if (j == (int)(w & 3u)) continue;
+              const uint32_t u = vat(nb2, j);
+              const uint4 nb3 = a.cells[u >> 2].n;
               for (int l = 0; l <= D; l++)
-                if (a.cells[vat(nb3, l) >> 2].cand < K) want = false;
+                if (l != (int)(u & 3u) && a.cells[vat(nb3, l) >> 2].cand < K) want = false;
             }
           }
         }
