@@ -264,8 +264,12 @@ int dt_batch_autotune(const double* points, const int64_t* offsets, int64_t num_
  *                      A result is handed out once; later calls give DT_OK
  *                      with *out = NULL.  DT_E_INVALID_ARG: unknown ticket.
  *   dt_server_wait:    as poll, but blocks until the job is done.
- *   dt_server_destroy: finishes all submitted jobs, joins the workers and
- *                      frees every result not handed out.
+ *   dt_server_destroy: finishes all submitted jobs, joins the workers,
+ *                      frees every result not handed out and returns the
+ *                      workers' cached scratch memory to the device.
+ * A finished job keeps a small record (status, timestamps) until the
+ * server is destroyed.  Submitted device points must be ready: the copy
+ * runs on the default stream.
  */
 typedef struct dt_server dt_server;
 int dt_server_create(size_t hbm_budget_bytes, const dt_options* opt, dt_server** srv);

@@ -20,6 +20,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -194,7 +195,14 @@ struct dt_server {
           b.push_back(j);
         }
       }
-      if (!b.empty()) run_batch_of(b, st);
+      if (!b.empty()) {
+        try {
+          run_batch_of(b, st);
+        } catch (const std::bad_alloc&) {   // host memory for the batch
+          for (Job* j : b)
+            if (!j->res && j->status == DT_OK) j->status = DT_E_NOMEM;
+        }
+      }
       {
         std::lock_guard<std::mutex> lk(mu);
         double now = mono_s() - t0;
@@ -253,7 +261,12 @@ extern "C" int dt_server_submit(dt_server* s, const double* points, int64_t n, i
     delete j;
     return DT_E_NOMEM;
   }
-  j->host.resize((size_t)n * D);
+  try {
+    j->host.resize((size_t)n * D);
+  } catch (const std::bad_alloc&) {
+    delete j;
+    return DT_E_NOMEM;
+  }
   {
     if (points_on_device) {
       if (hipMemcpy(j->host.data(), points, (size_t)n * D * 8, hipMemcpyDeviceToHost) !=
@@ -329,5 +342,8 @@ extern "C" void dt_server_destroy(dt_server* s) {
     delete kv.second->res;
     delete kv.second;
   }
+  // hand the workers' cached scratch memory back to the device
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, s->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
   delete s;
 }
