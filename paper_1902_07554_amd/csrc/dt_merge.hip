@@ -62,8 +62,12 @@ __device__ __forceinline__ uint32_t key_of(const double4* P, uint32_t v) {
 // least as close to a foreign sample s as to t, which needs the ball to
 // reach the bisector of s and t; such s lie within |t - ctr| + 2r of the
 // centre.  Margins cover the rounding of the assignment's distance keys.
+// hint: a sample of the own block to measure against (the test holds for
+// any own sample; the one nearest the centre is the tightest).  Without a
+// hint the centre's nearest sample is searched.
 template <int D>
-__device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, double r) {
+__device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, double r,
+                           uint32_t hint = 0xFFFFFFFFu) {
   if (R.kind == BORDER_BOXES) {
     const double* b = R.boxes + (size_t)me * 6;
     for (int k = 0; k < D; k++)
@@ -71,8 +75,15 @@ __device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, doub
     return false;
   }
   double d2t;
-  uint32_t t = grid_nearest(R.S, R.start, R.items, R.G, ctr[0], ctr[1], D == 3 ? ctr[2] : 0.0, &d2t);
-  if (R.part[t] != me) return true;
+  uint32_t t = hint;
+  if (t == 0xFFFFFFFFu) {
+    t = grid_nearest(R.S, R.start, R.items, R.G, ctr[0], ctr[1], D == 3 ? ctr[2] : 0.0, &d2t);
+    if (R.part[t] != me) return true;
+  } else {
+    const double4 q = R.S[t];
+    const double dx = ctr[0] - q.x, dy = ctr[1] - q.y, dz = (D == 3 ? ctr[2] : 0.0) - q.z;
+    d2t = (dx * dx + dy * dy) + dz * dz;
+  }
   double4 tp = R.S[t];
   double rad = sqrt(d2t) * (1.0 + 1e-9) + 2.0 * r;
   int lo[3], hi[3];
@@ -281,7 +292,21 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
         double m = R.margin[key_of(P, v[0])];
 #pragma unroll
         for (int i = 1; i <= D; i++) m = fmax(m, R.margin[key_of(P, v[i])]);
-        flag = !(m > 2.0 * r) && region_hit<D>(R, pset[v[0]], ctr, r);
+        if (!(m > 2.0 * r)) {
+          // the own sample nearest the centre among the vertices' samples
+          uint32_t t = 0xFFFFFFFFu;
+          double best = INFINITY;
+          const double cz = D == 3 ? ctr[2] : 0.0;
+#pragma unroll
+          for (int i = 0; i <= D; i++) {
+            const uint32_t s = R.nearest[key_of(P, v[i])];
+            const double4 q = R.S[s];
+            const double dx = ctr[0] - q.x, dy = ctr[1] - q.y, dz = cz - q.z;
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            if (d2 < best) { best = d2; t = s; }
+          }
+          flag = region_hit<D>(R, pset[v[0]], ctr, r, t);
+        }
         // refined: of the region test's simplices keep those whose sphere
         // really holds a point of another partition
         if (flag && R.refine) flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
