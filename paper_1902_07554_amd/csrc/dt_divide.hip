@@ -581,6 +581,10 @@ __device__ __forceinline__ unsigned long long ord_bits(double x) {
   unsigned long long u = (unsigned long long)__double_as_longlong(x);
   return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
+__device__ __forceinline__ double from_ord_d(unsigned long long o) {
+  const unsigned long long u = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
+  return __longlong_as_double((long long)u);
+}
 
 __global__ void k_kd_keys(const double4* P, uint32_t n, int dim, unsigned long long* keys,
                           uint32_t* vals) {
@@ -614,6 +618,318 @@ __global__ void k_kd_split(const unsigned long long* segk, const uint32_t* vals,
   }
 }
 
+// ---- kd level by selection (instead of sorting): per segment, the
+// element of rank floor(m/2) in (coordinate, id) order is found by a
+// histogram of the coordinate over the candidates' extent, narrowed to the
+// bin that holds the wanted rank until that bin is small, then an exact
+// sort of that bin, then a comparison of every point with the element
+// found.  The split is the one a full sort gives.  The bin of a coordinate
+// is a monotone function of it, so equal coordinates share a bin, the
+// order of the bins is the order of the coordinates, and the points of one
+// bin are exactly those between its smallest and largest coordinate.
+constexpr uint32_t KD_HIST = 16384;  // bins of all segments of one level
+constexpr uint32_t KD_MINBINS = 64;
+constexpr uint32_t KD_CAP = 4096;    // largest median bin sorted in LDS
+constexpr uint32_t KD_MAXSEG = 1024; // segments with an LDS extent table
+constexpr uint32_t KD_GRID = 1024;   // blocks of the streaming passes
+constexpr int KD_NARROW = 4;         // narrowing passes before the sort
+
+__device__ __forceinline__ double kd_coord(const double4& p, int dim) {
+  return dim == 0 ? p.x : (dim == 1 ? p.y : p.z);
+}
+
+// bin of x among `bins` equal parts of the segment's candidate range
+__device__ __forceinline__ uint32_t kd_bin(double x, const unsigned long long* cand, uint32_t s,
+                                           uint32_t bins) {
+  const double lo = from_ord_d(cand[2 * s]), hi = from_ord_d(cand[2 * s + 1]);
+  const double w = hi - lo;
+  if (!(w > 0)) return 0;
+  const double t = (x - lo) / w * (double)bins;
+  const int b = (int)t;
+  return b < 0 ? 0u : (b >= (int)bins ? bins - 1 : (uint32_t)b);
+}
+
+// extent of the candidates of every active segment (those in its range,
+// and, when narrowing, in its chosen bin): per-block table in LDS, then
+// one global atomic per segment and block
+__global__ __launch_bounds__(256) void k_kd_extent(const double4* P, uint32_t n, int dim,
+                                                   const uint32_t* seg, uint32_t nseg,
+                                                   const unsigned long long* cand,
+                                                   const uint32_t* act, const uint32_t* info,
+                                                   uint32_t bins, int narrow,
+                                                   unsigned long long* out) {
+  __shared__ unsigned long long s_lo[KD_MAXSEG], s_hi[KD_MAXSEG];
+  for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x) {
+    s_lo[s] = ~0ull;
+    s_hi[s] = 0ull;
+  }
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t s = seg[i];
+    if (!act[s]) continue;
+    const double x = kd_coord(P[i], dim);
+    const unsigned long long o = ord_bits(x);
+    if (o < cand[2 * s] || o > cand[2 * s + 1]) continue;
+    if (narrow && kd_bin(x, cand, s, bins) != info[4 * s]) continue;
+    atomicMin(&s_lo[s], o);
+    atomicMax(&s_hi[s], o);
+  }
+  __syncthreads();
+  for (uint32_t s = threadIdx.x; s < nseg; s += blockDim.x)
+    if (s_lo[s] != ~0ull) {
+      atomicMin(&out[2 * s], s_lo[s]);
+      atomicMax(&out[2 * s + 1], s_hi[s]);
+    }
+}
+
+// the new candidate range of every active segment
+__global__ void k_kd_adopt(uint32_t nseg, const uint32_t* act, const unsigned long long* ext,
+                           unsigned long long* cand) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg || !act[s]) return;
+  cand[2 * s] = ext[2 * s];
+  cand[2 * s + 1] = ext[2 * s + 1];
+}
+
+// histogram of the candidates of all active segments (nseg * bins <=
+// KD_HIST): per-block in LDS, then added to the global one
+__global__ __launch_bounds__(256) void k_kd_hist(const double4* P, uint32_t n, int dim,
+                                                 const uint32_t* seg, uint32_t bins,
+                                                 uint32_t total, const unsigned long long* cand,
+                                                 const uint32_t* act, uint32_t* hist) {
+  __shared__ uint32_t s_h[KD_HIST];
+  for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) s_h[j] = 0;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t s = seg[i];
+    if (!act[s]) continue;
+    const double x = kd_coord(P[i], dim);
+    const unsigned long long o = ord_bits(x);
+    if (o < cand[2 * s] || o > cand[2 * s + 1]) continue;
+    atomicAdd(&s_h[s * bins + kd_bin(x, cand, s, bins)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < total; j += blockDim.x)
+    if (s_h[j]) atomicAdd(&hist[j], s_h[j]);
+}
+
+// one block per active segment: the bin holding the wanted rank among the
+// candidates (on the first pass floor(m/2) of the m points), the rank
+// inside that bin and the bin's count; the first pass also records m
+__global__ __launch_bounds__(256) void k_kd_findbin(const uint32_t* hist, uint32_t bins,
+                                                    const uint32_t* act, int first,
+                                                    uint32_t* info) {
+  __shared__ uint32_t s_sum[256];
+  const uint32_t s = blockIdx.x;
+  if (!act[s]) return;
+  const uint32_t* h = hist + (size_t)s * bins;
+  const uint32_t chunk = (bins + 255) / 256;
+  const uint32_t b0 = threadIdx.x * chunk, b1 = min(b0 + chunk, bins);
+  uint32_t local = 0;
+  for (uint32_t b = b0; b < b1; b++) local += h[b];
+  s_sum[threadIdx.x] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (uint32_t t = 0; t < 256; t++) m += s_sum[t];
+    const uint32_t want = first ? m / 2 : info[4 * s + 1];
+    uint32_t cum = 0, bin = 0, cnt = 0, rank = 0;
+    if (want < m) {
+      uint32_t t = 0;
+      while (cum + s_sum[t] <= want) cum += s_sum[t++];
+      for (uint32_t b = t * chunk;; b++) {
+        if (cum + h[b] > want) {
+          bin = b;
+          cnt = h[b];
+          rank = want - cum;
+          break;
+        }
+        cum += h[b];
+      }
+    }
+    info[4 * s] = bin;
+    info[4 * s + 1] = rank;
+    info[4 * s + 2] = cnt;
+    if (first) info[4 * s + 3] = m;
+  }
+}
+
+__global__ void k_kd_collect(const double4* P, uint32_t n, int dim, const uint32_t* seg,
+                             uint32_t bins, const unsigned long long* cand, const uint32_t* info,
+                             const uint32_t* base, uint32_t* fill, uint32_t* items) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = seg[i];
+  const double x = kd_coord(P[i], dim);
+  const unsigned long long o = ord_bits(x);
+  if (o < cand[2 * s] || o > cand[2 * s + 1]) return;
+  if (kd_bin(x, cand, s, bins) != info[4 * s]) return;
+  const uint32_t slot = atomicAdd(&fill[s], 1u);
+  if (slot < info[4 * s + 2]) items[base[s] + slot] = i;
+}
+
+// one block per segment: sort the chosen bin's elements by (coordinate,
+// id) in LDS (bitonic) and keep the one of the wanted rank
+__global__ __launch_bounds__(256) void k_kd_select(const double4* P, int dim, const uint32_t* info,
+                                                   const uint32_t* base, const uint32_t* items,
+                                                   unsigned long long* med, double* split) {
+  __shared__ unsigned long long s_key[KD_CAP];
+  __shared__ uint32_t s_id[KD_CAP];
+  const uint32_t s = blockIdx.x;
+  const uint32_t cnt = info[4 * s + 2], rank = info[4 * s + 1], m = info[4 * s + 3];
+  if (m == 0) {
+    if (threadIdx.x == 0) {
+      med[2 * s] = ~0ull;
+      med[2 * s + 1] = ~0ull;
+      split[s] = NAN;
+    }
+    return;
+  }
+  uint32_t np2 = 1;
+  while (np2 < cnt) np2 <<= 1;
+  for (uint32_t j = threadIdx.x; j < np2; j += blockDim.x) {
+    if (j < cnt) {
+      const uint32_t id = items[base[s] + j];
+      s_key[j] = ord_bits(kd_coord(P[id], dim));
+      s_id[j] = id;
+    } else {
+      s_key[j] = ~0ull;
+      s_id[j] = 0xFFFFFFFFu;
+    }
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= np2; size <<= 1)
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t j = threadIdx.x; j < np2; j += blockDim.x) {
+        const uint32_t o = j ^ stride;
+        if (o > j) {
+          const bool up = (j & size) == 0;
+          const bool gt = s_key[j] > s_key[o] || (s_key[j] == s_key[o] && s_id[j] > s_id[o]);
+          if (gt == up) {
+            const unsigned long long tk = s_key[j];
+            s_key[j] = s_key[o];
+            s_key[o] = tk;
+            const uint32_t ti = s_id[j];
+            s_id[j] = s_id[o];
+            s_id[o] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  if (threadIdx.x == 0) {
+    med[2 * s] = s_key[rank];
+    med[2 * s + 1] = s_id[rank];
+    split[s] = kd_coord(P[s_id[rank]], dim);
+  }
+}
+
+// lower child: the floor(m/2) smallest (coordinate, id); upper: the rest
+__global__ void k_kd_classify(const double4* P, uint32_t n, int dim, uint32_t* seg,
+                              const unsigned long long* med) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = seg[i];
+  const unsigned long long key = ord_bits(kd_coord(P[i], dim));
+  const unsigned long long mk = med[2 * s], mi = med[2 * s + 1];
+  const bool upper = key > mk || (key == mk && (unsigned long long)i >= mi);
+  seg[i] = 2 * s + (upper ? 1u : 0u);
+}
+
+// One level of the kd split by selection.  *done stays false when the
+// level does not fit the selection (too many segments, or a median bin
+// that stays larger than the LDS sort takes, as with many equal
+// coordinates); the caller then sorts.
+static int kd_level_select(const double4* P, uint32_t n, int dim, int l, uint32_t nseg,
+                           DevBuf& pid, DevBuf& dsplit, bool* done, hipStream_t st) {
+  *done = false;
+  uint32_t bins = KD_HIST >> l;
+  if (bins < KD_MINBINS) bins = KD_MINBINS;
+  if (nseg > KD_MAXSEG || (uint64_t)nseg * bins > KD_HIST || n == 0) return DT_OK;
+  const uint32_t total = nseg * bins;
+  uint32_t grid = dblocks(n);
+  if (grid > KD_GRID) grid = KD_GRID;
+  DevBuf cand, ext, act, hist, info, base, fill, items, med;
+  DT_TRY(cand.alloc((size_t)nseg * 16));
+  DT_TRY(ext.alloc((size_t)nseg * 16));
+  DT_TRY(act.alloc((size_t)nseg * 4));
+  DT_TRY(hist.alloc((size_t)total * 4));
+  DT_TRY(info.alloc((size_t)nseg * 16));
+  std::vector<unsigned long long> all(2 * nseg), empty(2 * nseg);
+  for (uint32_t s = 0; s < nseg; s++) {
+    all[2 * s] = 0ull;
+    all[2 * s + 1] = ~0ull;
+    empty[2 * s] = ~0ull;
+    empty[2 * s + 1] = 0ull;
+  }
+  std::vector<uint32_t> hact(nseg, 1u);
+  DT_HIP(hipMemcpyAsync(cand.p, all.data(), (size_t)nseg * 16, hipMemcpyHostToDevice, st));
+  DT_HIP(hipMemcpyAsync(ext.p, empty.data(), (size_t)nseg * 16, hipMemcpyHostToDevice, st));
+  DT_HIP(hipMemcpyAsync(act.p, hact.data(), (size_t)nseg * 4, hipMemcpyHostToDevice, st));
+  const uint32_t sb = (nseg + 255) / 256;
+  // candidate range of every segment: all of its points
+  hipLaunchKernelGGL(k_kd_extent, dim3(grid), dim3(256), 0, st, P, n, dim, pid.as<uint32_t>(),
+                     nseg, cand.as<unsigned long long>(), act.as<uint32_t>(), info.as<uint32_t>(),
+                     bins, 0, ext.as<unsigned long long>());
+  hipLaunchKernelGGL(k_kd_adopt, dim3(sb), dim3(256), 0, st, nseg, act.as<uint32_t>(),
+                     ext.as<unsigned long long>(), cand.as<unsigned long long>());
+  std::vector<uint32_t> hinfo(4 * nseg);
+  bool small = false;
+  for (int pass = 0; pass <= KD_NARROW; pass++) {
+    if (pass > 0) {
+      // narrow the still active segments to their chosen bin
+      DT_HIP(hipMemcpyAsync(ext.p, empty.data(), (size_t)nseg * 16, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_kd_extent, dim3(grid), dim3(256), 0, st, P, n, dim,
+                         pid.as<uint32_t>(), nseg, cand.as<unsigned long long>(),
+                         act.as<uint32_t>(), info.as<uint32_t>(), bins, 1,
+                         ext.as<unsigned long long>());
+      hipLaunchKernelGGL(k_kd_adopt, dim3(sb), dim3(256), 0, st, nseg, act.as<uint32_t>(),
+                         ext.as<unsigned long long>(), cand.as<unsigned long long>());
+    }
+    DT_HIP(hipMemsetAsync(hist.p, 0, (size_t)total * 4, st));
+    hipLaunchKernelGGL(k_kd_hist, dim3(grid), dim3(256), 0, st, P, n, dim, pid.as<uint32_t>(),
+                       bins, total, cand.as<unsigned long long>(), act.as<uint32_t>(),
+                       hist.as<uint32_t>());
+    hipLaunchKernelGGL(k_kd_findbin, dim3(nseg), dim3(256), 0, st, hist.as<uint32_t>(), bins,
+                       act.as<uint32_t>(), pass == 0 ? 1 : 0, info.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    DT_HIP(hipMemcpyAsync(hinfo.data(), info.p, (size_t)nseg * 16, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    small = true;
+    for (uint32_t s = 0; s < nseg; s++) {
+      if (!hact[s]) continue;
+      if (hinfo[4 * s + 2] <= KD_CAP) hact[s] = 0;
+      else small = false;
+    }
+    if (small) break;
+    DT_HIP(hipMemcpyAsync(act.p, hact.data(), (size_t)nseg * 4, hipMemcpyHostToDevice, st));
+  }
+  if (!small) return DT_OK;   // coordinates too close or equal: sort
+  std::vector<uint32_t> hbase(nseg);
+  uint64_t tot = 0;
+  for (uint32_t s = 0; s < nseg; s++) {
+    hbase[s] = (uint32_t)tot;
+    tot += hinfo[4 * s + 2];
+  }
+  DT_TRY(base.alloc((size_t)nseg * 4));
+  DT_TRY(fill.alloc((size_t)nseg * 4));
+  DT_TRY(items.alloc((size_t)(tot ? tot : 1) * 4));
+  DT_TRY(med.alloc((size_t)nseg * 16));
+  DT_HIP(hipMemcpyAsync(base.p, hbase.data(), (size_t)nseg * 4, hipMemcpyHostToDevice, st));
+  DT_HIP(hipMemsetAsync(fill.p, 0, (size_t)nseg * 4, st));
+  hipLaunchKernelGGL(k_kd_collect, dim3(dblocks(n)), dim3(DB), 0, st, P, n, dim,
+                     pid.as<uint32_t>(), bins, cand.as<unsigned long long>(), info.as<uint32_t>(),
+                     base.as<uint32_t>(), fill.as<uint32_t>(), items.as<uint32_t>());
+  hipLaunchKernelGGL(k_kd_select, dim3(nseg), dim3(256), 0, st, P, dim, info.as<uint32_t>(),
+                     base.as<uint32_t>(), items.as<uint32_t>(), med.as<unsigned long long>(),
+                     dsplit.as<double>());
+  hipLaunchKernelGGL(k_kd_classify, dim3(dblocks(n)), dim3(DB), 0, st, P, n, dim,
+                     pid.as<uint32_t>(), med.as<unsigned long long>());
+  DT_HIP(hipGetLastError());
+  *done = true;
+  return DT_OK;
+}
+
 int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, DevBuf& boxes,
               hipStream_t st) {
   int levels = 0;
@@ -636,6 +952,9 @@ int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, DevB
   DT_TRY(off.alloc((size_t)(k + 1) * 4));
   for (int l = 0; l < levels; l++) {
     uint32_t nseg = 1u << l;
+    bool selected = false;
+    DT_TRY(kd_level_select(P, n, l % D, l, nseg, pid, dsplit, &selected, st));
+    if (!selected) {
     hipLaunchKernelGGL(k_kd_keys, dim3(dblocks(n)), dim3(DB), 0, st, P, n, l % D,
                        keys.as<unsigned long long>(), vals.as<uint32_t>());
     DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), vals.as<uint32_t>(), n, 64, st));
@@ -653,6 +972,7 @@ int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, DevB
                        keys.as<unsigned long long>(), vals.as<uint32_t>(), n, off.as<uint32_t>(),
                        pid.as<uint32_t>(), P, l % D, dsplit.as<double>());
     DT_HIP(hipGetLastError());
+    }
     std::vector<double> hs(nseg);
     DT_HIP(hipMemcpyAsync(hs.data(), dsplit.p, (size_t)nseg * 8, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));

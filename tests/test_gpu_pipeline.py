@@ -97,6 +97,21 @@ def test_lattice_through_pipeline(dtlib, dim, side, k):
             assert np.array_equal(oracle.canonical(res.rows()), want), (divide, border)
 
 
+def test_kd_divide_selection_and_ties(dtlib):
+    """The kd divide's median split, found by selection, equals the split of
+    a full (coordinate, id) sort: at a size with many points per histogram
+    bin, and on columns of equal x coordinates whose median bin is too large
+    for the in-LDS sort (that level is split by the sorting path)."""
+    p = inputs.make("bubbles", 300_000, 3, seed=4)
+    res = dtlib.triangulate(p, k=64, divide="kd", keep_stages=1)
+    assert np.array_equal(res.stage("pid").astype(np.int64), oracle.kd_divide(p, 64))
+    rng = np.random.default_rng(6)
+    q = np.stack([rng.integers(0, 8, 40_000).astype(np.float64), rng.random(40_000)], 1)
+    q = np.unique(q, axis=0)
+    res = dtlib.triangulate(q, k=16, divide="kd", keep_stages=1)
+    assert np.array_equal(res.stage("pid").astype(np.int64), oracle.kd_divide(q, 16))
+
+
 def test_independent_of_division(dtlib):
     """DT(P) does not depend on the division: k, divide and seed vary."""
     p = inputs.bubbles(30_000, 3, seed=8)
