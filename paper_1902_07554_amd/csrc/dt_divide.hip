@@ -381,6 +381,21 @@ __global__ void k_count_u32(const uint32_t* x, uint32_t m, uint32_t* cnt) {
   if (i < m) atomicAdd(&cnt[x[i]], 1u);
 }
 
+// the same count with a per-block table in LDS (few keys, many items):
+// one global atomic per key and block instead of one per item
+constexpr uint32_t COUNT_LDS_KEYS = 4096;
+__global__ __launch_bounds__(256) void k_count_u32_lds(const uint32_t* x, uint32_t m, uint32_t k,
+                                                       uint32_t* cnt) {
+  __shared__ uint32_t s_c[COUNT_LDS_KEYS];
+  for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) s_c[j] = 0;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    atomicAdd(&s_c[x[i]], 1u);
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < k; j += blockDim.x)
+    if (s_c[j]) atomicAdd(&cnt[j], s_c[j]);
+}
+
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
                      const dt_options& o, const double lo[3], const double hi[3],
                      DevBuf& part, double* cut, hipStream_t st) {
@@ -995,7 +1010,12 @@ int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, DevB
 int count_by(const uint32_t* x, uint32_t m, uint32_t k, uint32_t* cnt, hipStream_t st) {
   DT_HIP(hipMemsetAsync(cnt, 0, (size_t)k * 4, st));
   if (m == 0) return DT_OK;
-  hipLaunchKernelGGL(k_count_u32, dim3(dblocks(m)), dim3(DB), 0, st, x, m, cnt);
+  if (k <= COUNT_LDS_KEYS && m >= 65536) {
+    const uint32_t nb = dblocks(m) < 512 ? dblocks(m) : 512;
+    hipLaunchKernelGGL(k_count_u32_lds, dim3(nb), dim3(256), 0, st, x, m, k, cnt);
+  } else {
+    hipLaunchKernelGGL(k_count_u32, dim3(dblocks(m)), dim3(DB), 0, st, x, m, cnt);
+  }
   DT_HIP(hipGetLastError());
   return DT_OK;
 }

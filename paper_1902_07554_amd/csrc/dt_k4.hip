@@ -644,38 +644,57 @@ __global__ void k4_select(K4Args a) {
       const unsigned long long K = bid_key(p);
       want = (a.cells[L].cand == K);
       if (want && a.rings > 0) {
-        uint4 nb = a.cells[L].n;
+        // Each ring's loads are issued together (one dependent step for the
+        // links, one for the bids): a link that leads back is redirected to
+        // a cell of an inner ring, whose bid is known not to be smaller, so
+        // no load waits on a branch.
+        const uint4 nb = a.cells[L].n;
+        uint32_t c1[D + 1];
 #pragma unroll
-        for (int i = 0; i <= D; i++)
-          if (a.cells[vat(nb, i) >> 2].cand < K) want = false;
+        for (int i = 0; i <= D; i++) c1[i] = vat(nb, i);
+        unsigned long long m = NOKEY;
+#pragma unroll
+        for (int i = 0; i <= D; i++) m = min(m, a.cells[c1[i] >> 2].cand);
+        if (m < K) want = false;
         // Second and third rings: a smaller bid two or three cells away
         // almost always claims a cell next to this cavity.  Skipping such
         // candidates now (they would lose) saves their searches; the
         // smallest bid of all is never skipped, so every round still
         // inserts a point.
-        // (each step skips the facet leading back: its index in the
-        // neighbour is the low two bits of the link)
+        // (a link's low two bits are the index of the facet leading back)
         if (want && a.rings > 1) {
+          uint4 n2[D + 1];
 #pragma unroll
-          for (int i = 0; i <= D && want; i++) {
-            const uint32_t w = vat(nb, i);
-            const uint4 nb2 = a.cells[w >> 2].n;
+          for (int i = 0; i <= D; i++) n2[i] = a.cells[c1[i] >> 2].n;
+          uint32_t c2[D + 1][D + 1];
+#pragma unroll
+          for (int i = 0; i <= D; i++)
 #pragma unroll
             for (int j = 0; j <= D; j++)
-              if (j != (int)(w & 3u) && a.cells[vat(nb2, j) >> 2].cand < K) want = false;
-          }
-        }
-        if (want && a.rings > 2) {
-          for (int i = 0; i <= D && want; i++) {
-            const uint32_t w = vat(nb, i);
-            const uint4 nb2 = a.cells[w >> 2].n;
-            for (int j = 0; j <= D && want; j++) {
-              if (j == (int)(w & 3u)) continue;
-              const uint32_t u = vat(nb2, j);
-              const uint4 nb3 = a.cells[u >> 2].n;
-              for (int l = 0; l <= D; l++)
-                if (l != (int)(u & 3u) && a.cells[vat(nb3, l) >> 2].cand < K) want = false;
+              c2[i][j] = (j == (int)(c1[i] & 3u)) ? c1[i] : vat(n2[i], j);
+          m = NOKEY;
+#pragma unroll
+          for (int i = 0; i <= D; i++)
+#pragma unroll
+            for (int j = 0; j <= D; j++) m = min(m, a.cells[c2[i][j] >> 2].cand);
+          if (m < K) want = false;
+          if (want && a.rings > 2) {
+            m = NOKEY;
+#pragma unroll
+            for (int i = 0; i <= D; i++) {
+              uint4 n3[D + 1];
+#pragma unroll
+              for (int j = 0; j <= D; j++) n3[j] = a.cells[c2[i][j] >> 2].n;
+#pragma unroll
+              for (int j = 0; j <= D; j++)
+#pragma unroll
+                for (int l = 0; l <= D; l++) {
+                  const uint32_t x =
+                      (l == (int)(c2[i][j] & 3u)) ? c2[i][j] : vat(n3[j], l);
+                  m = min(m, a.cells[x >> 2].cand);
+                }
             }
+            if (m < K) want = false;
           }
         }
       }
