@@ -327,7 +327,8 @@ __device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q
                          unsigned long long qk) {
   for (int step = 0; step < (1 << 16); step++) {
     if (c >= a.cap) break;
-    uint4 v = a.cells[c].v;
+    // vertices and neighbours together: the next step needs no further load
+    const uint4 v = a.cells[c].v, nb = a.cells[c].n;
     int inf = -1;
     bool bad = false;
 #pragma unroll
@@ -339,7 +340,7 @@ __device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q
     if (bad) break;
     if (inf >= 0) {
       if (conflict<D, F32>(a, pr, v, q, qp, qk)) return c;
-      c = vat(a.cells[c].n, inf) >> 2;
+      c = vat(nb, inf) >> 2;
       continue;
     }
     PtsX X;
@@ -359,7 +360,7 @@ __device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q
       if (pr.template orient<D>(X) < 0) exitf = i;
     }
     if (exitf < 0) return c;
-    c = vat(a.cells[c].n, exitf) >> 2;
+    c = vat(nb, exitf) >> 2;
   }
   atomicOr(&a.ctr->flags, FAIL_WALK);
   return 0;
@@ -838,10 +839,11 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
           s_abort[g] = 1;
           break;
         }
+        // both claims in one step (same cell record)
         const unsigned long long cc = __atomic_load_n(&a.cells[t].cav, __ATOMIC_RELAXED);
+        const unsigned long long sh = __atomic_load_n(&a.cells[t].shell, __ATOMIC_RELAXED);
         if (cc == K) continue;
         if (cc < K) { s_abort[g] = 1; break; }
-        const unsigned long long sh = __atomic_load_n(&a.cells[t].shell, __ATOMIC_RELAXED);
         if (sh == K) continue;
         if (conflict<D, F32>(a, pr, tv, p, qp, qk)) {
           // a cavity cell in a smaller candidate's shell fails verification
@@ -973,18 +975,22 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
     __syncthreads();
     for (uint32_t h = lane; h < n; h += 64) {
       const uint32_t c = cl.cell(h);
-      if (a.cells[c].cav != K || a.cells[c].shell <= K) { s_fail = 1; continue; }
+      // the cell's claims and links in one step, the neighbours' claims in
+      // the next
+      const unsigned long long cv = a.cells[c].cav, sh = a.cells[c].shell;
       const uint4 nb = a.cells[c].n;
+      bool oob = false;
 #pragma unroll
-      for (int i = 0; i <= D; i++) {
-        const uint32_t t = vat(nb, i) >> 2;
-        if (t >= a.cap) {
-          atomicOr(&a.ctr->flags, FAIL_INVARIANT);
-          s_fail = 1;
-          break;
-        }
-        if (a.cells[t].cav < K) s_fail = 1;
+      for (int i = 0; i <= D; i++) oob |= (vat(nb, i) >> 2) >= a.cap;
+      if (oob) {
+        atomicOr(&a.ctr->flags, FAIL_INVARIANT);
+        s_fail = 1;
+        continue;
       }
+      unsigned long long m = NOKEY;
+#pragma unroll
+      for (int i = 0; i <= D; i++) m = min(m, a.cells[vat(nb, i) >> 2].cav);
+      if (cv != K || sh <= K || m < K) s_fail = 1;
     }
     __syncthreads();
     if (s_fail) continue;
