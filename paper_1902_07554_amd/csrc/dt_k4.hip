@@ -735,7 +735,7 @@ constexpr uint32_t CAV_GROUPS = 4;
 constexpr uint32_t CAV_LANES = 64 / CAV_GROUPS;
 
 template <int D, bool F32>
-__global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
+__device__ __forceinline__ void cavity_body(K4Args& a) {
   constexpr uint32_t G = CAV_GROUPS, GL = CAV_LANES;
   constexpr uint32_t IDLE = 0, BUSY = 1, EXHAUSTED = 2;
   __shared__ uint32_t s_n[G], s_flo[G], s_fhi[G], s_abort[G], s_gave[G], s_ext[G], s_slot[G],
@@ -881,6 +881,17 @@ __global__ __launch_bounds__(64, 4) void k4_cavity(K4Args a) {
     if (cells) atomicAdd(&a.sx->cavcells[blockIdx.x % NSTRIPE], cells);
   }
   flush_pred<D>(a.sx, pr.st);
+}
+
+// The FP32-filter variant runs at four waves per SIMD; the FP64 one keeps
+// its wider working set in registers at three.
+template <int D>
+__global__ __launch_bounds__(64, 4) void k4_cavity_f32(K4Args a) {
+  cavity_body<D, true>(a);
+}
+template <int D>
+__global__ __launch_bounds__(64, 3) void k4_cavity_f64(K4Args a) {
+  cavity_body<D, false>(a);
 }
 
 // New cell index of boundary facet (cavity position h, facet f).
@@ -1308,10 +1319,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
       else hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
       DT_PROF_END(st);
       DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
-      if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gc), dim3(64), 0, st, a);
-      else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gc), dim3(64), 0, st, a);
-      else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gc), dim3(64), 0, st, a);
-      else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gc), dim3(64), 0, st, a);
+      if (D == 2 && a.fp32) hipLaunchKernelGGL(k4_cavity_f32<2>, dim3(gc), dim3(64), 0, st, a);
+      else if (D == 2) hipLaunchKernelGGL(k4_cavity_f64<2>, dim3(gc), dim3(64), 0, st, a);
+      else if (a.fp32) hipLaunchKernelGGL(k4_cavity_f32<3>, dim3(gc), dim3(64), 0, st, a);
+      else hipLaunchKernelGGL(k4_cavity_f64<3>, dim3(gc), dim3(64), 0, st, a);
       DT_PROF_END(st);
       DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
       if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);
