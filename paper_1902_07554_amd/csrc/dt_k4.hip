@@ -730,16 +730,24 @@ __global__ void k4_select(K4Args a) {
 // found twice); each neighbour found not in conflict gets a shell claim.
 // A smaller claim anywhere means this candidate cannot win: its search
 // stops.  All control state is per group in LDS; the barriers are outside
-// every group-dependent branch.
+// every group-dependent branch.  Three waves per SIMD: the working set of
+// the filters stays in registers (no spills), which pays more than a
+// fourth wave.
 constexpr uint32_t CAV_GROUPS = 4;
 constexpr uint32_t CAV_LANES = 64 / CAV_GROUPS;
+constexpr uint32_t CAV_STASH = 64;
 
 template <int D, bool F32>
-__device__ __forceinline__ void cavity_body(K4Args& a) {
+__global__ __launch_bounds__(64, 3) void k4_cavity(K4Args a) {
   constexpr uint32_t G = CAV_GROUPS, GL = CAV_LANES;
   constexpr uint32_t IDLE = 0, BUSY = 1, EXHAUSTED = 2;
   __shared__ uint32_t s_n[G], s_flo[G], s_fhi[G], s_abort[G], s_gave[G], s_ext[G], s_slot[G],
       s_state[G];
+  // Links of recently found cavity cells, by cavity position modulo CAV_STASH
+  // (tagged with the position): the next level reads a frontier cell's
+  // neighbours here instead of from its list entry and cell record.
+  __shared__ uint32_t s_tag[G][CAV_STASH];
+  __shared__ uint4 s_lnk[G][CAV_STASH];
   PredT<F32> pr;
   pr.init(&a.ctr->flags);
   const uint32_t lane = threadIdx.x, g = lane / GL, gl = lane % GL;
@@ -792,6 +800,7 @@ __device__ __forceinline__ void cavity_body(K4Args& a) {
       p = a.cand_pt[slot];
       K = make_key(a.round, p);
       load_pt(a.pts, p, qp, qk);
+      for (uint32_t j = gl; j < CAV_STASH; j += GL) s_tag[g][j] = DONE;
     }
     // leaders make room for the level's appends
     if (gl == 0 && busy && !s_abort[g] && s_flo[g] < s_fhi[g]) {
@@ -822,14 +831,20 @@ __device__ __forceinline__ void cavity_body(K4Args& a) {
         if (s_abort[g]) break;
         const uint32_t h = flo + it / (D + 1);
         const int i = (int)(it % (D + 1));
-        const uint32_t c = h < a.cavcap ? la[h] : lb[h - a.cavcap];
-        const uint32_t t = vat(a.cells[c].n, i) >> 2;
+        const uint32_t si = h % CAV_STASH;
+        uint32_t t;
+        if (s_tag[g][si] == h) {
+          t = vat(s_lnk[g][si], i) >> 2;
+        } else {
+          const uint32_t c = h < a.cavcap ? la[h] : lb[h - a.cavcap];
+          t = vat(a.cells[c].n, i) >> 2;
+        }
         if (t >= a.cap) {
           atomicOr(&a.ctr->flags, FAIL_INVARIANT);
           s_abort[g] = 1;
           break;
         }
-        const uint4 tv = a.cells[t].v;
+        const uint4 tv = a.cells[t].v, tn = a.cells[t].n;
         bool badv = false;
 #pragma unroll
         for (int r = 0; r <= D; r++)
@@ -854,6 +869,12 @@ __device__ __forceinline__ void cavity_body(K4Args& a) {
           const uint32_t pos = atomicAdd(&s_n[g], 1u);
           if (pos < a.cavcap) la[pos] = t;
           else lb[pos - a.cavcap] = t;
+          // the slot's previous entry is from an earlier level (no reader
+          // of this level can hold its tag)
+          if (pos < flo + CAV_STASH) {
+            s_tag[g][pos % CAV_STASH] = pos;
+            s_lnk[g][pos % CAV_STASH] = tn;
+          }
         } else {
           atomicMin(&a.cells[t].shell, K);
         }
@@ -881,17 +902,6 @@ __device__ __forceinline__ void cavity_body(K4Args& a) {
     if (cells) atomicAdd(&a.sx->cavcells[blockIdx.x % NSTRIPE], cells);
   }
   flush_pred<D>(a.sx, pr.st);
-}
-
-// The FP32-filter variant runs at four waves per SIMD; the FP64 one keeps
-// its wider working set in registers at three.
-template <int D>
-__global__ __launch_bounds__(64, 4) void k4_cavity_f32(K4Args a) {
-  cavity_body<D, true>(a);
-}
-template <int D>
-__global__ __launch_bounds__(64, 3) void k4_cavity_f64(K4Args a) {
-  cavity_body<D, false>(a);
 }
 
 // New cell index of boundary facet (cavity position h, facet f).
@@ -1319,10 +1329,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
       else hipLaunchKernelGGL(k4_select<3>, dim3(ga), dim3(BLOCK), 0, st, a);
       DT_PROF_END(st);
       DT_PROF_BEGIN(DT_KERN_K4_CAVITY, st);
-      if (D == 2 && a.fp32) hipLaunchKernelGGL(k4_cavity_f32<2>, dim3(gc), dim3(64), 0, st, a);
-      else if (D == 2) hipLaunchKernelGGL(k4_cavity_f64<2>, dim3(gc), dim3(64), 0, st, a);
-      else if (a.fp32) hipLaunchKernelGGL(k4_cavity_f32<3>, dim3(gc), dim3(64), 0, st, a);
-      else hipLaunchKernelGGL(k4_cavity_f64<3>, dim3(gc), dim3(64), 0, st, a);
+      if (D == 2 && a.fp32) hipLaunchKernelGGL((k4_cavity<2, true>), dim3(gc), dim3(64), 0, st, a);
+      else if (D == 2) hipLaunchKernelGGL((k4_cavity<2, false>), dim3(gc), dim3(64), 0, st, a);
+      else if (a.fp32) hipLaunchKernelGGL((k4_cavity<3, true>), dim3(gc), dim3(64), 0, st, a);
+      else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gc), dim3(64), 0, st, a);
       DT_PROF_END(st);
       DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
       if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);
