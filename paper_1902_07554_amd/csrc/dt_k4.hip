@@ -950,15 +950,19 @@ __device__ __forceinline__ uint32_t new_cell_link(K4Args& a, CavList& cl, uint32
   int sin = i, sout = j;
   uint4 vcur = a.cells[c].v;
   for (int step = 0; step < 4096; step++) {
+    // each step: the current cell's link and position, then the next
+    // cell's claim and vertices (each pair from one cell record)
     const uint32_t nbr = vat(a.cells[cur].n, sout);
+    const uint32_t cpos = a.cells[cur].pos;
     const uint32_t ncell = nbr >> 2;
     if (ncell >= a.cap) break;
-    if (a.cells[ncell].cav != K) {
-      const uint32_t xp = facet_cell(cl.info(a.cells[cur].pos), sout, base);
+    const unsigned long long ncav = a.cells[ncell].cav;
+    const uint4 vn = a.cells[ncell].v;
+    if (ncav != K) {
+      const uint32_t xp = facet_cell(cl.info(cpos), sout, base);
       return (xp << 2) | (uint32_t)sin;
     }
     const uint32_t av = vat(vcur, sin);
-    const uint4 vn = a.cells[ncell].v;
     int nout = 0;
 #pragma unroll
     for (int r = 0; r <= D; r++)
@@ -994,6 +998,9 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
     }
     if (lane == 0) s_fail = 0;
     __syncthreads();
+    // boundary-facet mask of the lane's first cavity cell, kept for the
+    // numbering below
+    uint32_t mask0 = 0, c0 = 0;
     for (uint32_t h = lane; h < n; h += 64) {
       const uint32_t c = cl.cell(h);
       // the cell's claims and links in one step, the neighbours' claims in
@@ -1009,9 +1016,18 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
         continue;
       }
       unsigned long long m = NOKEY;
+      uint32_t mk = 0;
 #pragma unroll
-      for (int i = 0; i <= D; i++) m = min(m, a.cells[vat(nb, i) >> 2].cav);
+      for (int i = 0; i <= D; i++) {
+        const unsigned long long ci = a.cells[vat(nb, i) >> 2].cav;
+        m = min(m, ci);
+        if (ci != K) mk |= 1u << i;
+      }
       if (cv != K || sh <= K || m < K) s_fail = 1;
+      if (h == lane) {
+        mask0 = mk;
+        c0 = c;
+      }
     }
     __syncthreads();
     if (s_fail) continue;
@@ -1022,7 +1038,10 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
       const uint32_t h = start + lane;
       uint32_t mask = 0;
       uint32_t c = 0;
-      if (h < n) {
+      if (h < n && start == 0) {
+        c = c0;
+        mask = mask0;
+      } else if (h < n) {
         c = cl.cell(h);
         const uint4 nb = a.cells[c].n;
 #pragma unroll
