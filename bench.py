@@ -51,8 +51,9 @@ def kernel_bytes(name: str, st: dict, dim: int) -> float:
         return ins * (2 * CELL + 8 + v * PT)
     if name == "k4_pick":       # per walk step (about D+1 orientation tests): cell + D+1 points
         return (o / v) * (2 * CELL + v * PT)
-    if name == "k4_select":     # per candidate: its cell's bid and neighbours, two rings of bids
-        return st["candidates"] * (8 + CELL + (dim + 1) * (8 + CELL + (dim + 1) * 8))
+    if name == "k4_select":     # per candidate: its cell's bid and links, three rings of bids
+        r1, r2, r3 = v, v * dim, v * dim * dim     # cells one, two and three facet-hops away
+        return st["candidates"] * (8 + CELL + r1 * (8 + CELL) + r2 * (8 + CELL) + r3 * 8)
     if name == "k4_insert":     # per cavity cell: vertices, neighbours, two claim words
         return st["cavity_cells"] * (2 * CELL + 16)
     if name == "assign":        # per point: read the point, write block and nearest sample
