@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("refine_iters", ctypes.c_int), ("keep_stages", ctypes.c_int),
                 ("border", ctypes.c_int), ("profile", ctypes.c_int),
                 ("start_active", ctypes.c_int), ("grow_div", ctypes.c_int),
-                ("cand_blocks", ctypes.c_int), ("recursive", ctypes.c_int)]
+                ("cand_blocks", ctypes.c_int), ("grow_num", ctypes.c_int),
+                ("recursive", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -309,7 +310,7 @@ def batch_autotune(points, offsets, sample_points: int = 0, **opts) -> dict:
     if st != DT_OK:
         raise DTError(st)
     return {"start_active": out.start_active, "grow_div": out.grow_div,
-            "cand_blocks": out.cand_blocks}
+            "cand_blocks": out.cand_blocks, "grow_num": out.grow_num}
 
 
 class Server:

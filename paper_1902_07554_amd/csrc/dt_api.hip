@@ -123,6 +123,7 @@ int check_options(const dt_options* in, dt_options& o) {
   if (o.start_active < 0 || o.start_active > (1 << 24)) return DT_E_INVALID_ARG;
   if (o.grow_div < 0 || o.grow_div > (1 << 20)) return DT_E_INVALID_ARG;
   if (o.cand_blocks < 0 || o.cand_blocks > (1 << 20)) return DT_E_INVALID_ARG;
+  if (o.grow_num != 0 && (o.grow_num < 9 || o.grow_num > 32)) return DT_E_INVALID_ARG;
   if (o.recursive != 0 && o.recursive != 1) return DT_E_INVALID_ARG;
   return DT_OK;
 }

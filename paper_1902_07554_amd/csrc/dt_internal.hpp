@@ -103,10 +103,12 @@ struct LocalJob {
   uint32_t start_active = 256;    // active points per set in the first level
   uint32_t grow_div = 64;         // next level when pending < inserted / grow_div
   uint32_t cand_blocks = 16384;   // cap on cavity/insert wavefronts
+  uint32_t grow_num = 0;          // threshold growth per level in eighths; 0: by set count
   void tune(const dt_options& o) {
     if (o.start_active > 0) start_active = (uint32_t)o.start_active;
     if (o.grow_div > 0) grow_div = (uint32_t)o.grow_div;
     if (o.cand_blocks > 0) cand_blocks = (uint32_t)o.cand_blocks;
+    if (o.grow_num > 0) grow_num = (uint32_t)o.grow_num;
   }
 };
 

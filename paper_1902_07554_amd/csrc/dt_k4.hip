@@ -79,6 +79,7 @@ struct K4Args {
   uint32_t* act;        // active point list (a superset of the pending points);
                         // its length and the level's threshold live in ctr
   uint32_t grow_div;
+  uint32_t grow_num;    // threshold growth per level, in eighths
   uint32_t rings;       // bid rings checked by the selection (0 to 3)
   int fp32;
 };
@@ -563,7 +564,9 @@ __global__ void k4_ctl_end(K4Args a) {
   const unsigned long long left = c->pending >= ins ? c->pending - ins : 0;
   const unsigned long long lim = c->done / a.grow_div;
   if (c->thresh < PMAX && left < (lim > 256 ? lim : 256)) {
-    c->thresh = c->thresh * 2 > PMAX ? PMAX : c->thresh * 2;
+    unsigned long long nt = (unsigned long long)c->thresh * a.grow_num / 8;
+    if (nt <= c->thresh) nt = c->thresh + 1;
+    c->thresh = nt > PMAX ? PMAX : (uint32_t)nt;
   } else if (ins == 0) {
     if (++c->stall > 8) c->flags |= FAIL_NO_PROGRESS;
   }
@@ -1301,14 +1304,20 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     fprintf(stderr, "[k4] init npts %u sets %u active %u cells %u flags %x\n", npts, job.nsets,
             hctr->active, hctr->cells, hctr->flags);
   if (hctr->flags) return DT_E_INTERNAL;
-  // activation levels: about start_active points per set at first, doubled
-  // whenever fewer are pending than 1/grow_div of those already inserted
+  // activation levels: about start_active points per set at first, grown
+  // by grow_num/8 whenever fewer are pending than 1/grow_div of those
+  // already inserted
   // (decided on the device, see k4_ctl_end)
   const uint32_t PMAX = 1u << 20;
   uint64_t t0 = ((uint64_t)PMAX * job.start_active * job.nsets) / (npts ? npts : 1);
   uint32_t thresh0 = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
   a.act = actbuf.as<uint32_t>();
   a.grow_div = job.grow_div ? job.grow_div : 64;
+  // Smaller steps between levels keep the pending points sparser: fewer
+  // candidates lose.  Many sets (the batched local triangulations) gain
+  // most from x1.25; one set from x1.5 (measured on the 4M bubbles and 1M
+  // uniform workloads).
+  a.grow_num = job.grow_num ? job.grow_num : (job.nsets > 1 ? 10u : 12u);
   a.rings = 3;   // three rings of bids: fewest rounds on clustered 3D input
   hipLaunchKernelGGL(k4_ctl_init, dim3(1), dim3(1), 0, st, a, thresh0);
   // Rounds run back to back in groups; the host reads the control state

@@ -1,7 +1,7 @@
 // Autotuner of the batched local triangulation's launch parameters.
 //
-// The tunables (first-level activation per set, level growth rule, cap on
-// the cavity/insert wavefronts) change only how the rounds of the parallel
+// The tunables (first-level activation per set, level growth rule and
+// step, cap on the cavity/insert wavefronts) change only how the rounds of the parallel
 // insertion are scheduled, never the triangulation.  The tuner times
 // batched runs on a sample of the batch's sets that keeps its size mix
 // (every s-th set), one tunable at a time (coordinate descent from the
@@ -74,6 +74,7 @@ extern "C" int dt_batch_autotune(const double* points, const int64_t* offsets, i
       r.start_active = it->second.start_active;
       r.grow_div = it->second.grow_div;
       r.cand_blocks = it->second.cand_blocks;
+      r.grow_num = it->second.grow_num;
       *tuned = r;
       return DT_OK;
     }
@@ -116,6 +117,7 @@ extern "C" int dt_batch_autotune(const double* points, const int64_t* offsets, i
   best.start_active = 256;
   best.grow_div = 64;
   best.cand_blocks = 16384;
+  best.grow_num = num_sets > 1 ? 10 : 12;
   double best_ms = 0;
   DT_TRY(trial(best, &best_ms));
   const int starts[] = {64, 1024};
@@ -142,6 +144,15 @@ extern "C" int dt_batch_autotune(const double* points, const int64_t* offsets, i
     DT_TRY(trial(t, &ms));
     if (ms < GAIN * best_ms) { best_ms = ms; best = t; }
   }
+  const int steps[] = {9, 12, 16};
+  for (int v : steps) {
+    if (v == best.grow_num) continue;
+    dt_options t = best;
+    t.grow_num = v;
+    double ms;
+    DT_TRY(trial(t, &ms));
+    if (ms < GAIN * best_ms) { best_ms = ms; best = t; }
+  }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
@@ -150,6 +161,7 @@ extern "C" int dt_batch_autotune(const double* points, const int64_t* offsets, i
   r.start_active = best.start_active;
   r.grow_div = best.grow_div;
   r.cand_blocks = best.cand_blocks;
+  r.grow_num = best.grow_num;
   *tuned = r;
   return DT_OK;
 }

@@ -80,12 +80,14 @@ def test_autotuned_batch_is_identical(dtlib):
     pts, offsets = inputs.batch_sets(96, 64, 8192, dim=2, seed=4)
     print(f"[autotune] sets=96 n={offsets[-1]}", flush=True)
     tuned = dtlib.batch_autotune(pts, offsets, sample_points=60000)
-    assert set(tuned) == {"start_active", "grow_div", "cand_blocks"}
+    assert set(tuned) == {"start_active", "grow_div", "cand_blocks", "grow_num"}
+    assert 9 <= tuned["grow_num"] <= 32
     # a second call of the same size class comes from the cache
     assert dtlib.batch_autotune(pts, offsets, sample_points=60000) == tuned
     a = dtlib.batch_triangulate(pts, offsets, **tuned)
     b = dtlib.batch_triangulate(pts, offsets)
-    c = dtlib.batch_triangulate(pts, offsets, start_active=16, grow_div=64, cand_blocks=1)
+    c = dtlib.batch_triangulate(pts, offsets, start_active=16, grow_div=64, cand_blocks=1,
+                                grow_num=32)
     ra, rb, rc = a.rows(), b.rows(), c.rows()
     soa, sob, soc = a.set_offsets(96), b.set_offsets(96), c.set_offsets(96)
     for s in range(96):
