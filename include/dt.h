@@ -90,7 +90,7 @@ typedef struct dt_options {
    * picks them for a batch).  They change timing only, never the result. */
   int start_active;  /* points per set active in the first level; default 256       */
   int grow_div;      /* next level starts when pending < inserted/grow_div; default 64 */
-  int cand_blocks;   /* cap on wavefronts of the cavity/insert launches; default 16384 */
+  int cand_blocks;   /* cap on wavefronts of the cavity/insert launches; default 32768 */
   int grow_num;      /* growth of the threshold per level, in eighths (9..32, i.e.
                         x1.125..x4); default 10 for several sets, 12 for one set   */
   /* 1: recursive bisection (Section "Recursive Bisection"): log2 k levels of

@@ -102,7 +102,7 @@ struct LocalJob {
   // launch tunables (timing only)
   uint32_t start_active = 256;    // active points per set in the first level
   uint32_t grow_div = 64;         // next level when pending < inserted / grow_div
-  uint32_t cand_blocks = 16384;   // cap on cavity/insert wavefronts
+  uint32_t cand_blocks = 32768;   // cap on cavity/insert wavefronts
   uint32_t grow_num = 0;          // threshold growth per level in eighths; 0: by set count
   void tune(const dt_options& o) {
     if (o.start_active > 0) start_active = (uint32_t)o.start_active;

@@ -116,13 +116,13 @@ extern "C" int dt_batch_autotune(const double* points, const int64_t* offsets, i
   dt_options best = o;
   best.start_active = 256;
   best.grow_div = 64;
-  best.cand_blocks = 16384;
+  best.cand_blocks = 32768;
   best.grow_num = num_sets > 1 ? 10 : 12;
   double best_ms = 0;
   DT_TRY(trial(best, &best_ms));
   const int starts[] = {64, 1024};
   const int grows[] = {8, 1024};
-  const int blocks[] = {4096, 65536};
+  const int blocks[] = {16384, 65536};
   for (int v : starts) {
     dt_options t = best;
     t.start_active = v;
