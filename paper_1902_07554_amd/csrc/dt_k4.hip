@@ -979,28 +979,52 @@ __device__ __forceinline__ uint32_t new_cell_link(K4Args& a, CavList& cl, uint32
   return 0xFFFFFFFFu;
 }
 
+// Blocks of INS_WAVES wavefronts, one candidate per wavefront at a time:
+// each wavefront verifies and numbers its candidate's boundary facets,
+// then one thread takes the new cells of all the block's winners with a
+// single atomic (a counter that every winner hit alone serialises the
+// whole launch), then each wavefront builds its cells.
+constexpr uint32_t INS_WAVES = 8;
+
+// Barrier of one wavefront (its lanes run in lockstep: only the memory
+// ordering of a barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 template <int D>
-__global__ __launch_bounds__(64) void k4_insert(K4Args a) {
-  __shared__ uint32_t s_fail, s_run, s_base;
-  __shared__ uint32_t s_ftab[FTAB];   // boundary facet f: cavity position << 2 | facet
-  const uint32_t lane = threadIdx.x;
+__global__ __launch_bounds__(64 * INS_WAVES) void k4_insert(K4Args a) {
+  __shared__ uint32_t s_failw[INS_WAVES], s_runw[INS_WAVES], s_basew[INS_WAVES];
+  __shared__ uint32_t s_ftabw[INS_WAVES][FTAB];   // boundary facet f: cavity position << 2 | facet
+  __shared__ uint32_t s_poolfail;
+  const uint32_t wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  uint32_t& s_fail = s_failw[wv];
+  uint32_t& s_run = s_runw[wv];
+  uint32_t* s_ftab = s_ftabw[wv];
   const uint32_t ncand = min(a.ctr->ncand, a.maxcand);
   uint32_t won = 0;
-  for (uint32_t slot = blockIdx.x; slot < ncand; slot += gridDim.x) {
-    const uint32_t n = a.cand_n[slot];
-    if (n == 0) continue;
-    if (lane == 0) atomicAdd(&a.sx->verified[blockIdx.x % NSTRIPE], 1ull);
-    const uint32_t p = a.cand_pt[slot];
+  for (uint32_t first = blockIdx.x * INS_WAVES; first < ncand; first += gridDim.x * INS_WAVES) {
+    const uint32_t slot = first + wv;
+    const uint32_t n = slot < ncand ? a.cand_n[slot] : 0u;
+    const uint32_t p = n ? a.cand_pt[slot] : 0u;
     const unsigned long long K = make_key(a.round, p);
     CavList cl{a.cav + (size_t)slot * a.cavcap, a.cavinfo + (size_t)slot * a.cavcap, nullptr,
                nullptr, a.cavcap};
-    const uint32_t e = a.cand_ext[slot];
-    if (e != DONE) {
-      cl.b = a.extcell + (size_t)e * EXTCAP;
-      cl.ib = a.extinfo + (size_t)e * EXTCAP;
+    if (n) {
+      const uint32_t e = a.cand_ext[slot];
+      if (e != DONE) {
+        cl.b = a.extcell + (size_t)e * EXTCAP;
+        cl.ib = a.extinfo + (size_t)e * EXTCAP;
+      }
     }
-    if (lane == 0) s_fail = 0;
-    __syncthreads();
+    if (lane == 0) {
+      s_fail = n ? 0u : 1u;
+      s_run = 0;
+      if (n) atomicAdd(&a.sx->verified[(blockIdx.x * INS_WAVES + wv) % NSTRIPE], 1ull);
+    }
+    wave_sync();
     // boundary-facet mask of the lane's first cavity cell, kept for the
     // numbering below
     uint32_t mask0 = 0, c0 = 0;
@@ -1032,12 +1056,10 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
         c0 = c;
       }
     }
-    __syncthreads();
-    if (s_fail) continue;
+    wave_sync();
+    const bool win = s_fail == 0;
     // boundary facets of every cavity cell and their new cell numbers
-    if (lane == 0) s_run = 0;
-    __syncthreads();
-    for (uint32_t start = 0; start < n; start += 64) {
+    for (uint32_t start = 0; win && start < n; start += 64) {
       const uint32_t h = start + lane;
       uint32_t mask = 0;
       uint32_t c = 0;
@@ -1068,22 +1090,31 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
           if ((mask >> i & 1u) && f < FTAB) s_ftab[f++] = (h << 2) | (uint32_t)i;
       }
       const uint32_t total = __shfl(incl, 63, 64);
-      __syncthreads();
+      wave_sync();
       if (lane == 0) s_run = run + total;
-      __syncthreads();
+      wave_sync();
     }
-    const uint32_t nbf = s_run;
-    if (lane == 0) {
-      uint32_t b = atomicAdd(&a.ctr->cells, nbf);
-      if (b + nbf > a.cap) {
-        atomicOr(&a.ctr->flags, FAIL_CELL_POOL);
-        s_fail = 1;
+    // one allocation for the block's winners
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (uint32_t w = 0; w < INS_WAVES; w++) {
+        const uint32_t m = s_failw[w] ? 0u : s_runw[w];
+        s_basew[w] = tot;
+        tot += m;
       }
-      s_base = b;
+      const uint32_t b = tot ? atomicAdd(&a.ctr->cells, tot) : 0u;
+      s_poolfail = 0;
+      if ((uint64_t)b + tot > a.cap) {
+        atomicOr(&a.ctr->flags, FAIL_CELL_POOL);
+        s_poolfail = 1;
+      }
+      for (uint32_t w = 0; w < INS_WAVES; w++) s_basew[w] += b;
     }
     __syncthreads();
-    if (s_fail) continue;
-    const uint32_t base = s_base;
+    if (win && !s_poolfail) {
+    const uint32_t nbf = s_run;
+    const uint32_t base = s_basew[wv];
     if (nbf <= FTAB) {
       // facet-parallel build: one task per (boundary facet, other facet of
       // the new cell); the numbering written by the other lanes is read here
@@ -1172,9 +1203,11 @@ __global__ __launch_bounds__(64) void k4_insert(K4Args a) {
       a.ploc[p] = DONE;
       won++;
     }
+    }
+    // the block's LDS is reused by the next candidates
     __syncthreads();
   }
-  if (lane == 0 && won) atomicAdd(&a.sx->ins[blockIdx.x % NSTRIPE], won);
+  if (lane == 0 && won) atomicAdd(&a.sx->ins[(blockIdx.x * INS_WAVES + wv) % NSTRIPE], won);
 }
 
 // ------------------------------------------------------------ extraction
@@ -1326,6 +1359,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   const uint32_t ga = npts ? (nblk(npts) < 8192 ? nblk(npts) : 8192) : 1;
   uint64_t cbound = npts < maxcand ? (npts ? npts : 1) : maxcand;
   const uint32_t gi = (uint32_t)(cbound < job.cand_blocks ? cbound : job.cand_blocks);
+  // the insert runs INS_WAVES candidates per block
+  const uint32_t gib = (gi + INS_WAVES - 1) / INS_WAVES;
   // the cavity search runs CAV_GROUPS candidates per block
   const uint32_t gc = (gi + CAV_GROUPS - 1) / CAV_GROUPS;
   // DT_DEBUG=2: one round per group, traced
@@ -1363,8 +1398,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
       else hipLaunchKernelGGL((k4_cavity<3, false>), dim3(gc), dim3(64), 0, st, a);
       DT_PROF_END(st);
       DT_PROF_BEGIN(DT_KERN_K4_INSERT, st);
-      if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gi), dim3(64), 0, st, a);
-      else hipLaunchKernelGGL(k4_insert<3>, dim3(gi), dim3(64), 0, st, a);
+      if (D == 2) hipLaunchKernelGGL(k4_insert<2>, dim3(gib), dim3(64 * INS_WAVES), 0, st, a);
+      else hipLaunchKernelGGL(k4_insert<3>, dim3(gib), dim3(64 * INS_WAVES), 0, st, a);
       DT_PROF_END(st);
       hipLaunchKernelGGL(k4_ctl_end, dim3(1), dim3(1), 0, st, a);
       DT_HIP(hipGetLastError());
