@@ -265,6 +265,8 @@ __global__ void k_point_margin(const double4* pts, uint32_t n, const uint32_t* n
   margin[id] = f;
 }
 
+constexpr uint32_t NB_STRIPES = 64;   // copies of the border-simplex counter
+
 template <int D>
 __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cells,
                          uint32_t ncells, BGrid G, const uint32_t* owner, Region R,
@@ -366,8 +368,11 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
   } else if (c < ncells) {
     cflag[c] = 0;
   }
+  // striped count (one address for every wavefront would serialise)
   unsigned long long m = __ballot(flag && finite);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(nb, (unsigned long long)__popcll(m));
+  if ((threadIdx.x & 63) == 0 && m)
+    atomicAdd(&nb[(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % NB_STRIPES],
+              (unsigned long long)__popcll(m));
 }
 
 // Points of partitions that have no full-dimensional triangulation (fewer
@@ -389,9 +394,9 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
   DT_TRY(owner.alloc(grid ? total * 4 : 16));
   DT_TRY(vbflag.alloc((size_t)n * 4));
   DT_TRY(out.cflag.alloc((size_t)pool.ncells + 1));
-  DT_TRY(nb.alloc(8));
+  DT_TRY(nb.alloc(NB_STRIPES * 8));
   DT_HIP(hipMemsetAsync(vbflag.p, 0, (size_t)n * 4, st));
-  DT_HIP(hipMemsetAsync(nb.p, 0, 8, st));
+  DT_HIP(hipMemsetAsync(nb.p, 0, NB_STRIPES * 8, st));
   if (grid) {
     // occupancy of the grid cells (only the grid primitive uses it)
     DT_HIP(hipMemsetAsync(owner.p, 0xFF, total * 4, st));
@@ -450,12 +455,14 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
   hipLaunchKernelGGL(k_degenerate_parts, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
                      job.pset, job.npts, pool.set_cell0.as<uint32_t>(), vbflag.as<uint32_t>());
   DT_HIP(hipGetLastError());
-  unsigned long long hnb = 0;
+  unsigned long long hnbs[NB_STRIPES];
   uint32_t hpf = 0;
-  DT_HIP(hipMemcpyAsync(&hnb, nb.p, 8, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipMemcpyAsync(hnbs, nb.p, NB_STRIPES * 8, hipMemcpyDeviceToHost, st));
   DT_HIP(hipMemcpyAsync(&hpf, pflags.p, 4, hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
   if (hpf) return DT_E_INTERNAL;   // the exact predicate ran out of expansion capacity
+  unsigned long long hnb = 0;
+  for (uint32_t i = 0; i < NB_STRIPES; i++) hnb += hnbs[i];
   out.nb_finite = hnb;
   DT_TRY(compact_indices(vbflag.as<uint32_t>(), n, out.vb, &out.nvb, st));
   return DT_OK;
