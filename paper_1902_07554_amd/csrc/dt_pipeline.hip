@@ -156,7 +156,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   }
   double t2 = now_ms();
   if (ns == 1) {
-    // single set: count, then compact with one atomic per wave
+    // single set: count the rows per block, scan, write them in cell order
     DT_TRY(k4_extract(job, pool, nullptr, cx.dflag.as<uint32_t>(), nullptr, st));
     uint32_t hcount = 0;
     DT_HIP(hipMemcpyAsync(cx.hflag, cx.dflag.p, 4, hipMemcpyDeviceToHost, st));
