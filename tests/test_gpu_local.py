@@ -71,6 +71,11 @@ def test_error_paths(dtlib):
     with pytest.raises(dtlib.DTError) as e:
         dtlib.triangulate(np.zeros((5, 4)))
     assert e.value.status == dtlib.DT_E_INVALID_ARG
+    # level step outside 9..32 eighths
+    for bad in (8, 33):
+        with pytest.raises(dtlib.DTError) as e:
+            dtlib.triangulate(np.array([[0, 0], [1, 0], [0, 1.0]]), grow_num=bad)
+        assert e.value.status == dtlib.DT_E_INVALID_ARG
 
 
 def test_autotuned_batch_is_identical(dtlib):
