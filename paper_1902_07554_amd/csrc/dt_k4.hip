@@ -48,6 +48,7 @@ namespace dtk {
 constexpr int BLOCK = 256;
 // ploc flag: the stored cell is only a start for the walk (dormant point)
 constexpr uint32_t NEEDWALK = 0x80000000u;
+constexpr uint32_t NEAR_WIN = 4;   // neighbours on each side searched for a walk start
 // ploc flag: the point's bid is in place on its (live) cell
 constexpr uint32_t BIDDED = 0x40000000u;
 constexpr uint32_t LOCMASK = 0x3FFFFFFFu;   // cell indices stay below 2^30
@@ -80,6 +81,7 @@ struct K4Args {
                         // its length and the level's threshold live in ctr
   uint32_t grow_div;
   uint32_t grow_num;    // threshold growth per level, in eighths
+  uint32_t* vcell;      // a cell incident to each inserted point (start of later walks)
   uint32_t rings;       // bid rings checked by the selection (0 to 3)
   int fp32;
 };
@@ -470,7 +472,10 @@ __global__ void k4_init_sets(K4Args a) {
     init_cell(a.cells[base + x], cells[x]);
     a.cells[base + x].n = nb;
   }
-  for (int j = 0; j <= D; j++) a.ploc[iv[j]] = DONE;
+  for (int j = 0; j <= D; j++) {
+    a.ploc[iv[j]] = DONE;
+    a.vcell[iv[j]] = base;
+  }
   a.set_cell0[s] = base;
 }
 
@@ -604,6 +609,23 @@ __global__ void k4_pick(K4Args a) {
       const bool need = (raw & NEEDWALK) != 0;
       bool bid = (raw & BIDDED) != 0;
       uint32_t L = raw & LOCMASK;
+      if (need) {
+        // First location of a newly active point: start at a cell of an
+        // inserted point next to it in the (spatially sorted) point order
+        // instead of the set's first cell, whose forward pointers lead far.
+        const uint32_t s = a.pset[p], lo = a.set_off[s], hi = a.set_off[s + 1];
+        uint32_t nb[2 * NEAR_WIN];
+#pragma unroll
+        for (uint32_t d = 1; d <= NEAR_WIN; d++) {
+          nb[2 * d - 2] = p >= lo + d ? a.ploc[p - d] : 0u;
+          nb[2 * d - 1] = p + d < hi ? a.ploc[p + d] : 0u;
+        }
+        uint32_t q = DONE;
+#pragma unroll
+        for (uint32_t j = 0; j < 2 * NEAR_WIN; j++)
+          if (q == DONE && nb[j] == DONE) q = (j & 1u) ? p + (j / 2 + 1) : p - (j / 2 + 1);
+        if (q != DONE) L = a.vcell[q];
+      }
       if (need || a.cells[L].fwd != ALIVE) {
         for (int h = 0; h < (1 << 16); h++) {
           uint32_t f = a.cells[L].fwd;
@@ -1201,6 +1223,7 @@ __global__ __launch_bounds__(64 * INS_WAVES) void k4_insert(K4Args a) {
     }
     if (lane == 0) {
       a.ploc[p] = DONE;
+      a.vcell[p] = base;   // every cell of the star has p as a vertex
       won++;
     }
     }
@@ -1293,6 +1316,8 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   DT_TRY(extcell.alloc((size_t)MAXEXT * EXTCAP * 4));
   DT_TRY(extinfo.alloc((size_t)MAXEXT * EXTCAP * 4));
   DT_TRY(ploc.alloc((size_t)npts * 4));
+  DevBuf vcell;
+  DT_TRY(vcell.alloc((size_t)(npts ? npts : 1) * 4));
   DT_TRY(cand_pt.alloc((size_t)maxcand * 4));
   DT_TRY(cand_n.alloc((size_t)maxcand * 4));
   DT_TRY(cav.alloc((size_t)maxcand * cavcap * 4));
@@ -1323,6 +1348,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.cavcap = cavcap;
   a.round = 0;
   a.fp32 = job.fp32 ? 1 : 0;
+  a.vcell = vcell.as<uint32_t>();
 
   if (D == 2)
     hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
