@@ -25,6 +25,11 @@ def gpu_available() -> bool:
 def dtlib():
     """The HIP library through its Python binding; a GPU test fails loudly
     if the library is not built."""
+    # torch first: its HIP runtime is the one the library then binds to
+    # (the tests hand it device tensors too)
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
     from paper_1902_07554_amd import binding
     binding.load()
     return binding

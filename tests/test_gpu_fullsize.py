@@ -1,0 +1,121 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (device-resident points, the same options).
+
+A full DT of millions of points is out of the oracle's reach, so these
+tests compare what a smaller oracle run determines exactly.  For a box B,
+a simplex whose circumball lies inside B is a simplex of DT(P) if and only
+if it is a simplex of DT(P inside B): the points outside B are outside its
+ball (the empty-ball definition of the DT, with the same symbolic
+perturbation by point id on both sides).  So, for a few boxes of about
+20,000 points, the GPU simplices with a ball inside the box must equal,
+element by element, the oracle's simplices of the box's points with a
+ball inside the box.  Batches are compared set by set on sampled sets."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1902_07554_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+BOX_POINTS = 20_000
+
+
+def _balls(p, rows):
+    """Circumcentres and radii (FP64) of the simplices rows (ids into p)."""
+    dim = p.shape[1]
+    v = p[rows]                                   # m x (dim+1) x dim
+    a = v[:, 1:, :] - v[:, :1, :]                 # m x dim x dim
+    rhs = 0.5 * np.einsum("mij,mij->mi", a, a)
+    c = np.linalg.solve(a, rhs[..., None])[..., 0]
+    return v[:, 0, :] + c, np.sqrt(np.einsum("mi,mi->m", c, c))
+
+
+def _inside(p, rows, lo, hi):
+    """Rows whose circumball is strictly inside the box [lo, hi] (a margin
+    far above the rounding of the centre and radius)."""
+    if len(rows) == 0:
+        return rows
+    ctr, r = _balls(p, rows)
+    tol = 1e-7 * float(np.max(hi - lo))
+    ok = np.all((ctr - r[:, None] - tol > lo) & (ctr + r[:, None] + tol < hi), axis=1)
+    ok &= np.isfinite(r)
+    return rows[ok]
+
+
+def _box_check(p, got_rows, seed, boxes=3):
+    """Compare the GPU rows with the oracle in `boxes` boxes of about
+    BOX_POINTS points centred on random input points."""
+    rng = np.random.default_rng(seed)
+    n = len(p)
+    for b in range(boxes):
+        c = p[rng.integers(n)]
+        dist = np.max(np.abs(p - c), axis=1)
+        d = np.partition(dist, BOX_POINTS)[BOX_POINTS]
+        lo, hi = c - d, c + d
+        ids = np.nonzero(dist < d)[0]
+        inb = np.zeros(n, bool)
+        inb[ids] = True
+        mine = got_rows[np.all(inb[got_rows], axis=1)]
+        mine = oracle.canonical(_inside(p, mine, lo, hi))
+        want = oracle.canonical(_inside(p, oracle.delaunay(p[ids], ids), lo, hi))
+        print(f"[fullsize] box {b}: {len(ids)} points, {len(want)} simplices inside", flush=True)
+        assert len(want) > len(ids), "box too thin to test"
+        assert np.array_equal(mine, want), f"box {b} differs"
+
+
+def _row_hash(rows):
+    """Order-free fingerprint of a set of rows (sorted ids per row)."""
+    r = np.sort(rows.astype(np.uint64), axis=1)
+    h = np.zeros(len(r), np.uint64)
+    for j in range(r.shape[1]):
+        h = (h ^ r[:, j]) * np.uint64(0x9E3779B97F4A7C15)
+        h ^= h >> np.uint64(29)
+    return int(h.sum(dtype=np.uint64)), len(r)
+
+
+def test_bubbles_4m_k256_as_benchmarked(dtlib):
+    """4M bubbles, k = 256, sqrt(n) sample, FP32 filter: the benchmark's
+    headline run; boxes against the oracle, and the kd divide's output is
+    the same simplex set."""
+    import torch
+    p = inputs.make("bubbles", 4_194_304, 3, seed=1)
+    dp = torch.from_numpy(p).cuda()
+    print("[fullsize] bubbles 4M sample divide", flush=True)
+    res = dtlib.triangulate(dp, k=256, sample_rate=0.0, precision="fp32")
+    rows = res.rows().astype(np.int64)
+    st = res.stats()
+    assert len(rows) == st["num_simplices"]
+    _box_check(p, rows, seed=11)
+    print("[fullsize] bubbles 4M kd divide", flush=True)
+    kd = dtlib.triangulate(dp, k=256, divide="kd", precision="fp32")
+    assert _row_hash(kd.rows()) == _row_hash(rows)
+
+
+@pytest.mark.parametrize("divide", ["sample", "kd"])
+def test_uniform_1m_k64(dtlib, divide):
+    """1M uniform points, k = 64, 0.5 % sample, FP64 + exact."""
+    import torch
+    p = inputs.make("uniform", 1_048_576, 3, seed=1)
+    print(f"[fullsize] uniform 1M {divide}", flush=True)
+    res = dtlib.triangulate(torch.from_numpy(p).cuda(), k=64, sample_rate=0.005, divide=divide)
+    rows = res.rows().astype(np.int64)
+    _box_check(p, rows, seed=12, boxes=2)
+
+
+def test_batch_4096_sets_autotuned(dtlib):
+    """4096 2D sets, sizes log-uniform in [64, 65536], uniform or normal:
+    the autotuned batched run; sampled sets equal the oracle's DT."""
+    import torch
+    pts, off = inputs.batch_sets(4096, 64, 65536, dim=2, seed=1)
+    dp = torch.from_numpy(pts).cuda()
+    print(f"[fullsize] batch 4096 sets, {off[-1]} points", flush=True)
+    tuned = dtlib.batch_autotune(dp, off)
+    res = dtlib.batch_triangulate(dp, off, **tuned)
+    rows = res.rows()
+    so = res.set_offsets(4096)
+    for s in range(0, 4096, 128):
+        a, b = off[s], off[s + 1]
+        got = oracle.canonical(rows[so[s]:so[s + 1]])
+        want = oracle.delaunay(pts[a:b], np.arange(a, b))
+        assert np.array_equal(got, want), f"set {s}"
