@@ -289,6 +289,8 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // Proposal: move v to the neighbouring block with the largest connection
 // weight if that beats the current block.  Half the vertices (by a hash
 // alternating with the sweep) may move per sweep to damp oscillation.
+constexpr uint32_t LP_DEG = 48;   // degrees handled from private copies
+
 __global__ void k_lp_propose(uint32_t eta, const uint32_t* off, const uint32_t* adj,
                              const double* w, const uint32_t* part, uint32_t sweep,
                              uint32_t* pblock, double* pgain, uint32_t* pcount) {
@@ -299,23 +301,52 @@ __global__ void k_lp_propose(uint32_t eta, const uint32_t* off, const uint32_t* 
   uint32_t a = off[v], b = off[v + 1];
   uint32_t cur = part[v];
   double own = 0.0;
-  for (uint32_t i = a; i < b; i++)
-    if (part[adj[i]] == cur) own += w[i];
   uint32_t best = DONE;
   double bestw = 0.0;
-  for (uint32_t i = a; i < b; i++) {
-    uint32_t pb = part[adj[i]];
-    if (pb == cur) continue;
-    bool seen = false;
-    for (uint32_t j = a; j < i; j++)
-      if (part[adj[j]] == pb) { seen = true; break; }
-    if (seen) continue;
-    double c = 0.0;
-    for (uint32_t j = i; j < b; j++)
-      if (part[adj[j]] == pb) c += w[j];
-    if (c > bestw || (c == bestw && best != DONE && pb < best)) {
-      bestw = c;
-      best = pb;
+  if (b - a <= LP_DEG) {
+    // the neighbours' blocks and weights gathered once (independent loads),
+    // then the per-block sums from the private copies, in the same order
+    uint32_t nbk[LP_DEG];
+    double nw[LP_DEG];
+    const uint32_t d = b - a;
+    for (uint32_t i = 0; i < d; i++) {
+      nbk[i] = part[adj[a + i]];
+      nw[i] = w[a + i];
+    }
+    for (uint32_t i = 0; i < d; i++)
+      if (nbk[i] == cur) own += nw[i];
+    for (uint32_t i = 0; i < d; i++) {
+      const uint32_t pb = nbk[i];
+      if (pb == cur) continue;
+      bool seen = false;
+      for (uint32_t j = 0; j < i; j++)
+        if (nbk[j] == pb) { seen = true; break; }
+      if (seen) continue;
+      double c = 0.0;
+      for (uint32_t j = i; j < d; j++)
+        if (nbk[j] == pb) c += nw[j];
+      if (c > bestw || (c == bestw && best != DONE && pb < best)) {
+        bestw = c;
+        best = pb;
+      }
+    }
+  } else {
+    for (uint32_t i = a; i < b; i++)
+      if (part[adj[i]] == cur) own += w[i];
+    for (uint32_t i = a; i < b; i++) {
+      uint32_t pb = part[adj[i]];
+      if (pb == cur) continue;
+      bool seen = false;
+      for (uint32_t j = a; j < i; j++)
+        if (part[adj[j]] == pb) { seen = true; break; }
+      if (seen) continue;
+      double c = 0.0;
+      for (uint32_t j = i; j < b; j++)
+        if (part[adj[j]] == pb) c += w[j];
+      if (c > bestw || (c == bestw && best != DONE && pb < best)) {
+        bestw = c;
+        best = pb;
+      }
     }
   }
   if (best != DONE && bestw - own > 1e-12 * (bestw + own + 1.0)) {
