@@ -33,7 +33,7 @@ enum : uint32_t {
 struct alignas(64) Cell {
   uint4 v;                    // vertices (point indices, INF_V = infinite)
   uint4 n;                    // neighbours: cell << 2 | facet index in the neighbour
-  unsigned long long cand;    // smallest bid of a pending point inside
+  unsigned long long spare;   // unused (the bids live in an array of their own)
   unsigned long long cav;     // cavity claim (round-stamped key)
   unsigned long long shell;   // shell claim (round-stamped key)
   unsigned int fwd;           // ALIVE, or the first cell of the star that replaced it

@@ -82,6 +82,10 @@ struct K4Args {
   uint32_t grow_div;
   uint32_t grow_num;    // threshold growth per level, in eighths
   uint32_t* vcell;      // a cell incident to each inserted point (start of later walks)
+  // smallest bid of a pending point inside each cell: an array of its own,
+  // so that the selection's ring checks read 8 bytes per cell from lines
+  // shared by the cells of one star (allocated together)
+  unsigned long long* bid;
   uint32_t rings;       // bid rings checked by the selection (0 to 3)
   int fp32;
 };
@@ -114,10 +118,14 @@ struct CavList {
 __device__ __forceinline__ uint32_t vat(const uint4& v, int i) {
   return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
-// A new cell: vertices, no claims, alive (neighbours are written apart).
-__device__ __forceinline__ void init_cell(Cell& c, const uint4& v) {
+// A new cell: vertices, no bid, no claims, alive (neighbours are written
+// apart).
+template <class A>
+__device__ __forceinline__ void init_cell(A& a, uint32_t x, const uint4& v) {
+  Cell& c = a.cells[x];
+  a.bid[x] = NOKEY;
   c.v = v;
-  c.cand = NOKEY;
+  c.spare = 0;
   c.cav = NOKEY;
   c.shell = NOKEY;
   c.fwd = ALIVE;
@@ -469,7 +477,7 @@ __global__ void k4_init_sets(K4Args a) {
       }
     }
     if (D == 2) nb.w = NOSLOT;
-    init_cell(a.cells[base + x], cells[x]);
+    init_cell(a, base + x, cells[x]);
     a.cells[base + x].n = nb;
   }
   for (int j = 0; j <= D; j++) {
@@ -639,7 +647,7 @@ __global__ void k4_pick(K4Args a) {
         bid = false;
       }
       if (!bid) {
-        atomicMin(&a.cells[L].cand, bid_key(p));
+        atomicMin(&a.bid[L], bid_key(p));
         a.ploc[p] = L | BIDDED;
       }
     }
@@ -668,7 +676,7 @@ __global__ void k4_select(K4Args a) {
     if (raw != DONE && (raw & NEEDWALK) == 0 && prio_of(p) < thresh) {
       const uint32_t L = raw & LOCMASK;
       const unsigned long long K = bid_key(p);
-      want = (a.cells[L].cand == K);
+      want = (a.bid[L] == K);
       if (want && a.rings > 0) {
         // Each ring's loads are issued together (one dependent step for the
         // links, one for the bids): a link that leads back is redirected to
@@ -680,7 +688,7 @@ __global__ void k4_select(K4Args a) {
         for (int i = 0; i <= D; i++) c1[i] = vat(nb, i);
         unsigned long long m = NOKEY;
 #pragma unroll
-        for (int i = 0; i <= D; i++) m = min(m, a.cells[c1[i] >> 2].cand);
+        for (int i = 0; i <= D; i++) m = min(m, a.bid[c1[i] >> 2]);
         if (m < K) want = false;
         // Second and third rings: a smaller bid two or three cells away
         // almost always claims a cell next to this cavity.  Skipping such
@@ -702,7 +710,7 @@ __global__ void k4_select(K4Args a) {
 #pragma unroll
           for (int i = 0; i <= D; i++)
 #pragma unroll
-            for (int j = 0; j <= D; j++) m = min(m, a.cells[c2[i][j] >> 2].cand);
+            for (int j = 0; j <= D; j++) m = min(m, a.bid[c2[i][j] >> 2]);
           if (m < K) want = false;
           if (want && a.rings > 2) {
             m = NOKEY;
@@ -717,7 +725,7 @@ __global__ void k4_select(K4Args a) {
                 for (int l = 0; l <= D; l++) {
                   const uint32_t x =
                       (l == (int)(c2[i][j] & 3u)) ? c2[i][j] : vat(n3[j], l);
-                  m = min(m, a.cells[x >> 2].cand);
+                  m = min(m, a.bid[x >> 2]);
                 }
             }
             if (m < K) want = false;
@@ -957,7 +965,7 @@ __device__ __forceinline__ void new_cell_outer(K4Args& a, uint32_t c, uint32_t i
   const uint32_t x = facet_cell(inf, i, base);
   uint4 nv = a.cells[c].v;
   vset(nv, i, p);
-  init_cell(a.cells[x], nv);
+  init_cell(a, x, nv);
   const uint32_t out = vat(a.cells[c].n, i);
   *nslot(a.cells, x, i) = out;
   if (D == 2) *nslot(a.cells, x, 3) = NOSLOT;
@@ -1208,7 +1216,7 @@ __global__ __launch_bounds__(64 * INS_WAVES) void k4_insert(K4Args a) {
           }
           vset(nn, j, link);
         }
-        init_cell(a.cells[x], nv);
+        init_cell(a, x, nv);
         a.cells[x].n = nn;
       }
     }
@@ -1316,8 +1324,9 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   DT_TRY(extcell.alloc((size_t)MAXEXT * EXTCAP * 4));
   DT_TRY(extinfo.alloc((size_t)MAXEXT * EXTCAP * 4));
   DT_TRY(ploc.alloc((size_t)npts * 4));
-  DevBuf vcell;
+  DevBuf vcell, bidbuf;
   DT_TRY(vcell.alloc((size_t)(npts ? npts : 1) * 4));
+  DT_TRY(bidbuf.alloc((size_t)cap * 8));
   DT_TRY(cand_pt.alloc((size_t)maxcand * 4));
   DT_TRY(cand_n.alloc((size_t)maxcand * 4));
   DT_TRY(cav.alloc((size_t)maxcand * cavcap * 4));
@@ -1349,6 +1358,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.round = 0;
   a.fp32 = job.fp32 ? 1 : 0;
   a.vcell = vcell.as<uint32_t>();
+  a.bid = bidbuf.as<unsigned long long>();
 
   if (D == 2)
     hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
