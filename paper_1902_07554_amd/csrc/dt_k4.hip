@@ -4,8 +4,10 @@
 //
 // Every set of a job is triangulated at once, in synchronous rounds of
 // parallel Bowyer-Watson insertion over all sets together:
-//   pick     every uninserted point bids for the cell it lies in; each cell
-//            keeps its lowest random key (one candidate per cell);
+//   pick     every active uninserted point bids for the cell it lies in;
+//            each cell keeps its lowest random key;
+//   select   a point that holds its cell's bid becomes a candidate unless a
+//            cell within three facet-hops holds a smaller one;
 //   cavity   each candidate grows its conflict region (cells whose
 //            circumsphere strictly contains it, or hull cells whose facet it
 //            sees) and claims those cells and the cells around them with
@@ -27,11 +29,13 @@
 // followed by parallel flipping can stall in 3D on configurations no flip
 // repairs; cavity insertion with priority claims always terminates.
 //
-// Data layout (HBM): cells as uint4 vertices + uint4 neighbours
-// (neighbour = cell << 2 | facet index in the neighbour), one 64-bit claim
-// word per cell for the candidate, cavity and shell claims.  New cells are
-// always appended (old slots are never reused within a job), so a
-// destroyed cell keeps its data and a forward pointer for the walk.
+// Data layout (HBM): one 64-byte record per cell (uint4 vertices, uint4
+// neighbours = cell << 2 | facet index in the neighbour, the 64-bit cavity
+// and shell claims, the forward pointer and the cavity position), and the
+// cells' bids in an array of their own.  New cells are always appended
+// (old slots are never reused within a job), so a destroyed cell keeps its
+// data and a forward pointer for the walk; the cells of one star are
+// contiguous.
 #include "dt_common.hpp"
 #include "dt_internal.hpp"
 #include "dt_pred.hpp"
