@@ -158,7 +158,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   S.stage_ms[DT_STAGE_VALIDATE] = t1 - t0;
 
   // ---- divide
-  DevBuf pid, sid, Sp, part, nearest, boxes;
+  DevBuf pid, sid, Sp, part, nearest, boxes, goff, gadj;
   SampleGrid sgrid;
   CellPool spool;
   LocalJob sjob;
@@ -203,7 +203,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     double tb = now_ms();
     S.stage_ms[DT_STAGE_SAMPLE_DT] = tb - ta;
     DT_TRY(partition_sample(Sp.as<double4>(), eta, D, spool, (uint32_t)k, o, lo, hi, part, &cut,
-                            st));
+                            goff, gadj, st));
     double tc = now_ms();
     S.stage_ms[DT_STAGE_PARTITION] = tc - tb;
     DT_TRY(assign_points(P.as<double4>(), n, Sp.as<double4>(), eta, D, part.as<uint32_t>(), lo, hi,
@@ -300,6 +300,8 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
       reg.items = sgrid.items.as<uint32_t>();
       reg.G = sgrid.G;
       reg.nearest = nearest.as<uint32_t>();
+      reg.goff = goff.as<uint32_t>();
+      reg.gadj = gadj.as<uint32_t>();
     } else {
       reg.kind = BORDER_BOXES;
       reg.boxes = boxes.as<double>();

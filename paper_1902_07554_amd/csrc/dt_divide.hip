@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void k_count_u32_lds(const uint32_t* x, uint32
 
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
                      const dt_options& o, const double lo[3], const double hi[3],
-                     DevBuf& part, double* cut, hipStream_t st) {
+                     DevBuf& part, double* cut, DevBuf& goff, DevBuf& gadj, hipStream_t st) {
   // edges
   uint32_t ncells = pool.ncells;
   uint32_t tsize = 1024;
@@ -530,6 +530,8 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   DT_HIP(hipGetLastError());
   DT_HIP(hipMemcpyAsync(cut, dcut.p, 8, hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
+  goff = std::move(off);
+  gadj = std::move(adj);
   return DT_OK;
 }
 

@@ -9,7 +9,8 @@
 //     the partition owning each cell's points (or "mixed", or empty); the
 //     ball is tested against the cells of other partitions (box-sphere);
 //   region (default): the exact regions of the divide -- Voronoi cells of
-//     the sample for the sample divide, boxes for the kd divide.  The circumball is computed in FP64 and
+//     the sample for the sample divide (searched over the sample's Delaunay
+//     graph), boxes for the kd divide.  The circumball is computed in FP64 and
 // enlarged by a bound far above its rounding error, and nearly flat
 // simplices are always flagged, so the test can only over-flag.  Every
 // simplex is tested, not only those reachable from the hull: partitions of
@@ -110,6 +111,86 @@ __device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, doub
           if (ds - dt <= 2.0 * gap * r + 1e-12 * (ds + dt)) return true;
         }
       }
+  return false;
+}
+
+// Voronoi test over the sample's Delaunay graph, for the sample divide.
+// First a greedy descent from the own sample t: move to the neighbour of
+// smallest key (fl(d^2) to the centre, id) while it beats the current one;
+// a sample that no Delaunay neighbour beats is the nearest to the centre up
+// to rounding.  Then the cells the ball reaches: from a reached own sample
+// u, a neighbour w is reached when the ball meets w's side of the bisector
+// of u and w and also w's side of the bisector of t and w (the centre is at
+// most r from each, with a slack far above the rounding of the distances);
+// w's cell lies on w's side of both, so a cell that the ball meets passes
+// both tests.  Voronoi cells are convex and tile space, so the cells that
+// the ball meets are linked through shared facets, that is through
+// Delaunay edges of the sample, and each of them is reached.  A reached
+// sample of another block flags the simplex; so do a long descent or more
+// than VW_CAP reached cells.  vis: VW_CAP slots, stride MB.
+constexpr int VW_CAP = 16;
+constexpr int VW_STEPS = 64;
+
+template <int D>
+__device__ bool voronoi_walk_hit(const Region& R, uint32_t me, const double* ctr, double r,
+                                 uint32_t t, uint32_t* vis) {
+  const double cx = ctr[0], cy = ctr[1], cz = D == 3 ? ctr[2] : 0.0;
+  double4 tp = R.S[t];
+  double dt;
+  {
+    const double dx = cx - tp.x, dy = cy - tp.y, dz = cz - tp.z;
+    dt = (dx * dx + dy * dy) + dz * dz;
+  }
+  for (int step = 0;; step++) {
+    if (step == VW_STEPS) return true;
+    uint32_t best = t;
+    double bd = dt;
+    long long bid = __double_as_longlong(tp.w);
+    double4 bp = tp;
+    const uint32_t a = R.goff[t], b = R.goff[t + 1];
+    for (uint32_t j = a; j < b; j++) {
+      const uint32_t w = R.gadj[j];
+      const double4 q = R.S[w];
+      const double dx = cx - q.x, dy = cy - q.y, dz = cz - q.z;
+      const double d = (dx * dx + dy * dy) + dz * dz;
+      const long long id = __double_as_longlong(q.w);
+      if (d < bd || (d == bd && id < bid)) { best = w; bd = d; bid = id; bp = q; }
+    }
+    if (best == t) break;
+    t = best;
+    dt = bd;
+    tp = bp;
+  }
+  if (R.part[t] != me) return true;
+  // does the ball reach w's side of the bisector of u and w?  (signed
+  // distance of the centre from it, on u's side: (dw - du) / (2 |w - u|))
+  auto reach = [&](const double4& up, double du, const double4& q, double dw) {
+    const double ex = q.x - up.x, ey = q.y - up.y, ez = q.z - up.z;
+    const double gap = sqrt(ex * ex + ey * ey + ez * ez);
+    return dw - du <= 2.0 * gap * r + 2e-12 * (du + dw + 2.0 * r * r);
+  };
+  int nv = 1, head = 0;
+  vis[0] = t;
+  while (head < nv) {
+    const uint32_t u = vis[(size_t)head++ * MB];
+    const double4 up = R.S[u];
+    const double ux = cx - up.x, uy = cy - up.y, uz = cz - up.z;
+    const double du = (ux * ux + uy * uy) + uz * uz;
+    const uint32_t a = R.goff[u], b = R.goff[u + 1];
+    for (uint32_t j = a; j < b; j++) {
+      const uint32_t w = R.gadj[j];
+      bool seen = false;
+      for (int i = 0; i < nv; i++) seen |= vis[(size_t)i * MB] == w;
+      if (seen) continue;
+      const double4 q = R.S[w];
+      const double ax = cx - q.x, ay = cy - q.y, az = cz - q.z;
+      const double dw = (ax * ax + ay * ay) + az * az;
+      if (reach(up, du, q, dw) && (u == t || reach(tp, dt, q, dw))) {
+        if (R.part[w] != me || nv == VW_CAP) return true;
+        vis[(size_t)nv++ * MB] = w;
+      }
+    }
+  }
   return false;
 }
 
@@ -272,6 +353,7 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
                          uint32_t ncells, BGrid G, const uint32_t* owner, Region R,
                          uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb,
                          uint32_t* flags) {
+  __shared__ uint32_t s_vis[VW_CAP * MB];
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   bool flag = false, finite = false;
   if (c < ncells && cells[c].fwd == ALIVE) {
@@ -307,7 +389,8 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
             const double d2 = (dx * dx + dy * dy) + dz * dz;
             if (d2 < best) { best = d2; t = s; }
           }
-          flag = region_hit<D>(R, pset[v[0]], ctr, r, t);
+          flag = R.gadj ? voronoi_walk_hit<D>(R, pset[v[0]], ctr, r, t, s_vis + threadIdx.x)
+                        : region_hit<D>(R, pset[v[0]], ctr, r, t);
         }
         // refined: of the region test's simplices keep those whose sphere
         // really holds a point of another partition
