@@ -200,11 +200,13 @@ void dt_result_free(dt_result* r);
  *   DT_ARR_LOCAL     int32[m_l x (D+2)] finite simplices of all T_i as
  *                    input indices plus a last column: 1 if in B
  *   DT_ARR_BORDER_DT int32[m_b x (D+1)] finite simplices of T_B
+ *   DT_ARR_NEAREST   int32[n]    nearest sample of every point (index into
+ *                    DT_ARR_SAMPLE; sample divide only)
  * `count` receives the number of elements (rows x columns); pass dst = NULL
  * to query it.
  */
 enum { DT_ARR_SAMPLE = 0, DT_ARR_SAMPLE_DT, DT_ARR_PART, DT_ARR_PID, DT_ARR_ORDER,
-       DT_ARR_BORDER_V, DT_ARR_LOCAL, DT_ARR_BORDER_DT, DT_NUM_ARR };
+       DT_ARR_BORDER_V, DT_ARR_LOCAL, DT_ARR_BORDER_DT, DT_ARR_NEAREST, DT_NUM_ARR };
 int dt_result_stage(const dt_result* r, int which, void* dst, int64_t cap, int64_t* count);
 
 /*

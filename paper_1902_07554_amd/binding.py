@@ -28,7 +28,7 @@ STAGES = ["validate", "sample", "sample_dt", "partition", "assign", "scatter", "
 KERNELS = ["k4_pick", "k4_cavity", "k4_insert", "assign", "bucket", "border", "merge",
            "k4_select"]
 ARR = {"sample": 0, "sample_dt": 1, "part": 2, "pid": 3, "order": 4, "border_v": 5,
-       "local": 6, "border_dt": 7}
+       "local": 6, "border_dt": 7, "nearest": 8}
 EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_count",
            "dt_result_dim", "dt_result_copy", "dt_result_stats", "dt_result_free",
            "dt_result_stage", "dt_batch_triangulate", "dt_result_set_offsets",

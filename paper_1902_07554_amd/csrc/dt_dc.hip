@@ -207,7 +207,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     double tc = now_ms();
     S.stage_ms[DT_STAGE_PARTITION] = tc - tb;
     DT_TRY(assign_points(P.as<double4>(), n, Sp.as<double4>(), eta, D, part.as<uint32_t>(), lo, hi,
-                         pid, nearest, sgrid, st));
+                         goff.as<uint32_t>(), gadj.as<uint32_t>(), pid, nearest, sgrid, st));
     S.stage_ms[DT_STAGE_ASSIGN] = now_ms() - tc;
     S.eta = eta;
     S.cut_weight = cut;
@@ -368,6 +368,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
       for (uint32_t i = 0; i < eta; i++) d[i] = h[i];
       DT_TRY(pool_rows_host(sjob, spool, D, r->stage[DT_ARR_SAMPLE_DT], st));
       DT_TRY(to_host<uint32_t>(r->stage[DT_ARR_PART], part.p, eta, st));
+      DT_TRY(to_host<uint32_t>(r->stage[DT_ARR_NEAREST], nearest.p, n, st));
     }
     DT_TRY(to_host<uint32_t>(r->stage[DT_ARR_PID], pid.p, n, st));
     DT_TRY(to_host<uint32_t>(r->stage[DT_ARR_ORDER], order.p, n, st));

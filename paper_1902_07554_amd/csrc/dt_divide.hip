@@ -536,6 +536,8 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
 }
 
 // ------------------------------------------------------------ 5. assign
+// start-grid cells per sample for the descent of the assignment
+constexpr double AW_CELLS = 32.0;
 static Grid make_grid(const double lo[3], const double hi[3], int D, double cells_target) {
   Grid G;
   double vol = 1.0;
@@ -578,22 +580,119 @@ __global__ void k_grid_fill(uint32_t m, const uint32_t* cellof, const uint32_t* 
   items[start[c] + atomicAdd(&cur[c], 1u)] = i;
 }
 
-// Exact nearest sample under the key (fl(d^2), sample id).
-__global__ void k_assign(const double4* P, uint32_t n, const double4* S, const uint32_t* start,
-                         const uint32_t* items, Grid G, const uint32_t* part, uint32_t* pid,
-                         uint32_t* nearest) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double4 p = P[i];
+// Start sample of every cell of a finer grid: the sample nearest to the
+// cell's centre.
+__global__ void k_start_cells(const double4* S, const uint32_t* start, const uint32_t* items,
+                              Grid G, Grid F, uint32_t nf, uint32_t* first) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nf) return;
+  const uint32_t x = c % F.g[0], y = (c / F.g[0]) % F.g[1], z = c / (F.g[0] * F.g[1]);
   double d2;
-  uint32_t s = grid_nearest(S, start, items, G, p.x, p.y, p.z, &d2);
-  nearest[i] = s;
-  pid[i] = part[s];
+  first[c] = grid_nearest(S, start, items, G, F.lo[0] + (x + 0.5) * F.h,
+                          F.lo[1] + (y + 0.5) * F.h, F.lo[2] + (z + 0.5) * F.h, &d2);
+}
+
+// Nearest sample by descent over the sample's Delaunay graph, exact under
+// the key (fl(d^2), id).  The squared distance to x, taken over the sample
+// points, is the lifted height less an affine function, and the Delaunay
+// triangulation is the lower hull of the lifted points; so every set
+// {s : |x - s|^2 <= L} is connected through Delaunay edges, and a sample no
+// neighbour beats is the nearest.  With rounding, the descent stops at a
+// sample t that no neighbour beats under the key; every sample whose key
+// could be below t's lies in {|x - s|^2 <= fl(d_t^2)(1 + 1e-9)}, which is
+// connected and holds t, so the search through that set finds the least
+// key.  When no neighbour of t is in it, t is the answer.  A long descent
+// or a large near-tie set falls back to the grid search.
+constexpr int AW_CAP = 16;
+constexpr int AW_STEPS = 256;
+
+__global__ __launch_bounds__(DB) void k_assign_walk(const double4* P, uint32_t n, const double4* S,
+                                                    const uint32_t* goff, const uint32_t* gadj,
+                                                    Grid F, const uint32_t* first,
+                                                    const uint32_t* start, const uint32_t* items,
+                                                    Grid G, const uint32_t* part, uint32_t* pid,
+                                                    uint32_t* nearest) {
+  __shared__ uint32_t s_vis[AW_CAP * DB];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t* vis = s_vis + threadIdx.x;
+  const double4 p = P[i];
+  const uint32_t fc = ((uint32_t)cell_coord(p.z, F.lo[2], F.h, F.g[2]) * F.g[1] +
+                       cell_coord(p.y, F.lo[1], F.h, F.g[1])) * F.g[0] +
+                      cell_coord(p.x, F.lo[0], F.h, F.g[0]);
+  uint32_t t = first[fc];
+  double4 tp = S[t];
+  double bd;
+  {
+    const double dx = p.x - tp.x, dy = p.y - tp.y, dz = p.z - tp.z;
+    bd = (dx * dx + dy * dy) + dz * dz;
+  }
+  long long bid = __double_as_longlong(tp.w);
+  bool fallback = true, ties = false;
+  for (int step = 0; step < AW_STEPS; step++) {
+    uint32_t best = t;
+    double nd = bd, dmin = INFINITY;
+    long long nid = bid;
+    const uint32_t a = goff[t], b = goff[t + 1];
+    for (uint32_t j = a; j < b; j++) {
+      const uint32_t w = gadj[j];
+      const double4 q = S[w];
+      const double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+      const double d = (dx * dx + dy * dy) + dz * dz;
+      const long long id = __double_as_longlong(q.w);
+      dmin = fmin(dmin, d);
+      if (d < nd || (d == nd && id < nid)) { best = w; nd = d; nid = id; }
+    }
+    if (best == t) {
+      fallback = false;
+      ties = dmin <= bd * (1.0 + 1e-9);
+      break;
+    }
+    t = best;
+    bd = nd;
+    bid = nid;
+  }
+  if (!fallback && ties) {
+    // the near-tie set around t
+    const double lim = bd * (1.0 + 1e-9);
+    uint32_t bs = t;
+    double kd = bd;
+    long long kid = bid;
+    int nv = 1, head = 0;
+    vis[0] = t;
+    while (head < nv && !fallback) {
+      const uint32_t u = vis[(size_t)head++ * DB];
+      const uint32_t a = goff[u], b = goff[u + 1];
+      for (uint32_t j = a; j < b; j++) {
+        const uint32_t w = gadj[j];
+        bool seen = false;
+        for (int k = 0; k < nv; k++) seen |= vis[(size_t)k * DB] == w;
+        if (seen) continue;
+        const double4 q = S[w];
+        const double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+        const double d = (dx * dx + dy * dy) + dz * dz;
+        if (!(d <= lim)) continue;
+        if (nv == AW_CAP) { fallback = true; break; }
+        vis[(size_t)nv++ * DB] = w;
+        const long long id = __double_as_longlong(q.w);
+        if (d < kd || (d == kd && id < kid)) { bs = w; kd = d; kid = id; }
+      }
+    }
+    t = bs;
+  }
+  if (fallback) {
+    double d2;
+    t = grid_nearest(S, start, items, G, p.x, p.y, p.z, &d2);
+  }
+  nearest[i] = t;
+  pid[i] = part[t];
 }
 
 int assign_points(const double4* P, uint32_t n, const double4* S, uint32_t eta, int D,
-                  const uint32_t* part, const double lo[3], const double hi[3], DevBuf& pid,
+                  const uint32_t* part, const double lo[3], const double hi[3],
+                  const uint32_t* goff, const uint32_t* gadj, DevBuf& pid,
                   DevBuf& nearest, SampleGrid& sg, hipStream_t st) {
+  if (!goff || !gadj) return DT_E_INTERNAL;
   Grid G = make_grid(lo, hi, D, eta / 2.0);
   sg.G = G;
   uint32_t ncell = (uint32_t)G.g[0] * G.g[1] * G.g[2];
@@ -615,9 +714,17 @@ int assign_points(const double4* P, uint32_t n, const double4* S, uint32_t eta, 
                      items.as<uint32_t>());
   DT_TRY(pid.alloc((size_t)n * 4));
   DT_TRY(nearest.alloc((size_t)n * 4));
+  // start samples on a grid of about AW_CELLS cells per sample
+  const Grid F = make_grid(lo, hi, D, eta * AW_CELLS);
+  const uint32_t nf = (uint32_t)F.g[0] * F.g[1] * F.g[2];
+  DevBuf first;
+  DT_TRY(first.alloc((size_t)nf * 4));
+  hipLaunchKernelGGL(k_start_cells, dim3(dblocks(nf)), dim3(DB), 0, st, S, start.as<uint32_t>(),
+                     items.as<uint32_t>(), G, F, nf, first.as<uint32_t>());
   DT_PROF_BEGIN(DT_KERN_ASSIGN, st);
-  hipLaunchKernelGGL(k_assign, dim3(dblocks(n)), dim3(DB), 0, st, P, n, S, start.as<uint32_t>(),
-                     items.as<uint32_t>(), G, part, pid.as<uint32_t>(), nearest.as<uint32_t>());
+  hipLaunchKernelGGL(k_assign_walk, dim3(dblocks(n)), dim3(DB), 0, st, P, n, S, goff, gadj, F,
+                     first.as<uint32_t>(), start.as<uint32_t>(), items.as<uint32_t>(), G, part,
+                     pid.as<uint32_t>(), nearest.as<uint32_t>());
   DT_PROF_END(st);
   DT_HIP(hipGetLastError());
   DT_HIP(hipStreamSynchronize(st));

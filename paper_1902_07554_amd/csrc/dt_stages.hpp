@@ -24,8 +24,11 @@ struct SampleGrid {
   Grid G;
   DevBuf start, items;
 };
+// goff/gadj: the sample's Delaunay graph (the descent search starts on it;
+// the grid is its fallback and the region test's).
 int assign_points(const double4* P, uint32_t n, const double4* S, uint32_t eta, int D,
-                  const uint32_t* part, const double lo[3], const double hi[3], DevBuf& pid,
+                  const uint32_t* part, const double lo[3], const double hi[3],
+                  const uint32_t* goff, const uint32_t* gadj, DevBuf& pid,
                   DevBuf& nearest, SampleGrid& sg, hipStream_t st);
 // boxes: k x 6 doubles (lo xyz, hi xyz) of every block's region.
 int kd_divide(const double4* P, uint32_t n, int D, uint32_t k, DevBuf& pid, DevBuf& boxes,

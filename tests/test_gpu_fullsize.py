@@ -92,6 +92,23 @@ def test_bubbles_4m_k256_as_benchmarked(dtlib):
     assert _row_hash(kd.rows()) == _row_hash(rows)
 
 
+def test_bubbles_4m_nearest_sample(dtlib):
+    """The nearest-sample assignment of the 4M bubbles run: 50,000 sampled
+    points against the oracle's search over all samples, and the partition
+    of every point is that of its nearest sample."""
+    import torch
+    p = inputs.make("bubbles", 4_194_304, 3, seed=1)
+    print("[fullsize] bubbles 4M nearest sample", flush=True)
+    res = dtlib.triangulate(torch.from_numpy(p).cuda(), k=256, sample_rate=0.0, precision="fp32",
+                            keep_stages=1)
+    sid = res.stage("sample")
+    near = res.stage("nearest").astype(np.int64)
+    part = res.stage("part").astype(np.int64)
+    assert np.array_equal(res.stage("pid"), part[near])
+    pick = np.random.default_rng(13).choice(len(p), 50_000, replace=False)
+    assert np.array_equal(near[pick], oracle.nearest_sample(p[pick], p[sid], sid))
+
+
 @pytest.mark.parametrize("divide", ["sample", "kd"])
 def test_uniform_1m_k64(dtlib, divide):
     """1M uniform points, k = 64, 0.5 % sample, FP64 + exact."""

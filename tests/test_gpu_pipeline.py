@@ -29,6 +29,7 @@ def _stage_checks(dtlib, p, k, rate, seed, divide, border="region"):
         part = res.stage("part").astype(np.int64)
         assert oracle.balanced(part, k, 0.05)
         near = oracle.nearest_sample(p, p[sid], sid)
+        assert np.array_equal(res.stage("nearest"), near)
         assert np.array_equal(pid, part[near])
     else:
         assert np.array_equal(pid, oracle.kd_divide(p, k))
