@@ -289,70 +289,74 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // Proposal: move v to the neighbouring block with the largest connection
 // weight if that beats the current block.  Half the vertices (by a hash
 // alternating with the sweep) may move per sweep to damp oscillation.
-constexpr uint32_t LP_DEG = 48;   // degrees handled from private copies
+// One wavefront per vertex: lane i holds neighbour i's block and weight in
+// LDS, and sums the weights of the lanes with its block in neighbour order
+// (the same order for every lane of that block); a reduction picks the
+// largest sum, ties to the smaller block.  Degrees above 64 are summed by
+// lane 0 in the same order.
+constexpr uint32_t LP_WAVES = 4;   // vertices per 256-thread block
 
-__global__ void k_lp_propose(uint32_t eta, const uint32_t* off, const uint32_t* adj,
-                             const double* w, const uint32_t* part, uint32_t sweep,
-                             uint32_t* pblock, double* pgain, uint32_t* pcount) {
-  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= eta) return;
-  pblock[v] = DONE;
+__global__ __launch_bounds__(64 * LP_WAVES) void k_lp_propose(
+    uint32_t eta, const uint32_t* off, const uint32_t* adj, const double* w,
+    const uint32_t* part, uint32_t sweep, uint32_t* pblock, double* pgain, uint32_t* pcount) {
+  __shared__ uint32_t s_b[LP_WAVES][64];
+  __shared__ double s_w[LP_WAVES][64];
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t v = blockIdx.x * LP_WAVES + wv;
+  if (v >= eta) return;   // whole wavefronts leave together
+  if (lane == 0) pblock[v] = DONE;
   if (((mix32(v) + sweep) & 1u) != 0) return;
-  uint32_t a = off[v], b = off[v + 1];
-  uint32_t cur = part[v];
+  const uint32_t a = off[v], b = off[v + 1], d = b - a;
+  const uint32_t cur = part[v];
+  double c = 0.0;          // this lane's block sum
+  uint32_t pb = DONE;      // this lane's block
   double own = 0.0;
-  uint32_t best = DONE;
-  double bestw = 0.0;
-  if (b - a <= LP_DEG) {
-    // the neighbours' blocks and weights gathered once (independent loads),
-    // then the per-block sums from the private copies, in the same order
-    uint32_t nbk[LP_DEG];
-    double nw[LP_DEG];
-    const uint32_t d = b - a;
-    for (uint32_t i = 0; i < d; i++) {
-      nbk[i] = part[adj[a + i]];
-      nw[i] = w[a + i];
+  if (d <= 64) {
+    if (lane < d) {
+      pb = part[adj[a + lane]];
+      s_b[wv][lane] = pb;
+      s_w[wv][lane] = w[a + lane];
     }
-    for (uint32_t i = 0; i < d; i++)
-      if (nbk[i] == cur) own += nw[i];
-    for (uint32_t i = 0; i < d; i++) {
-      const uint32_t pb = nbk[i];
-      if (pb == cur) continue;
-      bool seen = false;
-      for (uint32_t j = 0; j < i; j++)
-        if (nbk[j] == pb) { seen = true; break; }
-      if (seen) continue;
-      double c = 0.0;
-      for (uint32_t j = i; j < d; j++)
-        if (nbk[j] == pb) c += nw[j];
-      if (c > bestw || (c == bestw && best != DONE && pb < best)) {
-        bestw = c;
-        best = pb;
-      }
-    }
-  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (uint32_t j = 0; j < d; j++)
+      if (s_b[wv][j] == cur) own += s_w[wv][j];
+    if (lane < d && pb != cur)
+      for (uint32_t j = 0; j < d; j++)
+        if (s_b[wv][j] == pb) c += s_w[wv][j];
+  } else if (lane == 0) {
+    // long lists: lane 0 alone, same sums, first occurrences in order
     for (uint32_t i = a; i < b; i++)
       if (part[adj[i]] == cur) own += w[i];
+    double bestw = 0.0;
+    uint32_t best = DONE;
     for (uint32_t i = a; i < b; i++) {
-      uint32_t pb = part[adj[i]];
-      if (pb == cur) continue;
+      const uint32_t q = part[adj[i]];
+      if (q == cur) continue;
       bool seen = false;
       for (uint32_t j = a; j < i; j++)
-        if (part[adj[j]] == pb) { seen = true; break; }
+        if (part[adj[j]] == q) { seen = true; break; }
       if (seen) continue;
-      double c = 0.0;
+      double t = 0.0;
       for (uint32_t j = i; j < b; j++)
-        if (part[adj[j]] == pb) c += w[j];
-      if (c > bestw || (c == bestw && best != DONE && pb < best)) {
-        bestw = c;
-        best = pb;
-      }
+        if (part[adj[j]] == q) t += w[j];
+      if (t > bestw || (t == bestw && best != DONE && q < best)) { bestw = t; best = q; }
     }
+    c = bestw;
+    pb = best;
   }
-  if (best != DONE && bestw - own > 1e-12 * (bestw + own + 1.0)) {
-    pblock[v] = best;
-    pgain[v] = bestw - own;
-    atomicAdd(&pcount[best], 1u);
+  // largest sum, ties to the smaller block; a sum must be positive
+  if (!(c > 0.0)) pb = DONE;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double oc = __shfl_xor(c, o, 64);
+    const uint32_t ob = __shfl_xor(pb, o, 64);
+    if (ob != DONE && (pb == DONE || oc > c || (oc == c && ob < pb))) { c = oc; pb = ob; }
+  }
+  if (lane == 0 && pb != DONE && c - own > 1e-12 * (c + own + 1.0)) {
+    pblock[v] = pb;
+    pgain[v] = c - own;
+    atomicAdd(&pcount[pb], 1u);
   }
 }
 
@@ -507,7 +511,8 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   for (int it = 0; it < o.refine_iters; it++) {
     DT_HIP(hipMemsetAsync(pcount.p, 0, (size_t)(k + 1) * 4, st));
     DT_HIP(hipMemsetAsync(pcur.p, 0, (size_t)(k + 1) * 4, st));
-    hipLaunchKernelGGL(k_lp_propose, dim3(dblocks(eta)), dim3(DB), 0, st, eta, off.as<uint32_t>(),
+    hipLaunchKernelGGL(k_lp_propose, dim3((eta + LP_WAVES - 1) / LP_WAVES), dim3(64 * LP_WAVES), 0,
+                       st, eta, off.as<uint32_t>(),
                        adj.as<uint32_t>(), w.as<double>(), part.as<uint32_t>(), (uint32_t)it,
                        pblock.as<uint32_t>(), pgain.as<double>(), pcount.as<uint32_t>());
     DT_TRY(exclusive_scan(pcount.as<uint32_t>(), poff.as<uint32_t>(), k + 1, st));

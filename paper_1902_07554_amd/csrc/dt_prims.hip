@@ -75,6 +75,12 @@ static int scan_rec(const uint32_t* in, uint32_t* out, uint32_t n, hipStream_t s
 
 int exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t n, hipStream_t st) {
   if (n == 0) return DT_OK;
+  if (n <= (uint32_t)SB) {
+    // one block, no temporaries: nothing to wait for
+    hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(256), 0, st, in, out, n, (uint32_t*)nullptr);
+    DT_HIP(hipGetLastError());
+    return DT_OK;
+  }
   std::vector<DevBuf> tmp;
   tmp.reserve(16);
   DT_TRY(scan_rec(in, out, n, st, tmp));
