@@ -135,33 +135,6 @@ template <int D>
 __device__ bool voronoi_walk_hit(const Region& R, uint32_t me, const double* ctr, double r,
                                  uint32_t t, uint32_t* vis) {
   const double cx = ctr[0], cy = ctr[1], cz = D == 3 ? ctr[2] : 0.0;
-  double4 tp = R.S[t];
-  double dt;
-  {
-    const double dx = cx - tp.x, dy = cy - tp.y, dz = cz - tp.z;
-    dt = (dx * dx + dy * dy) + dz * dz;
-  }
-  for (int step = 0;; step++) {
-    if (step == VW_STEPS) return true;
-    uint32_t best = t;
-    double bd = dt;
-    long long bid = __double_as_longlong(tp.w);
-    double4 bp = tp;
-    const uint32_t a = R.goff[t], b = R.goff[t + 1];
-    for (uint32_t j = a; j < b; j++) {
-      const uint32_t w = R.gadj[j];
-      const double4 q = R.S[w];
-      const double dx = cx - q.x, dy = cy - q.y, dz = cz - q.z;
-      const double d = (dx * dx + dy * dy) + dz * dz;
-      const long long id = __double_as_longlong(q.w);
-      if (d < bd || (d == bd && id < bid)) { best = w; bd = d; bid = id; bp = q; }
-    }
-    if (best == t) break;
-    t = best;
-    dt = bd;
-    tp = bp;
-  }
-  if (R.part[t] != me) return true;
   // does the ball reach w's side of the bisector of u and w?  (signed
   // distance of the centre from it, on u's side: (dw - du) / (2 |w - u|))
   auto reach = [&](const double4& up, double du, const double4& q, double dw) {
@@ -169,8 +142,56 @@ __device__ bool voronoi_walk_hit(const Region& R, uint32_t me, const double* ctr
     const double gap = sqrt(ex * ex + ey * ey + ez * ez);
     return dw - du <= 2.0 * gap * r + 2e-12 * (du + dw + 2.0 * r * r);
   };
+  double4 tp = R.S[t];
+  double dt;
+  {
+    const double dx = cx - tp.x, dy = cy - tp.y, dz = cz - tp.z;
+    dt = (dx * dx + dy * dy) + dz * dz;
+  }
+  // the descent's last pass also tests t's neighbours for the search
+  // (lists of up to 64), so the search starts one cell in
+  uint64_t hits = 0;
+  bool fused = false;
+  for (int step = 0;; step++) {
+    if (step == VW_STEPS) return true;
+    uint32_t best = t;
+    double bd = dt;
+    long long bid = __double_as_longlong(tp.w);
+    double4 bp = tp;
+    const uint32_t a = R.goff[t], b = R.goff[t + 1];
+    const bool track = b - a <= 64;
+    uint64_t hm = 0;
+    for (uint32_t j = a; j < b; j++) {
+      const uint32_t w = R.gadj[j];
+      const double4 q = R.S[w];
+      const double dx = cx - q.x, dy = cy - q.y, dz = cz - q.z;
+      const double d = (dx * dx + dy * dy) + dz * dz;
+      const long long id = __double_as_longlong(q.w);
+      if (d < bd || (d == bd && id < bid)) { best = w; bd = d; bid = id; bp = q; }
+      if (track && reach(tp, dt, q, d)) hm |= 1ull << (j - a);
+    }
+    if (best == t) {
+      hits = hm;
+      fused = track;
+      break;
+    }
+    t = best;
+    dt = bd;
+    tp = bp;
+  }
+  if (R.part[t] != me) return true;
   int nv = 1, head = 0;
   vis[0] = t;
+  if (fused) {
+    head = 1;
+    const uint32_t a = R.goff[t];
+    while (hits) {
+      const uint32_t w = R.gadj[a + __builtin_ctzll(hits)];
+      hits &= hits - 1;
+      if (R.part[w] != me || nv == VW_CAP) return true;
+      vis[(size_t)nv++ * MB] = w;
+    }
+  }
   while (head < nv) {
     const uint32_t u = vis[(size_t)head++ * MB];
     const double4 up = R.S[u];
