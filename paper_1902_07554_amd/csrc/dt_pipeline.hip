@@ -31,19 +31,36 @@ __global__ void k_set_of_point(const uint32_t* off, uint32_t nsets, uint32_t n, 
 }
 
 // Write the live finite cells grouped by set: row slot = set_base[s] +
-// cursor[s]++ (order inside a set is unspecified).
+// cursor[s]++ (order inside a set is unspecified).  The cells of one star
+// are allocated together, so neighbouring lanes mostly hold cells of one
+// set: the lanes of each set in a wavefront share one cursor atomic.
 template <int D>
 __global__ void k_extract_grouped(const double4* pts, const uint32_t* pset, const Cell* cells, uint32_t ncells, const uint32_t* set_base,
                                   uint32_t* cursor, int32_t* rows) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells || cells[c].fwd != ALIVE) return;
-  uint4 v = cells[c].v;
+  bool live = c < ncells && cells[c].fwd == ALIVE;
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (live) v = cells[c].v;
   uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int i = 0; i <= D; i++)
-    if (vv[i] == INF_V) return;
-  uint32_t s = pset[v.x];
-  uint32_t slot = set_base[s] + atomicAdd(&cursor[s], 1u);
+    if (vv[i] == INF_V) live = false;
+  const uint32_t s = live ? pset[v.x] : 0xFFFFFFFFu;
+  const uint32_t lane = __lane_id();
+  uint32_t slot = 0;
+  unsigned long long todo = __ballot(live);
+  while (todo) {
+    const int lead = __ffsll(todo) - 1;
+    const uint32_t ls = __shfl(s, lead, 64);
+    const unsigned long long same = __ballot(live && s == ls);
+    uint32_t base = 0;
+    if ((int)lane == lead) base = atomicAdd(&cursor[ls], (uint32_t)__popcll(same));
+    base = __shfl(base, lead, 64);
+    if (live && s == ls)
+      slot = set_base[ls] + base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  if (!live) return;
   int32_t k[4];
 #pragma unroll
   for (int i = 0; i <= D; i++) k[i] = (int32_t)__double_as_longlong(pts[vv[i]].w);
