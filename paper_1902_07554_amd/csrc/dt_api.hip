@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "dt_common.hpp"
@@ -43,6 +44,105 @@ extern "C" const char* dt_strerror(int s) {
 }
 
 namespace dtk {
+
+// Cache of large device blocks (see cached_malloc).  Blocks of at least
+// CACHE_MIN bytes are rounded up to CACHE_GRAIN; a request takes the
+// smallest free block of its device that is at most a quarter larger.  At
+// most CACHE_CAP bytes are kept; an allocation that fails first returns the
+// kept blocks of its device to the driver.  The blocks are never freed at
+// exit (the runtime may be gone by then; the process end releases them).
+namespace {
+constexpr size_t CACHE_MIN = size_t(16) << 20;
+constexpr size_t CACHE_GRAIN = size_t(2) << 20;
+constexpr size_t CACHE_CAP = size_t(48) << 30;
+struct CachedBlock {
+  void* p;
+  size_t size;
+  int dev;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock>* g_cache = new std::vector<CachedBlock>();
+size_t g_cached = 0;
+}  // namespace
+
+hipError_t cached_malloc(void** p, size_t n, size_t* blk) {
+  *blk = 0;
+  if (n < CACHE_MIN) return hipMalloc(p, n);
+  const size_t want = (n + CACHE_GRAIN - 1) / CACHE_GRAIN * CACHE_GRAIN;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    size_t best = g_cache->size();
+    for (size_t i = 0; i < g_cache->size(); i++) {
+      const CachedBlock& b = (*g_cache)[i];
+      if (b.dev == dev && b.size >= want && b.size - want <= want / 4 &&
+          (best == g_cache->size() || b.size < (*g_cache)[best].size))
+        best = i;
+    }
+    if (best < g_cache->size()) {
+      *p = (*g_cache)[best].p;
+      *blk = (*g_cache)[best].size;
+      g_cached -= *blk;
+      g_cache->erase(g_cache->begin() + best);
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, want);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    std::vector<CachedBlock> mine;
+    {
+      std::lock_guard<std::mutex> g(g_cache_mu);
+      for (size_t i = 0; i < g_cache->size();) {
+        if ((*g_cache)[i].dev == dev) {
+          mine.push_back((*g_cache)[i]);
+          g_cached -= (*g_cache)[i].size;
+          g_cache->erase(g_cache->begin() + i);
+        } else {
+          i++;
+        }
+      }
+    }
+    for (const CachedBlock& b : mine) (void)hipFree(b.p);
+    e = hipMalloc(p, want);
+  }
+  if (e == hipSuccess) *blk = want;
+  return e;
+}
+
+void cached_free(void* p, size_t blk) {
+  // the block's own device (the current one may have changed since)
+  hipPointerAttribute_t at;
+  int cur = 0;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess || hipGetDevice(&cur) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(p);
+    return;
+  }
+  const int dev = at.device;
+  // kernels queued on any stream of that device may still use the block
+  if (dev != cur) (void)hipSetDevice(dev);
+  (void)hipDeviceSynchronize();
+  if (dev != cur) (void)hipSetDevice(cur);
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_cache->push_back({p, blk, dev});
+    g_cached += blk;
+    // over the cap: return the largest blocks
+    while (g_cached > CACHE_CAP && !g_cache->empty()) {
+      size_t big = 0;
+      for (size_t i = 1; i < g_cache->size(); i++)
+        if ((*g_cache)[i].size > (*g_cache)[big].size) big = i;
+      drop.push_back((*g_cache)[big].p);
+      g_cached -= (*g_cache)[big].size;
+      g_cache->erase(g_cache->begin() + big);
+    }
+  }
+  for (void* q : drop) (void)hipFree(q);
+}
 
 // Pinned host words of the call contexts, kept per thread and reused
 // (freeing pinned memory synchronises the device).

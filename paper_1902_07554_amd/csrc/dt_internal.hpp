@@ -33,33 +33,50 @@ struct AllocStreamScope {
   ~AllocStreamScope();
 };
 
+// Large plain allocations go through a process-wide cache of device
+// blocks: a released block is kept (after a device-wide synchronisation,
+// as hipFree would do) and handed out again for a request of about its
+// size.  Repeated runs of one workload then reuse the same blocks instead
+// of asking the driver for gigabytes per call, which on a busy machine can
+// stall for seconds.  *blk receives the block size (0: plain hipMalloc).
+hipError_t cached_malloc(void** p, size_t n, size_t* blk);
+void cached_free(void* p, size_t blk);
+
 // Owning device buffer.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  size_t blk = 0;              // size of a cached block (0: not cached)
   hipStream_t ast = nullptr;   // stream of a stream-ordered allocation
   bool ordered = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), ast(o.ast), ordered(o.ordered) {
+  DevBuf(DevBuf&& o) noexcept
+      : p(o.p), bytes(o.bytes), blk(o.blk), ast(o.ast), ordered(o.ordered) {
     o.p = nullptr;
     o.bytes = 0;
+    o.blk = 0;
     o.ordered = false;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; bytes = o.bytes; ast = o.ast; ordered = o.ordered;
-      o.p = nullptr; o.bytes = 0; o.ordered = false;
+      p = o.p; bytes = o.bytes; blk = o.blk; ast = o.ast; ordered = o.ordered;
+      o.p = nullptr; o.bytes = 0; o.blk = 0; o.ordered = false;
     }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)(ordered ? hipFreeAsync(p, ast) : hipFree(p));
+    if (p) {
+      if (ordered) (void)hipFreeAsync(p, ast);
+      else if (blk) cached_free(p, blk);
+      else (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
+    blk = 0;
     ordered = false;
   }
   static int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? DT_E_NOMEM : DT_E_DEVICE; }
@@ -76,12 +93,12 @@ struct DevBuf {
     ordered = true;
     return DT_OK;
   }
-  // Memory that outlives the call (result rows): always hipMalloc.
+  // Memory that outlives the call (result rows): never stream-ordered.
   int alloc_plain(size_t n) {
     release();
     if (n == 0) n = 16;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) { p = nullptr; return status_of(e); }
+    hipError_t e = cached_malloc(&p, n, &blk);
+    if (e != hipSuccess) { p = nullptr; blk = 0; return status_of(e); }
     bytes = n;
     return DT_OK;
   }
