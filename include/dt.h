@@ -166,6 +166,18 @@ int dt_triangulate(const double* points, int64_t n, int D, int k, double sample_
                    const dt_options* opt, int points_on_device, void* stream,
                    dt_result** out);
 
+/*
+ * dt_release_cached_memory -- return to the driver the device blocks that
+ * the library keeps between calls.  Large scratch and result buffers (16 MB
+ * and more) are not freed when a call ends but kept, at most 48 GB per
+ * process, and handed to later calls of about the same size.  This waits for
+ * every device that holds such blocks and frees them.  Blocks in use by
+ * results or by calls running on other threads are not affected; they join
+ * the cache when released.  Returns DT_OK, or DT_E_DEVICE if a device call
+ * fails (the remaining blocks are still freed).
+ */
+int dt_release_cached_memory(void);
+
 /* Number of simplices in a result (all sets for batch results). */
 int64_t dt_result_count(const dt_result* r);
 /* Dimension D of a result. */

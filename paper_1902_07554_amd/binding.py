@@ -33,7 +33,8 @@ EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_cou
            "dt_result_dim", "dt_result_copy", "dt_result_stats", "dt_result_free",
            "dt_result_stage", "dt_batch_triangulate", "dt_result_set_offsets",
            "dt_server_create", "dt_server_submit", "dt_server_poll", "dt_server_wait",
-           "dt_server_times", "dt_server_destroy", "dt_batch_autotune", "dt_result_neighbors"]
+           "dt_server_times", "dt_server_destroy", "dt_batch_autotune", "dt_result_neighbors",
+           "dt_release_cached_memory"]
 
 
 class Options(ctypes.Structure):
@@ -129,8 +130,17 @@ def load():
     lib.dt_server_times.restype = I
     lib.dt_server_destroy.argtypes = [VP]
     lib.dt_server_destroy.restype = None
+    lib.dt_release_cached_memory.argtypes = []
+    lib.dt_release_cached_memory.restype = I
     _lib = lib
     return lib
+
+
+def release_cached_memory() -> None:
+    """Free the device blocks the library keeps between calls."""
+    st = load().dt_release_cached_memory()
+    if st != DT_OK:
+        raise DTError(st)
 
 
 def strerror(status: int) -> str:

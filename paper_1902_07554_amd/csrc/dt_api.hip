@@ -144,6 +144,30 @@ void cached_free(void* p, size_t blk) {
   for (void* q : drop) (void)hipFree(q);
 }
 
+int release_cached_memory() {
+  std::vector<CachedBlock> all;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    all.swap(*g_cache);
+    g_cached = 0;
+  }
+  if (all.empty()) return DT_OK;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  int status = DT_OK;
+  std::sort(all.begin(), all.end(),
+            [](const CachedBlock& x, const CachedBlock& y) { return x.dev < y.dev; });
+  for (size_t i = 0; i < all.size(); i++) {
+    if (i == 0 || all[i].dev != all[i - 1].dev) {
+      if (hipSetDevice(all[i].dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        status = DT_E_DEVICE;
+    }
+    if (hipFree(all[i].p) != hipSuccess) status = DT_E_DEVICE;
+  }
+  if (cur >= 0 && hipSetDevice(cur) != hipSuccess) status = DT_E_DEVICE;
+  return status;
+}
+
 // Pinned host words of the call contexts, kept per thread and reused
 // (freeing pinned memory synchronises the device).
 namespace {
@@ -229,6 +253,8 @@ int check_options(const dt_options* in, dt_options& o) {
 }
 
 }  // namespace dtk
+
+extern "C" int dt_release_cached_memory(void) { return dtk::release_cached_memory(); }
 
 extern "C" int dt_triangulate(const double* points, int64_t n, int D, int k, double sample_rate,
                               const dt_options* opt, int points_on_device, void* stream,

@@ -48,6 +48,8 @@ def test_library_loads_and_binds(libpath):
     assert b.dt_strerror(binding.DT_E_DUPLICATE)
     o = binding.options()
     assert o.divide == 0
+    # nothing cached yet: returns at once, without a device call
+    assert b.dt_release_cached_memory() == binding.DT_OK
 
 
 def test_binding_structs_match_header(tmp_path):

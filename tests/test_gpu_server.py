@@ -116,3 +116,22 @@ def test_server_poll_until_done(dtlib):
     finally:
         srv.close()
     assert np.array_equal(oracle.canonical(r.rows()), oracle.delaunay(p))
+
+
+def test_release_cached_memory(dtlib):
+    """The blocks kept between calls go back to the driver; a later call
+    allocates afresh and gives the same simplices."""
+    import torch
+    p = inputs.make("bubbles", 300_000, 3, seed=2)
+    dp = torch.from_numpy(p).cuda()
+    print("[release] first run", flush=True)
+    a = oracle.canonical(dtlib.triangulate(dp, k=16, precision="fp32").rows())
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    dtlib.release_cached_memory()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free1 > free0
+    print("[release] second run", flush=True)
+    b = oracle.canonical(dtlib.triangulate(dp, k=16, precision="fp32").rows())
+    assert np.array_equal(a, b)
+    dtlib.release_cached_memory()
