@@ -31,11 +31,6 @@ static uint32_t sample_size(uint32_t n, double rate, int D) {
   return (uint32_t)e;
 }
 
-__global__ void k_fill_u32(uint32_t* x, uint32_t n, uint32_t v) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = v;
-}
-
 __global__ void k_set_of_point2(const uint32_t* off, uint32_t nsets, uint32_t n, uint32_t* pset) {
   uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
