@@ -12,7 +12,11 @@ compared with the oracle in the gpu tests).
    minimum over all samples, ties included.
 2. The Voronoi walk of the border test: a simplex of T_i whose circumball
    the walk does not flag holds no point of another partition, so every
-   simplex of T_i that is not in DT(P) is flagged."""
+   simplex of T_i that is not in DT(P) is flagged.  The same holds for the
+   clearance prefilter in front of it: a simplex is settled without the walk
+   when a vertex's least distance to a bisector of its own sample and a
+   foreign sample exceeds 2r (the GPU uses a lower bound of that distance,
+   which settles fewer)."""
 import numpy as np
 
 import oracle
@@ -134,6 +138,15 @@ def test_voronoi_walk_flags_every_non_delaunay_simplex():
     near = oracle.nearest_sample(p, S, sid)
     pid = part[near]
     full = {tuple(r) for r in oracle.delaunay(p)}
+    # clearance of every point from the foreign cells, over all samples
+    clear = np.empty(n)
+    for j in range(n):
+        t = near[j]
+        fs = np.nonzero(part != part[t])[0]
+        ds = np.einsum("ij,ij->i", p[j] - S[fs], p[j] - S[fs])
+        dt = float((p[j] - S[t]) @ (p[j] - S[t]))
+        clear[j] = np.min((ds - dt) / (2.0 * np.linalg.norm(S[fs] - S[t], axis=1)))
+    settled = 0
     flagged = missed = total = outside = 0
     for i in range(k):
         mine = np.nonzero(pid == i)[0]
@@ -148,9 +161,11 @@ def test_voronoi_walk_flags_every_non_delaunay_simplex():
             f = _walk_flags(c, r, S, sid, part, adj, i, t)
             flagged += f
             total += 1
+            pre = max(clear[j] for j in row) > 2.0 * r
+            settled += pre
             if tuple(row) not in full:
                 outside += 1
-                missed += not f
+                missed += (not f) + pre
     # the case has simplices to catch, and the walk does not flag everything
-    assert outside > 0 and flagged < total
+    assert outside > 0 and flagged < total and settled > 0
     assert missed == 0
