@@ -597,7 +597,8 @@ __global__ void k_start_cells(const double4* S, const uint32_t* start, const uin
                           F.lo[1] + (y + 0.5) * F.h, F.lo[2] + (z + 0.5) * F.h, &d2);
 }
 
-// Nearest sample by descent over the sample's Delaunay graph, exact under
+// Nearest sample (Algorithm 2: every point joins the block of its nearest
+// sample point) by descent over the sample's Delaunay graph, exact under
 // the key (fl(d^2), id).  The squared distance to x, taken over the sample
 // points, is the lifted height less an affine function, and the Delaunay
 // triangulation is the lower hull of the lifted points; so every set

@@ -114,7 +114,9 @@ __device__ bool region_hit(const Region& R, uint32_t me, const double* ctr, doub
   return false;
 }
 
-// Voronoi test over the sample's Delaunay graph, for the sample divide.
+// Voronoi test over the sample's Delaunay graph, for the sample divide (the
+// intersection test of Algorithm 1, "Border triangulation", against the
+// regions of Algorithm 2's partition).
 // First a greedy descent from the own sample t: move to the neighbour of
 // smallest key (fl(d^2) to the centre, id) while it beats the current one;
 // a sample that no Delaunay neighbour beats is the nearest to the centre up
