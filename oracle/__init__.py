@@ -15,11 +15,14 @@ Two layers:
       - sample_ids          Algorithm 2, the random sample of eta(n) points
       - graph_edges/weights Algorithm 2 + Table "weights", DT edges as graph
       - nearest_sample      Algorithm 2, nearest sample point of every point
-      - bucket_order        Algorithm 2, the partitions P_1..P_k as buckets
+      - buckets             Algorithm 2, the partitions P_1..P_k
       - kd_divide           Section "Recursive Bisection": cyclic median split
       - merge               Algorithm 1, "Merging"
       - partition metrics   Section "Partitioning Quality" (deviation, c_v,
                             o_DT, cut weight)
+      - certify             Section "Delaunay Triangulations": a certificate
+                            that a claimed simplex set is DT(P), for sizes
+                            beyond the plain triangulation's reach
 """
 from __future__ import annotations
 
@@ -63,8 +66,21 @@ def _load():
         lib.orc_insphere.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_insphere.restype = ctypes.c_int
         lib.orc_free.argtypes = [ctypes.c_void_p]
+        lib.orc_certify.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_Cert),
+                                    ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                    ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_certify.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+class _Cert(ctypes.Structure):
+    _fields_ = [("bad_rows", ctypes.c_int64), ("flat", ctypes.c_int64),
+                ("over_shared", ctypes.c_int64), ("interior", ctypes.c_int64),
+                ("hull", ctypes.c_int64), ("same_side", ctypes.c_int64),
+                ("not_local", ctypes.c_int64), ("unused", ctypes.c_int64),
+                ("edges", ctypes.c_int64), ("volume", ctypes.c_double)]
 
 
 class OracleError(RuntimeError):
@@ -126,6 +142,66 @@ def delaunay(points: np.ndarray, ids: np.ndarray | None = None) -> np.ndarray:
         lib.orc_free(out)
     loc = arr.reshape(-1, dim + 1).astype(np.int64)
     return canonical(ids[loc])
+
+
+def certify(points: np.ndarray, rows: np.ndarray, ids: np.ndarray | None = None) -> dict:
+    """Certificate that `rows` (m x (D+1) point indices) is DT(points)
+    under the perturbation of `delaunay` (Section "Delaunay
+    Triangulations"), computed in dt_oracle.c: counts of invalid rows, flat
+    simplices, facets in more than two simplices, interior facets whose
+    simplices lie on one side, interior facets that are not locally
+    Delaunay, unused points; the number of edges, interior and hull facets;
+    the summed volume; and the hull facets as sorted rows of D indices.
+    The caller compares the hull facets and the volume with the convex
+    hull.  ids: perturbation order (default: the index)."""
+    lib = _load()
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, dim = pts.shape
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    if r.ndim != 2 or r.shape[1] != dim + 1:
+        raise ValueError("rows must be m x (D+1)")
+    k = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
+    c = _Cert()
+    hp = ctypes.POINTER(ctypes.c_int32)()
+    nh = ctypes.c_int64(0)
+    st = lib.orc_certify(pts.ctypes.data, None if k is None else k.ctypes.data, n, dim,
+                         r.ctypes.data, len(r), ctypes.byref(c), ctypes.byref(hp), ctypes.byref(nh))
+    if st != OK:
+        raise OracleError(st)
+    try:
+        hull = np.ctypeslib.as_array(hp, shape=(nh.value * dim,)).copy() if nh.value else \
+            np.zeros(0, np.int32)
+    finally:
+        lib.orc_free(hp)
+    out = {f: getattr(c, f) for f, _ in _Cert._fields_}
+    out["hull_facets"] = hull.reshape(-1, dim).astype(np.int64)
+    out["n"], out["m"], out["dim"] = n, len(r), dim
+    return out
+
+
+def certificate_ok(cert: dict, hull_facets: np.ndarray, hull_volume: float,
+                   rtol: float = 1e-9) -> list[str]:
+    """The conditions under which a certified row set is DT(P): no
+    violation counts, the hull facets equal the convex hull's (sorted rows),
+    the volume equals the hull's, and the Euler characteristic of a
+    triangulated D-ball (V - E + F - T = 1 in 3D, V - E + F = 1 in 2D).
+    Returns the failed conditions (empty when all hold)."""
+    bad = [f for f in ("bad_rows", "flat", "over_shared", "same_side", "not_local", "unused")
+           if cert[f]]
+    mine = np.unique(np.sort(np.asarray(cert["hull_facets"]), axis=1), axis=0)
+    want = np.unique(np.sort(np.asarray(hull_facets, dtype=np.int64), axis=1), axis=0)
+    if mine.shape != want.shape or not np.array_equal(mine, want):
+        bad.append("hull_facets")
+    if not abs(cert["volume"] - hull_volume) <= rtol * abs(hull_volume):
+        bad.append("volume")
+    v = cert["n"] - cert["unused"]
+    if cert["dim"] == 3:
+        chi = v - cert["edges"] + (cert["interior"] + cert["hull"]) - cert["m"]
+    else:
+        chi = v - cert["edges"] + cert["m"]
+    if chi != 1:
+        bad.append("euler")
+    return bad
 
 
 def orient(pts: np.ndarray) -> int:
@@ -238,37 +314,12 @@ def nearest_sample(points: np.ndarray, sample_pts: np.ndarray,
     return out
 
 
-def morton_codes(points: np.ndarray) -> np.ndarray:
-    """Position along the Z-order (Morton) curve over the bounding box of
-    the points: every coordinate is scaled to [0, 1] in the box, clamped,
-    quantised to 10 bits in 3D (15 in 2D) by truncation, and the bits are
-    interleaved with x lowest (bit b of axis a goes to bit D*b + a)."""
-    p = np.asarray(points, dtype=np.float64)
-    n, d = p.shape
-    bits = 10 if d == 3 else 15
-    cells = float((1 << bits) - 1)
-    lo, hi = p.min(axis=0), p.max(axis=0)
-    w = hi - lo
-    inv = np.where(w > 0, 1.0 / np.where(w > 0, w, 1.0), 0.0)
-    codes = np.zeros(n, dtype=np.uint64)
-    for a in range(d):
-        t = np.minimum(np.maximum((p[:, a] - lo[a]) * inv[a], 0.0), 1.0) * cells
-        q = t.astype(np.uint64)
-        for b in range(bits):
-            codes |= ((q >> np.uint64(b)) & np.uint64(1)) << np.uint64(d * b + a)
-    return codes
-
-
-def bucket_order(pid: np.ndarray, points: np.ndarray | None = None) -> np.ndarray:
-    """The partitions P_1..P_k as contiguous buckets in partition order.
-    Inside a bucket the method allows any order; the library orders it
-    along the Morton curve of the whole input's bounding box (ties by
-    original index).  Without points: ascending original index."""
+def buckets(pid: np.ndarray, k: int) -> list[np.ndarray]:
+    """Algorithm 2: the partitions P_1..P_k -- P_i holds the points whose
+    nearest sample lies in block i.  Returned as ascending index arrays in
+    block order; the method fixes no order of the points inside a block."""
     pid = np.asarray(pid, dtype=np.int64)
-    if points is None:
-        return np.argsort(pid, kind="stable")
-    code = morton_codes(points)
-    return np.lexsort((np.arange(len(pid)), code, pid))
+    return [np.nonzero(pid == i)[0] for i in range(k)]
 
 
 def kd_divide(points: np.ndarray, k: int) -> np.ndarray:

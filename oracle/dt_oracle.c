@@ -235,12 +235,15 @@ static int exact_in_core(int D, const double *const *P) {
 /* Each evaluates the same polynomial in double precision.  With every  */
 /* operation rounding to nearest, the computed value is                 */
 /*   sum_t term_t * prod_{j<=K} (1 + d_j),  |d_j| <= u = 2^-53,         */
-/* where K is the longest chain of operations from an input coordinate  */
-/* to the result.  Hence |err| <= gamma_K * P with P the same polynomial */
-/* over absolute values, and the P computed in floating point is at      */
-/* least P*(1 - gamma_K).  So |value| > 2*K*u*P_computed certifies the   */
-/* sign.  Results near the underflow range go to the exact path.        */
-/* The K used below are upper bounds on the actual chain lengths.       */
+/* where K counts, for the longest term, the rounded differences that   */
+/* enter it (one per input factor, i.e. its degree) plus the rounded    */
+/* products and sums on its path to the result.  Hence                  */
+/* |err| <= gamma_K * P with P the same polynomial over absolute values, */
+/* and the P computed in floating point is at least P*(1 - gamma_K).    */
+/* gamma_K * P <= K*u*P_computed*(1 + O(K u)), so |value| > K*u*P_comp. */
+/* certifies the sign up to that O(Ku) term; the bound used is twice    */
+/* that, the factor 2 being slack.  Results near the underflow range go */
+/* to the exact path.                                                   */
 /* ------------------------------------------------------------------ */
 #define U53 (DBL_EPSILON * 0.5)
 #define TINY 1e-280
@@ -253,8 +256,8 @@ static int certify(double v, double perm, int K, int *sign) {
     return 0;
 }
 
-/* det[p_i - p_0], chain length: sub 1, mul 2, sub 3 (2D);
- * sub 1, mul 2, sub 3, mul 4, add 5, add 6 (3D). */
+/* det[p_i - p_0].  2D: degree 2, path mul, sub -> K = 2 + 2 = 4.
+ * 3D: degree 3, path mul, sub (minor), mul, sub, add -> K = 3 + 5 = 8. */
 static int or_filter(int D, const double *const *P, int *sign) {
     if (D == 2) {
         double ax = P[1][0] - P[0][0], ay = P[1][1] - P[0][1];
@@ -280,7 +283,12 @@ static int or_filter(int D, const double *const *P, int *sign) {
     }
 }
 
-/* det[p_i - q, |p_i - q|^2]; chain length <= 6 (2D) and <= 10 (3D). */
+/* det[p_i - q, |p_i - q|^2].
+ * 2D: degree 4; path mul, add (height), mul, sub (minor), mul, sub, add
+ *     -> K = 4 + 7 = 11.
+ * 3D: degree 5; path mul, add, add (height), mul, sub (2x2 minor), mul,
+ *     sub, add (3x3 minor), mul (height times minor), three accumulations
+ *     (the first, from 0, is exact) -> K = 5 + 12 = 17. */
 static int in_filter(int D, const double *const *P, int *sign) {
     const double *q = P[D + 1];
     if (D == 2) {
@@ -299,7 +307,7 @@ static int in_filter(int D, const double *const *P, int *sign) {
         double p2 = fabs(x[0] * y[1]) + fabs(y[0] * x[1]);
         double v = l[0] * m0 - l[1] * m1 + l[2] * m2;
         double p = la[0] * p0 + la[1] * p1 + la[2] * p2;
-        return certify(v, p, 8, sign);
+        return certify(v, p, 11, sign);
     } else {
         double d[4][3], l[4];
         for (int i = 0; i < 4; i++) {
@@ -325,7 +333,7 @@ static int in_filter(int D, const double *const *P, int *sign) {
             if ((i + 3) & 1) v -= term; else v += term;
             p += l[i] * q3;
         }
-        return certify(v, p, 14, sign);
+        return certify(v, p, 17, sign);
     }
 }
 
@@ -843,6 +851,219 @@ int orc_dt(const double *X, const int64_t *keys, int64_t n, int D,
     free(T.cv); free(T.cn); free(T.mark); free(T.seen); free(T.dead); free(T.freel);
     free(kk);
     return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Certificate of a claimed Delaunay triangulation.                      */
+/* A set of full-dimensional simplices on the input points is DT(P)     */
+/* (paper, Section "Delaunay Triangulations": no point inside any        */
+/* simplex's circumsphere) when it is a triangulation of P that is       */
+/* locally Delaunay at every interior facet:                            */
+/*   - every facet lies in at most two simplices, the two of an interior */
+/*     facet on opposite sides of it, the facets in one simplex are the  */
+/*     convex hull's facets (checked by the caller), and the volumes sum */
+/*     to the hull's volume (checked by the caller): the simplices then  */
+/*     tile the convex hull exactly once;                               */
+/*   - every point is a vertex (under the perturbed lifting every point */
+/*     is a vertex of the lower hull);                                  */
+/*   - for every interior facet, the apex of one simplex is outside the */
+/*     other's circumsphere under the same perturbation as orc_dt: the   */
+/*     lifted simplices then form a locally convex, hence convex, lower  */
+/*     surface, which is the lower hull of the lifted points.           */
+/* Counts of every violation are returned; the hull facets (in one      */
+/* simplex only) are returned as sorted rows of D point indices.         */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t bad_rows;     /* an index out of range or repeated in a row   */
+    int64_t flat;         /* simplices with Orient1 = 0                   */
+    int64_t over_shared;  /* facets in more than two simplices            */
+    int64_t interior;     /* facets in exactly two simplices              */
+    int64_t hull;         /* facets in exactly one simplex                */
+    int64_t same_side;    /* interior facets with both apexes on one side */
+    int64_t not_local;    /* interior facets failing the empty-sphere test */
+    int64_t unused;       /* points that are no vertex                    */
+    int64_t edges;        /* distinct edges                               */
+    double volume;        /* sum of the simplices' volumes                */
+} orc_cert_t;
+
+typedef struct { uint32_t a, b, row; int32_t j; } facet_t;
+
+static int facet_cmp(const void *x, const void *y) {
+    const facet_t *f = x, *g = y;
+    if (f->a != g->a) return f->a < g->a ? -1 : 1;
+    if (f->b != g->b) return f->b < g->b ? -1 : 1;
+    return 0;
+}
+static int u32_cmp(const void *x, const void *y) {
+    uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
+    return a < b ? -1 : (a > b);
+}
+
+int orc_certify(const double *X, const int64_t *keys, int64_t n, int D, const int32_t *rows,
+                int64_t m, orc_cert_t *out, int32_t **hull_out, int64_t *nhull) {
+    memset(out, 0, sizeof(*out));
+    *hull_out = NULL;
+    *nhull = 0;
+    if ((D != 2 && D != 3) || n < 0 || m < 0) return ORC_INVALID;
+    const int V = D + 1;
+    int64_t *kk = NULL;
+    if (!keys) {
+        kk = malloc(sizeof(int64_t) * (size_t)(n + 1));
+        if (!kk) return ORC_NOMEM;
+        for (int64_t i = 0; i < n; i++) kk[i] = i;
+        keys = kk;
+    }
+    uint8_t *used = calloc((size_t)n + 1, 1);
+    int64_t *fcnt = calloc((size_t)n + 1, sizeof(int64_t));   /* facets per smallest vertex */
+    int64_t *ecnt = calloc((size_t)n + 1, sizeof(int64_t));   /* edges per smallest vertex */
+    int32_t *srt = malloc(sizeof(int32_t) * (size_t)(m * V + 1));
+    uint8_t *okrow = malloc((size_t)m + 1);
+    if (!used || !fcnt || !ecnt || !srt || !okrow) {
+        free(used); free(fcnt); free(ecnt); free(srt); free(okrow); free(kk);
+        return ORC_NOMEM;
+    }
+    long double vol = 0.0L;
+    const double fact = (D == 2) ? 2.0 : 6.0;
+    /* rows: validity, orientation, volume; sorted copies */
+    for (int64_t r = 0; r < m; r++) {
+        int32_t *v = srt + r * V;
+        int ok = 1;
+        for (int i = 0; i < V; i++) {
+            v[i] = rows[r * V + i];
+            if (v[i] < 0 || v[i] >= n) ok = 0;
+        }
+        for (int i = 1; i < V; i++)
+            for (int j = i; j > 0 && v[j] < v[j - 1]; j--) {
+                int32_t t = v[j]; v[j] = v[j - 1]; v[j - 1] = t;
+            }
+        for (int i = 1; i < V && ok; i++)
+            if (v[i] == v[i - 1]) ok = 0;
+        okrow[r] = (uint8_t)ok;
+        if (!ok) { out->bad_rows++; continue; }
+        const double *P[4];
+        for (int i = 0; i < V; i++) P[i] = X + (int64_t)v[i] * D;
+        if (orient1(D, P) == 0) out->flat++;
+        double det;
+        if (D == 2) {
+            det = (P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[1][1] - P[0][1]) * (P[2][0] - P[0][0]);
+        } else {
+            double a[3], b[3], c[3];
+            for (int k = 0; k < 3; k++) {
+                a[k] = P[1][k] - P[0][k];
+                b[k] = P[2][k] - P[0][k];
+                c[k] = P[3][k] - P[0][k];
+            }
+            det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                  a[2] * (b[0] * c[1] - b[1] * c[0]);
+        }
+        vol += (long double)fabs(det) / fact;
+        for (int i = 0; i < V; i++) used[v[i]] = 1;
+        for (int j = 0; j < V; j++) fcnt[v[j == 0 ? 1 : 0]]++;
+        for (int i = 0; i < V; i++)
+            for (int j = i + 1; j < V; j++) ecnt[v[i]]++;
+    }
+    out->volume = (double)vol;
+    for (int64_t i = 0; i < n; i++)
+        if (!used[i]) out->unused++;
+    /* bucket the facets by their smallest vertex (counting sort) */
+    int64_t *fstart = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *estart = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!fstart || !estart) {
+        free(used); free(fcnt); free(ecnt); free(srt); free(okrow); free(kk);
+        free(fstart); free(estart);
+        return ORC_NOMEM;
+    }
+    int64_t fs = 0, es = 0;
+    for (int64_t i = 0; i < n; i++) {
+        fstart[i] = fs; fs += fcnt[i]; fcnt[i] = fstart[i];
+        estart[i] = es; es += ecnt[i]; ecnt[i] = estart[i];
+    }
+    fstart[n] = fs;
+    estart[n] = es;
+    facet_t *F = malloc(sizeof(facet_t) * (size_t)(fs + 1));
+    uint32_t *E = malloc(sizeof(uint32_t) * (size_t)(es + 1));
+    if (!F || !E) {
+        free(used); free(fcnt); free(ecnt); free(srt); free(okrow); free(kk);
+        free(fstart); free(estart); free(F); free(E);
+        return ORC_NOMEM;
+    }
+    for (int64_t r = 0; r < m; r++) {
+        if (!okrow[r]) continue;
+        const int32_t *v = srt + r * V;
+        for (int j = 0; j < V; j++) {
+            int32_t f[3];
+            int c = 0;
+            for (int i = 0; i < V; i++)
+                if (i != j) f[c++] = v[i];
+            facet_t x;
+            x.a = (uint32_t)f[1];
+            x.b = (D == 3) ? (uint32_t)f[2] : 0u;
+            x.row = (uint32_t)r;
+            x.j = j;
+            F[fcnt[f[0]]++] = x;
+        }
+        for (int i = 0; i < V; i++)
+            for (int j = i + 1; j < V; j++) E[ecnt[v[i]]++] = (uint32_t)v[j];
+    }
+    /* distinct edges */
+    for (int64_t u = 0; u < n; u++) {
+        int64_t a = estart[u], b = estart[u + 1];
+        if (b - a > 1) qsort(E + a, (size_t)(b - a), sizeof(uint32_t), u32_cmp);
+        for (int64_t i = a; i < b; i++)
+            if (i == a || E[i] != E[i - 1]) out->edges++;
+    }
+    /* facets: pairing, sides, local Delaunay */
+    int64_t hcap = 1024, hn = 0;
+    int32_t *H = malloc(sizeof(int32_t) * (size_t)hcap * D);
+    int st = H ? ORC_OK : ORC_NOMEM;
+    for (int64_t u = 0; u < n && st == ORC_OK; u++) {
+        int64_t a = fstart[u], b = fstart[u + 1];
+        if (b - a > 1) qsort(F + a, (size_t)(b - a), sizeof(facet_t), facet_cmp);
+        for (int64_t i = a; i < b;) {
+            int64_t e = i + 1;
+            while (e < b && F[e].a == F[i].a && F[e].b == F[i].b) e++;
+            int32_t fv[3] = {(int32_t)u, (int32_t)F[i].a, (int32_t)F[i].b};
+            if (e - i > 2) {
+                out->over_shared++;
+            } else if (e - i == 1) {
+                out->hull++;
+                if (hn == hcap) {
+                    int32_t *h2 = realloc(H, sizeof(int32_t) * (size_t)hcap * 2 * D);
+                    if (!h2) { st = ORC_NOMEM; break; }
+                    H = h2;
+                    hcap *= 2;
+                }
+                for (int k = 0; k < D; k++) H[hn * D + k] = fv[k];
+                hn++;
+            } else {
+                out->interior++;
+                const int32_t *r1 = srt + (int64_t)F[i].row * V, *r2 = srt + (int64_t)F[i + 1].row * V;
+                int32_t pa = r1[F[i].j], pb = r2[F[i + 1].j];
+                const double *P[5];
+                int64_t kq[5];
+                for (int k = 0; k < D; k++) { P[k] = X + (int64_t)fv[k] * D; kq[k] = keys[fv[k]]; }
+                P[D] = X + (int64_t)pa * D;
+                kq[D] = keys[pa];
+                int oa = orient1(D, P);
+                P[D] = X + (int64_t)pb * D;
+                int ob = orient1(D, P);
+                if (oa == 0 || ob == 0 || oa == ob) out->same_side++;
+                /* pb against the circumsphere of (facet, pa) */
+                P[D] = X + (int64_t)pa * D;
+                P[D + 1] = X + (int64_t)pb * D;
+                kq[D + 1] = keys[pb];
+                int s = in_pert(D, P, kq);
+                if (oa == 0 || s == 0 || oa * s > 0) out->not_local++;
+            }
+            i = e;
+        }
+    }
+    free(used); free(fcnt); free(ecnt); free(srt); free(okrow); free(kk);
+    free(fstart); free(estart); free(F); free(E);
+    if (st != ORC_OK) { free(H); return st; }
+    *hull_out = H;
+    *nhull = hn;
+    return ORC_OK;
 }
 
 void orc_free(void *p) { free(p); }

@@ -81,6 +81,18 @@ def test_perturbation_matches_eps_polynomial(dim):
     assert checked >= 3 * 24
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_predicates_in_the_filter_band(dim):
+    """Near-ties with relative offsets 2^-20 .. 2^-60, scaled by 2^-80 ..
+    2^80, and query points next to a vertex: the floating-point filters must
+    hand every case they cannot certify to the exact stage."""
+    from tests import near_ties
+    for q in near_ties.insphere_queries(dim, 160, seed=31 + dim):
+        assert oracle.insphere(q) == X.insphere_sign(q), q
+    for q in near_ties.orient_queries(dim, 160, seed=41 + dim):
+        assert oracle.orient(q) == X.orient1(q), q
+
+
 # ----------------------------------------------------------------- DT checks
 def _conflict_ref(pts, ids, simplex, q):
     """Brute-force perturbed conflict test with exact Fraction arithmetic."""

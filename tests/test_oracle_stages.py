@@ -79,49 +79,10 @@ def test_nearest_sample_brute_force_with_ties():
     assert got[-1] == 5
 
 
-def test_bucket_order_stable():
+def test_buckets_are_the_partitions():
     pid = np.array([2, 0, 1, 0, 2, 1, 0])
-    assert oracle.bucket_order(pid).tolist() == [1, 3, 6, 2, 5, 0, 4]
-
-
-def test_morton_codes_closed_forms():
-    """Corners of the box: one axis at its maximum sets every D-th bit from
-    that axis' offset (the sums of geometric series); the origin is 0."""
-    p3 = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0],
-                   [1.0, 1.0, 1.0]])
-    c3 = oracle.morton_codes(p3)
-    ones3 = (8 ** 10 - 1) // 7            # bits 0, 3, ..., 27
-    assert c3.tolist() == [0, ones3, 2 * ones3, 4 * ones3, 7 * ones3]
-    p2 = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
-    ones2 = (4 ** 15 - 1) // 3            # bits 0, 2, ..., 28
-    assert oracle.morton_codes(p2).tolist() == [0, ones2, 2 * ones2, 3 * ones2]
-
-
-def test_morton_codes_bit_interleave_brute_force():
-    """Against a string-built interleaving of the truncated cell indices."""
-    rng = np.random.default_rng(5)
-    for d, bits in ((2, 15), (3, 10)):
-        p = rng.random((200, d)) * 7.0 - 3.0
-        lo, hi = p.min(0), p.max(0)
-        got = oracle.morton_codes(p)
-        for i in range(len(p)):
-            q = [int(min(max((p[i, a] - lo[a]) * (1.0 / (hi[a] - lo[a])), 0.0), 1.0)
-                     * ((1 << bits) - 1)) for a in range(d)]
-            s = "".join(str((q[a] >> b) & 1) for b in reversed(range(bits))
-                        for a in reversed(range(d)))
-            assert int(got[i]) == int(s, 2)
-
-
-def test_bucket_order_with_points_groups_and_follows_curve():
-    p = inputs.uniform(500, 3, seed=3)
-    pid = np.arange(500) % 4
-    order = oracle.bucket_order(pid, p)
-    assert sorted(order.tolist()) == list(range(500))
-    assert np.all(np.diff(pid[order]) >= 0)
-    code = oracle.morton_codes(p)
-    for b in range(4):
-        inb = order[pid[order] == b]
-        assert np.all(np.diff(code[inb].astype(np.int64)) >= 0)
+    b = oracle.buckets(pid, 4)
+    assert [x.tolist() for x in b] == [[1, 3, 6], [2, 5], [0, 4], []]
 
 
 def test_kd_divide_boxes():
