@@ -214,12 +214,53 @@ void dt_result_free(dt_result* r);
  *   DT_ARR_BORDER_DT int32[m_b x (D+1)] finite simplices of T_B
  *   DT_ARR_NEAREST   int32[n]    nearest sample of every point (index into
  *                    DT_ARR_SAMPLE; sample divide only)
+ *   DT_ARR_GRAPH     int32[e x 2] edges of the sample's Delaunay graph
+ *                    (Algorithm 2), input indices u < v, rows ascending
+ *                    (sample divide only)
+ *   DT_ARR_WEIGHTS   double[e]   weight of each DT_ARR_GRAPH edge (Table
+ *                    "weights", with the chosen dt_options.weight)
  * `count` receives the number of elements (rows x columns); pass dst = NULL
  * to query it.
  */
 enum { DT_ARR_SAMPLE = 0, DT_ARR_SAMPLE_DT, DT_ARR_PART, DT_ARR_PID, DT_ARR_ORDER,
-       DT_ARR_BORDER_V, DT_ARR_LOCAL, DT_ARR_BORDER_DT, DT_ARR_NEAREST, DT_NUM_ARR };
+       DT_ARR_BORDER_V, DT_ARR_LOCAL, DT_ARR_BORDER_DT, DT_ARR_NEAREST, DT_ARR_GRAPH,
+       DT_ARR_WEIGHTS, DT_NUM_ARR };
 int dt_result_stage(const dt_result* r, int which, void* dst, int64_t cap, int64_t* count);
+
+/*
+ * dt_predicates -- the two geometric predicates that decide every
+ * combinatorial step of the method (Section "Geometric Primitives"; the
+ * triangulations rely on exact orientation and in-sphere tests), on a batch
+ * of point tuples, evaluated on the device by the same chain of filters the
+ * triangulation uses: with DT_PREC_FP32 an FP32 filter, then an FP64 filter,
+ * then exact expansion arithmetic; with DT_PREC_FP64 the last two.  Each
+ * filter certifies a sign only above its a-priori rounding bound, so the
+ * answer is always the exact sign.
+ *   kind   DT_PRED_ORIENT:   sign of Orient1(p_0..p_D) = det[p_i 1] (may be 0);
+ *          DT_PRED_INSPHERE: sign of In(p_0..p_D, q) =
+ *                            det[p_i |p_i|^2 1; q |q|^2 1] under the symbolic
+ *                            perturbation of the lifting by `keys` (a
+ *                            smaller key perturbs more); positive means q
+ *                            is inside the circumsphere of a positively
+ *                            oriented p_0..p_D.  Never 0 unless p_0..p_D
+ *                            and q are all on one hyperplane.
+ *   D      2 or 3
+ *   pts    device memory, nq tuples of np = D+1 (orient) or D+2 (in-sphere,
+ *          q last) points, row-major doubles: coordinate a of point i of
+ *          tuple t at pts[(t*np + i)*D + a]; coordinates must be finite
+ *   keys   device memory, nq x np int64 perturbation keys (in-sphere only;
+ *          NULL = the position 0..np-1 inside the tuple); unused for orient
+ *   sign   device memory, nq int8 results (-1, 0, 1)
+ *   stage  device memory or NULL, nq int8: 0 decided by the FP32 filter,
+ *          1 by the FP64 filter, 2 by the exact stage
+ * The caller owns every buffer.  Synchronises `stream`.  DT_OK,
+ * DT_E_INVALID_ARG (kind, D, precision, nq < 0, NULL pointers),
+ * DT_E_INTERNAL (exact-stage capacity exceeded; results invalid),
+ * DT_E_DEVICE, DT_E_NOMEM.
+ */
+enum { DT_PRED_ORIENT = 0, DT_PRED_INSPHERE = 1 };
+int dt_predicates(int kind, int D, int precision, const double* pts, const int64_t* keys,
+                  int64_t nq, int8_t* sign, int8_t* stage, void* stream);
 
 /*
  * dt_batch_triangulate -- DT of many independent point sets in one batched

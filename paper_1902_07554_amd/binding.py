@@ -28,13 +28,13 @@ STAGES = ["validate", "sample", "sample_dt", "partition", "assign", "scatter", "
 KERNELS = ["k4_pick", "k4_cavity", "k4_insert", "assign", "bucket", "border", "merge",
            "k4_select"]
 ARR = {"sample": 0, "sample_dt": 1, "part": 2, "pid": 3, "order": 4, "border_v": 5,
-       "local": 6, "border_dt": 7, "nearest": 8}
+       "local": 6, "border_dt": 7, "nearest": 8, "graph": 9, "weights": 10}
 EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_count",
            "dt_result_dim", "dt_result_copy", "dt_result_stats", "dt_result_free",
            "dt_result_stage", "dt_batch_triangulate", "dt_result_set_offsets",
            "dt_server_create", "dt_server_submit", "dt_server_poll", "dt_server_wait",
            "dt_server_times", "dt_server_destroy", "dt_batch_autotune", "dt_result_neighbors",
-           "dt_release_cached_memory"]
+           "dt_release_cached_memory", "dt_predicates"]
 
 
 class Options(ctypes.Structure):
@@ -130,6 +130,8 @@ def load():
     lib.dt_server_times.restype = I
     lib.dt_server_destroy.argtypes = [VP]
     lib.dt_server_destroy.restype = None
+    lib.dt_predicates.argtypes = [I, I, I, VP, VP, I64, VP, VP, VP]
+    lib.dt_predicates.restype = I
     lib.dt_release_cached_memory.argtypes = []
     lib.dt_release_cached_memory.restype = I
     _lib = lib
@@ -250,7 +252,7 @@ class Result:
         st = lib.dt_result_stage(self.h, which, None, 0, ctypes.byref(cnt))
         if st != DT_OK:
             raise DTError(st)
-        dt = np.int64 if name == "sample" else np.int32
+        dt = {"sample": np.int64, "weights": np.float64}.get(name, np.int32)
         out = np.empty(cnt.value, dtype=dt)
         if cnt.value:
             st = lib.dt_result_stage(self.h, which, out.ctypes.data, cnt.value, ctypes.byref(cnt))
@@ -261,6 +263,8 @@ class Result:
             return out.reshape(-1, d + 1)
         if name == "local":
             return out.reshape(-1, d + 2)
+        if name == "graph":
+            return out.reshape(-1, 2)
         return out
 
     def set_offsets(self, num_sets: int) -> np.ndarray:
@@ -269,6 +273,32 @@ class Result:
         if st != DT_OK:
             raise DTError(st)
         return out
+
+
+def predicates(kind: str, tuples, keys=None, precision: str = "fp64"):
+    """dt_predicates: signs (and deciding stages) of orientation
+    ("orient") or in-sphere ("insphere") tests on (q, np, D) point tuples.
+    Inputs are moved to the GPU with torch; returns two numpy int8 arrays
+    (sign, stage: 0 FP32 filter, 1 FP64 filter, 2 exact)."""
+    import torch
+    lib = load()
+    t = torch.as_tensor(np.ascontiguousarray(tuples, dtype=np.float64)).cuda()
+    nq, npts, d = t.shape
+    kt = None
+    if keys is not None:
+        kt = torch.as_tensor(np.ascontiguousarray(keys, dtype=np.int64)).cuda()
+        if tuple(kt.shape) != (nq, npts):
+            raise ValueError("keys must be (q, np)")
+    sign = torch.empty(nq, dtype=torch.int8, device=t.device)
+    stage = torch.empty(nq, dtype=torch.int8, device=t.device)
+    st = lib.dt_predicates({"orient": 0, "insphere": 1}[kind], d, PRECISION[precision],
+                           ctypes.c_void_p(t.data_ptr()),
+                           ctypes.c_void_p(kt.data_ptr()) if kt is not None else None, nq,
+                           ctypes.c_void_p(sign.data_ptr()), ctypes.c_void_p(stage.data_ptr()),
+                           ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream))
+    if st != DT_OK:
+        raise DTError(st)
+    return sign.cpu().numpy(), stage.cpu().numpy()
 
 
 def triangulate(points, k: int = 1, sample_rate: float = 0.0, **opts) -> Result:

@@ -18,12 +18,16 @@
 //      non-overlapping doubles built from the error-free two-sum and
 //      two-product transformations; Shewchuk 1997) on the original
 //      coordinates.
-// Error bounds: a value computed through a chain of at most K rounded
-// operations from exact inputs satisfies |err| <= gamma_K * P, where P is
-// the same polynomial over absolute values and gamma_K = K u / (1 - K u);
-// P itself is computed with relative error <= gamma_K.  Hence
-// |value| > 2 K u P_hat certifies the sign (u = 2^-53 for FP64, 2^-24 for
-// FP32).  Each K below bounds the chain length of its expression.
+// Error bounds: for the longest term of an expression, K counts the
+// roundings it passes through: one per input factor (the rounded
+// coordinate differences; in FP32 two, the FP64 difference and the
+// conversion) plus the rounded products and sums on its path to the
+// result.  The computed value then satisfies |err| <= gamma_K * P, where P
+// is the same polynomial over absolute values and gamma_K = K u / (1 - K u);
+// P itself is computed with relative error <= gamma_K.  So |value| >
+// K u P_hat certifies the sign up to terms of order (K u)^2; the bound used
+// is 2 K u P_hat, the factor 2 being slack (u = 2^-53 for FP64, 2^-24 for
+// FP32).
 //
 // Ties (In = 0 exactly) are broken by a symbolic perturbation of the
 // lifting: the height of point i becomes |p_i|^2 + eps_i with
@@ -318,7 +322,8 @@ __device__ __forceinline__ int cert64(double v, double p, double K) {
   return (v > b) ? 1 : ((v < -b) ? -1 : 0);
 }
 
-// sign det[p_i - p_0] (D x D); chain <= 3 (2D) / 6 (3D)
+// sign det[p_i - p_0] (D x D).  2D: degree 2, path mul, sub -> K = 4.
+// 3D: degree 3, path mul, sub (minor), mul, sub, add -> K = 3 + 5 = 8.
 template <int D>
 __device__ __forceinline__ int orient_f64(const PtsX& X) {
   if (D == 2) {
@@ -338,7 +343,12 @@ __device__ __forceinline__ int orient_f64(const PtsX& X) {
   }
 }
 
-// sign det[p_i - q, |p_i - q|^2] ((D+1)x(D+1)); chain <= 6 (2D) / 10 (3D)
+// sign det[p_i - q, |p_i - q|^2] ((D+1)x(D+1)).
+// 2D: degree 4; path mul, add (height), mul, sub (minor), mul, sub, add
+//     -> K = 4 + 7 = 11.
+// 3D: degree 5; path mul, add, add (height), mul, sub (2x2 minor), mul,
+//     sub, add (3x3 minor), mul, three accumulations (the first, from 0,
+//     is exact) -> K = 5 + 12 = 17.
 template <int D>
 __device__ __forceinline__ int in_f64(const PtsX& X) {
   if (D == 2) {
@@ -350,7 +360,7 @@ __device__ __forceinline__ int in_f64(const PtsX& X) {
     double a = x1 * y2, b = y1 * x2, cc = x0 * y2, d = y0 * x2, e = x0 * y1, f = y0 * x1;
     double v = l0 * (a - b) - l1 * (cc - d) + l2 * (e - f);
     double p = l0 * (fabs(a) + fabs(b)) + l1 * (fabs(cc) + fabs(d)) + l2 * (fabs(e) + fabs(f));
-    return cert64(v, p, 8.0);
+    return cert64(v, p, 11.0);
   } else {
     const double* q = X.p[4];
     double d[4][3], l[4];
@@ -375,7 +385,7 @@ __device__ __forceinline__ int in_f64(const PtsX& X) {
       v = ((i & 1) == 0) ? v - t : v + t;   // cofactor sign (-1)^(i+3)
       p += l[i] * q3;
     }
-    return cert64(v, p, 14.0);
+    return cert64(v, p, 17.0);
   }
 }
 
@@ -384,8 +394,9 @@ __device__ __forceinline__ int in_f64(const PtsX& X) {
 // in [1, 2), then rounded to FP32.  Per input factor that is two roundings
 // (FP64 subtraction, folded into an FP32 unit, and the conversion); a term
 // of degree g with a chain of c FP32 operations thus carries K = 2g + c
-// units of 2^-24.  Underflow of FP32 intermediates is absorbed by an
-// absolute allowance far above any possible accumulation (< 1e-40).
+// units of 2^-24 (the paths are those of the FP64 filters).  Underflow of
+// FP32 intermediates (each at most 2^-150 absolute, a few hundred of them)
+// is absorbed by an absolute allowance of 1e-36, far above their sum.
 constexpr float U32 = 5.9604645e-08f;   // 2^-24
 
 __device__ __forceinline__ int cert32(float v, float p, float K) {
@@ -430,7 +441,7 @@ __device__ __forceinline__ int orient_f32(const PtsX& X) {
     float v = A0 * (x12 - x21) - A1 * (x02 - x20) + A2 * (x01 - x10);
     float p = fabsf(A0) * (fabsf(x12) + fabsf(x21)) + fabsf(A1) * (fabsf(x02) + fabsf(x20)) +
               fabsf(A2) * (fabsf(x01) + fabsf(x10));
-    return cert32(v, p, 12.0f);                                  // g=3, c=6
+    return cert32(v, p, 11.0f);                                  // g=3, c=5
   }
 }
 
@@ -460,7 +471,7 @@ __device__ __forceinline__ int in_f32(const PtsX& X) {
     float v = L[0] * (a - b) - L[1] * (cc - d) + L[2] * (e - f);
     float p = L[0] * (fabsf(a) + fabsf(b)) + L[1] * (fabsf(cc) + fabsf(d)) +
               L[2] * (fabsf(e) + fabsf(f));
-    return cert32(v, p, 14.0f);                                  // g=4, c=6
+    return cert32(v, p, 15.0f);                                  // g=4, c=7
   } else {
     const double* q = X.p[4];
     double d[4][3];
@@ -497,7 +508,7 @@ __device__ __forceinline__ int in_f32(const PtsX& X) {
       v = ((i & 1) == 0) ? v - t : v + t;
       p += L[i] * q3;
     }
-    return cert32(v, p, 20.0f);                                  // g=5, c=10
+    return cert32(v, p, 22.0f);                                  // g=5, c=12
   }
 }
 
