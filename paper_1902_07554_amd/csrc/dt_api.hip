@@ -378,7 +378,7 @@ extern "C" int dt_result_stage(const dt_result* r, int which, void* dst, int64_t
                                int64_t* count) {
   if (!r || which < 0 || which >= DT_NUM_ARR || !count) return DT_E_INVALID_ARG;
   const std::vector<char>& a = r->stage[which];
-  int64_t esz = (which == DT_ARR_SAMPLE) ? 8 : 4;
+  int64_t esz = (which == DT_ARR_SAMPLE || which == DT_ARR_WEIGHTS) ? 8 : 4;
   *count = (int64_t)a.size() / esz;
   if (!dst) return DT_OK;
   if (cap < *count) return DT_E_INVALID_ARG;

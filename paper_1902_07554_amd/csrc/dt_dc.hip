@@ -153,7 +153,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
   S.stage_ms[DT_STAGE_VALIDATE] = t1 - t0;
 
   // ---- divide
-  DevBuf pid, sid, Sp, part, nearest, boxes, goff, gadj;
+  DevBuf pid, sid, Sp, part, nearest, boxes, goff, gadj, gw;
   SampleGrid sgrid;
   CellPool spool;
   LocalJob sjob;
@@ -198,7 +198,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     double tb = now_ms();
     S.stage_ms[DT_STAGE_SAMPLE_DT] = tb - ta;
     DT_TRY(partition_sample(Sp.as<double4>(), eta, D, spool, (uint32_t)k, o, lo, hi, part, &cut,
-                            goff, gadj, st));
+                            goff, gadj, gw, st));
     double tc = now_ms();
     S.stage_ms[DT_STAGE_PARTITION] = tc - tb;
     DT_TRY(assign_points(P.as<double4>(), n, Sp.as<double4>(), eta, D, part.as<uint32_t>(), lo, hi,
@@ -363,6 +363,36 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
       for (uint32_t i = 0; i < eta; i++) d[i] = h[i];
       DT_TRY(pool_rows_host(sjob, spool, D, r->stage[DT_ARR_SAMPLE_DT], st));
       DT_TRY(to_host<uint32_t>(r->stage[DT_ARR_PART], part.p, eta, st));
+      // the sample graph as edges (u < v, input ids) with their weights
+      {
+        std::vector<uint32_t> ho(eta + 1);
+        DT_HIP(hipMemcpyAsync(ho.data(), goff.p, (size_t)(eta + 1) * 4, hipMemcpyDeviceToHost, st));
+        DT_HIP(hipStreamSynchronize(st));
+        const uint32_t na = ho[eta];
+        std::vector<uint32_t> ha(na);
+        std::vector<double> hw(na);
+        if (na) {
+          DT_HIP(hipMemcpyAsync(ha.data(), gadj.p, (size_t)na * 4, hipMemcpyDeviceToHost, st));
+          DT_HIP(hipMemcpyAsync(hw.data(), gw.p, (size_t)na * 8, hipMemcpyDeviceToHost, st));
+          DT_HIP(hipStreamSynchronize(st));
+        }
+        // sample-local index v is the v-th smallest sample id, and every
+        // adjacency list is sorted, so v's entries above v come out in
+        // (u, v) order
+        std::vector<int32_t> ed;
+        std::vector<double> ew;
+        for (uint32_t v = 0; v < eta; v++)
+          for (uint32_t i = ho[v]; i < ho[v + 1]; i++)
+            if (ha[i] > v) {
+              ed.push_back((int32_t)h[v]);
+              ed.push_back((int32_t)h[ha[i]]);
+              ew.push_back(hw[i]);
+            }
+        r->stage[DT_ARR_GRAPH].resize(ed.size() * 4);
+        if (!ed.empty()) memcpy(r->stage[DT_ARR_GRAPH].data(), ed.data(), ed.size() * 4);
+        r->stage[DT_ARR_WEIGHTS].resize(ew.size() * 8);
+        if (!ew.empty()) memcpy(r->stage[DT_ARR_WEIGHTS].data(), ew.data(), ew.size() * 8);
+      }
       DT_TRY(to_host<uint32_t>(r->stage[DT_ARR_NEAREST], nearest.p, n, st));
     }
     DT_TRY(to_host<uint32_t>(r->stage[DT_ARR_PID], pid.p, n, st));

@@ -433,7 +433,8 @@ __global__ __launch_bounds__(256) void k_count_u32_lds(const uint32_t* x, uint32
 
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
                      const dt_options& o, const double lo[3], const double hi[3],
-                     DevBuf& part, double* cut, DevBuf& goff, DevBuf& gadj, hipStream_t st) {
+                     DevBuf& part, double* cut, DevBuf& goff, DevBuf& gadj, DevBuf& gw,
+                     hipStream_t st) {
   // edges
   uint32_t ncells = pool.ncells;
   uint32_t tsize = 1024;
@@ -537,6 +538,7 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   DT_HIP(hipStreamSynchronize(st));
   goff = std::move(off);
   gadj = std::move(adj);
+  gw = std::move(w);
   return DT_OK;
 }
 

@@ -15,10 +15,12 @@ int gather_points(const double4* P, const uint32_t* idx, uint32_t m, double4* ou
 // and in order, so each keeps its range).  Labels travel with the points.
 int spatial_sort(DevBuf& pts, uint32_t n, int D, const double lo[3], const double hi[3],
                  const uint32_t* prefix, int prefix_bits, hipStream_t st);
-// goff/gadj receive the sample's Delaunay graph (CSR, sorted lists).
+// goff/gadj receive the sample's Delaunay graph (CSR, sorted lists) and
+// gw the weight of every adjacency entry.
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
                      const dt_options& o, const double lo[3], const double hi[3],
-                     DevBuf& part, double* cut, DevBuf& goff, DevBuf& gadj, hipStream_t st);
+                     DevBuf& part, double* cut, DevBuf& goff, DevBuf& gadj, DevBuf& gw,
+                     hipStream_t st);
 // Samples bucketed by grid cell (cells in start[0..ncell], items).
 struct SampleGrid {
   Grid G;

@@ -72,6 +72,15 @@ def lattice(side: int, dim: int, seed: int = 1, scale: float = 1.0) -> np.ndarra
     return g[rng.permutation(len(g))]
 
 
+def jittered_lattice(side: int, dim: int, rel: float, seed: int = 1) -> np.ndarray:
+    """Integer grid points, each coordinate moved by a uniform offset of at
+    most `rel` grid steps, randomly permuted: near-ties everywhere, at a
+    chosen distance from exact degeneracy."""
+    rng = np.random.default_rng(seed)
+    g = lattice(side, dim, seed=seed)
+    return g + rel * rng.uniform(-1.0, 1.0, g.shape)
+
+
 def batch_sets(num_sets: int = 4096, lo: int = 64, hi: int = 65536,
                dim: int = 2, seed: int = 1):
     """Independent point sets with sizes log-uniform in [lo, hi]; each set is

@@ -9,7 +9,9 @@ ball (the empty-ball definition of the DT, with the same symbolic
 perturbation by point id on both sides).  So, for a few boxes of about
 20,000 points, the GPU simplices with a ball inside the box must equal,
 element by element, the oracle's simplices of the box's points with a
-ball inside the box.  Batches are compared set by set on sampled sets."""
+ball inside the box.  Besides, every simplex of the headline and 1M runs
+is certified against the definition of DT(P) by oracle.certify.  Batches
+are compared set by set on sampled sets."""
 import numpy as np
 import pytest
 
@@ -64,32 +66,58 @@ def _box_check(p, got_rows, seed, boxes=3):
         assert np.array_equal(mine, want), f"box {b} differs"
 
 
-def _row_hash(rows):
-    """Order-free fingerprint of a set of rows (sorted ids per row)."""
-    r = np.sort(rows.astype(np.uint64), axis=1)
-    h = np.zeros(len(r), np.uint64)
-    for j in range(r.shape[1]):
-        h = (h ^ r[:, j]) * np.uint64(0x9E3779B97F4A7C15)
-        h ^= h >> np.uint64(29)
-    return int(h.sum(dtype=np.uint64)), len(r)
+def _certify(p, rows):
+    """The whole output against the definition of DT(P) (oracle.certify):
+    a triangulation of the convex hull (facets shared by at most two
+    simplices on opposite sides, hull facets equal to Qhull's, volumes
+    summing to the hull's, every point a vertex, Euler characteristic of a
+    ball) that is locally Delaunay at every interior facet under the
+    oracle's exact perturbed in-sphere predicate."""
+    from scipy.spatial import ConvexHull
+    cert = oracle.certify(p, rows)
+    h = ConvexHull(p)
+    bad = oracle.certificate_ok(cert, h.simplices, h.volume)
+    print(f"[fullsize] certificate: {cert['m']} simplices, {cert['interior']} interior facets, "
+          f"{cert['hull']} hull facets, failed: {bad}", flush=True)
+    assert bad == [], {k: v for k, v in cert.items() if k != "hull_facets"}
 
 
-def test_bubbles_4m_k256_as_benchmarked(dtlib):
+def _same_set(a, b):
+    """Two row sets are equal (rows compared after sorting their ids)."""
+    return np.array_equal(oracle.canonical(a), oracle.canonical(b))
+
+
+@pytest.fixture(scope="module")
+def bubbles_4m():
+    return inputs.make("bubbles", 4_194_304, 3, seed=1)
+
+
+def test_bubbles_4m_k256_as_benchmarked(dtlib, bubbles_4m):
     """4M bubbles, k = 256, sqrt(n) sample, FP32 filter: the benchmark's
-    headline run; boxes against the oracle, and the kd divide's output is
-    the same simplex set."""
+    headline run; every one of its simplices certified against the
+    definition, and boxes against the oracle's own triangulation."""
     import torch
-    p = inputs.make("bubbles", 4_194_304, 3, seed=1)
+    p = bubbles_4m
     dp = torch.from_numpy(p).cuda()
     print("[fullsize] bubbles 4M sample divide", flush=True)
     res = dtlib.triangulate(dp, k=256, sample_rate=0.0, precision="fp32")
-    rows = res.rows().astype(np.int64)
+    rows = res.rows()
     st = res.stats()
     assert len(rows) == st["num_simplices"]
-    _box_check(p, rows, seed=11)
-    print("[fullsize] bubbles 4M kd divide", flush=True)
-    kd = dtlib.triangulate(dp, k=256, divide="kd", precision="fp32")
-    assert _row_hash(kd.rows()) == _row_hash(rows)
+    _certify(p, rows)
+    _box_check(p, rows.astype(np.int64), seed=11, boxes=1)
+
+
+def test_bubbles_4m_kd_equals_sample(dtlib, bubbles_4m):
+    """The kd divide's output on the same input is the same simplex set,
+    compared row by row."""
+    import torch
+    dp = torch.from_numpy(bubbles_4m).cuda()
+    print("[fullsize] bubbles 4M kd vs sample divide", flush=True)
+    a = dtlib.triangulate(dp, k=256, sample_rate=0.0, precision="fp32").rows()
+    b = dtlib.triangulate(dp, k=256, divide="kd", precision="fp32").rows()
+    assert len(a) == len(b)
+    assert _same_set(a, b)
 
 
 def test_bubbles_4m_nearest_sample(dtlib):
@@ -111,13 +139,15 @@ def test_bubbles_4m_nearest_sample(dtlib):
 
 @pytest.mark.parametrize("divide", ["sample", "kd"])
 def test_uniform_1m_k64(dtlib, divide):
-    """1M uniform points, k = 64, 0.5 % sample, FP64 + exact."""
+    """1M uniform points, k = 64, 0.5 % sample, FP64 + exact: the whole
+    output certified, and a box against the oracle's triangulation."""
     import torch
     p = inputs.make("uniform", 1_048_576, 3, seed=1)
     print(f"[fullsize] uniform 1M {divide}", flush=True)
     res = dtlib.triangulate(torch.from_numpy(p).cuda(), k=64, sample_rate=0.005, divide=divide)
-    rows = res.rows().astype(np.int64)
-    _box_check(p, rows, seed=12, boxes=2)
+    rows = res.rows()
+    _certify(p, rows)
+    _box_check(p, rows.astype(np.int64), seed=12, boxes=1)
 
 
 def test_batch_4096_sets_autotuned(dtlib):

@@ -138,6 +138,22 @@ def test_fp32_filter_matches_oracle(dtlib, dim, n, dist):
         assert ins["exact"] > 0
 
 
+@pytest.mark.parametrize("dim,side,rel,k", [(3, 9, 2.0 ** -20, 1), (3, 9, 2.0 ** -33, 1),
+                                            (3, 9, 2.0 ** -45, 1), (2, 40, 2.0 ** -30, 1),
+                                            (3, 12, 2.0 ** -28, 8), (2, 50, 2.0 ** -40, 4)])
+def test_fp32_filter_on_jittered_lattices(dtlib, dim, side, rel, k):
+    """Lattices moved by relative 2^-20 .. 2^-45: every in-sphere test is a
+    near-tie inside or just outside the FP32 filter's band; the FP32 mode
+    must still give the oracle's simplex set, directly and divided."""
+    p = inputs.jittered_lattice(side, dim, rel, seed=3)
+    print(f"[fp32] jittered lattice dim={dim} side={side} rel=2^{np.log2(rel):.0f} k={k}",
+          flush=True)
+    res = dtlib.triangulate(p, k=k, sample_rate=0.05, precision="fp32")
+    assert np.array_equal(_rows(res), oracle.delaunay(p))
+    ins = res.stats()["pred"]["insphere3d" if dim == 3 else "insphere2d"]
+    assert ins["fp64"] + ins["exact"] > 0
+
+
 @pytest.mark.parametrize("dim,k", [(2, 1), (3, 1), (3, 8)])
 def test_neighbors_match_oracle(dtlib, dim, k):
     """dt_result_neighbors equals the facet-sharing definition on the rows

@@ -12,28 +12,73 @@ from paper_1902_07554_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _stage_checks(dtlib, p, k, rate, seed, divide, border="region"):
+def _check_buckets(order, pid, k):
+    """Algorithm 2's partitions as buckets: `order` is a permutation of the
+    points, grouped by partition in partition order, and bucket i holds
+    exactly P_i (the order inside a bucket is free)."""
+    n = len(pid)
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.all(np.diff(pid[order]) >= 0)
+    off = np.concatenate([[0], np.cumsum(np.bincount(pid, minlength=k))])
+    for i, members in enumerate(oracle.buckets(pid, k)):
+        assert np.array_equal(np.sort(order[off[i]:off[i + 1]]), members), f"bucket {i}"
+
+
+def _check_graph(res, p, sid, part, k, weight, st):
+    """Algorithm 2's weighted graph (the sample DT's edges, Table "weights")
+    and the partition's cut weight (Section "Partitioning Quality") against
+    the oracle, given the same sample triangulation."""
+    edges = res.stage("graph").astype(np.int64)
+    w = res.stage("weights")
+    want = oracle.graph_edges(oracle.canonical(res.stage("sample_dt")))
+    assert np.array_equal(edges, want), "sample-graph edges"
+    ww = oracle.edge_weights(p, want, kind=weight)
+    np.testing.assert_allclose(w, ww, rtol=1e-12, atol=1e-12)
+    part_of = np.full(len(p), -1, dtype=np.int64)
+    part_of[sid] = part
+    cut = oracle.cut_weight(want, ww, part_of)
+    assert st["cut_weight"] == pytest.approx(cut, rel=1e-9, abs=1e-9)
+
+
+def _check_metrics(st, pid, k, n, eta, nvb, loc_flag, n_tb):
+    """Section "Partitioning Quality": deviation, c_v, o_DT and the border
+    sizes, from the oracle's formulas on the stage arrays."""
+    sizes = np.bincount(pid, minlength=k)
+    assert st["max_dev"] == pytest.approx(float(oracle.deviation(sizes).max()), rel=1e-12, abs=1e-12)
+    assert st["cv"] == pytest.approx(oracle.coeff_variation(sizes), rel=1e-12, abs=1e-12)
+    assert st["max_part"] == sizes.max() and st["min_part"] == sizes.min()
+    assert st["o_dt"] == pytest.approx(oracle.overtriangulation(n, eta, nvb), rel=1e-15)
+    assert st["border_simplices"] == int(loc_flag.sum())
+    assert st["local_simplices"] == len(loc_flag)
+    assert st["tb_simplices"] == n_tb
+
+
+def _stage_checks(dtlib, p, k, rate, seed, divide, border="region", weight="log", eps=0.05,
+                  grid_cell=1.0):
     n, dim = p.shape
     res = dtlib.triangulate(p, k=k, sample_rate=rate, divide=divide, seed=seed, keep_stages=1,
-                            border=border)
+                            border=border, weight=weight, eps=eps, grid_cell=grid_cell)
     ids = np.arange(n)
     full = oracle.delaunay(p)
     got = oracle.canonical(res.rows())
     assert np.array_equal(got, full), "merged simplex set differs from the oracle"
     pid = res.stage("pid").astype(np.int64)
+    st = res.stats()
+    eta = 0
     if divide == "sample":
         eta = oracle.sample_size(n, rate, dim)
         sid = res.stage("sample")
         assert np.array_equal(sid, oracle.sample_ids(n, eta, seed))
         assert np.array_equal(oracle.canonical(res.stage("sample_dt")), oracle.delaunay(p[sid], sid))
         part = res.stage("part").astype(np.int64)
-        assert oracle.balanced(part, k, 0.05)
+        assert oracle.balanced(part, k, eps)
         near = oracle.nearest_sample(p, p[sid], sid)
         assert np.array_equal(res.stage("nearest"), near)
         assert np.array_equal(pid, part[near])
+        _check_graph(res, p, sid, part, k, weight, st)
     else:
         assert np.array_equal(pid, oracle.kd_divide(p, k))
-    assert np.array_equal(res.stage("order"), oracle.bucket_order(pid, p))
+    _check_buckets(res.stage("order").astype(np.int64), pid, k)
     loc = res.stage("local")
     rows, flag = oracle.canonical(loc[:, :-1]), None
     # per-partition triangulations and border soundness
@@ -55,10 +100,11 @@ def _stage_checks(dtlib, p, k, rate, seed, divide, border="region"):
                 assert f, "a simplex of T_i outside DT(P) was not flagged"
     vb = res.stage("border_v")
     assert set(np.unique(srows[flag])) <= set(vb.tolist())
-    assert np.array_equal(oracle.canonical(res.stage("border_dt")), oracle.delaunay(p[vb], vb))
-    st = res.stats()
+    tb = oracle.delaunay(p[vb], vb)
+    assert np.array_equal(oracle.canonical(res.stage("border_dt")), tb)
     assert st["border_vertices"] == len(vb)
     assert st["num_simplices"] == len(full)
+    _check_metrics(st, pid, k, n, eta, len(vb), flag, len(tb))
     return res
 
 
@@ -84,6 +130,38 @@ def test_3d_stages(dtlib, divide, dist, k, border):
     p = inputs.make(dist, 20_000, 3, seed=4)
     print(f"[pipeline] 3d 20k {dist} {divide} k={k} border={border}", flush=True)
     _stage_checks(dtlib, p, k, 0.01, 3, divide, border)
+
+
+@pytest.mark.parametrize("weight,eps,grid_cell,border", [
+    ("const", 0.05, 1.0, "region"), ("inverse", 0.05, 1.0, "region"),
+    ("linear", 0.05, 1.0, "region"), ("log", 0.03, 1.0, "region"), ("log", 0.3, 1.0, "region"),
+    ("log", 0.05, 0.5, "grid"), ("log", 0.05, 2.0, "grid"), ("inverse", 0.3, 2.0, "grid")])
+def test_weights_balance_and_grid_sizes(dtlib, weight, eps, grid_cell, border):
+    """Table "weights" (constant, inverse, linear next to log), the balance
+    bound at eps 0.03 and 0.3, and the grid test at c_G = 1/2 and 2
+    (Section "Grid-based Intersection Test"): every stage against the
+    oracle, the final set bit for bit."""
+    p = inputs.make("bubbles", 20_000, 3, seed=21)
+    print(f"[pipeline] weight={weight} eps={eps} c_G={grid_cell} border={border}", flush=True)
+    _stage_checks(dtlib, p, 16, 0.02, 5, "sample", border, weight=weight, eps=eps,
+                  grid_cell=grid_cell)
+
+
+def test_partition_is_deterministic_and_cuts_less_than_its_start(dtlib):
+    """The partitioner is not KaHIP, whose output is not reproducible; its
+    own pins: the same blocks on every run, and label propagation never
+    raises the cut of its starting blocks (the kd split of the sample)."""
+    p = inputs.make("bubbles", 40_000, 3, seed=3)
+    a = dtlib.triangulate(p, k=16, sample_rate=0.02, keep_stages=1)
+    b = dtlib.triangulate(p, k=16, sample_rate=0.02, keep_stages=1)
+    assert np.array_equal(a.stage("part"), b.stage("part"))
+    assert np.array_equal(a.stage("pid"), b.stage("pid"))
+    sid = a.stage("sample")
+    edges = a.stage("graph").astype(np.int64)
+    w = a.stage("weights")
+    start = np.full(len(p), -1, dtype=np.int64)
+    start[sid] = oracle.kd_divide(p[sid], 16)
+    assert a.stats()["cut_weight"] <= oracle.cut_weight(edges, w, start) + 1e-9
 
 
 @pytest.mark.parametrize("dim,side,k", [(2, 60, 4), (3, 12, 8)])
