@@ -13,6 +13,13 @@ FP32-filtered predicates with FP64 and exact fallbacks.  The metric is
 Mpoints/s with the sample divide; the kd median-split divide runs on the
 same input for comparison, with balance and border sizes for both.
 
+The same line carries the two patterns: a batching leg (4096 independent
+2D sets, sizes log-uniform in [64, 65536], one batched run with autotuned
+tunables against one launch per set) and a serving leg (a Poisson stream of
+3D jobs, n log-uniform in [1e3, 1e6], half uniform half bubbles, for
+--serve-seconds at --serve-rate jobs/s: Mpoints/s and p50/p99 latency from
+arrival to result).
+
 Prints one JSON line (rank 0).  `--gpus N` with N > 1 is not supported: the
 build targets one GPU.
 """
@@ -35,13 +42,53 @@ WORKLOADS = {
     "uniform-2d-10k-k4": ("uniform", 10_000, 2, 4, 0.01, "fp64"),
 }
 
-# Algorithmic bytes per unit of work of each timed kernel: the records the
-# kernel must gather or stream for that unit.
+# Bytes per unit of work.  Two figures per kernel:
+#   algorithmic bytes -- what the method itself must move (the per-unit
+#     figures of the measurement plan), the basis of the roofline fraction;
+#   work bytes -- the records the kernel gathers for the work it actually
+#     does (losing searches and repeated tests included), reported beside.
 PT = 32          # point record: x, y, z, id (double4)
 CELL = 16        # cell vertex record (uint4); neighbours another 16
 
 
-def kernel_bytes(name: str, st: dict, dim: int) -> float:
+def simplices_per_point(dim: int) -> float:
+    """Simplices per point of a random Delaunay triangulation: about 6.77
+    in 3D (uniform points in the cube), 2 in 2D."""
+    return 6.77 if dim == 3 else 2.0
+
+
+def inserted_points(st: dict) -> int:
+    """Points inserted by all local-DT runs of a step: the local sets, the
+    sample (sample divide) and the border set."""
+    if st.get("k", 1) <= 1:
+        return int(st["n"])
+    return int(st["n"] + st["eta"] + st["border_vertices"])
+
+
+def alg_bytes(name: str, st: dict, dim: int) -> float:
+    """Algorithmic bytes of one step for a kernel (0 when the kernel has no
+    figure of its own).  The local DT's figure (its output: per point the
+    simplices it adds, D+1 vertex and D+1 neighbour words of 4 bytes each)
+    belongs to the four insertion kernels together and is attributed to the
+    cavity search, the one that bounds them."""
+    n = st["n"]
+    v = dim + 1
+    if name == "k4_cavity":
+        return inserted_points(st) * simplices_per_point(dim) * 8 * v
+    if name == "assign":        # read the coordinates, write the block (1 byte)
+        return n * (8 * dim + 1)
+    if name == "bucket":        # read coordinates and block, write coordinates and id
+        return n * (8 * dim + 1 + 8 * dim + 4)
+    if name == "border":        # per local simplex: its vertex words and its flag
+        return st["local_simplices"] * (4 * v + 1)
+    if name == "merge":         # read T_i simplices + flags, write DT(P), hash B, probe T_B
+        return (st["local_simplices"] * (4 * v + 1) + st["num_simplices"] * 4 * v
+                + st["border_simplices"] * (4 * v + 4) + st["tb_simplices"] * 4 * v)
+    return 0.0
+
+
+def work_bytes(name: str, st: dict, dim: int) -> float:
+    """Bytes gathered for the work a kernel actually did in one step."""
     pred = st["pred"]
     o = pred["orient3d" if dim == 3 else "orient2d"]["calls"]
     ins = pred["insphere3d" if dim == 3 else "insphere2d"]["calls"]
@@ -65,6 +112,43 @@ def kernel_bytes(name: str, st: dict, dim: int) -> float:
     if name == "merge":         # per simplex of T_i and T_B: vertices, keys, flag, row
         return (st["local_simplices"] + st["tb_simplices"]) * (CELL + v * PT + 1 + 4 * v)
     return 0.0
+
+
+def sig(x: float, digits: int = 4) -> float:
+    """x rounded to `digits` significant digits."""
+    return float(f"{x:.{digits}g}")
+
+
+def roofline_object(dom: str, per_step: dict, st: dict, dim: int, workload: str) -> dict:
+    """Roofline of the dominant kernel: algorithmic bytes per launch over
+    the average launch duration (HIP events on the launch stream), against
+    the HBM peak; measured HBM traffic per launch from the committed counter
+    summary; and the work behind it (tests per inserted point, rounds,
+    candidates against winners)."""
+    launches = per_step[dom]["launches"]
+    a = alg_bytes(dom, st, dim) / launches
+    w = work_bytes(dom, st, dim) / launches
+    avg_s = per_step[dom]["ms"] / 1000.0 / launches
+    achieved = a / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = measured_traffic(dom, workload)
+    ins = inserted_points(st)
+    pred = st["pred"]
+    return {"bound": "hbm", "kernel": dom, "achieved": sig(achieved), "peak": 8000.0,
+            "unit": "GB/s", "frac": sig(achieved / 8000.0),
+            "traffic": round(traffic) if traffic is not None else None,
+            "algorithmic_bytes_per_launch": round(a),
+            "algorithmic_rule": ("inserted points x simplices per point x (D+1) x 8 B"
+                                 if dom == "k4_cavity" else "per-unit figure x units"),
+            "work_bytes_per_launch": round(w),
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches_per_step": launches,
+            "ms_per_step": round(per_step[dom]["ms"], 3),
+            "inserted_points": ins,
+            "insphere_tests_per_inserted_point":
+                round(pred["insphere3d" if dim == 3 else "insphere2d"]["calls"] / ins, 2),
+            "orient_tests_per_inserted_point":
+                round(pred["orient3d" if dim == 3 else "orient2d"]["calls"] / ins, 2),
+            "rounds": st["rounds"], "candidates": st["candidates"], "winners": ins,
+            "kernel_source": kernel_source_hash()}
 
 
 def cpu_model() -> str:
@@ -327,6 +411,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bubbles-3d-4M-k256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-kd", action="store_true", help="skip the kd-divide comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batching leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--cpu-sample", type=int, default=1_500_000,
                     help="points of the CPU-oracle baseline sample (0 = skip)")
     ap.add_argument("--mode", default="dt", choices=["dt", "batch", "serve", "copy", "sweep"],
@@ -368,23 +454,19 @@ def main() -> int:
     per_step = {name: {"ms": v["ms"], "launches": v["launches"]}
                 for name, v in kern.items() if v["launches"]}
     dom = max(per_step, key=lambda x: per_step[x]["ms"])
-    launches = per_step[dom]["launches"]
-    dom_bytes = kernel_bytes(dom, pst, dim) / launches          # algorithmic bytes per launch
-    dom_avg_s = per_step[dom]["ms"] / 1000.0 / launches        # average launch duration
-    achieved = dom_bytes / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
-    traffic = measured_traffic(dom, args.workload)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": 8000.0,
-                "unit": "GB/s", "frac": round(achieved / 8000.0, 5),
-                "traffic": round(traffic) if traffic is not None else None,
-                "algorithmic_bytes_per_launch": round(dom_bytes),
-                "avg_launch_us": round(dom_avg_s * 1e6, 2), "launches_per_step": launches,
-                "ms_per_step": round(per_step[dom]["ms"], 3),
-                "kernel_source": kernel_source_hash()}
+    roofline = roofline_object(dom, per_step, pst, dim, args.workload)
     kernels = {}
     for name, v in per_step.items():
-        b = kernel_bytes(name, pst, dim)
+        sec = v["ms"] / 1000.0
+        a, w = alg_bytes(name, pst, dim), work_bytes(name, pst, dim)
         kernels[name] = {"ms": round(v["ms"], 3), "launches": v["launches"],
-                         "GB/s": round(b / (v["ms"] / 1000.0) / 1e9, 2) if v["ms"] > 0 else None}
+                         "alg_GB/s": round(a / sec / 1e9, 2) if sec > 0 and a else None,
+                         "work_GB/s": round(w / sec / 1e9, 2) if sec > 0 else None}
+    k4_ms = sum(per_step[x]["ms"] for x in ("k4_pick", "k4_select", "k4_cavity", "k4_insert")
+                if x in per_step)
+    kernels["k4_all_four"] = {"ms": round(k4_ms, 3),
+                              "alg_GB/s": round(alg_bytes("k4_cavity", pst, dim) / (k4_ms / 1000.0)
+                                                / 1e9, 2) if k4_ms > 0 else None}
 
     def summary(s):
         return {"border_vertices": s["border_vertices"], "border_simplices": s["border_simplices"],
@@ -422,9 +504,19 @@ def main() -> int:
         line["kd_divide"] = dict(value=round(n / (kms / 1000.0) / 1e6, 4), ms_per_step=round(kms, 3),
                                  **summary(kst))
         line["sample_vs_kd_speedup"] = round(kms / ms, 4)
-        line["kd_simplices_equal"] = bool(kres.count == res.count)
+        line["kd_simplex_count_equal"] = bool(kres.count == res.count)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(host, min(args.cpu_sample, n))
+    del pts, res
+    if not args.no_batch:
+        b = bench_batch(args)
+        line["batch"] = {k2: b[k2] for k2 in ("value", "unit", "ms_per_step", "config",
+                                               "autotuned", "default_tunables_ms",
+                                               "per_set_launches", "batched_vs_per_set")}
+    if not args.no_serve:
+        v = bench_serve(args)
+        line["serve"] = {k2: v[k2] for k2 in ("value", "unit", "p50_ms", "p99_ms", "max_ms",
+                                               "ms_per_step", "config")}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -27,7 +27,18 @@
  *   - every call returns a status (DT_OK = 0, negative on error) and never
  *     aborts.  Results are opaque handles owning device memory until
  *     dt_result_free.
- *   - the library holds no global mutable state.
+ *   - threads: calls on different results, streams or servers may run
+ *     concurrently from several host threads.  One result must not be used
+ *     by two calls at once.  The library keeps two process-wide caches,
+ *     each behind its own lock:
+ *       * device blocks of 16 MB and more that calls release (at most
+ *         48 GB, see dt_release_cached_memory).  A block released during a
+ *         call carries an event recorded on that call's stream; the next
+ *         call that takes it makes its own stream wait for that event, so
+ *         a release never waits for other streams.  Blocks of a result freed
+ *         by dt_result_free are idle (every call that touches a result
+ *         synchronises its stream before returning);
+ *       * the launch tunables chosen by dt_batch_autotune, per size class.
  */
 #ifndef DT_MI355X_H
 #define DT_MI355X_H

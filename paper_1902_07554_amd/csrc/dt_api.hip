@@ -59,11 +59,35 @@ struct CachedBlock {
   void* p;
   size_t size;
   int dev;
+  hipEvent_t ready;   // recorded after the block's last uses (null: none pending)
 };
 std::mutex g_cache_mu;
 std::vector<CachedBlock>* g_cache = new std::vector<CachedBlock>();
 size_t g_cached = 0;
+
+struct UseStream {
+  bool set = false;
+  hipStream_t s = nullptr;
+};
+thread_local UseStream g_use;
+thread_local int g_quiescent = 0;
+
+void drop_block(const CachedBlock& b) {
+  if (b.ready) (void)hipEventDestroy(b.ready);
+  (void)hipFree(b.p);
+}
 }  // namespace
+
+UseStreamScope::UseStreamScope(hipStream_t s) : prev_set(g_use.set), prev(g_use.s) {
+  g_use.set = true;
+  g_use.s = s;
+}
+UseStreamScope::~UseStreamScope() {
+  g_use.set = prev_set;
+  g_use.s = prev;
+}
+QuiescentScope::QuiescentScope() { g_quiescent++; }
+QuiescentScope::~QuiescentScope() { g_quiescent--; }
 
 hipError_t cached_malloc(void** p, size_t n, size_t* blk) {
   *blk = 0;
@@ -82,10 +106,22 @@ hipError_t cached_malloc(void** p, size_t n, size_t* blk) {
         best = i;
     }
     if (best < g_cache->size()) {
-      *p = (*g_cache)[best].p;
-      *blk = (*g_cache)[best].size;
-      g_cached -= *blk;
+      const CachedBlock b = (*g_cache)[best];
+      g_cached -= b.size;
       g_cache->erase(g_cache->begin() + best);
+      *p = b.p;
+      *blk = b.size;
+      if (b.ready) {
+        // order this call's work after the releasing call's last uses
+        e = g_use.set ? hipStreamWaitEvent(g_use.s, b.ready, 0) : hipEventSynchronize(b.ready);
+        (void)hipEventDestroy(b.ready);
+        if (e != hipSuccess) {
+          (void)hipFree(b.p);
+          *p = nullptr;
+          *blk = 0;
+          return e;
+        }
+      }
       return hipSuccess;
     }
   }
@@ -105,7 +141,7 @@ hipError_t cached_malloc(void** p, size_t n, size_t* blk) {
         }
       }
     }
-    for (const CachedBlock& b : mine) (void)hipFree(b.p);
+    for (const CachedBlock& b : mine) drop_block(b);
     e = hipMalloc(p, want);
   }
   if (e == hipSuccess) *blk = want;
@@ -122,26 +158,42 @@ void cached_free(void* p, size_t blk) {
     return;
   }
   const int dev = at.device;
-  // kernels queued on any stream of that device may still use the block
-  if (dev != cur) (void)hipSetDevice(dev);
-  (void)hipDeviceSynchronize();
-  if (dev != cur) (void)hipSetDevice(cur);
-  std::vector<void*> drop;
+  hipEvent_t ready = nullptr;
+  if (g_quiescent) {
+    // every operation on the block has been synchronised
+  } else if (g_use.set && dev == cur &&
+             hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess) {
+    // the block's uses are all on the call's stream: mark their end
+    if (hipEventRecord(ready, g_use.s) != hipSuccess) {
+      (void)hipEventDestroy(ready);
+      ready = nullptr;
+      (void)hipGetLastError();
+      (void)hipDeviceSynchronize();
+    }
+  } else {
+    // unknown stream: kernels queued on any stream of that device may
+    // still use the block
+    (void)hipGetLastError();
+    if (dev != cur) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    if (dev != cur) (void)hipSetDevice(cur);
+  }
+  std::vector<CachedBlock> drop;
   {
     std::lock_guard<std::mutex> g(g_cache_mu);
-    g_cache->push_back({p, blk, dev});
+    g_cache->push_back({p, blk, dev, ready});
     g_cached += blk;
     // over the cap: return the largest blocks
     while (g_cached > CACHE_CAP && !g_cache->empty()) {
       size_t big = 0;
       for (size_t i = 1; i < g_cache->size(); i++)
         if ((*g_cache)[i].size > (*g_cache)[big].size) big = i;
-      drop.push_back((*g_cache)[big].p);
+      drop.push_back((*g_cache)[big]);
       g_cached -= (*g_cache)[big].size;
       g_cache->erase(g_cache->begin() + big);
     }
   }
-  for (void* q : drop) (void)hipFree(q);
+  for (const CachedBlock& b : drop) drop_block(b);
 }
 
 int release_cached_memory() {
@@ -162,6 +214,7 @@ int release_cached_memory() {
       if (hipSetDevice(all[i].dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         status = DT_E_DEVICE;
     }
+    if (all[i].ready) (void)hipEventDestroy(all[i].ready);
     if (hipFree(all[i].p) != hipSuccess) status = DT_E_DEVICE;
   }
   if (cur >= 0 && hipSetDevice(cur) != hipSuccess) status = DT_E_DEVICE;
@@ -267,6 +320,7 @@ extern "C" int dt_triangulate(const double* points, int64_t n, int D, int k, dou
   DT_TRY(check_options(opt, o));
   if (n < D + 1) return DT_E_DEGENERATE;
   hipStream_t st = (hipStream_t)stream;
+  UseStreamScope use(st);
   dt_result* r = new dt_result();
   r->D = D;
   Profiler prof;
@@ -306,6 +360,7 @@ extern "C" int dt_batch_triangulate(const double* points, const int64_t* ids,
   dt_options o;
   DT_TRY(check_options(opt, o));
   hipStream_t st = (hipStream_t)stream;
+  UseStreamScope use(st);
   dt_result* r = new dt_result();
   r->D = D;
   Profiler prof;
@@ -349,6 +404,7 @@ extern "C" int dt_result_neighbors(const dt_result* r, int32_t* dst, int64_t cap
   if (!r || (!dst && r->m > 0) || cap_rows < r->m) return DT_E_INVALID_ARG;
   if (r->m == 0) return DT_OK;
   hipStream_t st = (hipStream_t)stream;
+  UseStreamScope use(st);
   if (!r->nbr_ready) {
     DT_TRY(compute_neighbors(*r, r->nbr, st));
     r->nbr_ready = true;
@@ -366,7 +422,12 @@ extern "C" int dt_result_stats(const dt_result* r, dt_stats* s) {
   return DT_OK;
 }
 
-extern "C" void dt_result_free(dt_result* r) { delete r; }
+extern "C" void dt_result_free(dt_result* r) {
+  // every call that touches a result synchronises its stream before it
+  // returns, so nothing is pending on the result's memory
+  QuiescentScope q;
+  delete r;
+}
 
 extern "C" int dt_result_set_offsets(const dt_result* r, int64_t* dst, int64_t cap) {
   if (!r || !dst || cap < (int64_t)r->set_offsets.size()) return DT_E_INVALID_ARG;

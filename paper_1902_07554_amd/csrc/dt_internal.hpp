@@ -33,12 +33,32 @@ struct AllocStreamScope {
   ~AllocStreamScope();
 };
 
+// The stream every device operation of the current call runs on (set by
+// the entry points for the duration of a call).
+struct UseStreamScope {
+  bool prev_set;
+  hipStream_t prev;
+  explicit UseStreamScope(hipStream_t s);
+  ~UseStreamScope();
+};
+// Blocks released inside this scope carry no pending device work (every
+// operation on them has been synchronised, e.g. a result being freed).
+struct QuiescentScope {
+  QuiescentScope();
+  ~QuiescentScope();
+};
+
 // Large plain allocations go through a process-wide cache of device
-// blocks: a released block is kept (after a device-wide synchronisation,
-// as hipFree would do) and handed out again for a request of about its
-// size.  Repeated runs of one workload then reuse the same blocks instead
-// of asking the driver for gigabytes per call, which on a busy machine can
-// stall for seconds.  *blk receives the block size (0: plain hipMalloc).
+// blocks: a released block is kept and handed out again for a request of
+// about its size.  Repeated runs of one workload then reuse the same blocks
+// instead of asking the driver for gigabytes per call, which on a busy
+// machine can stall for seconds.  A block released during a call keeps an
+// event recorded on the call's stream (after its last uses); the next call
+// to take it makes its own stream wait for that event (or waits on the
+// host when it has none), so no release synchronises the device.  A block
+// released outside any call and not in a quiescent scope waits for its
+// device to finish, as hipFree would.  *blk receives the block size (0:
+// plain hipMalloc).
 hipError_t cached_malloc(void** p, size_t n, size_t* blk);
 void cached_free(void* p, size_t blk);
 
@@ -70,9 +90,13 @@ struct DevBuf {
   ~DevBuf() { release(); }
   void release() {
     if (p) {
-      if (ordered) (void)hipFreeAsync(p, ast);
-      else if (blk) cached_free(p, blk);
-      else (void)hipFree(p);
+      if (ordered) {
+        (void)hipFreeAsync(p, ast);
+      } else if (blk) {
+        cached_free(p, blk);
+      } else {
+        (void)hipFree(p);
+      }
     }
     p = nullptr;
     bytes = 0;

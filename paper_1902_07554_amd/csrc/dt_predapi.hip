@@ -63,6 +63,7 @@ extern "C" int dt_predicates(int kind, int D, int precision, const double* pts,
   if (nq == 0) return DT_OK;
   if (!pts || !sign) return DT_E_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
+  UseStreamScope use(st);
   DevBuf flag;
   DT_TRY(flag.alloc(4));
   DT_HIP(hipMemsetAsync(flag.p, 0, 4, st));

@@ -175,8 +175,10 @@ struct dt_server {
     if (hipSetDevice(device) != hipSuccess ||
         hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
       st = nullptr;
-    // scratch of the runs comes from the stream-ordered pool on this stream
+    // scratch of the runs comes from the stream-ordered pool on this stream,
+    // and blocks of the block cache released here are marked with events on it
     AllocStreamScope scope(st);
+    UseStreamScope use(st);
     for (;;) {
       std::vector<Job*> b;
       {

@@ -61,6 +61,7 @@ extern "C" int dt_batch_autotune(const double* points, const int64_t* offsets, i
   o.keep_stages = 0;
   o.sort_output = 0;
   hipStream_t st = (hipStream_t)stream;
+  UseStreamScope use(st);
   if (total == 0) {
     *tuned = o;
     return DT_OK;
