@@ -239,6 +239,39 @@ enum { DT_ARR_SAMPLE = 0, DT_ARR_SAMPLE_DT, DT_ARR_PART, DT_ARR_PID, DT_ARR_ORDE
 int dt_result_stage(const dt_result* r, int which, void* dst, int64_t cap, int64_t* count);
 
 /*
+ * dt_triangulate_noalloc -- dt_triangulate with k = 1 (the parallel
+ * triangulation of the whole set, without a divide) for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  The call allocates
+ * nothing (no hipMalloc, hipFree, pinned host memory or library
+ * allocation): its scratch memory is one static device array of
+ * DT_NOALLOC_SCRATCH_BYTES per GPU, held by each GPU the library runs this
+ * call on until the process ends.  The array keeps the contents of the
+ * last call; the call clears what must start at zero.  Calls on one GPU
+ * share the array: within a process they are serialised by a lock (one
+ * call at a time per device), and the call synchronises `stream` before it
+ * returns.
+ *   points   device memory, n x D row-major doubles (caller-owned)
+ *   n        D+1 <= n <= DT_NOALLOC_MAX_POINTS_2D / _3D
+ *   opt      NULL for defaults; precision and the launch tunables apply,
+ *            sort_output must be 0, the divide options are unused
+ *   rows     device memory, cap_rows x (D+1) int32: the finite simplices
+ *            of DT(P) as rows of input indices, ascending within a row
+ *            (row order unspecified)
+ *   count    receives the number of simplices m (also when cap_rows < m)
+ * Errors: DT_E_INVALID_ARG (bad D or pointers, sort_output set, or
+ * cap_rows < m: *count then says how many rows are needed),
+ * DT_E_NOMEM (n above the maximum for D: the job does not fit the
+ * scratch array), DT_E_NONFINITE, DT_E_DUPLICATE, DT_E_DEGENERATE,
+ * DT_E_DEVICE, DT_E_INTERNAL.
+ */
+#define DT_NOALLOC_SCRATCH_BYTES (256u << 20)
+#define DT_NOALLOC_MAX_POINTS_2D 131072
+#define DT_NOALLOC_MAX_POINTS_3D 49152
+int dt_triangulate_noalloc(const double* points, int64_t n, int D, const dt_options* opt,
+                           int32_t* rows, int64_t cap_rows, int64_t* count, void* stream);
+
+/*
  * dt_predicates -- the two geometric predicates that decide every
  * combinatorial step of the method (Section "Geometric Primitives"; the
  * triangulations rely on exact orientation and in-sphere tests), on a batch

@@ -34,7 +34,8 @@ EXPORTS = ["dt_default_options", "dt_strerror", "dt_triangulate", "dt_result_cou
            "dt_result_stage", "dt_batch_triangulate", "dt_result_set_offsets",
            "dt_server_create", "dt_server_submit", "dt_server_poll", "dt_server_wait",
            "dt_server_times", "dt_server_destroy", "dt_batch_autotune", "dt_result_neighbors",
-           "dt_release_cached_memory", "dt_predicates"]
+           "dt_release_cached_memory", "dt_predicates", "dt_triangulate_noalloc"]
+NOALLOC_MAX_POINTS = {2: 131072, 3: 49152}
 
 
 class Options(ctypes.Structure):
@@ -130,6 +131,8 @@ def load():
     lib.dt_server_times.restype = I
     lib.dt_server_destroy.argtypes = [VP]
     lib.dt_server_destroy.restype = None
+    lib.dt_triangulate_noalloc.argtypes = [VP, I64, I, P(Options), VP, I64, P(I64), VP]
+    lib.dt_triangulate_noalloc.restype = I
     lib.dt_predicates.argtypes = [I, I, I, VP, VP, I64, VP, VP, VP]
     lib.dt_predicates.restype = I
     lib.dt_release_cached_memory.argtypes = []
@@ -299,6 +302,30 @@ def predicates(kind: str, tuples, keys=None, precision: str = "fp64"):
     if st != DT_OK:
         raise DTError(st)
     return sign.cpu().numpy(), stage.cpu().numpy()
+
+
+def triangulate_noalloc(points, out=None, **opts):
+    """dt_triangulate_noalloc: DT(points) with k = 1 and no allocation by
+    the library.  points: a float64 (n, D) torch tensor on the GPU.  out:
+    an int32 (cap, D+1) device tensor for the rows (allocated here by torch
+    when None, with room for 8n rows).  Returns the rows as a device tensor
+    view of `out`."""
+    import torch
+    lib = load()
+    if not (isinstance(points, torch.Tensor) and points.is_cuda):
+        raise ValueError("points must be a CUDA tensor")
+    ptr, n, d, _, keep, stream = _pointer(points)
+    if out is None:
+        out = torch.empty((max(8 * n, 1), d + 1), dtype=torch.int32, device=points.device)
+    o = options(**opts)
+    cnt = ctypes.c_int64(0)
+    st = lib.dt_triangulate_noalloc(ctypes.c_void_p(ptr), n, d, ctypes.byref(o),
+                                    ctypes.c_void_p(out.data_ptr()), out.shape[0],
+                                    ctypes.byref(cnt), ctypes.c_void_p(stream))
+    del keep
+    if st != DT_OK:
+        raise DTError(st, f"(count {cnt.value})")
+    return out[:cnt.value]
 
 
 def triangulate(points, k: int = 1, sample_rate: float = 0.0, **opts) -> Result:

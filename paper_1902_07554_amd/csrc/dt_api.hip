@@ -233,17 +233,25 @@ struct PinnedCache {
 thread_local PinnedCache g_pinned;
 constexpr size_t PINNED_BLOCK = 512;
 static_assert(sizeof(Counters) + 16 <= PINNED_BLOCK, "pinned block too small");
+
+// Host words of a call running in a workspace: plain (pageable) memory,
+// so that such a call asks for no pinned allocation either; every copy
+// into it is followed by a stream synchronisation before it is read.
+alignas(64) thread_local char g_ws_host[PINNED_BLOCK];
 }  // namespace
 
 Ctx::~Ctx() {
-  if (hctr) g_pinned.free_blocks.push_back(hctr);
+  if (hctr && pinned) g_pinned.free_blocks.push_back(hctr);
 }
 
 int Ctx::init() {
   DT_TRY(dctr.alloc(sizeof(Counters)));
   DT_TRY(dflag.alloc(16));
   void* b = nullptr;
-  if (!g_pinned.free_blocks.empty()) {
+  if (workspace()) {
+    b = g_ws_host;
+    pinned = false;
+  } else if (!g_pinned.free_blocks.empty()) {
     b = g_pinned.free_blocks.back();
     g_pinned.free_blocks.pop_back();
   } else {
@@ -253,6 +261,11 @@ int Ctx::init() {
   hflag = reinterpret_cast<uint32_t*>(static_cast<char*>(b) + sizeof(Counters));
   return DT_OK;
 }
+
+static thread_local Workspace* g_workspace = nullptr;
+Workspace* workspace() { return g_workspace; }
+WorkspaceScope::WorkspaceScope(Workspace* w) : prev(g_workspace) { g_workspace = w; }
+WorkspaceScope::~WorkspaceScope() { g_workspace = prev; }
 
 static thread_local hipStream_t g_alloc_stream = nullptr;
 hipStream_t alloc_stream() { return g_alloc_stream; }

@@ -33,6 +33,25 @@ struct AllocStreamScope {
   ~AllocStreamScope();
 };
 
+// Workspace mode: while a thread has a workspace set, DevBuf::alloc and
+// DevBuf::alloc_plain carve their memory from it (256-byte aligned, bump
+// order) and never call an allocator; releasing the most recent block
+// gives it back, any other release keeps its bytes until the workspace is
+// reset.  All work of such a call runs on one stream, so a block reused
+// after its release is ordered after every earlier use.
+struct Workspace {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  size_t peak = 0;
+};
+Workspace* workspace();
+struct WorkspaceScope {
+  Workspace* prev;
+  explicit WorkspaceScope(Workspace* w);
+  ~WorkspaceScope();
+};
+
 // The stream every device operation of the current call runs on (set by
 // the entry points for the duration of a call).
 struct UseStreamScope {
@@ -69,28 +88,34 @@ struct DevBuf {
   size_t blk = 0;              // size of a cached block (0: not cached)
   hipStream_t ast = nullptr;   // stream of a stream-ordered allocation
   bool ordered = false;
+  Workspace* ws = nullptr;     // carved from this workspace
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   DevBuf(DevBuf&& o) noexcept
-      : p(o.p), bytes(o.bytes), blk(o.blk), ast(o.ast), ordered(o.ordered) {
+      : p(o.p), bytes(o.bytes), blk(o.blk), ast(o.ast), ordered(o.ordered), ws(o.ws) {
     o.p = nullptr;
     o.bytes = 0;
     o.blk = 0;
     o.ordered = false;
+    o.ws = nullptr;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; bytes = o.bytes; blk = o.blk; ast = o.ast; ordered = o.ordered;
-      o.p = nullptr; o.bytes = 0; o.blk = 0; o.ordered = false;
+      p = o.p; bytes = o.bytes; blk = o.blk; ast = o.ast; ordered = o.ordered; ws = o.ws;
+      o.p = nullptr; o.bytes = 0; o.blk = 0; o.ordered = false; o.ws = nullptr;
     }
     return *this;
   }
   ~DevBuf() { release(); }
+  static size_t ws_round(size_t n) { return (n + 255) & ~(size_t)255; }
   void release() {
     if (p) {
-      if (ordered) {
+      if (ws) {
+        if (static_cast<char*>(p) + ws_round(bytes) == ws->base + ws->used)
+          ws->used = static_cast<size_t>(static_cast<char*>(p) - ws->base);
+      } else if (ordered) {
         (void)hipFreeAsync(p, ast);
       } else if (blk) {
         cached_free(p, blk);
@@ -102,10 +127,25 @@ struct DevBuf {
     bytes = 0;
     blk = 0;
     ordered = false;
+    ws = nullptr;
   }
   static int status_of(hipError_t e) { return e == hipErrorOutOfMemory ? DT_E_NOMEM : DT_E_DEVICE; }
+  // Memory from the thread's workspace (see Workspace).
+  int alloc_ws(Workspace* w, size_t n) {
+    release();
+    if (n == 0) n = 16;
+    const size_t r = ws_round(n);
+    if (w->used > w->cap || r > w->cap - w->used) return DT_E_NOMEM;
+    p = w->base + w->used;
+    w->used += r;
+    if (w->used > w->peak) w->peak = w->used;
+    bytes = n;
+    ws = w;
+    return DT_OK;
+  }
   // Scratch memory (stream-ordered when the thread has an allocation stream).
   int alloc(size_t n) {
+    if (Workspace* w = workspace()) return alloc_ws(w, n);
     hipStream_t s = alloc_stream();
     if (!s) return alloc_plain(n);
     release();
@@ -119,6 +159,7 @@ struct DevBuf {
   }
   // Memory that outlives the call (result rows): never stream-ordered.
   int alloc_plain(size_t n) {
+    if (Workspace* w = workspace()) return alloc_ws(w, n);
     release();
     if (n == 0) n = 16;
     hipError_t e = cached_malloc(&p, n, &blk);

@@ -23,6 +23,7 @@ struct Ctx {
   DevBuf dctr, dflag;
   Counters* hctr = nullptr;
   uint32_t* hflag = nullptr;
+  bool pinned = true;   // hctr is a pinned block of the per-thread cache
   ~Ctx();
   int init();
   Counters* dc() const { return dctr.as<Counters>(); }
