@@ -148,6 +148,8 @@ typedef struct dt_stats {
   int64_t candidates;         /* cavity searches (winning and losing) over all rounds   */
   int64_t divide_used;        /* DT_DIVIDE_SAMPLE or DT_DIVIDE_KD                        */
   double divide_stat;         /* DT_DIVIDE_AUTO: the sample's grid-count variation       */
+  int64_t large_cavities;     /* insertion rounds in which one cavity outgrew the
+                                 per-candidate lists and used a pool-sized list   */
 } dt_stats;
 
 typedef struct dt_result dt_result;
@@ -328,8 +330,9 @@ int dt_result_set_offsets(const dt_result* r, int64_t* dst, int64_t cap);
  * grow_div, cand_blocks) for batches like this one.  Times batched runs on
  * every s-th set (about sample_points points in all; <= 0 means 4 Mi),
  * changing one tunable at a time from the defaults (a trial is the faster
- * of two runs; a change must gain 3 %), and writes opt (NULL =
- * defaults) with the fastest tunables into *tuned.  The choice is cached
+ * of two runs; a change must gain 3 %); a result other than the defaults
+ * is kept only if it is also 2 % faster on the whole batch.  Writes opt
+ * (NULL = defaults) with the chosen tunables into *tuned.  The choice is cached
  * per (D, precision, log2 mean set size, log2 set count) for the life of
  * the process; a cached class returns at once.  points / offsets /
  * points_on_device / stream as for dt_batch_triangulate.  The tunables
@@ -342,13 +345,17 @@ int dt_batch_autotune(const double* points, const int64_t* offsets, int64_t num_
 /*
  * Serving (continuous batching; the paper's method applied to a stream of
  * independent requests).  A server owns a device-memory budget and four
- * worker threads, each with its own stream.  Jobs are admitted in arrival
- * order while their estimated footprint fits the budget (a job alone may
- * use the whole budget).  A worker takes the admitted jobs that have not
- * started: consecutive direct jobs (k = 1) of one dimension run together
- * as one batched run (as dt_batch_triangulate, up to 8 Mi points), a
- * divide-and-conquer job (k > 1) runs alone; the workers' runs overlap
- * on the device.  Each job's result (rows labelled by row index, sorted
+ * worker threads, each with its own stream.  A job's points are copied to
+ * device memory at submission and stay there until the job is done (the
+ * queue lives on the device; these copies are outside the budget).  Jobs
+ * are admitted in arrival order while their estimated footprint fits the
+ * budget (a job alone may use the whole budget).  A worker takes the
+ * admitted jobs that have not started: consecutive jobs of one dimension
+ * with at most 2 Mi points each run together as one batched run of
+ * independent sets (as dt_batch_triangulate, up to 8 Mi points; the k of
+ * such a job is not used, since the result does not depend on it), a
+ * larger job runs alone with its k-way divide-and-conquer; the workers'
+ * runs overlap on the device.  Each job's result (rows labelled by row index, sorted
  * when opt.sort_output) is identical to dt_triangulate on its own; if a
  * batched run fails its jobs run again one by one, so each gets its own
  * status.  Statistics of a batched job are those of its batch (n, k,

@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("probe_hist", ctypes.c_int64 * 16), ("kern_ms", ctypes.c_double * 8),
                 ("kern_launches", ctypes.c_int64 * 8), ("cavity_cells", ctypes.c_int64),
                 ("candidates", ctypes.c_int64),
-                ("divide_used", ctypes.c_int64), ("divide_stat", ctypes.c_double)]
+                ("divide_used", ctypes.c_int64), ("divide_stat", ctypes.c_double),
+                ("large_cavities", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_

@@ -70,6 +70,13 @@ struct Counters {
   unsigned long long cand_total;  // candidates over all rounds
   unsigned int last_ins;          // inserted in the last round (diagnostics)
   unsigned int last_cand;         // candidates in the last round (diagnostics)
+  // candidates whose cavity outgrew its list this round: the smallest
+  // bid key among them; that point may use the pool-sized list next round
+  unsigned long long giant_req;
+  unsigned int giant_owner;       // point allowed the pool-sized list (DONE: none)
+  unsigned int giant_need;        // 1: a request came before the list existed
+  unsigned int giant_rounds;      // rounds with a pool-sized-list owner
+  unsigned int pad3;
 };
 
 }  // namespace dtk

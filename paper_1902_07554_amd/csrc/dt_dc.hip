@@ -91,6 +91,7 @@ static void add_pred(dt_stats& s, const K4Stats& ks) {
   for (int i = 0; i < 4; i++)
     for (int j = 0; j < 4; j++) s.pred[i][j] += (int64_t)ks.pred[i][j];
   s.rounds += ks.rounds;
+  s.large_cavities += ks.giant_rounds;
   s.cavity_cells += (int64_t)ks.cavity_cells;
   s.candidates += (int64_t)ks.candidates;
 }

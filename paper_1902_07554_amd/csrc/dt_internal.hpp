@@ -208,6 +208,7 @@ struct K4Stats {
   unsigned long long candidates = 0;
   unsigned long long verified = 0;    // cavity searches that completed
   int rounds = 0;
+  uint32_t giant_rounds = 0;   // rounds in which a cavity used the pool-sized list
   uint32_t maxcav = 0;
   unsigned long long pred[4][4] = {};
 };

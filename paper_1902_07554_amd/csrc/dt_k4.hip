@@ -92,6 +92,11 @@ struct K4Args {
   unsigned long long* bid;
   uint32_t rings;       // bid rings checked by the selection (0 to 3)
   int fp32;
+  // pool-sized cavity list for the one candidate per round whose cavity
+  // outgrew the regular list (allocated on the first such request)
+  uint32_t* gcell;
+  uint32_t* ginfo;
+  uint32_t gcap;
 };
 
 // Large cavities spill from the fixed per-candidate list into extension
@@ -107,6 +112,8 @@ struct Stripes {
   unsigned long long verified[NSTRIPE];   // candidates whose search completed
 };
 constexpr uint32_t EXTCAP = 8192;
+// cand_ext value of the candidate that uses the pool-sized list
+constexpr uint32_t GIANT = 0xFFFFFFFEu;
 
 struct CavList {
   uint32_t* a;
@@ -553,6 +560,18 @@ __global__ void k4_ctl_init(K4Args a, uint32_t thresh0) {
   c->rebuild = 1;
   c->nact = 0;
   c->built_thresh = thresh0;
+  c->giant_req = NOKEY;
+  c->giant_owner = DONE;
+  c->giant_need = 0;
+  c->giant_rounds = 0;
+}
+
+// Continue after the host has allocated the pool-sized cavity list.
+__global__ void k4_resume(K4Args a) {
+  Counters* c = a.ctr;
+  c->giant_need = 0;
+  c->stall = 0;
+  c->skip = (c->remaining == 0 || c->flags) ? 1u : 0u;
 }
 
 // End of a round: account the insertions, move to the next level when
@@ -588,6 +607,17 @@ __global__ void k4_ctl_end(K4Args a) {
     if (++c->stall > 8) c->flags |= FAIL_NO_PROGRESS;
   }
   if (ins) c->stall = 0;
+  // the smallest candidate whose cavity outgrew its list gets the
+  // pool-sized list next round; if that list does not exist yet, pause
+  // (skip) until the host has allocated it
+  c->giant_owner = c->giant_req != NOKEY ? (uint32_t)(c->giant_req & 0xFFFFFFFFull) : DONE;
+  c->giant_req = NOKEY;
+  if (c->giant_owner != DONE) c->giant_rounds++;
+  if (c->giant_owner != DONE && a.gcap == 0) {
+    c->giant_need = 1;
+    c->stall = 0;
+    c->skip = 1;
+  }
   if (c->remaining == 0 || c->flags) c->skip = 1;
   c->ncand = c->inserted = c->overflow = c->extused = c->pending = 0;
   if (c->thresh != c->built_thresh || c->ins_since * 2 > c->nact) {
@@ -811,12 +841,16 @@ __global__ __launch_bounds__(64, 3) void k4_cavity(K4Args a) {
         const uint32_t q = a.cand_pt[slot];
         const unsigned long long Kq = make_key(a.round, q);
         const uint32_t L = a.ploc[q] & LOCMASK;
-        a.cand_ext[slot] = DONE;
+        const bool giant = a.gcap != 0 && q == a.ctr->giant_owner;
+        a.cand_ext[slot] = giant ? GIANT : DONE;
         // the own cell was claimed at selection; a smaller claim means a
         // smaller candidate's cavity holds it already
         const bool ok = atomicMin(&a.cells[L].cav, Kq) >= Kq;
-        if (ok) a.cav[(size_t)slot * a.cavcap] = L;
-        s_ext[g] = DONE;
+        if (ok) {
+          if (giant) a.gcell[0] = L;
+          else a.cav[(size_t)slot * a.cavcap] = L;
+        }
+        s_ext[g] = giant ? GIANT : DONE;
         s_abort[g] = ok ? 0u : 1u;
         s_gave[g] = 0;
         s_n[g] = ok ? 1u : 0u;
@@ -840,7 +874,7 @@ __global__ __launch_bounds__(64, 3) void k4_cavity(K4Args a) {
       for (uint32_t j = gl; j < CAV_STASH; j += GL) s_tag[g][j] = DONE;
     }
     // leaders make room for the level's appends
-    if (gl == 0 && busy && !s_abort[g] && s_flo[g] < s_fhi[g]) {
+    if (gl == 0 && busy && !s_abort[g] && s_flo[g] < s_fhi[g] && s_ext[g] != GIANT) {
       const uint32_t items = (s_fhi[g] - s_flo[g]) * (D + 1);
       if (s_n[g] + items > a.cavcap) {
         if (s_n[g] + items > a.cavcap + EXTCAP) {
@@ -857,12 +891,18 @@ __global__ __launch_bounds__(64, 3) void k4_cavity(K4Args a) {
           }
         }
       }
+      // a cavity too large for the regular list asks for the pool-sized
+      // one (the smallest such candidate of the round gets it next round)
+      if (s_gave[g]) atomicMin(&a.ctr->giant_req, bid_key(p));
     }
     __syncthreads();
     const uint32_t flo = s_flo[g], fhi = s_fhi[g];
     if (busy && !s_abort[g] && flo < fhi) {
-      uint32_t* la = a.cav + (size_t)slot * a.cavcap;
-      uint32_t* lb = (s_ext[g] == DONE) ? nullptr : a.extcell + (size_t)s_ext[g] * EXTCAP;
+      const bool giant = s_ext[g] == GIANT;
+      uint32_t* la = giant ? a.gcell : a.cav + (size_t)slot * a.cavcap;
+      const uint32_t lcap = giant ? a.gcap : a.cavcap;
+      uint32_t* lb = (giant || s_ext[g] == DONE) ? nullptr
+                                                 : a.extcell + (size_t)s_ext[g] * EXTCAP;
       const uint32_t items = (fhi - flo) * (D + 1);
       for (uint32_t it = gl; it < items; it += GL) {
         if (s_abort[g]) break;
@@ -873,7 +913,7 @@ __global__ __launch_bounds__(64, 3) void k4_cavity(K4Args a) {
         if (s_tag[g][si] == h) {
           t = vat(s_lnk[g][si], i) >> 2;
         } else {
-          const uint32_t c = h < a.cavcap ? la[h] : lb[h - a.cavcap];
+          const uint32_t c = h < lcap ? la[h] : lb[h - lcap];
           t = vat(a.cells[c].n, i) >> 2;
         }
         if (t >= a.cap) {
@@ -904,8 +944,17 @@ __global__ __launch_bounds__(64, 3) void k4_cavity(K4Args a) {
           if (old < K) { s_abort[g] = 1; break; }
           if (old == K) continue;
           const uint32_t pos = atomicAdd(&s_n[g], 1u);
-          if (pos < a.cavcap) la[pos] = t;
-          else lb[pos - a.cavcap] = t;
+          if (pos < lcap) {
+            la[pos] = t;
+          } else if (lb && pos - lcap < EXTCAP) {
+            lb[pos - lcap] = t;
+          } else {
+            // only the pool-sized list can get here: more cavity cells
+            // than cells in the pool
+            atomicOr(&a.ctr->flags, FAIL_INVARIANT);
+            s_abort[g] = 1;
+            break;
+          }
           // the slot's previous entry is from an earlier level (no reader
           // of this level can hold its tag)
           if (pos < flo + CAV_STASH) {
@@ -1048,7 +1097,11 @@ __global__ __launch_bounds__(64 * INS_WAVES) void k4_insert(K4Args a) {
                nullptr, a.cavcap};
     if (n) {
       const uint32_t e = a.cand_ext[slot];
-      if (e != DONE) {
+      if (e == GIANT) {
+        cl.a = a.gcell;
+        cl.ia = a.ginfo;
+        cl.cap = a.gcap;
+      } else if (e != DONE) {
         cl.b = a.extcell + (size_t)e * EXTCAP;
         cl.ib = a.extinfo + (size_t)e * EXTCAP;
       }
@@ -1363,6 +1416,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.fp32 = job.fp32 ? 1 : 0;
   a.vcell = vcell.as<uint32_t>();
   a.bid = bidbuf.as<unsigned long long>();
+  DevBuf gcell, ginfo;
+  a.gcell = nullptr;
+  a.ginfo = nullptr;
+  a.gcap = 0;
 
   if (D == 2)
     hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
@@ -1456,11 +1513,27 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     if (trace)
       fprintf(stderr, "[k4r] %u %u %u %u %u\n", hctr->rounds, hctr->thresh, hctr->nact,
               hctr->last_cand, hctr->last_ins);
+    if (hctr->giant_need) {
+      // a cavity outgrew the regular lists: give its candidate a list as
+      // large as the pool (no cavity can hold more cells), then go on
+      if (!gcell.p) {
+        DT_TRY(gcell.alloc(cap * sizeof(uint32_t)));
+        DT_TRY(ginfo.alloc(cap * sizeof(uint32_t)));
+        a.gcell = gcell.as<uint32_t>();
+        a.ginfo = ginfo.as<uint32_t>();
+        a.gcap = pool.cap;
+      }
+      if (dbg) fprintf(stderr, "[k4] pool-sized cavity list for point %u\n", hctr->giant_owner);
+      hipLaunchKernelGGL(k4_resume, dim3(1), dim3(1), 0, st, a);
+      DT_HIP(hipGetLastError());
+      continue;
+    }
     if (hctr->skip) break;
     if (group < 32 && !trace) group *= 2;
   }
   ks.rounds = (int)hctr->rounds;
   ks.candidates = hctr->cand_total;
+  ks.giant_rounds = hctr->giant_rounds;
   pool.ncells = hctr->cells;
   {
     Stripes hs;

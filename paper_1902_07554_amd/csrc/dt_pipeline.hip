@@ -73,6 +73,14 @@ __global__ void k_extract_grouped(const double4* pts, const uint32_t* pset, cons
   for (int i = 0; i <= D; i++) rows[(size_t)slot * (D + 1) + i] = k[i];
 }
 
+// Label of every point: its index inside its set.
+__global__ void k_local_labels(const uint32_t* off, const uint32_t* pset, uint32_t n,
+                               long long* keys) {
+  uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  keys[p] = (long long)(p - off[pset[p]]);
+}
+
 int extract_grouped(const LocalJob& job, const CellPool& pool,
                     const std::vector<int64_t>& set_offsets, int32_t* rows, hipStream_t st) {
   const uint32_t ns = job.nsets;
@@ -116,7 +124,8 @@ static int stage_input(const double* points, uint64_t n, int D, bool on_device, 
 }
 
 int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, int64_t num_sets,
-              int D, const dt_options& o, bool on_device, hipStream_t st, dt_result* r) {
+              int D, const dt_options& o, bool on_device, hipStream_t st, dt_result* r,
+              bool local_ids) {
   double t0 = now_ms();
   Ctx cx;
   DT_TRY(cx.init());
@@ -130,7 +139,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   DevBuf din, dkeys, pts, scratch, pset, setoff;
   const double* dp = nullptr;
   DT_TRY(stage_input(points, n, D, on_device, din, &dp, st));
-  if (ids) {
+  if (ids && !local_ids) {
     DT_TRY(dkeys.alloc((size_t)n * 8));
     DT_HIP(hipMemcpyAsync(dkeys.p, ids, (size_t)n * 8, hipMemcpyHostToDevice, st));
   }
@@ -141,8 +150,15 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   DT_TRY(pset.alloc((size_t)n * 4));
   hipLaunchKernelGGL(k_set_of_point, dim3(blocks(n)), dim3(TB), 0, st, setoff.as<uint32_t>(), ns,
                      n, pset.as<uint32_t>());
+  if (local_ids) {
+    DT_TRY(dkeys.alloc((size_t)n * 8));
+    hipLaunchKernelGGL(k_local_labels, dim3(blocks(n)), dim3(TB), 0, st, setoff.as<uint32_t>(),
+                       pset.as<uint32_t>(), n, dkeys.as<long long>());
+    DT_HIP(hipGetLastError());
+  }
   DT_TRY(pts.alloc((size_t)n * sizeof(double4)));
-  DT_TRY(prep_points(dp, ids ? dkeys.as<long long>() : nullptr, ns > 1 ? pset.as<uint32_t>() : nullptr,
+  DT_TRY(prep_points(dp, (ids || local_ids) ? dkeys.as<long long>() : nullptr,
+                     ns > 1 ? pset.as<uint32_t>() : nullptr,
                      n, D, pts.as<double4>(), scratch, cx.dflag.as<uint32_t>(), cx.hflag, st));
   {
     // order every set along a space-filling curve (the set is the major
@@ -200,6 +216,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   double t3 = now_ms();
   r->stats.num_simplices = r->m;
   r->stats.rounds = ks.rounds;
+  r->stats.large_cavities = ks.giant_rounds;
   r->stats.cavity_cells = (int64_t)ks.cavity_cells;
   r->stats.candidates = (int64_t)ks.candidates;
   fill_pred_stats(r->stats, ks);

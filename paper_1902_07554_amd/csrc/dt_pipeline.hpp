@@ -39,8 +39,10 @@ int run_triangulate(const double* points, int64_t n, int D, int k, double sample
                     const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
 int run_dc(const double* points, int64_t n, int D, int k, double sample_rate,
            const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+// local_ids: label every point by its index inside its set (ids unused).
 int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, int64_t num_sets,
-              int D, const dt_options& o, bool on_device, hipStream_t st, dt_result* r);
+              int D, const dt_options& o, bool on_device, hipStream_t st, dt_result* r,
+              bool local_ids = false);
 // Recursive bisection: log2 k levels of 2-way division, k-1 merges.
 int run_recursive(const double* points, int64_t n, int D, int k, double sample_rate,
                   const dt_options& o, bool on_device, hipStream_t st, dt_result* r);

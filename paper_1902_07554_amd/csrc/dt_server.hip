@@ -1,18 +1,20 @@
 // Serving: continuous batching of triangulation jobs under a device-memory
 // budget.
 //
-// A job is admitted (FIFO) when its estimated footprint fits the remaining
-// budget.  Four worker threads, each with its own HIP stream, repeatedly take
-// the admitted jobs that have not started: a run of consecutive direct jobs
-// (k = 1) is triangulated together as one batched run (all of them share
-// every kernel launch); a divide-and-conquer job (k > 1) runs on its own.
-// Jobs that arrive while a batch runs are admitted as memory frees up and
-// start with the next batch, which may run concurrently with the other
-// workers' batches.  A job's result is DT of its own points labelled by row
-// index, with the row index as tie-break order: what dt_triangulate returns
-// for it alone, since the triangulation depends only on the point set.  If a
-// batched run fails, its jobs run again one by one so that each gets its own
-// status.
+// A job's points are copied to device memory when it is submitted and stay
+// there until it finishes.  A job is admitted (FIFO) when its estimated
+// footprint fits the remaining budget.  Four worker threads, each with its
+// own HIP stream, repeatedly take the admitted jobs that have not started:
+// a run of consecutive jobs of at most DIRECT_MAX points (whatever their k)
+// is triangulated together as one batched run of independent sets (all of
+// them share every kernel launch); a larger job runs on its own with its
+// divide-and-conquer.  Jobs that arrive while a batch runs are admitted as
+// memory frees up and start with the next batch, which may run concurrently
+// with the other workers' batches.  A job's result is DT of its own points
+// labelled by row index, with the row index as tie-break order: what
+// dt_triangulate returns for it alone, since the triangulation depends only
+// on the point set.  If a batched run fails, its jobs run again one by one
+// so that each gets its own status.
 #include <string.h>
 
 #include <chrono>
@@ -45,7 +47,7 @@ struct Job {
   int64_t n = 0;
   int D = 3, k = 1;
   double rate = 0.0;
-  std::vector<double> host;   // points (host copy)
+  DevBuf dev;                  // points (device copy, n x D doubles)
   size_t footprint = 0;
   double t[3] = {0, 0, 0};    // submitted, admitted, done
   int status = DT_OK;
@@ -69,6 +71,10 @@ size_t footprint_of(int64_t n, int D, int k) {
 }
 
 constexpr int64_t MAX_BATCH_POINTS = 8 << 20;
+// Jobs up to this size join batched runs of independent sets: one set of a
+// batch costs far less than a divide-and-conquer run of its own, whose
+// rounds are latency-bound (the result is the same either way).
+constexpr int64_t DIRECT_MAX = 1 << 21;
 // One worker per hardware queue the runtime gives a process by default.
 constexpr int NUM_WORKERS = 4;
 
@@ -105,7 +111,8 @@ struct dt_server {
   void run_alone(Job* j, hipStream_t st) {
     dt_result* r = new dt_result();
     r->D = j->D;
-    int s = run_triangulate(j->host.data(), j->n, j->D, j->k, j->rate, opt, false, st, r);
+    const int k = j->n <= DIRECT_MAX ? 1 : j->k;
+    int s = run_triangulate(j->dev.as<double>(), j->n, j->D, k, j->rate, opt, true, st, r);
     if (s == DT_OK && opt.sort_output) s = sort_rows_inplace(r, st);
     if (s != DT_OK) {
       delete r;
@@ -154,16 +161,19 @@ struct dt_server {
     int D = b[0]->D;   // a batch holds jobs of one dimension
     std::vector<int64_t> off(b.size() + 1, 0);
     for (size_t i = 0; i < b.size(); i++) off[i + 1] = off[i] + b[i]->n;
-    std::vector<double> pts((size_t)off.back() * D);
-    std::vector<int64_t> ids((size_t)off.back());
-    for (size_t i = 0; i < b.size(); i++) {
-      memcpy(pts.data() + off[i] * D, b[i]->host.data(), (size_t)b[i]->n * D * 8);
-      for (int64_t q = 0; q < b[i]->n; q++) ids[off[i] + q] = q;
-    }
+    // the jobs' points side by side (device to device); every point is
+    // labelled by its index inside its job
+    DevBuf pts;
+    int s = pts.alloc((size_t)off.back() * D * 8);
+    for (size_t i = 0; s == DT_OK && i < b.size(); i++)
+      if (hipMemcpyAsync(pts.as<double>() + off[i] * D, b[i]->dev.p, (size_t)b[i]->n * D * 8,
+                         hipMemcpyDeviceToDevice, st) != hipSuccess)
+        s = DT_E_DEVICE;
     dt_result all;
     all.D = D;
-    int s = run_batch(pts.data(), ids.data(), off.data(), (int64_t)b.size(), D, opt, false, st,
-                      &all);
+    if (s == DT_OK)
+      s = run_batch(pts.as<double>(), nullptr, off.data(), (int64_t)b.size(), D, opt, true, st,
+                    &all, true);
     for (size_t i = 0; i < b.size(); i++) {
       if (s == DT_OK) split_out(b[i], all, all.set_offsets[i], all.set_offsets[i + 1], st);
       else run_alone(b[i], st);
@@ -188,7 +198,7 @@ struct dt_server {
         int64_t pts = 0;
         while (!ready.empty()) {
           Job* j = ready.front();
-          if (!b.empty() && (j->k > 1 || b[0]->k > 1 || j->D != b[0]->D ||
+          if (!b.empty() && (j->n > DIRECT_MAX || b[0]->n > DIRECT_MAX || j->D != b[0]->D ||
                              pts + j->n > MAX_BATCH_POINTS))
             break;
           ready.pop_front();
@@ -200,7 +210,7 @@ struct dt_server {
       if (!b.empty()) {
         try {
           run_batch_of(b, st);
-        } catch (const std::bad_alloc&) {   // host memory for the batch
+        } catch (const std::bad_alloc&) {   // host memory of the batch's bookkeeping
           for (Job* j : b)
             if (!j->res && j->status == DT_OK) j->status = DT_E_NOMEM;
         }
@@ -212,8 +222,7 @@ struct dt_server {
           j->done = true;
           j->t[2] = now;
           used -= j->footprint;
-          j->host.clear();
-          j->host.shrink_to_fit();
+          j->dev.release();   // its last uses were on this worker's stream
         }
         admit();
       }
@@ -258,27 +267,22 @@ extern "C" int dt_server_submit(dt_server* s, const double* points, int64_t n, i
   j->D = D;
   j->k = k;
   j->rate = sample_rate;
-  j->footprint = footprint_of(n, D, k);
+  j->footprint = footprint_of(n, D, n <= DIRECT_MAX ? 1 : k);
   if (j->footprint > s->budget) {
     delete j;
     return DT_E_NOMEM;
   }
-  try {
-    j->host.resize((size_t)n * D);
-  } catch (const std::bad_alloc&) {
+  // the job's points live on the device from now until the job is done
+  int as = j->dev.alloc_plain((size_t)n * D * 8);
+  if (as != DT_OK) {
     delete j;
-    return DT_E_NOMEM;
+    return as;
   }
-  {
-    if (points_on_device) {
-      if (hipMemcpy(j->host.data(), points, (size_t)n * D * 8, hipMemcpyDeviceToHost) !=
-          hipSuccess) {
-        delete j;
-        return DT_E_DEVICE;
-      }
-    } else {
-      memcpy(j->host.data(), points, (size_t)n * D * 8);
-    }
+  if (hipMemcpy(j->dev.p, points, (size_t)n * D * 8,
+                points_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    delete j;
+    return DT_E_DEVICE;
   }
   {
     std::lock_guard<std::mutex> lk(s->mu);

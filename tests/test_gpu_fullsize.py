@@ -120,6 +120,18 @@ def test_bubbles_4m_kd_equals_sample(dtlib, bubbles_4m):
     assert _same_set(a, b)
 
 
+def test_bubbles_4m_as_one_set(dtlib, bubbles_4m):
+    """The whole 4M bubbles input as a single set (k = 1): clustered
+    points give cavities larger than the per-candidate lists, which take the
+    pool-sized list; the whole output is certified."""
+    import torch
+    print("[fullsize] bubbles 4M, one set", flush=True)
+    res = dtlib.triangulate(torch.from_numpy(bubbles_4m).cuda(), k=1, precision="fp32")
+    print(f"[fullsize] rounds with a pool-sized cavity list: {res.stats()['large_cavities']}",
+          flush=True)
+    _certify(bubbles_4m, res.rows())
+
+
 def test_bubbles_4m_nearest_sample(dtlib):
     """The nearest-sample assignment of the 4M bubbles run: 50,000 sampled
     points against the oracle's search over all samples, and the partition

@@ -154,6 +154,46 @@ def test_fp32_filter_on_jittered_lattices(dtlib, dim, side, rel, k):
     assert ins["fp64"] + ins["exact"] > 0
 
 
+def _sphere_and_centre(n, dim, seed, jitter=1e-4):
+    """n points within a relative `jitter` of the unit sphere (circle) and
+    its centre, randomly permuted: inserted after a few percent of the
+    sphere points, the centre's conflict region holds almost every cell."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, dim))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    v *= 1.0 + jitter * rng.uniform(-1.0, 1.0, (n, 1))
+    p = np.concatenate([v, np.zeros((1, dim))])
+    return p[rng.permutation(len(p))]
+
+
+def _circles_and_centres(count, n, seed):
+    """`count` circles of n points each (radius 1, centres 4 apart on a
+    line) and their centres, randomly permuted: each centre inserted after
+    a fifth of its circle's points has a conflict region of more than 8,300
+    triangles."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for c in range(count):
+        t = rng.uniform(0.0, 2.0 * np.pi, n)
+        ring = np.stack([np.cos(t), np.sin(t)], 1) + [4.0 * c, 0.0]
+        parts += [ring, [[4.0 * c, 0.0]]]
+    p = np.concatenate(parts)
+    return p[rng.permutation(len(p))]
+
+
+@pytest.mark.parametrize("dim,n,precision", [(3, 100_000, "fp64"), (2, 12_000, "fp32")])
+def test_cavity_larger_than_the_candidate_lists(dtlib, dim, n, precision):
+    """A cavity of more cells than a candidate's list and its extension
+    chunk hold (192 + 8192 in 3D, 96 + 8192 in 2D) is inserted through the
+    pool-sized list: the result is the oracle's DT."""
+    p = _sphere_and_centre(n, dim, seed=5) if dim == 3 else _circles_and_centres(10, n, seed=5)
+    print(f"[large cavity] dim={dim} n={len(p)}", flush=True)
+    res = dtlib.triangulate(p, k=1, precision=precision)
+    st = res.stats()
+    assert st["large_cavities"] >= 1
+    assert np.array_equal(_rows(res), oracle.delaunay(p))
+
+
 @pytest.mark.parametrize("dim,k", [(2, 1), (3, 1), (3, 8)])
 def test_neighbors_match_oracle(dtlib, dim, k):
     """dt_result_neighbors equals the facet-sharing definition on the rows

@@ -45,6 +45,29 @@ def test_server_mix_matches_standalone_and_oracle(dtlib):
         assert t[0] <= t[1] <= t[2]
 
 
+def test_server_large_jobs_match_standalone(dtlib):
+    """Jobs of the served workload's largest sizes: two of 1M points
+    (batched with small jobs as independent sets) and one of 2.2M points
+    (above the batching limit: its own k-way divide-and-conquer), each
+    identical to dt_triangulate on it alone with its k."""
+    jobs = [(inputs.make("bubbles", 1_000_000, 3, seed=31), 64),
+            (inputs.make("uniform", 5_000, 3, seed=32), 1),
+            (inputs.make("uniform", 1_000_000, 3, seed=33), 64),
+            (inputs.make("bubbles", 40_000, 3, seed=34), 2),
+            (inputs.make("uniform", 2_200_000, 3, seed=35), 128)]
+    print("[server] large jobs", flush=True)
+    srv = dtlib.Server(64 << 30)
+    try:
+        tickets = [srv.submit(p, k=k) for p, k in jobs]
+        got = [oracle.canonical(srv.wait(t).rows()) for t in tickets]
+    finally:
+        srv.close()
+    for i, ((p, k), rows) in enumerate(zip(jobs, got)):
+        alone = oracle.canonical(dtlib.triangulate(p, k=k, precision="fp64").rows())
+        assert np.array_equal(rows, alone), i
+    assert np.array_equal(got[1], oracle.delaunay(jobs[1][0]))
+
+
 def test_server_fifo_admission_under_budget(dtlib):
     """A budget of about one job: admission times follow ticket order and
     every job still finishes."""
