@@ -373,12 +373,13 @@ __global__ void k_lp_list(uint32_t eta, const uint32_t* pblock, const uint32_t* 
 // (capacity measured at the start of the sweep, so the bound always holds).
 __global__ void k_lp_accept(uint32_t eta, const uint32_t* pblock, const double* pgain,
                             const uint32_t* poff, const uint32_t* pcount, const uint32_t* plist,
-                            const int* size, int lmax, uint32_t* part, int* delta) {
+                            const int* size, int lmax, const int* lmax_of, uint32_t* part,
+                            int* delta) {
   uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= eta) return;
   uint32_t b = pblock[v];
   if (b == DONE) return;
-  int room = lmax - size[b];
+  int room = (lmax_of ? lmax_of[b] : lmax) - size[b];
   if (room <= 0) return;
   double g = pgain[v];
   uint32_t rank = 0;
@@ -431,10 +432,8 @@ __global__ __launch_bounds__(256) void k_count_u32_lds(const uint32_t* x, uint32
     if (s_c[j]) atomicAdd(&cnt[j], s_c[j]);
 }
 
-int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
-                     const dt_options& o, const double lo[3], const double hi[3],
-                     DevBuf& part, double* cut, DevBuf& goff, DevBuf& gadj, DevBuf& gw,
-                     hipStream_t st) {
+int sample_graph(const double4* S, uint32_t eta, int D, const CellPool& pool, int weight,
+                 double dstar, DevBuf& goff, DevBuf& gadj, DevBuf& gw, hipStream_t st) {
   // edges
   uint32_t ncells = pool.ncells;
   uint32_t tsize = 1024;
@@ -446,8 +445,10 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   DT_TRY(ecount.alloc(4));
   DT_HIP(hipMemsetAsync(table.p, 0xFF, (size_t)tsize * 8, st));
   DT_HIP(hipMemsetAsync(ecount.p, 0, 4, st));
-  hipLaunchKernelGGL(k_edges, dim3(dblocks(ncells)), dim3(DB), 0, st, pool.cells.as<Cell>(), ncells, D, table.as<unsigned long long>(),
-                     tsize - 1, elist.as<uint32_t>(), ecount.as<uint32_t>(), ecap);
+  if (ncells)
+    hipLaunchKernelGGL(k_edges, dim3(dblocks(ncells)), dim3(DB), 0, st, pool.cells.as<Cell>(),
+                       ncells, D, table.as<unsigned long long>(), tsize - 1, elist.as<uint32_t>(),
+                       ecount.as<uint32_t>(), ecap);
   DT_HIP(hipGetLastError());
   uint32_t m = 0;
   DT_HIP(hipMemcpyAsync(&m, ecount.p, 4, hipMemcpyDeviceToHost, st));
@@ -461,17 +462,69 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   DT_TRY(w.alloc((size_t)2 * m * 8 + 8));
   DT_HIP(hipMemsetAsync(deg.p, 0, (size_t)(eta + 1) * 4, st));
   DT_HIP(hipMemsetAsync(cur.p, 0, (size_t)(eta + 1) * 4, st));
-  hipLaunchKernelGGL(k_degree, dim3(dblocks(m)), dim3(DB), 0, st, elist.as<uint32_t>(), m,
-                     deg.as<uint32_t>());
+  if (m)
+    hipLaunchKernelGGL(k_degree, dim3(dblocks(m)), dim3(DB), 0, st, elist.as<uint32_t>(), m,
+                       deg.as<uint32_t>());
   DT_TRY(exclusive_scan(deg.as<uint32_t>(), off.as<uint32_t>(), eta + 1, st));
-  hipLaunchKernelGGL(k_fill_adj, dim3(dblocks(m)), dim3(DB), 0, st, elist.as<uint32_t>(), m,
-                     off.as<uint32_t>(), cur.as<uint32_t>(), adj.as<uint32_t>());
-  double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
-  double dstar = sqrt(dx * dx + dy * dy + dz * dz);
+  if (m)
+    hipLaunchKernelGGL(k_fill_adj, dim3(dblocks(m)), dim3(DB), 0, st, elist.as<uint32_t>(), m,
+                       off.as<uint32_t>(), cur.as<uint32_t>(), adj.as<uint32_t>());
   if (!(dstar > 0)) dstar = 1.0;
   hipLaunchKernelGGL(k_adj_weights, dim3(dblocks(eta)), dim3(DB), 0, st, S, eta,
-                     off.as<uint32_t>(), adj.as<uint32_t>(), w.as<double>(), o.weight, dstar);
+                     off.as<uint32_t>(), adj.as<uint32_t>(), w.as<double>(), weight, dstar);
   DT_HIP(hipGetLastError());
+  goff = std::move(off);
+  gadj = std::move(adj);
+  gw = std::move(w);
+  return DT_OK;
+}
+
+int refine_partition(uint32_t eta, const uint32_t* goff, const uint32_t* gadj, const double* gw,
+                     uint32_t* part, uint32_t k, int lmax, const int* lmax_of, int iters,
+                     hipStream_t st) {
+  DevBuf size, delta, pblock, pgain, pcount, poff, pcur, plist;
+  DT_TRY(size.alloc((size_t)k * 4));
+  DT_TRY(delta.alloc((size_t)k * 4));
+  DT_TRY(pblock.alloc((size_t)eta * 4));
+  DT_TRY(pgain.alloc((size_t)eta * 8));
+  DT_TRY(pcount.alloc((size_t)(k + 1) * 4));
+  DT_TRY(poff.alloc((size_t)(k + 1) * 4));
+  DT_TRY(pcur.alloc((size_t)(k + 1) * 4));
+  DT_TRY(plist.alloc((size_t)eta * 4));
+  DT_HIP(hipMemsetAsync(size.p, 0, (size_t)k * 4, st));
+  DT_HIP(hipMemsetAsync(delta.p, 0, (size_t)k * 4, st));
+  hipLaunchKernelGGL(k_count_u32, dim3(dblocks(eta)), dim3(DB), 0, st, part, eta,
+                     (uint32_t*)size.p);
+  for (int it = 0; it < iters; it++) {
+    DT_HIP(hipMemsetAsync(pcount.p, 0, (size_t)(k + 1) * 4, st));
+    DT_HIP(hipMemsetAsync(pcur.p, 0, (size_t)(k + 1) * 4, st));
+    hipLaunchKernelGGL(k_lp_propose, dim3((eta + LP_WAVES - 1) / LP_WAVES), dim3(64 * LP_WAVES), 0,
+                       st, eta, goff, gadj, gw, part, (uint32_t)it, pblock.as<uint32_t>(),
+                       pgain.as<double>(), pcount.as<uint32_t>());
+    DT_TRY(exclusive_scan(pcount.as<uint32_t>(), poff.as<uint32_t>(), k + 1, st));
+    hipLaunchKernelGGL(k_lp_list, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
+                       pblock.as<uint32_t>(), poff.as<uint32_t>(), pcur.as<uint32_t>(),
+                       plist.as<uint32_t>());
+    hipLaunchKernelGGL(k_lp_accept, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
+                       pblock.as<uint32_t>(), pgain.as<double>(), poff.as<uint32_t>(),
+                       pcount.as<uint32_t>(), plist.as<uint32_t>(), (const int*)size.p, lmax,
+                       lmax_of, part, (int*)delta.p);
+    hipLaunchKernelGGL(k_apply_delta, dim3(dblocks(k)), dim3(DB), 0, st, k, (int*)size.p,
+                       (int*)delta.p);
+    DT_HIP(hipGetLastError());
+  }
+  // the buffers are freed on return
+  DT_HIP(hipStreamSynchronize(st));
+  return DT_OK;
+}
+
+int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
+                     const dt_options& o, const double lo[3], const double hi[3],
+                     DevBuf& part, double* cut, DevBuf& goff, DevBuf& gadj, DevBuf& gw,
+                     hipStream_t st) {
+  double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+  double dstar = sqrt(dx * dx + dy * dy + dz * dz);
+  DT_TRY(sample_graph(S, eta, D, pool, o.weight, dstar, goff, gadj, gw, st));
   // initial blocks: recursive coordinate bisection of the sample (compact,
   // balanced to +-1 vertex when k is a power of two); otherwise k equal
   // chunks of the sample in Morton order
@@ -494,51 +547,18 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
                        k, part.as<uint32_t>());
   }
   // label propagation under the balance bound
-  DevBuf size, delta, pblock, pgain, pcount, poff, pcur, plist;
-  DT_TRY(size.alloc((size_t)k * 4));
-  DT_TRY(delta.alloc((size_t)k * 4));
-  DT_TRY(pblock.alloc((size_t)eta * 4));
-  DT_TRY(pgain.alloc((size_t)eta * 8));
-  DT_TRY(pcount.alloc((size_t)(k + 1) * 4));
-  DT_TRY(poff.alloc((size_t)(k + 1) * 4));
-  DT_TRY(pcur.alloc((size_t)(k + 1) * 4));
-  DT_TRY(plist.alloc((size_t)eta * 4));
-  DT_HIP(hipMemsetAsync(size.p, 0, (size_t)k * 4, st));
-  DT_HIP(hipMemsetAsync(delta.p, 0, (size_t)k * 4, st));
-  hipLaunchKernelGGL(k_count_u32, dim3(dblocks(eta)), dim3(DB), 0, st, part.as<uint32_t>(), eta,
-                     (uint32_t*)size.p);
   uint32_t avg = (eta + k - 1) / k;
   int lmax = (int)floor((1.0 + o.eps) * (double)avg + 1e-9);
-  for (int it = 0; it < o.refine_iters; it++) {
-    DT_HIP(hipMemsetAsync(pcount.p, 0, (size_t)(k + 1) * 4, st));
-    DT_HIP(hipMemsetAsync(pcur.p, 0, (size_t)(k + 1) * 4, st));
-    hipLaunchKernelGGL(k_lp_propose, dim3((eta + LP_WAVES - 1) / LP_WAVES), dim3(64 * LP_WAVES), 0,
-                       st, eta, off.as<uint32_t>(),
-                       adj.as<uint32_t>(), w.as<double>(), part.as<uint32_t>(), (uint32_t)it,
-                       pblock.as<uint32_t>(), pgain.as<double>(), pcount.as<uint32_t>());
-    DT_TRY(exclusive_scan(pcount.as<uint32_t>(), poff.as<uint32_t>(), k + 1, st));
-    hipLaunchKernelGGL(k_lp_list, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
-                       pblock.as<uint32_t>(), poff.as<uint32_t>(), pcur.as<uint32_t>(),
-                       plist.as<uint32_t>());
-    hipLaunchKernelGGL(k_lp_accept, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
-                       pblock.as<uint32_t>(), pgain.as<double>(), poff.as<uint32_t>(),
-                       pcount.as<uint32_t>(), plist.as<uint32_t>(), (const int*)size.p, lmax,
-                       part.as<uint32_t>(), (int*)delta.p);
-    hipLaunchKernelGGL(k_apply_delta, dim3(dblocks(k)), dim3(DB), 0, st, k, (int*)size.p,
-                       (int*)delta.p);
-    DT_HIP(hipGetLastError());
-  }
+  DT_TRY(refine_partition(eta, goff.as<uint32_t>(), gadj.as<uint32_t>(), gw.as<double>(),
+                          part.as<uint32_t>(), k, lmax, nullptr, o.refine_iters, st));
   DevBuf dcut;
   DT_TRY(dcut.alloc(8));
   DT_HIP(hipMemsetAsync(dcut.p, 0, 8, st));
-  hipLaunchKernelGGL(k_cut, dim3(dblocks(eta)), dim3(DB), 0, st, eta, off.as<uint32_t>(),
-                     adj.as<uint32_t>(), w.as<double>(), part.as<uint32_t>(), dcut.as<double>());
+  hipLaunchKernelGGL(k_cut, dim3(dblocks(eta)), dim3(DB), 0, st, eta, goff.as<uint32_t>(),
+                     gadj.as<uint32_t>(), gw.as<double>(), part.as<uint32_t>(), dcut.as<double>());
   DT_HIP(hipGetLastError());
   DT_HIP(hipMemcpyAsync(cut, dcut.p, 8, hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
-  goff = std::move(off);
-  gadj = std::move(adj);
-  gw = std::move(w);
   return DT_OK;
 }
 

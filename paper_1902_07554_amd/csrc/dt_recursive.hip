@@ -1,22 +1,28 @@
 // Recursive bisection (Section "Recursive Bisection"): log2 k levels of
 // 2-way division, then k-1 merges bottom-up.  This is the scheme of the
 // original divide-and-conquer triangulation (cyclic median split) and its
-// sample-based variant (a new sample per level); the one-shot k-way
-// division of Algorithm 1 is in dt_dc.hip.
+// sample-based variant (a new sample per block and level); the one-shot
+// k-way division of Algorithm 1 is in dt_dc.hip.
 //
 // Division: every level splits every block in two; the leaf index of a
 // point spells its path from the root (bit 1 = upper half), so its block
 // at the level with 2^l blocks is leaf >> (log2 k - l).
 //   kd:     the cyclic median split (kd_divide);
-//   sample: in every block, the eta(|block|) points of smallest random key
-//           form the block's sample; the sample is split at its median
-//           along its widest axis (the graph partitioner's initial cut for
-//           two parts), and every point of the block takes the side of its
-//           nearest sample of the block, under the key (fl(d^2), id).
+//   sample: Algorithm 2 with k = 2 in every block: the eta(|block|) points
+//           of smallest random key form the block's sample; the samples of
+//           all blocks are triangulated in one batched run; each block's
+//           sample graph (its Delaunay edges, weighted as in Table
+//           "weights") is cut in two by the partitioner (a median split of
+//           the sample along its widest axis, refined by label
+//           propagation under the balance bound); every point of the block
+//           takes the side of its nearest sample of the block, under the
+//           key (fl(d^2), id).
 // Merging (level by level, all parents of a level in one batched run):
 // the triangulations of the two children of a parent are known as simplex
-// lists; a simplex is a border simplex when its ball may reach a grid cell
-// holding points of the sibling (the grid test), the hull facets of each
+// lists; a simplex is a border simplex when its ball may reach the
+// sibling's region (the region test: the sibling's Voronoi cells of the
+// level's sample, or the sibling's kd box; or, on request, the grid test
+// against cells holding points of the sibling); the hull facets of each
 // child add their vertices; the border vertices of every parent are
 // triangulated together; the parent keeps the children's other simplices
 // and the border triangulation's simplices that span both children or are
@@ -34,6 +40,7 @@
 #include "dt_prep.hpp"
 #include "dt_prims.hpp"
 #include "dt_stages.hpp"
+#include "dt_region.hpp"
 
 namespace dtk {
 
@@ -77,8 +84,8 @@ __global__ void k_rb_sample_keys(uint32_t n, const uint32_t* pid, uint64_t salt,
 // nearest sample of the point's own block (grid over this level's samples;
 // samples of other blocks are skipped; exact argmin of (fl(d^2), id))
 __global__ void k_rb_assign(const double4* P, uint32_t n, const double4* S, const uint32_t* sblock,
-                            const uint8_t* sside, const uint32_t* start, const uint32_t* items,
-                            Grid G, uint32_t* pid) {
+                            const uint32_t* slabel, const uint32_t* start, const uint32_t* items,
+                            Grid G, uint32_t* pid, uint32_t* nearest) {
   const uint32_t i = blockIdx.x * RB + threadIdx.x;
   if (i >= n) return;
   const double4 p = P[i];
@@ -138,7 +145,77 @@ __global__ void k_rb_assign(const double4* P, uint32_t n, const double4* S, cons
       if (dm * dm > best * (1.0 + 1e-9)) break;
     }
   }
-  pid[i] = 2 * me + (bests == 0xFFFFFFFFu ? 0u : (uint32_t)sside[bests]);
+  pid[i] = 2 * me + (bests == 0xFFFFFFFFu ? 0u : (slabel[bests] & 1u));
+  nearest[i] = bests;
+}
+
+// the samples of every block: slot j of block b takes the (j - soff[b])-th
+// point of b's segment of the (block, random key) order
+__global__ void k_rb_take(const uint32_t* sorted, const uint32_t* seg, const uint32_t* soff,
+                          uint32_t nb, uint32_t ns, uint32_t* sidx, uint32_t* sblk) {
+  const uint32_t j = blockIdx.x * RB + threadIdx.x;
+  if (j >= ns) return;
+  const uint32_t b = seg_of(soff, nb, j);
+  sidx[j] = sorted[seg[b] + (j - soff[b])];
+  sblk[j] = b;
+}
+
+// order-preserving unsigned image of a double
+__device__ __forceinline__ unsigned long long ord_of(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// bounding box of every block's sample (ordered images, atomic min / max)
+__global__ void k_rb_sbox(const double4* S, const uint32_t* sblk, uint32_t ns, int D,
+                          unsigned long long* bmin, unsigned long long* bmax) {
+  const uint32_t j = blockIdx.x * RB + threadIdx.x;
+  if (j >= ns) return;
+  const double4 q = S[j];
+  const double c[3] = {q.x, q.y, q.z};
+  const uint32_t b = sblk[j];
+  for (int a = 0; a < D; a++) {
+    atomicMin(&bmin[(size_t)b * 3 + a], ord_of(c[a]));
+    atomicMax(&bmax[(size_t)b * 3 + a], ord_of(c[a]));
+  }
+}
+
+__device__ __forceinline__ double dbl_of(unsigned long long o) {
+  const unsigned long long u = (o >> 63) ? (o & 0x7FFFFFFFFFFFFFFFull) : ~o;
+  return __longlong_as_double((long long)u);
+}
+
+// sort key of a sample: its block, then its coordinate along the block
+// sample's widest axis (the median split of the partitioner's initial cut)
+__global__ void k_rb_axis_keys(const double4* S, const uint32_t* sblk, uint32_t ns, int D,
+                               int lbits, const unsigned long long* bmin,
+                               const unsigned long long* bmax, unsigned long long* keys,
+                               uint32_t* vals) {
+  const uint32_t j = blockIdx.x * RB + threadIdx.x;
+  if (j >= ns) return;
+  const uint32_t b = sblk[j];
+  int ax = 0;
+  double wmax = -1.0;
+  for (int a = 0; a < D; a++) {
+    const double w = dbl_of(bmax[(size_t)b * 3 + a]) - dbl_of(bmin[(size_t)b * 3 + a]);
+    if (w > wmax) { wmax = w; ax = a; }
+  }
+  const double4 q = S[j];
+  const double c = ax == 0 ? q.x : (ax == 1 ? q.y : q.z);
+  keys[j] = ((unsigned long long)b << (64 - lbits)) | (ord_of(c) >> lbits);
+  vals[j] = j;
+}
+
+// first cut: the lower half (floor) of every block's sample along its axis
+// is side 0; label = 2 * block + side
+__global__ void k_rb_first_side(const uint32_t* vals, const uint32_t* sblk, const uint32_t* off,
+                                uint32_t ns, uint32_t* label) {
+  const uint32_t q = blockIdx.x * RB + threadIdx.x;
+  if (q >= ns) return;
+  const uint32_t j = vals[q];
+  const uint32_t b = sblk[j];
+  const uint32_t m = off[b + 1] - off[b];
+  label[j] = 2 * b + ((q - off[b]) < m / 2 ? 0u : 1u);
 }
 
 __global__ void k_rb_grid_count(const double4* S, uint32_t m, Grid G, uint32_t* cnt,
@@ -236,6 +313,58 @@ __global__ void k_rb_border(const double4* P, const int32_t* rows, uint32_t m,
     if (f)
       for (int j = 0; j <= D; j++) vbflag[v[j]] = 1u;
     // hull facets of the child
+    for (int j = 0; j <= D; j++)
+      if (nbr[(size_t)i * (D + 1) + j] < 0)
+        for (int t = 0; t <= D; t++)
+          if (t != j) vbflag[v[t]] = 1u;
+    flag[i] = f ? 1 : 0;
+  }
+  const unsigned long long b = __ballot(f);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(nb, (unsigned long long)__popcll(b));
+}
+
+// border simplices of the children by the region test: the ball reaches
+// the sibling's Voronoi cells of the level's sample (a walk over the
+// sample's Delaunay graph from the vertices' nearest sample), or leaves the
+// child's kd box; hull facets of a child add their vertices.
+template <int D>
+__global__ __launch_bounds__(RB) void k_rb_border_region(
+    const double4* P, const int32_t* rows, uint32_t m, const uint32_t* tag, const int32_t* nbr,
+    Region R, const uint32_t* nearest, const double* cbox, uint8_t* flag, uint32_t* vbflag,
+    unsigned long long* nb) {
+  __shared__ uint32_t s_vis[VW_CAP * RB];
+  const uint32_t i = blockIdx.x * RB + threadIdx.x;
+  bool f = false;
+  if (i < m) {
+    uint32_t v[4] = {0, 0, 0, 0};
+    for (int j = 0; j <= D; j++) v[j] = (uint32_t)rows[(size_t)i * (D + 1) + j];
+    const uint32_t me = tag[i];
+    double ctr[3], r = 0.0;
+    if (!circumball<D>(P[v[0]], P[v[1]], P[v[2]], P[v[D == 3 ? 3 : 2]], ctr, &r)) {
+      f = true;
+    } else if (cbox) {
+      const double* b = cbox + (size_t)me * 6;
+      for (int k = 0; k < D; k++)
+        if (ctr[k] - r <= b[k] || ctr[k] + r >= b[3 + k]) f = true;
+    } else {
+      // the own sample nearest the centre among the vertices' samples
+      uint32_t t = nearest[v[0]];
+      double best = INFINITY;
+      const double cz = D == 3 ? ctr[2] : 0.0;
+      for (int j = 0; j <= D; j++) {
+        const uint32_t sj = nearest[v[j]];
+        const double4 q = R.S[sj];
+        const double dx = ctr[0] - q.x, dy = ctr[1] - q.y, dz = cz - q.z;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < best) { best = d2; t = sj; }
+      }
+      // a sample without Delaunay neighbours belongs to a block whose
+      // sample has no full-dimensional triangulation: no walk, flagged
+      f = R.goff[t + 1] == R.goff[t] ||
+          voronoi_walk_hit<D, RB>(R, me, ctr, r, t, s_vis + threadIdx.x);
+    }
+    if (f)
+      for (int j = 0; j <= D; j++) vbflag[v[j]] = 1u;
     for (int j = 0; j <= D; j++)
       if (nbr[(size_t)i * (D + 1) + j] < 0)
         for (int t = 0; t <= D; t++)
@@ -366,114 +495,6 @@ uint32_t rb_sample_size(uint32_t m, double rate, int D) {
   return (uint32_t)e;
 }
 
-// leaf index of every point by sample bisection
-int sample_bisect(const DevBuf& P, uint32_t n, int D, int levels, double rate, uint64_t seed,
-                  const double lo[3], const double hi[3], DevBuf& pid, hipStream_t st) {
-  DT_TRY(pid.alloc((size_t)n * 4));
-  DT_HIP(hipMemsetAsync(pid.p, 0, (size_t)n * 4, st));
-  DevBuf keys, vals, cnt;
-  DT_TRY(keys.alloc((size_t)n * 8));
-  DT_TRY(vals.alloc((size_t)n * 4));
-  std::vector<double4> hp;
-  for (int l = 0; l < levels; l++) {
-    const uint32_t nb = 1u << l;
-    DT_TRY(cnt.alloc((size_t)nb * 4));
-    DT_TRY(count_by(pid.as<uint32_t>(), n, nb, cnt.as<uint32_t>(), st));
-    std::vector<uint32_t> hc(nb);
-    DT_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)nb * 4, hipMemcpyDeviceToHost, st));
-    hipLaunchKernelGGL(k_rb_sample_keys, dim3(rblocks(n)), dim3(RB), 0, st, n,
-                       pid.as<uint32_t>(), seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(l + 1)),
-                       keys.as<unsigned long long>(), vals.as<uint32_t>());
-    DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), vals.as<uint32_t>(), n, 40 + l, st));
-    std::vector<uint32_t> order(n);
-    DT_HIP(hipMemcpyAsync(order.data(), vals.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
-    if (hp.empty()) {
-      hp.resize(n);
-      DT_HIP(hipMemcpyAsync(hp.data(), P.p, (size_t)n * sizeof(double4), hipMemcpyDeviceToHost,
-                            st));
-    }
-    DT_HIP(hipStreamSynchronize(st));
-    // samples of every block, split at the median of the widest axis
-    std::vector<double4> S;
-    std::vector<uint32_t> sblock;
-    std::vector<uint8_t> sside;
-    uint32_t seg = 0;
-    for (uint32_t b = 0; b < nb; b++) {
-      const uint32_t m = hc[b];
-      const uint32_t eta = m ? rb_sample_size(m, rate, D) : 0;
-      std::vector<uint32_t> smp(order.begin() + seg, order.begin() + seg + eta);
-      seg += m;
-      if (eta == 0) continue;
-      double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-      for (uint32_t s : smp) {
-        const double c[3] = {hp[s].x, hp[s].y, hp[s].z};
-        for (int a = 0; a < 3; a++) {
-          blo[a] = std::min(blo[a], c[a]);
-          bhi[a] = std::max(bhi[a], c[a]);
-        }
-      }
-      int ax = 0;
-      for (int a = 1; a < D; a++)
-        if (bhi[a] - blo[a] > bhi[ax] - blo[ax]) ax = a;
-      auto coord = [&](uint32_t s) { return ax == 0 ? hp[s].x : (ax == 1 ? hp[s].y : hp[s].z); };
-      std::sort(smp.begin(), smp.end(), [&](uint32_t a2, uint32_t b2) {
-        const double ca = coord(a2), cb = coord(b2);
-        return ca < cb || (ca == cb && a2 < b2);
-      });
-      for (uint32_t j = 0; j < eta; j++) {
-        S.push_back(hp[smp[j]]);
-        sblock.push_back(b);
-        sside.push_back(j < eta / 2 ? 0 : 1);
-      }
-    }
-    const uint32_t ns = (uint32_t)S.size();
-    DevBuf dS, dsb, dss, gcnt, gstart, gcur, gitems, gcell;
-    DT_TRY(dS.alloc((size_t)ns * sizeof(double4)));
-    DT_TRY(dsb.alloc((size_t)ns * 4));
-    DT_TRY(dss.alloc((size_t)ns));
-    DT_HIP(hipMemcpyAsync(dS.p, S.data(), (size_t)ns * sizeof(double4), hipMemcpyHostToDevice, st));
-    DT_HIP(hipMemcpyAsync(dsb.p, sblock.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
-    DT_HIP(hipMemcpyAsync(dss.p, sside.data(), (size_t)ns, hipMemcpyHostToDevice, st));
-    // grid of about ns/2 cells over the input box
-    Grid G;
-    {
-      double vol = 1.0;
-      int nd = 0;
-      for (int a = 0; a < D; a++)
-        if (hi[a] > lo[a]) { vol *= hi[a] - lo[a]; nd++; }
-      const double target = ns / 2.0 > 1.0 ? ns / 2.0 : 1.0;
-      double h = nd ? pow(vol / target, 1.0 / nd) : 1.0;
-      if (!(h > 0)) h = 1.0;
-      for (int a = 0; a < 3; a++) {
-        G.lo[a] = lo[a];
-        long g = a < D ? (long)floor((hi[a] - lo[a]) / h) + 1 : 1;
-        G.g[a] = (int)std::max(1L, std::min(g, 1024L));
-      }
-      G.h = h;
-    }
-    const uint32_t ncell = (uint32_t)G.g[0] * G.g[1] * G.g[2];
-    DT_TRY(gcnt.alloc((size_t)(ncell + 1) * 4));
-    DT_TRY(gstart.alloc((size_t)(ncell + 1) * 4));
-    DT_TRY(gcur.alloc((size_t)ncell * 4));
-    DT_TRY(gitems.alloc((size_t)ns * 4));
-    DT_TRY(gcell.alloc((size_t)ns * 4));
-    DT_HIP(hipMemsetAsync(gcnt.p, 0, (size_t)(ncell + 1) * 4, st));
-    DT_HIP(hipMemsetAsync(gcur.p, 0, (size_t)ncell * 4, st));
-    hipLaunchKernelGGL(k_rb_grid_count, dim3(rblocks(ns)), dim3(RB), 0, st, dS.as<double4>(), ns, G,
-                       gcnt.as<uint32_t>(), gcell.as<uint32_t>());
-    DT_TRY(exclusive_scan(gcnt.as<uint32_t>(), gstart.as<uint32_t>(), ncell + 1, st));
-    hipLaunchKernelGGL(k_rb_grid_fill, dim3(rblocks(ns)), dim3(RB), 0, st, ns,
-                       gcell.as<uint32_t>(), gstart.as<uint32_t>(), gcur.as<uint32_t>(),
-                       gitems.as<uint32_t>());
-    hipLaunchKernelGGL(k_rb_assign, dim3(rblocks(n)), dim3(RB), 0, st, P.as<double4>(), n,
-                       dS.as<double4>(), dsb.as<uint32_t>(), dss.as<uint8_t>(),
-                       gstart.as<uint32_t>(), gitems.as<uint32_t>(), G, pid.as<uint32_t>());
-    DT_HIP(hipGetLastError());
-    DT_HIP(hipStreamSynchronize(st));
-  }
-  return DT_OK;
-}
-
 // batch of point sets from per-set point lists: points gathered by index,
 // sets in order, spatial order inside each set
 int make_job(const DevBuf& P, const uint32_t* idx, uint32_t m, const uint32_t* set_of_item,
@@ -502,6 +523,157 @@ int make_job(const DevBuf& P, const uint32_t* idx, uint32_t m, const uint32_t* s
   job.set_off = off.as<uint32_t>();
   job.fp32 = fp32;
   job.tune(o);
+  return DT_OK;
+}
+
+// The regions of one level of the sample bisection, kept for its merge:
+// the level's samples (a batched job, grouped by block), the label 2 *
+// block + side of every sample, the samples' Delaunay graph, and the
+// nearest sample (of its own block) of every point.
+struct LevelRegion {
+  DevBuf pts, pset, off, label, goff, gadj, gw, nearest;
+  uint32_t ns = 0;
+};
+
+// Leaf index of every point by sample bisection (Algorithm 2 with k = 2 in
+// every block of every level).
+int sample_bisect(const DevBuf& P, uint32_t n, int D, int levels, double rate,
+                  const dt_options& o, const double lo[3], const double hi[3], Ctx& cx,
+                  dt_stats& S, DevBuf& pid, std::vector<LevelRegion>& lv, hipStream_t st) {
+  const bool fp32 = o.precision == DT_PREC_FP32;
+  double dstar = 0.0;
+  for (int a = 0; a < 3; a++) dstar += (hi[a] - lo[a]) * (hi[a] - lo[a]);
+  dstar = sqrt(dstar);
+  DT_TRY(pid.alloc((size_t)n * 4));
+  DT_HIP(hipMemsetAsync(pid.p, 0, (size_t)n * 4, st));
+  DevBuf keys, vals;
+  DT_TRY(keys.alloc((size_t)n * 8));
+  DT_TRY(vals.alloc((size_t)n * 4));
+  lv.clear();
+  lv.resize(levels);
+  for (int l = 0; l < levels; l++) {
+    LevelRegion& L = lv[l];
+    const uint32_t nb = 1u << l;
+    // points per block, then every block's points by random key
+    DevBuf cnt;
+    DT_TRY(cnt.alloc((size_t)nb * 4));
+    DT_TRY(count_by(pid.as<uint32_t>(), n, nb, cnt.as<uint32_t>(), st));
+    std::vector<uint32_t> hc(nb);
+    DT_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)nb * 4, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_rb_sample_keys, dim3(rblocks(n)), dim3(RB), 0, st, n,
+                       pid.as<uint32_t>(), o.seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(l + 1)),
+                       keys.as<unsigned long long>(), vals.as<uint32_t>());
+    DT_TRY(radix_sort_pairs(keys.as<unsigned long long>(), vals.as<uint32_t>(), n, 40 + l, st));
+    DT_HIP(hipStreamSynchronize(st));
+    // sample sizes eta(|block|) and their places
+    std::vector<uint32_t> seg(nb + 1, 0), soff(nb + 1, 0);
+    std::vector<int> lmax(2 * nb);
+    for (uint32_t b = 0; b < nb; b++) {
+      const uint32_t eta = hc[b] ? rb_sample_size(hc[b], rate, D) : 0;
+      seg[b + 1] = seg[b] + hc[b];
+      soff[b + 1] = soff[b] + eta;
+      const double half = ceil(eta / 2.0);
+      lmax[2 * b] = lmax[2 * b + 1] = (int)floor((1.0 + o.eps) * half + 1e-9);
+    }
+    const uint32_t ns = soff[nb];
+    L.ns = ns;
+    DevBuf dseg, dsoff, sidx, sblk, dlmax;
+    DT_TRY(dseg.alloc((size_t)(nb + 1) * 4));
+    DT_TRY(dsoff.alloc((size_t)(nb + 1) * 4));
+    DT_TRY(sidx.alloc((size_t)(ns ? ns : 1) * 4));
+    DT_TRY(sblk.alloc((size_t)(ns ? ns : 1) * 4));
+    DT_TRY(dlmax.alloc((size_t)2 * nb * 4));
+    DT_HIP(hipMemcpyAsync(dseg.p, seg.data(), (size_t)(nb + 1) * 4, hipMemcpyHostToDevice, st));
+    DT_HIP(hipMemcpyAsync(dsoff.p, soff.data(), (size_t)(nb + 1) * 4, hipMemcpyHostToDevice, st));
+    DT_HIP(hipMemcpyAsync(dlmax.p, lmax.data(), (size_t)2 * nb * 4, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_rb_take, dim3(rblocks(ns)), dim3(RB), 0, st, vals.as<uint32_t>(),
+                       dseg.as<uint32_t>(), dsoff.as<uint32_t>(), nb, ns, sidx.as<uint32_t>(),
+                       sblk.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    // the samples of all blocks triangulated in one batched run
+    LocalJob sjob;
+    DT_TRY(make_job(P, sidx.as<uint32_t>(), ns, sblk.as<uint32_t>(), nb, D, lo, hi, fp32, o, L.pts,
+                    L.pset, L.off, sjob, st));
+    CellPool spool;
+    {
+      K4Stats ks;
+      int s = k4_run(sjob, spool, cx.dc(), cx.hctr, st, ks);
+      for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) S.pred[i][j] += (int64_t)ks.pred[i][j];
+      S.rounds += ks.rounds;
+      S.large_cavities += ks.giant_rounds;
+      if (s != DT_OK) { S.fail = cx.hctr->flags; return s; }
+    }
+    S.eta += ns;
+    // every block's sample graph cut in two: a median split along the
+    // widest axis of the block's sample, refined by label propagation
+    DT_TRY(sample_graph(L.pts.as<double4>(), ns, D, spool, o.weight, dstar, L.goff, L.gadj, L.gw,
+                        st));
+    spool = CellPool();
+    DevBuf bmin, bmax, ak, av;
+    DT_TRY(bmin.alloc((size_t)nb * 3 * 8));
+    DT_TRY(bmax.alloc((size_t)nb * 3 * 8));
+    DT_TRY(ak.alloc((size_t)(ns ? ns : 1) * 8));
+    DT_TRY(av.alloc((size_t)(ns ? ns : 1) * 4));
+    DT_TRY(L.label.alloc((size_t)(ns ? ns : 1) * 4));
+    DT_HIP(hipMemsetAsync(bmin.p, 0xFF, (size_t)nb * 3 * 8, st));
+    DT_HIP(hipMemsetAsync(bmax.p, 0, (size_t)nb * 3 * 8, st));
+    hipLaunchKernelGGL(k_rb_sbox, dim3(rblocks(ns)), dim3(RB), 0, st, L.pts.as<double4>(),
+                       L.pset.as<uint32_t>(), ns, D, bmin.as<unsigned long long>(),
+                       bmax.as<unsigned long long>());
+    hipLaunchKernelGGL(k_rb_axis_keys, dim3(rblocks(ns)), dim3(RB), 0, st, L.pts.as<double4>(),
+                       L.pset.as<uint32_t>(), ns, D, l ? l : 1, bmin.as<unsigned long long>(),
+                       bmax.as<unsigned long long>(), ak.as<unsigned long long>(),
+                       av.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    DT_TRY(radix_sort_pairs(ak.as<unsigned long long>(), av.as<uint32_t>(), ns, 64, st));
+    hipLaunchKernelGGL(k_rb_first_side, dim3(rblocks(ns)), dim3(RB), 0, st, av.as<uint32_t>(),
+                       L.pset.as<uint32_t>(), L.off.as<uint32_t>(), ns, L.label.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    DT_TRY(refine_partition(ns, L.goff.as<uint32_t>(), L.gadj.as<uint32_t>(), L.gw.as<double>(),
+                            L.label.as<uint32_t>(), 2 * nb, 0, dlmax.as<int>(), o.refine_iters,
+                            st));
+    // every point takes the side of its nearest sample of its own block
+    // (grid of about ns/2 cells over the input box)
+    Grid G;
+    {
+      double vol = 1.0;
+      int nd = 0;
+      for (int a = 0; a < D; a++)
+        if (hi[a] > lo[a]) { vol *= hi[a] - lo[a]; nd++; }
+      const double target = ns / 2.0 > 1.0 ? ns / 2.0 : 1.0;
+      double h = nd ? pow(vol / target, 1.0 / nd) : 1.0;
+      if (!(h > 0)) h = 1.0;
+      for (int a = 0; a < 3; a++) {
+        G.lo[a] = lo[a];
+        long g = a < D ? (long)floor((hi[a] - lo[a]) / h) + 1 : 1;
+        G.g[a] = (int)std::max(1L, std::min(g, 1024L));
+      }
+      G.h = h;
+    }
+    const uint32_t ncell = (uint32_t)G.g[0] * G.g[1] * G.g[2];
+    DevBuf gcnt, gstart, gcur, gitems, gcell;
+    DT_TRY(gcnt.alloc((size_t)(ncell + 1) * 4));
+    DT_TRY(gstart.alloc((size_t)(ncell + 1) * 4));
+    DT_TRY(gcur.alloc((size_t)ncell * 4));
+    DT_TRY(gitems.alloc((size_t)(ns ? ns : 1) * 4));
+    DT_TRY(gcell.alloc((size_t)(ns ? ns : 1) * 4));
+    DT_HIP(hipMemsetAsync(gcnt.p, 0, (size_t)(ncell + 1) * 4, st));
+    DT_HIP(hipMemsetAsync(gcur.p, 0, (size_t)ncell * 4, st));
+    hipLaunchKernelGGL(k_rb_grid_count, dim3(rblocks(ns)), dim3(RB), 0, st, L.pts.as<double4>(),
+                       ns, G, gcnt.as<uint32_t>(), gcell.as<uint32_t>());
+    DT_TRY(exclusive_scan(gcnt.as<uint32_t>(), gstart.as<uint32_t>(), ncell + 1, st));
+    hipLaunchKernelGGL(k_rb_grid_fill, dim3(rblocks(ns)), dim3(RB), 0, st, ns,
+                       gcell.as<uint32_t>(), gstart.as<uint32_t>(), gcur.as<uint32_t>(),
+                       gitems.as<uint32_t>());
+    DT_TRY(L.nearest.alloc((size_t)n * 4));
+    hipLaunchKernelGGL(k_rb_assign, dim3(rblocks(n)), dim3(RB), 0, st, P.as<double4>(), n,
+                       L.pts.as<double4>(), L.pset.as<uint32_t>(), L.label.as<uint32_t>(),
+                       gstart.as<uint32_t>(), gitems.as<uint32_t>(), G, pid.as<uint32_t>(),
+                       L.nearest.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    DT_HIP(hipStreamSynchronize(st));
+  }
   return DT_OK;
 }
 
@@ -542,10 +714,16 @@ int run_recursive(const double* points, int64_t n64, int D, int k, double rate,
 
   // ---- division into k leaves
   DevBuf leaf, boxes;
+  std::vector<LevelRegion> lv;
+  std::vector<double> hbox;
+  const bool region = o.border != DT_BORDER_GRID;
   if (divide == DT_DIVIDE_KD) {
     DT_TRY(kd_divide(P.as<double4>(), n, D, (uint32_t)k, leaf, boxes, st));
+    hbox.resize((size_t)k * 6);
+    DT_HIP(hipMemcpyAsync(hbox.data(), boxes.p, (size_t)k * 6 * 8, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
   } else {
-    DT_TRY(sample_bisect(P, n, D, levels, rate, o.seed, lo, hi, leaf, st));
+    DT_TRY(sample_bisect(P, n, D, levels, rate, o, lo, hi, cx, S, leaf, lv, st));
   }
   double t2 = now_ms();
   S.stage_ms[DT_STAGE_ASSIGN] = t2 - t1;
@@ -571,6 +749,7 @@ int run_recursive(const double* points, int64_t n64, int D, int k, double rate,
     for (int i = 0; i < 4; i++)
       for (int j = 0; j < 4; j++) S.pred[i][j] += (int64_t)ks.pred[i][j];
     S.rounds += ks.rounds;
+    S.large_cavities += ks.giant_rounds;
     if (s != DT_OK) { S.fail = cx.hctr->flags; return s; }
   }
   // rows grouped by leaf
@@ -620,26 +799,68 @@ int run_recursive(const double* points, int64_t n64, int D, int k, double rate,
     DT_TRY(tag.alloc((size_t)(m ? m : 1) * 4));
     hipLaunchKernelGGL(k_rb_row_tags, dim3(rblocks(m)), dim3(RB), 0, st, off32.as<uint32_t>(),
                        nchild, m, tag.as<uint32_t>());
-    DT_TRY(owner.alloc(gtotal * 4));
-    DT_HIP(hipMemsetAsync(owner.p, 0xFF, gtotal * 4, st));
-    hipLaunchKernelGGL(k_rb_occupancy, dim3(rblocks(n)), dim3(RB), 0, st, P.as<double4>(), n,
-                       leaf.as<uint32_t>(), cshift, G, owner.as<uint32_t>());
+    if (!region) {
+      DT_TRY(owner.alloc(gtotal * 4));
+      DT_HIP(hipMemsetAsync(owner.p, 0xFF, gtotal * 4, st));
+      hipLaunchKernelGGL(k_rb_occupancy, dim3(rblocks(n)), dim3(RB), 0, st, P.as<double4>(), n,
+                         leaf.as<uint32_t>(), cshift, G, owner.as<uint32_t>());
+    }
     DT_TRY(flag.alloc((size_t)(m ? m : 1)));
     DT_TRY(vbflag.alloc((size_t)n * 4));
     DT_TRY(nb.alloc(8));
     DT_HIP(hipMemsetAsync(vbflag.p, 0, (size_t)n * 4, st));
     DT_HIP(hipMemsetAsync(nb.p, 0, 8, st));
+    DevBuf cbox;
+    Region R;
+    if (region && divide == DT_DIVIDE_KD) {
+      // the box of every child: the union of its leaves' boxes
+      std::vector<double> cb((size_t)nchild * 6);
+      for (uint32_t c = 0; c < nchild; c++) {
+        double* b = cb.data() + (size_t)c * 6;
+        for (int a = 0; a < 3; a++) {
+          b[a] = INFINITY;
+          b[3 + a] = -INFINITY;
+        }
+        for (uint32_t f = c << cshift; f < (c + 1) << cshift; f++)
+          for (int a = 0; a < 3; a++) {
+            b[a] = std::min(b[a], hbox[(size_t)f * 6 + a]);
+            b[3 + a] = std::max(b[3 + a], hbox[(size_t)f * 6 + 3 + a]);
+          }
+      }
+      DT_TRY(cbox.alloc(cb.size() * 8));
+      DT_HIP(hipMemcpyAsync(cbox.p, cb.data(), cb.size() * 8, hipMemcpyHostToDevice, st));
+    } else if (region) {
+      R.kind = BORDER_VORONOI;
+      R.S = lv[l].pts.as<double4>();
+      R.part = lv[l].label.as<uint32_t>();
+      R.goff = lv[l].goff.as<uint32_t>();
+      R.gadj = lv[l].gadj.as<uint32_t>();
+    }
     DT_PROF_BEGIN(DT_KERN_BORDER, st);
-    if (D == 2)
+    if (region) {
+      const uint32_t* near = divide == DT_DIVIDE_KD ? nullptr : lv[l].nearest.as<uint32_t>();
+      const double* cbp = divide == DT_DIVIDE_KD ? cbox.as<double>() : nullptr;
+      if (D == 2)
+        hipLaunchKernelGGL(k_rb_border_region<2>, dim3(rblocks(m)), dim3(RB), 0, st,
+                           P.as<double4>(), cur.rows.as<int32_t>(), m, tag.as<uint32_t>(),
+                           nbr.as<int32_t>(), R, near, cbp, flag.as<uint8_t>(),
+                           vbflag.as<uint32_t>(), nb.as<unsigned long long>());
+      else
+        hipLaunchKernelGGL(k_rb_border_region<3>, dim3(rblocks(m)), dim3(RB), 0, st,
+                           P.as<double4>(), cur.rows.as<int32_t>(), m, tag.as<uint32_t>(),
+                           nbr.as<int32_t>(), R, near, cbp, flag.as<uint8_t>(),
+                           vbflag.as<uint32_t>(), nb.as<unsigned long long>());
+    } else if (D == 2) {
       hipLaunchKernelGGL(k_rb_border<2>, dim3(rblocks(m)), dim3(RB), 0, st, P.as<double4>(),
                          cur.rows.as<int32_t>(), m, tag.as<uint32_t>(), nbr.as<int32_t>(), G,
                          owner.as<uint32_t>(), flag.as<uint8_t>(), vbflag.as<uint32_t>(),
                          nb.as<unsigned long long>());
-    else
+    } else {
       hipLaunchKernelGGL(k_rb_border<3>, dim3(rblocks(m)), dim3(RB), 0, st, P.as<double4>(),
                          cur.rows.as<int32_t>(), m, tag.as<uint32_t>(), nbr.as<int32_t>(), G,
                          owner.as<uint32_t>(), flag.as<uint8_t>(), vbflag.as<uint32_t>(),
                          nb.as<unsigned long long>());
+    }
     DT_PROF_END(st);
     DT_HIP(hipGetLastError());
     unsigned long long hnb = 0;
@@ -677,6 +898,7 @@ int run_recursive(const double* points, int64_t n64, int D, int k, double rate,
       for (int i = 0; i < 4; i++)
         for (int j = 0; j < 4; j++) S.pred[i][j] += (int64_t)ks.pred[i][j];
       S.rounds += ks.rounds;
+      S.large_cavities += ks.giant_rounds;
       if (s != DT_OK) { S.fail = cx.hctr->flags; return s; }
     }
     double tc = now_ms();
@@ -772,12 +994,18 @@ int run_recursive(const double* points, int64_t n64, int D, int k, double rate,
   S.stage_ms[DT_STAGE_BORDER_DT] = tdt_total;
   double t4 = now_ms();
   S.stage_ms[DT_STAGE_MERGE] = t4 - t3 - tb_total - tdt_total;
+  if (o.keep_stages) {
+    r->stage[DT_ARR_PID].resize((size_t)n * 4);
+    DT_HIP(hipMemcpyAsync(r->stage[DT_ARR_PID].data(), leaf.p, (size_t)n * 4,
+                          hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+  }
   r->rows = std::move(cur.rows);
   r->m = cur.m;
   r->set_offsets = {0, r->m};
   S.num_simplices = r->m;
   S.stage_ms[DT_STAGE_TOTAL] = now_ms() - t0;
-  S.o_dt = ((double)n + S.border_vertices) / (double)n;
+  S.o_dt = ((double)n + S.eta + S.border_vertices) / (double)n;
   return DT_OK;
 }
 

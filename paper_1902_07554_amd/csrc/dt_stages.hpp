@@ -15,6 +15,17 @@ int gather_points(const double4* P, const uint32_t* idx, uint32_t m, double4* ou
 // and in order, so each keeps its range).  Labels travel with the points.
 int spatial_sort(DevBuf& pts, uint32_t n, int D, const double lo[3], const double hi[3],
                  const uint32_t* prefix, int prefix_bits, hipStream_t st);
+// The Delaunay graph of a sample (Algorithm 2) from its triangulation (any
+// batch: edges join vertices of one set): CSR offsets goff[eta+1], sorted
+// adjacency lists gadj, and the weight of every adjacency entry gw (Table
+// "weights", d* the bounding-box diagonal of the input).
+int sample_graph(const double4* S, uint32_t eta, int D, const CellPool& pool, int weight,
+                 double dstar, DevBuf& goff, DevBuf& gadj, DevBuf& gw, hipStream_t st);
+// Label propagation on that graph: part[v] in [0, k); a move never takes a
+// block above its bound (lmax_of[b] if given, else lmax).
+int refine_partition(uint32_t eta, const uint32_t* goff, const uint32_t* gadj, const double* gw,
+                     uint32_t* part, uint32_t k, int lmax, const int* lmax_of, int iters,
+                     hipStream_t st);
 // goff/gadj receive the sample's Delaunay graph (CSR, sorted lists) and
 // gw the weight of every adjacency entry.
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,

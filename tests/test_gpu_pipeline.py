@@ -253,17 +253,33 @@ def test_auto_divide(dtlib, dist, want):
     assert np.array_equal(res.rows(), oracle.delaunay(p))
 
 
-@pytest.mark.parametrize("dim,dist,n,k,divide", [
-    (2, "uniform", 10_000, 4, "kd"), (2, "normal", 10_000, 8, "sample"),
-    (3, "bubbles", 20_000, 8, "kd"), (3, "bubbles", 20_000, 16, "sample"),
-    (3, "uniform", 20_000, 2, "sample")])
-def test_recursive_bisection(dtlib, dim, dist, n, k, divide):
-    """Section "Recursive Bisection": log2 k levels of 2-way division and
-    k-1 merges give DT(P) as well."""
+@pytest.mark.parametrize("dim,dist,n,k,divide,border", [
+    (2, "uniform", 10_000, 4, "kd", "region"), (2, "normal", 10_000, 8, "sample", "region"),
+    (3, "bubbles", 20_000, 8, "kd", "region"), (3, "bubbles", 20_000, 16, "sample", "region"),
+    (3, "uniform", 20_000, 2, "sample", "region"), (3, "bubbles", 20_000, 16, "sample", "grid"),
+    (3, "uniform", 20_000, 8, "kd", "grid"), (2, "uniform", 12_000, 32, "sample", "region")])
+def test_recursive_bisection(dtlib, dim, dist, n, k, divide, border):
+    """Section "Recursive Bisection": log2 k levels of 2-way division (kd:
+    cyclic median split; sample: per block a new sample, its Delaunay
+    graph cut in two, nearest-sample assignment) and k-1 merges (region or
+    grid test) give DT(P) as well; every level halves every block."""
     p = inputs.make(dist, n, dim, seed=11)
-    print(f"[pipeline] recursive {dim}d {dist} k={k} {divide}", flush=True)
-    res = dtlib.triangulate(p, k=k, sample_rate=0.02, divide=divide, recursive=1, sort_output=1)
+    print(f"[pipeline] recursive {dim}d {dist} k={k} {divide} {border}", flush=True)
+    res = dtlib.triangulate(p, k=k, sample_rate=0.02, divide=divide, recursive=1, sort_output=1,
+                            border=border, keep_stages=1)
     assert np.array_equal(res.rows(), oracle.delaunay(p))
     st = res.stats()
     assert st["num_simplices"] == len(res.rows())
     assert st["border_vertices"] > 0
+    leaf = res.stage("pid").astype(np.int64)
+    assert leaf.min() >= 0 and leaf.max() < k
+    if divide == "kd":
+        assert np.array_equal(leaf, oracle.kd_divide(p, k))
+    else:
+        # the samples of all levels, and a split of every block at every level
+        levels = int(np.log2(k))
+        assert st["eta"] >= oracle.sample_size(n, 0.02, dim) + (levels - 1)
+        for l in range(1, levels + 1):
+            blocks = np.bincount(leaf >> (levels - l), minlength=1 << l)
+            assert (blocks > 0).all(), (l, blocks)
+        assert st["o_dt"] == pytest.approx((n + st["eta"] + st["border_vertices"]) / n)
