@@ -310,7 +310,8 @@ def bench_serve(args) -> dict:
     """Serving pattern: Poisson stream of 3D jobs (mean rate --serve-rate per
     second over --serve-seconds), n log-uniform in [1e3, 1e6], half uniform
     half bubbles; k = max(1, n / 16384) rounded to a power of two; HBM
-    budget 64 GiB.  Latency = arrival to result ready."""
+    budget --serve-budget-gib (192 GiB of the 288 by default).  Latency =
+    arrival to result ready."""
     import math
     import threading
     import numpy as np
@@ -320,7 +321,7 @@ def bench_serve(args) -> dict:
     data = [inputs.make(kind, n, 3, seed=js) for _, n, kind, js in jobs]
     ks = [1 << max(0, round(math.log2(max(1.0, n / 16384)))) for _, n, _, _ in jobs]
     torch.cuda.synchronize()
-    srv = binding.Server(64 << 30)
+    srv = binding.Server(int(args.serve_budget_gib) << 30)
     tickets = [None] * len(jobs)
     t0 = time.perf_counter()
 
@@ -352,7 +353,7 @@ def bench_serve(args) -> dict:
         "config": {"workload": "serve-3d-poisson", "rate_per_s": args.serve_rate,
                    "seconds": args.serve_seconds, "jobs": len(jobs), "points": total,
                    "n": "log-uniform [1e3, 1e6]", "kinds": "uniform / bubbles",
-                   "hbm_budget_GiB": 64, "offered_Mpoints_per_s":
+                   "hbm_budget_GiB": args.serve_budget_gib, "offered_Mpoints_per_s":
                        round(total / args.serve_seconds / 1e6, 3)},
         "p50_ms": round(float(np.percentile(lat, 50)), 2),
         "p99_ms": round(float(np.percentile(lat, 99)), 2),
@@ -419,6 +420,8 @@ def main() -> int:
                     help="dt: the headline triangulation; batch / serve: the patterns")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-budget-gib", type=int, default=192,
+                    help="HBM budget of the server (GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "

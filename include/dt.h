@@ -344,7 +344,7 @@ int dt_batch_autotune(const double* points, const int64_t* offsets, int64_t num_
 
 /*
  * Serving (continuous batching; the paper's method applied to a stream of
- * independent requests).  A server owns a device-memory budget and four
+ * independent requests).  A server owns a device-memory budget and two
  * worker threads, each with its own stream.  A job's points are copied to
  * device memory at submission and stay there until the job is done (the
  * queue lives on the device; these copies are outside the budget).  Jobs
@@ -352,7 +352,7 @@ int dt_batch_autotune(const double* points, const int64_t* offsets, int64_t num_
  * budget (a job alone may use the whole budget).  A worker takes the
  * admitted jobs that have not started: consecutive jobs of one dimension
  * with at most 2 Mi points each run together as one batched run of
- * independent sets (as dt_batch_triangulate, up to 8 Mi points; the k of
+ * independent sets (as dt_batch_triangulate, up to 32 Mi points; the k of
  * such a job is not used, since the result does not depend on it), a
  * larger job runs alone with its k-way divide-and-conquer; the workers'
  * runs overlap on the device.  Each job's result (rows labelled by row index, sorted

@@ -3,7 +3,7 @@
 //
 // A job's points are copied to device memory when it is submitted and stay
 // there until it finishes.  A job is admitted (FIFO) when its estimated
-// footprint fits the remaining budget.  Four worker threads, each with its
+// footprint fits the remaining budget.  Two worker threads, each with its
 // own HIP stream, repeatedly take the admitted jobs that have not started:
 // a run of consecutive jobs of at most DIRECT_MAX points (whatever their k)
 // is triangulated together as one batched run of independent sets (all of
@@ -15,6 +15,8 @@
 // dt_triangulate returns for it alone, since the triangulation depends only
 // on the point set.  If a batched run fails, its jobs run again one by one
 // so that each gets its own status.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -70,13 +72,20 @@ size_t footprint_of(int64_t n, int D, int k) {
   return (size_t)n * per + (64u << 20);
 }
 
-constexpr int64_t MAX_BATCH_POINTS = 8 << 20;
+// Up to 32 Mi points per batched run: a batch's rounds are about those of
+// its largest set, so larger batches amortise them (64 Mi no longer fits
+// the device with its cell pool).
+constexpr int64_t MAX_BATCH_POINTS = 32 << 20;
 // Jobs up to this size join batched runs of independent sets: one set of a
 // batch costs far less than a divide-and-conquer run of its own, whose
 // rounds are latency-bound (the result is the same either way).
 constexpr int64_t DIRECT_MAX = 1 << 21;
-// One worker per hardware queue the runtime gives a process by default.
-constexpr int NUM_WORKERS = 4;
+// Two workers: a batch can start while another runs.  Measured on the
+// Poisson stream of 3D jobs (200 jobs/s, n log-uniform in [1e3, 1e6]): two
+// workers with 32 Mi-point batches served 16.3 Mpoints/s, four workers 10.7
+// (the rounds of four batches contend for the device) and four workers with
+// 8 Mi-point batches 9.2.
+constexpr int NUM_WORKERS = 2;
 
 }  // namespace
 
@@ -93,6 +102,7 @@ struct dt_server {
   bool stop = false;
   uint64_t next = 1;
   int device = 0;
+  bool trace = false;   // DT_DEBUG set: one line per batch on stderr
 
   // admit from the front while the budget allows (called with mu held)
   void admit() {
@@ -207,6 +217,7 @@ struct dt_server {
           b.push_back(j);
         }
       }
+      const double tb0 = mono_s();
       if (!b.empty()) {
         try {
           run_batch_of(b, st);
@@ -214,6 +225,15 @@ struct dt_server {
           for (Job* j : b)
             if (!j->res && j->status == DT_OK) j->status = DT_E_NOMEM;
         }
+      }
+      if (trace && !b.empty()) {
+        int64_t pts = 0, mx = 0;
+        for (Job* j : b) {
+          pts += j->n;
+          mx = j->n > mx ? j->n : mx;
+        }
+        fprintf(stderr, "[srv] t %.3f batch %zu jobs %lld points (largest %lld) %.1f ms\n",
+                mono_s() - t0, b.size(), (long long)pts, (long long)mx, (mono_s() - tb0) * 1e3);
       }
       {
         std::lock_guard<std::mutex> lk(mu);
@@ -244,6 +264,7 @@ extern "C" int dt_server_create(size_t hbm_budget_bytes, const dt_options* opt, 
   s->opt.keep_stages = 0;
   s->budget = hbm_budget_bytes;
   s->t0 = mono_s();
+  s->trace = getenv("DT_DEBUG") != nullptr;
   DT_HIP_DEL(hipGetDevice(&s->device), s);
   // keep memory freed by the workers in the device's stream-ordered pool
   hipMemPool_t pool;
