@@ -335,15 +335,30 @@ def bench_serve(args) -> dict:
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
+    # jobs whose result is also computed alone afterwards (identity check)
+    rng = np.random.default_rng(7)
+    small = [i for i, (_, n, _, _) in enumerate(jobs) if n <= 200_000]
+    check = set(rng.choice(small, size=min(8, len(small)), replace=False).tolist()) if small else set()
+    kept = {}
     lat, total = [], 0
     for i, t in enumerate(tickets):
         r = srv.wait(t)
         total += jobs[i][1]
         tt = srv.times(t)
         lat.append(tt[2] - tt[0])
+        if i in check:
+            kept[i] = r.rows()
         del r
     wall = time.perf_counter() - t0
     srv.close()
+
+    def canon(rows):
+        rows = np.sort(rows.astype(np.int64), axis=1)
+        return rows[np.lexsort(rows.T[::-1])]
+
+    identical = all(np.array_equal(canon(kept[i]),
+                                   canon(binding.triangulate(data[i], k=ks[i]).rows()))
+                    for i in sorted(kept))
     lat = np.array(lat) * 1000.0
     return {
         "metric": "Mpoints/s and p50/p99 latency of a served Poisson stream of 3D DT jobs",
@@ -358,6 +373,7 @@ def bench_serve(args) -> dict:
         "p50_ms": round(float(np.percentile(lat, 50)), 2),
         "p99_ms": round(float(np.percentile(lat, 99)), 2),
         "max_ms": round(float(lat.max()), 2),
+        "alone_vs_mix": {"jobs_checked": len(kept), "identical": bool(identical)},
     }
 
 
@@ -519,7 +535,7 @@ def main() -> int:
     if not args.no_serve:
         v = bench_serve(args)
         line["serve"] = {k2: v[k2] for k2 in ("value", "unit", "p50_ms", "p99_ms", "max_ms",
-                                               "ms_per_step", "config")}
+                                               "ms_per_step", "config", "alone_vs_mix")}
     print(json.dumps(line), flush=True)
     return 0
 
