@@ -226,7 +226,7 @@ __device__ bool bbox_hit(const Region& R, uint32_t me, const double* ctr, double
 // clearance above 2 r holds no point of another block.
 template <int D>
 __global__ void k_point_margin(const double4* pts, uint32_t n, const uint32_t* nearest,
-                               Region R, double* margin) {
+                               Region R, double* margin, uint32_t* near_loc) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double4 q = pts[i];
@@ -264,7 +264,11 @@ __global__ void k_point_margin(const double4* pts, uint32_t n, const uint32_t* n
           f = fmin(f, d);
         }
       }
-  margin[id] = f;
+  // by the point's index in the job (cells' vertices index the job's
+  // points, which are in spatial order: the border test's loads of
+  // neighbouring vertices share cache lines)
+  margin[i] = f;
+  near_loc[i] = t;
 }
 
 constexpr uint32_t NB_STRIPES = 64;   // copies of the border-simplex counter
@@ -294,9 +298,9 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
         flag = true;
       } else if (R.kind == BORDER_VORONOI && R.margin) {
         // clearance of the vertices first (every vertex lies on the sphere)
-        double m = R.margin[key_of(P, v[0])];
+        double m = R.margin[v[0]];
 #pragma unroll
-        for (int i = 1; i <= D; i++) m = fmax(m, R.margin[key_of(P, v[i])]);
+        for (int i = 1; i <= D; i++) m = fmax(m, R.margin[v[i]]);
         if (!(m > 2.0 * r)) {
           // the own sample nearest the centre among the vertices' samples
           uint32_t t = 0xFFFFFFFFu;
@@ -304,7 +308,7 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
           const double cz = D == 3 ? ctr[2] : 0.0;
 #pragma unroll
           for (int i = 0; i <= D; i++) {
-            const uint32_t s = R.nearest[key_of(P, v[i])];
+            const uint32_t s = R.near_loc[v[i]];
             const double4 q = R.S[s];
             const double dx = ctr[0] - q.x, dy = ctr[1] - q.y, dz = cz - q.z;
             const double d2 = (dx * dx + dy * dy) + dz * dz;
@@ -394,7 +398,7 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
   uint64_t total = 1;
   const BGrid G = make_bgrid(lo, hi, D, cells_target, &total);
   const bool grid = reg.kind == BORDER_GRID;
-  DevBuf owner, vbflag, nb, margin;
+  DevBuf owner, vbflag, nb, margin, near_loc;
   DT_TRY(owner.alloc(grid ? total * 4 : 16));
   DT_TRY(vbflag.alloc((size_t)n * 4));
   DT_TRY(out.cflag.alloc((size_t)pool.ncells + 1));
@@ -436,14 +440,18 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
   }
   DT_PROF_BEGIN(DT_KERN_BORDER, st);
   if (reg.kind == BORDER_VORONOI && reg.nearest && job.npts) {
-    DT_TRY(margin.alloc((size_t)n * sizeof(double)));
+    DT_TRY(margin.alloc((size_t)job.npts * sizeof(double)));
+    DT_TRY(near_loc.alloc((size_t)job.npts * sizeof(uint32_t)));
     if (D == 2)
       hipLaunchKernelGGL(k_point_margin<2>, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
-                         job.npts, reg.nearest, reg, margin.as<double>());
+                         job.npts, reg.nearest, reg, margin.as<double>(),
+                         near_loc.as<uint32_t>());
     else
       hipLaunchKernelGGL(k_point_margin<3>, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
-                         job.npts, reg.nearest, reg, margin.as<double>());
+                         job.npts, reg.nearest, reg, margin.as<double>(),
+                         near_loc.as<uint32_t>());
     R.margin = margin.as<double>();
+    R.near_loc = near_loc.as<uint32_t>();
   }
   if (D == 2)
     hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,

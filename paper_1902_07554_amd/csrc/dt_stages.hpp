@@ -68,7 +68,8 @@ struct Region {
   Grid G{};
   const double* boxes = nullptr;   // k x 6 (boxes)
   const uint32_t* nearest = nullptr;  // nearest sample of every point, by id (Voronoi)
-  const double* margin = nullptr;     // filled by border_detect (Voronoi)
+  const double* margin = nullptr;     // filled by border_detect (Voronoi), by job point index
+  const uint32_t* near_loc = nullptr; // nearest sample of every job point (Voronoi), by job index
   const uint32_t* goff = nullptr;     // Delaunay graph of the sample (Voronoi)
   const uint32_t* gadj = nullptr;
   // filled by border_detect: bounding boxes of the partitions (bbox), and
