@@ -46,7 +46,7 @@ __global__ void k_set_of_point2(const uint32_t* off, uint32_t nsets, uint32_t n,
 // Finite live cells of a pool with their border flag (stage output).
 template <int D>
 __global__ void k_rows_with_flag(const double4* P, const Cell* cells,
-                                 uint32_t ncells, const uint8_t* cflag, int32_t* rows,
+                                 uint32_t ncells, const unsigned long long* hashm, int32_t* rows,
                                  uint32_t* count) {
   uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells || cells[c].fwd != ALIVE) return;
@@ -63,7 +63,7 @@ __global__ void k_rows_with_flag(const double4* P, const Cell* cells,
     }
   uint32_t s = atomicAdd(count, 1u);
   for (int i = 0; i <= D; i++) rows[(size_t)s * (D + 2) + i] = k[i];
-  rows[(size_t)s * (D + 2) + D + 1] = cflag[c];
+  rows[(size_t)s * (D + 2) + D + 1] = (int32_t)((hashm[c >> 6] >> (c & 63u)) & 1ull);
 }
 
 template <class T>
@@ -408,11 +408,13 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
         if (D == 2)
           hipLaunchKernelGGL(k_rows_with_flag<2>, dim3(cblocks(pool.ncells)), dim3(CB), 0, st,
                              job.pts, pool.cells.as<Cell>(), pool.ncells,
-                             bo.cflag.as<uint8_t>(), rows.as<int32_t>(), c2.as<uint32_t>());
+                             bo.hashm.as<unsigned long long>(), rows.as<int32_t>(),
+                             c2.as<uint32_t>());
         else
           hipLaunchKernelGGL(k_rows_with_flag<3>, dim3(cblocks(pool.ncells)), dim3(CB), 0, st,
                              job.pts, pool.cells.as<Cell>(), pool.ncells,
-                             bo.cflag.as<uint8_t>(), rows.as<int32_t>(), c2.as<uint32_t>());
+                             bo.hashm.as<unsigned long long>(), rows.as<int32_t>(),
+                             c2.as<uint32_t>());
         DT_HIP(hipGetLastError());
       }
       DT_TRY(to_host<int32_t>(r->stage[DT_ARR_LOCAL], rows.p, (size_t)S.local_simplices * (D + 2),

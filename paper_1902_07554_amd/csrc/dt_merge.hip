@@ -273,114 +273,199 @@ __global__ void k_point_margin(const double4* pts, uint32_t n, const uint32_t* n
 
 constexpr uint32_t NB_STRIPES = 64;   // copies of the border-simplex counter
 
+// The test of one live cell c: flag it, and its vertices (vbflag), when
+// its circumsphere may reach another partition.  finite: no vertex is the
+// infinite one.  vis: the thread's slots in the walk's LDS list.
+template <int D>
+__device__ __forceinline__ void border_cell(const double4* P, const uint32_t* pset,
+                                            const Cell* cells, uint32_t c, const BGrid& G,
+                                            const uint32_t* owner, const Region& R,
+                                            uint32_t* vbflag, uint32_t* flags, uint32_t* vis,
+                                            bool& flag, bool& finite) {
+  flag = false;
+  finite = false;
+  uint4 v4 = cells[c].v;
+  uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+  bool inf = false;
+#pragma unroll
+  for (int i = 0; i <= D; i++)
+    if (v[i] == INF_V) inf = true;
+  if (inf) {
+    flag = true;
+  } else {
+    finite = true;
+    double ctr[3], r = 0.0;
+    const bool sliver = !circumball<D>(P[v[0]], P[v[1]], P[v[2]], P[v[D == 3 ? 3 : 2]], ctr, &r);
+    if (sliver) {
+      flag = true;
+    } else if (R.kind == BORDER_VORONOI && R.margin) {
+      // clearance of the vertices first (every vertex lies on the sphere)
+      double m = R.margin[v[0]];
+#pragma unroll
+      for (int i = 1; i <= D; i++) m = fmax(m, R.margin[v[i]]);
+      if (!(m > 2.0 * r)) {
+        // the own sample nearest the centre among the vertices' samples
+        uint32_t t = 0xFFFFFFFFu;
+        double best = INFINITY;
+        const double cz = D == 3 ? ctr[2] : 0.0;
+#pragma unroll
+        for (int i = 0; i <= D; i++) {
+          const uint32_t s = R.near_loc[v[i]];
+          const double4 q = R.S[s];
+          const double dx = ctr[0] - q.x, dy = ctr[1] - q.y, dz = cz - q.z;
+          const double d2 = (dx * dx + dy * dy) + dz * dz;
+          if (d2 < best) { best = d2; t = s; }
+        }
+        flag = R.gadj ? voronoi_walk_hit<D, MB>(R, pset[v[0]], ctr, r, t, vis)
+                      : region_hit<D>(R, pset[v[0]], ctr, r, t);
+      }
+      // refined: of the region test's simplices keep those whose sphere
+      // really holds a point of another partition
+      if (flag && R.refine) flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
+    } else if (R.kind == BORDER_BBOX) {
+      flag = bbox_hit<D>(R, pset[v[0]], ctr, r);
+    } else if (R.kind == BORDER_EXACT) {
+      flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
+    } else if (R.kind != BORDER_GRID) {
+      flag = region_hit<D>(R, pset[v[0]], ctr, r);
+      if (flag && R.refine) flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
+    } else {
+      uint32_t me = pset[v[0]];
+      int lo[3], hi[3];
+      long ncover = 1;
+      for (int k = 0; k < 3; k++) {
+        if (k < D) {
+          lo[k] = bcoord(ctr[k] - r, G, k);
+          hi[k] = bcoord(ctr[k] + r, G, k);
+        } else {
+          lo[k] = hi[k] = 0;
+        }
+        ncover *= (hi[k] - lo[k] + 1);
+      }
+      if (ncover > 4096) {
+        flag = true;
+      } else {
+        double r2 = r * r;
+        for (int z = lo[2]; z <= hi[2] && !flag; z++)
+          for (int y = lo[1]; y <= hi[1] && !flag; y++)
+            for (int x = lo[0]; x <= hi[0] && !flag; x++) {
+              uint32_t own = owner[((uint32_t)z * G.g[1] + y) * G.g[0] + x];
+              if (own == OWN_EMPTY || own == me) continue;
+              // squared distance from the centre to the grid cell (box)
+              int cc[3] = {x, y, z};
+              double d2 = 0.0;
+              for (int k = 0; k < D; k++) {
+                double bl = G.lo[k] + cc[k] * G.h, bh = bl + G.h;
+                // the first and last cells extend to infinity (points are clamped)
+                if (cc[k] == 0) bl = -INFINITY;
+                if (cc[k] == G.g[k] - 1) bh = INFINITY;
+                double t = ctr[k] < bl ? bl - ctr[k] : (ctr[k] > bh ? ctr[k] - bh : 0.0);
+                d2 += t * t;
+              }
+              if (d2 <= r2) flag = true;
+            }
+      }
+    }
+  }
+  if (flag) {
+#pragma unroll
+    for (int i = 0; i <= D; i++)
+      if (v[i] != INF_V) vbflag[key_of(P, v[i])] = 1u;
+  }
+}
+
+// Tiles of the cell pool.  The pool holds every cell ever created, about
+// four for each live one (destroyed cells keep their records), so each
+// wavefront takes a tile of BT * 64 consecutive cells, lists the ones it
+// has to work on in LDS (from the cells' forward words, or from a bit mask
+// of the tile), and then works on the listed cells with all its lanes.
+// A block of MB threads takes BTILES_PER_BLOCK consecutive tiles.
+constexpr uint32_t BT = 4;
+constexpr uint32_t BTILE = BT * 64;
+constexpr uint32_t BTILES_PER_BLOCK = MB / 64;
+constexpr uint32_t BWORDS = BT * BTILES_PER_BLOCK;   // mask words of a block
+static inline uint32_t btiles(uint64_t n) {
+  return (uint32_t)((n + BTILE * BTILES_PER_BLOCK - 1) / (BTILE * BTILES_PER_BLOCK));
+}
+
+// Barrier of one wavefront (LDS written by some lanes, read by others).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The live cells of the wavefront's tile, in cell order, listed in LDS;
+// returns their number (the same in every lane).
+__device__ __forceinline__ uint32_t list_live(const Cell* cells, uint32_t ncells, uint32_t tile0,
+                                              uint32_t lane, uint32_t* list) {
+  uint32_t n = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < BT; j++) {
+    const uint32_t c = tile0 + j * 64 + lane;
+    const bool alive = c < ncells && cells[c].fwd == ALIVE;
+    const unsigned long long m = __ballot(alive);
+    if (alive) list[n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = c;
+    n += (uint32_t)__popcll(m);
+  }
+  wave_sync_lds();
+  return n;
+}
+
+// The cells of the tile whose bits are set in its BT mask words.
+__device__ __forceinline__ uint32_t list_masked(const unsigned long long* words, uint32_t tile0,
+                                                uint32_t lane, uint32_t* list) {
+  uint32_t n = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < BT; j++) {
+    const unsigned long long m = words[j];
+    if ((m >> lane) & 1ull)
+      list[n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = tile0 + j * 64 + lane;
+    n += (uint32_t)__popcll(m);
+  }
+  wave_sync_lds();
+  return n;
+}
+
+// Border test of every live cell.  Output per tile: two bit masks over its
+// cells, emitm (finite and not flagged: output as it is) and hashm (finite
+// and flagged: the border simplices B), and the border vertices (vbflag).
 template <int D>
 __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cells,
                          uint32_t ncells, BGrid G, const uint32_t* owner, Region R,
-                         uint8_t* cflag, uint32_t* vbflag, unsigned long long* nb,
-                         uint32_t* flags) {
+                         unsigned long long* emitm, unsigned long long* hashm,
+                         uint32_t* vbflag, unsigned long long* nb, uint32_t* flags) {
   __shared__ uint32_t s_vis[VW_CAP * MB];
-  uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  bool flag = false, finite = false;
-  if (c < ncells && cells[c].fwd == ALIVE) {
-    uint4 v4 = cells[c].v;
-    uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
-    bool inf = false;
-#pragma unroll
-    for (int i = 0; i <= D; i++)
-      if (v[i] == INF_V) inf = true;
-    if (inf) {
-      flag = true;
-    } else {
-      finite = true;
-      double ctr[3], r = 0.0;
-      const bool sliver = !circumball<D>(P[v[0]], P[v[1]], P[v[2]], P[v[D == 3 ? 3 : 2]], ctr, &r);
-      if (sliver) {
-        flag = true;
-      } else if (R.kind == BORDER_VORONOI && R.margin) {
-        // clearance of the vertices first (every vertex lies on the sphere)
-        double m = R.margin[v[0]];
-#pragma unroll
-        for (int i = 1; i <= D; i++) m = fmax(m, R.margin[v[i]]);
-        if (!(m > 2.0 * r)) {
-          // the own sample nearest the centre among the vertices' samples
-          uint32_t t = 0xFFFFFFFFu;
-          double best = INFINITY;
-          const double cz = D == 3 ? ctr[2] : 0.0;
-#pragma unroll
-          for (int i = 0; i <= D; i++) {
-            const uint32_t s = R.near_loc[v[i]];
-            const double4 q = R.S[s];
-            const double dx = ctr[0] - q.x, dy = ctr[1] - q.y, dz = cz - q.z;
-            const double d2 = (dx * dx + dy * dy) + dz * dz;
-            if (d2 < best) { best = d2; t = s; }
-          }
-          flag = R.gadj ? voronoi_walk_hit<D, MB>(R, pset[v[0]], ctr, r, t, s_vis + threadIdx.x)
-                        : region_hit<D>(R, pset[v[0]], ctr, r, t);
-        }
-        // refined: of the region test's simplices keep those whose sphere
-        // really holds a point of another partition
-        if (flag && R.refine) flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
-      } else if (R.kind == BORDER_BBOX) {
-        flag = bbox_hit<D>(R, pset[v[0]], ctr, r);
-      } else if (R.kind == BORDER_EXACT) {
-        flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
-      } else if (R.kind != BORDER_GRID) {
-        flag = region_hit<D>(R, pset[v[0]], ctr, r);
-        if (flag && R.refine) flag = exact_hit<D>(P, pset, v, pset[v[0]], ctr, r, G, R, flags);
-      } else {
-        uint32_t me = pset[v[0]];
-        int lo[3], hi[3];
-        long ncover = 1;
-        for (int k = 0; k < 3; k++) {
-          if (k < D) {
-            lo[k] = bcoord(ctr[k] - r, G, k);
-            hi[k] = bcoord(ctr[k] + r, G, k);
-          } else {
-            lo[k] = hi[k] = 0;
-          }
-          ncover *= (hi[k] - lo[k] + 1);
-        }
-        if (ncover > 4096) {
-          flag = true;
-        } else {
-          double r2 = r * r;
-          for (int z = lo[2]; z <= hi[2] && !flag; z++)
-            for (int y = lo[1]; y <= hi[1] && !flag; y++)
-              for (int x = lo[0]; x <= hi[0] && !flag; x++) {
-                uint32_t own = owner[((uint32_t)z * G.g[1] + y) * G.g[0] + x];
-                if (own == OWN_EMPTY || own == me) continue;
-                // squared distance from the centre to the grid cell (box)
-                int cc[3] = {x, y, z};
-                double d2 = 0.0;
-                for (int k = 0; k < D; k++) {
-                  double bl = G.lo[k] + cc[k] * G.h, bh = bl + G.h;
-                  // the first and last cells extend to infinity (points are clamped)
-                  if (cc[k] == 0) bl = -INFINITY;
-                  if (cc[k] == G.g[k] - 1) bh = INFINITY;
-                  double t = ctr[k] < bl ? bl - ctr[k] : (ctr[k] > bh ? ctr[k] - bh : 0.0);
-                  d2 += t * t;
-                }
-                if (d2 <= r2) flag = true;
-              }
-        }
-      }
+  __shared__ uint32_t s_live[BTILES_PER_BLOCK][BTILE];
+  __shared__ unsigned long long s_em[BTILES_PER_BLOCK][BT], s_hm[BTILES_PER_BLOCK][BT];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t tile0 = (blockIdx.x * BTILES_PER_BLOCK + w) * BTILE;
+  if (lane < BT) {
+    s_em[w][lane] = 0;
+    s_hm[w][lane] = 0;
+  }
+  uint32_t* live = s_live[w];
+  const uint32_t nlive = list_live(cells, ncells, tile0, lane, live);
+  unsigned long long cnt = 0;
+  for (uint32_t b = 0; b < nlive; b += 64) {
+    bool flag = false, finite = false;
+    if (b + lane < nlive) {
+      const uint32_t c = live[b + lane];
+      border_cell<D>(P, pset, cells, c, G, owner, R, vbflag, flags, s_vis + threadIdx.x, flag,
+                     finite);
+      const uint32_t o = c - tile0;
+      if (finite) atomicOr(flag ? &s_hm[w][o >> 6] : &s_em[w][o >> 6], 1ull << (o & 63u));
     }
-    if (flag) {
-      cflag[c] = 1;
-#pragma unroll
-      for (int i = 0; i <= D; i++)
-        if (v[i] != INF_V) vbflag[key_of(P, v[i])] = 1u;
-    } else {
-      cflag[c] = 0;
-    }
-  } else if (c < ncells) {
-    cflag[c] = 0;
+    cnt += (unsigned long long)__popcll(__ballot(flag && finite));
+  }
+  wave_sync_lds();
+  if (lane < BT) {
+    emitm[tile0 / 64 + lane] = s_em[w][lane];
+    hashm[tile0 / 64 + lane] = s_hm[w][lane];
   }
   // striped count (one address for every wavefront would serialise)
-  unsigned long long m = __ballot(flag && finite);
-  if ((threadIdx.x & 63) == 0 && m)
-    atomicAdd(&nb[(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % NB_STRIPES],
-              (unsigned long long)__popcll(m));
+  if (lane == 0 && cnt)
+    atomicAdd(&nb[(blockIdx.x * BTILES_PER_BLOCK + w) % NB_STRIPES], cnt);
 }
 
 // Points of partitions that have no full-dimensional triangulation (fewer
@@ -401,7 +486,10 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
   DevBuf owner, vbflag, nb, margin, near_loc;
   DT_TRY(owner.alloc(grid ? total * 4 : 16));
   DT_TRY(vbflag.alloc((size_t)n * 4));
-  DT_TRY(out.cflag.alloc((size_t)pool.ncells + 1));
+  const size_t nwords = (size_t)btiles(pool.ncells) * BWORDS;
+  DT_TRY(out.emitm.alloc((nwords ? nwords : 1) * 8));
+  DT_TRY(out.hashm.alloc((nwords ? nwords : 1) * 8));
+  out.nwords = nwords;
   DT_TRY(nb.alloc(NB_STRIPES * 8));
   DT_HIP(hipMemsetAsync(vbflag.p, 0, (size_t)n * 4, st));
   DT_HIP(hipMemsetAsync(nb.p, 0, NB_STRIPES * 8, st));
@@ -453,15 +541,19 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
     R.margin = margin.as<double>();
     R.near_loc = near_loc.as<uint32_t>();
   }
-  if (D == 2)
-    hipLaunchKernelGGL(k_border<2>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+  if (pool.ncells == 0) {
+    // nothing to test (every partition degenerate)
+  } else if (D == 2)
+    hipLaunchKernelGGL(k_border<2>, dim3(btiles(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cells.as<Cell>(), pool.ncells, G,
-                       owner.as<uint32_t>(), R, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       owner.as<uint32_t>(), R, out.emitm.as<unsigned long long>(),
+                       out.hashm.as<unsigned long long>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>(), pflags.as<uint32_t>());
   else
-    hipLaunchKernelGGL(k_border<3>, dim3(mblocks(pool.ncells)), dim3(MB), 0, st, job.pts,
+    hipLaunchKernelGGL(k_border<3>, dim3(btiles(pool.ncells)), dim3(MB), 0, st, job.pts,
                        job.pset, pool.cells.as<Cell>(), pool.ncells, G,
-                       owner.as<uint32_t>(), R, out.cflag.as<uint8_t>(), vbflag.as<uint32_t>(),
+                       owner.as<uint32_t>(), R, out.emitm.as<unsigned long long>(),
+                       out.hashm.as<unsigned long long>(), vbflag.as<uint32_t>(),
                        nb.as<unsigned long long>(), pflags.as<uint32_t>());
   DT_PROF_END(st);
   hipLaunchKernelGGL(k_degenerate_parts, dim3(mblocks(job.npts)), dim3(MB), 0, st, job.pts,
@@ -498,18 +590,6 @@ __device__ __forceinline__ uint32_t hkey(const uint32_t k[4]) {
   return (uint32_t)(h * 0xBF58476D1CE4E5B9ull >> 32);
 }
 
-template <int D>
-__device__ __forceinline__ bool finite_live(const Cell* cells, uint32_t c,
-                                            uint4& v) {
-  if (cells[c].fwd != ALIVE) return false;
-  v = cells[c].v;
-  uint32_t vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int i = 0; i <= D; i++)
-    if (vv[i] == INF_V) return false;
-  return true;
-}
-
 
 template <int D>
 __device__ __forceinline__ void write_row(int32_t* rows, uint32_t slot, const uint32_t k[4]) {
@@ -521,21 +601,50 @@ __device__ __forceinline__ void write_row(int32_t* rows, uint32_t slot, const ui
 // atomic cursor and comes out in cell order: a marking pass (per block:
 // the number of cells to output, and the number of finite cells for the
 // statistics; local flagged cells go into the table, border cells are
-// looked up in it), a scan of the block counts, and a writing pass.
+// looked up in it), a scan of the block counts, and a writing pass.  The
+// passes work on tiles (above): the local pool's from the border test's
+// masks, the border pool's from the forward words and then a mask of its
+// own.
 
-// Local pass 1: count unflagged finite cells; insert flagged ones into B.
+// Sum over the lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Cells to output and finite cells of a block, from its mask words
+// (wavefront 0 counts; the others return 0).
+__device__ __forceinline__ void block_mask_counts(const unsigned long long* emitm,
+                                                  const unsigned long long* finm, uint32_t& ne,
+                                                  uint32_t& nf) {
+  const uint32_t t = threadIdx.x;
+  const size_t wd = (size_t)blockIdx.x * BWORDS + t;
+  uint32_t e = 0, f = 0;
+  if (t < BWORDS) {
+    const unsigned long long em = emitm[wd];
+    e = (uint32_t)__popcll(em);
+    f = finm ? e + (uint32_t)__popcll(finm[wd]) : 0u;
+  }
+  ne = t < 64 ? wave_total(e) : 0u;
+  nf = t < 64 ? wave_total(f) : 0u;
+}
+
+// Local pass 1: the flagged finite cells (B) go into the table; the block
+// counts come from the masks.
 template <int D>
 __global__ void k_merge_mark_local(const double4* P, const Cell* cells,
-                                   uint32_t ncells, const uint8_t* cflag, uint32_t* occ,
-                                   uint4* tkeys, uint32_t tmask, uint32_t* bemit,
-                                   uint32_t* bfinite, uint32_t* flags) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  uint4 v;
-  const bool live = c < ncells && finite_live<D>(cells, c, v);
-  const bool flagged = live && cflag[c] != 0;
-  if (flagged) {
+                                   const unsigned long long* emitm,
+                                   const unsigned long long* hashm, uint32_t* occ, uint4* tkeys,
+                                   uint32_t tmask, uint32_t* bemit, uint32_t* bfinite,
+                                   uint32_t* flags) {
+  __shared__ uint32_t s_list[BTILES_PER_BLOCK][BTILE];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t tile0 = (blockIdx.x * BTILES_PER_BLOCK + w) * BTILE;
+  uint32_t* list = s_list[w];
+  const uint32_t nh = list_masked(hashm + tile0 / 64, tile0, lane, list);
+  for (uint32_t b = lane; b < nh; b += 64) {
     uint32_t k[4];
-    sorted_keys(P, v, D, k);
+    sorted_keys(P, cells[list[b]].v, D, k);
     const uint32_t h = hkey(k);
     for (uint32_t pr = 0; pr <= tmask; pr++) {
       const uint32_t s = (h + pr) & tmask;
@@ -547,47 +656,63 @@ __global__ void k_merge_mark_local(const double4* P, const Cell* cells,
     }
   }
   uint32_t ne, nf;
-  block_exclusive<MB>((live && !flagged) ? 1u : 0u, &ne);
-  block_exclusive<MB>(live ? 1u : 0u, &nf);
+  block_mask_counts(emitm, hashm, ne, nf);
   if (threadIdx.x == 0) {
     bemit[blockIdx.x] = ne;
     bfinite[blockIdx.x] = nf;
   }
 }
 
-// Local pass 2: write the unflagged finite cells.
+// Pass 2 of either pool: write the cells of the emit mask, the block's at
+// its offset, in cell order.
 template <int D>
-__global__ void k_merge_write_local(const double4* P, const Cell* cells,
-                                    uint32_t ncells, const uint8_t* cflag, const uint32_t* boff,
-                                    int32_t* rows) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  uint4 v;
-  const bool emit = c < ncells && finite_live<D>(cells, c, v) && cflag[c] == 0;
-  uint32_t tot;
-  const uint32_t pre = block_exclusive<MB>(emit ? 1u : 0u, &tot);
-  if (!emit) return;
-  uint32_t k[4];
-  sorted_keys(P, v, D, k);
-  write_row<D>(rows, boff[blockIdx.x] + pre, k);
+__global__ void k_merge_write(const double4* P, const Cell* cells,
+                              const unsigned long long* emitm, const uint32_t* boff,
+                              uint32_t base, int32_t* rows) {
+  __shared__ uint32_t s_list[BTILES_PER_BLOCK][BTILE];
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t tile0 = (blockIdx.x * BTILES_PER_BLOCK + w) * BTILE;
+  uint32_t* list = s_list[w];
+  // rows of the block's earlier tiles
+  uint32_t before = 0;
+  for (uint32_t x = 0; x < w * BT; x++)
+    before += (uint32_t)__popcll(emitm[(size_t)blockIdx.x * BWORDS + x]);
+  const uint32_t ne = list_masked(emitm + tile0 / 64, tile0, lane, list);
+  const uint32_t at = base + boff[blockIdx.x] + before;
+  for (uint32_t b = lane; b < ne; b += 64) {
+    uint32_t k[4];
+    sorted_keys(P, cells[list[b]].v, D, k);
+    write_row<D>(rows, at + b, k);
+  }
 }
 
 // Border pass 1: a finite cell of T_B is output if it spans several
-// partitions or its vertex set is in B; the decision is kept per cell.
+// partitions or its vertex set is in B; the decision is kept in a mask.
 template <int D>
 __global__ void k_merge_mark_border(const double4* P, const Cell* cells,
                                     uint32_t ncells, const uint32_t* pid_by_id,
                                     const uint32_t* occ, const uint4* tkeys, uint32_t tmask,
-                                    uint8_t* emitf, uint32_t* bemit, uint32_t* bfinite,
-                                    unsigned long long* probe_hist) {
+                                    unsigned long long* emitm, uint32_t* bemit,
+                                    uint32_t* bfinite, unsigned long long* probe_hist) {
   // probe-length histogram: per block in LDS, one global add per bin
   __shared__ uint32_t s_hist[16];
+  __shared__ uint32_t s_list[BTILES_PER_BLOCK][BTILE];
+  __shared__ unsigned long long s_em[BTILES_PER_BLOCK][BT];
+  __shared__ uint32_t s_fin;
   if (threadIdx.x < 16) s_hist[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_fin = 0;
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t tile0 = (blockIdx.x * BTILES_PER_BLOCK + w) * BTILE;
+  if (lane < BT) s_em[w][lane] = 0;
   __syncthreads();
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  uint4 v;
-  const bool live = c < ncells && finite_live<D>(cells, c, v);
-  bool emit = false;
-  if (live) {
+  uint32_t* list = s_list[w];
+  const uint32_t nlive = list_live(cells, ncells, tile0, lane, list);
+  uint32_t nfin = 0;
+  for (uint32_t b = lane; b < nlive; b += 64) {
+    const uint32_t c = list[b];
+    const uint4 v = cells[c].v;
+    if (v.x == INF_V || v.y == INF_V || v.z == INF_V || (D == 3 && v.w == INF_V)) continue;
+    nfin++;
     uint32_t k[4];
     sorted_keys(P, v, D, k);
     const uint32_t p0 = pid_by_id[k[0]];
@@ -595,9 +720,8 @@ __global__ void k_merge_mark_border(const double4* P, const Cell* cells,
 #pragma unroll
     for (int i = 1; i <= D; i++)
       if (pid_by_id[k[i]] != p0) span = true;
-    if (span) {
-      emit = true;
-    } else {
+    bool emit = span;
+    if (!span) {
       const uint32_t h = hkey(k);
       uint32_t pr = 0;
       for (; pr <= tmask; pr++) {
@@ -611,32 +735,25 @@ __global__ void k_merge_mark_border(const double4* P, const Cell* cells,
       }
       atomicAdd(&s_hist[pr < 15 ? pr : 15], 1u);
     }
+    const uint32_t o = c - tile0;
+    if (emit) atomicOr(&s_em[w][o >> 6], 1ull << (o & 63u));
   }
-  if (c < ncells) emitf[c] = emit ? 1 : 0;
-  uint32_t ne, nf;
-  block_exclusive<MB>(emit ? 1u : 0u, &ne);
-  block_exclusive<MB>(live ? 1u : 0u, &nf);
+  nfin = wave_total(nfin);
+  if (lane == 0 && nfin) atomicAdd(&s_fin, nfin);
+  __syncthreads();
+  if (lane < BT) emitm[tile0 / 64 + lane] = s_em[w][lane];
+  uint32_t ne = 0;
+  if (threadIdx.x < 64) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t e = t < BWORDS ? (uint32_t)__popcll(s_em[t / BT][t % BT]) : 0u;
+    ne = wave_total(e);
+  }
   if (threadIdx.x == 0) {
     bemit[blockIdx.x] = ne;
-    bfinite[blockIdx.x] = nf;
+    bfinite[blockIdx.x] = s_fin;
   }
   if (threadIdx.x < 16 && s_hist[threadIdx.x])
     atomicAdd(&probe_hist[threadIdx.x], (unsigned long long)s_hist[threadIdx.x]);
-}
-
-// Border pass 2: write the kept cells after the local ones.
-template <int D>
-__global__ void k_merge_write_border(const double4* P, const Cell* cells, uint32_t ncells,
-                                     const uint8_t* emitf, const uint32_t* boff, uint32_t base,
-                                     int32_t* rows) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool emit = c < ncells && emitf[c] != 0;
-  uint32_t tot;
-  const uint32_t pre = block_exclusive<MB>(emit ? 1u : 0u, &tot);
-  if (!emit) return;
-  uint32_t k[4];
-  sorted_keys(P, cells[c].v, D, k);
-  write_row<D>(rows, base + boff[blockIdx.x] + pre, k);
 }
 
 // Sum of n block counts: exclusive offsets into off[0..n], total returned.
@@ -654,8 +771,8 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
                  int64_t probe_hist[16], hipStream_t st) {
   uint32_t tsize = 64;
   while (tsize < 2 * b.nb_finite + 16) tsize <<= 1;
-  const uint32_t nbl = mblocks(pool.ncells), nbb = mblocks(bpool.ncells);
-  DevBuf occ, tkeys, hist, flags, lemit, lfin, loff, bemit, bfin, boff, emitf, junk;
+  const uint32_t nbl = btiles(pool.ncells), nbb = btiles(bpool.ncells);
+  DevBuf occ, tkeys, hist, flags, lemit, lfin, loff, bemit, bfin, boff, bemitm, junk;
   DT_TRY(occ.alloc((size_t)tsize * 4));
   DT_TRY(tkeys.alloc((size_t)tsize * 16));
   DT_TRY(hist.alloc(16 * 8));
@@ -666,7 +783,7 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
   DT_TRY(bemit.alloc((size_t)(nbb + 1) * 4));
   DT_TRY(bfin.alloc((size_t)(nbb + 1) * 4));
   DT_TRY(boff.alloc((size_t)(nbb + 1) * 4));
-  DT_TRY(emitf.alloc((size_t)(bpool.ncells ? bpool.ncells : 1)));
+  DT_TRY(bemitm.alloc((size_t)(nbb ? nbb : 1) * BWORDS * 8));
   DT_TRY(junk.alloc((size_t)(((nbl > nbb) ? nbl : nbb) + 1) * 4));
   DT_HIP(hipMemsetAsync(occ.p, 0, (size_t)tsize * 4, st));
   DT_HIP(hipMemsetAsync(hist.p, 0, 16 * 8, st));
@@ -675,28 +792,30 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
   if (pool.ncells) {
     if (D == 2)
       hipLaunchKernelGGL(k_merge_mark_local<2>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cells.as<Cell>(), pool.ncells,
-                         b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         lemit.as<uint32_t>(), lfin.as<uint32_t>(), flags.as<uint32_t>());
+                         pool.cells.as<Cell>(), b.emitm.as<unsigned long long>(),
+                         b.hashm.as<unsigned long long>(), occ.as<uint32_t>(), tkeys.as<uint4>(),
+                         tsize - 1, lemit.as<uint32_t>(), lfin.as<uint32_t>(),
+                         flags.as<uint32_t>());
     else
       hipLaunchKernelGGL(k_merge_mark_local<3>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cells.as<Cell>(), pool.ncells,
-                         b.cflag.as<uint8_t>(), occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         lemit.as<uint32_t>(), lfin.as<uint32_t>(), flags.as<uint32_t>());
+                         pool.cells.as<Cell>(), b.emitm.as<unsigned long long>(),
+                         b.hashm.as<unsigned long long>(), occ.as<uint32_t>(), tkeys.as<uint4>(),
+                         tsize - 1, lemit.as<uint32_t>(), lfin.as<uint32_t>(),
+                         flags.as<uint32_t>());
   }
   if (bpool.ncells) {
     if (D == 2)
       hipLaunchKernelGGL(k_merge_mark_border<2>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
                          bpool.cells.as<Cell>(), bpool.ncells,
                          pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         emitf.as<uint8_t>(), bemit.as<uint32_t>(), bfin.as<uint32_t>(),
-                         hist.as<unsigned long long>());
+                         bemitm.as<unsigned long long>(), bemit.as<uint32_t>(),
+                         bfin.as<uint32_t>(), hist.as<unsigned long long>());
     else
       hipLaunchKernelGGL(k_merge_mark_border<3>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
                          bpool.cells.as<Cell>(), bpool.ncells,
                          pid_by_id, occ.as<uint32_t>(), tkeys.as<uint4>(), tsize - 1,
-                         emitf.as<uint8_t>(), bemit.as<uint32_t>(), bfin.as<uint32_t>(),
-                         hist.as<unsigned long long>());
+                         bemitm.as<unsigned long long>(), bemit.as<uint32_t>(),
+                         bfin.as<uint32_t>(), hist.as<unsigned long long>());
   }
   DT_PROF_END(st);
   DT_HIP(hipGetLastError());
@@ -714,22 +833,22 @@ int merge_output(const LocalJob& job, const CellPool& pool, const BorderOut& b,
   DT_PROF_BEGIN(DT_KERN_MERGE, st);
   if (nl) {
     if (D == 2)
-      hipLaunchKernelGGL(k_merge_write_local<2>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cells.as<Cell>(), pool.ncells,
-                         b.cflag.as<uint8_t>(), loff.as<uint32_t>(), rows.as<int32_t>());
+      hipLaunchKernelGGL(k_merge_write<2>, dim3(nbl), dim3(MB), 0, st, job.pts,
+                         pool.cells.as<Cell>(), b.emitm.as<unsigned long long>(),
+                         loff.as<uint32_t>(), 0u, rows.as<int32_t>());
     else
-      hipLaunchKernelGGL(k_merge_write_local<3>, dim3(nbl), dim3(MB), 0, st, job.pts,
-                         pool.cells.as<Cell>(), pool.ncells,
-                         b.cflag.as<uint8_t>(), loff.as<uint32_t>(), rows.as<int32_t>());
+      hipLaunchKernelGGL(k_merge_write<3>, dim3(nbl), dim3(MB), 0, st, job.pts,
+                         pool.cells.as<Cell>(), b.emitm.as<unsigned long long>(),
+                         loff.as<uint32_t>(), 0u, rows.as<int32_t>());
   }
   if (nb) {
     if (D == 2)
-      hipLaunchKernelGGL(k_merge_write_border<2>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
-                         bpool.cells.as<Cell>(), bpool.ncells, emitf.as<uint8_t>(),
+      hipLaunchKernelGGL(k_merge_write<2>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
+                         bpool.cells.as<Cell>(), bemitm.as<unsigned long long>(),
                          boff.as<uint32_t>(), nl, rows.as<int32_t>());
     else
-      hipLaunchKernelGGL(k_merge_write_border<3>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
-                         bpool.cells.as<Cell>(), bpool.ncells, emitf.as<uint8_t>(),
+      hipLaunchKernelGGL(k_merge_write<3>, dim3(nbb), dim3(MB), 0, st, bjob.pts,
+                         bpool.cells.as<Cell>(), bemitm.as<unsigned long long>(),
                          boff.as<uint32_t>(), nl, rows.as<int32_t>());
   }
   DT_PROF_END(st);

@@ -50,7 +50,11 @@ int count_by(const uint32_t* x, uint32_t m, uint32_t k, uint32_t* cnt, hipStream
 
 // Border and merge (dt_merge.hip)
 struct BorderOut {
-  DevBuf cflag;         // [pool.ncells] 1 = border simplex (or hull cell)
+  // bit masks over the local pool's cells (bit c % 64 of word c / 64):
+  // finite live cells to output as they are, and the finite border
+  // simplices B; nwords words each (whole blocks of tiles)
+  DevBuf emitm, hashm;
+  size_t nwords = 0;
   DevBuf vb;            // border vertices (global ids, ascending)
   uint32_t nvb = 0;
   uint64_t nb_finite = 0;   // |B| (finite flagged cells)
