@@ -59,10 +59,11 @@ def simplices_per_point(dim: int) -> float:
 
 def inserted_points(st: dict) -> int:
     """Points inserted by all local-DT runs of a step: the local sets, the
-    sample (sample divide) and the border set."""
+    sample (sample divide, unless it was gift-wrapped) and the border set."""
     if st.get("k", 1) <= 1:
         return int(st["n"])
-    return int(st["n"] + st["eta"] + st["border_vertices"])
+    sample = 0 if st.get("wrap_levels", 0) else st["eta"]
+    return int(st["n"] + sample + st["border_vertices"])
 
 
 def alg_bytes(name: str, st: dict, dim: int) -> float:
@@ -428,6 +429,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bubbles-3d-4M-k256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-kd", action="store_true", help="skip the kd-divide comparison")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the comparison with the whole input as one set (k = 1)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--cpu-sample", type=int, default=1_500_000,
@@ -524,6 +527,12 @@ def main() -> int:
                                  **summary(kst))
         line["sample_vs_kd_speedup"] = round(kms / ms, 4)
         line["kd_simplex_count_equal"] = bool(kres.count == res.count)
+    if not args.no_direct:
+        # context, not the method: the same input triangulated as one set
+        dres, dms, _, _ = run(binding, pts, args.steps, args.warmup, 1, 0.0, precision=prec)
+        line["direct_k1"] = {"value": round(n / (dms / 1000.0) / 1e6, 4),
+                             "ms_per_step": round(dms, 3), "rounds": dres.stats()["rounds"],
+                             "simplex_count_equal": bool(dres.count == res.count)}
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(host, min(args.cpu_sample, n))
     del pts, res

@@ -110,6 +110,11 @@ typedef struct dt_options {
    * merges bottom-up with the grid test; k must be a power of two.
    * 0 (default): one k-way division and one merge (Algorithm 1). */
   int recursive;
+  /* Triangulation of the sample (sample divide, one k-way division): 0
+   * (default) gift-wraps samples of at most 8192 points and inserts larger
+   * ones in parallel rounds; -1 always inserts in parallel rounds.  Both
+   * give the same simplices (timing only). */
+  int wrap_sample;
 } dt_options;
 
 /* Kernels timed when dt_options.profile = 1. */
@@ -150,6 +155,8 @@ typedef struct dt_stats {
   double divide_stat;         /* DT_DIVIDE_AUTO: the sample's grid-count variation       */
   int64_t large_cavities;     /* insertion rounds in which one cavity outgrew the
                                  per-candidate lists and used a pool-sized list   */
+  int64_t wrap_levels;        /* facet levels of the gift-wrapped sample
+                                 triangulation (0: parallel insertion)           */
 } dt_stats;
 
 typedef struct dt_result dt_result;

@@ -13,6 +13,7 @@
 
 #include "dt_common.hpp"
 #include "dt_internal.hpp"
+#include "dt_gwrap.hpp"
 #include "dt_pipeline.hpp"
 #include "dt_prep.hpp"
 #include "dt_prims.hpp"
@@ -191,10 +192,22 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     sjob.pset = sset.as<uint32_t>();
     sjob.set_off = soff.as<uint32_t>();
     sjob.fp32 = o.precision == DT_PREC_FP32;
-    K4Stats ks;
-    int s = k4_run(sjob, spool, cx.dc(), cx.hctr, st, ks);
-    add_pred(S, ks);
-    if (s != DT_OK) { S.fail = cx.hctr->flags; return s; }
+    // a sample of a few thousand points is gift-wrapped; a larger one, or
+    // one the wrap declines, is triangulated by parallel insertion
+    uint32_t wrap = 0;
+    int s = DT_E_NOT_READY;
+    if (eta <= GW_MAX_POINTS && o.wrap_sample >= 0)
+      s = gift_wrap(Sp.as<double4>(), eta, D, sjob.fp32, spool, &wrap, st);
+    if (s == DT_E_NOT_READY) {
+      K4Stats ks;
+      wrap = 0;
+      s = k4_run(sjob, spool, cx.dc(), cx.hctr, st, ks);
+      add_pred(S, ks);
+      if (s != DT_OK) { S.fail = cx.hctr->flags; return s; }
+    } else if (s != DT_OK) {
+      return s;
+    }
+    S.wrap_levels = wrap;
     if (spool.ncells == 0) return DT_E_DEGENERATE;
     double tb = now_ms();
     S.stage_ms[DT_STAGE_SAMPLE_DT] = tb - ta;

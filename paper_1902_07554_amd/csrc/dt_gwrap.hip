@@ -1,0 +1,477 @@
+// Delaunay triangulation of one small point set by gift wrapping: the
+// sample triangulation of Algorithm 2 (eta(n) = sqrt(n) points by default,
+// Section "Sample Size").
+//
+// Parallel insertion spends about a hundred rounds on the start-up of a
+// small single set (while the triangulation has few cells, the cavities of
+// the candidates overlap and one or two points are inserted per round), and
+// every round is a chain of dependent gathers.  Gift wrapping inserts
+// nothing: from one Delaunay simplex, each facet finds the simplex on its
+// other side directly, and the facets of the simplices found are searched
+// in the next level.  The simplex beyond an oriented facet f is (f, p) for
+// the point p strictly beyond f whose sphere through f holds no other such
+// point: of two candidates p and q, q comes first when it lies inside the
+// sphere through f and p (spheres through f form a pencil, and the
+// in-sphere test orders the candidates along it).  Because f is a facet of
+// a Delaunay simplex on its near side, the balls of the pencil beyond that
+// simplex's ball hold no point on the near side either, so (f, p) is
+// Delaunay.  A facet with no point strictly beyond it lies on the hull.
+// Points on f's own hyperplane can never complete it (the simplex would be
+// flat).
+//
+// Exactness: orientation and the perturbed in-sphere test are the
+// library's predicates (FP32 or FP64 filter, then exact), so the simplices
+// found are the finite cells of the same perturbed Delaunay triangulation
+// that parallel insertion builds.  The seed is a simplex through point 0
+// and D of its 16 nearest points whose circumsphere holds no point, checked
+// against every point.  When no such simplex is among them, or a capacity
+// runs out, the caller triangulates the set by parallel insertion instead.
+//
+// Cost: a facet search reads every point, one wavefront per facet, so the
+// work is about D (D+1) / 2 * 6.8 n^2 predicate evaluations in 3D; it is
+// used for sets of at most GW_MAX_POINTS points.  A level is one launch;
+// the number of levels is the depth of the simplices' adjacency graph from
+// the seed (tens for a few thousand points).
+#include "dt_common.hpp"
+#include "dt_internal.hpp"
+#include "dt_pred.hpp"
+#include "dt_gwrap.hpp"
+
+#include <vector>
+
+namespace dtk {
+
+namespace {
+
+constexpr uint32_t GW_NN = 16;              // nearest points tried for the seed
+constexpr uint32_t GW_NONE = 0xFFFFFFFFu;
+constexpr uint32_t GW_MAX_LEVELS = 4096;
+constexpr uint32_t GW_THREADS = 256;        // level kernel: four facets per block
+constexpr uint32_t GW_LEVEL_BLOCKS = 1024;  // grid of the level kernel (a grid-stride loop)
+constexpr uint32_t GW_GROUP = 8;            // levels launched between two reads of the counters
+
+// device failure bits of the wrap (any: the caller falls back)
+enum : uint32_t { GW_FAIL_SEED = 1u, GW_FAIL_CAP = 2u, GW_FAIL_HASH = 4u };
+
+__device__ __forceinline__ uint32_t vget(const uint4& v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ void vput(uint4& v, int i, uint32_t x) {
+  if (i == 0) v.x = x;
+  else if (i == 1) v.y = x;
+  else if (i == 2) v.z = x;
+  else v.w = x;
+}
+
+__device__ __forceinline__ void gw_load(const double4* P, uint32_t i, double* p,
+                                        unsigned long long& key) {
+  const double4 t = P[i];
+  p[0] = t.x;
+  p[1] = t.y;
+  p[2] = t.z;
+  key = (unsigned long long)__double_as_longlong(t.w);
+}
+
+// Point (p, key) into slot i of X, i known only at run time: an unrolled
+// select, so that X stays in registers.
+template <int D>
+__device__ __forceinline__ void put_slot(PtsX& X, uint32_t i, const double* p,
+                                         unsigned long long key) {
+#pragma unroll
+  for (int k = 0; k <= D; k++)
+    if ((uint32_t)k == i) {
+      X.p[k][0] = p[0];
+      X.p[k][1] = p[1];
+      X.p[k][2] = p[2];
+      X.key[k] = key;
+    }
+}
+
+// Sorted vertex indices of a simplex packed into one key (16 bits each).
+template <int D>
+__device__ __forceinline__ unsigned long long simplex_key(const uint4& v) {
+  uint32_t k[4] = {v.x, v.y, v.z, D == 3 ? v.w : 0u};
+#pragma unroll
+  for (int i = 1; i <= D; i++)
+#pragma unroll
+    for (int j = i; j > 0; j--)
+      if (k[j] < k[j - 1]) {
+        const uint32_t t = k[j];
+        k[j] = k[j - 1];
+        k[j - 1] = t;
+      }
+  unsigned long long key = 0;
+#pragma unroll
+  for (int i = 0; i <= D; i++) key = (key << 16) | (unsigned long long)k[i];
+  return key;
+}
+
+__device__ __forceinline__ uint32_t key_hash(unsigned long long k) {
+  k *= 0x9E3779B97F4A7C15ull;
+  return (uint32_t)(k >> 32) ^ (uint32_t)k;
+}
+
+// Sign of the orientation of the simplex v (D+1 vertex indices).
+template <int D, bool F32>
+__device__ __forceinline__ int simplex_orient(const double4* P, PredT<F32>& pr, const uint4& v) {
+  PtsX X;
+#pragma unroll
+  for (int i = 0; i <= D; i++) gw_load(P, vget(v, i), X.p[i], X.key[i]);
+  return pr.template orient<D>(X);
+}
+
+// Is point q strictly inside the circumsphere of the positively oriented
+// simplex v (perturbed)?
+template <int D, bool F32>
+__device__ __forceinline__ bool in_sphere(const double4* P, PredT<F32>& pr, const uint4& v,
+                                          uint32_t q) {
+  PtsX X;
+#pragma unroll
+  for (int i = 0; i <= D; i++) gw_load(P, vget(v, i), X.p[i], X.key[i]);
+  gw_load(P, q, X.p[D + 1], X.key[D + 1]);
+  return pr.template insphere<D>(X) > 0;
+}
+
+// The GW_NN points nearest to point 0 (by squared distance, then index),
+// one block: GW_NN rounds of a block-wide minimum.
+__global__ void k_gw_nearest(const double4* P, uint32_t n, uint32_t* nn) {
+  __shared__ unsigned long long s_best[GW_THREADS / 64];
+  __shared__ uint32_t s_taken[GW_NN];
+  const double4 o = P[0];
+  const uint32_t want = n - 1 < GW_NN ? n - 1 : GW_NN;
+  for (uint32_t r = 0; r < want; r++) {
+    unsigned long long best = ~0ull;
+    for (uint32_t j = 1 + threadIdx.x; j < n; j += blockDim.x) {
+      bool taken = false;
+      for (uint32_t t = 0; t < r; t++) taken |= (s_taken[t] == j);
+      if (taken) continue;
+      const double4 q = P[j];
+      const double dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
+      const float d2 = (float)(dx * dx + dy * dy + dz * dz);
+      // distance rounded to FP32 and the index: any GW_NN near points do
+      const unsigned long long k = ((unsigned long long)__float_as_uint(d2) << 32) | j;
+      best = k < best ? k : best;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long x = __shfl_xor(best, off, 64);
+      best = x < best ? x : best;
+    }
+    if ((threadIdx.x & 63u) == 0) s_best[threadIdx.x / 64] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long b = s_best[0];
+      for (uint32_t w = 1; w < blockDim.x / 64; w++) b = s_best[w] < b ? s_best[w] : b;
+      s_taken[r] = (uint32_t)(b & 0xFFFFFFFFull);
+      nn[r] = s_taken[r];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nn[GW_NN] = want;
+}
+
+// Candidate seed simplex c: point 0 and D of the near points (combination
+// number c in lexicographic order), positively oriented; false when flat.
+template <int D, bool F32>
+__device__ bool seed_candidate(const double4* P, PredT<F32>& pr, const uint32_t* nn,
+                               uint32_t m, uint32_t c, uint4& v) {
+  uint32_t idx[3] = {0, 0, 0};
+  uint32_t left = c;
+  bool found = false;
+  if (D == 2) {
+    for (uint32_t a = 0; a < m && !found; a++)
+      for (uint32_t b = a + 1; b < m && !found; b++) {
+        if (left == 0) { idx[0] = a; idx[1] = b; found = true; }
+        else left--;
+      }
+  } else {
+    for (uint32_t a = 0; a < m && !found; a++)
+      for (uint32_t b = a + 1; b < m && !found; b++)
+        for (uint32_t e = b + 1; e < m && !found; e++) {
+          if (left == 0) { idx[0] = a; idx[1] = b; idx[2] = e; found = true; }
+          else left--;
+        }
+  }
+  if (!found) return false;
+  v = make_uint4(0u, nn[idx[0]], nn[idx[1]], D == 3 ? nn[idx[2]] : NOSLOT);
+  const int o = simplex_orient<D, F32>(P, pr, v);
+  if (o == 0) return false;
+  if (o < 0) {
+    const uint32_t t = v.y;
+    v.y = v.z;
+    v.z = t;
+  }
+  return true;
+}
+
+// One wavefront per candidate seed: is its circumsphere empty of every
+// point?  The smallest empty candidate's number is kept.
+template <int D, bool F32>
+__global__ void k_gw_seed(const double4* P, uint32_t n, const uint32_t* nn, uint32_t ncomb,
+                          uint32_t* best, uint32_t* flags) {
+  PredT<F32> pr;
+  pr.init(flags);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  if (c >= ncomb) return;
+  const uint32_t m = nn[GW_NN];
+  uint4 v;
+  if (!seed_candidate<D, F32>(P, pr, nn, m, c, v)) return;
+  bool hit = false;
+  for (uint32_t q = lane; q < n && !hit; q += 64) {
+    bool vert = false;
+#pragma unroll
+    for (int i = 0; i <= D; i++) vert |= (vget(v, i) == q);
+    if (!vert && in_sphere<D, F32>(P, pr, v, q)) hit = true;
+  }
+  if (__ballot(hit) == 0ull && lane == 0) atomicMin(best, c);
+}
+
+// Hash set of the simplices found (keys only) and the cell list.
+struct GwState {
+  const double4* P;
+  uint32_t n;
+  Cell* cells;
+  uint32_t cap;
+  uint32_t* ncells;
+  unsigned long long* table;
+  uint32_t tmask;
+  uint32_t* flags;
+};
+
+// Record simplex v unless it is known; true when it is new (then *idx is
+// its cell).
+template <int D>
+__device__ bool gw_record(const GwState& g, const uint4& v, uint32_t* idx) {
+  const unsigned long long key = simplex_key<D>(v);
+  const uint32_t h = key_hash(key);
+  for (uint32_t pr = 0; pr <= g.tmask; pr++) {
+    const uint32_t s = (h + pr) & g.tmask;
+    const unsigned long long old = atomicCAS(&g.table[s], ~0ull, key);
+    if (old == key) return false;
+    if (old == ~0ull) {
+      const uint32_t c = atomicAdd(g.ncells, 1u);
+      if (c >= g.cap) {
+        atomicOr(g.flags, (uint32_t)GW_FAIL_CAP);
+        return false;
+      }
+      Cell& x = g.cells[c];
+      x.v = v;
+      x.n = make_uint4(0u, 0u, 0u, 0u);
+      x.spare = 0;
+      x.cav = NOKEY;
+      x.shell = NOKEY;
+      x.fwd = ALIVE;
+      x.pos = 0;
+      *idx = c;
+      return true;
+    }
+  }
+  atomicOr(g.flags, (uint32_t)GW_FAIL_HASH);
+  return false;
+}
+
+// The seed simplex becomes cell 0; its D+1 facets form the first level.
+template <int D, bool F32>
+__global__ void k_gw_start(GwState g, const uint32_t* nn, const uint32_t* best,
+                           uint32_t* front, uint32_t* cnt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (*best == GW_NONE) {
+    atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
+    return;
+  }
+  PredT<F32> pr;
+  pr.init(g.flags);
+  uint4 v;
+  if (!seed_candidate<D, F32>(g.P, pr, nn, nn[GW_NN], *best, v)) {
+    atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
+    return;
+  }
+  uint32_t c = 0;
+  if (!gw_record<D>(g, v, &c)) {
+    atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
+    return;
+  }
+  for (uint32_t i = 0; i <= (uint32_t)D; i++) front[i] = (c << 2) | i;
+  cnt[0] = D + 1;
+}
+
+// One level: every facet of the input list, one wavefront each, finds the
+// simplex beyond it; a simplex not found before is recorded and its other
+// D facets go to the output list.  Facet (c, i) is the facet of cell c
+// opposite its vertex i, searched away from that vertex.
+template <int D, bool F32>
+__global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32_t* fin,
+                                                         const uint32_t* cnt_in, uint32_t* fout,
+                                                         uint32_t* cnt_out, uint32_t fcap) {
+  const uint32_t nin = *cnt_in;
+  if (nin == 0 || *g.flags) return;
+  PredT<F32> pr;
+  pr.init(g.flags);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wpb = GW_THREADS / 64;
+  for (uint32_t e = blockIdx.x * wpb + threadIdx.x / 64; e < nin; e += gridDim.x * wpb) {
+    const uint32_t ent = fin[e];
+    const uint32_t c = ent >> 2, i = ent & 3u;
+    // the facet's vertices with two of them swapped: (facet, x) is then
+    // positively oriented exactly for x strictly beyond the facet
+    uint4 t = g.cells[c].v;
+    const int a = i == 0 ? 1 : 0, b = i <= 1 ? 2 : 1;
+    {
+      const uint32_t s = vget(t, a);
+      vput(t, a, vget(t, b));
+      vput(t, b, s);
+    }
+    // facet points in their slots (slot i takes the candidate)
+    PtsX F;
+#pragma unroll
+    for (int k = 0; k <= D; k++) {
+      F.p[k][0] = F.p[k][1] = F.p[k][2] = 0.0;
+      F.key[k] = 0;
+      if (k != (int)i) gw_load(g.P, vget(t, k), F.p[k], F.key[k]);
+    }
+    // this lane's first candidate along the pencil, over its share
+    uint32_t best = GW_NONE;
+    double bp[3] = {0.0, 0.0, 0.0};
+    unsigned long long bk = 0;
+    for (uint32_t q = lane; q < g.n; q += 64) {
+      bool vert = false;
+#pragma unroll
+      for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
+      if (vert) continue;
+      double qp[3];
+      unsigned long long qk;
+      gw_load(g.P, q, qp, qk);
+      PtsX X = F;
+      put_slot<D>(X, i, qp, qk);
+      if (pr.template orient<D>(X) <= 0) continue;
+      bool take = best == GW_NONE;
+      if (!take) {
+        put_slot<D>(X, i, bp, bk);
+        X.p[D + 1][0] = qp[0]; X.p[D + 1][1] = qp[1]; X.p[D + 1][2] = qp[2];
+        X.key[D + 1] = qk;
+        take = pr.template insphere<D>(X) > 0;
+      }
+      if (take) {
+        best = q;
+        bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
+        bk = qk;
+      }
+    }
+    // the wavefront's first candidate: a minimum over the lanes under the
+    // same order (a strict total order, so every lane ends with it)
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = __shfl_xor(best, off, 64);
+      if (o == GW_NONE || o == best) continue;
+      double op[3];
+      unsigned long long ok;
+      gw_load(g.P, o, op, ok);
+      bool take = best == GW_NONE;
+      if (!take) {
+        PtsX X = F;
+        put_slot<D>(X, i, bp, bk);
+        X.p[D + 1][0] = op[0]; X.p[D + 1][1] = op[1]; X.p[D + 1][2] = op[2];
+        X.key[D + 1] = ok;
+        take = pr.template insphere<D>(X) > 0;
+      }
+      if (take) {
+        best = o;
+        bp[0] = op[0]; bp[1] = op[1]; bp[2] = op[2];
+        bk = ok;
+      }
+    }
+    if (lane == 0 && best != GW_NONE) {
+      vput(t, (int)i, best);
+      uint32_t nc = 0;
+      if (gw_record<D>(g, t, &nc)) {
+        const uint32_t at = atomicAdd(cnt_out, (uint32_t)D);
+        if (at + D > fcap) {
+          atomicOr(g.flags, (uint32_t)GW_FAIL_CAP);
+        } else {
+          uint32_t w = at;
+          for (uint32_t k = 0; k <= (uint32_t)D; k++)
+            if (k != i) fout[w++] = (nc << 2) | k;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int gift_wrap(const double4* P, uint32_t n, int D, bool fp32, CellPool& pool, uint32_t* levels,
+              hipStream_t st) {
+  *levels = 0;
+  if (n < (uint32_t)D + 2 || n > GW_MAX_POINTS || (D != 2 && D != 3)) return DT_E_NOT_READY;
+  // about 6.8 n simplices in 3D and 2 n in 2D; room for far more
+  const size_t cap = (size_t)n * (D == 3 ? 12 : 4) + 64;
+  size_t tsize = 64;
+  while (tsize < 2 * cap) tsize <<= 1;
+  const size_t fcap = cap * (size_t)D + 8;
+  DevBuf nn, best, flags, table, fa, fb, cnt;
+  DT_TRY(pool.cells.alloc(cap * sizeof(Cell)));
+  DT_TRY(pool.set_cell0.alloc(16));
+  DT_TRY(nn.alloc((GW_NN + 1) * 4));
+  DT_TRY(best.alloc(16));
+  DT_TRY(flags.alloc(16));
+  DT_TRY(table.alloc(tsize * 8));
+  DT_TRY(fa.alloc(fcap * 4));
+  DT_TRY(fb.alloc(fcap * 4));
+  DT_TRY(cnt.alloc((size_t)(GW_MAX_LEVELS + 1) * 4 + 4));
+  uint32_t* ncells = cnt.as<uint32_t>() + GW_MAX_LEVELS + 1;
+  DT_HIP(hipMemsetAsync(best.p, 0xFF, 4, st));
+  DT_HIP(hipMemsetAsync(flags.p, 0, 4, st));
+  DT_HIP(hipMemsetAsync(table.p, 0xFF, tsize * 8, st));
+  DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)(GW_MAX_LEVELS + 2) * 4, st));
+  DT_HIP(hipMemsetAsync(pool.set_cell0.p, 0, 4, st));
+  GwState g{P, n, pool.cells.as<Cell>(), (uint32_t)cap, ncells,
+            table.as<unsigned long long>(), (uint32_t)(tsize - 1), flags.as<uint32_t>()};
+  const uint32_t m = n - 1 < GW_NN ? n - 1 : GW_NN;
+  const uint32_t ncomb = D == 2 ? m * (m - 1) / 2 : m * (m - 1) * (m - 2) / 6;
+  hipLaunchKernelGGL(k_gw_nearest, dim3(1), dim3(GW_THREADS), 0, st, P, n, nn.as<uint32_t>());
+  const uint32_t sb = (ncomb * 64 + GW_THREADS - 1) / GW_THREADS;
+#define GW_LAUNCH(K, ...)                                                                 \
+  do {                                                                                    \
+    if (D == 2 && fp32) hipLaunchKernelGGL((K<2, true>), __VA_ARGS__);                    \
+    else if (D == 2) hipLaunchKernelGGL((K<2, false>), __VA_ARGS__);                      \
+    else if (fp32) hipLaunchKernelGGL((K<3, true>), __VA_ARGS__);                         \
+    else hipLaunchKernelGGL((K<3, false>), __VA_ARGS__);                                  \
+  } while (0)
+  GW_LAUNCH(k_gw_seed, dim3(sb), dim3(GW_THREADS), 0, st, P, n, nn.as<uint32_t>(), ncomb,
+            best.as<uint32_t>(), flags.as<uint32_t>());
+  GW_LAUNCH(k_gw_start, dim3(1), dim3(64), 0, st, g, nn.as<uint32_t>(), best.as<uint32_t>(),
+            fa.as<uint32_t>(), cnt.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  uint32_t lev = 0;
+  for (;;) {
+    for (uint32_t r = 0; r < GW_GROUP && lev < GW_MAX_LEVELS; r++, lev++) {
+      const uint32_t* fin = (lev & 1u) ? fb.as<uint32_t>() : fa.as<uint32_t>();
+      uint32_t* fout = (lev & 1u) ? fa.as<uint32_t>() : fb.as<uint32_t>();
+      GW_LAUNCH(k_gw_level, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS), 0, st, g, fin,
+                cnt.as<uint32_t>() + lev, fout, cnt.as<uint32_t>() + lev + 1, (uint32_t)fcap);
+    }
+    DT_HIP(hipGetLastError());
+    uint32_t h[2] = {0, 0};
+    DT_HIP(hipMemcpyAsync(&h[0], cnt.as<uint32_t>() + lev, 4, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipMemcpyAsync(&h[1], flags.p, 4, hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    if (h[1]) return DT_E_NOT_READY;          // no seed, or a capacity: fall back
+    if (h[0] == 0) break;
+    if (lev >= GW_MAX_LEVELS) return DT_E_NOT_READY;
+  }
+#undef GW_LAUNCH
+  uint32_t nc = 0;
+  std::vector<uint32_t> hc(lev + 1);
+  DT_HIP(hipMemcpyAsync(&nc, ncells, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)(lev + 1) * 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  pool.cap = (uint32_t)cap;
+  pool.ncells = nc;
+  // levels that had facets to search
+  uint32_t nl = 0;
+  for (uint32_t x = 0; x <= lev; x++) nl += hc[x] ? 1u : 0u;
+  *levels = nl;
+  return DT_OK;
+}
+
+}  // namespace dtk

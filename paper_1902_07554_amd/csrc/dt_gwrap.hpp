@@ -1,0 +1,20 @@
+// Gift-wrapping triangulation of one small point set (dt_gwrap.hip).
+#pragma once
+#include "dt_internal.hpp"
+
+namespace dtk {
+
+// Sets of at most this many points are gift-wrapped (each facet search
+// reads every point).
+constexpr uint32_t GW_MAX_POINTS = 8192;
+
+// The finite Delaunay simplices of the n points P (D = 2 or 3, indices into
+// P, positively oriented) as live cells of `pool` (vertices only; no
+// neighbour links, no hull cells).  DT_OK: done, *levels = facet levels
+// searched.  DT_E_NOT_READY: not done (too many points, no empty seed
+// simplex among point 0's nearest, or a capacity ran out); the caller
+// triangulates the set by parallel insertion instead.  Synchronises `st`.
+int gift_wrap(const double4* P, uint32_t n, int D, bool fp32, CellPool& pool, uint32_t* levels,
+              hipStream_t st);
+
+}  // namespace dtk

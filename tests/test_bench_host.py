@@ -33,6 +33,8 @@ def test_algorithmic_bytes_per_unit():
     # simplices of 4 vertex and 4 neighbour words of 4 bytes in 3D
     st = _stats(n=1000, k=8, eta=30, vb=200)
     assert bench.inserted_points(st) == 1230
+    # a gift-wrapped sample is not inserted
+    assert bench.inserted_points(dict(st, wrap_levels=25)) == 1200
     assert bench.alg_bytes("k4_cavity", st, 3) == pytest.approx(1230 * 6.77 * 32)
     assert bench.alg_bytes("k4_cavity", _stats(n=1000), 2) == pytest.approx(1000 * 2 * 24)
     # assign 25 B, scatter 53 B per point in 3D (17 and 37 in 2D)

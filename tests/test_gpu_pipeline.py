@@ -283,3 +283,33 @@ def test_recursive_bisection(dtlib, dim, dist, n, k, divide, border):
             blocks = np.bincount(leaf >> (levels - l), minlength=1 << l)
             assert (blocks > 0).all(), (l, blocks)
         assert st["o_dt"] == pytest.approx((n + st["eta"] + st["border_vertices"]) / n)
+
+
+@pytest.mark.parametrize("dim,dist,n,rate,prec", [
+    (3, "bubbles", 200_000, 0.0, "fp32"),      # eta = sqrt(n) = 447
+    (3, "uniform", 400_000, 0.02, "fp64"),     # eta = 8000, near the wrap's limit
+    (2, "normal", 100_000, 0.05, "fp32"),      # eta = 5000
+    (3, "lattice", 8000, 0.25, "fp64"),        # co-spherical and coplanar samples
+    (2, "lattice", 4900, 0.3, "fp32"),
+    (3, "jittered", 8000, 0.25, "fp32"),       # near-ties at 2^-30 grid steps
+])
+def test_sample_triangulation_gift_wrapped(dtlib, dim, dist, n, rate, prec):
+    """The sample's Delaunay triangulation by gift wrapping (one facet
+    search per simplex facet, level by level from an empty seed simplex)
+    equals the oracle's DT of the sample, and the whole run gives the same
+    simplices as with the sample inserted in parallel rounds."""
+    if dist == "lattice":
+        p = inputs.lattice(round(n ** (1.0 / dim)), dim, seed=4)
+    elif dist == "jittered":
+        p = inputs.jittered_lattice(round(n ** (1.0 / dim)), dim, 2.0 ** -30, seed=4)
+    else:
+        p = inputs.make(dist, n, dim, seed=4)
+    print(f"[wrap] dim={dim} dist={dist} n={len(p)} rate={rate} {prec}", flush=True)
+    res = dtlib.triangulate(p, k=16, sample_rate=rate, keep_stages=1, precision=prec)
+    st = res.stats()
+    assert st["wrap_levels"] > 0
+    sid = res.stage("sample").astype(np.int64)
+    assert np.array_equal(oracle.canonical(res.stage("sample_dt")), oracle.delaunay(p[sid], sid))
+    ref = dtlib.triangulate(p, k=16, sample_rate=rate, precision=prec, wrap_sample=-1)
+    assert ref.stats()["wrap_levels"] == 0
+    assert np.array_equal(oracle.canonical(res.rows()), oracle.canonical(ref.rows()))
