@@ -197,7 +197,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     uint32_t wrap = 0;
     int s = DT_E_NOT_READY;
     if (eta <= GW_MAX_POINTS && o.wrap_sample >= 0)
-      s = gift_wrap(Sp.as<double4>(), eta, D, sjob.fp32, spool, &wrap, st);
+      s = gift_wrap(Sp.as<double4>(), eta, D, spool, &wrap, st);
     if (s == DT_E_NOT_READY) {
       K4Stats ks;
       wrap = 0;

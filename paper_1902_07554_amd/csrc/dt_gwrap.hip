@@ -20,12 +20,16 @@
 // flat).
 //
 // Exactness: orientation and the perturbed in-sphere test are the
-// library's predicates (FP32 or FP64 filter, then exact), so the simplices
+// library's predicates (FP64 filter, then exact), so the simplices
 // found are the finite cells of the same perturbed Delaunay triangulation
 // that parallel insertion builds.  The seed is a simplex through point 0
 // and D of its 16 nearest points whose circumsphere holds no point, checked
 // against every point.  When no such simplex is among them, or a capacity
 // runs out, the caller triangulates the set by parallel insertion instead.
+//
+// The FP64 filter comes first here whatever the run's precision: the
+// tests that decide a facet compare nearly cospherical candidates, where the
+// FP32 filter often cannot decide and the out-of-line stages would run.
 //
 // Cost: a facet search reads every point, one wavefront per facet, so the
 // work is about D (D+1) / 2 * 6.8 n^2 predicate evaluations in 3D; it is
@@ -33,6 +37,7 @@
 // the number of levels is the depth of the simplices' adjacency graph from
 // the seed (tens for a few thousand points).
 #include "dt_common.hpp"
+#include "dt_geom.hpp"
 #include "dt_internal.hpp"
 #include "dt_pred.hpp"
 #include "dt_gwrap.hpp"
@@ -49,6 +54,7 @@ constexpr uint32_t GW_MAX_LEVELS = 4096;
 constexpr uint32_t GW_THREADS = 256;        // level kernel: four facets per block
 constexpr uint32_t GW_LEVEL_BLOCKS = 1024;  // grid of the level kernel (a grid-stride loop)
 constexpr uint32_t GW_GROUP = 8;            // levels launched between two reads of the counters
+constexpr uint32_t GW_LDS_POINTS = 2048;    // sets copied into LDS by each level block (64 KB)
 
 // device failure bits of the wrap (any: the caller falls back)
 enum : uint32_t { GW_FAIL_SEED = 1u, GW_FAIL_CAP = 2u, GW_FAIL_HASH = 4u };
@@ -87,6 +93,71 @@ __device__ __forceinline__ void put_slot(PtsX& X, uint32_t i, const double* p,
     }
 }
 
+// The facet's circumcentre cf and squared circumradius r2 (in the facet's
+// hyperplane) and a normal nrm pointing away from the point v on its near
+// side, in FP64.  A sphere through the facet has its centre at cf + s nrm;
+// a point x beyond the facet lies on the one with
+//   s(x) = (|x - cf|^2 - r2) / (2 (x - cf) . nrm),
+// so ordering the points beyond the facet by s(x) orders them along the
+// pencil.  Used only to guess a good first candidate.  False when the
+// facet is too flat to say.
+template <int D>
+__device__ __forceinline__ bool facet_frame(const PtsX& F, uint32_t i, const double4& v,
+                                            double cf[3], double* r2, double nrm[3]) {
+  // the facet's points in slot order (selects, so that they stay in
+  // registers)
+  double a[3], b[3], c[3];
+#pragma unroll
+  for (int x = 0; x < 3; x++) {
+    const int ka = i == 0 ? 1 : 0;
+    const int kb = i <= 1 ? 2 : 1;
+    const int kc = i <= 2 ? 3 : 2;
+    a[x] = ka == 0 ? F.p[0][x] : F.p[1][x];
+    b[x] = kb == 1 ? F.p[1][x] : F.p[2][x];
+    c[x] = D == 3 ? (kc == 2 ? F.p[2][x] : F.p[3][x]) : 0.0;
+  }
+  if (D == 2) {
+    const double ex = b[0] - a[0], ey = b[1] - a[1];
+    cf[0] = 0.5 * (a[0] + b[0]);
+    cf[1] = 0.5 * (a[1] + b[1]);
+    cf[2] = 0.0;
+    *r2 = 0.25 * (ex * ex + ey * ey);
+    nrm[0] = -ey;
+    nrm[1] = ex;
+    nrm[2] = 0.0;
+  } else {
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                          e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l1 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+    const double l2 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    const double nn = nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2];
+    if (!(nn > 1e-20 * l1 * l2)) return false;
+    const double u[3] = {l1 * e2[0] - l2 * e1[0], l1 * e2[1] - l2 * e1[1],
+                         l1 * e2[2] - l2 * e1[2]};
+    const double inv = 0.5 / nn;
+    const double o[3] = {(u[1] * nv[2] - u[2] * nv[1]) * inv, (u[2] * nv[0] - u[0] * nv[2]) * inv,
+                         (u[0] * nv[1] - u[1] * nv[0]) * inv};
+    cf[0] = a[0] + o[0];
+    cf[1] = a[1] + o[1];
+    cf[2] = a[2] + o[2];
+    *r2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+    nrm[0] = nv[0];
+    nrm[1] = nv[1];
+    nrm[2] = nv[2];
+  }
+  const double side = (v.x - cf[0]) * nrm[0] + (v.y - cf[1]) * nrm[1] +
+                      (D == 3 ? (v.z - cf[2]) * nrm[2] : 0.0);
+  if (side == 0.0) return false;
+  if (side > 0.0) {
+    nrm[0] = -nrm[0];
+    nrm[1] = -nrm[1];
+    nrm[2] = -nrm[2];
+  }
+  return true;
+}
+
 // Sorted vertex indices of a simplex packed into one key (16 bits each).
 template <int D>
 __device__ __forceinline__ unsigned long long simplex_key(const uint4& v) {
@@ -112,8 +183,8 @@ __device__ __forceinline__ uint32_t key_hash(unsigned long long k) {
 }
 
 // Sign of the orientation of the simplex v (D+1 vertex indices).
-template <int D, bool F32>
-__device__ __forceinline__ int simplex_orient(const double4* P, PredT<F32>& pr, const uint4& v) {
+template <int D>
+__device__ __forceinline__ int simplex_orient(const double4* P, PredT<false>& pr, const uint4& v) {
   PtsX X;
 #pragma unroll
   for (int i = 0; i <= D; i++) gw_load(P, vget(v, i), X.p[i], X.key[i]);
@@ -122,8 +193,8 @@ __device__ __forceinline__ int simplex_orient(const double4* P, PredT<F32>& pr, 
 
 // Is point q strictly inside the circumsphere of the positively oriented
 // simplex v (perturbed)?
-template <int D, bool F32>
-__device__ __forceinline__ bool in_sphere(const double4* P, PredT<F32>& pr, const uint4& v,
+template <int D>
+__device__ __forceinline__ bool in_sphere(const double4* P, PredT<false>& pr, const uint4& v,
                                           uint32_t q) {
   PtsX X;
 #pragma unroll
@@ -132,47 +203,37 @@ __device__ __forceinline__ bool in_sphere(const double4* P, PredT<F32>& pr, cons
   return pr.template insphere<D>(X) > 0;
 }
 
-// The GW_NN points nearest to point 0 (by squared distance, then index),
-// one block: GW_NN rounds of a block-wide minimum.
+// GW_NN points near point 0, one block: the nearest point of each thread's
+// share (by squared distance rounded to FP32, then index), and of those
+// the GW_NN smallest by rank.  Any near points do: they only propose seeds,
+// each checked exactly.
 __global__ void k_gw_nearest(const double4* P, uint32_t n, uint32_t* nn) {
-  __shared__ unsigned long long s_best[GW_THREADS / 64];
-  __shared__ uint32_t s_taken[GW_NN];
+  __shared__ unsigned long long s_key[GW_THREADS];
   const double4 o = P[0];
-  const uint32_t want = n - 1 < GW_NN ? n - 1 : GW_NN;
-  for (uint32_t r = 0; r < want; r++) {
-    unsigned long long best = ~0ull;
-    for (uint32_t j = 1 + threadIdx.x; j < n; j += blockDim.x) {
-      bool taken = false;
-      for (uint32_t t = 0; t < r; t++) taken |= (s_taken[t] == j);
-      if (taken) continue;
-      const double4 q = P[j];
-      const double dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
-      const float d2 = (float)(dx * dx + dy * dy + dz * dz);
-      // distance rounded to FP32 and the index: any GW_NN near points do
-      const unsigned long long k = ((unsigned long long)__float_as_uint(d2) << 32) | j;
-      best = k < best ? k : best;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long x = __shfl_xor(best, off, 64);
-      best = x < best ? x : best;
-    }
-    if ((threadIdx.x & 63u) == 0) s_best[threadIdx.x / 64] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long b = s_best[0];
-      for (uint32_t w = 1; w < blockDim.x / 64; w++) b = s_best[w] < b ? s_best[w] : b;
-      s_taken[r] = (uint32_t)(b & 0xFFFFFFFFull);
-      nn[r] = s_taken[r];
-    }
-    __syncthreads();
+  unsigned long long best = ~0ull;
+  for (uint32_t j = 1 + threadIdx.x; j < n; j += GW_THREADS) {
+    const double4 q = P[j];
+    const double dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
+    const float d2 = (float)(dx * dx + dy * dy + dz * dz);
+    const unsigned long long k = ((unsigned long long)__float_as_uint(d2) << 32) | j;
+    best = k < best ? k : best;
   }
-  if (threadIdx.x == 0) nn[GW_NN] = want;
+  s_key[threadIdx.x] = best;
+  __syncthreads();
+  uint32_t rank = 0, real = 0;
+  for (uint32_t t = 0; t < GW_THREADS; t++) {
+    const unsigned long long x = s_key[t];
+    rank += x < best ? 1u : 0u;
+    real += x != ~0ull ? 1u : 0u;
+  }
+  if (best != ~0ull && rank < GW_NN) nn[rank] = (uint32_t)(best & 0xFFFFFFFFull);
+  if (threadIdx.x == 0) nn[GW_NN] = real < GW_NN ? real : GW_NN;
 }
 
 // Candidate seed simplex c: point 0 and D of the near points (combination
 // number c in lexicographic order), positively oriented; false when flat.
-template <int D, bool F32>
-__device__ bool seed_candidate(const double4* P, PredT<F32>& pr, const uint32_t* nn,
+template <int D>
+__device__ bool seed_candidate(const double4* P, PredT<false>& pr, const uint32_t* nn,
                                uint32_t m, uint32_t c, uint4& v) {
   uint32_t idx[3] = {0, 0, 0};
   uint32_t left = c;
@@ -193,7 +254,7 @@ __device__ bool seed_candidate(const double4* P, PredT<F32>& pr, const uint32_t*
   }
   if (!found) return false;
   v = make_uint4(0u, nn[idx[0]], nn[idx[1]], D == 3 ? nn[idx[2]] : NOSLOT);
-  const int o = simplex_orient<D, F32>(P, pr, v);
+  const int o = simplex_orient<D>(P, pr, v);
   if (o == 0) return false;
   if (o < 0) {
     const uint32_t t = v.y;
@@ -205,23 +266,33 @@ __device__ bool seed_candidate(const double4* P, PredT<F32>& pr, const uint32_t*
 
 // One wavefront per candidate seed: is its circumsphere empty of every
 // point?  The smallest empty candidate's number is kept.
-template <int D, bool F32>
+template <int D>
 __global__ void k_gw_seed(const double4* P, uint32_t n, const uint32_t* nn, uint32_t ncomb,
                           uint32_t* best, uint32_t* flags) {
-  PredT<F32> pr;
+  PredT<false> pr;
   pr.init(flags);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
   if (c >= ncomb) return;
   const uint32_t m = nn[GW_NN];
   uint4 v;
-  if (!seed_candidate<D, F32>(P, pr, nn, m, c, v)) return;
+  if (!seed_candidate<D>(P, pr, nn, m, c, v)) return;
+  // only points inside the conservatively enlarged circumball can be
+  // strictly inside the sphere (a nearly flat candidate tests them all)
+  double sc[3] = {0.0, 0.0, 0.0}, sr = 0.0;
+  const bool ball = circumball<D>(P[v.x], P[v.y], P[v.z], P[D == 3 ? v.w : v.z], sc, &sr);
+  const double sr2 = sr * sr;
   bool hit = false;
   for (uint32_t q = lane; q < n && !hit; q += 64) {
+    if (ball) {
+      const double4 t = P[q];
+      const double dx = t.x - sc[0], dy = t.y - sc[1], dz = t.z - sc[2];
+      if (dx * dx + dy * dy + dz * dz > sr2) continue;
+    }
     bool vert = false;
 #pragma unroll
     for (int i = 0; i <= D; i++) vert |= (vget(v, i) == q);
-    if (!vert && in_sphere<D, F32>(P, pr, v, q)) hit = true;
+    if (!vert && in_sphere<D>(P, pr, v, q)) hit = true;
   }
   if (__ballot(hit) == 0ull && lane == 0) atomicMin(best, c);
 }
@@ -271,7 +342,7 @@ __device__ bool gw_record(const GwState& g, const uint4& v, uint32_t* idx) {
 }
 
 // The seed simplex becomes cell 0; its D+1 facets form the first level.
-template <int D, bool F32>
+template <int D>
 __global__ void k_gw_start(GwState g, const uint32_t* nn, const uint32_t* best,
                            uint32_t* front, uint32_t* cnt) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -279,10 +350,10 @@ __global__ void k_gw_start(GwState g, const uint32_t* nn, const uint32_t* best,
     atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
     return;
   }
-  PredT<F32> pr;
+  PredT<false> pr;
   pr.init(g.flags);
   uint4 v;
-  if (!seed_candidate<D, F32>(g.P, pr, nn, nn[GW_NN], *best, v)) {
+  if (!seed_candidate<D>(g.P, pr, nn, nn[GW_NN], *best, v)) {
     atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
     return;
   }
@@ -299,16 +370,27 @@ __global__ void k_gw_start(GwState g, const uint32_t* nn, const uint32_t* best,
 // simplex beyond it; a simplex not found before is recorded and its other
 // D facets go to the output list.  Facet (c, i) is the facet of cell c
 // opposite its vertex i, searched away from that vertex.
-template <int D, bool F32>
+// With LDS (sets of at most GW_LDS_POINTS points) the block first copies
+// every point into LDS: a facet search is then a chain of LDS reads rather
+// than of L2 loads.
+template <int D, bool LDS>
 __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32_t* fin,
                                                          const uint32_t* cnt_in, uint32_t* fout,
                                                          uint32_t* cnt_out, uint32_t fcap) {
+  extern __shared__ double4 s_pts[];
   const uint32_t nin = *cnt_in;
   if (nin == 0 || *g.flags) return;
-  PredT<F32> pr;
+  const uint32_t wpb = GW_THREADS / 64;
+  if (blockIdx.x * wpb >= nin) return;
+  const double4* PP = g.P;
+  if (LDS) {
+    for (uint32_t j = threadIdx.x; j < g.n; j += GW_THREADS) s_pts[j] = g.P[j];
+    __syncthreads();
+    PP = s_pts;
+  }
+  PredT<false> pr;
   pr.init(g.flags);
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wpb = GW_THREADS / 64;
   for (uint32_t e = blockIdx.x * wpb + threadIdx.x / 64; e < nin; e += gridDim.x * wpb) {
     const uint32_t ent = fin[e];
     const uint32_t c = ent >> 2, i = ent & 3u;
@@ -327,34 +409,123 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
     for (int k = 0; k <= D; k++) {
       F.p[k][0] = F.p[k][1] = F.p[k][2] = 0.0;
       F.key[k] = 0;
-      if (k != (int)i) gw_load(g.P, vget(t, k), F.p[k], F.key[k]);
+      if (k != (int)i) gw_load(PP, vget(t, k), F.p[k], F.key[k]);
     }
-    // this lane's first candidate along the pencil, over its share
+    // A first candidate: the least pencil parameter in FP64 over all
+    // points beyond the facet (a guess; the exact order decides below).
+    uint32_t guess = GW_NONE;
+    {
+      double cf[3], r2, nrm[3];
+      if (facet_frame<D>(F, i, PP[vget(t, (int)i)], cf, &r2, nrm)) {
+        double bnum = 0.0, bden = 1.0;
+        for (uint32_t q0 = lane; q0 < g.n; q0 += 4 * 64) {
+          double4 cp[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const uint32_t q = q0 + 64u * (uint32_t)u;
+            cp[u] = PP[q < g.n ? q : 0u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const uint32_t q = q0 + 64u * (uint32_t)u;
+            const double wx = cp[u].x - cf[0], wy = cp[u].y - cf[1], wz = cp[u].z - cf[2];
+            const double h = wx * nrm[0] + wy * nrm[1] + (D == 3 ? wz * nrm[2] : 0.0);
+            if (q >= g.n || !(h > 0.0)) continue;
+            // the facet's own points lie on its hyperplane (h is rounding)
+            bool vert = false;
+#pragma unroll
+            for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
+            if (vert) continue;
+            const double num = (wx * wx + wy * wy + (D == 3 ? wz * wz : 0.0)) - r2;
+            if (guess == GW_NONE || num * bden < bnum * h) {
+              guess = q;
+              bnum = num;
+              bden = h;
+            }
+          }
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const uint32_t oq = __shfl_xor(guess, off, 64);
+          const double on = __shfl_xor(bnum, off, 64), od = __shfl_xor(bden, off, 64);
+          if (oq != GW_NONE && (guess == GW_NONE || on * bden < bnum * od)) {
+            guess = oq;
+            bnum = on;
+            bden = od;
+          }
+        }
+        guess = __shfl(guess, 0, 64);
+      }
+    }
+    // The exact scan starts from the guess when it lies strictly beyond the
+    // facet: a point outside the conservatively enlarged ball through the
+    // facet and the current candidate cannot come before it (it is not
+    // strictly inside the sphere), so only points inside the ball are
+    // tested.  Points are loaded four at a time, ahead of the tests.
     uint32_t best = GW_NONE;
     double bp[3] = {0.0, 0.0, 0.0};
     unsigned long long bk = 0;
-    for (uint32_t q = lane; q < g.n; q += 64) {
-      bool vert = false;
-#pragma unroll
-      for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
-      if (vert) continue;
+    bool ball = false;
+    double sc[3] = {0.0, 0.0, 0.0}, sr2 = 0.0;
+    if (guess != GW_NONE) {
       double qp[3];
       unsigned long long qk;
-      gw_load(g.P, q, qp, qk);
+      gw_load(PP, guess, qp, qk);
       PtsX X = F;
       put_slot<D>(X, i, qp, qk);
-      if (pr.template orient<D>(X) <= 0) continue;
-      bool take = best == GW_NONE;
-      if (!take) {
-        put_slot<D>(X, i, bp, bk);
-        X.p[D + 1][0] = qp[0]; X.p[D + 1][1] = qp[1]; X.p[D + 1][2] = qp[2];
-        X.key[D + 1] = qk;
-        take = pr.template insphere<D>(X) > 0;
-      }
-      if (take) {
-        best = q;
+      if (pr.template orient<D>(X) > 0) {
+        best = guess;
         bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
         bk = qk;
+        uint4 tq = t;
+        vput(tq, (int)i, guess);
+        double r = 0.0;
+        ball = circumball<D>(PP[tq.x], PP[tq.y], PP[tq.z], PP[D == 3 ? tq.w : tq.z], sc, &r);
+        sr2 = r * r;
+      }
+    }
+    for (uint32_t q0 = lane; q0 < g.n; q0 += 4 * 64) {
+      double4 cp[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t q = q0 + 64u * (uint32_t)u;
+        cp[u] = PP[q < g.n ? q : 0u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t q = q0 + 64u * (uint32_t)u;
+        if (q >= g.n || q == best) continue;
+        if (ball) {
+          const double dx = cp[u].x - sc[0], dy = cp[u].y - sc[1], dz = cp[u].z - sc[2];
+          if (dx * dx + dy * dy + dz * dz > sr2) continue;
+        }
+        bool vert = false;
+#pragma unroll
+        for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
+        if (vert) continue;
+        const double qp[3] = {cp[u].x, cp[u].y, cp[u].z};
+        const unsigned long long qk = (unsigned long long)__double_as_longlong(cp[u].w);
+        PtsX X = F;
+        put_slot<D>(X, i, qp, qk);
+        if (pr.template orient<D>(X) <= 0) continue;
+        bool take = best == GW_NONE;
+        if (!take) {
+          put_slot<D>(X, i, bp, bk);
+          X.p[D + 1][0] = qp[0]; X.p[D + 1][1] = qp[1]; X.p[D + 1][2] = qp[2];
+          X.key[D + 1] = qk;
+          take = pr.template insphere<D>(X) > 0;
+        }
+        if (take) {
+          best = q;
+          bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
+          bk = qk;
+          uint4 tq = t;
+          vput(tq, (int)i, q);
+          double r = 0.0;
+          ball = circumball<D>(PP[tq.x], PP[tq.y], PP[tq.z], PP[D == 3 ? tq.w : tq.z], sc,
+                               &r);
+          sr2 = r * r;
+        }
       }
     }
     // the wavefront's first candidate: a minimum over the lanes under the
@@ -365,7 +536,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
       if (o == GW_NONE || o == best) continue;
       double op[3];
       unsigned long long ok;
-      gw_load(g.P, o, op, ok);
+      gw_load(PP, o, op, ok);
       bool take = best == GW_NONE;
       if (!take) {
         PtsX X = F;
@@ -399,7 +570,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
 
 }  // namespace
 
-int gift_wrap(const double4* P, uint32_t n, int D, bool fp32, CellPool& pool, uint32_t* levels,
+int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* levels,
               hipStream_t st) {
   *levels = 0;
   if (n < (uint32_t)D + 2 || n > GW_MAX_POINTS || (D != 2 && D != 3)) return DT_E_NOT_READY;
@@ -432,10 +603,13 @@ int gift_wrap(const double4* P, uint32_t n, int D, bool fp32, CellPool& pool, ui
   const uint32_t sb = (ncomb * 64 + GW_THREADS - 1) / GW_THREADS;
 #define GW_LAUNCH(K, ...)                                                                 \
   do {                                                                                    \
-    if (D == 2 && fp32) hipLaunchKernelGGL((K<2, true>), __VA_ARGS__);                    \
-    else if (D == 2) hipLaunchKernelGGL((K<2, false>), __VA_ARGS__);                      \
-    else if (fp32) hipLaunchKernelGGL((K<3, true>), __VA_ARGS__);                         \
-    else hipLaunchKernelGGL((K<3, false>), __VA_ARGS__);                                  \
+    if (D == 2) hipLaunchKernelGGL((K<2>), __VA_ARGS__);                                  \
+    else hipLaunchKernelGGL((K<3>), __VA_ARGS__);                                         \
+  } while (0)
+#define GW_LAUNCH_LDS(K, L, ...)                                                          \
+  do {                                                                                    \
+    if (D == 2) hipLaunchKernelGGL((K<2, L>), __VA_ARGS__);                               \
+    else hipLaunchKernelGGL((K<3, L>), __VA_ARGS__);                                      \
   } while (0)
   GW_LAUNCH(k_gw_seed, dim3(sb), dim3(GW_THREADS), 0, st, P, n, nn.as<uint32_t>(), ncomb,
             best.as<uint32_t>(), flags.as<uint32_t>());
@@ -447,8 +621,14 @@ int gift_wrap(const double4* P, uint32_t n, int D, bool fp32, CellPool& pool, ui
     for (uint32_t r = 0; r < GW_GROUP && lev < GW_MAX_LEVELS; r++, lev++) {
       const uint32_t* fin = (lev & 1u) ? fb.as<uint32_t>() : fa.as<uint32_t>();
       uint32_t* fout = (lev & 1u) ? fa.as<uint32_t>() : fb.as<uint32_t>();
-      GW_LAUNCH(k_gw_level, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS), 0, st, g, fin,
-                cnt.as<uint32_t>() + lev, fout, cnt.as<uint32_t>() + lev + 1, (uint32_t)fcap);
+      if (n <= GW_LDS_POINTS)
+        GW_LAUNCH_LDS(k_gw_level, true, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS),
+                      (size_t)n * sizeof(double4), st, g, fin, cnt.as<uint32_t>() + lev, fout,
+                      cnt.as<uint32_t>() + lev + 1, (uint32_t)fcap);
+      else
+        GW_LAUNCH_LDS(k_gw_level, false, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS), 0, st, g, fin,
+                      cnt.as<uint32_t>() + lev, fout, cnt.as<uint32_t>() + lev + 1,
+                      (uint32_t)fcap);
     }
     DT_HIP(hipGetLastError());
     uint32_t h[2] = {0, 0};
@@ -460,6 +640,7 @@ int gift_wrap(const double4* P, uint32_t n, int D, bool fp32, CellPool& pool, ui
     if (lev >= GW_MAX_LEVELS) return DT_E_NOT_READY;
   }
 #undef GW_LAUNCH
+#undef GW_LAUNCH_LDS
   uint32_t nc = 0;
   std::vector<uint32_t> hc(lev + 1);
   DT_HIP(hipMemcpyAsync(&nc, ncells, 4, hipMemcpyDeviceToHost, st));

@@ -14,7 +14,7 @@ constexpr uint32_t GW_MAX_POINTS = 8192;
 // searched.  DT_E_NOT_READY: not done (too many points, no empty seed
 // simplex among point 0's nearest, or a capacity ran out); the caller
 // triangulates the set by parallel insertion instead.  Synchronises `st`.
-int gift_wrap(const double4* P, uint32_t n, int D, bool fp32, CellPool& pool, uint32_t* levels,
+int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* levels,
               hipStream_t st);
 
 }  // namespace dtk
