@@ -275,15 +275,18 @@ constexpr uint32_t NB_STRIPES = 64;   // copies of the border-simplex counter
 
 // The test of one live cell c: flag it, and its vertices (vbflag), when
 // its circumsphere may reach another partition.  finite: no vertex is the
-// infinite one.  vis: the thread's slots in the walk's LDS list.
+// infinite one.  vis: the thread's slots in the walk's LDS list.  defer:
+// a cell whose Voronoi test needs the walk over the sample's graph is left
+// undecided (walk = true, nothing written) for a second pass.
 template <int D>
 __device__ __forceinline__ void border_cell(const double4* P, const uint32_t* pset,
                                             const Cell* cells, uint32_t c, const BGrid& G,
                                             const uint32_t* owner, const Region& R,
                                             uint32_t* vbflag, uint32_t* flags, uint32_t* vis,
-                                            bool& flag, bool& finite) {
+                                            bool defer, bool& flag, bool& finite, bool& walk) {
   flag = false;
   finite = false;
+  walk = false;
   uint4 v4 = cells[c].v;
   uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
   bool inf = false;
@@ -303,6 +306,10 @@ __device__ __forceinline__ void border_cell(const double4* P, const uint32_t* ps
       double m = R.margin[v[0]];
 #pragma unroll
       for (int i = 1; i <= D; i++) m = fmax(m, R.margin[v[i]]);
+      if (!(m > 2.0 * r) && defer) {
+        walk = true;
+        return;
+      }
       if (!(m > 2.0 * r)) {
         // the own sample nearest the centre among the vertices' samples
         uint32_t t = 0xFFFFFFFFu;
@@ -447,12 +454,35 @@ __global__ void k_border(const double4* P, const uint32_t* pset, const Cell* cel
   uint32_t* live = s_live[w];
   const uint32_t nlive = list_live(cells, ncells, tile0, lane, live);
   unsigned long long cnt = 0;
+  // First pass: every cell the cheap tests decide; the cells whose Voronoi
+  // test needs the walk are listed again (at the front of the same list,
+  // behind the entries already read) and walked in a second pass with all
+  // lanes.
+  uint32_t nwalk = 0;
   for (uint32_t b = 0; b < nlive; b += 64) {
-    bool flag = false, finite = false;
+    bool flag = false, finite = false, walk = false;
+    uint32_t c = 0;
     if (b + lane < nlive) {
+      c = live[b + lane];
+      border_cell<D>(P, pset, cells, c, G, owner, R, vbflag, flags, s_vis + threadIdx.x, true,
+                     flag, finite, walk);
+      const uint32_t o = c - tile0;
+      if (finite && !walk)
+        atomicOr(flag ? &s_hm[w][o >> 6] : &s_em[w][o >> 6], 1ull << (o & 63u));
+    }
+    cnt += (unsigned long long)__popcll(__ballot(flag && finite));
+    const unsigned long long m = __ballot(walk);
+    wave_sync_lds();
+    if (walk) live[nwalk + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = c;
+    nwalk += (uint32_t)__popcll(m);
+    wave_sync_lds();
+  }
+  for (uint32_t b = 0; b < nwalk; b += 64) {
+    bool flag = false, finite = false, walk = false;
+    if (b + lane < nwalk) {
       const uint32_t c = live[b + lane];
-      border_cell<D>(P, pset, cells, c, G, owner, R, vbflag, flags, s_vis + threadIdx.x, flag,
-                     finite);
+      border_cell<D>(P, pset, cells, c, G, owner, R, vbflag, flags, s_vis + threadIdx.x, false,
+                     flag, finite, walk);
       const uint32_t o = c - tile0;
       if (finite) atomicOr(flag ? &s_hm[w][o >> 6] : &s_em[w][o >> 6], 1ull << (o & 63u));
     }
