@@ -110,11 +110,13 @@ typedef struct dt_options {
    * merges bottom-up with the grid test; k must be a power of two.
    * 0 (default): one k-way division and one merge (Algorithm 1). */
   int recursive;
-  /* Triangulation of the sample (sample divide, one k-way division): 0
-   * (default) gift-wraps samples of at most 8192 points and inserts larger
-   * ones in parallel rounds; -1 always inserts in parallel rounds.  Both
-   * give the same simplices (timing only). */
-  int wrap_sample;
+  /* Gift wrapping where it pays (timing only; the simplices are the same):
+   * 0 (default) gift-wraps the sample of the sample divide when it has at
+   * most 8192 points, and starts every single set of at least 65,536 points
+   * (the border set, a direct triangulation) from the gift-wrapped
+   * triangulation of its first 4096 or so points in insertion order; -1
+   * inserts every point in parallel rounds. */
+  int gift_wrap;
 } dt_options;
 
 /* Kernels timed when dt_options.profile = 1. */
@@ -157,6 +159,7 @@ typedef struct dt_stats {
                                  per-candidate lists and used a pool-sized list   */
   int64_t wrap_levels;        /* facet levels of the gift-wrapped sample
                                  triangulation (0: parallel insertion)           */
+  int64_t seeded_sets;        /* single sets started from a gift-wrapped seed     */
 } dt_stats;
 
 typedef struct dt_result dt_result;

@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("border", ctypes.c_int), ("profile", ctypes.c_int),
                 ("start_active", ctypes.c_int), ("grow_div", ctypes.c_int),
                 ("cand_blocks", ctypes.c_int), ("grow_num", ctypes.c_int),
-                ("recursive", ctypes.c_int), ("wrap_sample", ctypes.c_int)]
+                ("recursive", ctypes.c_int), ("gift_wrap", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
                 ("kern_launches", ctypes.c_int64 * 8), ("cavity_cells", ctypes.c_int64),
                 ("candidates", ctypes.c_int64),
                 ("divide_used", ctypes.c_int64), ("divide_stat", ctypes.c_double),
-                ("large_cavities", ctypes.c_int64), ("wrap_levels", ctypes.c_int64)]
+                ("large_cavities", ctypes.c_int64), ("wrap_levels", ctypes.c_int64),
+                ("seeded_sets", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_

@@ -315,7 +315,7 @@ int check_options(const dt_options* in, dt_options& o) {
   if (o.cand_blocks < 0 || o.cand_blocks > (1 << 20)) return DT_E_INVALID_ARG;
   if (o.grow_num != 0 && (o.grow_num < 9 || o.grow_num > 32)) return DT_E_INVALID_ARG;
   if (o.recursive != 0 && o.recursive != 1) return DT_E_INVALID_ARG;
-  if (o.wrap_sample != 0 && o.wrap_sample != -1) return DT_E_INVALID_ARG;
+  if (o.gift_wrap != 0 && o.gift_wrap != -1) return DT_E_INVALID_ARG;
   return DT_OK;
 }
 

@@ -93,6 +93,7 @@ static void add_pred(dt_stats& s, const K4Stats& ks) {
     for (int j = 0; j < 4; j++) s.pred[i][j] += (int64_t)ks.pred[i][j];
   s.rounds += ks.rounds;
   s.large_cavities += ks.giant_rounds;
+  s.seeded_sets += ks.seeded;
   s.cavity_cells += (int64_t)ks.cavity_cells;
   s.candidates += (int64_t)ks.candidates;
 }
@@ -196,7 +197,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
     // one the wrap declines, is triangulated by parallel insertion
     uint32_t wrap = 0;
     int s = DT_E_NOT_READY;
-    if (eta <= GW_MAX_POINTS && o.wrap_sample >= 0)
+    if (eta <= GW_MAX_POINTS && o.gift_wrap >= 0)
       s = gift_wrap(Sp.as<double4>(), eta, D, spool, &wrap, st);
     if (s == DT_E_NOT_READY) {
       K4Stats ks;

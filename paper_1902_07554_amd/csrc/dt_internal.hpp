@@ -186,7 +186,9 @@ struct LocalJob {
   uint32_t grow_div = 64;         // next level when pending < inserted / grow_div
   uint32_t cand_blocks = 32768;   // cap on cavity/insert wavefronts
   uint32_t grow_num = 0;          // threshold growth per level in eighths; 0: by set count
+  bool seed = true;               // a large single set starts from a gift-wrapped seed
   void tune(const dt_options& o) {
+    seed = o.gift_wrap >= 0;
     if (o.start_active > 0) start_active = (uint32_t)o.start_active;
     if (o.grow_div > 0) grow_div = (uint32_t)o.grow_div;
     if (o.cand_blocks > 0) cand_blocks = (uint32_t)o.cand_blocks;
@@ -209,6 +211,7 @@ struct K4Stats {
   unsigned long long verified = 0;    // cavity searches that completed
   int rounds = 0;
   uint32_t giant_rounds = 0;   // rounds in which a cavity used the pool-sized list
+  uint32_t seeded = 0;         // 1: the set started from a gift-wrapped seed
   uint32_t maxcav = 0;
   unsigned long long pred[4][4] = {};
 };

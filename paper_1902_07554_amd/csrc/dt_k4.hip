@@ -41,6 +41,7 @@
 #include "dt_pred.hpp"
 #include "dt_block.hpp"
 #include "dt_prims.hpp"
+#include "dt_gwrap.hpp"
 
 #include <stdio.h>
 #include <stdlib.h>
@@ -1355,6 +1356,262 @@ __global__ void k4_reset_claims(Cell* cells, uint32_t used) {
   cells[c].shell = NOKEY;
 }
 
+// ------------------------------------------------------------ seeded start
+// A single large set starts from the Delaunay triangulation of its first
+// points in priority order, built by gift wrapping (dt_gwrap.hip), instead
+// of from one simplex.  Parallel insertion spends its first hundred-odd
+// rounds on those points (while the triangulation has few cells, the
+// cavities of the candidates overlap and a round inserts a point or two),
+// each round a chain of dependent gathers.  The seed's simplices get their
+// neighbour links by matching facets, and every hull facet gets a hull cell
+// (the infinite vertex and the facet), linked to its neighbours across the
+// hull's ridges, exactly as the insertion keeps them.  The seed points are
+// then inserted; the rest continue in activation levels above them.
+constexpr uint32_t SEED_POINTS = 4096;     // expected seed size
+constexpr uint32_t SEED_MIN_SET = 65536;   // smaller single sets start from one simplex
+constexpr uint32_t SEED_KEY_BITS = 21;     // facet keys: three seed-point indices of 21 bits
+
+// The points below the priority threshold T, gathered.
+__global__ void k_seed_pick(uint32_t npts, uint32_t T, const double4* pts, uint32_t* cnt,
+                            uint32_t* sidx, double4* spts, uint32_t cap) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts || prio_of(p) >= T) return;
+  const uint32_t i = atomicAdd(cnt, 1u);
+  if (i < cap) {
+    sidx[i] = p;
+    spts[i] = pts[p];
+  }
+}
+
+// The wrapped simplices as cells of the pool (vertex indices of the job),
+// their vertices inserted.
+template <int D>
+__global__ void k_seed_cells(const Cell* wc, uint32_t nf, const uint32_t* sidx, Cell* cells,
+                             unsigned long long* bid, uint32_t* vcell, uint32_t* ploc) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nf) return;
+  uint4 v = wc[c].v;
+#pragma unroll
+  for (int i = 0; i <= D; i++) vset(v, i, sidx[vat(v, i)]);
+  if (D == 2) v.w = NOSLOT;
+  Cell& x = cells[c];
+  x.v = v;
+  x.n = make_uint4(0u, 0u, 0u, D == 2 ? NOSLOT : 0u);
+  x.spare = 0;
+  x.cav = NOKEY;
+  x.shell = NOKEY;
+  x.fwd = ALIVE;
+  x.pos = 0;
+  bid[c] = NOKEY;
+#pragma unroll
+  for (int i = 0; i <= D; i++) {
+    vcell[vat(v, i)] = c;
+    ploc[vat(v, i)] = DONE;
+  }
+}
+
+// Facet and ridge tables: a key and the (cell << 2 | slot) of the two cells
+// that share it.
+struct SeedTab {
+  unsigned long long* key;
+  uint32_t* e0;
+  uint32_t* e1;
+  uint32_t mask;
+};
+
+__device__ __forceinline__ void seed_tab_put(const SeedTab& t, unsigned long long key,
+                                             uint32_t val, uint32_t* flags) {
+  uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 32);
+  for (uint32_t pr = 0; pr <= t.mask; pr++) {
+    const uint32_t s = (h + pr) & t.mask;
+    const unsigned long long old = atomicCAS(&t.key[s], ~0ull, key);
+    if (old == ~0ull) { t.e0[s] = val; return; }
+    if (old == key) { t.e1[s] = val; return; }
+  }
+  atomicOr(flags, FAIL_HASH);
+}
+
+// Key of the facet of cell vertices v (indices into the seed's points)
+// opposite slot i: the sorted finite indices (the infinite vertex is left
+// out; hull ridges have their own table).
+template <int D>
+__device__ __forceinline__ unsigned long long seed_key(const uint4& v, int i) {
+  uint32_t k[3] = {0u, 0u, 0u};
+  int m = 0;
+#pragma unroll
+  for (int j = 0; j <= D; j++)
+    if (j != i && vat(v, j) != INF_V) {
+      if (m == 0) k[0] = vat(v, j);
+      else if (m == 1) k[1] = vat(v, j);
+      else k[2] = vat(v, j);
+      m++;
+    }
+  if (m == 1) return (unsigned long long)k[0];
+  if (k[1] < k[0]) { const uint32_t t = k[0]; k[0] = k[1]; k[1] = t; }
+  if (m == 3) {
+    if (k[2] < k[1]) { const uint32_t t = k[1]; k[1] = k[2]; k[2] = t; }
+    if (k[1] < k[0]) { const uint32_t t = k[0]; k[0] = k[1]; k[1] = t; }
+    return ((unsigned long long)k[0] << (2 * SEED_KEY_BITS)) |
+           ((unsigned long long)k[1] << SEED_KEY_BITS) | (unsigned long long)k[2];
+  }
+  return ((unsigned long long)k[0] << 32) | (unsigned long long)k[1];
+}
+
+template <int D>
+__global__ void k_seed_facets(const Cell* wc, uint32_t nf, SeedTab t, uint32_t* flags) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t c = x / (D + 1), i = x % (D + 1);
+  if (c >= nf) return;
+  seed_tab_put(t, seed_key<D>(wc[c].v, (int)i), (c << 2) | i, flags);
+}
+
+// Twin facets link their cells; a facet without a twin is on the hull and
+// gets a hull cell (the facet with the infinite vertex in slot i and two
+// other slots swapped, as the first cells of a set are made), whose
+// ridges go to the ridge table.
+template <int D>
+__global__ void k_seed_link(const Cell* wc, const uint32_t* sidx, Cell* cells, SeedTab t,
+                            SeedTab r, uint32_t* ncells, uint32_t cap, unsigned long long* bid,
+                            uint32_t* flags) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > t.mask || t.key[s] == ~0ull) return;
+  const uint32_t a = t.e0[s], b = t.e1[s];
+  if (b != DONE) {
+    *nslot(cells, a >> 2, a & 3u) = b;
+    *nslot(cells, b >> 2, b & 3u) = a;
+    return;
+  }
+  const uint32_t c = a >> 2, i = a & 3u;
+  const uint32_t h = atomicAdd(ncells, 1u);
+  if (h >= cap) {
+    atomicOr(flags, FAIL_CELL_POOL);
+    return;
+  }
+  // in seed indices (for the ridge keys), then in job indices
+  uint4 w = wc[c].v;
+  vset(w, (int)i, INF_V);
+  const int x = (i == 0) ? 1 : 0, y = (i <= 1) ? 2 : 1;
+  const uint32_t tv = vat(w, x);
+  vset(w, x, vat(w, y));
+  vset(w, y, tv);
+  uint4 wj = w;
+#pragma unroll
+  for (int j = 0; j <= D; j++)
+    if (vat(w, j) != INF_V) vset(wj, j, sidx[vat(w, j)]);
+  if (D == 2) wj.w = NOSLOT;
+  Cell& hc = cells[h];
+  hc.v = wj;
+  hc.n = make_uint4(0u, 0u, 0u, D == 2 ? NOSLOT : 0u);
+  hc.spare = 0;
+  hc.cav = NOKEY;
+  hc.shell = NOKEY;
+  hc.fwd = ALIVE;
+  hc.pos = 0;
+  bid[h] = NOKEY;
+  *nslot(cells, h, i) = a;
+  *nslot(cells, c, i) = (h << 2) | i;
+#pragma unroll
+  for (int j = 0; j <= D; j++)
+    if (j != (int)i) seed_tab_put(r, seed_key<D>(w, j), (h << 2) | (uint32_t)j, flags);
+}
+
+// Hull cells that share a ridge link to each other.
+__global__ void k_seed_ridges(Cell* cells, SeedTab r, uint32_t* flags) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > r.mask || r.key[s] == ~0ull) return;
+  const uint32_t a = r.e0[s], b = r.e1[s];
+  if (b == DONE) {
+    atomicOr(flags, FAIL_INVARIANT);
+    return;
+  }
+  *nslot(cells, a >> 2, a & 3u) = b;
+  *nslot(cells, b >> 2, b & 3u) = a;
+}
+
+static inline uint32_t nblk(uint32_t n);
+
+// Build the seed of a single set into the pool and the point records
+// (ploc, vcell).  DT_OK: *ncells cells made, *thresh the first activation
+// threshold above the seed; DT_E_NOT_READY: not seeded (the caller starts
+// from one simplex; nothing it uses was written).
+static int seed_single_set(const LocalJob& job, const K4Args& a, uint32_t* ncells,
+                           uint32_t* thresh, hipStream_t st) {
+  const int D = job.D;
+  const uint32_t npts = job.npts;
+  const uint32_t PMAX = 1u << 20;
+  const uint32_t T = (uint32_t)(((uint64_t)PMAX * SEED_POINTS) / npts);
+  const uint32_t scap = GW_MAX_POINTS;
+  DevBuf cnt, sidx, spts, flags;
+  DT_TRY(cnt.alloc(16));
+  DT_TRY(sidx.alloc((size_t)scap * 4));
+  DT_TRY(spts.alloc((size_t)scap * sizeof(double4)));
+  DT_TRY(flags.alloc(16));
+  DT_HIP(hipMemsetAsync(cnt.p, 0, 4, st));
+  DT_HIP(hipMemsetAsync(flags.p, 0, 4, st));
+  hipLaunchKernelGGL(k_seed_pick, dim3(nblk(npts)), dim3(BLOCK), 0, st, npts, T, job.pts,
+                     cnt.as<uint32_t>(), sidx.as<uint32_t>(), spts.as<double4>(), scap);
+  DT_HIP(hipGetLastError());
+  uint32_t m = 0;
+  DT_HIP(hipMemcpyAsync(&m, cnt.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  if (m > scap || m < (uint32_t)D + 2) return DT_E_NOT_READY;
+  CellPool wp;
+  uint32_t levels = 0;
+  const int g = gift_wrap(spts.as<double4>(), m, D, wp, &levels, st);
+  if (g != DT_OK) return g;
+  const uint32_t nf = wp.ncells;
+  if (nf == 0 || (uint64_t)nf * 2 + 64 > a.cap) return DT_E_NOT_READY;
+  // facets: (D+1) per cell, at most half of them twins
+  uint32_t fsz = 64;
+  while (fsz < 2u * (D + 1) * nf) fsz <<= 1;
+  uint32_t rsz = 64;
+  while (rsz < 2u * (D + 1) * nf) rsz <<= 1;
+  DevBuf fk, f0, f1, rk, r0, r1, nc;
+  DT_TRY(fk.alloc((size_t)fsz * 8));
+  DT_TRY(f0.alloc((size_t)fsz * 4));
+  DT_TRY(f1.alloc((size_t)fsz * 4));
+  DT_TRY(rk.alloc((size_t)rsz * 8));
+  DT_TRY(r0.alloc((size_t)rsz * 4));
+  DT_TRY(r1.alloc((size_t)rsz * 4));
+  DT_TRY(nc.alloc(16));
+  DT_HIP(hipMemsetAsync(fk.p, 0xFF, (size_t)fsz * 8, st));
+  DT_HIP(hipMemsetAsync(f1.p, 0xFF, (size_t)fsz * 4, st));
+  DT_HIP(hipMemsetAsync(rk.p, 0xFF, (size_t)rsz * 8, st));
+  DT_HIP(hipMemsetAsync(r1.p, 0xFF, (size_t)rsz * 4, st));
+  DT_HIP(hipMemcpyAsync(nc.p, &nf, 4, hipMemcpyHostToDevice, st));
+  const SeedTab ft{fk.as<unsigned long long>(), f0.as<uint32_t>(), f1.as<uint32_t>(), fsz - 1};
+  const SeedTab rt{rk.as<unsigned long long>(), r0.as<uint32_t>(), r1.as<uint32_t>(), rsz - 1};
+  if (D == 2) {
+    hipLaunchKernelGGL(k_seed_cells<2>, dim3(nblk(nf)), dim3(BLOCK), 0, st, wp.cells.as<Cell>(),
+                       nf, sidx.as<uint32_t>(), a.cells, a.bid, a.vcell, a.ploc);
+    hipLaunchKernelGGL(k_seed_facets<2>, dim3(nblk(nf * 3)), dim3(BLOCK), 0, st,
+                       wp.cells.as<Cell>(), nf, ft, flags.as<uint32_t>());
+    hipLaunchKernelGGL(k_seed_link<2>, dim3(nblk(fsz)), dim3(BLOCK), 0, st, wp.cells.as<Cell>(),
+                       sidx.as<uint32_t>(), a.cells, ft, rt, nc.as<uint32_t>(), a.cap, a.bid,
+                       flags.as<uint32_t>());
+  } else {
+    hipLaunchKernelGGL(k_seed_cells<3>, dim3(nblk(nf)), dim3(BLOCK), 0, st, wp.cells.as<Cell>(),
+                       nf, sidx.as<uint32_t>(), a.cells, a.bid, a.vcell, a.ploc);
+    hipLaunchKernelGGL(k_seed_facets<3>, dim3(nblk(nf * 4)), dim3(BLOCK), 0, st,
+                       wp.cells.as<Cell>(), nf, ft, flags.as<uint32_t>());
+    hipLaunchKernelGGL(k_seed_link<3>, dim3(nblk(fsz)), dim3(BLOCK), 0, st, wp.cells.as<Cell>(),
+                       sidx.as<uint32_t>(), a.cells, ft, rt, nc.as<uint32_t>(), a.cap, a.bid,
+                       flags.as<uint32_t>());
+  }
+  hipLaunchKernelGGL(k_seed_ridges, dim3(nblk(rsz)), dim3(BLOCK), 0, st, a.cells, rt,
+                     flags.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  uint32_t h[2] = {0, 0};
+  DT_HIP(hipMemcpyAsync(&h[0], nc.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipMemcpyAsync(&h[1], flags.p, 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  if (h[1]) return DT_E_INTERNAL;
+  *ncells = h[0];
+  const uint64_t t1 = (uint64_t)T + T / 2;
+  *thresh = (uint32_t)(t1 > PMAX ? PMAX : t1);
+  return DT_OK;
+}
+
 // ------------------------------------------------------------ host driver
 static inline uint32_t nblk(uint32_t n) { return (n + BLOCK - 1) / BLOCK; }
 
@@ -1421,10 +1678,33 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.ginfo = nullptr;
   a.gcap = 0;
 
-  if (D == 2)
-    hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
-  else
-    hipLaunchKernelGGL(k4_init_sets<3>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
+  // a large single set starts from a gift-wrapped seed (see above)
+  uint32_t seed_cells = 0, seed_thresh = 0;
+  // (not inside a caller's workspace: the seed's scratch is not counted
+  // in its size)
+  if (job.nsets == 1 && job.seed && npts >= SEED_MIN_SET && (D == 2 || D == 3) &&
+      workspace() == nullptr) {
+    const int sr = seed_single_set(job, a, &seed_cells, &seed_thresh, st);
+    if (sr == DT_OK) {
+      // seed_cells outlives the copy (the stream is synchronised below)
+      DT_HIP(hipMemcpyAsync(&dctr->cells, &seed_cells, 4, hipMemcpyHostToDevice, st));
+      DT_HIP(hipMemsetAsync(pool.set_cell0.p, 0, 4, st));
+      ks.seeded = 1;
+    } else if (sr == DT_E_NOT_READY || sr == DT_E_INTERNAL) {
+      // start from one simplex: clear what the seed wrote
+      seed_cells = 0;
+      DT_HIP(hipMemsetAsync(ploc.p, 0, (size_t)npts * 4, st));
+      DT_HIP(hipMemsetAsync(dctr, 0, sizeof(Counters), st));
+    } else {
+      return sr;
+    }
+  }
+  if (!seed_cells) {
+    if (D == 2)
+      hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
+    else
+      hipLaunchKernelGGL(k4_init_sets<3>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
+  }
   hipLaunchKernelGGL(k4_place_init, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
   DT_HIP(hipGetLastError());
   DT_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -1441,6 +1721,7 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   const uint32_t PMAX = 1u << 20;
   uint64_t t0 = ((uint64_t)PMAX * job.start_active * job.nsets) / (npts ? npts : 1);
   uint32_t thresh0 = (uint32_t)(t0 < 16 ? 16 : (t0 > PMAX ? PMAX : t0));
+  if (seed_cells && seed_thresh > thresh0) thresh0 = seed_thresh;
   a.act = actbuf.as<uint32_t>();
   a.grow_div = job.grow_div ? job.grow_div : 64;
   // Smaller steps between levels keep the pending points sparser: fewer

@@ -217,6 +217,7 @@ int run_batch(const double* points, const int64_t* ids, const int64_t* offsets, 
   r->stats.num_simplices = r->m;
   r->stats.rounds = ks.rounds;
   r->stats.large_cavities = ks.giant_rounds;
+  r->stats.seeded_sets = ks.seeded;
   r->stats.cavity_cells = (int64_t)ks.cavity_cells;
   r->stats.candidates = (int64_t)ks.candidates;
   fill_pred_stats(r->stats, ks);

@@ -59,7 +59,7 @@ def test_binding_structs_match_header(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dt.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dt_options), '
                    'sizeof(dt_stats), offsetof(dt_options, recursive), '
-                   'offsetof(dt_stats, candidates), offsetof(dt_options, wrap_sample), '
+                   'offsetof(dt_stats, candidates), offsetof(dt_options, gift_wrap), '
                    'offsetof(dt_stats, wrap_levels));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
@@ -68,5 +68,5 @@ def test_binding_structs_match_header(tmp_path):
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(binding.Options), ctypes.sizeof(binding.Stats),
             binding.Options.recursive.offset, binding.Stats.candidates.offset,
-            binding.Options.wrap_sample.offset, binding.Stats.wrap_levels.offset]
+            binding.Options.gift_wrap.offset, binding.Stats.wrap_levels.offset]
     assert got == want

@@ -220,3 +220,32 @@ def test_neighbors_stay_inside_each_set(dtlib):
         got = nb[lo:hi].astype(np.int64)
         got[got >= 0] -= lo
         assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dim,kind,n,prec", [
+    (3, "bubbles", 120_000, "fp32"),
+    (3, "uniform", 100_000, "fp64"),
+    (2, "normal", 150_000, "fp32"),
+    (2, "lattice", 67_600, "fp64"),     # 260 x 260: every tie perturbed
+    (3, "jittered", 68_921, "fp32"),    # 41^3, moved by 2^-30 grid steps
+])
+def test_single_set_seeded_by_gift_wrap(dtlib, dim, kind, n, prec):
+    """A single set of at least 65,536 points starts from the gift-wrapped
+    triangulation of its first points in insertion order (neighbour links by
+    facet matching, a hull cell per hull facet) and inserts the rest in
+    parallel rounds: the oracle's simplices, as when it starts from one
+    simplex."""
+    if kind == "lattice":
+        p = inputs.lattice(round(n ** (1.0 / dim)), dim, seed=6)
+    elif kind == "jittered":
+        p = inputs.jittered_lattice(round(n ** (1.0 / dim)), dim, 2.0 ** -30, seed=6)
+    else:
+        p = inputs.make(kind, n, dim, seed=6)
+    print(f"[seed] dim={dim} kind={kind} n={len(p)} {prec}", flush=True)
+    res = dtlib.triangulate(p, k=1, precision=prec)
+    assert res.stats()["seeded_sets"] == 1
+    got = _rows(res)
+    assert np.array_equal(got, oracle.delaunay(p))
+    ref = dtlib.triangulate(p, k=1, precision=prec, gift_wrap=-1)
+    assert ref.stats()["seeded_sets"] == 0
+    assert np.array_equal(_rows(ref), got)

@@ -310,6 +310,6 @@ def test_sample_triangulation_gift_wrapped(dtlib, dim, dist, n, rate, prec):
     assert st["wrap_levels"] > 0
     sid = res.stage("sample").astype(np.int64)
     assert np.array_equal(oracle.canonical(res.stage("sample_dt")), oracle.delaunay(p[sid], sid))
-    ref = dtlib.triangulate(p, k=16, sample_rate=rate, precision=prec, wrap_sample=-1)
+    ref = dtlib.triangulate(p, k=16, sample_rate=rate, precision=prec, gift_wrap=-1)
     assert ref.stats()["wrap_levels"] == 0
     assert np.array_equal(oracle.canonical(res.rows()), oracle.canonical(ref.rows()))
