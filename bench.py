@@ -443,7 +443,7 @@ def main() -> int:
                     help="HBM budget of the server (GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+        print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark runs on one GPU "
               "(sharding over several GPUs is a design, not built)", file=sys.stderr)
         return 2
     if args.mode == "batch":
@@ -527,6 +527,18 @@ def main() -> int:
                                  **summary(kst))
         line["sample_vs_kd_speedup"] = round(kms / ms, 4)
         line["kd_simplex_count_equal"] = bool(kres.count == res.count)
+    if not args.no_kd and k != 16:
+        # context: both divides at the paper's own k = 16 (its runtime
+        # experiments use k = t = 16)
+        r16, ms16, _, _ = run(binding, pts, args.steps, args.warmup, 16, rate, precision=prec,
+                              divide="sample")
+        k16, kms16, _, _ = run(binding, pts, args.steps, args.warmup, 16, rate, precision=prec,
+                               divide="kd")
+        line["k16"] = {"sample_ms_per_step": round(ms16, 3), "kd_ms_per_step": round(kms16, 3),
+                       "sample_vs_kd_speedup": round(kms16 / ms16, 4),
+                       "border_vertices": {"sample": r16.stats()["border_vertices"],
+                                           "kd": k16.stats()["border_vertices"]},
+                       "simplex_counts_equal": bool(r16.count == k16.count == res.count)}
     if not args.no_direct:
         # context, not the method: the same input triangulated as one set
         dres, dms, _, _ = run(binding, pts, args.steps, args.warmup, 1, 0.0, precision=prec)
