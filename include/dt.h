@@ -117,6 +117,12 @@ typedef struct dt_options {
    * triangulation of its first 4096 or so points in insertion order; -1
    * inserts every point in parallel rounds. */
   int gift_wrap;
+  /* Pair exchanges in the partitioner's sweeps: 0 (default) lets a vertex
+   * whose best block is full swap with a vertex of that block that wants
+   * its block, when the exchange lowers the cut (block sizes unchanged);
+   * -1 moves vertices into free room only.  The result does not depend on
+   * it, the blocks and the border do. */
+  int refine_swaps;
 } dt_options;
 
 /* Kernels timed when dt_options.profile = 1. */

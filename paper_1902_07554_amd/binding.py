@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("border", ctypes.c_int), ("profile", ctypes.c_int),
                 ("start_active", ctypes.c_int), ("grow_div", ctypes.c_int),
                 ("cand_blocks", ctypes.c_int), ("grow_num", ctypes.c_int),
-                ("recursive", ctypes.c_int), ("gift_wrap", ctypes.c_int)]
+                ("recursive", ctypes.c_int), ("gift_wrap", ctypes.c_int),
+                ("refine_swaps", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

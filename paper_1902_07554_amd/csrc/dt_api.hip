@@ -316,6 +316,7 @@ int check_options(const dt_options* in, dt_options& o) {
   if (o.grow_num != 0 && (o.grow_num < 9 || o.grow_num > 32)) return DT_E_INVALID_ARG;
   if (o.recursive != 0 && o.recursive != 1) return DT_E_INVALID_ARG;
   if (o.gift_wrap != 0 && o.gift_wrap != -1) return DT_E_INVALID_ARG;
+  if (o.refine_swaps != 0 && o.refine_swaps != -1) return DT_E_INVALID_ARG;
   return DT_OK;
 }
 

@@ -306,6 +306,7 @@ int run_dc(const double* points, int64_t n64, int D, int k, double rate, const d
       reg.kind = BORDER_VORONOI;
       reg.S = Sp.as<double4>();
       reg.part = part.as<uint32_t>();
+      reg.ns = eta;
       reg.start = sgrid.start.as<uint32_t>();
       reg.items = sgrid.items.as<uint32_t>();
       reg.G = sgrid.G;

@@ -369,16 +369,78 @@ __global__ void k_lp_list(uint32_t eta, const uint32_t* pblock, const uint32_t* 
   plist[poff[b] + atomicAdd(&pcur[b], 1u)] = v;
 }
 
+// Pair exchanges between full blocks.  A proposal A -> B whose block B has
+// no room cannot move alone; it is paired with the proposal B -> A of the
+// same rank (gains descending, ties to the smaller vertex), and the pair
+// swaps when the exchange lowers the cut: g_v + g_u - 2 w(u, v) > 0, the
+// exchange gain of Kernighan and Lin.  Block sizes do not change, so the
+// balance bound holds with no room at all (8 samples per block at the
+// default sample size and k = 256).  Decided from the sweep's starting
+// blocks; k_lp_accept applies the swaps.
+__global__ void k_lp_swap(uint32_t eta, const uint32_t* off, const uint32_t* adj, const double* w,
+                          const uint32_t* part, const uint32_t* pblock, const double* pgain,
+                          const uint32_t* poff, const uint32_t* pcount, const uint32_t* plist,
+                          const int* size, int lmax, const int* lmax_of, uint32_t* pswap) {
+  uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= eta) return;
+  uint32_t swap = 0;
+  const uint32_t b = pblock[v];
+  if (b != DONE) {
+    const uint32_t a = part[v];
+    const int room_b = (lmax_of ? lmax_of[b] : lmax) - size[b];
+    const int room_a = (lmax_of ? lmax_of[a] : lmax) - size[a];
+    if (room_a <= 0 && room_b <= 0) {
+      const double g = pgain[v];
+      uint32_t rank = 0;
+      for (uint32_t i = poff[b]; i < poff[b] + pcount[b]; i++) {
+        const uint32_t x = plist[i];
+        if (part[x] != a) continue;
+        const double gx = pgain[x];
+        if (gx > g || (gx == g && x < v)) rank++;
+      }
+      // the partner: rank-th proposal B -> A
+      uint32_t u = DONE;
+      double gu = 0.0;
+      for (uint32_t i = poff[a]; i < poff[a] + pcount[a] && u == DONE; i++) {
+        const uint32_t x = plist[i];
+        if (part[x] != b) continue;
+        const double gx = pgain[x];
+        uint32_t rx = 0;
+        for (uint32_t j = poff[a]; j < poff[a] + pcount[a]; j++) {
+          const uint32_t y = plist[j];
+          if (part[y] != b) continue;
+          const double gy = pgain[y];
+          if (gy > gx || (gy == gx && y < x)) rx++;
+        }
+        if (rx == rank) { u = x; gu = gx; }
+      }
+      if (u != DONE) {
+        double wuv = 0.0;
+        for (uint32_t i = off[v]; i < off[v + 1]; i++)
+          if (adj[i] == u) wuv += w[i];
+        const double sum = g + gu, cost = 2.0 * wuv;
+        if (sum - cost > 1e-12 * (sum + cost + 1.0)) swap = 1;
+      }
+    }
+  }
+  pswap[v] = swap;
+}
+
 // Accept the best proposals into each block up to its free capacity
-// (capacity measured at the start of the sweep, so the bound always holds).
+// (capacity measured at the start of the sweep, so the bound always holds),
+// and the pair exchanges decided by k_lp_swap.
 __global__ void k_lp_accept(uint32_t eta, const uint32_t* pblock, const double* pgain,
                             const uint32_t* poff, const uint32_t* pcount, const uint32_t* plist,
-                            const int* size, int lmax, const int* lmax_of, uint32_t* part,
-                            int* delta) {
+                            const int* size, int lmax, const int* lmax_of, const uint32_t* pswap,
+                            uint32_t* part, int* delta) {
   uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= eta) return;
   uint32_t b = pblock[v];
   if (b == DONE) return;
+  if (pswap && pswap[v]) {
+    part[v] = b;
+    return;
+  }
   int room = (lmax_of ? lmax_of[b] : lmax) - size[b];
   if (room <= 0) return;
   double g = pgain[v];
@@ -481,8 +543,8 @@ int sample_graph(const double4* S, uint32_t eta, int D, const CellPool& pool, in
 
 int refine_partition(uint32_t eta, const uint32_t* goff, const uint32_t* gadj, const double* gw,
                      uint32_t* part, uint32_t k, int lmax, const int* lmax_of, int iters,
-                     hipStream_t st) {
-  DevBuf size, delta, pblock, pgain, pcount, poff, pcur, plist;
+                     bool swaps, hipStream_t st) {
+  DevBuf size, delta, pblock, pgain, pcount, poff, pcur, plist, pswap;
   DT_TRY(size.alloc((size_t)k * 4));
   DT_TRY(delta.alloc((size_t)k * 4));
   DT_TRY(pblock.alloc((size_t)eta * 4));
@@ -491,6 +553,7 @@ int refine_partition(uint32_t eta, const uint32_t* goff, const uint32_t* gadj, c
   DT_TRY(poff.alloc((size_t)(k + 1) * 4));
   DT_TRY(pcur.alloc((size_t)(k + 1) * 4));
   DT_TRY(plist.alloc((size_t)eta * 4));
+  if (swaps) DT_TRY(pswap.alloc((size_t)eta * 4));
   DT_HIP(hipMemsetAsync(size.p, 0, (size_t)k * 4, st));
   DT_HIP(hipMemsetAsync(delta.p, 0, (size_t)k * 4, st));
   hipLaunchKernelGGL(k_count_u32, dim3(dblocks(eta)), dim3(DB), 0, st, part, eta,
@@ -505,10 +568,15 @@ int refine_partition(uint32_t eta, const uint32_t* goff, const uint32_t* gadj, c
     hipLaunchKernelGGL(k_lp_list, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
                        pblock.as<uint32_t>(), poff.as<uint32_t>(), pcur.as<uint32_t>(),
                        plist.as<uint32_t>());
+    if (swaps)
+      hipLaunchKernelGGL(k_lp_swap, dim3(dblocks(eta)), dim3(DB), 0, st, eta, goff, gadj, gw,
+                         part, pblock.as<uint32_t>(), pgain.as<double>(), poff.as<uint32_t>(),
+                         pcount.as<uint32_t>(), plist.as<uint32_t>(), (const int*)size.p, lmax,
+                         lmax_of, pswap.as<uint32_t>());
     hipLaunchKernelGGL(k_lp_accept, dim3(dblocks(eta)), dim3(DB), 0, st, eta,
                        pblock.as<uint32_t>(), pgain.as<double>(), poff.as<uint32_t>(),
                        pcount.as<uint32_t>(), plist.as<uint32_t>(), (const int*)size.p, lmax,
-                       lmax_of, part, (int*)delta.p);
+                       lmax_of, swaps ? pswap.as<uint32_t>() : nullptr, part, (int*)delta.p);
     hipLaunchKernelGGL(k_apply_delta, dim3(dblocks(k)), dim3(DB), 0, st, k, (int*)size.p,
                        (int*)delta.p);
     DT_HIP(hipGetLastError());
@@ -550,7 +618,8 @@ int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool
   uint32_t avg = (eta + k - 1) / k;
   int lmax = (int)floor((1.0 + o.eps) * (double)avg + 1e-9);
   DT_TRY(refine_partition(eta, goff.as<uint32_t>(), gadj.as<uint32_t>(), gw.as<double>(),
-                          part.as<uint32_t>(), k, lmax, nullptr, o.refine_iters, st));
+                          part.as<uint32_t>(), k, lmax, nullptr, o.refine_iters,
+                          o.refine_swaps == 0, st));
   DevBuf dcut;
   DT_TRY(dcut.alloc(8));
   DT_HIP(hipMemsetAsync(dcut.p, 0, 8, st));

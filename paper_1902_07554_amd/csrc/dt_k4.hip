@@ -1067,7 +1067,11 @@ __device__ __forceinline__ uint32_t new_cell_link(K4Args& a, CavList& cl, uint32
 // each wavefront verifies and numbers its candidate's boundary facets,
 // then one thread takes the new cells of all the block's winners with a
 // single atomic (a counter that every winner hit alone serialises the
-// whole launch), then each wavefront builds its cells.
+// whole launch), then each wavefront builds its cells.  Eight waves per
+// SIMD (at most 64 registers): its chains of dependent gathers gain more
+// from the extra waves than they lose to a few spilled bytes (the step's
+// insert 62.0 -> 58.5 ms on 4M clustered points; the selection and the
+// walk lose at higher occupancy, their spills are larger).
 constexpr uint32_t INS_WAVES = 8;
 
 // Barrier of one wavefront (its lanes run in lockstep: only the memory
@@ -1079,7 +1083,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <int D>
-__global__ __launch_bounds__(64 * INS_WAVES) void k4_insert(K4Args a) {
+__global__ __launch_bounds__(64 * INS_WAVES, 8) void k4_insert(K4Args a) {
   __shared__ uint32_t s_failw[INS_WAVES], s_runw[INS_WAVES], s_basew[INS_WAVES];
   __shared__ uint32_t s_ftabw[INS_WAVES][FTAB];   // boundary facet f: cavity position << 2 | facet
   __shared__ uint32_t s_poolfail;

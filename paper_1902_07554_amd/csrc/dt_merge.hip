@@ -271,6 +271,138 @@ __global__ void k_point_margin(const double4* pts, uint32_t n, const uint32_t* n
   near_loc[i] = t;
 }
 
+// Barrier of one wavefront (LDS written by some lanes, read by others).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The same clearance from a short list per sample.  For the sample t, the
+// foreign samples (of other blocks) are ranked by their distance from t;
+// the nearest ML of them are listed with their distance gap = |s - t|, and
+// rho_t is half the distance of the nearest one not listed (infinite when
+// all are listed).  A foreign sample s not listed has |s - t| >= 2 rho_t,
+// and any point x that the assignment gives to s is at least about
+// |s - t| / 2 from t (it is no farther from s than from t, up to the
+// rounding of the keys), so for a point q of t's cell such an x lies at
+// least rho_t - |q - t| from q.  The clearance of q is the least of that
+// bound and the bisector distances of the listed samples: it needs no
+// grid and no scan of the block's own samples.
+constexpr uint32_t ML = 32;               // foreign samples listed per sample
+constexpr uint32_t ML_MAX_SAMPLES = 65536;  // larger samples use the grid scan
+
+// One wavefront per sample t: the (ML+1)-th smallest key (squared distance
+// rounded to FP32, whose bit patterns order as the values) by four 8-bit
+// radix passes over the foreign samples, then the samples with a smaller
+// key are listed and the least distance of the others gives rho_t.
+__global__ __launch_bounds__(64) void k_margin_lists(const double4* S, const uint32_t* part,
+                                                     uint32_t ns, double4* lent, uint32_t* lcnt,
+                                                     double* rho) {
+  __shared__ uint32_t s_h[256];
+  __shared__ uint32_t s_pick[2];
+  const uint32_t t = blockIdx.x, lane = threadIdx.x;
+  if (t >= ns) return;
+  const uint32_t me = part[t];
+  const double4 tp = S[t];
+  auto key_of_s = [&](uint32_t s, double& gap2) {
+    const double4 q = S[s];
+    const double ex = q.x - tp.x, ey = q.y - tp.y, ez = q.z - tp.z;
+    gap2 = ex * ex + ey * ey + ez * ez;
+    return (uint32_t)__float_as_uint((float)gap2);
+  };
+  uint32_t nf = 0;
+  for (uint32_t b = 0; b < ns; b += 64) {
+    const uint32_t s = b + lane;
+    nf += (uint32_t)__popcll(__ballot(s < ns && part[s] != me));
+  }
+  uint32_t thr = 0xFFFFFFFFu;   // keys below it are listed
+  if (nf > ML) {
+    uint32_t prefix = 0, pmask = 0, rank = ML;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      for (uint32_t j = lane; j < 256; j += 64) s_h[j] = 0;
+      wave_sync_lds();
+      for (uint32_t s = lane; s < ns; s += 64) {
+        if (part[s] == me) continue;
+        double g2;
+        const uint32_t key = key_of_s(s, g2);
+        if ((key & pmask) == prefix) atomicAdd(&s_h[(key >> shift) & 255u], 1u);
+      }
+      wave_sync_lds();
+      if (lane == 0) {
+        uint32_t below = 0, bin = 255;
+        for (uint32_t j = 0; j < 256; j++) {
+          if (below + s_h[j] > rank) { bin = j; break; }
+          below += s_h[j];
+        }
+        s_pick[0] = bin;
+        s_pick[1] = below;
+      }
+      wave_sync_lds();
+      prefix |= s_pick[0] << shift;
+      pmask |= 255u << shift;
+      rank -= s_pick[1];
+      wave_sync_lds();
+    }
+    thr = prefix;
+  }
+  uint32_t n = 0;
+  double rmin = INFINITY;
+  for (uint32_t b = 0; b < ns; b += 64) {
+    const uint32_t s = b + lane;
+    bool take = false;
+    double g2 = 0.0;
+    if (s < ns && part[s] != me) {
+      const uint32_t key = key_of_s(s, g2);
+      take = nf <= ML || key < thr;
+      if (!take) rmin = fmin(rmin, sqrt(g2));
+    }
+    const unsigned long long m = __ballot(take);
+    if (take) {
+      const double4 q = S[s];
+      lent[(size_t)t * ML + n + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] =
+          make_double4(q.x, q.y, q.z, sqrt(g2));
+    }
+    n += (uint32_t)__popcll(m);
+  }
+  for (int o = 32; o > 0; o >>= 1) rmin = fmin(rmin, __shfl_xor(rmin, o, 64));
+  if (lane == 0) {
+    lcnt[t] = n;
+    rho[t] = 0.5 * rmin;
+  }
+}
+
+template <int D>
+__global__ void k_point_margin_list(const double4* pts, uint32_t n, const uint32_t* nearest,
+                                    const double4* S, const double4* lent, const uint32_t* lcnt,
+                                    const double* rho, double* margin, uint32_t* near_loc) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 q = pts[i];
+  const uint32_t id = (uint32_t)__double_as_longlong(q.w);
+  const uint32_t t = nearest[id];
+  const double4 tp = S[t];
+  const double qz = D == 3 ? q.z : 0.0;
+  const double tx = q.x - tp.x, ty = q.y - tp.y, tz = qz - tp.z;
+  const double dt = tx * tx + ty * ty + tz * tz;
+  const double rt = sqrt(dt);
+  // the samples not listed: rho_t - |q - t|, with slack for the rounding
+  // of both distances (rho_t is infinite when every foreign one is listed)
+  double f = rho[t] * (1.0 - 1e-9) - rt * (1.0 + 1e-9);
+  const uint32_t cnt = lcnt[t];
+  const double4* e = lent + (size_t)t * ML;
+  for (uint32_t j = 0; j < cnt; j++) {
+    const double4 sp = e[j];
+    const double ax = q.x - sp.x, ay = q.y - sp.y, az = qz - sp.z;
+    const double ds = ax * ax + ay * ay + az * az;
+    // signed distance from the bisector, less the rounding slack of the
+    // assignment keys (as in k_point_margin)
+    f = fmin(f, (ds - dt - 1e-12 * (ds + dt)) / (2.0 * sp.w));
+  }
+  margin[i] = f;
+  near_loc[i] = t;
+}
+
 constexpr uint32_t NB_STRIPES = 64;   // copies of the border-simplex counter
 
 // The test of one live cell c: flag it, and its vertices (vbflag), when
@@ -393,13 +525,6 @@ constexpr uint32_t BTILES_PER_BLOCK = MB / 64;
 constexpr uint32_t BWORDS = BT * BTILES_PER_BLOCK;   // mask words of a block
 static inline uint32_t btiles(uint64_t n) {
   return (uint32_t)((n + BTILE * BTILES_PER_BLOCK - 1) / (BTILE * BTILES_PER_BLOCK));
-}
-
-// Barrier of one wavefront (LDS written by some lanes, read by others).
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // The live cells of the wavefront's tile, in cell order, listed in LDS;
@@ -556,8 +681,33 @@ int border_detect(const LocalJob& job, const CellPool& pool, const Region& reg, 
     R.cstart = cstart.as<uint32_t>();
     R.citems = citems.as<uint32_t>();
   }
+  DevBuf lent, lcnt, lrho;
+  const bool lists = reg.kind == BORDER_VORONOI && reg.nearest && job.npts && reg.ns > 0 &&
+                     reg.ns <= ML_MAX_SAMPLES;
+  if (lists) {
+    DT_TRY(lent.alloc((size_t)reg.ns * ML * sizeof(double4)));
+    DT_TRY(lcnt.alloc((size_t)reg.ns * 4));
+    DT_TRY(lrho.alloc((size_t)reg.ns * 8));
+    hipLaunchKernelGGL(k_margin_lists, dim3(reg.ns), dim3(64), 0, st, reg.S, reg.part, reg.ns,
+                       lent.as<double4>(), lcnt.as<uint32_t>(), lrho.as<double>());
+  }
   DT_PROF_BEGIN(DT_KERN_BORDER, st);
-  if (reg.kind == BORDER_VORONOI && reg.nearest && job.npts) {
+  if (lists) {
+    DT_TRY(margin.alloc((size_t)job.npts * sizeof(double)));
+    DT_TRY(near_loc.alloc((size_t)job.npts * 4));
+    if (D == 2)
+      hipLaunchKernelGGL(k_point_margin_list<2>, dim3(mblocks(job.npts)), dim3(MB), 0, st,
+                         job.pts, job.npts, reg.nearest, reg.S, lent.as<double4>(),
+                         lcnt.as<uint32_t>(), lrho.as<double>(), margin.as<double>(),
+                         near_loc.as<uint32_t>());
+    else
+      hipLaunchKernelGGL(k_point_margin_list<3>, dim3(mblocks(job.npts)), dim3(MB), 0, st,
+                         job.pts, job.npts, reg.nearest, reg.S, lent.as<double4>(),
+                         lcnt.as<uint32_t>(), lrho.as<double>(), margin.as<double>(),
+                         near_loc.as<uint32_t>());
+    R.margin = margin.as<double>();
+    R.near_loc = near_loc.as<uint32_t>();
+  } else if (reg.kind == BORDER_VORONOI && reg.nearest && job.npts) {
     DT_TRY(margin.alloc((size_t)job.npts * sizeof(double)));
     DT_TRY(near_loc.alloc((size_t)job.npts * sizeof(uint32_t)));
     if (D == 2)

@@ -632,7 +632,7 @@ int sample_bisect(const DevBuf& P, uint32_t n, int D, int levels, double rate,
     DT_HIP(hipGetLastError());
     DT_TRY(refine_partition(ns, L.goff.as<uint32_t>(), L.gadj.as<uint32_t>(), L.gw.as<double>(),
                             L.label.as<uint32_t>(), 2 * nb, 0, dlmax.as<int>(), o.refine_iters,
-                            st));
+                            o.refine_swaps == 0, st));
     // every point takes the side of its nearest sample of its own block
     // (grid of about ns/2 cells over the input box)
     Grid G;

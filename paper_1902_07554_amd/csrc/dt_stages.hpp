@@ -22,10 +22,11 @@ int spatial_sort(DevBuf& pts, uint32_t n, int D, const double lo[3], const doubl
 int sample_graph(const double4* S, uint32_t eta, int D, const CellPool& pool, int weight,
                  double dstar, DevBuf& goff, DevBuf& gadj, DevBuf& gw, hipStream_t st);
 // Label propagation on that graph: part[v] in [0, k); a move never takes a
-// block above its bound (lmax_of[b] if given, else lmax).
+// block above its bound (lmax_of[b] if given, else lmax); with swaps, pairs
+// of vertices may also exchange full blocks.
 int refine_partition(uint32_t eta, const uint32_t* goff, const uint32_t* gadj, const double* gw,
                      uint32_t* part, uint32_t k, int lmax, const int* lmax_of, int iters,
-                     hipStream_t st);
+                     bool swaps, hipStream_t st);
 // goff/gadj receive the sample's Delaunay graph (CSR, sorted lists) and
 // gw the weight of every adjacency entry.
 int partition_sample(const double4* S, uint32_t eta, int D, const CellPool& pool, uint32_t k,
@@ -67,6 +68,7 @@ struct Region {
   int kind = BORDER_GRID;
   const double4* S = nullptr;      // samples (Voronoi)
   const uint32_t* part = nullptr;  // block of every sample
+  uint32_t ns = 0;                 // number of samples (Voronoi)
   const uint32_t* start = nullptr; // sample grid
   const uint32_t* items = nullptr;
   Grid G{};

@@ -57,10 +57,11 @@ def test_binding_structs_match_header(tmp_path):
     from paper_1902_07554_amd import binding
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dt.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dt_options), '
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dt_options), '
                    'sizeof(dt_stats), offsetof(dt_options, recursive), '
                    'offsetof(dt_stats, candidates), offsetof(dt_options, gift_wrap), '
-                   'offsetof(dt_stats, wrap_levels));return 0;}\n')
+                   'offsetof(dt_stats, wrap_levels), offsetof(dt_options, refine_swaps));'
+                   'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
                    check=True)
@@ -68,5 +69,6 @@ def test_binding_structs_match_header(tmp_path):
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(binding.Options), ctypes.sizeof(binding.Stats),
             binding.Options.recursive.offset, binding.Stats.candidates.offset,
-            binding.Options.gift_wrap.offset, binding.Stats.wrap_levels.offset]
+            binding.Options.gift_wrap.offset, binding.Stats.wrap_levels.offset,
+            binding.Options.refine_swaps.offset]
     assert got == want

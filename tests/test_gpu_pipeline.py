@@ -164,6 +164,41 @@ def test_partition_is_deterministic_and_cuts_less_than_its_start(dtlib):
     assert a.stats()["cut_weight"] <= oracle.cut_weight(edges, w, start) + 1e-9
 
 
+def test_pair_exchanges_under_a_strict_bound(dtlib):
+    """At eight samples per block the 5 % bound leaves no room (the 4M
+    clustered workload's setting, eta = 2048 and k = 256), so only pair
+    exchanges can change the kd start.  With them the blocks stay within
+    the bound and the same on every run, the cut is no larger than with
+    moves alone or at the start, and the simplex set is the oracle's
+    whichever partition is used (Algorithm 1 does not depend on it)."""
+    p = inputs.make("bubbles", 40_000, 3, seed=5)
+    k, rate = 64, 512 / 40_000
+    print(f"[pipeline] pair exchanges k={k} eta=512", flush=True)
+    on = dtlib.triangulate(p, k=k, sample_rate=rate, keep_stages=1)
+    again = dtlib.triangulate(p, k=k, sample_rate=rate, keep_stages=1)
+    off = dtlib.triangulate(p, k=k, sample_rate=rate, keep_stages=1, refine_swaps=-1)
+    assert on.stats()["eta"] == 512
+    part_on = on.stage("part")
+    assert np.array_equal(part_on, again.stage("part"))
+    sid = on.stage("sample")
+    full = np.full(len(p), -1, dtype=np.int64)
+    full[sid] = part_on
+    assert oracle.balanced(part_on, k, 0.05)
+    assert np.bincount(part_on, minlength=k).max() == 8
+    edges = on.stage("graph").astype(np.int64)
+    w = on.stage("weights")
+    start = np.full(len(p), -1, dtype=np.int64)
+    start[sid] = oracle.kd_divide(p[sid], k)
+    assert np.array_equal(start[sid], off.stage("part"))   # nothing moves without exchanges
+    cut_on = oracle.cut_weight(edges, w, full)
+    assert on.stats()["cut_weight"] == pytest.approx(cut_on, rel=1e-9, abs=1e-9)
+    assert cut_on <= oracle.cut_weight(edges, w, start) + 1e-9
+    assert not np.array_equal(part_on, off.stage("part"))
+    want = oracle.canonical(oracle.delaunay(p))
+    for r in (on, off):
+        assert np.array_equal(oracle.canonical(r.rows()), want)
+
+
 @pytest.mark.parametrize("dim,side,k", [(2, 60, 4), (3, 12, 8)])
 def test_lattice_through_pipeline(dtlib, dim, side, k):
     """Degenerate input: ties everywhere, also across partition borders."""

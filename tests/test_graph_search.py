@@ -169,3 +169,68 @@ def test_voronoi_walk_flags_every_non_delaunay_simplex():
     # the case has simplices to catch, and the walk does not flag everything
     assert outside > 0 and flagged < total and settled > 0
     assert missed == 0
+
+
+def _list_clearance(p, S, part, near, ml):
+    """The clearance from a short list per sample: the ml foreign samples
+    of smallest squared distance to t rounded to FP32 (keys below the
+    (ml+1)-th smallest key), and rho_t, half the least distance of the
+    foreign samples not listed."""
+    ns = len(S)
+    lists, rho = [], np.full(ns, np.inf)
+    for t in range(ns):
+        fs = np.nonzero(part != part[t])[0]
+        e = S[fs] - S[t]
+        g2 = e[:, 0] * e[:, 0] + e[:, 1] * e[:, 1] + e[:, 2] * e[:, 2]
+        if len(fs) <= ml:
+            lists.append(fs)
+            continue
+        keys = g2.astype(np.float32)
+        thr = np.sort(keys)[ml]
+        take = keys < thr
+        assert take.sum() <= ml
+        lists.append(fs[take])
+        rho[t] = 0.5 * float(np.sqrt(g2[~take].min()))
+    out = np.empty(len(p))
+    from_rho = 0
+    for j in range(len(p)):
+        t = near[j]
+        dt = float((p[j] - S[t]) @ (p[j] - S[t]))
+        rt = np.sqrt(dt)
+        f = rho[t] * (1.0 - 1e-9) - rt * (1.0 + 1e-9)
+        f_rho = f
+        for s in lists[t]:
+            ds = float((p[j] - S[s]) @ (p[j] - S[s]))
+            gap = float(np.linalg.norm(S[s] - S[t]))
+            f = min(f, (ds - dt - 1e-12 * (ds + dt)) / (2.0 * gap))
+        from_rho += f == f_rho
+        out[j] = f
+    return out, from_rho
+
+
+def test_listed_clearance_is_a_lower_bound():
+    """The border test's clearance of a point from the foreign Voronoi
+    cells, taken from its sample's list of nearest foreign samples and the
+    distance bound for the others, never exceeds the clearance over all
+    foreign samples, and with a short list the bound for the others decides
+    some points."""
+    p = inputs.make("bubbles", 3000, 3, seed=8)
+    eta, k = 96, 8
+    sid, S, adj = _sample_graph(p, len(p), eta, seed=4)
+    part = np.arange(eta) * k // eta
+    near = oracle.nearest_sample(p, S, sid)
+    exact = np.empty(len(p))
+    for j in range(len(p)):
+        t = near[j]
+        fs = np.nonzero(part != part[t])[0]
+        ds = np.einsum("ij,ij->i", p[j] - S[fs], p[j] - S[fs])
+        dt = float((p[j] - S[t]) @ (p[j] - S[t]))
+        exact[j] = np.min((ds - dt) / (2.0 * np.linalg.norm(S[fs] - S[t], axis=1)))
+    for ml in (2, 6, 32):
+        got, from_rho = _list_clearance(p, S, part, near, ml)
+        assert np.all(got <= exact + 1e-12 * np.abs(exact))
+        if ml <= 6:
+            assert from_rho > 0
+    # with the library's list length the bound is nearly the exact one
+    got, _ = _list_clearance(p, S, part, near, 32)
+    assert np.mean(got >= exact - 1e-6 * np.abs(exact)) > 0.9
