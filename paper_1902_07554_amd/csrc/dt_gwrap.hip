@@ -1,6 +1,9 @@
-// Delaunay triangulation of one small point set by gift wrapping: the
-// sample triangulation of Algorithm 2 (eta(n) = sqrt(n) points by default,
-// Section "Sample Size").
+// Delaunay triangulation of small point sets by gift wrapping: the sample
+// triangulation of Algorithm 2 (eta(n) = sqrt(n) points by default, Section
+// "Sample Size"), and the seeds of the parallel insertion (the first points
+// of every large set, see dt_k4.hip).  Several independent sets are wrapped
+// together: each facet searches only the points of its own set, and the
+// levels of all sets run in the same launches.
 //
 // Parallel insertion spends about a hundred rounds on the start-up of a
 // small single set (while the triangulation has few cells, the cavities of
@@ -22,18 +25,20 @@
 // Exactness: orientation and the perturbed in-sphere test are the
 // library's predicates (FP64 filter, then exact), so the simplices
 // found are the finite cells of the same perturbed Delaunay triangulation
-// that parallel insertion builds.  The seed is a simplex through point 0
-// and D of its 16 nearest points whose circumsphere holds no point, checked
-// against every point.  When no such simplex is among them, or a capacity
-// runs out, the caller triangulates the set by parallel insertion instead.
+// that parallel insertion builds.  The seed of a set is a simplex through
+// its first point and D of that point's 16 nearest whose circumsphere holds
+// no point of the set, checked against every one.  When some set has no
+// such simplex among them, or a capacity runs out, the caller triangulates
+// the sets by parallel insertion instead.
 //
 // The FP64 filter comes first here whatever the run's precision: the
 // tests that decide a facet compare nearly cospherical candidates, where the
 // FP32 filter often cannot decide and the out-of-line stages would run.
 //
-// Cost: a facet search reads every point, one wavefront per facet, so the
-// work is about D (D+1) / 2 * 6.8 n^2 predicate evaluations in 3D; it is
-// used for sets of at most GW_MAX_POINTS points.  A level is one launch;
+// Cost: a facet search reads every point of its set, one wavefront per
+// facet, so the work is about D (D+1) / 2 * 6.8 n^2 predicate evaluations
+// per set of n points in 3D; it is used for sets of at most GW_MAX_POINTS
+// points.  A level is one launch;
 // the number of levels is the depth of the simplices' adjacency graph from
 // the seed (tens for a few thousand points).
 #include "dt_common.hpp"
@@ -42,6 +47,9 @@
 #include "dt_pred.hpp"
 #include "dt_gwrap.hpp"
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <vector>
 
 namespace dtk {
@@ -49,12 +57,14 @@ namespace dtk {
 namespace {
 
 constexpr uint32_t GW_NN = 16;              // nearest points tried for the seed
+constexpr uint32_t GW_BASES = 4;            // start points tried per set for the seed
 constexpr uint32_t GW_NONE = 0xFFFFFFFFu;
 constexpr uint32_t GW_MAX_LEVELS = 4096;
 constexpr uint32_t GW_THREADS = 256;        // level kernel: four facets per block
 constexpr uint32_t GW_LEVEL_BLOCKS = 1024;  // grid of the level kernel (a grid-stride loop)
 constexpr uint32_t GW_GROUP = 8;            // levels launched between two reads of the counters
-constexpr uint32_t GW_LDS_POINTS = 2048;    // sets copied into LDS by each level block (64 KB)
+constexpr uint32_t GW_LDS_POINTS = 2048;    // a single set this small is copied into LDS (64 KB)
+constexpr int GW_LOCAL_BITS = 13;           // set-local point index in simplex keys (8192 points)
 
 // device failure bits of the wrap (any: the caller falls back)
 enum : uint32_t { GW_FAIL_SEED = 1u, GW_FAIL_CAP = 2u, GW_FAIL_HASH = 4u };
@@ -158,10 +168,12 @@ __device__ __forceinline__ bool facet_frame(const PtsX& F, uint32_t i, const dou
   return true;
 }
 
-// Sorted vertex indices of a simplex packed into one key (16 bits each).
+// The simplex's set and its sorted set-local vertex indices (13 bits each)
+// packed into one key.
 template <int D>
-__device__ __forceinline__ unsigned long long simplex_key(const uint4& v) {
-  uint32_t k[4] = {v.x, v.y, v.z, D == 3 ? v.w : 0u};
+__device__ __forceinline__ unsigned long long simplex_key(const uint4& v, uint32_t set,
+                                                          uint32_t base) {
+  uint32_t k[4] = {v.x - base, v.y - base, v.z - base, D == 3 ? v.w - base : 0u};
 #pragma unroll
   for (int i = 1; i <= D; i++)
 #pragma unroll
@@ -171,9 +183,9 @@ __device__ __forceinline__ unsigned long long simplex_key(const uint4& v) {
         k[j] = k[j - 1];
         k[j - 1] = t;
       }
-  unsigned long long key = 0;
+  unsigned long long key = (unsigned long long)set;
 #pragma unroll
-  for (int i = 0; i <= D; i++) key = (key << 16) | (unsigned long long)k[i];
+  for (int i = 0; i <= D; i++) key = (key << GW_LOCAL_BITS) | (unsigned long long)k[i];
   return key;
 }
 
@@ -203,15 +215,30 @@ __device__ __forceinline__ bool in_sphere(const double4* P, PredT<false>& pr, co
   return pr.template insphere<D>(X) > 0;
 }
 
-// GW_NN points near point 0, one block: the nearest point of each thread's
-// share (by squared distance rounded to FP32, then index), and of those
-// the GW_NN smallest by rank.  Any near points do: they only propose seeds,
-// each checked exactly.
-__global__ void k_gw_nearest(const double4* P, uint32_t n, uint32_t* nn) {
+// Start point b of a set (b < GW_BASES): spread over the set's points.
+__device__ __forceinline__ uint32_t gw_base(uint32_t lo, uint32_t hi, uint32_t b) {
+  return lo + b * ((hi - lo) / GW_BASES);
+}
+
+// GW_NN points near each start point of each set, one block per (set,
+// start): the nearest point of each thread's share (by squared distance
+// rounded to FP32, then index), and of those the GW_NN smallest by rank.
+// Any near points do: they only propose seeds, each checked exactly.  The
+// list of (set s, start b) is nn[(s * GW_BASES + b) * (GW_NN + 1) ...], its
+// length last.
+__global__ void k_gw_nearest(const double4* P, const uint32_t* soff, uint32_t* nn_all) {
   __shared__ unsigned long long s_key[GW_THREADS];
-  const double4 o = P[0];
+  const uint32_t set = blockIdx.x / GW_BASES, lo = soff[set], hi = soff[set + 1];
+  const uint32_t ob = gw_base(lo, hi, blockIdx.x % GW_BASES);
+  uint32_t* nn = nn_all + (size_t)blockIdx.x * (GW_NN + 1);
+  if (hi - lo < 2) {
+    if (threadIdx.x == 0) nn[GW_NN] = 0;
+    return;
+  }
+  const double4 o = P[ob];
   unsigned long long best = ~0ull;
-  for (uint32_t j = 1 + threadIdx.x; j < n; j += GW_THREADS) {
+  for (uint32_t j = lo + threadIdx.x; j < hi; j += GW_THREADS) {
+    if (j == ob) continue;
     const double4 q = P[j];
     const double dx = q.x - o.x, dy = q.y - o.y, dz = q.z - o.z;
     const float d2 = (float)(dx * dx + dy * dy + dz * dz);
@@ -230,11 +257,12 @@ __global__ void k_gw_nearest(const double4* P, uint32_t n, uint32_t* nn) {
   if (threadIdx.x == 0) nn[GW_NN] = real < GW_NN ? real : GW_NN;
 }
 
-// Candidate seed simplex c: point 0 and D of the near points (combination
-// number c in lexicographic order), positively oriented; false when flat.
+// Candidate seed simplex c: the set's first point o and D of the near
+// points (combination number c in lexicographic order), positively
+// oriented; false when flat.
 template <int D>
 __device__ bool seed_candidate(const double4* P, PredT<false>& pr, const uint32_t* nn,
-                               uint32_t m, uint32_t c, uint4& v) {
+                               uint32_t m, uint32_t c, uint32_t o, uint4& v) {
   uint32_t idx[3] = {0, 0, 0};
   uint32_t left = c;
   bool found = false;
@@ -253,10 +281,10 @@ __device__ bool seed_candidate(const double4* P, PredT<false>& pr, const uint32_
         }
   }
   if (!found) return false;
-  v = make_uint4(0u, nn[idx[0]], nn[idx[1]], D == 3 ? nn[idx[2]] : NOSLOT);
-  const int o = simplex_orient<D>(P, pr, v);
-  if (o == 0) return false;
-  if (o < 0) {
+  v = make_uint4(o, nn[idx[0]], nn[idx[1]], D == 3 ? nn[idx[2]] : NOSLOT);
+  const int sg = simplex_orient<D>(P, pr, v);
+  if (sg == 0) return false;
+  if (sg < 0) {
     const uint32_t t = v.y;
     v.y = v.z;
     v.z = t;
@@ -264,26 +292,38 @@ __device__ bool seed_candidate(const double4* P, PredT<false>& pr, const uint32_
   return true;
 }
 
-// One wavefront per candidate seed: is its circumsphere empty of every
-// point?  The smallest empty candidate's number is kept.
+// Seed candidates of a set with m near points.
 template <int D>
-__global__ void k_gw_seed(const double4* P, uint32_t n, const uint32_t* nn, uint32_t ncomb,
-                          uint32_t* best, uint32_t* flags) {
+__host__ __device__ __forceinline__ uint32_t seed_combos(uint32_t m) {
+  return D == 2 ? m * (m - 1) / 2 : m * (m - 1) * (m - 2) / 6;
+}
+
+// One wavefront per candidate seed of each (set, start) (ncomb each): is
+// its circumsphere empty of every point of the set?  The smallest empty
+// candidate's number is kept per (set, start).
+template <int D>
+__global__ void k_gw_seed(const double4* P, const uint32_t* soff, uint32_t nsets,
+                          const uint32_t* nn_all, uint32_t ncomb, uint32_t* best_all,
+                          uint32_t* flags) {
   PredT<false> pr;
   pr.init(flags);
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t c = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  if (c >= ncomb) return;
+  const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const uint32_t sb = w / ncomb, c = w % ncomb, set = sb / GW_BASES;
+  if (set >= nsets) return;
+  const uint32_t* nn = nn_all + (size_t)sb * (GW_NN + 1);
   const uint32_t m = nn[GW_NN];
+  if (m < (uint32_t)D || c >= seed_combos<D>(m)) return;
+  const uint32_t lo = soff[set], hi = soff[set + 1];
   uint4 v;
-  if (!seed_candidate<D>(P, pr, nn, m, c, v)) return;
+  if (!seed_candidate<D>(P, pr, nn, m, c, gw_base(lo, hi, sb % GW_BASES), v)) return;
   // only points inside the conservatively enlarged circumball can be
   // strictly inside the sphere (a nearly flat candidate tests them all)
   double sc[3] = {0.0, 0.0, 0.0}, sr = 0.0;
   const bool ball = circumball<D>(P[v.x], P[v.y], P[v.z], P[D == 3 ? v.w : v.z], sc, &sr);
   const double sr2 = sr * sr;
   bool hit = false;
-  for (uint32_t q = lane; q < n && !hit; q += 64) {
+  for (uint32_t q = lo + lane; q < hi && !hit; q += 64) {
     if (ball) {
       const double4 t = P[q];
       const double dx = t.x - sc[0], dy = t.y - sc[1], dz = t.z - sc[2];
@@ -294,13 +334,32 @@ __global__ void k_gw_seed(const double4* P, uint32_t n, const uint32_t* nn, uint
     for (int i = 0; i <= D; i++) vert |= (vget(v, i) == q);
     if (!vert && in_sphere<D>(P, pr, v, q)) hit = true;
   }
-  if (__ballot(hit) == 0ull && lane == 0) atomicMin(best, c);
+  if (__ballot(hit) == 0ull && lane == 0) atomicMin(best_all + sb, c);
+}
+
+// The seed simplex of a set: the empty candidate of its first start point
+// that has one.  False when none has.
+template <int D>
+__device__ bool gw_pick_seed(const double4* P, PredT<false>& pr, const uint32_t* soff,
+                             uint32_t set, const uint32_t* nn_all, const uint32_t* best_all,
+                             uint4& v) {
+  const uint32_t lo = soff[set], hi = soff[set + 1];
+  for (uint32_t b = 0; b < GW_BASES; b++) {
+    const uint32_t sb = set * GW_BASES + b;
+    const uint32_t* nn = nn_all + (size_t)sb * (GW_NN + 1);
+    if (best_all[sb] != GW_NONE &&
+        seed_candidate<D>(P, pr, nn, nn[GW_NN], best_all[sb], gw_base(lo, hi, b), v))
+      return true;
+  }
+  return false;
 }
 
 // Hash set of the simplices found (keys only) and the cell list.
 struct GwState {
   const double4* P;
   uint32_t n;
+  const uint32_t* soff;   // set s: points soff[s] .. soff[s+1]
+  const uint32_t* sof;    // set of every point
   Cell* cells;
   uint32_t cap;
   uint32_t* ncells;
@@ -309,128 +368,107 @@ struct GwState {
   uint32_t* flags;
 };
 
-// Record simplex v unless it is known; true when it is new (then *idx is
-// its cell).
+// Claim simplex v (of set `set`) in the hash set: 1 when it is new, 0 when
+// it is known, -1 when the table is full.
 template <int D>
-__device__ bool gw_record(const GwState& g, const uint4& v, uint32_t* idx) {
-  const unsigned long long key = simplex_key<D>(v);
+__device__ int gw_claim(const GwState& g, const uint4& v, uint32_t set) {
+  const unsigned long long key = simplex_key<D>(v, set, g.soff[set]);
   const uint32_t h = key_hash(key);
   for (uint32_t pr = 0; pr <= g.tmask; pr++) {
     const uint32_t s = (h + pr) & g.tmask;
     const unsigned long long old = atomicCAS(&g.table[s], ~0ull, key);
-    if (old == key) return false;
-    if (old == ~0ull) {
-      const uint32_t c = atomicAdd(g.ncells, 1u);
-      if (c >= g.cap) {
-        atomicOr(g.flags, (uint32_t)GW_FAIL_CAP);
-        return false;
-      }
-      Cell& x = g.cells[c];
-      x.v = v;
-      x.n = make_uint4(0u, 0u, 0u, 0u);
-      x.spare = 0;
-      x.cav = NOKEY;
-      x.shell = NOKEY;
-      x.fwd = ALIVE;
-      x.pos = 0;
-      *idx = c;
-      return true;
-    }
+    if (old == key) return 0;
+    if (old == ~0ull) return 1;
   }
   atomicOr(g.flags, (uint32_t)GW_FAIL_HASH);
-  return false;
+  return -1;
 }
 
-// The seed simplex becomes cell 0; its D+1 facets form the first level.
+__device__ __forceinline__ void gw_cell(Cell& x, const uint4& v) {
+  x.v = v;
+  x.n = make_uint4(0u, 0u, 0u, 0u);
+  x.spare = 0;
+  x.cav = NOKEY;
+  x.shell = NOKEY;
+  x.fwd = ALIVE;
+  x.pos = 0;
+}
+
+// Record simplex v unless it is known; true when it is new (then *idx is
+// its cell, taken from the one counter of the pool).
 template <int D>
-__global__ void k_gw_start(GwState g, const uint32_t* nn, const uint32_t* best,
-                           uint32_t* front, uint32_t* cnt) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (*best == GW_NONE) {
-    atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
-    return;
+__device__ bool gw_record(const GwState& g, const uint4& v, uint32_t set, uint32_t* idx) {
+  if (gw_claim<D>(g, v, set) != 1) return false;
+  const uint32_t c = atomicAdd(g.ncells, 1u);
+  if (c >= g.cap) {
+    atomicOr(g.flags, (uint32_t)GW_FAIL_CAP);
+    return false;
   }
+  gw_cell(g.cells[c], v);
+  *idx = c;
+  return true;
+}
+
+// The seed simplex of every set (one thread per set) becomes a cell; its
+// D+1 facets join the first level.  An empty set is skipped.
+template <int D>
+__global__ void k_gw_start(GwState g, uint32_t nsets, const uint32_t* nn_all,
+                           const uint32_t* best_all, uint32_t* front, uint32_t* cnt) {
+  const uint32_t set = blockIdx.x * blockDim.x + threadIdx.x;
+  if (set >= nsets || g.soff[set] == g.soff[set + 1]) return;
   PredT<false> pr;
   pr.init(g.flags);
   uint4 v;
-  if (!seed_candidate<D>(g.P, pr, nn, nn[GW_NN], *best, v)) {
+  if (!gw_pick_seed<D>(g.P, pr, g.soff, set, nn_all, best_all, v)) {
     atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
     return;
   }
   uint32_t c = 0;
-  if (!gw_record<D>(g, v, &c)) {
+  if (!gw_record<D>(g, v, set, &c)) {
     atomicOr(g.flags, (uint32_t)GW_FAIL_SEED);
     return;
   }
-  for (uint32_t i = 0; i <= (uint32_t)D; i++) front[i] = (c << 2) | i;
-  cnt[0] = D + 1;
+  const uint32_t at = atomicAdd(cnt, (uint32_t)D + 1);
+  for (uint32_t i = 0; i <= (uint32_t)D; i++) front[at + i] = (c << 2) | i;
 }
 
-// One level: every facet of the input list, one wavefront each, finds the
-// simplex beyond it; a simplex not found before is recorded and its other
-// D facets go to the output list.  Facet (c, i) is the facet of cell c
-// opposite its vertex i, searched away from that vertex.
-// With LDS (sets of at most GW_LDS_POINTS points) the block first copies
-// every point into LDS: a facet search is then a chain of LDS reads rather
-// than of L2 loads.
-template <int D, bool LDS>
-__global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32_t* fin,
-                                                         const uint32_t* cnt_in, uint32_t* fout,
-                                                         uint32_t* cnt_out, uint32_t fcap) {
-  extern __shared__ double4 s_pts[];
-  const uint32_t nin = *cnt_in;
-  if (nin == 0 || *g.flags) return;
-  const uint32_t wpb = GW_THREADS / 64;
-  if (blockIdx.x * wpb >= nin) return;
-  const double4* PP = g.P;
-  if (LDS) {
-    for (uint32_t j = threadIdx.x; j < g.n; j += GW_THREADS) s_pts[j] = g.P[j];
-    __syncthreads();
-    PP = s_pts;
-  }
-  PredT<false> pr;
-  pr.init(g.flags);
-  const uint32_t lane = threadIdx.x & 63u;
-  for (uint32_t e = blockIdx.x * wpb + threadIdx.x / 64; e < nin; e += gridDim.x * wpb) {
-    const uint32_t ent = fin[e];
-    const uint32_t c = ent >> 2, i = ent & 3u;
-    // the facet's vertices with two of them swapped: (facet, x) is then
-    // positively oriented exactly for x strictly beyond the facet
-    uint4 t = g.cells[c].v;
-    const int a = i == 0 ? 1 : 0, b = i <= 1 ? 2 : 1;
-    {
-      const uint32_t s = vget(t, a);
-      vput(t, a, vget(t, b));
-      vput(t, b, s);
-    }
+// The search of one facet by one wavefront: facet i of the simplex t (two
+// of its vertices already swapped, so that (facet, x) is positively
+// oriented exactly for x strictly beyond it) among the points lo .. hi of
+// its set; point x is PP[x - pb].  Returns the point beyond the facet whose
+// sphere through it holds no other such point, or GW_NONE (a hull facet);
+// the same in every lane.
+template <int D>
+__device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, uint32_t lo,
+                              uint32_t hi, const uint4& t, uint32_t i, uint32_t lane) {
     // facet points in their slots (slot i takes the candidate)
     PtsX F;
 #pragma unroll
     for (int k = 0; k <= D; k++) {
       F.p[k][0] = F.p[k][1] = F.p[k][2] = 0.0;
       F.key[k] = 0;
-      if (k != (int)i) gw_load(PP, vget(t, k), F.p[k], F.key[k]);
+      if (k != (int)i) gw_load(PP, vget(t, k) - pb, F.p[k], F.key[k]);
     }
     // A first candidate: the least pencil parameter in FP64 over all
     // points beyond the facet (a guess; the exact order decides below).
     uint32_t guess = GW_NONE;
     {
       double cf[3], r2, nrm[3];
-      if (facet_frame<D>(F, i, PP[vget(t, (int)i)], cf, &r2, nrm)) {
+      if (facet_frame<D>(F, i, PP[vget(t, (int)i) - pb], cf, &r2, nrm)) {
         double bnum = 0.0, bden = 1.0;
-        for (uint32_t q0 = lane; q0 < g.n; q0 += 4 * 64) {
+        for (uint32_t q0 = lo + lane; q0 < hi; q0 += 4 * 64) {
           double4 cp[4];
 #pragma unroll
           for (int u = 0; u < 4; u++) {
             const uint32_t q = q0 + 64u * (uint32_t)u;
-            cp[u] = PP[q < g.n ? q : 0u];
+            cp[u] = PP[(q < hi ? q : lo) - pb];
           }
 #pragma unroll
           for (int u = 0; u < 4; u++) {
             const uint32_t q = q0 + 64u * (uint32_t)u;
             const double wx = cp[u].x - cf[0], wy = cp[u].y - cf[1], wz = cp[u].z - cf[2];
             const double h = wx * nrm[0] + wy * nrm[1] + (D == 3 ? wz * nrm[2] : 0.0);
-            if (q >= g.n || !(h > 0.0)) continue;
+            if (q >= hi || !(h > 0.0)) continue;
             // the facet's own points lie on its hyperplane (h is rounding)
             bool vert = false;
 #pragma unroll
@@ -470,7 +508,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
     if (guess != GW_NONE) {
       double qp[3];
       unsigned long long qk;
-      gw_load(PP, guess, qp, qk);
+      gw_load(PP, guess - pb, qp, qk);
       PtsX X = F;
       put_slot<D>(X, i, qp, qk);
       if (pr.template orient<D>(X) > 0) {
@@ -480,21 +518,22 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
         uint4 tq = t;
         vput(tq, (int)i, guess);
         double r = 0.0;
-        ball = circumball<D>(PP[tq.x], PP[tq.y], PP[tq.z], PP[D == 3 ? tq.w : tq.z], sc, &r);
+        ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
+                            PP[(D == 3 ? tq.w : tq.z) - pb], sc, &r);
         sr2 = r * r;
       }
     }
-    for (uint32_t q0 = lane; q0 < g.n; q0 += 4 * 64) {
+    for (uint32_t q0 = lo + lane; q0 < hi; q0 += 4 * 64) {
       double4 cp[4];
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const uint32_t q = q0 + 64u * (uint32_t)u;
-        cp[u] = PP[q < g.n ? q : 0u];
+        cp[u] = PP[(q < hi ? q : lo) - pb];
       }
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const uint32_t q = q0 + 64u * (uint32_t)u;
-        if (q >= g.n || q == best) continue;
+        if (q >= hi || q == best) continue;
         if (ball) {
           const double dx = cp[u].x - sc[0], dy = cp[u].y - sc[1], dz = cp[u].z - sc[2];
           if (dx * dx + dy * dy + dz * dz > sr2) continue;
@@ -522,8 +561,8 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
           uint4 tq = t;
           vput(tq, (int)i, q);
           double r = 0.0;
-          ball = circumball<D>(PP[tq.x], PP[tq.y], PP[tq.z], PP[D == 3 ? tq.w : tq.z], sc,
-                               &r);
+          ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
+                               PP[(D == 3 ? tq.w : tq.z) - pb], sc, &r);
           sr2 = r * r;
         }
       }
@@ -536,7 +575,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
       if (o == GW_NONE || o == best) continue;
       double op[3];
       unsigned long long ok;
-      gw_load(PP, o, op, ok);
+      gw_load(PP, o - pb, op, ok);
       bool take = best == GW_NONE;
       if (!take) {
         PtsX X = F;
@@ -551,10 +590,54 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
         bk = ok;
       }
     }
+    return best;
+}
+
+// One level: every facet of the input list, one wavefront each, finds the
+// simplex beyond it; a simplex not found before is recorded and its other
+// D facets go to the output list.  Facet (c, i) is the facet of cell c
+// opposite its vertex i, searched away from that vertex.
+// With LDS (sets of at most GW_LDS_POINTS points) the block first copies
+// every point into LDS: a facet search is then a chain of LDS reads rather
+// than of L2 loads.
+template <int D, bool LDS>
+__global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32_t* fin,
+                                                         const uint32_t* cnt_in, uint32_t* fout,
+                                                         uint32_t* cnt_out, uint32_t fcap) {
+  extern __shared__ double4 s_pts[];
+  const uint32_t nin = *cnt_in;
+  if (nin == 0 || *g.flags) return;
+  const uint32_t wpb = GW_THREADS / 64;
+  if (blockIdx.x * wpb >= nin) return;
+  const double4* PP = g.P;
+  if (LDS) {
+    for (uint32_t j = threadIdx.x; j < g.n; j += GW_THREADS) s_pts[j] = g.P[j];
+    __syncthreads();
+    PP = s_pts;
+  }
+  PredT<false> pr;
+  pr.init(g.flags);
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint32_t e = blockIdx.x * wpb + threadIdx.x / 64; e < nin; e += gridDim.x * wpb) {
+    const uint32_t ent = fin[e];
+    const uint32_t c = ent >> 2, i = ent & 3u;
+    // the facet's vertices with two of them swapped: (facet, x) is then
+    // positively oriented exactly for x strictly beyond the facet
+    uint4 t = g.cells[c].v;
+    const int a = i == 0 ? 1 : 0, b = i <= 1 ? 2 : 1;
+    // the points of the facet's set
+    const uint32_t set = g.sof[vget(t, a)];
+    const uint32_t lo = g.soff[set], hi = g.soff[set + 1];
+    {
+      const uint32_t s = vget(t, a);
+      vput(t, a, vget(t, b));
+      vput(t, b, s);
+    }
+    const uint32_t best = gw_search<D>(pr, PP, 0, lo, hi, t, i, lane);
     if (lane == 0 && best != GW_NONE) {
       vput(t, (int)i, best);
       uint32_t nc = 0;
-      if (gw_record<D>(g, t, &nc)) {
+      if (gw_record<D>(g, t, set, &nc)) {
         const uint32_t at = atomicAdd(cnt_out, (uint32_t)D);
         if (at + D > fcap) {
           atomicOr(g.flags, (uint32_t)GW_FAIL_CAP);
@@ -568,39 +651,52 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32
   }
 }
 
+// The set of every point.
+__global__ void k_gw_setof(const uint32_t* soff, uint32_t* sof) {
+  const uint32_t set = blockIdx.x, lo = soff[set], hi = soff[set + 1];
+  for (uint32_t j = lo + threadIdx.x; j < hi; j += blockDim.x) sof[j] = set;
+}
+
 }  // namespace
 
-int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* levels,
-              hipStream_t st) {
+int gift_wrap_sets(const double4* P, uint32_t n, const uint32_t* soff, uint32_t nsets,
+                   uint32_t max_set, int D, CellPool& pool, uint32_t* levels, hipStream_t st) {
   *levels = 0;
-  if (n < (uint32_t)D + 2 || n > GW_MAX_POINTS || (D != 2 && D != 3)) return DT_E_NOT_READY;
+  if ((D != 2 && D != 3) || nsets == 0 || n < (uint32_t)D + 2 || max_set > GW_MAX_POINTS)
+    return DT_E_NOT_READY;
+  // the set's number and D+1 local indices share one 64-bit key
+  if ((uint64_t)nsets > (1ull << (64 - (D + 1) * GW_LOCAL_BITS))) return DT_E_NOT_READY;
   // about 6.8 n simplices in 3D and 2 n in 2D; room for far more
-  const size_t cap = (size_t)n * (D == 3 ? 12 : 4) + 64;
+  const size_t cap = (size_t)n * (D == 3 ? 12 : 4) + (size_t)64 * nsets;
+  if (cap >= (1ull << 30)) return DT_E_NOT_READY;
   size_t tsize = 64;
   while (tsize < 2 * cap) tsize <<= 1;
   const size_t fcap = cap * (size_t)D + 8;
-  DevBuf nn, best, flags, table, fa, fb, cnt;
+  DevBuf nn, best, flags, table, fa, fb, cnt, sof;
   DT_TRY(pool.cells.alloc(cap * sizeof(Cell)));
   DT_TRY(pool.set_cell0.alloc(16));
-  DT_TRY(nn.alloc((GW_NN + 1) * 4));
-  DT_TRY(best.alloc(16));
+  DT_TRY(nn.alloc((size_t)nsets * GW_BASES * (GW_NN + 1) * 4));
+  DT_TRY(best.alloc((size_t)nsets * GW_BASES * 4));
   DT_TRY(flags.alloc(16));
   DT_TRY(table.alloc(tsize * 8));
   DT_TRY(fa.alloc(fcap * 4));
   DT_TRY(fb.alloc(fcap * 4));
   DT_TRY(cnt.alloc((size_t)(GW_MAX_LEVELS + 1) * 4 + 4));
+  DT_TRY(sof.alloc((size_t)n * 4));
   uint32_t* ncells = cnt.as<uint32_t>() + GW_MAX_LEVELS + 1;
-  DT_HIP(hipMemsetAsync(best.p, 0xFF, 4, st));
+  DT_HIP(hipMemsetAsync(best.p, 0xFF, (size_t)nsets * GW_BASES * 4, st));
   DT_HIP(hipMemsetAsync(flags.p, 0, 4, st));
   DT_HIP(hipMemsetAsync(table.p, 0xFF, tsize * 8, st));
   DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)(GW_MAX_LEVELS + 2) * 4, st));
   DT_HIP(hipMemsetAsync(pool.set_cell0.p, 0, 4, st));
-  GwState g{P, n, pool.cells.as<Cell>(), (uint32_t)cap, ncells,
+  hipLaunchKernelGGL(k_gw_setof, dim3(nsets), dim3(GW_THREADS), 0, st, soff, sof.as<uint32_t>());
+  GwState g{P, n, soff, sof.as<uint32_t>(), pool.cells.as<Cell>(), (uint32_t)cap, ncells,
             table.as<unsigned long long>(), (uint32_t)(tsize - 1), flags.as<uint32_t>()};
-  const uint32_t m = n - 1 < GW_NN ? n - 1 : GW_NN;
-  const uint32_t ncomb = D == 2 ? m * (m - 1) / 2 : m * (m - 1) * (m - 2) / 6;
-  hipLaunchKernelGGL(k_gw_nearest, dim3(1), dim3(GW_THREADS), 0, st, P, n, nn.as<uint32_t>());
-  const uint32_t sb = (ncomb * 64 + GW_THREADS - 1) / GW_THREADS;
+  const uint32_t ncomb = D == 2 ? seed_combos<2>(GW_NN) : seed_combos<3>(GW_NN);
+  hipLaunchKernelGGL(k_gw_nearest, dim3(nsets * GW_BASES), dim3(GW_THREADS), 0, st, P, soff,
+                     nn.as<uint32_t>());
+  const uint64_t sw = (uint64_t)nsets * GW_BASES * ncomb;
+  const uint32_t sb = (uint32_t)((sw * 64 + GW_THREADS - 1) / GW_THREADS);
 #define GW_LAUNCH(K, ...)                                                                 \
   do {                                                                                    \
     if (D == 2) hipLaunchKernelGGL((K<2>), __VA_ARGS__);                                  \
@@ -611,17 +707,18 @@ int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* lev
     if (D == 2) hipLaunchKernelGGL((K<2, L>), __VA_ARGS__);                               \
     else hipLaunchKernelGGL((K<3, L>), __VA_ARGS__);                                      \
   } while (0)
-  GW_LAUNCH(k_gw_seed, dim3(sb), dim3(GW_THREADS), 0, st, P, n, nn.as<uint32_t>(), ncomb,
-            best.as<uint32_t>(), flags.as<uint32_t>());
-  GW_LAUNCH(k_gw_start, dim3(1), dim3(64), 0, st, g, nn.as<uint32_t>(), best.as<uint32_t>(),
-            fa.as<uint32_t>(), cnt.as<uint32_t>());
+  GW_LAUNCH(k_gw_seed, dim3(sb), dim3(GW_THREADS), 0, st, P, soff, nsets, nn.as<uint32_t>(),
+            ncomb, best.as<uint32_t>(), flags.as<uint32_t>());
+  GW_LAUNCH(k_gw_start, dim3((nsets + 63) / 64), dim3(64), 0, st, g, nsets, nn.as<uint32_t>(),
+            best.as<uint32_t>(), fa.as<uint32_t>(), cnt.as<uint32_t>());
   DT_HIP(hipGetLastError());
+  const bool lds = nsets == 1 && n <= GW_LDS_POINTS;
   uint32_t lev = 0;
   for (;;) {
     for (uint32_t r = 0; r < GW_GROUP && lev < GW_MAX_LEVELS; r++, lev++) {
       const uint32_t* fin = (lev & 1u) ? fb.as<uint32_t>() : fa.as<uint32_t>();
       uint32_t* fout = (lev & 1u) ? fa.as<uint32_t>() : fb.as<uint32_t>();
-      if (n <= GW_LDS_POINTS)
+      if (lds)
         GW_LAUNCH_LDS(k_gw_level, true, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS),
                       (size_t)n * sizeof(double4), st, g, fin, cnt.as<uint32_t>() + lev, fout,
                       cnt.as<uint32_t>() + lev + 1, (uint32_t)fcap);
@@ -635,7 +732,10 @@ int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* lev
     DT_HIP(hipMemcpyAsync(&h[0], cnt.as<uint32_t>() + lev, 4, hipMemcpyDeviceToHost, st));
     DT_HIP(hipMemcpyAsync(&h[1], flags.p, 4, hipMemcpyDeviceToHost, st));
     DT_HIP(hipStreamSynchronize(st));
-    if (h[1]) return DT_E_NOT_READY;          // no seed, or a capacity: fall back
+    if (h[1]) {                               // no seed, or a capacity: fall back
+      if (getenv("DT_DEBUG")) fprintf(stderr, "[gwrap] failure bits %x at level %u\n", h[1], lev);
+      return DT_E_NOT_READY;
+    }
     if (h[0] == 0) break;
     if (lev >= GW_MAX_LEVELS) return DT_E_NOT_READY;
   }
@@ -653,6 +753,18 @@ int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* lev
   for (uint32_t x = 0; x <= lev; x++) nl += hc[x] ? 1u : 0u;
   *levels = nl;
   return DT_OK;
+}
+
+int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* levels,
+              hipStream_t st) {
+  *levels = 0;
+  if (n < (uint32_t)D + 2 || n > GW_MAX_POINTS || (D != 2 && D != 3)) return DT_E_NOT_READY;
+  DevBuf soff;
+  DT_TRY(soff.alloc(8));
+  const uint32_t h[2] = {0u, n};
+  DT_HIP(hipMemcpyAsync(soff.p, h, 8, hipMemcpyHostToDevice, st));
+  // (h outlives the copy: gift_wrap_sets synchronises the stream)
+  return gift_wrap_sets(P, n, soff.as<uint32_t>(), 1, n, D, pool, levels, st);
 }
 
 }  // namespace dtk

@@ -1,4 +1,4 @@
-// Gift-wrapping triangulation of one small point set (dt_gwrap.hip).
+// Gift-wrapping triangulation of small point sets (dt_gwrap.hip).
 #pragma once
 #include "dt_internal.hpp"
 
@@ -16,5 +16,13 @@ constexpr uint32_t GW_MAX_POINTS = 8192;
 // triangulates the set by parallel insertion instead.  Synchronises `st`.
 int gift_wrap(const double4* P, uint32_t n, int D, CellPool& pool, uint32_t* levels,
               hipStream_t st);
+
+// The same for nsets independent sets wrapped together: set s is the points
+// P[soff[s] .. soff[s+1]) (soff on the device; a set is empty or holds
+// D+2 to GW_MAX_POINTS points, max_set the largest), and every cell's
+// vertices lie in one set.  DT_E_NOT_READY when any set cannot be wrapped
+// (or more sets than the simplex keys can tell apart).  Synchronises `st`.
+int gift_wrap_sets(const double4* P, uint32_t n, const uint32_t* soff, uint32_t nsets,
+                   uint32_t max_set, int D, CellPool& pool, uint32_t* levels, hipStream_t st);
 
 }  // namespace dtk

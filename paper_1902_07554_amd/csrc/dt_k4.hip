@@ -393,9 +393,14 @@ __device__ uint32_t walk(const K4Args& a, PredT<F32>& pr, uint32_t c, uint32_t q
 // One thread per set: the first D+1 affinely independent points (in index
 // order) form the initial cell, plus one hull cell per facet.
 template <int D>
-__global__ void k4_init_sets(K4Args a) {
+__global__ void k4_init_sets(K4Args a, const uint32_t* seeded0) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.nsets) return;
+  // a set started from a seed (its first cell given)
+  if (seeded0 && seeded0[s] != DONE) {
+    a.set_cell0[s] = seeded0[s];
+    return;
+  }
   PredT<false> pr;
   pr.init(&a.ctr->flags);
   uint32_t lo = a.set_off[s], hi = a.set_off[s + 1];
@@ -1534,6 +1539,12 @@ __global__ void k_seed_ridges(Cell* cells, SeedTab r, uint32_t* flags) {
 
 static inline uint32_t nblk(uint32_t n);
 
+// The wrapped simplices of the seed points sidx (their indices into the
+// job's points) as cells of the pool, with their links and a hull cell on
+// every hull facet.  DT_OK: *ncells cells made.
+static int seed_link(const LocalJob& job, const K4Args& a, const DevBuf& sidx, CellPool& wp,
+                     uint32_t* ncells, hipStream_t st);
+
 // Build the seed of a single set into the pool and the point records
 // (ploc, vcell).  DT_OK: *ncells cells made, *thresh the first activation
 // threshold above the seed; DT_E_NOT_READY: not seeded (the caller starts
@@ -1563,6 +1574,148 @@ static int seed_single_set(const LocalJob& job, const K4Args& a, uint32_t* ncell
   uint32_t levels = 0;
   const int g = gift_wrap(spts.as<double4>(), m, D, wp, &levels, st);
   if (g != DT_OK) return g;
+  DT_TRY(seed_link(job, a, sidx, wp, ncells, st));
+  const uint64_t t1 = (uint64_t)T + T / 2;
+  *thresh = (uint32_t)(t1 > PMAX ? PMAX : t1);
+  return DT_OK;
+}
+
+// Seeds for the sets of a batched run (the local triangulations of the
+// divide, a batch of independent sets).  Every set of at least
+// SEED_SET_MIN points starts from the triangulation of its points below a
+// common priority threshold T, all sets gift-wrapped together; a set whose
+// seed would be smaller than SEED_SET_MIN_SEED or larger than the wrap
+// takes starts from one simplex as before.  The seeds' cells are made
+// exactly as for a single set.  A facet search reads every point of its
+// set, so the wrap's cost grows with the seed size times the seeds' total:
+// a set of average size gets SEED_SET_POINTS, and fewer when the seeds
+// together would pass SEED_TOTAL (measured on 4M clustered points: 1024
+// per set pays at k = 16 and 64, where 256 sets of 1024 cost more than
+// they save; 128 per set still pays there).
+constexpr uint32_t SEED_SET_POINTS = 1024;
+constexpr uint32_t SEED_TOTAL = 32768;
+constexpr uint32_t SEED_SET_MIN = 8192;
+constexpr uint32_t SEED_SET_MIN_SEED = 64;
+
+__global__ void k_seed_count(uint32_t npts, uint32_t T, const uint32_t* pset, uint32_t* scnt) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npts && prio_of(p) < T) atomicAdd(&scnt[pset[p]], 1u);
+}
+
+__global__ void k_seed_flag(uint32_t npts, uint32_t T, const uint32_t* pset,
+                            const uint32_t* smark, uint32_t* flag) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npts) flag[p] = (prio_of(p) < T && smark[pset[p]]) ? 1u : 0u;
+}
+
+__global__ void k_seed_gather(const double4* pts, const uint32_t* sidx, uint32_t m,
+                              double4* spts) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) spts[i] = pts[sidx[i]];
+}
+
+// The first cell of every seeded set: its wrapped cell of least index.
+__global__ void k_seed_cell0(const Cell* wc, uint32_t nf, const uint32_t* sidx,
+                             const uint32_t* pset, uint32_t* seeded0) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nf) atomicMin(&seeded0[pset[sidx[wc[c].v.x]]], c);
+}
+
+static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint32_t* ncells,
+                     uint32_t* thresh, uint32_t* nseeded, hipStream_t st) {
+  const int D = job.D;
+  const uint32_t npts = job.npts, ns = job.nsets;
+  const uint32_t PMAX = 1u << 20;
+  *nseeded = 0;
+  std::vector<uint32_t> off(ns + 1);
+  DT_HIP(hipMemcpyAsync(off.data(), job.set_off, (size_t)(ns + 1) * 4, hipMemcpyDeviceToHost,
+                        st));
+  DT_HIP(hipStreamSynchronize(st));
+  uint32_t nmax = 0, nbig = 0;
+  uint64_t pbig = 0;
+  for (uint32_t i = 0; i < ns; i++) {
+    const uint32_t n = off[i + 1] - off[i];
+    nmax = std::max(nmax, n);
+    if (n >= SEED_SET_MIN) {
+      nbig++;
+      pbig += n;
+    }
+  }
+  if (nbig == 0) return DT_E_NOT_READY;
+  // the seed of a set of average size among those seeded, at most 3/4 of
+  // the wrap's limit in the largest
+  const uint64_t per = std::min<uint64_t>(SEED_SET_POINTS, SEED_TOTAL / nbig);
+  uint64_t T = (uint64_t)PMAX * per * nbig / pbig;
+  T = std::min<uint64_t>(T, (uint64_t)PMAX * (GW_MAX_POINTS * 3 / 4) / nmax);
+  if (T < 16) return DT_E_NOT_READY;
+  DevBuf scnt, smark, flag, sidx, spts, soff;
+  DT_TRY(scnt.alloc((size_t)ns * 4));
+  DT_HIP(hipMemsetAsync(scnt.p, 0, (size_t)ns * 4, st));
+  hipLaunchKernelGGL(k_seed_count, dim3(nblk(npts)), dim3(BLOCK), 0, st, npts, (uint32_t)T,
+                     job.pset, scnt.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  std::vector<uint32_t> cnt(ns), mark(ns), so(ns + 1);
+  DT_HIP(hipMemcpyAsync(cnt.data(), scnt.p, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
+  DT_HIP(hipStreamSynchronize(st));
+  uint32_t m = 0, mmax = 0, nsd = 0;
+  for (uint32_t i = 0; i < ns; i++) {
+    mark[i] = (off[i + 1] - off[i] >= SEED_SET_MIN && cnt[i] >= SEED_SET_MIN_SEED &&
+               cnt[i] <= GW_MAX_POINTS) ? 1u : 0u;
+    so[i] = m;
+    if (mark[i]) {
+      m += cnt[i];
+      mmax = std::max(mmax, cnt[i]);
+      nsd++;
+    }
+  }
+  so[ns] = m;
+  // seed indices share 21-bit fields in the facet keys
+  if (nsd == 0 || m >= (1u << SEED_KEY_BITS)) return DT_E_NOT_READY;
+  DT_TRY(smark.alloc((size_t)ns * 4));
+  DT_TRY(soff.alloc((size_t)(ns + 1) * 4));
+  DT_TRY(flag.alloc((size_t)npts * 4));
+  DT_HIP(hipMemcpyAsync(smark.p, mark.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+  DT_HIP(hipMemcpyAsync(soff.p, so.data(), (size_t)(ns + 1) * 4, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_seed_flag, dim3(nblk(npts)), dim3(BLOCK), 0, st, npts, (uint32_t)T,
+                     job.pset, smark.as<uint32_t>(), flag.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  uint32_t mc = 0;
+  DT_TRY(compact_indices(flag.as<uint32_t>(), npts, sidx, &mc, st));
+  if (mc != m) return DT_E_INTERNAL;
+  DT_TRY(spts.alloc((size_t)m * sizeof(double4)));
+  hipLaunchKernelGGL(k_seed_gather, dim3(nblk(m)), dim3(BLOCK), 0, st, job.pts,
+                     sidx.as<uint32_t>(), m, spts.as<double4>());
+  DT_HIP(hipGetLastError());
+  CellPool wp;
+  uint32_t levels = 0;
+  const bool dbg = getenv("DT_DEBUG") != nullptr;
+  const int g = gift_wrap_sets(spts.as<double4>(), m, soff.as<uint32_t>(), ns, mmax, D, wp,
+                               &levels, st);
+  if (dbg)
+    fprintf(stderr, "[seed] sets %u of %u, %u points (largest %u), T %llu: wrap %d, %u levels\n",
+            nsd, ns, m, mmax, (unsigned long long)T, g, levels);
+  if (g != DT_OK) return g;
+  const int l = seed_link(job, a, sidx, wp, ncells, st);
+  if (dbg && l != DT_OK) fprintf(stderr, "[seed] link %d\n", l);
+  DT_TRY(l);
+  DT_TRY(seeded0.alloc((size_t)ns * 4));
+  DT_HIP(hipMemsetAsync(seeded0.p, 0xFF, (size_t)ns * 4, st));
+  hipLaunchKernelGGL(k_seed_cell0, dim3(nblk(wp.ncells)), dim3(BLOCK), 0, st,
+                     wp.cells.as<Cell>(), wp.ncells, sidx.as<uint32_t>(), job.pset,
+                     seeded0.as<uint32_t>());
+  DT_HIP(hipGetLastError());
+  const uint64_t t1 = T + T / 2;
+  *thresh = (uint32_t)(t1 > PMAX ? PMAX : t1);
+  *nseeded = nsd;
+  return DT_OK;
+}
+
+static int seed_link(const LocalJob& job, const K4Args& a, const DevBuf& sidx, CellPool& wp,
+                     uint32_t* ncells, hipStream_t st) {
+  const int D = job.D;
+  DevBuf flags;
+  DT_TRY(flags.alloc(16));
+  DT_HIP(hipMemsetAsync(flags.p, 0, 4, st));
   const uint32_t nf = wp.ncells;
   if (nf == 0 || (uint64_t)nf * 2 + 64 > a.cap) return DT_E_NOT_READY;
   // facets: (D+1) per cell, at most half of them twins
@@ -1611,8 +1764,6 @@ static int seed_single_set(const LocalJob& job, const K4Args& a, uint32_t* ncell
   DT_HIP(hipStreamSynchronize(st));
   if (h[1]) return DT_E_INTERNAL;
   *ncells = h[0];
-  const uint64_t t1 = (uint64_t)T + T / 2;
-  *thresh = (uint32_t)(t1 > PMAX ? PMAX : t1);
   return DT_OK;
 }
 
@@ -1682,8 +1833,10 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
   a.ginfo = nullptr;
   a.gcap = 0;
 
-  // a large single set starts from a gift-wrapped seed (see above)
+  // a large single set, and every large set of a batched run, starts from
+  // a gift-wrapped seed (see above)
   uint32_t seed_cells = 0, seed_thresh = 0;
+  DevBuf seeded0;
   // (not inside a caller's workspace: the seed's scratch is not counted
   // in its size)
   if (job.nsets == 1 && job.seed && npts >= SEED_MIN_SET && (D == 2 || D == 3) &&
@@ -1702,12 +1855,28 @@ int k4_run(const LocalJob& job, CellPool& pool, Counters* dctr, Counters* hctr, 
     } else {
       return sr;
     }
+  } else if (job.nsets > 1 && job.seed && (D == 2 || D == 3) && workspace() == nullptr) {
+    uint32_t nsd = 0;
+    const int sr = seed_sets(job, a, seeded0, &seed_cells, &seed_thresh, &nsd, st);
+    if (sr == DT_OK) {
+      DT_HIP(hipMemcpyAsync(&dctr->cells, &seed_cells, 4, hipMemcpyHostToDevice, st));
+      ks.seeded = nsd;
+    } else if (sr == DT_E_NOT_READY || sr == DT_E_INTERNAL) {
+      seed_cells = 0;
+      seeded0 = DevBuf();
+      DT_HIP(hipMemsetAsync(ploc.p, 0, (size_t)npts * 4, st));
+      DT_HIP(hipMemsetAsync(dctr, 0, sizeof(Counters), st));
+    } else {
+      return sr;
+    }
   }
-  if (!seed_cells) {
+  if (!seed_cells || seeded0.p) {
     if (D == 2)
-      hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_init_sets<2>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a,
+                         seeded0.as<uint32_t>());
     else
-      hipLaunchKernelGGL(k4_init_sets<3>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a);
+      hipLaunchKernelGGL(k4_init_sets<3>, dim3(nblk(job.nsets)), dim3(BLOCK), 0, st, a,
+                         seeded0.as<uint32_t>());
   }
   hipLaunchKernelGGL(k4_place_init, dim3(nblk(npts)), dim3(BLOCK), 0, st, a);
   DT_HIP(hipGetLastError());

@@ -430,7 +430,20 @@ __device__ __forceinline__ void border_cell(const double4* P, const uint32_t* ps
   } else {
     finite = true;
     double ctr[3], r = 0.0;
-    const bool sliver = !circumball<D>(P[v[0]], P[v[1]], P[v[2]], P[v[D == 3 ? 3 : 2]], ctr, &r);
+    // the ball from the vertices in index order, so that its rounding (and
+    // the decisions near the margins) depends on the simplex alone, not on
+    // the order in which its cell lists them
+    uint32_t w[4] = {v[0], v[1], v[2], v[3]};
+#pragma unroll
+    for (int i = 1; i <= D; i++)
+#pragma unroll
+      for (int j = i; j > 0; j--)
+        if (w[j] < w[j - 1]) {
+          const uint32_t t = w[j];
+          w[j] = w[j - 1];
+          w[j - 1] = t;
+        }
+    const bool sliver = !circumball<D>(P[w[0]], P[w[1]], P[w[2]], P[w[D == 3 ? 3 : 2]], ctr, &r);
     if (sliver) {
       flag = true;
     } else if (R.kind == BORDER_VORONOI && R.margin) {

@@ -249,3 +249,38 @@ def test_single_set_seeded_by_gift_wrap(dtlib, dim, kind, n, prec):
     ref = dtlib.triangulate(p, k=1, precision=prec, gift_wrap=-1)
     assert ref.stats()["seeded_sets"] == 0
     assert np.array_equal(_rows(ref), got)
+
+
+@pytest.mark.parametrize("dim,prec", [(3, "fp32"), (3, "fp64"), (2, "fp32")])
+def test_batch_sets_seeded_by_gift_wrap(dtlib, dim, prec):
+    """Every set of a batched run with at least 8192 points starts from the
+    gift-wrapped triangulation of its points below a common priority
+    threshold (all sets wrapped together); smaller sets start from one
+    simplex.  Each set's simplices are the oracle's, and the same as when
+    every set starts from one simplex.  The sets mix distributions, a
+    lattice (every tie perturbed) and a lattice moved by 2^-30 steps."""
+    side = 24 if dim == 3 else 110
+    sets = [inputs.make("bubbles", 15_000, dim, seed=11),
+            inputs.make("uniform", 9_000, dim, seed=12),
+            inputs.make("normal", 600, dim, seed=13),          # small: one simplex
+            inputs.lattice(side, dim, seed=14),
+            inputs.jittered_lattice(side - 2, dim, 2.0 ** -30, seed=15),
+            inputs.make("uniform", 3_000, dim, seed=16),       # small: one simplex
+            inputs.make("normal", 20_000, dim, seed=17)]
+    sizes = [len(x) for x in sets]
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    pts = np.concatenate(sets)
+    ids = np.concatenate([np.arange(n) for n in sizes]).astype(np.int64)
+    print(f"[seed-sets] dim={dim} {prec} sizes={sizes}", flush=True)
+    res = dtlib.batch_triangulate(pts, offsets, ids=ids, precision=prec)
+    assert res.stats()["seeded_sets"] == sum(1 for n in sizes if n >= 8192)
+    ref = dtlib.batch_triangulate(pts, offsets, ids=ids, precision=prec, gift_wrap=-1)
+    assert ref.stats()["seeded_sets"] == 0
+    rows, so = res.rows(), res.set_offsets(len(sizes))
+    rrows, rso = ref.rows(), ref.set_offsets(len(sizes))
+    for s in range(len(sizes)):
+        got = oracle.canonical(rows[so[s]:so[s + 1]])
+        want = oracle.delaunay(sets[s])
+        assert np.array_equal(got, want), s
+        assert np.array_equal(oracle.canonical(rrows[rso[s]:rso[s + 1]]), got), s
+
