@@ -46,6 +46,7 @@
 #include "dt_internal.hpp"
 #include "dt_pred.hpp"
 #include "dt_gwrap.hpp"
+#include "dt_prims.hpp"
 
 #include <stdio.h>
 #include <stdlib.h>
@@ -63,6 +64,7 @@ constexpr uint32_t GW_MAX_LEVELS = 4096;
 constexpr uint32_t GW_THREADS = 256;        // level kernel: four facets per block
 constexpr uint32_t GW_LEVEL_BLOCKS = 1024;  // grid of the level kernel (a grid-stride loop)
 constexpr uint32_t GW_GROUP = 8;            // levels launched between two reads of the counters
+constexpr uint32_t GW_CHUNK = 64;           // facets per block between two allocations (at most)
 constexpr uint32_t GW_LDS_POINTS = 2048;    // a single set this small is copied into LDS (64 KB)
 constexpr int GW_LOCAL_BITS = 13;           // set-local point index in simplex keys (8192 points)
 
@@ -172,7 +174,7 @@ __device__ __forceinline__ bool facet_frame(const PtsX& F, uint32_t i, const dou
 // packed into one key.
 template <int D>
 __device__ __forceinline__ unsigned long long simplex_key(const uint4& v, uint32_t set,
-                                                          uint32_t base) {
+                                                          uint32_t base, int bits) {
   uint32_t k[4] = {v.x - base, v.y - base, v.z - base, D == 3 ? v.w - base : 0u};
 #pragma unroll
   for (int i = 1; i <= D; i++)
@@ -185,7 +187,7 @@ __device__ __forceinline__ unsigned long long simplex_key(const uint4& v, uint32
       }
   unsigned long long key = (unsigned long long)set;
 #pragma unroll
-  for (int i = 0; i <= D; i++) key = (key << GW_LOCAL_BITS) | (unsigned long long)k[i];
+  for (int i = 0; i <= D; i++) key = (key << bits) | (unsigned long long)k[i];
   return key;
 }
 
@@ -354,6 +356,15 @@ __device__ bool gw_pick_seed(const double4* P, PredT<false>& pr, const uint32_t*
   return false;
 }
 
+// Uniform grid over each set's points, the points sorted by cell: for set
+// s, meta[4s ..] = its lower corner and the inverse cell edge, dims[4s ..]
+// = the cells per axis and the index of its first cell; cell c holds the
+// points cstart[c] .. cstart[c+1].
+struct GwGrid {
+  const double* meta;
+  const int* dims;
+  const uint32_t* cstart;
+};
 // Hash set of the simplices found (keys only) and the cell list.
 struct GwState {
   const double4* P;
@@ -366,13 +377,16 @@ struct GwState {
   unsigned long long* table;
   uint32_t tmask;
   uint32_t* flags;
+  int kbits;              // bits of a set-local index in the simplex keys
+  GwGrid grid;            // used when has_grid
+  bool has_grid;
 };
 
 // Claim simplex v (of set `set`) in the hash set: 1 when it is new, 0 when
 // it is known, -1 when the table is full.
 template <int D>
 __device__ int gw_claim(const GwState& g, const uint4& v, uint32_t set) {
-  const unsigned long long key = simplex_key<D>(v, set, g.soff[set]);
+  const unsigned long long key = simplex_key<D>(v, set, g.soff[set], g.kbits);
   const uint32_t h = key_hash(key);
   for (uint32_t pr = 0; pr <= g.tmask; pr++) {
     const uint32_t s = (h + pr) & g.tmask;
@@ -413,7 +427,8 @@ __device__ bool gw_record(const GwState& g, const uint4& v, uint32_t set, uint32
 // D+1 facets join the first level.  An empty set is skipped.
 template <int D>
 __global__ void k_gw_start(GwState g, uint32_t nsets, const uint32_t* nn_all,
-                           const uint32_t* best_all, uint32_t* front, uint32_t* cnt) {
+                           const uint32_t* best_all, uint32_t* front, uint32_t* cnt,
+                           uint32_t* first) {
   const uint32_t set = blockIdx.x * blockDim.x + threadIdx.x;
   if (set >= nsets || g.soff[set] == g.soff[set + 1]) return;
   PredT<false> pr;
@@ -430,58 +445,75 @@ __global__ void k_gw_start(GwState g, uint32_t nsets, const uint32_t* nn_all,
   }
   const uint32_t at = atomicAdd(cnt, (uint32_t)D + 1);
   for (uint32_t i = 0; i <= (uint32_t)D; i++) front[at + i] = (c << 2) | i;
+  if (first) first[set] = c;
+}
+
+constexpr uint32_t GW_BALL_CELLS = 512;     // larger balls scan the whole set
+
+__device__ __forceinline__ int gw_coord(double x, double lo, double inv, int g) {
+  const double f = (x - lo) * inv;
+  if (!(f >= 0.0)) return 0;
+  return f >= (double)g ? g - 1 : (int)f;
 }
 
 // The search of one facet by one wavefront: facet i of the simplex t (two
 // of its vertices already swapped, so that (facet, x) is positively
 // oriented exactly for x strictly beyond it) among the points lo .. hi of
-// its set; point x is PP[x - pb].  Returns the point beyond the facet whose
-// sphere through it holds no other such point, or GW_NONE (a hull facet);
-// the same in every lane.
+// set `set`; point x is PP[x - pb].  Returns the point beyond the facet
+// whose sphere through it holds no other such point, or GW_NONE (a hull
+// facet); the same in every lane.  With a grid, the first candidate comes
+// from the cells around the facet's circumcentre and the exact pass reads
+// only the cells under the ball through the facet and that candidate (any
+// point that comes before it lies strictly inside that sphere); without
+// one, or when the ball covers too many cells, every point is read.
 template <int D>
 __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, uint32_t lo,
-                              uint32_t hi, const uint4& t, uint32_t i, uint32_t lane) {
-    // facet points in their slots (slot i takes the candidate)
-    PtsX F;
+                              uint32_t hi, const uint4& t, uint32_t i, uint32_t lane,
+                              const GwGrid& G, bool grid, uint32_t set) {
+  // facet points in their slots (slot i takes the candidate)
+  PtsX F;
 #pragma unroll
-    for (int k = 0; k <= D; k++) {
-      F.p[k][0] = F.p[k][1] = F.p[k][2] = 0.0;
-      F.key[k] = 0;
-      if (k != (int)i) gw_load(PP, vget(t, k) - pb, F.p[k], F.key[k]);
-    }
-    // A first candidate: the least pencil parameter in FP64 over all
-    // points beyond the facet (a guess; the exact order decides below).
-    uint32_t guess = GW_NONE;
-    {
-      double cf[3], r2, nrm[3];
-      if (facet_frame<D>(F, i, PP[vget(t, (int)i) - pb], cf, &r2, nrm)) {
-        double bnum = 0.0, bden = 1.0;
-        for (uint32_t q0 = lo + lane; q0 < hi; q0 += 4 * 64) {
-          double4 cp[4];
+  for (int k = 0; k <= D; k++) {
+    F.p[k][0] = F.p[k][1] = F.p[k][2] = 0.0;
+    F.key[k] = 0;
+    if (k != (int)i) gw_load(PP, vget(t, k) - pb, F.p[k], F.key[k]);
+  }
+  double gl[3] = {0.0, 0.0, 0.0}, ginv = 0.0;
+  int gd[3] = {1, 1, 1}, gbase = 0;
+  if (grid) {
+    gl[0] = G.meta[4 * set];
+    gl[1] = G.meta[4 * set + 1];
+    gl[2] = G.meta[4 * set + 2];
+    ginv = G.meta[4 * set + 3];
+    gd[0] = G.dims[4 * set];
+    gd[1] = G.dims[4 * set + 1];
+    gd[2] = G.dims[4 * set + 2];
+    gbase = G.dims[4 * set + 3];
+  }
+  // A first candidate: the least pencil parameter in FP64 over the points
+  // beyond the facet (a guess; the exact order decides below).
+  uint32_t guess = GW_NONE;
+  {
+    double cf[3], r2, nrm[3];
+    if (facet_frame<D>(F, i, PP[vget(t, (int)i) - pb], cf, &r2, nrm)) {
+      double bnum = 0.0, bden = 1.0;
+      auto consider = [&](uint32_t q, const double4& cp) {
+        const double wx = cp.x - cf[0], wy = cp.y - cf[1], wz = cp.z - cf[2];
+        const double h = wx * nrm[0] + wy * nrm[1] + (D == 3 ? wz * nrm[2] : 0.0);
+        if (!(h > 0.0)) return;
+        // the facet's own points lie on its hyperplane (h is rounding)
+        bool vert = false;
 #pragma unroll
-          for (int u = 0; u < 4; u++) {
-            const uint32_t q = q0 + 64u * (uint32_t)u;
-            cp[u] = PP[(q < hi ? q : lo) - pb];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            const uint32_t q = q0 + 64u * (uint32_t)u;
-            const double wx = cp[u].x - cf[0], wy = cp[u].y - cf[1], wz = cp[u].z - cf[2];
-            const double h = wx * nrm[0] + wy * nrm[1] + (D == 3 ? wz * nrm[2] : 0.0);
-            if (q >= hi || !(h > 0.0)) continue;
-            // the facet's own points lie on its hyperplane (h is rounding)
-            bool vert = false;
-#pragma unroll
-            for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
-            if (vert) continue;
-            const double num = (wx * wx + wy * wy + (D == 3 ? wz * wz : 0.0)) - r2;
-            if (guess == GW_NONE || num * bden < bnum * h) {
-              guess = q;
-              bnum = num;
-              bden = h;
-            }
-          }
+        for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
+        if (vert) return;
+        const double num = (wx * wx + wy * wy + (D == 3 ? wz * wz : 0.0)) - r2;
+        if (guess == GW_NONE || num * bden < bnum * h) {
+          guess = q;
+          bnum = num;
+          bden = h;
         }
+      };
+      auto reduce = [&]() {
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
           const uint32_t oq = __shfl_xor(guess, off, 64);
@@ -493,36 +525,125 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
           }
         }
         guess = __shfl(guess, 0, 64);
+      };
+      if (grid) {
+        // the cells around the facet's circumcentre
+        const int cx = gw_coord(cf[0], gl[0], ginv, gd[0]);
+        const int cy = gw_coord(cf[1], gl[1], ginv, gd[1]);
+        const int cz = D == 3 ? gw_coord(cf[2], gl[2], ginv, gd[2]) : 0;
+        const int x0 = max(cx - 1, 0), x1 = min(cx + 1, gd[0] - 1);
+        for (int z = max(cz - 1, 0); z <= min(cz + 1, gd[2] - 1); z++)
+          for (int y = max(cy - 1, 0); y <= min(cy + 1, gd[1] - 1); y++) {
+            const int row = gbase + (z * gd[1] + y) * gd[0];
+            const uint32_t a = G.cstart[row + x0], b = G.cstart[row + x1 + 1];
+            for (uint32_t q = a + lane; q < b; q += 64) consider(q, PP[q - pb]);
+          }
+        reduce();
+      }
+      if (guess == GW_NONE) {
+        for (uint32_t q0 = lo + lane; q0 < hi; q0 += 4 * 64) {
+          double4 cp[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const uint32_t q = q0 + 64u * (uint32_t)u;
+            cp[u] = PP[(q < hi ? q : lo) - pb];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const uint32_t q = q0 + 64u * (uint32_t)u;
+            if (q < hi) consider(q, cp[u]);
+          }
+        }
+        reduce();
       }
     }
-    // The exact scan starts from the guess when it lies strictly beyond the
-    // facet: a point outside the conservatively enlarged ball through the
-    // facet and the current candidate cannot come before it (it is not
-    // strictly inside the sphere), so only points inside the ball are
-    // tested.  Points are loaded four at a time, ahead of the tests.
-    uint32_t best = GW_NONE;
-    double bp[3] = {0.0, 0.0, 0.0};
-    unsigned long long bk = 0;
-    bool ball = false;
-    double sc[3] = {0.0, 0.0, 0.0}, sr2 = 0.0;
-    if (guess != GW_NONE) {
-      double qp[3];
-      unsigned long long qk;
-      gw_load(PP, guess - pb, qp, qk);
-      PtsX X = F;
-      put_slot<D>(X, i, qp, qk);
-      if (pr.template orient<D>(X) > 0) {
-        best = guess;
-        bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
-        bk = qk;
-        uint4 tq = t;
-        vput(tq, (int)i, guess);
-        double r = 0.0;
-        ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
-                            PP[(D == 3 ? tq.w : tq.z) - pb], sc, &r);
-        sr2 = r * r;
-      }
+  }
+  // The exact scan starts from the guess when it lies strictly beyond the
+  // facet: a point outside the conservatively enlarged ball through the
+  // facet and the current candidate cannot come before it (it is not
+  // strictly inside the sphere), so only points inside the ball are
+  // tested.
+  uint32_t best = GW_NONE;
+  double bp[3] = {0.0, 0.0, 0.0};
+  unsigned long long bk = 0;
+  bool ball = false;
+  double sc[3] = {0.0, 0.0, 0.0}, sr2 = 0.0, sr = 0.0;
+  if (guess != GW_NONE) {
+    double qp[3];
+    unsigned long long qk;
+    gw_load(PP, guess - pb, qp, qk);
+    PtsX X = F;
+    put_slot<D>(X, i, qp, qk);
+    if (pr.template orient<D>(X) > 0) {
+      best = guess;
+      bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
+      bk = qk;
+      uint4 tq = t;
+      vput(tq, (int)i, guess);
+      ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
+                           PP[(D == 3 ? tq.w : tq.z) - pb], sc, &sr);
+      sr2 = sr * sr;
     }
+  }
+  auto test = [&](uint32_t q, const double4& cp) {
+    if (q == best) return;
+    if (ball) {
+      const double dx = cp.x - sc[0], dy = cp.y - sc[1], dz = cp.z - sc[2];
+      if (dx * dx + dy * dy + dz * dz > sr2) return;
+    }
+    bool vert = false;
+#pragma unroll
+    for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
+    if (vert) return;
+    const double qp[3] = {cp.x, cp.y, cp.z};
+    const unsigned long long qk = (unsigned long long)__double_as_longlong(cp.w);
+    PtsX X = F;
+    put_slot<D>(X, i, qp, qk);
+    if (pr.template orient<D>(X) <= 0) return;
+    bool take = best == GW_NONE;
+    if (!take) {
+      put_slot<D>(X, i, bp, bk);
+      X.p[D + 1][0] = qp[0]; X.p[D + 1][1] = qp[1]; X.p[D + 1][2] = qp[2];
+      X.key[D + 1] = qk;
+      take = pr.template insphere<D>(X) > 0;
+    }
+    if (take) {
+      best = q;
+      bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
+      bk = qk;
+      uint4 tq = t;
+      vput(tq, (int)i, q);
+      double r = 0.0;
+      ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
+                           PP[(D == 3 ? tq.w : tq.z) - pb], sc, &r);
+      sr2 = r * r;
+    }
+  };
+  // the cells under the guess's ball, when there are few of them
+  bool local = false;
+  if (grid && ball) {
+    int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+    long long ncell = 1;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      if (k < D) {
+        c0[k] = gw_coord(sc[k] - sr, gl[k], ginv, gd[k]);
+        c1[k] = gw_coord(sc[k] + sr, gl[k], ginv, gd[k]);
+      }
+      ncell *= c1[k] - c0[k] + 1;
+    }
+    if (ncell <= (long long)GW_BALL_CELLS) {
+      local = true;
+      for (int z = c0[2]; z <= c1[2]; z++)
+        for (int y = c0[1]; y <= c1[1]; y++) {
+          const int row = gbase + (z * gd[1] + y) * gd[0];
+          const uint32_t a = G.cstart[row + c0[0]], b = G.cstart[row + c1[0] + 1];
+          for (uint32_t q = a + lane; q < b; q += 64) test(q, PP[q - pb]);
+        }
+    }
+  }
+  if (!local) {
+    // every point, loaded four at a time ahead of the tests
     for (uint32_t q0 = lo + lane; q0 < hi; q0 += 4 * 64) {
       double4 cp[4];
 #pragma unroll
@@ -533,111 +654,156 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
 #pragma unroll
       for (int u = 0; u < 4; u++) {
         const uint32_t q = q0 + 64u * (uint32_t)u;
-        if (q >= hi || q == best) continue;
-        if (ball) {
-          const double dx = cp[u].x - sc[0], dy = cp[u].y - sc[1], dz = cp[u].z - sc[2];
-          if (dx * dx + dy * dy + dz * dz > sr2) continue;
-        }
-        bool vert = false;
-#pragma unroll
-        for (int k = 0; k <= D; k++) vert |= (k != (int)i && vget(t, k) == q);
-        if (vert) continue;
-        const double qp[3] = {cp[u].x, cp[u].y, cp[u].z};
-        const unsigned long long qk = (unsigned long long)__double_as_longlong(cp[u].w);
-        PtsX X = F;
-        put_slot<D>(X, i, qp, qk);
-        if (pr.template orient<D>(X) <= 0) continue;
-        bool take = best == GW_NONE;
-        if (!take) {
-          put_slot<D>(X, i, bp, bk);
-          X.p[D + 1][0] = qp[0]; X.p[D + 1][1] = qp[1]; X.p[D + 1][2] = qp[2];
-          X.key[D + 1] = qk;
-          take = pr.template insphere<D>(X) > 0;
-        }
-        if (take) {
-          best = q;
-          bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
-          bk = qk;
-          uint4 tq = t;
-          vput(tq, (int)i, q);
-          double r = 0.0;
-          ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
-                               PP[(D == 3 ? tq.w : tq.z) - pb], sc, &r);
-          sr2 = r * r;
-        }
+        if (q < hi) test(q, cp[u]);
       }
     }
-    // the wavefront's first candidate: a minimum over the lanes under the
-    // same order (a strict total order, so every lane ends with it)
+  }
+  // the wavefront's first candidate: a minimum over the lanes under the
+  // same order (a strict total order, so every lane ends with it)
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t o = __shfl_xor(best, off, 64);
-      if (o == GW_NONE || o == best) continue;
-      double op[3];
-      unsigned long long ok;
-      gw_load(PP, o - pb, op, ok);
-      bool take = best == GW_NONE;
-      if (!take) {
-        PtsX X = F;
-        put_slot<D>(X, i, bp, bk);
-        X.p[D + 1][0] = op[0]; X.p[D + 1][1] = op[1]; X.p[D + 1][2] = op[2];
-        X.key[D + 1] = ok;
-        take = pr.template insphere<D>(X) > 0;
-      }
-      if (take) {
-        best = o;
-        bp[0] = op[0]; bp[1] = op[1]; bp[2] = op[2];
-        bk = ok;
-      }
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_xor(best, off, 64);
+    if (o == GW_NONE || o == best) continue;
+    double op[3];
+    unsigned long long ok;
+    gw_load(PP, o - pb, op, ok);
+    bool take = best == GW_NONE;
+    if (!take) {
+      PtsX X = F;
+      put_slot<D>(X, i, bp, bk);
+      X.p[D + 1][0] = op[0]; X.p[D + 1][1] = op[1]; X.p[D + 1][2] = op[2];
+      X.key[D + 1] = ok;
+      take = pr.template insphere<D>(X) > 0;
     }
-    return best;
+    if (take) {
+      best = o;
+      bp[0] = op[0]; bp[1] = op[1]; bp[2] = op[2];
+      bk = ok;
+    }
+  }
+  return best;
 }
 
 // One level: every facet of the input list, one wavefront each, finds the
 // simplex beyond it; a simplex not found before is recorded and its other
 // D facets go to the output list.  Facet (c, i) is the facet of cell c
-// opposite its vertex i, searched away from that vertex.
-// With LDS (sets of at most GW_LDS_POINTS points) the block first copies
-// every point into LDS: a facet search is then a chain of LDS reads rather
-// than of L2 loads.
-template <int D, bool LDS>
+// opposite its vertex i, searched away from that vertex, among the points
+// of its own set (through the sets' grid).
+template <int D>
 __global__ __launch_bounds__(GW_THREADS) void k_gw_level(GwState g, const uint32_t* fin,
                                                          const uint32_t* cnt_in, uint32_t* fout,
                                                          uint32_t* cnt_out, uint32_t fcap) {
+  // new simplices of the block's chunk of facets: one allocation of cells
+  // and of next-level facets per chunk (counters that every new simplex
+  // hit alone would serialise a large level); the chunk is one facet per
+  // wavefront on small levels, so that they spread over the device
+  __shared__ uint4 s_new[GW_CHUNK];
+  __shared__ uint32_t s_opp[GW_CHUNK];
+  __shared__ uint32_t s_nnew, s_cbase, s_fbase, s_ok;
+  const uint32_t nin = *cnt_in;
+  if (nin == 0 || *g.flags) return;
+  const uint32_t wpb = GW_THREADS / 64;
+  uint32_t ch = (nin + gridDim.x - 1) / gridDim.x;
+  ch = (ch + wpb - 1) / wpb * wpb;
+  ch = ch < wpb ? wpb : (ch > GW_CHUNK ? GW_CHUNK : ch);
+  if (blockIdx.x * ch >= nin) return;
+  const double4* PP = g.P;
+  PredT<false> pr;
+  pr.init(g.flags);
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint32_t c0 = blockIdx.x * ch; c0 < nin; c0 += gridDim.x * ch) {
+    if (threadIdx.x == 0) s_nnew = 0;
+    __syncthreads();
+    const uint32_t c1 = min(c0 + ch, nin);
+    for (uint32_t e = c0 + threadIdx.x / 64; e < c1; e += wpb) {
+      const uint32_t ent = fin[e];
+      const uint32_t c = ent >> 2, i = ent & 3u;
+      // the facet's vertices with two of them swapped: (facet, x) is then
+      // positively oriented exactly for x strictly beyond the facet
+      uint4 t = g.cells[c].v;
+      const int a = i == 0 ? 1 : 0, b = i <= 1 ? 2 : 1;
+      // the points of the facet's set
+      const uint32_t set = g.sof[vget(t, a)];
+      const uint32_t lo = g.soff[set], hi = g.soff[set + 1];
+      {
+        const uint32_t x = vget(t, a);
+        vput(t, a, vget(t, b));
+        vput(t, b, x);
+      }
+      const uint32_t best = gw_search<D>(pr, PP, 0, lo, hi, t, i, lane, g.grid, g.has_grid, set);
+      if (lane == 0 && best != GW_NONE) {
+        vput(t, (int)i, best);
+        if (gw_claim<D>(g, t, set) == 1) {
+          const uint32_t k = atomicAdd(&s_nnew, 1u);
+          s_new[k] = t;
+          s_opp[k] = i;
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t nn = s_nnew;
+    if (threadIdx.x == 0) {
+      s_ok = 0;
+      if (nn) {
+        const uint32_t cb = atomicAdd(g.ncells, nn);
+        const uint32_t fb = atomicAdd(cnt_out, nn * (uint32_t)D);
+        if ((uint64_t)cb + nn > g.cap || (uint64_t)fb + (uint64_t)nn * D > fcap) {
+          atomicOr(g.flags, (uint32_t)GW_FAIL_CAP);
+        } else {
+          s_cbase = cb;
+          s_fbase = fb;
+          s_ok = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_ok) {
+      for (uint32_t k = threadIdx.x; k < nn; k += GW_THREADS) {
+        const uint32_t nc = s_cbase + k;
+        gw_cell(g.cells[nc], s_new[k]);
+        uint32_t w = s_fbase + k * (uint32_t)D;
+        for (uint32_t f = 0; f <= (uint32_t)D; f++)
+          if (f != s_opp[k]) fout[w++] = (nc << 2) | f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The same level for a single set copied into LDS by every block (sets of
+// at most GW_LDS_POINTS points): a facet search is then a chain of LDS
+// reads rather than of L2 loads; such sets have few facets per level, so
+// each new simplex takes its cell and facets from the counters directly.
+template <int D>
+__global__ __launch_bounds__(GW_THREADS) void k_gw_level_lds(GwState g, const uint32_t* fin,
+                                                             const uint32_t* cnt_in,
+                                                             uint32_t* fout, uint32_t* cnt_out,
+                                                             uint32_t fcap) {
   extern __shared__ double4 s_pts[];
   const uint32_t nin = *cnt_in;
   if (nin == 0 || *g.flags) return;
   const uint32_t wpb = GW_THREADS / 64;
   if (blockIdx.x * wpb >= nin) return;
-  const double4* PP = g.P;
-  if (LDS) {
-    for (uint32_t j = threadIdx.x; j < g.n; j += GW_THREADS) s_pts[j] = g.P[j];
-    __syncthreads();
-    PP = s_pts;
-  }
+  for (uint32_t j = threadIdx.x; j < g.n; j += GW_THREADS) s_pts[j] = g.P[j];
+  __syncthreads();
   PredT<false> pr;
   pr.init(g.flags);
   const uint32_t lane = threadIdx.x & 63u;
   for (uint32_t e = blockIdx.x * wpb + threadIdx.x / 64; e < nin; e += gridDim.x * wpb) {
     const uint32_t ent = fin[e];
     const uint32_t c = ent >> 2, i = ent & 3u;
-    // the facet's vertices with two of them swapped: (facet, x) is then
-    // positively oriented exactly for x strictly beyond the facet
     uint4 t = g.cells[c].v;
     const int a = i == 0 ? 1 : 0, b = i <= 1 ? 2 : 1;
-    // the points of the facet's set
-    const uint32_t set = g.sof[vget(t, a)];
-    const uint32_t lo = g.soff[set], hi = g.soff[set + 1];
     {
-      const uint32_t s = vget(t, a);
+      const uint32_t x = vget(t, a);
       vput(t, a, vget(t, b));
-      vput(t, b, s);
+      vput(t, b, x);
     }
-    const uint32_t best = gw_search<D>(pr, PP, 0, lo, hi, t, i, lane);
+    const uint32_t best = gw_search<D>(pr, s_pts, 0, 0, g.n, t, i, lane, g.grid, false, 0);
     if (lane == 0 && best != GW_NONE) {
       vput(t, (int)i, best);
       uint32_t nc = 0;
-      if (gw_record<D>(g, t, set, &nc)) {
+      if (gw_record<D>(g, t, 0, &nc)) {
         const uint32_t at = atomicAdd(cnt_out, (uint32_t)D);
         if (at + D > fcap) {
           atomicOr(g.flags, (uint32_t)GW_FAIL_CAP);
@@ -657,15 +823,122 @@ __global__ void k_gw_setof(const uint32_t* soff, uint32_t* sof) {
   for (uint32_t j = lo + threadIdx.x; j < hi; j += blockDim.x) sof[j] = set;
 }
 
+// Grid of each set (one block per set): its bounding box, about two
+// points per cell, at most GW_GRID_AXIS cells per axis.  dims[4s + 3]
+// receives the set's cell count (the host turns it into the first cell).
+constexpr int GW_GRID_AXIS = 256;
+__global__ void k_gw_grid_dims(const double4* P, const uint32_t* soff, int D, double* meta,
+                               int* dims) {
+  __shared__ double s_lo[3][GW_THREADS], s_hi[3][GW_THREADS];
+  const uint32_t set = blockIdx.x, lo = soff[set], hi = soff[set + 1];
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (uint32_t j = lo + threadIdx.x; j < hi; j += GW_THREADS) {
+    const double4 q = P[j];
+    const double c[3] = {q.x, q.y, q.z};
+    for (int k = 0; k < 3; k++) {
+      mn[k] = fmin(mn[k], c[k]);
+      mx[k] = fmax(mx[k], c[k]);
+    }
+  }
+  for (int k = 0; k < 3; k++) {
+    s_lo[k][threadIdx.x] = mn[k];
+    s_hi[k][threadIdx.x] = mx[k];
+  }
+  __syncthreads();
+  for (uint32_t w = GW_THREADS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 3; k++) {
+        s_lo[k][threadIdx.x] = fmin(s_lo[k][threadIdx.x], s_lo[k][threadIdx.x + w]);
+        s_hi[k][threadIdx.x] = fmax(s_hi[k][threadIdx.x], s_hi[k][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const uint32_t n = hi - lo;
+  double e[3], vol = 1.0;
+  int nd = 0;
+  for (int k = 0; k < 3; k++) {
+    e[k] = (k < D && n) ? s_hi[k][0] - s_lo[k][0] : 0.0;
+    if (e[k] > 0.0) {
+      vol *= e[k];
+      nd++;
+    }
+  }
+  const double target = n > 2 ? 0.5 * n : 1.0;
+  double h = nd ? pow(vol / target, 1.0 / nd) : 1.0;
+  if (!(h > 0.0)) h = 1.0;
+  int g[3];
+  // a flat set would get far more cells than points: coarser until at
+  // most about four cells per point
+  for (int it = 0; it < 64; it++) {
+    for (int k = 0; k < 3; k++) {
+      const double c = e[k] > 0.0 ? floor(e[k] / h) + 1.0 : 1.0;
+      g[k] = c > GW_GRID_AXIS ? GW_GRID_AXIS : (int)c;
+    }
+    if ((double)g[0] * g[1] * g[2] <= 4.0 * n + 64.0) break;
+    h *= 1.25;
+  }
+  for (int k = 0; k < 3; k++) meta[4 * set + k] = n ? s_lo[k][0] : 0.0;
+  meta[4 * set + 3] = 1.0 / h;
+  dims[4 * set] = g[0];
+  dims[4 * set + 1] = g[1];
+  dims[4 * set + 2] = g[2];
+  dims[4 * set + 3] = g[0] * g[1] * g[2];
+}
+
+// Cell of every point (one thread per point), counted per cell.
+__global__ void k_gw_grid_cell(const double4* P, uint32_t n, const uint32_t* sof,
+                               const double* meta, const int* dims, int D, uint32_t* cellof,
+                               uint32_t* cnt) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t s = sof[j];
+  const double4 q = P[j];
+  const double inv = meta[4 * s + 3];
+  const int cx = gw_coord(q.x, meta[4 * s], inv, dims[4 * s]);
+  const int cy = gw_coord(q.y, meta[4 * s + 1], inv, dims[4 * s + 1]);
+  const int cz = D == 3 ? gw_coord(q.z, meta[4 * s + 2], inv, dims[4 * s + 2]) : 0;
+  const uint32_t c = (uint32_t)dims[4 * s + 3] + ((uint32_t)cz * dims[4 * s + 1] + cy) * dims[4 * s] + cx;
+  cellof[j] = c;
+  atomicAdd(&cnt[c], 1u);
+}
+
+// The points in cell order (each set keeps its range); perm[new] = old.
+__global__ void k_gw_grid_fill(const double4* P, uint32_t n, const uint32_t* cellof,
+                               const uint32_t* cstart, uint32_t* cur, double4* out,
+                               uint32_t* perm) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t c = cellof[j];
+  const uint32_t at = cstart[c] + atomicAdd(&cur[c], 1u);
+  out[at] = P[j];
+  perm[at] = j;
+}
+
+// Cell vertices back to the caller's point indices.
+__global__ void k_gw_unperm(Cell* cells, uint32_t nc, const uint32_t* perm, int D) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  uint4 v = cells[c].v;
+  v.x = perm[v.x];
+  v.y = perm[v.y];
+  v.z = perm[v.z];
+  if (D == 3) v.w = perm[v.w];
+  cells[c].v = v;
+}
+
 }  // namespace
 
 int gift_wrap_sets(const double4* P, uint32_t n, const uint32_t* soff, uint32_t nsets,
-                   uint32_t max_set, int D, CellPool& pool, uint32_t* levels, hipStream_t st) {
+                   uint32_t max_set, int D, CellPool& pool, uint32_t* levels, hipStream_t st,
+                   uint32_t* first) {
   *levels = 0;
-  if ((D != 2 && D != 3) || nsets == 0 || n < (uint32_t)D + 2 || max_set > GW_MAX_POINTS)
-    return DT_E_NOT_READY;
-  // the set's number and D+1 local indices share one 64-bit key
-  if ((uint64_t)nsets > (1ull << (64 - (D + 1) * GW_LOCAL_BITS))) return DT_E_NOT_READY;
+  if ((D != 2 && D != 3) || nsets == 0 || n < (uint32_t)D + 2) return DT_E_NOT_READY;
+  // the set's number and D+1 set-local indices share one 64-bit key: 16
+  // bits per index for a single set, 13 for several
+  const int kbits = nsets == 1 ? 16 : GW_LOCAL_BITS;
+  if (max_set > (nsets == 1 ? GW_MAX_POINTS : GW_MAX_SET_POINTS)) return DT_E_NOT_READY;
+  if ((uint64_t)nsets > (1ull << (64 - (D + 1) * kbits))) return DT_E_NOT_READY;
   // about 6.8 n simplices in 3D and 2 n in 2D; room for far more
   const size_t cap = (size_t)n * (D == 3 ? 12 : 4) + (size_t)64 * nsets;
   if (cap >= (1ull << 30)) return DT_E_NOT_READY;
@@ -690,8 +963,51 @@ int gift_wrap_sets(const double4* P, uint32_t n, const uint32_t* soff, uint32_t 
   DT_HIP(hipMemsetAsync(cnt.p, 0, (size_t)(GW_MAX_LEVELS + 2) * 4, st));
   DT_HIP(hipMemsetAsync(pool.set_cell0.p, 0, 4, st));
   hipLaunchKernelGGL(k_gw_setof, dim3(nsets), dim3(GW_THREADS), 0, st, soff, sof.as<uint32_t>());
+  const bool lds = nsets == 1 && n <= GW_LDS_POINTS;
+  // the grid (not for a single set small enough for LDS): the points
+  // sorted by cell within each set
+  DevBuf gmeta, gdims, gcnt, gstart, gcur, cellof, P2, perm;
+  GwGrid grid{nullptr, nullptr, nullptr};
+  if (!lds) {
+    DT_TRY(gmeta.alloc((size_t)nsets * 4 * sizeof(double)));
+    DT_TRY(gdims.alloc((size_t)nsets * 4 * sizeof(int)));
+    hipLaunchKernelGGL(k_gw_grid_dims, dim3(nsets), dim3(GW_THREADS), 0, st, P, soff, D,
+                       gmeta.as<double>(), gdims.as<int>());
+    DT_HIP(hipGetLastError());
+    std::vector<int> hd((size_t)nsets * 4);
+    DT_HIP(hipMemcpyAsync(hd.data(), gdims.p, hd.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    DT_HIP(hipStreamSynchronize(st));
+    uint64_t ncell = 0;
+    for (uint32_t i = 0; i < nsets; i++) {
+      const uint64_t c = (uint64_t)hd[4 * i + 3];
+      hd[4 * i + 3] = (int)ncell;
+      ncell += c;
+    }
+    if (ncell >= (1ull << 31)) return DT_E_NOT_READY;
+    DT_HIP(hipMemcpyAsync(gdims.p, hd.data(), hd.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DT_TRY(gcnt.alloc((size_t)(ncell + 1) * 4));
+    DT_TRY(gstart.alloc((size_t)(ncell + 1) * 4));
+    DT_TRY(gcur.alloc((size_t)ncell * 4));
+    DT_TRY(cellof.alloc((size_t)n * 4));
+    DT_TRY(P2.alloc((size_t)n * sizeof(double4)));
+    DT_TRY(perm.alloc((size_t)n * 4));
+    DT_HIP(hipMemsetAsync(gcnt.p, 0, (size_t)(ncell + 1) * 4, st));
+    DT_HIP(hipMemsetAsync(gcur.p, 0, (size_t)ncell * 4, st));
+    const uint32_t nb = (n + GW_THREADS - 1) / GW_THREADS;
+    hipLaunchKernelGGL(k_gw_grid_cell, dim3(nb), dim3(GW_THREADS), 0, st, P, n, sof.as<uint32_t>(),
+                       gmeta.as<double>(), gdims.as<int>(), D, cellof.as<uint32_t>(),
+                       gcnt.as<uint32_t>());
+    DT_TRY(exclusive_scan(gcnt.as<uint32_t>(), gstart.as<uint32_t>(), (uint32_t)ncell + 1, st));
+    hipLaunchKernelGGL(k_gw_grid_fill, dim3(nb), dim3(GW_THREADS), 0, st, P, n,
+                       cellof.as<uint32_t>(), gstart.as<uint32_t>(), gcur.as<uint32_t>(),
+                       P2.as<double4>(), perm.as<uint32_t>());
+    DT_HIP(hipGetLastError());
+    grid = GwGrid{gmeta.as<double>(), gdims.as<int>(), gstart.as<uint32_t>()};
+    P = P2.as<double4>();
+  }
   GwState g{P, n, soff, sof.as<uint32_t>(), pool.cells.as<Cell>(), (uint32_t)cap, ncells,
-            table.as<unsigned long long>(), (uint32_t)(tsize - 1), flags.as<uint32_t>()};
+            table.as<unsigned long long>(), (uint32_t)(tsize - 1), flags.as<uint32_t>(),
+            kbits, grid, !lds};
   const uint32_t ncomb = D == 2 ? seed_combos<2>(GW_NN) : seed_combos<3>(GW_NN);
   hipLaunchKernelGGL(k_gw_nearest, dim3(nsets * GW_BASES), dim3(GW_THREADS), 0, st, P, soff,
                      nn.as<uint32_t>());
@@ -702,30 +1018,23 @@ int gift_wrap_sets(const double4* P, uint32_t n, const uint32_t* soff, uint32_t 
     if (D == 2) hipLaunchKernelGGL((K<2>), __VA_ARGS__);                                  \
     else hipLaunchKernelGGL((K<3>), __VA_ARGS__);                                         \
   } while (0)
-#define GW_LAUNCH_LDS(K, L, ...)                                                          \
-  do {                                                                                    \
-    if (D == 2) hipLaunchKernelGGL((K<2, L>), __VA_ARGS__);                               \
-    else hipLaunchKernelGGL((K<3, L>), __VA_ARGS__);                                      \
-  } while (0)
   GW_LAUNCH(k_gw_seed, dim3(sb), dim3(GW_THREADS), 0, st, P, soff, nsets, nn.as<uint32_t>(),
             ncomb, best.as<uint32_t>(), flags.as<uint32_t>());
   GW_LAUNCH(k_gw_start, dim3((nsets + 63) / 64), dim3(64), 0, st, g, nsets, nn.as<uint32_t>(),
-            best.as<uint32_t>(), fa.as<uint32_t>(), cnt.as<uint32_t>());
+            best.as<uint32_t>(), fa.as<uint32_t>(), cnt.as<uint32_t>(), first);
   DT_HIP(hipGetLastError());
-  const bool lds = nsets == 1 && n <= GW_LDS_POINTS;
   uint32_t lev = 0;
   for (;;) {
     for (uint32_t r = 0; r < GW_GROUP && lev < GW_MAX_LEVELS; r++, lev++) {
       const uint32_t* fin = (lev & 1u) ? fb.as<uint32_t>() : fa.as<uint32_t>();
       uint32_t* fout = (lev & 1u) ? fa.as<uint32_t>() : fb.as<uint32_t>();
       if (lds)
-        GW_LAUNCH_LDS(k_gw_level, true, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS),
-                      (size_t)n * sizeof(double4), st, g, fin, cnt.as<uint32_t>() + lev, fout,
-                      cnt.as<uint32_t>() + lev + 1, (uint32_t)fcap);
+        GW_LAUNCH(k_gw_level_lds, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS),
+                  (size_t)n * sizeof(double4), st, g, fin, cnt.as<uint32_t>() + lev, fout,
+                  cnt.as<uint32_t>() + lev + 1, (uint32_t)fcap);
       else
-        GW_LAUNCH_LDS(k_gw_level, false, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS), 0, st, g, fin,
-                      cnt.as<uint32_t>() + lev, fout, cnt.as<uint32_t>() + lev + 1,
-                      (uint32_t)fcap);
+        GW_LAUNCH(k_gw_level, dim3(GW_LEVEL_BLOCKS), dim3(GW_THREADS), 0, st, g, fin,
+                  cnt.as<uint32_t>() + lev, fout, cnt.as<uint32_t>() + lev + 1, (uint32_t)fcap);
     }
     DT_HIP(hipGetLastError());
     uint32_t h[2] = {0, 0};
@@ -740,12 +1049,17 @@ int gift_wrap_sets(const double4* P, uint32_t n, const uint32_t* soff, uint32_t 
     if (lev >= GW_MAX_LEVELS) return DT_E_NOT_READY;
   }
 #undef GW_LAUNCH
-#undef GW_LAUNCH_LDS
   uint32_t nc = 0;
   std::vector<uint32_t> hc(lev + 1);
   DT_HIP(hipMemcpyAsync(&nc, ncells, 4, hipMemcpyDeviceToHost, st));
   DT_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)(lev + 1) * 4, hipMemcpyDeviceToHost, st));
   DT_HIP(hipStreamSynchronize(st));
+  if (!lds && nc) {
+    hipLaunchKernelGGL(k_gw_unperm, dim3((nc + GW_THREADS - 1) / GW_THREADS), dim3(GW_THREADS), 0,
+                       st, pool.cells.as<Cell>(), nc, perm.as<uint32_t>(), D);
+    DT_HIP(hipGetLastError());
+    DT_HIP(hipStreamSynchronize(st));
+  }
   pool.cap = (uint32_t)cap;
   pool.ncells = nc;
   // levels that had facets to search

@@ -1597,9 +1597,15 @@ constexpr uint32_t SEED_TOTAL = 32768;
 constexpr uint32_t SEED_SET_MIN = 8192;
 constexpr uint32_t SEED_SET_MIN_SEED = 64;
 
-__global__ void k_seed_count(uint32_t npts, uint32_t T, const uint32_t* pset, uint32_t* scnt) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < npts && prio_of(p) < T) atomicAdd(&scnt[pset[p]], 1u);
+// The points of each set below T (one block per set: a set's points are
+// consecutive).
+__global__ void k_seed_count(const uint32_t* set_off, uint32_t T, uint32_t* scnt) {
+  const uint32_t s = blockIdx.x, lo = set_off[s], hi = set_off[s + 1];
+  uint32_t c = 0;
+  for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x) c += prio_of(p) < T ? 1u : 0u;
+  uint32_t tot;
+  block_exclusive<BLOCK>(c, &tot);
+  if (threadIdx.x == 0) scnt[s] = tot;
 }
 
 __global__ void k_seed_flag(uint32_t npts, uint32_t T, const uint32_t* pset,
@@ -1612,13 +1618,6 @@ __global__ void k_seed_gather(const double4* pts, const uint32_t* sidx, uint32_t
                               double4* spts) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) spts[i] = pts[sidx[i]];
-}
-
-// The first cell of every seeded set: its wrapped cell of least index.
-__global__ void k_seed_cell0(const Cell* wc, uint32_t nf, const uint32_t* sidx,
-                             const uint32_t* pset, uint32_t* seeded0) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < nf) atomicMin(&seeded0[pset[sidx[wc[c].v.x]]], c);
 }
 
 static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint32_t* ncells,
@@ -1646,13 +1645,12 @@ static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint
   // the wrap's limit in the largest
   const uint64_t per = std::min<uint64_t>(SEED_SET_POINTS, SEED_TOTAL / nbig);
   uint64_t T = (uint64_t)PMAX * per * nbig / pbig;
-  T = std::min<uint64_t>(T, (uint64_t)PMAX * (GW_MAX_POINTS * 3 / 4) / nmax);
+  T = std::min<uint64_t>(T, (uint64_t)PMAX * (GW_MAX_SET_POINTS * 3 / 4) / nmax);
   if (T < 16) return DT_E_NOT_READY;
   DevBuf scnt, smark, flag, sidx, spts, soff;
   DT_TRY(scnt.alloc((size_t)ns * 4));
-  DT_HIP(hipMemsetAsync(scnt.p, 0, (size_t)ns * 4, st));
-  hipLaunchKernelGGL(k_seed_count, dim3(nblk(npts)), dim3(BLOCK), 0, st, npts, (uint32_t)T,
-                     job.pset, scnt.as<uint32_t>());
+  hipLaunchKernelGGL(k_seed_count, dim3(ns), dim3(BLOCK), 0, st, job.set_off, (uint32_t)T,
+                     scnt.as<uint32_t>());
   DT_HIP(hipGetLastError());
   std::vector<uint32_t> cnt(ns), mark(ns), so(ns + 1);
   DT_HIP(hipMemcpyAsync(cnt.data(), scnt.p, (size_t)ns * 4, hipMemcpyDeviceToHost, st));
@@ -1660,7 +1658,7 @@ static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint
   uint32_t m = 0, mmax = 0, nsd = 0;
   for (uint32_t i = 0; i < ns; i++) {
     mark[i] = (off[i + 1] - off[i] >= SEED_SET_MIN && cnt[i] >= SEED_SET_MIN_SEED &&
-               cnt[i] <= GW_MAX_POINTS) ? 1u : 0u;
+               cnt[i] <= GW_MAX_SET_POINTS) ? 1u : 0u;
     so[i] = m;
     if (mark[i]) {
       m += cnt[i];
@@ -1689,8 +1687,11 @@ static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint
   CellPool wp;
   uint32_t levels = 0;
   const bool dbg = getenv("DT_DEBUG") != nullptr;
+  // the first cell of every seeded set: its seed simplex (unseeded: DONE)
+  DT_TRY(seeded0.alloc((size_t)ns * 4));
+  DT_HIP(hipMemsetAsync(seeded0.p, 0xFF, (size_t)ns * 4, st));
   const int g = gift_wrap_sets(spts.as<double4>(), m, soff.as<uint32_t>(), ns, mmax, D, wp,
-                               &levels, st);
+                               &levels, st, seeded0.as<uint32_t>());
   if (dbg)
     fprintf(stderr, "[seed] sets %u of %u, %u points (largest %u), T %llu: wrap %d, %u levels\n",
             nsd, ns, m, mmax, (unsigned long long)T, g, levels);
@@ -1698,12 +1699,6 @@ static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint
   const int l = seed_link(job, a, sidx, wp, ncells, st);
   if (dbg && l != DT_OK) fprintf(stderr, "[seed] link %d\n", l);
   DT_TRY(l);
-  DT_TRY(seeded0.alloc((size_t)ns * 4));
-  DT_HIP(hipMemsetAsync(seeded0.p, 0xFF, (size_t)ns * 4, st));
-  hipLaunchKernelGGL(k_seed_cell0, dim3(nblk(wp.ncells)), dim3(BLOCK), 0, st,
-                     wp.cells.as<Cell>(), wp.ncells, sidx.as<uint32_t>(), job.pset,
-                     seeded0.as<uint32_t>());
-  DT_HIP(hipGetLastError());
   const uint64_t t1 = T + T / 2;
   *thresh = (uint32_t)(t1 > PMAX ? PMAX : t1);
   *nseeded = nsd;

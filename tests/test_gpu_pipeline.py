@@ -322,7 +322,8 @@ def test_recursive_bisection(dtlib, dim, dist, n, k, divide, border):
 
 @pytest.mark.parametrize("dim,dist,n,rate,prec", [
     (3, "bubbles", 200_000, 0.0, "fp32"),      # eta = sqrt(n) = 447
-    (3, "uniform", 400_000, 0.02, "fp64"),     # eta = 8000, near the wrap's limit
+    (3, "uniform", 400_000, 0.02, "fp64"),     # eta = 8000
+    (3, "bubbles", 600_000, 0.05, "fp32"),     # eta = 30000: 16-bit keys, the grid
     (2, "normal", 100_000, 0.05, "fp32"),      # eta = 5000
     (3, "lattice", 8000, 0.25, "fp64"),        # co-spherical and coplanar samples
     (2, "lattice", 4900, 0.3, "fp32"),
@@ -330,9 +331,10 @@ def test_recursive_bisection(dtlib, dim, dist, n, k, divide, border):
 ])
 def test_sample_triangulation_gift_wrapped(dtlib, dim, dist, n, rate, prec):
     """The sample's Delaunay triangulation by gift wrapping (one facet
-    search per simplex facet, level by level from an empty seed simplex)
-    equals the oracle's DT of the sample, and the whole run gives the same
-    simplices as with the sample inserted in parallel rounds."""
+    search per simplex facet, level by level from an empty seed simplex;
+    samples of more than 2048 points searched through a grid of their
+    cells) equals the oracle's DT of the sample, and the whole run gives the
+    same simplices as with the sample inserted in parallel rounds."""
     if dist == "lattice":
         p = inputs.lattice(round(n ** (1.0 / dim)), dim, seed=4)
     elif dist == "jittered":
