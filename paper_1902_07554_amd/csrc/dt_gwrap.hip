@@ -300,19 +300,23 @@ __host__ __device__ __forceinline__ uint32_t seed_combos(uint32_t m) {
   return D == 2 ? m * (m - 1) / 2 : m * (m - 1) * (m - 2) / 6;
 }
 
-// One wavefront per candidate seed of each (set, start) (ncomb each): is
-// its circumsphere empty of every point of the set?  The smallest empty
-// candidate's number is kept per (set, start).
+// One wavefront per candidate seed of each (set, start) for the starts
+// b0 .. b0 + nb - 1 (ncomb each): is its circumsphere empty of every point
+// of the set?  The smallest empty candidate's number is kept per (set,
+// start).  Later starts are searched only for the sets where the first
+// found nothing (a second launch; its other wavefronts return at once).
 template <int D>
 __global__ void k_gw_seed(const double4* P, const uint32_t* soff, uint32_t nsets,
-                          const uint32_t* nn_all, uint32_t ncomb, uint32_t* best_all,
-                          uint32_t* flags) {
+                          const uint32_t* nn_all, uint32_t ncomb, uint32_t b0, uint32_t nb,
+                          uint32_t* best_all, uint32_t* flags) {
   PredT<false> pr;
   pr.init(flags);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  const uint32_t sb = w / ncomb, c = w % ncomb, set = sb / GW_BASES;
+  const uint32_t c = w % ncomb, set = w / ncomb / nb;
   if (set >= nsets) return;
+  const uint32_t sb = set * GW_BASES + b0 + (w / ncomb) % nb;
+  if (b0 > 0 && best_all[set * GW_BASES] != GW_NONE) return;
   const uint32_t* nn = nn_all + (size_t)sb * (GW_NN + 1);
   const uint32_t m = nn[GW_NN];
   if (m < (uint32_t)D || c >= seed_combos<D>(m)) return;
@@ -1011,15 +1015,18 @@ int gift_wrap_sets(const double4* P, uint32_t n, const uint32_t* soff, uint32_t 
   const uint32_t ncomb = D == 2 ? seed_combos<2>(GW_NN) : seed_combos<3>(GW_NN);
   hipLaunchKernelGGL(k_gw_nearest, dim3(nsets * GW_BASES), dim3(GW_THREADS), 0, st, P, soff,
                      nn.as<uint32_t>());
-  const uint64_t sw = (uint64_t)nsets * GW_BASES * ncomb;
-  const uint32_t sb = (uint32_t)((sw * 64 + GW_THREADS - 1) / GW_THREADS);
+  const uint64_t sw0 = (uint64_t)nsets * ncomb, sw1 = sw0 * (GW_BASES - 1);
+  const uint32_t sb0 = (uint32_t)((sw0 * 64 + GW_THREADS - 1) / GW_THREADS);
+  const uint32_t sb1 = (uint32_t)((sw1 * 64 + GW_THREADS - 1) / GW_THREADS);
 #define GW_LAUNCH(K, ...)                                                                 \
   do {                                                                                    \
     if (D == 2) hipLaunchKernelGGL((K<2>), __VA_ARGS__);                                  \
     else hipLaunchKernelGGL((K<3>), __VA_ARGS__);                                         \
   } while (0)
-  GW_LAUNCH(k_gw_seed, dim3(sb), dim3(GW_THREADS), 0, st, P, soff, nsets, nn.as<uint32_t>(),
-            ncomb, best.as<uint32_t>(), flags.as<uint32_t>());
+  GW_LAUNCH(k_gw_seed, dim3(sb0), dim3(GW_THREADS), 0, st, P, soff, nsets, nn.as<uint32_t>(),
+            ncomb, 0u, 1u, best.as<uint32_t>(), flags.as<uint32_t>());
+  GW_LAUNCH(k_gw_seed, dim3(sb1), dim3(GW_THREADS), 0, st, P, soff, nsets, nn.as<uint32_t>(),
+            ncomb, 1u, GW_BASES - 1, best.as<uint32_t>(), flags.as<uint32_t>());
   GW_LAUNCH(k_gw_start, dim3((nsets + 63) / 64), dim3(64), 0, st, g, nsets, nn.as<uint32_t>(),
             best.as<uint32_t>(), fa.as<uint32_t>(), cnt.as<uint32_t>(), first);
   DT_HIP(hipGetLastError());
