@@ -35,12 +35,15 @@
 // tests that decide a facet compare nearly cospherical candidates, where the
 // FP32 filter often cannot decide and the out-of-line stages would run.
 //
-// Cost: a facet search reads every point of its set, one wavefront per
-// facet, so the work is about D (D+1) / 2 * 6.8 n^2 predicate evaluations
-// per set of n points in 3D; it is used for sets of at most GW_MAX_POINTS
-// points.  A level is one launch;
-// the number of levels is the depth of the simplices' adjacency graph from
-// the seed (tens for a few thousand points).
+// Cost: one wavefront per facet search.  A small single set is copied into
+// every block's LDS and each search reads all of it; larger sets, and every
+// set of a multi-set wrap, are searched through a uniform grid of their
+// points (the cells around the facet for a first candidate, then the cells
+// under the ball through the facet and that candidate).  A search is then
+// a chain of dependent loads and FP64 predicates of some tens of
+// microseconds.  A level is one launch; the number of levels is the depth
+// of the simplices' adjacency graph from the seed (tens for a few thousand
+// points).
 #include "dt_common.hpp"
 #include "dt_geom.hpp"
 #include "dt_internal.hpp"

@@ -1584,14 +1584,15 @@ static int seed_single_set(const LocalJob& job, const K4Args& a, uint32_t* ncell
 // divide, a batch of independent sets).  Every set of at least
 // SEED_SET_MIN points starts from the triangulation of its points below a
 // common priority threshold T, all sets gift-wrapped together; a set whose
-// seed would be smaller than SEED_SET_MIN_SEED or larger than the wrap
-// takes starts from one simplex as before.  The seeds' cells are made
-// exactly as for a single set.  A facet search reads every point of its
-// set, so the wrap's cost grows with the seed size times the seeds' total:
-// a set of average size gets SEED_SET_POINTS, and fewer when the seeds
-// together would pass SEED_TOTAL (measured on 4M clustered points: 1024
-// per set pays at k = 16 and 64, where 256 sets of 1024 cost more than
-// they save; 128 per set still pays there).
+// seed would be smaller than SEED_SET_MIN_SEED or larger than a wrapped
+// set may be starts from one simplex as before.  The seeds' cells are made
+// exactly as for a single set.  A facet search of the wrap is a chain of
+// dependent loads and FP64 predicates (about 20 us), so the wrap's cost
+// grows with the seeds' total: a set of average size gets
+// SEED_SET_POINTS, and fewer when the seeds together would pass SEED_TOTAL
+// (measured on 4M clustered points: 1024 per set pays at k = 16 and 64;
+// at k = 256, 256 seeds of 1024 cost more than they save, and 128 each
+// about break even).
 constexpr uint32_t SEED_SET_POINTS = 1024;
 constexpr uint32_t SEED_TOTAL = 32768;
 constexpr uint32_t SEED_SET_MIN = 8192;
@@ -1608,6 +1609,7 @@ __global__ void k_seed_count(const uint32_t* set_off, uint32_t T, uint32_t* scnt
   if (threadIdx.x == 0) scnt[s] = tot;
 }
 
+// The seed points: below T in a set chosen for a seed.
 __global__ void k_seed_flag(uint32_t npts, uint32_t T, const uint32_t* pset,
                             const uint32_t* smark, uint32_t* flag) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1620,6 +1622,12 @@ __global__ void k_seed_gather(const double4* pts, const uint32_t* sidx, uint32_t
   if (i < m) spts[i] = pts[sidx[i]];
 }
 
+// Seed the sets of a batched run into the pool and the point records.
+// DT_OK: *ncells cells made, seeded0[s] the first cell of every seeded set
+// (DONE for the others, which start from one simplex), *thresh the first
+// activation threshold above the seeds, *nseeded the sets seeded;
+// DT_E_NOT_READY or DT_E_INTERNAL: not seeded (the caller clears the point
+// records and starts every set from one simplex).
 static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint32_t* ncells,
                      uint32_t* thresh, uint32_t* nseeded, hipStream_t st) {
   const int D = job.D;
