@@ -1589,12 +1589,14 @@ static int seed_single_set(const LocalJob& job, const K4Args& a, uint32_t* ncell
 // exactly as for a single set.  A facet search of the wrap is a chain of
 // dependent loads and FP64 predicates (about 20 us), so the wrap's cost
 // grows with the seeds' total: a set of average size gets
-// SEED_SET_POINTS, and fewer when the seeds together would pass SEED_TOTAL
-// (measured on 4M clustered points: 1024 per set pays at k = 16 and 64;
-// at k = 256, 256 seeds of 1024 cost more than they save, and 128 each
-// about break even).
+// SEED_SET_POINTS, and fewer when the seeds together would pass the total
+// for the dimension (measured on 4M clustered 3D points: 1024 per set
+// pays at k = 16 and 64; at k = 256, 256 seeds of 1024 cost more than they
+// save, and 128 each about break even; 2D facet searches are cheaper: the
+// 4096-set 2D batch runs 389.5 -> 380.9 ms with 805 sets seeded).
 constexpr uint32_t SEED_SET_POINTS = 1024;
-constexpr uint32_t SEED_TOTAL = 32768;
+constexpr uint32_t SEED_TOTAL_3D = 32768;
+constexpr uint32_t SEED_TOTAL_2D = 262144;
 constexpr uint32_t SEED_SET_MIN = 8192;
 constexpr uint32_t SEED_SET_MIN_SEED = 64;
 
@@ -1651,7 +1653,8 @@ static int seed_sets(const LocalJob& job, const K4Args& a, DevBuf& seeded0, uint
   if (nbig == 0) return DT_E_NOT_READY;
   // the seed of a set of average size among those seeded, at most 3/4 of
   // the wrap's limit in the largest
-  const uint64_t per = std::min<uint64_t>(SEED_SET_POINTS, SEED_TOTAL / nbig);
+  const uint64_t per =
+      std::min<uint64_t>(SEED_SET_POINTS, (D == 2 ? SEED_TOTAL_2D : SEED_TOTAL_3D) / nbig);
   uint64_t T = (uint64_t)PMAX * per * nbig / pbig;
   T = std::min<uint64_t>(T, (uint64_t)PMAX * (GW_MAX_SET_POINTS * 3 / 4) / nmax);
   if (T < 16) return DT_E_NOT_READY;
