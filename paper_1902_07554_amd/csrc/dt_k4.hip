@@ -1034,14 +1034,17 @@ __device__ __forceinline__ void new_cell_outer(K4Args& a, uint32_t c, uint32_t i
 // Neighbour of the new cell on facet i of cavity cell c across its facet
 // j (a facet through the new point): rotate around the ridge shared by
 // facets i and j inside the cavity until leaving it; the boundary facet
-// reached carries that neighbour.
+// reached carries that neighbour.  Every step enters another cavity cell
+// around the ridge, so a cavity of n cells is left within n steps (a
+// thin input can put thousands of cells of one cavity around a ridge).
 template <int D>
 __device__ __forceinline__ uint32_t new_cell_link(K4Args& a, CavList& cl, uint32_t c, int i, int j,
-                                                  uint32_t base, unsigned long long K) {
+                                                  uint32_t base, unsigned long long K,
+                                                  uint32_t n) {
   uint32_t cur = c;
   int sin = i, sout = j;
   uint4 vcur = a.cells[c].v;
-  for (int step = 0; step < 4096; step++) {
+  for (uint32_t step = 0; step <= n; step++) {
     // each step: the current cell's link and position, then the next
     // cell's claim and vertices (each pair from one cell record)
     const uint32_t nbr = vat(a.cells[cur].n, sout);
@@ -1227,7 +1230,7 @@ __global__ __launch_bounds__(64 * INS_WAVES, 8) void k4_insert(K4Args a) {
         const uint32_t inf = cl.info(h);
         const uint32_t x = facet_cell(inf, i, base);
         if (jj == 0) new_cell_outer<D>(a, c, inf, i, base, p);
-        uint32_t link = new_cell_link<D>(a, cl, c, i, j, base, K);
+        uint32_t link = new_cell_link<D>(a, cl, c, i, j, base, K, n);
         if (link == 0xFFFFFFFFu) link = (x << 2) | (uint32_t)j;   // in-bounds; the run is abandoned
         *nslot(a.cells, x, j) = link;
       }
@@ -1257,7 +1260,7 @@ __global__ __launch_bounds__(64 * INS_WAVES, 8) void k4_insert(K4Args a) {
           int sin = i, sout = j;
           uint4 vcur = vc;
           uint32_t link = 0xFFFFFFFFu;
-          for (int step = 0; step < 4096; step++) {
+          for (uint32_t step = 0; step <= n; step++) {
             const uint32_t nbr = vat(a.cells[cur].n, sout);
             const uint32_t ncell = nbr >> 2;
             if (ncell >= a.cap) break;

@@ -284,3 +284,45 @@ def test_batch_sets_seeded_by_gift_wrap(dtlib, dim, prec):
         assert np.array_equal(got, want), s
         assert np.array_equal(oracle.canonical(rrows[rso[s]:rso[s + 1]]), got), s
 
+
+def _thin(n, seed):
+    """Points on a segment in the plane, up to the rounding of y = 1/4 + t/2
+    (a valid input: distinct, not all collinear in floating point, with
+    extremely thin triangles and cavities of thousands of cells)."""
+    t = np.random.default_rng(seed).random(n)
+    return np.stack([t, 0.25 + 0.5 * t], axis=1)
+
+
+def test_thin_sets_seeded_and_unseeded(dtlib):
+    """Nearly collinear sets, whose new points conflict with thousands of
+    triangles around one vertex: a batch with such a set among others, with
+    and without the gift-wrapped seeds, gives the oracle's triangles per
+    set; a single set of 70,000 such points (large enough for its own seed)
+    gives the same rows seeded and not, every interior edge locally
+    Delaunay under the oracle's exact predicate and every point a vertex
+    (the hull of such a set is beyond Qhull's precision, so the hull is not
+    compared)."""
+    sets = [inputs.make("normal", 10_000, 2, seed=32), _thin(9000, 31),
+            inputs.make("uniform", 12_000, 2, seed=33)]
+    sizes = [len(x) for x in sets]
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    pts = np.concatenate(sets)
+    ids = np.concatenate([np.arange(n) for n in sizes]).astype(np.int64)
+    print(f"[thin] batch sizes={sizes}", flush=True)
+    for gw, seeded in ((0, 3), (-1, 0)):
+        res = dtlib.batch_triangulate(pts, offsets, ids=ids, gift_wrap=gw)
+        assert res.stats()["seeded_sets"] == seeded
+        rows, so = res.rows(), res.set_offsets(len(sizes))
+        for s in range(len(sizes)):
+            got = oracle.canonical(rows[so[s]:so[s + 1]])
+            assert np.array_equal(got, oracle.delaunay(sets[s])), (gw, s)
+    p = _thin(70_000, 41)
+    print("[thin] single set n=70000", flush=True)
+    a = _rows(dtlib.triangulate(p, k=1))
+    b = _rows(dtlib.triangulate(p, k=1, gift_wrap=-1))
+    assert np.array_equal(a, b)
+    cert = oracle.certify(p, a)
+    assert [f for f in ("bad_rows", "flat", "over_shared", "same_side", "not_local", "unused")
+            if cert[f]] == []
+    assert len(p) - cert["edges"] + cert["m"] == 1      # Euler: a triangulated disk
+
