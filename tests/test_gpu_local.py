@@ -326,3 +326,20 @@ def test_thin_sets_seeded_and_unseeded(dtlib):
             if cert[f]] == []
     assert len(p) - cert["edges"] + cert["m"] == 1      # Euler: a triangulated disk
 
+
+def test_nearly_planar_3d_set(dtlib):
+    """3D points on a plane up to rounding (slivers everywhere, thousands
+    of tetrahedra around an edge in one cavity): the oracle's tetrahedra,
+    alone and batched with a seeded set, with and without gift wrapping."""
+    xy = np.random.default_rng(51).random((6000, 2))
+    p = np.stack([xy[:, 0], xy[:, 1], 0.3 + 0.2 * xy[:, 0] - 0.1 * xy[:, 1]], axis=1)
+    want = oracle.delaunay(p)
+    off = np.array([0, 6000, 15000])
+    q = np.concatenate([p, inputs.make("uniform", 9000, 3, seed=52)])
+    print("[thin] nearly planar 3D n=6000", flush=True)
+    for gw in (0, -1):
+        assert np.array_equal(_rows(dtlib.triangulate(p, k=1, gift_wrap=gw)), want), gw
+        r = dtlib.batch_triangulate(q, off, gift_wrap=gw)
+        so = r.set_offsets(2)
+        assert np.array_equal(oracle.canonical(r.rows()[so[0]:so[1]]), want), gw
+
