@@ -527,6 +527,7 @@ def main() -> int:
                                  **summary(kst))
         line["sample_vs_kd_speedup"] = round(kms / ms, 4)
         line["kd_simplex_count_equal"] = bool(kres.count == res.count)
+        del kres
     if not args.no_kd and k != 16:
         # context: both divides at the paper's own k = 16 (its runtime
         # experiments use k = t = 16)
@@ -539,21 +540,32 @@ def main() -> int:
                        "border_vertices": {"sample": r16.stats()["border_vertices"],
                                            "kd": k16.stats()["border_vertices"]},
                        "simplex_counts_equal": bool(r16.count == k16.count == res.count)}
+        del r16, k16
     if not args.no_direct:
         # context, not the method: the same input triangulated as one set
         dres, dms, _, _ = run(binding, pts, args.steps, args.warmup, 1, 0.0, precision=prec)
         line["direct_k1"] = {"value": round(n / (dms / 1000.0) / 1e6, 4),
                              "ms_per_step": round(dms, 3), "rounds": dres.stats()["rounds"],
                              "simplex_count_equal": bool(dres.count == res.count)}
+        del dres
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(host, min(args.cpu_sample, n))
     del pts, res
+
+    def fresh():
+        # each pattern leg starts without the blocks the previous legs left
+        # in the library's cache
+        binding.release_cached_memory()
+        torch.cuda.empty_cache()
+
     if not args.no_batch:
+        fresh()
         b = bench_batch(args)
         line["batch"] = {k2: b[k2] for k2 in ("value", "unit", "ms_per_step", "config",
                                                "autotuned", "default_tunables_ms",
                                                "per_set_launches", "batched_vs_per_set")}
     if not args.no_serve:
+        fresh()
         v = bench_serve(args)
         line["serve"] = {k2: v[k2] for k2 in ("value", "unit", "p50_ms", "p99_ms", "max_ms",
                                                "ms_per_step", "config", "alone_vs_mix")}
