@@ -457,6 +457,20 @@ __global__ void k_gw_start(GwState g, uint32_t nsets, const uint32_t* nn_all,
 
 constexpr uint32_t GW_BALL_CELLS = 512;     // larger balls scan the whole set
 
+// The conservative circumball of the facet's points (slots other than i of
+// F) and the candidate c in slot i, from the coordinates in registers (the
+// same values as the points' records, so the same ball).
+template <int D>
+__device__ __forceinline__ bool gw_ball(const PtsX& F, uint32_t i, const double* c, double sc[3],
+                                        double* r) {
+  double4 Q[D + 1];
+#pragma unroll
+  for (int k = 0; k <= D; k++)
+    Q[k] = (uint32_t)k == i ? make_double4(c[0], c[1], c[2], 0.0)
+                            : make_double4(F.p[k][0], F.p[k][1], F.p[k][2], 0.0);
+  return circumball<D>(Q[0], Q[1], Q[2], Q[D], sc, r);
+}
+
 __device__ __forceinline__ int gw_coord(double x, double lo, double inv, int g) {
   const double f = (x - lo) * inv;
   if (!(f >= 0.0)) return 0;
@@ -500,6 +514,8 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
   // A first candidate: the least pencil parameter in FP64 over the points
   // beyond the facet (a guess; the exact order decides below).
   uint32_t guess = GW_NONE;
+  double gp[3] = {0.0, 0.0, 0.0};   // the guess's coordinates and key, carried along
+  unsigned long long gk = 0;
   {
     double cf[3], r2, nrm[3];
     if (facet_frame<D>(F, i, PP[vget(t, (int)i) - pb], cf, &r2, nrm)) {
@@ -518,6 +534,10 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
           guess = q;
           bnum = num;
           bden = h;
+          gp[0] = cp.x;
+          gp[1] = cp.y;
+          gp[2] = cp.z;
+          gk = (unsigned long long)__double_as_longlong(cp.w);
         }
       };
       auto reduce = [&]() {
@@ -525,13 +545,24 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
         for (int off = 1; off < 64; off <<= 1) {
           const uint32_t oq = __shfl_xor(guess, off, 64);
           const double on = __shfl_xor(bnum, off, 64), od = __shfl_xor(bden, off, 64);
+          const double ox = __shfl_xor(gp[0], off, 64), oy = __shfl_xor(gp[1], off, 64),
+                       oz = __shfl_xor(gp[2], off, 64);
+          const unsigned long long ok = __shfl_xor(gk, off, 64);
           if (oq != GW_NONE && (guess == GW_NONE || on * bden < bnum * od)) {
             guess = oq;
             bnum = on;
             bden = od;
+            gp[0] = ox;
+            gp[1] = oy;
+            gp[2] = oz;
+            gk = ok;
           }
         }
         guess = __shfl(guess, 0, 64);
+        gp[0] = __shfl(gp[0], 0, 64);
+        gp[1] = __shfl(gp[1], 0, 64);
+        gp[2] = __shfl(gp[2], 0, 64);
+        gk = __shfl(gk, 0, 64);
       };
       if (grid) {
         // the cells around the facet's circumcentre
@@ -576,19 +607,13 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
   bool ball = false;
   double sc[3] = {0.0, 0.0, 0.0}, sr2 = 0.0, sr = 0.0;
   if (guess != GW_NONE) {
-    double qp[3];
-    unsigned long long qk;
-    gw_load(PP, guess - pb, qp, qk);
     PtsX X = F;
-    put_slot<D>(X, i, qp, qk);
+    put_slot<D>(X, i, gp, gk);
     if (pr.template orient<D>(X) > 0) {
       best = guess;
-      bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
-      bk = qk;
-      uint4 tq = t;
-      vput(tq, (int)i, guess);
-      ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
-                           PP[(D == 3 ? tq.w : tq.z) - pb], sc, &sr);
+      bp[0] = gp[0]; bp[1] = gp[1]; bp[2] = gp[2];
+      bk = gk;
+      ball = gw_ball<D>(F, i, gp, sc, &sr);
       sr2 = sr * sr;
     }
   }
@@ -618,11 +643,8 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
       best = q;
       bp[0] = qp[0]; bp[1] = qp[1]; bp[2] = qp[2];
       bk = qk;
-      uint4 tq = t;
-      vput(tq, (int)i, q);
       double r = 0.0;
-      ball = circumball<D>(PP[tq.x - pb], PP[tq.y - pb], PP[tq.z - pb],
-                           PP[(D == 3 ? tq.w : tq.z) - pb], sc, &r);
+      ball = gw_ball<D>(F, i, qp, sc, &r);
       sr2 = r * r;
     }
   };
@@ -670,10 +692,10 @@ __device__ uint32_t gw_search(PredT<false>& pr, const double4* PP, uint32_t pb, 
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t o = __shfl_xor(best, off, 64);
+    const double op[3] = {__shfl_xor(bp[0], off, 64), __shfl_xor(bp[1], off, 64),
+                          __shfl_xor(bp[2], off, 64)};
+    const unsigned long long ok = __shfl_xor(bk, off, 64);
     if (o == GW_NONE || o == best) continue;
-    double op[3];
-    unsigned long long ok;
-    gw_load(PP, o - pb, op, ok);
     bool take = best == GW_NONE;
     if (!take) {
       PtsX X = F;
