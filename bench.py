@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -389,14 +390,14 @@ def bench_sweep(args) -> dict:
     binding.triangulate(pts, k=k, precision="fp32")
     rows = []
 
-    def one(**o):
+    def one(kk=k, **o):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        r = binding.triangulate(pts, k=k, precision="fp32", **o)
+        r = binding.triangulate(pts, k=kk, precision="fp32", **o)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) * 1000.0
         st = r.stats()
-        row = dict(o)
+        row = dict(o, k=kk)
         row.update(ms=round(dt, 2), eta=st["eta"], border_vertices=st["border_vertices"],
                    border_simplices=st["border_simplices"], tb_simplices=st["tb_simplices"],
                    o_dt=round(st["o_dt"], 4), cv=round(st["cv"], 4),
@@ -417,6 +418,11 @@ def bench_sweep(args) -> dict:
     one(divide="kd", recursive=1)
     one(divide="sample", sample_rate=0.0, recursive=1)
     one(divide="auto", sample_rate=0.0)
+    # the logarithmic sample size (eta = log2 n = 20) needs k <= eta: at k = 16, beside the
+    # square-root sample and the kd divide at the same k
+    for rate in (math.log2(n) / n, 0.0):
+        one(kk=16, divide="sample", sample_rate=rate)
+    one(kk=16, divide="kd")
     return {"metric": "border size and runtime by primitive, sample size and weight",
             "config": {"workload": "bubbles-3d-1M-k64", "n": n, "k": k, "precision": "fp32"},
             "runs": rows}
