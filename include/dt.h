@@ -106,16 +106,21 @@ typedef struct dt_options {
                         x1.125..x4); default 10 for several sets, 12 for one set   */
   /* 1: recursive bisection (Section "Recursive Bisection"): log2 k levels of
    * 2-way division with the chosen divide (kd: cyclic median split; sample:
-   * a new sample per block and level, split at its median), then k-1
-   * merges bottom-up with the grid test; k must be a power of two.
+   * per block and level a new sample, its DT, a 2-way partition of its
+   * graph and nearest-sample assignment), then k-1 merges bottom-up, whose
+   * border test is the region test of the divide (DT_BORDER_GRID selects
+   * the grid test); k must be a power of two.
    * 0 (default): one k-way division and one merge (Algorithm 1). */
   int recursive;
   /* Gift wrapping where it pays (timing only; the simplices are the same):
    * 0 (default) gift-wraps the sample of the sample divide when it has at
-   * most 8192 points, and starts every single set of at least 65,536 points
+   * most 65,536 points, starts every single set of at least 65,536 points
    * (the border set, a direct triangulation) from the gift-wrapped
-   * triangulation of its first 4096 or so points in insertion order; -1
-   * inserts every point in parallel rounds. */
+   * triangulation of its first 4096 or so points in insertion order, and
+   * starts every set of at least 8192 points of a batched run (the blocks
+   * of a divide, a batch) from a gift-wrapped seed of up to 1024 of its
+   * first points; -1 inserts every point in parallel rounds.  A run in a
+   * caller's workspace (dt_triangulate_noalloc) wraps nothing. */
   int gift_wrap;
   /* Pair exchanges in the partitioner's sweeps: 0 (default) lets a vertex
    * whose best block is full swap with a vertex of that block that wants
